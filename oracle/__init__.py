@@ -78,6 +78,7 @@ class Info:
     verify_failures: int
     relres_recursive: float
     relres_true: float
+    breakdown_test: int = 0
 
     @property
     def status_name(self) -> str:
@@ -148,7 +149,7 @@ def arnoldi(A, r0, m: int, eps_b: Optional[float] = None):
 
 def _info(ii, dd):
     return Info(int(ii[0]), int(ii[1]), int(ii[2]), int(ii[3]), int(ii[4]), float(dd[0]),
-                float(dd[1]))
+                float(dd[1]), int(ii[5]))
 
 
 def gmres(A, b, x0=None, m: int = 30, tol: float = 1e-8, maxit: int = 10000,
@@ -159,7 +160,7 @@ def gmres(A, b, x0=None, m: int = 30, tol: float = 1e-8, maxit: int = 10000,
     b = np.ascontiguousarray(b, dtype=np.float64)
     x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
     hist = np.full(max(maxit, 1), np.nan) if history else None
-    ii = np.zeros(5, dtype=np.int32)
+    ii = np.zeros(6, dtype=np.int32)
     dd = np.zeros(2)
     eps = default_breakdown_eps() if eps_b is None else eps_b
     w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
@@ -182,7 +183,7 @@ def bicgstab(A, b, x0=None, tol: float = 1e-8, maxit: int = 10000,
     b = np.ascontiguousarray(b, dtype=np.float64)
     x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
     hist = np.full(max(maxit, 1), np.nan) if history else None
-    ii = np.zeros(5, dtype=np.int32)
+    ii = np.zeros(6, dtype=np.int32)
     dd = np.zeros(2)
     eps = default_breakdown_eps() if eps_b is None else eps_b
     w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)

@@ -56,7 +56,8 @@
 #define ORC_BREAKDOWN 2
 #define ORC_STAGNATED 3
 
-/* info_i layout: [iters, restarts, status, half_step, verify_failures]
+/* info_i layout: [iters, restarts, status, half_step, verify_failures, breakdown_test]
+ * breakdown_test: 0 none, 1 (r^,v), 2 (t,s), 3 (r^,r), 4 zero Hessenberg column
  * info_d layout: [relres_recursive, relres_true]                                     */
 
 /* ---------------------------------------------------------------------------------------
@@ -273,7 +274,7 @@ int orc_gmres(int n, const int* rp, const int* ci, const double* val, const doub
         free(V); free(H); free(r); free(w); free(z); free(c); free(cs); free(sn); free(g); free(y);
         return ORC_ERR_ALLOC;
     }
-    int iters = 0, restarts = 0, status = ORC_MAXIT, fails = 0;
+    int iters = 0, restarts = 0, status = ORC_MAXIT, fails = 0, brk = 0;
     double est = 1.0, relres_true = 1.0;
     const int ldh = m + 1;
 
@@ -307,7 +308,7 @@ int orc_gmres(int n, const int* rp, const int* ci, const double* val, const doub
             }
             /* new rotation annihilating h_{j+1,j} */
             double d = hypot(h[j], h[j + 1]);
-            if (d == 0.0) { status = ORC_BREAKDOWN; k = j; goto update; }
+            if (d == 0.0) { status = ORC_BREAKDOWN; brk = 4; k = j; goto update; }
             cs[j] = h[j] / d;
             sn[j] = h[j + 1] / d;
             h[j] = d;
@@ -355,7 +356,7 @@ int orc_gmres(int n, const int* rp, const int* ci, const double* val, const doub
 done:
     if (info_i) {
         info_i[0] = iters; info_i[1] = restarts; info_i[2] = status; info_i[3] = 0;
-        info_i[4] = fails;
+        info_i[4] = fails; info_i[5] = brk;
     }
     if (info_d) { info_d[0] = est; info_d[1] = relres_true; }
     free(V); free(H); free(r); free(w); free(z); free(c); free(cs); free(sn); free(g); free(y);
@@ -384,7 +385,7 @@ int orc_bicgstab(int n, const int* rp, const int* ci, const double* val, const d
         free(r); free(rh); free(p); free(v); free(s); free(t); free(ph); free(sh);
         return ORC_ERR_ALLOC;
     }
-    int iters = 0, restarts = 0, status = ORC_MAXIT, fails = 0, half = 0;
+    int iters = 0, restarts = 0, status = ORC_MAXIT, fails = 0, half = 0, brk = 0;
     double est = 1.0, relres_true = 1.0;
 
     residual(n, rp, ci, val, b, x, r);
@@ -405,7 +406,7 @@ int orc_bicgstab(int n, const int* rp, const int* ci, const double* val, const d
         int verify = 0;
         half = 0;
         while (!verify) {
-            if (fabs(rho) <= eps_b * rh_norm * nrm2(n, r)) { status = ORC_BREAKDOWN; goto final_check; }
+            if (fabs(rho) <= eps_b * rh_norm * nrm2(n, r)) { status = ORC_BREAKDOWN; brk = 3; goto final_check; }
             if (first) {
                 memcpy(p, r, sizeof(double) * nn);
             } else {
@@ -417,7 +418,7 @@ int orc_bicgstab(int n, const int* rp, const int* ci, const double* val, const d
             if (lu) { ilu0_apply(n, rp, ci, lu, p, ph); orc_spmv(n, rp, ci, val, ph, v); }
             else { memcpy(ph, p, sizeof(double) * nn); orc_spmv(n, rp, ci, val, p, v); }
             double sigma = dot(n, rh, v);
-            if (fabs(sigma) <= eps_b * rh_norm * nrm2(n, v)) { status = ORC_BREAKDOWN; goto final_check; }
+            if (fabs(sigma) <= eps_b * rh_norm * nrm2(n, v)) { status = ORC_BREAKDOWN; brk = 1; goto final_check; }
             alpha = rho / sigma;
             for (int i = 0; i < n; ++i) s[i] = r[i] - alpha * v[i];
             ++iters;
@@ -435,7 +436,7 @@ int orc_bicgstab(int n, const int* rp, const int* ci, const double* val, const d
             else { memcpy(sh, s, sizeof(double) * nn); orc_spmv(n, rp, ci, val, s, t); }
             double ts = dot(n, t, s);
             double tt = dot(n, t, t);
-            if (fabs(ts) <= eps_b * sqrt(tt) * nrm2(n, s)) { status = ORC_BREAKDOWN; goto final_check; }
+            if (fabs(ts) <= eps_b * sqrt(tt) * nrm2(n, s)) { status = ORC_BREAKDOWN; brk = 2; goto final_check; }
             omega = ts / tt;
             for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * ph[i] + omega * sh[i];
             for (int i = 0; i < n; ++i) r[i] = s[i] - omega * t[i];
@@ -460,7 +461,7 @@ final_check:
 done:
     if (info_i) {
         info_i[0] = iters; info_i[1] = restarts; info_i[2] = status; info_i[3] = half;
-        info_i[4] = fails;
+        info_i[4] = fails; info_i[5] = brk;
     }
     if (info_d) { info_d[0] = est; info_d[1] = relres_true; }
     free(r); free(rh); free(p); free(v); free(s); free(t); free(ph); free(sh);

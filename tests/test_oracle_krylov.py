@@ -192,7 +192,8 @@ def test_bicgstab_identity_half_step_and_rotation_breakdown():
     np.testing.assert_allclose(x, P.b, rtol=1e-15)
     R = dense_problem(np.array([[0.0, 1.0], [-1.0, 0.0]]), [1.0, 0.0])
     x, info = oracle.bicgstab(R, R.b, tol=1e-12)
-    assert info.status == oracle.BREAKDOWN and info.iters == 0
+    # r0 = b = e1, A e1 = -e2 is orthogonal to the shadow residual: (r^, A p) = 0
+    assert info.status == oracle.BREAKDOWN and info.iters == 0 and info.breakdown_test == 1
 
 
 def test_bicgstab_distinct_eigenvalues_terminate():
