@@ -1,0 +1,238 @@
+"""Benchmark: GS(p) + Krylov solves on the 80^3 convection-diffusion system, one MI355X.
+
+Workload (seeded, synthetic; generated on the host, uploaded before timing): 80^3 interior
+grid, 7-point central differences in flux form, diffusion piecewise constant over 8 z-slabs
+with values 10^U(0,6) (numpy default_rng(1002)), convection (20,-10,5), b = A u* with
+u* = sin(pi x) sin(pi y) sin(pi z); n = 512,000, nnz = 3,545,600, FP64 CSR with int32 indices.
+
+One step = the workload's four solves, each from the unscaled matrix resident in HBM:
+GS(p) (out of place) then the Krylov solve from x0 = 0 to a relative residual below 1e-10
+(measured on the GS(2)-scaled system), for p in {2, 1} and solver in {Bi-CGSTAB, GMRES(30)}.
+`value` = solves per second over the timed steps.
+
+Prints one JSON line. Also reports iterations/s, per-variant p50/p99 latency, the achieved
+bandwidth of the dominant kernel against the HBM roofline, and the CPU oracle's rate on a
+bounded sample of the same work.
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "solves/s at 1e-8 rel. residual, Krylov HBM GB/s vs peak, p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+VARIANTS = [(2, "bicgstab"), (2, "gmres30"), (1, "bicgstab"), (1, "gmres30")]
+KERNEL_NAMES = {"gmres_a": "k_gmres_a (CSR product + CGS2 pass-1 dots)",
+                "gmres_b": "k_gmres_b (CGS2 pass-1 update + pass-2 dots)",
+                "gmres_c": "k_gmres_c (CGS2 pass-2 update + norm)",
+                "bicg_p": "k_bicg_p (p update + CSR product + dots)",
+                "bicg_s": "k_bicg_s (s + CSR product + dots)",
+                "bicg_u": "k_bicg_u (x, r update + dots)",
+                "residual": "k_*_residual (true residual)",
+                "gmres_x": "k_gmres_x (x += V y)"}
+TOL = 1e-10
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--grid", type=int, default=80, help="N of the N^3 grid (default 80)")
+    ap.add_argument("--cpu-sample-iters", type=int, default=120,
+                    help="iterations per solver the CPU oracle runs for its baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probe", default="gmres_a",
+                    help="kernel class timed with HIP events during the timed steps")
+    ap.add_argument("--no-kernel-table", action="store_true",
+                    help="skip the extra untimed step per kernel class")
+    return ap.parse_args()
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q
+    lo = int(k)
+    hi = min(lo + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def cpu_baseline(P, gpu_iters, sample_iters):
+    """Time the FP64 oracle (single thread) on a bounded sample of the step: GS(p) in full and
+    `sample_iters` iterations of each solver; scale to one full step with the iteration
+    counts of the GPU run (the same algorithm takes the same number of iterations)."""
+    import oracle
+    t_total = 0.0
+    detail = {}
+    for p, method in VARIANTS:
+        t0 = time.perf_counter()
+        vo, bo, nrm, w = oracle.gs_scale(P, P.b, p)
+        t_gs = time.perf_counter() - t0
+        S = P.copy()
+        S.val, S.b = vo, bo
+        W = None if p == 2 else w
+        t0 = time.perf_counter()
+        if method == "bicgstab":
+            _, info = oracle.bicgstab(S, bo, tol=TOL, weights=W, maxit=sample_iters)
+        else:
+            _, info = oracle.gmres(S, bo, m=30, tol=TOL, weights=W, maxit=sample_iters)
+        t_it = (time.perf_counter() - t0) / max(info.iters, 1)
+        key = f"gs{p}_{method}"
+        est = t_gs + t_it * gpu_iters[key]
+        detail[key] = {"gs_s": round(t_gs, 4), "s_per_iter": round(t_it, 5),
+                       "sampled_iters": info.iters, "est_solve_s": round(est, 3)}
+        t_total += est
+    return {"value": round(len(VARIANTS) / t_total, 4), "unit": "solves/s", "cores": 1,
+            "kind": "oracle",
+            "sample": (f"GS(p) in full plus the first {sample_iters} iterations of each of the "
+                       f"4 solves, single-threaded FP64 C oracle; seconds/iteration scaled by "
+                       f"the GPU run's iteration counts"),
+            "per_variant": detail}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding is described in DESIGN.md but not implemented", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_0812_2769_amd import gsk, problems
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    P = problems.config2(args.grid)
+    print(f"bench: generated {P.name} n={P.n} nnz={P.nnz} in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    A = gsk.CsrMatrix.from_problem(P, dev)
+    b = torch.from_numpy(P.b).to(dev)
+    n = P.n
+    # Preallocated outputs and workspaces (outside the timed region)
+    val_s = torch.empty_like(A.val)
+    b_s = torch.empty_like(b)
+    weights = torch.empty(n, dtype=torch.float64, device=dev)
+    x = torch.empty(n, dtype=torch.float64, device=dev)
+    ws_gs = gsk.workspace(gsk.METHOD_GS, n, 0, dev)
+    ws_gm = gsk.workspace(gsk.METHOD_GMRES, n, 30, dev)
+    ws_bi = gsk.workspace(gsk.METHOD_BICGSTAB, n, 0, dev)
+    As = A.with_values(val_s)
+    c_A = A.c_struct()
+    import ctypes
+    stream = torch.cuda.current_stream(dev).cuda_stream
+
+    def gs(p):
+        rc = gsk.lib.gsk_gs_scale(ctypes.byref(c_A), b.data_ptr(), p, val_s.data_ptr(),
+                                  b_s.data_ptr(), None, weights.data_ptr(), ws_gs.data_ptr(),
+                                  ws_gs.numel(), stream)
+        if rc != 0:
+            raise gsk.GskError(rc, gsk.lib.gsk_last_error().decode())
+
+    def solve(p, method):
+        gs(p)
+        w = None if p == 2 else weights
+        if method == "bicgstab":
+            return gsk.bicgstab(As, b_s, tol=TOL, stop_weights=w, ws=ws_bi, x_out=x)[1]
+        return gsk.gmres(As, b_s, m=30, tol=TOL, stop_weights=w, ws=ws_gm, x_out=x)[1]
+
+    def step(lat, infos):
+        for p, method in VARIANTS:
+            t = time.perf_counter()
+            info = solve(p, method)
+            lat[f"gs{p}_{method}"].append(time.perf_counter() - t)
+            infos[f"gs{p}_{method}"] = info
+
+    lat = {f"gs{p}_{m}": [] for p, m in VARIANTS}
+    infos = {}
+    for i in range(args.warmup):
+        step({k: [] for k in lat}, infos)
+        print(f"bench: warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    gsk.probe_begin(args.probe)
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        step(lat, infos)
+        print(f"bench: step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    probe = gsk.probe_end()
+
+    def achieved(pr):
+        if pr["total_ms"] <= 0 or pr["busy_launches"] == 0:
+            return None
+        return {"achieved_GBs": round(pr["bytes"] / (pr["total_ms"] * 1e-3) / 1e9, 1),
+                "avg_launch_us": round(1e3 * pr["total_ms"] / pr["launches"], 3),
+                "bytes_per_launch": round(pr["bytes"] / pr["busy_launches"]),
+                "launches": pr["launches"], "busy_launches": pr["busy_launches"]}
+
+    kernels = {}
+    if not args.no_kernel_table:
+        for cls in gsk.KCLASS:
+            gsk.probe_begin(cls)
+            step({k: [] for k in lat}, {})
+            kernels[cls] = achieved(gsk.probe_end())
+
+    for key, info in infos.items():
+        if info.status != gsk.CONVERGED:
+            print(f"bench: WARNING {key} ended {info.status_name} at relres "
+                  f"{info.relres_true:.2e}", file=sys.stderr, flush=True)
+    solves = len(VARIANTS) * args.steps
+    iters_step = sum(i.iters for i in infos.values())
+    per_variant = {k: {"iters": infos[k].iters, "status": infos[k].status_name,
+                       "relres_true": infos[k].relres_true,
+                       "p50_ms": round(1e3 * pct(lat[k], 0.5), 3),
+                       "p99_ms": round(1e3 * pct(lat[k], 0.99), 3)} for k in lat}
+    all_lat = [v for k in lat for v in lat[k]]
+    out = {
+        "metric": METRIC,
+        "value": round(solves / elapsed, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"config2: {args.grid}^3 7-point convection-diffusion, 8 random "
+                               f"slabs, FP64 CSR; GS(1|2) x (Bi-CGSTAB | GMRES(30)), tol 1e-10",
+                   "n": n, "nnz": P.nnz, "solves_per_step": len(VARIANTS), "tol": TOL},
+        "iterations_per_s": round(iters_step * args.steps / elapsed, 1),
+        "latency_p50_ms": round(1e3 * pct(all_lat, 0.5), 3),
+        "latency_p99_ms": round(1e3 * pct(all_lat, 0.99), 3),
+        "per_variant": per_variant,
+        "roofline": None,
+        "cpu_baseline": None,
+        "kernels": kernels,
+    }
+    a = achieved(probe)
+    if a is not None:
+        out["roofline"] = {
+            "bound": "hbm", "achieved": a["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(a["achieved_GBs"] / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": KERNEL_NAMES[args.probe], "avg_launch_us": a["avg_launch_us"],
+            "bytes_per_launch": a["bytes_per_launch"], "launches": a["launches"],
+            "busy_launches": a["busy_launches"],
+            "note": ("achieved = algorithmic bytes of the working launches / summed HIP-event "
+                     "duration of all launches of the class over the timed steps")}
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(P, {k: infos[k].iters for k in infos},
+                                           args.cpu_sample_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,238 @@
+/*
+ * gsk: geometric scaling GS(p) followed by restarted GMRES(m) or Bi-CGSTAB, on one
+ * AMD Instinct MI355X (gfx950). C ABI.
+ *
+ * Paper: D. Gordon, R. Gordon, "Geometric scaling: a simple preconditioner for certain
+ * linear systems with discontinuous coefficients" (2009). The problem statement is in
+ * section 2: a consistent system A x = b (eq. (1)) with no zero row; D = diag(1/||a_i||_p);
+ * the geometrically scaled system D A x = D b (eq. (2)); Krylov solution from x0 (section
+ * 2.1) with the relative-residual stopping test of section 2.2.
+ *
+ * Conventions for every entry point:
+ *  - Matrix, vector and workspace pointers are DEVICE pointers (HIP device memory of the
+ *    current device), owned by the caller. The library never frees them and keeps no
+ *    pointer after the call returns. Vectors are dense FP64 arrays of length n.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream). All device work
+ *    is enqueued on it. Entry points that report results to the host (gs_scale's error
+ *    checks, the solvers' gsk_info, arnoldi's step count) synchronise that stream before
+ *    returning; gsk_spmv does not.
+ *  - The return value is GSK_OK (0) or a negative GSK_ERR_* code; gsk_last_error() then
+ *    gives a message (thread-local, valid until the next call from the same thread).
+ *    Non-convergence of a solver is not an error: it is reported in gsk_info.status.
+ *  - Matrices are CSR with int32 row pointers and column indices (0-based, columns sorted
+ *    ascending within each row, no duplicates) and FP64 values.
+ *  - Nothing is thrown across the ABI.
+ */
+#ifndef GSK_H
+#define GSK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GSK_VERSION 1
+
+/* Return codes */
+#define GSK_OK 0
+#define GSK_ERR_INVALID_ARG (-1) /* bad size, NULL pointer, p < 1, m out of range, ...     */
+#define GSK_ERR_ZERO_ROW (-2)    /* a row of A is zero: the paper's assumption is violated */
+#define GSK_ERR_NONFINITE (-3)   /* NaN or Inf in A or b, or a row norm overflowed          */
+#define GSK_ERR_WORKSPACE (-4)   /* workspace NULL, too small or misaligned (256 B)         */
+#define GSK_ERR_DEVICE (-5)      /* a HIP runtime call failed                               */
+
+/* Solver outcomes (gsk_info.status) */
+#define GSK_CONVERGED 0  /* true relative residual below tol                               */
+#define GSK_MAXIT 1      /* iteration cap reached (the paper's cap is 10,000, section 2.2)  */
+#define GSK_BREAKDOWN 2  /* a Krylov breakdown test fired (see gsk_options.breakdown_eps)  */
+#define GSK_STAGNATED 3  /* three recursive estimates below tol in a row failed the true    */
+                         /* residual check (the updated residual drifted from b - A x)      */
+
+/* Breakdown tests (gsk_info.breakdown_test) */
+#define GSK_BRK_NONE 0
+#define GSK_BRK_SIGMA 1   /* Bi-CGSTAB: |(r^, A p)| <= eps_b ||r^|| ||A p||                   */
+#define GSK_BRK_OMEGA 2   /* Bi-CGSTAB: |(t, s)| <= eps_b ||t|| ||s||                         */
+#define GSK_BRK_RHO 3     /* Bi-CGSTAB: |(r^, r)| <= eps_b ||r^|| ||r||                       */
+#define GSK_BRK_GIVENS 4  /* GMRES: the Hessenberg column to rotate is exactly zero          */
+
+/* Methods for gsk_workspace_bytes */
+#define GSK_METHOD_GS 0
+#define GSK_METHOD_GMRES 1
+#define GSK_METHOD_BICGSTAB 2
+#define GSK_METHOD_ARNOLDI 3
+
+/* Largest restart length supported by gsk_gmres / gsk_arnoldi. */
+#define GSK_MAX_RESTART 64
+
+typedef struct gsk_csr {
+    int32_t n;               /* rows = columns, n >= 1                                */
+    int64_t nnz;             /* = row_ptr[n] (checked against the device copy)        */
+    const int32_t* row_ptr;  /* device [n+1], row_ptr[0] = 0, non-decreasing          */
+    const int32_t* col_idx;  /* device [nnz], each in [0, n)                          */
+    const double* val;       /* device [nnz]                                          */
+} gsk_csr;
+
+typedef struct gsk_options {
+    int32_t maxit;              /* iteration cap (GMRES: Arnoldi steps; Bi-CGSTAB:
+                                   iterations). Default 10000 (section 2.2).              */
+    double breakdown_eps;       /* relative breakdown threshold. Default 1e-16 *
+                                   DBL_EPSILON: the paper relaxes AZTEC's brkdown_tol
+                                   (= DBL_EPSILON) by about 1e-16 (section 2.2).          */
+    const double* stop_weights; /* device [n] or NULL. The stopping test is made on the
+                                   GS(2)-scaled system (section 2.2); when the system was
+                                   scaled by GS(p) with p != 2, pass the weights
+                                   ||a_i||_p/||a_i||_2 written by gsk_gs_scale, and the
+                                   test measures ||W (b - A x)|| instead of ||b - A x||.  */
+    int32_t check_every;        /* Bi-CGSTAB: iterations enqueued between host status
+                                   reads (default 8; 1..256). GMRES reads once per cycle. */
+} gsk_options;
+
+typedef struct gsk_info {
+    int32_t iters;            /* GMRES: Arnoldi steps; Bi-CGSTAB: iterations (a half-step
+                                 exit counts as one)                                       */
+    int32_t restarts;         /* GMRES: cycles after the first; Bi-CGSTAB: recurrence
+                                 restarts after a failed true-residual check               */
+    int32_t status;           /* GSK_CONVERGED / GSK_MAXIT / GSK_BREAKDOWN / GSK_STAGNATED  */
+    int32_t half_step;        /* Bi-CGSTAB: 1 if it stopped on ||s|| after half a step      */
+    int32_t verify_failures;  /* consecutive failed true-residual checks at the end        */
+    int32_t breakdown_test;   /* with GSK_BREAKDOWN: which test fired (GSK_BRK_*), else 0    */
+    double relres_recursive;  /* last recursive estimate ||W r||/||W r0||                  */
+    double relres_true;       /* ||W (b - A x)|| / ||W (b - A x0)|| at return              */
+} gsk_info;
+
+/* Fills *opt with the defaults listed above. */
+void gsk_default_options(gsk_options* opt);
+
+/* Bytes of device workspace an entry point needs for a system of n rows (m: restart length
+ * for GSK_METHOD_GMRES / GSK_METHOD_ARNOLDI, ignored otherwise). Returns 0 for invalid
+ * arguments. The workspace must be 256-byte aligned; its contents need no initialisation
+ * and are garbage afterwards. */
+size_t gsk_workspace_bytes(int32_t method, int32_t n, int32_t m);
+
+/*
+ * GS(p) geometric scaling (section 1; section 2, eq. (2)): for each row i,
+ *   nrm_i = ||a_i||_p = (sum_j |a_ij|^p)^(1/p),   a_ij <- a_ij / nrm_i,   b_i <- b_i / nrm_i,
+ * so that every row of the scaled matrix has unit Lp-norm. p >= 1 is an integer (p = 2 in
+ * the paper's experiments; p = 1 is AZTEC's "row-sum scaling").
+ *   A        : input matrix (A->val is read).
+ *   b        : device [n] input right-hand side.
+ *   val_out  : device [nnz] scaled values (may equal A->val for in-place scaling).
+ *   b_out    : device [n] scaled right-hand side (may equal b).
+ *   row_norm : device [n] or NULL; receives nrm_i.
+ *   stop_weight : device [n] or NULL; receives ||a_i||_p / ||a_i||_2, the stop-test weights
+ *              to pass in gsk_options.stop_weights when p != 2 (all ones for p = 2).
+ *   ws, ws_bytes : workspace of gsk_workspace_bytes(GSK_METHOD_GS, n, 0) bytes.
+ * Errors: GSK_ERR_INVALID_ARG (p < 1, NULL pointers, n < 1), GSK_ERR_ZERO_ROW (some
+ * sum_j |a_ij|^p is zero), GSK_ERR_NONFINITE (NaN/Inf in A or b, or a norm that overflows).
+ * On GSK_ERR_ZERO_ROW / GSK_ERR_NONFINITE the outputs are unspecified (rows that passed are
+ * written, the others are not). Synchronises `stream`.
+ */
+int gsk_gs_scale(const gsk_csr* A, const double* b, int32_t p, double* val_out, double* b_out,
+                 double* row_norm, double* stop_weight, void* ws, size_t ws_bytes,
+                 void* stream);
+
+/*
+ * y = A x, FP64. Each row is summed in storage order with every product rounded before it
+ * is added (so the result equals a sequential CPU loop without fused multiply-add).
+ * x and y must not overlap. Asynchronous: enqueued on `stream`, no synchronisation.
+ * This is the sparse product inside every Krylov step of section 2's solvers.
+ */
+int gsk_spmv(const gsk_csr* A, const double* x, double* y, void* stream);
+
+/*
+ * m steps of Arnoldi with double classical Gram-Schmidt (section 2: AZTEC's GMRES
+ * orthogonalises with a double classical Gram-Schmidt step), started at r0 != 0:
+ *   v_1 = r0/||r0||; for j = 1..m: w = A v_j; twice { c = V_j^T w; w -= V_j c; h_{1:j,j} += c };
+ *   h_{j+1,j} = ||w||; v_{j+1} = w / h_{j+1,j}.
+ * Stops early at a happy breakdown (h_{j+1,j} <= eps_b ||A v_j||, eps_b = 1e-16*DBL_EPSILON).
+ *   V : device, column-major n x (m+1) with leading dimension ldv >= n; receives v_1..v_{k+1}
+ *       (v_{k+1} only when no breakdown occurred).
+ *   H : device, column-major (m+1) x m with leading dimension m+1; receives the Hessenberg
+ *       matrix (entries beyond the steps taken are zero).
+ *   steps : host int; receives the number of steps k taken (<= m).
+ *   ws, ws_bytes : workspace of gsk_workspace_bytes(GSK_METHOD_ARNOLDI, n, m) bytes.
+ * 1 <= m <= GSK_MAX_RESTART. Synchronises `stream`.
+ */
+int gsk_arnoldi(const gsk_csr* A, const double* r0, int32_t m, double* V, int64_t ldv,
+                double* H, int32_t* steps, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Restarted GMRES(m) (section 2: restarted GMRES with double classical Gram-Schmidt) on
+ * A x = b, normally the GS-scaled system.
+ *   x   : device [n]; holds x0 on entry (the paper uses x0 = 0, section 2.1) and the
+ *         solution on return.
+ *   m   : restart length, 1 <= m <= GSK_MAX_RESTART (the paper uses 10).
+ *   tol : stop when ||W (b - A x)|| / ||W (b - A x0)|| < tol (section 2.2), verified with the
+ *         true residual at the end of a cycle; W from opt->stop_weights (identity if NULL).
+ *   opt : NULL for the defaults.
+ *   info: host; receives the outcome.
+ *   ws, ws_bytes : workspace of gsk_workspace_bytes(GSK_METHOD_GMRES, n, m) bytes.
+ * Each Arnoldi step's orthogonalisation coefficients, the Givens rotations and the
+ * residual estimate stay on the device; the host reads a small status block once per cycle.
+ * Synchronises `stream`.
+ */
+int gsk_gmres(const gsk_csr* A, const double* b, double* x, int32_t m, double tol,
+              const gsk_options* opt, gsk_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Bi-CGSTAB (section 2: van der Vorst's Bi-CGSTAB) on A x = b, shadow residual r^ = r0.
+ * Arguments as for gsk_gmres without m; workspace gsk_workspace_bytes(GSK_METHOD_BICGSTAB,
+ * n, 0). All scalars (rho, alpha, omega, beta) stay on the device; the host reads a status
+ * block every opt->check_every iterations. Synchronises `stream`.
+ */
+int gsk_bicgstab(const gsk_csr* A, const double* b, double* x, double tol,
+                 const gsk_options* opt, gsk_info* info, void* ws, size_t ws_bytes,
+                 void* stream);
+
+/*
+ * Measurement hook (not part of the method): between gsk_probe_begin(c) and gsk_probe_end,
+ * every launch of kernel class c made by the solvers is bracketed by a pair of HIP events on
+ * the solver's stream, and each launch that did work (rather than returning at once because
+ * the solve had already finished) adds its algorithmic HBM bytes to a device counter, which
+ * is collected at the end of each solve. Algorithmic bytes per launch, n rows, nnz nonzeros,
+ * FP64 values, int32 indices, step j of an Arnoldi cycle (basis columns 0..j):
+ *   GMRES_A   12 nnz + 4 (n+1) + 8 n (j+2)   CSR + basis columns 0..j (column j is also the
+ *                                            product's source) + write w
+ *   GMRES_B   8 n (j+3)                      basis columns 0..j, read and write w
+ *   GMRES_C   8 n (j+3)                      basis columns 0..j, read w, write u_{j+1}
+ *   BICG_P    12 nnz + 4 (n+1) + 48 n        CSR, r p v r^, write p v (32 n on the first
+ *                                            iteration after a start: r r^, write p v)
+ *   BICG_S    12 nnz + 4 (n+1) + 24 n        CSR, r v, write t (+8 n with stop weights)
+ *   BICG_U    64 n                           r v p x t r^, write x r (+8 n with weights)
+ *   RESIDUAL  12 nnz + 4 (n+1) + 32 n        CSR, x b, write r (and r^ in Bi-CGSTAB: +8 n)
+ *   GMRES_X   8 n (k+2)                      k basis columns, read and write x
+ * Process-wide; not for concurrent use from several host threads. gsk_probe_end
+ * synchronises the device. The event records themselves add a little time per launch.
+ */
+#define GSK_KCLASS_GMRES_A 1
+#define GSK_KCLASS_GMRES_B 2
+#define GSK_KCLASS_GMRES_C 3
+#define GSK_KCLASS_BICG_P 4
+#define GSK_KCLASS_BICG_S 5
+#define GSK_KCLASS_BICG_U 6
+#define GSK_KCLASS_RESIDUAL 7
+#define GSK_KCLASS_GMRES_X 8
+
+typedef struct gsk_probe_result {
+    int64_t launches;       /* launches of the class that were timed                  */
+    int64_t busy_launches;  /* of those, launches that did work                       */
+    double total_ms;        /* sum of the event-measured durations of all launches    */
+    double bytes;           /* sum of the algorithmic bytes of the working launches   */
+} gsk_probe_result;
+
+int gsk_probe_begin(int32_t kernel_class);
+int gsk_probe_end(gsk_probe_result* out);
+
+/* Message for the last error returned on this thread ("" if none). */
+const char* gsk_last_error(void);
+
+/* GSK_VERSION of the built library. */
+int gsk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSK_H */

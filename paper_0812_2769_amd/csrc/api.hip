@@ -1,0 +1,377 @@
+// C ABI of the gsk library: argument checks, workspace sizing, error reporting.
+// The declarations and their documentation live in include/gsk.h.
+#include <float.h>
+#include <stdarg.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <atomic>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "gsk.h"
+#include "gsk_host.hpp"
+
+namespace gsk {
+
+namespace {
+thread_local std::string g_err;
+
+struct Pinned {
+  Summary sum[2];
+  int flags[4];
+};
+thread_local Pinned* g_pinned = nullptr;
+
+int set_err(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int set_err(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_err(hipError_t e, const char* what) {
+  return set_err(GSK_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+Pinned* pinned() {
+  if (!g_pinned) {
+    void* p = nullptr;
+    if (hipHostMalloc(&p, sizeof(Pinned), hipHostMallocDefault) != hipSuccess) return nullptr;
+    g_pinned = static_cast<Pinned*>(p);
+  }
+  return g_pinned;
+}
+
+int check_csr(const gsk_csr* A) {
+  if (!A) return set_err(GSK_ERR_INVALID_ARG, "matrix is NULL");
+  if (A->n < 1) return set_err(GSK_ERR_INVALID_ARG, "n = %d must be >= 1", (int)A->n);
+  if (A->nnz < 0 || A->nnz > (int64_t)INT32_MAX)
+    return set_err(GSK_ERR_INVALID_ARG, "nnz = %lld out of range", (long long)A->nnz);
+  if (!A->row_ptr) return set_err(GSK_ERR_INVALID_ARG, "row_ptr is NULL");
+  if (A->nnz > 0 && (!A->col_idx || !A->val))
+    return set_err(GSK_ERR_INVALID_ARG, "col_idx/val is NULL");
+  return GSK_OK;
+}
+
+int check_ws(void* ws, size_t ws_bytes, size_t need) {
+  if (!ws) return set_err(GSK_ERR_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+    return set_err(GSK_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  if (ws_bytes < need)
+    return set_err(GSK_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, need);
+  return GSK_OK;
+}
+
+Csr to_csr(const gsk_csr* A) {
+  return Csr{A->n, A->nnz, A->row_ptr, A->col_idx, A->val};
+}
+
+int params_from(const gsk_options* opt, SolveParams& prm, double tol) {
+  gsk_options o;
+  gsk_default_options(&o);
+  if (opt) o = *opt;
+  if (!(tol > 0.0) || !isfinite(tol)) return set_err(GSK_ERR_INVALID_ARG, "tol must be > 0");
+  if (o.maxit < 0) return set_err(GSK_ERR_INVALID_ARG, "maxit must be >= 0");
+  if (!(o.breakdown_eps >= 0.0) || !isfinite(o.breakdown_eps))
+    return set_err(GSK_ERR_INVALID_ARG, "breakdown_eps must be finite and >= 0");
+  if (o.check_every < 1 || o.check_every > 256)
+    return set_err(GSK_ERR_INVALID_ARG, "check_every must be in [1, 256]");
+  prm.maxit = o.maxit;
+  prm.tol = tol;
+  prm.eps_b = o.breakdown_eps;
+  prm.weights = o.stop_weights;
+  prm.check_every = o.check_every;
+  return GSK_OK;
+}
+
+void fill_info(gsk_info* info, const Summary& s) {
+  if (!info) return;
+  info->iters = s.iters;
+  info->restarts = s.restarts;
+  info->status = s.status;
+  info->half_step = s.half;
+  info->verify_failures = s.fails;
+  info->breakdown_test = s.status == GSK_BREAKDOWN ? s.brk : 0;
+  info->relres_recursive = s.relres_rec;
+  info->relres_true = s.relres_true;
+}
+
+struct Probe {
+  std::mutex mu;
+  std::atomic<int> cls{0};
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pairs;
+  hipEvent_t open = nullptr;
+  double total_ms = 0.0;
+  long long launches = 0;
+  long long busy = 0;
+  double bytes = 0.0;
+};
+
+Probe& probe_state() {
+  static Probe p;
+  return p;
+}
+
+hipEvent_t take_event(Probe& p) {
+  if (!p.pool.empty()) {
+    hipEvent_t e = p.pool.back();
+    p.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Adds the elapsed times of all recorded pairs (the caller has synchronised their streams)
+// and returns the events to the pool.
+void harvest(Probe& p) {
+  for (auto& pr : p.pairs) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) p.total_ms += ms;
+    p.launches += 1;
+    p.pool.push_back(pr.first);
+    p.pool.push_back(pr.second);
+  }
+  p.pairs.clear();
+}
+
+}  // namespace
+
+int probe_class() { return probe_state().cls.load(std::memory_order_relaxed); }
+
+void probe_begin(hipStream_t s) {
+  Probe& p = probe_state();
+  std::lock_guard<std::mutex> g(p.mu);
+  p.open = take_event(p);
+  if (p.open && hipEventRecord(p.open, s) != hipSuccess) {
+    p.pool.push_back(p.open);
+    p.open = nullptr;
+  }
+}
+
+void probe_end(hipStream_t s) {
+  Probe& p = probe_state();
+  std::lock_guard<std::mutex> g(p.mu);
+  if (!p.open) return;
+  hipEvent_t e = take_event(p);
+  if (e && hipEventRecord(e, s) == hipSuccess) {
+    p.pairs.emplace_back(p.open, e);
+  } else {
+    p.pool.push_back(p.open);
+    if (e) p.pool.push_back(e);
+  }
+  p.open = nullptr;
+}
+
+void probe_collect(const Work* device_work, hipStream_t s) {
+  Work w;
+  if (hipMemcpyAsync(&w, device_work, sizeof(Work), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return;
+  Probe& p = probe_state();
+  std::lock_guard<std::mutex> g(p.mu);
+  const int c = p.cls.load(std::memory_order_relaxed);
+  if (c <= KC_NONE || c >= KC_COUNT) return;
+  p.busy += w.busy[c];
+  p.bytes += w.bytes[c];
+  harvest(p);
+}
+
+Summary* pinned_summaries() {
+  Pinned* p = pinned();
+  return p ? p->sum : nullptr;
+}
+
+size_t workspace_bytes(int method, int n, int m) {
+  if (n < 1) return 0;
+  const size_t ld = vec_ld(n) * sizeof(double);
+  const size_t head = head_bytes(n);
+  switch (method) {
+    case GSK_METHOD_GS:
+      return kCtlBytes + kFlagBytes;
+    case GSK_METHOD_GMRES:
+      if (m < 1 || m > GSK_MAX_RESTART) return 0;
+      return head + (size_t)(m + 2) * ld;
+    case GSK_METHOD_ARNOLDI:
+      if (m < 1 || m > GSK_MAX_RESTART) return 0;
+      return head + ld;
+    case GSK_METHOD_BICGSTAB:
+      return head + 7 * ld;
+    default:
+      return 0;
+  }
+}
+
+}  // namespace gsk
+
+using namespace gsk;
+
+static_assert(GSK_MAX_RESTART == gsk::MMAX, "restart limit mismatch");
+
+extern "C" {
+
+void gsk_default_options(gsk_options* opt) {
+  if (!opt) return;
+  opt->maxit = 10000;
+  opt->breakdown_eps = 1e-16 * DBL_EPSILON;
+  opt->stop_weights = nullptr;
+  opt->check_every = 8;
+}
+
+size_t gsk_workspace_bytes(int32_t method, int32_t n, int32_t m) {
+  return gsk::workspace_bytes(method, n, m);
+}
+
+int gsk_version(void) { return GSK_VERSION; }
+
+int gsk_probe_begin(int32_t kernel_class) {
+  g_err.clear();
+  if (kernel_class < GSK_KCLASS_GMRES_A || kernel_class > GSK_KCLASS_GMRES_X)
+    return set_err(GSK_ERR_INVALID_ARG, "unknown kernel class %d", (int)kernel_class);
+  Probe& p = probe_state();
+  std::lock_guard<std::mutex> g(p.mu);
+  p.total_ms = 0.0;
+  p.launches = 0;
+  p.busy = 0;
+  p.bytes = 0.0;
+  p.pairs.clear();
+  p.open = nullptr;
+  p.cls.store(kernel_class, std::memory_order_relaxed);
+  return GSK_OK;
+}
+
+int gsk_probe_end(gsk_probe_result* out) {
+  g_err.clear();
+  Probe& p = probe_state();
+  hipError_t e = hipDeviceSynchronize();
+  std::lock_guard<std::mutex> g(p.mu);
+  harvest(p);
+  if (out) {
+    out->launches = p.launches;
+    out->busy_launches = p.busy;
+    out->total_ms = p.total_ms;
+    out->bytes = p.bytes;
+  }
+  p.cls.store(0, std::memory_order_relaxed);
+  if (e != hipSuccess) return hip_err(e, "probe end");
+  return GSK_OK;
+}
+
+const char* gsk_last_error(void) { return g_err.c_str(); }
+
+int gsk_gs_scale(const gsk_csr* A, const double* b, int32_t p, double* val_out, double* b_out,
+                 double* row_norm, double* stop_weight, void* ws, size_t ws_bytes,
+                 void* stream) {
+  g_err.clear();
+  int rc = check_csr(A);
+  if (rc) return rc;
+  if (p < 1) return set_err(GSK_ERR_INVALID_ARG, "p = %d must be >= 1", (int)p);
+  if (!b || !b_out || (A->nnz > 0 && !val_out))
+    return set_err(GSK_ERR_INVALID_ARG, "b, b_out or val_out is NULL");
+  rc = check_ws(ws, ws_bytes, gsk::workspace_bytes(GSK_METHOD_GS, A->n, 0));
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace W = carve(ws, A->n);
+  Csr C = to_csr(A);
+  hipError_t e;
+  if ((e = launch_clear_flags(W.flags, s)) != hipSuccess) return hip_err(e, "clear flags");
+  if ((e = launch_validate(C, W.flags, s)) != hipSuccess) return hip_err(e, "validate");
+  if ((e = launch_gs_scale(C, b, p, val_out, b_out, row_norm, stop_weight, W.flags, s)) !=
+      hipSuccess)
+    return hip_err(e, "gs_scale launch");
+  Pinned* pin = pinned();
+  if (!pin) return set_err(GSK_ERR_DEVICE, "pinned host buffer allocation failed");
+  if ((e = hipMemcpyAsync(pin->flags, W.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s)) !=
+      hipSuccess)
+    return hip_err(e, "flag read-back");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_err(e, "gs_scale");
+  if (pin->flags[0])
+    return set_err(GSK_ERR_INVALID_ARG,
+                   "CSR structure invalid (row_ptr not monotone from 0 to nnz, or a column "
+                   "index outside [0, n))");
+  if (pin->flags[2]) return set_err(GSK_ERR_NONFINITE, "non-finite entry or row norm overflow");
+  if (pin->flags[1]) return set_err(GSK_ERR_ZERO_ROW, "a row of A has zero Lp-norm");
+  return GSK_OK;
+}
+
+int gsk_spmv(const gsk_csr* A, const double* x, double* y, void* stream) {
+  g_err.clear();
+  int rc = check_csr(A);
+  if (rc) return rc;
+  if (!x || !y) return set_err(GSK_ERR_INVALID_ARG, "x or y is NULL");
+  hipError_t e = launch_spmv(to_csr(A), x, y, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_err(e, "spmv launch");
+  return GSK_OK;
+}
+
+int gsk_arnoldi(const gsk_csr* A, const double* r0, int32_t m, double* V, int64_t ldv, double* H,
+                int32_t* steps, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  int rc = check_csr(A);
+  if (rc) return rc;
+  if (m < 1 || m > GSK_MAX_RESTART)
+    return set_err(GSK_ERR_INVALID_ARG, "m = %d must be in [1, %d]", (int)m, GSK_MAX_RESTART);
+  if (!r0 || !V || !H || !steps) return set_err(GSK_ERR_INVALID_ARG, "NULL argument");
+  if (ldv < A->n) return set_err(GSK_ERR_INVALID_ARG, "ldv < n");
+  rc = check_ws(ws, ws_bytes, gsk::workspace_bytes(GSK_METHOD_ARNOLDI, A->n, m));
+  if (rc) return rc;
+  SolveResult r = arnoldi_run(to_csr(A), r0, m, V, ldv, H, ws, 1e-16 * DBL_EPSILON,
+                              static_cast<hipStream_t>(stream));
+  if (r.code == -1)
+    return set_err(GSK_ERR_INVALID_ARG, "invalid CSR structure or zero/non-finite r0");
+  if (r.code) return set_err(GSK_ERR_DEVICE, "arnoldi: HIP failure (%s)",
+                             hipGetErrorString(hipGetLastError()));
+  *steps = r.sum.steps;
+  return GSK_OK;
+}
+
+static int solve_common(bool is_gmres, const gsk_csr* A, const double* b, double* x, int32_t m,
+                        double tol, const gsk_options* opt, gsk_info* info, void* ws,
+                        size_t ws_bytes, void* stream) {
+  g_err.clear();
+  int rc = check_csr(A);
+  if (rc) return rc;
+  if (!b || !x) return set_err(GSK_ERR_INVALID_ARG, "b or x is NULL");
+  if (is_gmres && (m < 1 || m > GSK_MAX_RESTART))
+    return set_err(GSK_ERR_INVALID_ARG, "m = %d must be in [1, %d]", (int)m, GSK_MAX_RESTART);
+  SolveParams prm;
+  rc = params_from(opt, prm, tol);
+  if (rc) return rc;
+  rc = check_ws(ws, ws_bytes,
+                gsk::workspace_bytes(is_gmres ? GSK_METHOD_GMRES : GSK_METHOD_BICGSTAB, A->n, m));
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SolveResult r = is_gmres ? gmres_solve(to_csr(A), b, x, m, prm, ws, s)
+                           : bicgstab_solve(to_csr(A), b, x, prm, ws, s);
+  if (r.code == -1)
+    return set_err(GSK_ERR_INVALID_ARG,
+                   "CSR structure invalid (row_ptr not monotone from 0 to nnz, or a column "
+                   "index outside [0, n))");
+  if (r.code) return set_err(GSK_ERR_DEVICE, "solver: HIP failure (%s)",
+                             hipGetErrorString(hipGetLastError()));
+  fill_info(info, r.sum);
+  return GSK_OK;
+}
+
+int gsk_gmres(const gsk_csr* A, const double* b, double* x, int32_t m, double tol,
+              const gsk_options* opt, gsk_info* info, void* ws, size_t ws_bytes, void* stream) {
+  return solve_common(true, A, b, x, m, tol, opt, info, ws, ws_bytes, stream);
+}
+
+int gsk_bicgstab(const gsk_csr* A, const double* b, double* x, double tol,
+                 const gsk_options* opt, gsk_info* info, void* ws, size_t ws_bytes,
+                 void* stream) {
+  return solve_common(false, A, b, x, 0, tol, opt, info, ws, ws_bytes, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,491 @@
+// Bi-CGSTAB (van der Vorst; section 2 of the paper) on the device, shadow residual r^ = r0.
+//
+// One iteration is three streaming launches, each followed by a one-workgroup finalize launch
+// that sums the per-workgroup partials in a fixed order; every scalar stays on the device:
+//
+//   P  p = r + beta (p - omega v)       (p = r on the first iteration after a (re)start)
+//      v = A p, with the p entries of neighbouring rows recomputed inside the gather, so p
+//      is written once and never re-read for the product;  (r^, v), ||v||
+//      FP -> alpha = rho / (r^, v)
+//   S  s = r - alpha v (recomputed in the gather, never stored), t = A s;
+//      (t, s), (t, t), ||s||, ||W s||   FS -> half-step test, omega = (t, s) / (t, t)
+//   U  x += alpha p + omega s, r = s - omega t; (r^, r), ||r||, ||W r||
+//      FU -> stop test, rho, beta
+//
+// p and v are double-buffered (parity bit in the control block) because P reads the old p
+// and v of neighbouring rows while it writes the new ones. The residual launch R computes
+// r = b - A x for the initial residual and for every verification of a recursive
+// convergence claim; a failed verification restarts the recurrence from the true residual.
+#include "gsk_host.hpp"
+
+namespace gsk {
+
+struct BArgs {
+  const int* rp;
+  const int* ci;
+  const double* val;
+  int n;
+  int rpb;
+  Ctl* ctl;
+  double* partials;
+  double* r;
+  double* rh;
+  double* p[2];
+  double* v[2];
+  double* t;
+  double* x;
+  const double* b;
+  const double* W;
+  double csr_bytes;   // 12 nnz + 4 (n+1)
+};
+
+__device__ inline void brange(const BArgs& a, int lb, int& begin, int& end) {
+  begin = lb * a.rpb;
+  end = min(a.n, begin + a.rpb);
+  if (begin > a.n) begin = a.n;
+}
+
+__global__ __launch_bounds__(64) void k_bicg_init_ctl(Ctl* c, int maxit, double tol, double eps_b,
+                                                      int has_w) {
+  if (threadIdx.x != 0) return;
+  c->sum.state = ST_INIT;
+  c->sum.status = S_MAXIT;
+  c->sum.iters = 0;
+  c->sum.restarts = 0;
+  c->sum.half = 0;
+  c->sum.fails = 0;
+  c->sum.steps = 0;
+  c->sum.relres_rec = 1.0;
+  c->sum.relres_true = 1.0;
+  c->sum.brk = BRK_NONE;
+  for (int i = 0; i < KC_COUNT; ++i) {
+    c->work.bytes[i] = 0.0;
+    c->work.busy[i] = 0;
+  }
+  c->maxit = maxit;
+  c->m = 0;
+  c->j = c->k = c->claimed = 0;
+  c->first = 1;
+  c->parity = 0;
+  c->has_w = has_w;
+  c->broke = c->happy = 0;
+  c->tol = tol;
+  c->eps_b = eps_b;
+  c->ref = 0.0;
+  c->ratio = 1.0;
+  c->rho = c->rho_old = c->alpha = c->omega = c->beta = c->rh_norm = 0.0;
+}
+
+// R: r = b - A x, r^ = r (initial residual, verification, or final residual after a
+// breakdown); partials ||r||^2, ||W r||^2.
+__global__ __launch_bounds__(BS) void k_bicg_residual(BArgs a, const int* flags) {
+  Ctl* c = a.ctl;
+  const int st = c->sum.state;
+  if (st != ST_INIT && st != ST_VERIFY && st != ST_FINAL) return;
+  if (flags[0]) return;
+  count_work(c, KC_RESIDUAL, a.csr_bytes + 8.0 * a.n * ((st != ST_FINAL ? 4 : 2) + (a.W ? 1 : 0)));
+  __shared__ TileLds L;
+  __shared__ double red[NC_MAX * WAVES];
+  const int nb = gridDim.x;
+  const int lb = logical_block();
+  int rb, re;
+  brange(a, lb, rb, re);
+  double acc[2] = {0.0, 0.0};
+  for (int row0 = rb; row0 < re; row0 += BS) {
+    const int nrows = min(BS, re - row0);
+    const double y = csr_tile(a.rp, a.ci, a.val, row0, nrows, GatherX{a.x}, L);
+    if ((int)threadIdx.x < nrows) {
+      const int row = row0 + threadIdx.x;
+      const double r = a.b[row] - y;
+      if (st != ST_FINAL) {
+        a.r[row] = r;
+        a.rh[row] = r;
+      }
+      acc[0] += r * r;
+      if (a.W) {
+        const double wr = a.W[row] * r;
+        acc[1] += wr * wr;
+      }
+    }
+  }
+  block_partials<2>(acc, 2, a.partials, nb, lb, red);
+}
+
+// FR: reference residual, convergence check of a verification, or (re)start of the recurrence.
+__global__ __launch_bounds__(BS) void k_bicg_fin_residual(Ctl* c, const double* partials, int nb,
+                                                          int has_w, const int* flags) {
+  const int st = c->sum.state;
+  if (st != ST_INIT && st != ST_VERIFY && st != ST_FINAL) return;
+  if (flags[0]) {
+    if (threadIdx.x == 0) {
+      c->sum.state = ST_DONE;
+      c->sum.status = -1;
+    }
+    return;
+  }
+  __shared__ double out[8];
+  small_sums<2>(partials, nb, out);
+  if (threadIdx.x != 0) return;
+  const double nr = sqrt(out[0]);
+  const double nwr = has_w ? sqrt(out[1]) : nr;
+  if (st == ST_INIT) {
+    c->ref = nwr;
+    if (nwr == 0.0) {
+      c->sum.status = S_CONVERGED;
+      c->sum.relres_rec = 0.0;
+      c->sum.relres_true = 0.0;
+      c->sum.state = ST_DONE;
+      return;
+    }
+    if (c->maxit == 0) {
+      c->sum.status = S_MAXIT;
+      c->sum.state = ST_DONE;
+      return;
+    }
+  } else {
+    const double rt = nwr / c->ref;
+    c->sum.relres_true = rt;
+    if (st == ST_FINAL) {
+      c->sum.state = ST_DONE;   // status (breakdown) already set
+      return;
+    }
+    if (rt < c->tol) {
+      c->sum.status = S_CONVERGED;
+      c->sum.state = ST_DONE;
+      return;
+    }
+    if (c->sum.iters >= c->maxit) {
+      c->sum.status = S_MAXIT;
+      c->sum.state = ST_DONE;
+      return;
+    }
+    c->sum.fails += 1;
+    if (c->sum.fails >= 3) {
+      c->sum.status = S_STAGNATED;
+      c->sum.state = ST_DONE;
+      return;
+    }
+    c->sum.restarts += 1;
+  }
+  // (re)start the recurrence from r: r^ = r, rho = (r^, r)
+  c->rh_norm = nr;
+  c->rho = out[0];
+  c->sum.half = 0;
+  if (fabs(c->rho) <= c->eps_b * nr * nr) {
+    c->sum.status = S_BREAKDOWN;
+    c->sum.brk = BRK_RHO;
+    c->sum.state = ST_DONE;
+    return;
+  }
+  c->first = 1;
+  c->sum.state = ST_RUNNING;
+}
+
+// p update, shared by the row's own value and the gather of its neighbours (explicit fma so
+// both evaluations round identically).
+struct GatherP {
+  const double* __restrict__ r;
+  const double* __restrict__ p;
+  const double* __restrict__ v;
+  double beta, omega;
+  int first;
+  __device__ double operator()(int col) const {
+    return first ? r[col] : fma(beta, fma(-omega, v[col], p[col]), r[col]);
+  }
+};
+
+struct GatherS {
+  const double* __restrict__ r;
+  const double* __restrict__ v;
+  double alpha;
+  __device__ double operator()(int col) const { return fma(-alpha, v[col], r[col]); }
+};
+
+// P: new p, v = A p; partials (r^, v), ||v||^2.
+__global__ __launch_bounds__(BS) void k_bicg_p(BArgs a) {
+  Ctl* c = a.ctl;
+  if (c->sum.state != ST_RUNNING) return;
+  count_work(c, KC_BICG_P, a.csr_bytes + 8.0 * a.n * (c->first ? 4 : 6));
+  const int q = c->parity;
+  const double* pin = a.p[q];
+  const double* vin = a.v[q];
+  double* pout = a.p[q ^ 1];
+  double* vout = a.v[q ^ 1];
+  const GatherP G{a.r, pin, vin, c->beta, c->omega, c->first};
+  __shared__ TileLds L;
+  __shared__ double red[NC_MAX * WAVES];
+  const int nb = gridDim.x;
+  const int lb = logical_block();
+  int rb, re;
+  brange(a, lb, rb, re);
+  double acc[2] = {0.0, 0.0};
+  for (int row0 = rb; row0 < re; row0 += BS) {
+    const int nrows = min(BS, re - row0);
+    const double y = csr_tile(a.rp, a.ci, a.val, row0, nrows, G, L);
+    if ((int)threadIdx.x < nrows) {
+      const int row = row0 + threadIdx.x;
+      pout[row] = G(row);
+      vout[row] = y;
+      acc[0] += a.rh[row] * y;
+      acc[1] += y * y;
+    }
+  }
+  block_partials<2>(acc, 2, a.partials, nb, lb, red);
+}
+
+// FP: alpha = rho / (r^, v), or breakdown.
+__global__ __launch_bounds__(BS) void k_bicg_fin_p(Ctl* c, const double* partials, int nb) {
+  if (c->sum.state != ST_RUNNING) return;
+  __shared__ double out[8];
+  small_sums<2>(partials, nb, out);
+  if (threadIdx.x != 0) return;
+  const double sigma = out[0];
+  const double vn = sqrt(out[1]);
+  if (fabs(sigma) <= c->eps_b * c->rh_norm * vn) {
+    c->sum.status = S_BREAKDOWN;
+    c->sum.brk = BRK_SIGMA;
+    c->sum.state = ST_FINAL;
+    return;
+  }
+  c->alpha = c->rho / sigma;
+}
+
+// S: t = A s with s = r - alpha v; partials (t,s), (t,t), ||s||^2, ||W s||^2.
+__global__ __launch_bounds__(BS) void k_bicg_s(BArgs a) {
+  Ctl* c = a.ctl;
+  if (c->sum.state != ST_RUNNING) return;
+  count_work(c, KC_BICG_S, a.csr_bytes + 8.0 * a.n * (a.W ? 4 : 3));
+  const int q = c->parity ^ 1;   // the v written by P in this iteration
+  const GatherS G{a.r, a.v[q], c->alpha};
+  __shared__ TileLds L;
+  __shared__ double red[NC_MAX * WAVES];
+  const int nb = gridDim.x;
+  const int lb = logical_block();
+  int rb, re;
+  brange(a, lb, rb, re);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int row0 = rb; row0 < re; row0 += BS) {
+    const int nrows = min(BS, re - row0);
+    const double y = csr_tile(a.rp, a.ci, a.val, row0, nrows, G, L);
+    if ((int)threadIdx.x < nrows) {
+      const int row = row0 + threadIdx.x;
+      const double s = G(row);
+      a.t[row] = y;
+      acc[0] += y * s;
+      acc[1] += y * y;
+      acc[2] += s * s;
+      if (a.W) {
+        const double ws = a.W[row] * s;
+        acc[3] += ws * ws;
+      }
+    }
+  }
+  block_partials<4>(acc, 4, a.partials, nb, lb, red);
+}
+
+// FS: iteration count, half-step test on ||W s||, omega = (t,s)/(t,t), or breakdown.
+__global__ __launch_bounds__(BS) void k_bicg_fin_s(Ctl* c, const double* partials, int nb,
+                                                   int has_w) {
+  if (c->sum.state != ST_RUNNING) return;
+  __shared__ double out[8];
+  small_sums<4>(partials, nb, out);
+  if (threadIdx.x != 0) return;
+  c->sum.iters += 1;
+  const double sn = sqrt(out[2]);
+  const double est = (has_w ? sqrt(out[3]) : sn) / c->ref;
+  c->sum.relres_rec = est;
+  if (est < c->tol) {
+    c->sum.half = 1;
+    c->sum.state = ST_HALF;
+    return;
+  }
+  const double ts = out[0], tt = out[1];
+  if (fabs(ts) <= c->eps_b * sqrt(tt) * sn) {
+    c->sum.status = S_BREAKDOWN;
+    c->sum.brk = BRK_OMEGA;
+    c->sum.state = ST_FINAL;
+    return;
+  }
+  c->omega = ts / tt;
+}
+
+// U: x += alpha p + omega s, r = s - omega t; partials (r^, r), ||r||^2, ||W r||^2.
+// After a half-step exit only x += alpha p is done.
+__global__ __launch_bounds__(BS) void k_bicg_u(BArgs a) {
+  Ctl* c = a.ctl;
+  const int st = c->sum.state;
+  if (st != ST_RUNNING && st != ST_HALF) return;
+  count_work(c, KC_BICG_U, 8.0 * a.n * (st == ST_HALF ? 3 : (a.W ? 9 : 8)));
+  const int q = c->parity ^ 1;
+  const double* p = a.p[q];
+  const double* v = a.v[q];
+  const double alpha = c->alpha, omega = c->omega;
+  __shared__ double red[NC_MAX * WAVES];
+  const int nb = gridDim.x;
+  const int lb = logical_block();
+  int rb, re;
+  brange(a, lb, rb, re);
+  if (st == ST_HALF) {
+    for (int row = rb + threadIdx.x; row < re; row += BS) a.x[row] = fma(alpha, p[row], a.x[row]);
+    return;
+  }
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int row = rb + threadIdx.x; row < re; row += BS) {
+    const double s = fma(-alpha, v[row], a.r[row]);
+    a.x[row] = fma(omega, s, fma(alpha, p[row], a.x[row]));
+    const double r = fma(-omega, a.t[row], s);
+    a.r[row] = r;
+    acc[0] += a.rh[row] * r;
+    acc[1] += r * r;
+    if (a.W) {
+      const double wr = a.W[row] * r;
+      acc[2] += wr * wr;
+    }
+  }
+  block_partials<3>(acc, 3, a.partials, nb, lb, red);
+}
+
+// FU: stop test on ||W r|| (or the iteration cap), then rho, beta, or breakdown.
+__global__ __launch_bounds__(BS) void k_bicg_fin_u(Ctl* c, const double* partials, int nb,
+                                                   int has_w) {
+  const int st = c->sum.state;
+  if (st != ST_RUNNING && st != ST_HALF) return;
+  if (st == ST_HALF) {
+    if (threadIdx.x == 0) c->sum.state = ST_VERIFY;
+    return;
+  }
+  __shared__ double out[8];
+  small_sums<3>(partials, nb, out);
+  if (threadIdx.x != 0) return;
+  const double rn = sqrt(out[1]);
+  const double est = (has_w ? sqrt(out[2]) : rn) / c->ref;
+  c->sum.relres_rec = est;
+  if (est < c->tol || c->sum.iters >= c->maxit) {
+    c->sum.state = ST_VERIFY;
+    return;
+  }
+  const double rho_new = out[0];
+  if (fabs(rho_new) <= c->eps_b * c->rh_norm * rn) {
+    c->sum.status = S_BREAKDOWN;
+    c->sum.brk = BRK_RHO;
+    c->sum.state = ST_FINAL;
+    return;
+  }
+  c->beta = (rho_new / c->rho) * (c->alpha / c->omega);
+  c->rho_old = c->rho;
+  c->rho = rho_new;
+  c->first = 0;
+  c->parity ^= 1;
+}
+
+static void launch_residual(const BArgs& a, int nb, const int* flags, hipStream_t s) {
+  const bool pr = probe_class() == KC_RESIDUAL;
+  if (pr) probe_begin(s);
+  hipLaunchKernelGGL(k_bicg_residual, dim3(nb), dim3(BS), 0, s, a, flags);
+  if (pr) probe_end(s);
+  hipLaunchKernelGGL(k_bicg_fin_residual, dim3(1), dim3(BS), 0, s, a.ctl,
+                     (const double*)a.partials, nb, a.W ? 1 : 0, flags);
+}
+
+static void launch_iteration(const BArgs& a, int nb, hipStream_t s) {
+  const int hw = a.W ? 1 : 0;
+  const double* pt = a.partials;
+  const int pc = probe_class();
+  if (pc == KC_BICG_P) probe_begin(s);
+  hipLaunchKernelGGL(k_bicg_p, dim3(nb), dim3(BS), 0, s, a);
+  if (pc == KC_BICG_P) probe_end(s);
+  hipLaunchKernelGGL(k_bicg_fin_p, dim3(1), dim3(BS), 0, s, a.ctl, pt, nb);
+  if (pc == KC_BICG_S) probe_begin(s);
+  hipLaunchKernelGGL(k_bicg_s, dim3(nb), dim3(BS), 0, s, a);
+  if (pc == KC_BICG_S) probe_end(s);
+  hipLaunchKernelGGL(k_bicg_fin_s, dim3(1), dim3(BS), 0, s, a.ctl, pt, nb, hw);
+  if (pc == KC_BICG_U) probe_begin(s);
+  hipLaunchKernelGGL(k_bicg_u, dim3(nb), dim3(BS), 0, s, a);
+  if (pc == KC_BICG_U) probe_end(s);
+  hipLaunchKernelGGL(k_bicg_fin_u, dim3(1), dim3(BS), 0, s, a.ctl, pt, nb, hw);
+}
+
+static SolveResult bfail(int code) {
+  SolveResult r;
+  r.code = code;
+  r.sum = Summary{};
+  return r;
+}
+
+SolveResult bicgstab_solve(const Csr& A, const double* b, double* x, const SolveParams& prm,
+                           void* ws, hipStream_t s) {
+  Workspace Wk = carve(ws, A.n);
+  const Geom g = make_geom(A.n);
+  const size_t ld = vec_ld(A.n);
+  double* base = Wk.vecs;
+  BArgs a;
+  a.rp = A.rp;
+  a.ci = A.ci;
+  a.val = A.val;
+  a.n = A.n;
+  a.rpb = g.rpb;
+  a.ctl = Wk.ctl;
+  a.partials = Wk.partials;
+  a.r = base;
+  a.rh = base + ld;
+  a.p[0] = base + 2 * ld;
+  a.p[1] = base + 3 * ld;
+  a.v[0] = base + 4 * ld;
+  a.v[1] = base + 5 * ld;
+  a.t = base + 6 * ld;
+  a.x = x;
+  a.b = b;
+  a.W = prm.weights;
+  a.csr_bytes = csr_bytes(A);
+  if (launch_clear_flags(Wk.flags, s) != hipSuccess) return bfail(-5);
+  if (launch_validate(A, Wk.flags, s) != hipSuccess) return bfail(-5);
+  hipLaunchKernelGGL(k_bicg_init_ctl, dim3(1), dim3(64), 0, s, Wk.ctl, prm.maxit, prm.tol,
+                     prm.eps_b, prm.weights ? 1 : 0);
+  launch_residual(a, g.nb, Wk.flags, s);
+  if (hipGetLastError() != hipSuccess) return bfail(-5);
+
+  Summary* hs = pinned_summaries();
+  if (!hs) return bfail(-5);
+  hipEvent_t ev[2];
+  if (hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) != hipSuccess) return bfail(-5);
+  if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return bfail(-5);
+  }
+  SolveResult res;
+  res.code = 0;
+  int slot = 0;
+  bool pending = false, done = false;
+  const int k = prm.check_every;
+  // Every chunk either advances the iteration count or finishes; bound the loop generously.
+  const long max_chunks = (long)prm.maxit * 4 + 16;
+  for (long ch = 0; ch <= max_chunks && !done; ++ch) {
+    for (int it = 0; it < k; ++it) launch_iteration(a, g.nb, s);
+    launch_residual(a, g.nb, Wk.flags, s);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(&hs[slot], &Wk.ctl->sum, sizeof(Summary), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipEventRecord(ev[slot], s) != hipSuccess) {
+      res.code = -5;
+      break;
+    }
+    if (pending) {
+      if (hipEventSynchronize(ev[slot ^ 1]) != hipSuccess) { res.code = -5; break; }
+      if (hs[slot ^ 1].state == ST_DONE) done = true;
+    }
+    pending = true;
+    slot ^= 1;
+  }
+  if (hipStreamSynchronize(s) != hipSuccess && res.code == 0) res.code = -5;
+  if (res.code == 0 && probe_class() != KC_NONE) probe_collect(&Wk.ctl->work, s);
+  if (res.code == 0) {
+    res.sum = hs[slot ^ 1];
+    if (res.sum.state != ST_DONE) res.code = -5;
+    else if (res.sum.status < 0) res.code = -1;
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  return res;
+}
+
+}  // namespace gsk

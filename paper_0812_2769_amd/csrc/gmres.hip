@@ -1,0 +1,663 @@
+// Restarted GMRES(m) with double classical Gram-Schmidt (CGS2) Arnoldi, and the bare
+// Arnoldi process, on the device.
+//
+// Section 2 of the paper: restarted GMRES whose Arnoldi step orthogonalises with a double
+// classical Gram-Schmidt pass. One Arnoldi step j (basis columns u_0..u_j stored unnormalised
+// with scale factors sigma_i, so v_i = sigma_i u_i) is three streaming launches, each
+// followed by a small finalize launch that reduces the per-workgroup partials:
+//
+//   A  w = A v_j (CSR tile product), partial c1 = V_j^T w, ||w||^2   reads A, V_j; writes w
+//      FA: c1_i, ||A v_j||                                          (j+2 workgroups)
+//   B  w -= V_j c1, partial c2 = V_j^T w                             reads V_j, w; writes w
+//      FB: c2_i                                                     (j+1 workgroups)
+//   C  w -= V_j c2, u_{j+1} = w, partial ||w||^2                     reads V_j, w; writes u
+//      FC: h_{j+1,j}, Givens rotations, residual estimate, and at the end of a cycle the
+//          triangular solve for y                                   (1 workgroup)
+//
+// The basis is read three times per step instead of four: the update of pass 1 and the dot
+// products of pass 2 share one read, with the basis values held in registers. The division
+// v_{j+1} = w / h_{j+1,j} is never materialised: sigma_{j+1} = 1/h_{j+1,j} is folded into the
+// coefficients of later passes. At the end of a cycle X adds V_k y to x and R (+ FR)
+// recomputes the true residual r = b - A x, which either ends the solve or starts the next
+// cycle with u_0 = r.
+//
+// Every launch first checks the device-resident state and returns at once if the solve has
+// moved on, so a whole cycle can be enqueued (or replayed from a graph) blindly; the host
+// reads a small summary once per cycle.
+#include "gsk_host.hpp"
+
+namespace gsk {
+
+struct KArgs {
+  const int* rp;
+  const int* ci;
+  const double* val;
+  int n;
+  int rpb;
+  Ctl* ctl;
+  double* partials;
+  double csr_bytes;   // 12 nnz + 4 (n+1): one read of val, col_idx and row_ptr
+};
+
+__global__ __launch_bounds__(64) void k_init_ctl(Ctl* c, int maxit, int m, double tol,
+                                                 double eps_b, int has_w) {
+  if (threadIdx.x != 0) return;
+  c->sum.state = ST_INIT;
+  c->sum.status = S_MAXIT;
+  c->sum.iters = 0;
+  c->sum.restarts = 0;
+  c->sum.half = 0;
+  c->sum.fails = 0;
+  c->sum.steps = 0;
+  c->sum.brk = BRK_NONE;
+  for (int i = 0; i < KC_COUNT; ++i) {
+    c->work.bytes[i] = 0.0;
+    c->work.busy[i] = 0;
+  }
+  c->sum.relres_rec = 1.0;
+  c->sum.relres_true = 1.0;
+  c->maxit = maxit;
+  c->m = m;
+  c->j = 0;
+  c->k = 0;
+  c->claimed = 0;
+  c->first = 1;
+  c->parity = 0;
+  c->has_w = has_w;
+  c->broke = 0;
+  c->happy = 0;
+  c->tol = tol;
+  c->eps_b = eps_b;
+  c->ref = 0.0;
+  c->ratio = 1.0;
+  c->rho = c->rho_old = c->alpha = c->omega = c->beta = c->rh_norm = 0.0;
+  c->wnorm_pre = 0.0;
+}
+
+// Every streaming kernel below works on one tile of BS rows per workgroup, one row per
+// thread (workgroup lb of the XCD-aware numbering owns rows [lb*BS, lb*BS + BS)).
+__device__ inline int tile_rows(int n, int row0) { return max(0, min(BS, n - row0)); }
+
+// Workgroup total of one per-thread value into partials[col * nb + lb].
+__device__ inline void block_single_partial(double v, double* __restrict__ partials, int col,
+                                            int nb, int lb, double* lds) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < WAVES; ++q) s += lds[q];
+    partials[(size_t)col * nb + lb] = s;
+  }
+}
+
+// R: r = b - A x into u_0; partials ||r||^2 (column 0), ||W r||^2 (column 1).
+__global__ __launch_bounds__(BS) void k_gmres_residual(KArgs a, const double* __restrict__ b,
+                                                       const double* __restrict__ x,
+                                                       const double* __restrict__ W,
+                                                       double* __restrict__ u0,
+                                                       const int* flags) {
+  Ctl* c = a.ctl;
+  const int st = c->sum.state;
+  if (st != ST_INIT && st != ST_CYCLE_END) return;
+  if (flags[0]) return;
+  count_work(c, KC_RESIDUAL, a.csr_bytes + 8.0 * a.n * (W ? 4 : 3));
+  __shared__ TileLds L;
+  __shared__ double red[NC_MAX * WAVES];
+  const int nb = gridDim.x;
+  const int lb = logical_block();
+  const int row0 = lb * BS;
+  const int nrows = tile_rows(a.n, row0);
+  double acc[2] = {0.0, 0.0};
+  if (nrows > 0) {
+    const double y = csr_tile(a.rp, a.ci, a.val, row0, nrows, GatherX{x}, L);
+    if ((int)threadIdx.x < nrows) {
+      const int row = row0 + threadIdx.x;
+      const double r = b[row] - y;
+      u0[row] = r;
+      acc[0] = r * r;
+      if (W) {
+        const double wr = W[row] * r;
+        acc[1] = wr * wr;
+      }
+    }
+  }
+  block_partials<2>(acc, 2, a.partials, nb, lb, red);
+}
+
+// FR: convergence / restart decision after the true residual (see file comment).
+__global__ __launch_bounds__(BS) void k_gmres_fin_residual(Ctl* c, const double* partials,
+                                                           int nb, int has_w,
+                                                           const int* flags) {
+  const int st = c->sum.state;
+  if (st != ST_INIT && st != ST_CYCLE_END) return;
+  if (flags[0]) {
+    if (threadIdx.x == 0) {
+      c->sum.state = ST_DONE;
+      c->sum.status = -1;
+    }
+    return;
+  }
+  __shared__ double out[8];
+  small_sums<2>(partials, nb, out);
+  if (threadIdx.x != 0) return;
+  const double nr = sqrt(out[0]);
+  const double nwr = has_w ? sqrt(out[1]) : nr;
+  if (st == ST_INIT) {
+    c->ref = nwr;
+    if (nwr == 0.0) {
+      c->sum.status = S_CONVERGED;
+      c->sum.relres_rec = 0.0;
+      c->sum.relres_true = 0.0;
+      c->sum.state = ST_DONE;
+      return;
+    }
+    if (c->maxit == 0) {
+      c->sum.status = S_MAXIT;
+      c->sum.state = ST_DONE;
+      return;
+    }
+  } else {
+    const double rt = nwr / c->ref;
+    c->sum.relres_true = rt;
+    if (c->broke) {
+      c->sum.status = S_BREAKDOWN;
+      c->sum.state = ST_DONE;
+      return;
+    }
+    if (rt < c->tol) {
+      c->sum.status = S_CONVERGED;
+      c->sum.state = ST_DONE;
+      return;
+    }
+    if (c->sum.iters >= c->maxit) {
+      c->sum.status = S_MAXIT;
+      c->sum.state = ST_DONE;
+      return;
+    }
+    if (c->claimed) {
+      c->sum.fails += 1;
+      if (c->sum.fails >= 3) {
+        c->sum.status = S_STAGNATED;
+        c->sum.state = ST_DONE;
+        return;
+      }
+    } else {
+      c->sum.fails = 0;
+    }
+    c->sum.restarts += 1;
+  }
+  // start a cycle: v_0 = r / ||r||, g = ||r|| e_1
+  c->sigma[0] = 1.0 / nr;
+  c->g[0] = nr;
+  for (int i = 1; i <= c->m; ++i) c->g[i] = 0.0;
+  c->ratio = has_w ? nwr / nr : 1.0;
+  c->j = 0;
+  c->k = 0;
+  c->claimed = 0;
+  c->happy = 0;
+  c->sum.state = ST_RUNNING;
+}
+
+// A: w = sigma_j A u_j; partials of u_i . w (columns 0..j) and ||w||^2 (column j+1).
+// The basis values of the thread's row are loaded before the product so that their latency
+// overlaps it.
+template <int JM, class R>
+__global__ __launch_bounds__(BS) void k_gmres_a(KArgs a, const double* __restrict__ V, size_t ldv,
+                                                double* __restrict__ w, int j) {
+  Ctl* c = a.ctl;
+  if (c->sum.state != ST_RUNNING || c->j != j) return;
+  count_work(c, KC_GMRES_A, a.csr_bytes + 8.0 * a.n * (j + 2));
+  __shared__ TileLds L;
+  __shared__ double red[NC_MAX * WAVES];
+  __shared__ double red1[WAVES];
+  const int nb = gridDim.x;
+  const int lb = logical_block();
+  const int row0 = lb * BS;
+  const int nrows = tile_rows(a.n, row0);
+  const int row = row0 + threadIdx.x;
+  const bool mine = (int)threadIdx.x < nrows;
+  const R rd(V, ldv, j + 1);
+  double u[JM];
+#pragma unroll
+  for (int i = 0; i < JM; ++i) u[i] = (i <= j && mine) ? rd.load(i, row) : 0.0;
+  double wr = 0.0;
+  if (nrows > 0) {
+    const double y = csr_tile(a.rp, a.ci, a.val, row0, nrows, GatherX{V + (size_t)j * ldv}, L);
+    if (mine) {
+      wr = c->sigma[j] * y;
+      w[row] = wr;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < JM; ++i) u[i] *= wr;
+  block_halving_partials<JM>(u, j + 1, a.partials, nb, lb, red);
+  block_single_partial(wr * wr, a.partials, j + 1, nb, lb, red1);
+}
+
+// FA (j+2 workgroups): workgroup i <= j -> c1_i = sigma_i (u_i . w); workgroup j+1 -> ||A v_j||.
+__global__ __launch_bounds__(BS) void k_gmres_fin_a(Ctl* c, const double* partials, int nb,
+                                                    int j) {
+  if (c->sum.state != ST_RUNNING || c->j != j) return;
+  __shared__ double lds[WAVES];
+  const int col = blockIdx.x;
+  const double s = column_sum(partials + (size_t)col * nb, nb, lds);
+  if (threadIdx.x != 0) return;
+  if (col == j + 1) c->wnorm_pre = sqrt(s);
+  else c->c1[col] = c->sigma[col] * s;
+}
+
+// B: w -= sum_i c1_i v_i, then partials of u_i . w, sharing one read of the basis.
+template <int JM, class R>
+__global__ __launch_bounds__(BS) void k_gmres_b(KArgs a, const double* __restrict__ V, size_t ldv,
+                                                double* __restrict__ w, int j) {
+  Ctl* c = a.ctl;
+  if (c->sum.state != ST_RUNNING || c->j != j) return;
+  count_work(c, KC_GMRES_B, 8.0 * a.n * (j + 3));
+  __shared__ double d[JM];
+  __shared__ double red[NC_MAX * WAVES];
+  const int t = threadIdx.x;
+  if (t <= j && t < JM) d[t] = c->c1[t] * c->sigma[t];
+  const int nb = gridDim.x;
+  const int lb = logical_block();
+  const int row = lb * BS + t;
+  const bool mine = row < a.n;
+  const R rd(V, ldv, j + 1);
+  double u[JM];
+#pragma unroll
+  for (int i = 0; i < JM; ++i) u[i] = (i <= j && mine) ? rd.load(i, row) : 0.0;
+  double wr = mine ? w[row] : 0.0;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < JM; ++i)
+    if (i <= j) wr = fma(-d[i], u[i], wr);
+  if (mine) w[row] = wr;
+#pragma unroll
+  for (int i = 0; i < JM; ++i) u[i] *= wr;
+  block_halving_partials<JM>(u, j + 1, a.partials, nb, lb, red);
+}
+
+// FB (j+1 workgroups): c2_i = sigma_i (u_i . w).
+__global__ __launch_bounds__(BS) void k_gmres_fin_b(Ctl* c, const double* partials, int nb,
+                                                    int j) {
+  if (c->sum.state != ST_RUNNING || c->j != j) return;
+  __shared__ double lds[WAVES];
+  const int col = blockIdx.x;
+  const double s = column_sum(partials + (size_t)col * nb, nb, lds);
+  if (threadIdx.x == 0) c->c2[col] = c->sigma[col] * s;
+}
+
+// C: w -= sum_i c2_i v_i, u_{j+1} = w, partial ||w||^2.
+template <int JM, class R>
+__global__ __launch_bounds__(BS) void k_gmres_c(KArgs a, double* __restrict__ V, size_t ldv,
+                                                const double* __restrict__ w, int j) {
+  Ctl* c = a.ctl;
+  if (c->sum.state != ST_RUNNING || c->j != j) return;
+  count_work(c, KC_GMRES_C, 8.0 * a.n * (j + 3));
+  __shared__ double d[JM];
+  __shared__ double red[WAVES];
+  const int t = threadIdx.x;
+  if (t <= j && t < JM) d[t] = c->c2[t] * c->sigma[t];
+  const int nb = gridDim.x;
+  const int lb = logical_block();
+  const int row = lb * BS + t;
+  const bool mine = row < a.n;
+  const R rd(V, ldv, j + 1);
+  double u[JM];
+#pragma unroll
+  for (int i = 0; i < JM; ++i) u[i] = (i <= j && mine) ? rd.load(i, row) : 0.0;
+  double wr = mine ? w[row] : 0.0;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < JM; ++i)
+    if (i <= j) wr = fma(-d[i], u[i], wr);
+  if (mine) V[(size_t)(j + 1) * ldv + row] = wr;
+  block_single_partial(wr * wr, a.partials, 0, nb, lb, red);
+}
+
+// FC (1 workgroup): Hessenberg column, Givens rotations, residual estimate; at the end of a
+// cycle the k x k triangular solve H y = g (y stored pre-multiplied by sigma).
+__global__ __launch_bounds__(BS) void k_gmres_fin_c(Ctl* c, const double* partials, int nb,
+                                                    int j) {
+  if (c->sum.state != ST_RUNNING || c->j != j) return;
+  __shared__ double lds[WAVES];
+  __shared__ double s_h[MMAX + 2];
+  __shared__ double s_cs[MMAX], s_sn[MMAX];
+  __shared__ int s_end, s_k;
+  constexpr int LDH = MMAX + 1;
+  const int t = threadIdx.x;
+  const double nrm2 = column_sum(partials, nb, lds);
+  if (t <= j) {
+    s_h[t] = c->c1[t] + c->c2[t];
+    s_cs[t] = c->cs[t];
+    s_sn[t] = c->sn[t];
+  }
+  __syncthreads();
+  if (t == 0) {
+    const double hn = sqrt(nrm2);
+    s_h[j + 1] = hn;
+    for (int i = 0; i <= j + 1; ++i) c->Hraw[(size_t)j * LDH + i] = s_h[i];
+    const int happy = hn <= c->eps_b * c->wnorm_pre;
+    c->happy = happy;
+    if (!happy) c->sigma[j + 1] = 1.0 / hn;
+    for (int i = 0; i < j; ++i) {
+      const double tmp = s_cs[i] * s_h[i] + s_sn[i] * s_h[i + 1];
+      s_h[i + 1] = -s_sn[i] * s_h[i] + s_cs[i] * s_h[i + 1];
+      s_h[i] = tmp;
+    }
+    const double dd = hypot(s_h[j], s_h[j + 1]);
+    c->sum.iters += 1;
+    int end = 0, k = j + 1;
+    if (dd == 0.0) {
+      c->broke = 1;
+      c->sum.brk = BRK_GIVENS;
+      k = j;
+      end = 1;
+    } else {
+      const double cj = s_h[j] / dd;
+      const double sj = s_h[j + 1] / dd;
+      s_h[j] = dd;
+      s_h[j + 1] = 0.0;
+      const double gj = c->g[j];
+      c->g[j + 1] = -sj * gj;
+      c->g[j] = cj * gj;
+      c->cs[j] = cj;
+      c->sn[j] = sj;
+      const double est = fabs(c->g[j + 1]) * c->ratio / c->ref;
+      c->sum.relres_rec = est;
+      const int claimed = (est < c->tol) || happy;
+      c->claimed = claimed;
+      end = claimed || (c->sum.iters >= c->maxit) || (j + 1 == c->m);
+    }
+    for (int i = 0; i <= j + 1; ++i) c->H[(size_t)j * LDH + i] = s_h[i];
+    c->j = j + 1;
+    c->k = k;
+    s_end = end;
+    s_k = k;
+  }
+  __syncthreads();
+  if (!s_end) return;
+
+  __shared__ double s_H[MMAX][MMAX + 1];   // s_H[col][row]
+  __shared__ double s_g[MMAX + 1], s_y[MMAX];
+  const int k = s_k;
+  for (int idx = t; idx < k * k; idx += BS) {
+    const int col = idx / k, row = idx % k;
+    s_H[col][row] = (col == j) ? s_h[row] : c->H[(size_t)col * LDH + row];
+  }
+  if (t < k) s_g[t] = c->g[t];
+  __syncthreads();
+  for (int i = k - 1; i >= 0; --i) {
+    if (t == 0) s_y[i] = s_g[i] / s_H[i][i];
+    __syncthreads();
+    if (t < i) s_g[t] -= s_H[i][t] * s_y[i];
+    __syncthreads();
+  }
+  if (t < k) c->y[t] = s_y[t] * c->sigma[t];
+  __syncthreads();
+  if (t == 0) c->sum.state = ST_CYCLE_END;
+}
+
+// X: x += sum_{l<k} y_l v_l (y already carries sigma).
+template <class R>
+__global__ __launch_bounds__(BS) void k_gmres_x(KArgs a, const double* __restrict__ V, size_t ldv,
+                                                double* __restrict__ x) {
+  Ctl* c = a.ctl;
+  if (c->sum.state != ST_CYCLE_END) return;
+  __shared__ double s_y[MMAX];
+  const int k = c->k;
+  count_work(c, KC_GMRES_X, 8.0 * a.n * (k + 2));
+  const int t = threadIdx.x;
+  if (t < k) s_y[t] = c->y[t];
+  __syncthreads();
+  const int row = logical_block() * BS + t;
+  if (row >= a.n) return;
+  const R rd(V, ldv, k > 0 ? k : 1);
+  double acc = 0.0;
+  for (int l = 0; l < k; ++l) acc = fma(s_y[l], rd.load(l, row), acc);
+  x[row] = x[row] + acc;
+}
+
+// Arnoldi entry point: u_0 = r0, partial ||r0||^2.
+__global__ __launch_bounds__(BS) void k_arnoldi_start(KArgs a, const double* __restrict__ r0,
+                                                      double* __restrict__ u0, const int* flags) {
+  Ctl* c = a.ctl;
+  if (c->sum.state != ST_INIT || flags[0]) return;
+  __shared__ double red[WAVES];
+  const int nb = gridDim.x;
+  const int lb = logical_block();
+  const int row = lb * BS + threadIdx.x;
+  double v = 0.0;
+  if (row < a.n) {
+    const double r = r0[row];
+    u0[row] = r;
+    v = r * r;
+  }
+  block_single_partial(v, a.partials, 0, nb, lb, red);
+}
+
+__global__ __launch_bounds__(BS) void k_arnoldi_fin_start(Ctl* c, const double* partials, int nb,
+                                                          const int* flags) {
+  if (c->sum.state != ST_INIT) return;
+  if (flags[0]) {
+    if (threadIdx.x == 0) {
+      c->sum.state = ST_DONE;
+      c->sum.status = -1;
+    }
+    return;
+  }
+  __shared__ double lds[WAVES];
+  const double s = column_sum(partials, nb, lds);
+  if (threadIdx.x != 0) return;
+  const double nr = sqrt(s);
+  if (!(nr > 0.0) || !isfinite(nr)) {
+    c->sum.state = ST_DONE;
+    c->sum.status = -2;
+    return;
+  }
+  c->ref = 1.0;
+  c->ratio = 1.0;
+  c->sigma[0] = 1.0 / nr;
+  c->g[0] = nr;
+  for (int i = 1; i <= c->m; ++i) c->g[i] = 0.0;
+  c->j = 0;
+  c->sum.state = ST_RUNNING;
+}
+
+// Arnoldi entry point: normalise the stored columns in place and export H.
+__global__ __launch_bounds__(BS) void k_arnoldi_finish(KArgs a, double* __restrict__ V, size_t ldv,
+                                                       double* __restrict__ Hout, int m) {
+  Ctl* c = a.ctl;
+  if (c->sum.state != ST_CYCLE_END) return;
+  const int k = c->k;
+  const int cols = k + (c->happy ? 0 : 1);
+  const int64_t total = (int64_t)a.n * cols;
+  for (int64_t idx = (int64_t)blockIdx.x * BS + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * BS) {
+    const int col = (int)(idx / a.n);
+    const int row = (int)(idx % a.n);
+    V[(size_t)col * ldv + row] *= c->sigma[col];
+  }
+  if (blockIdx.x == 0) {
+    constexpr int LDH = MMAX + 1;
+    for (int idx = threadIdx.x; idx < (m + 1) * m; idx += BS) {
+      const int col = idx / (m + 1), row = idx % (m + 1);
+      Hout[idx] = (col < k && row <= col + 1) ? c->Hraw[(size_t)col * LDH + row] : 0.0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void k_arnoldi_done(Ctl* c) {
+  if (threadIdx.x == 0 && c->sum.state == ST_CYCLE_END) {
+    c->sum.steps = c->k;
+    c->sum.status = S_CONVERGED;
+    c->sum.state = ST_DONE;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Host drivers
+// ---------------------------------------------------------------------------------------
+static int pick_jm(int cols) { return cols <= 8 ? 8 : cols <= 16 ? 16 : cols <= 32 ? 32 : 64; }
+
+template <class R>
+static hipError_t launch_step(const KArgs& ka, int nb, double* V, size_t ldv, double* w, int j,
+                              hipStream_t s) {
+  const int jm = pick_jm(j + 1);
+  dim3 grid(nb), block(BS);
+  const int pc = probe_class();
+#define GSK_STEP(JMV)                                                                       \
+  if (pc == KC_GMRES_A) probe_begin(s);                                                     \
+  hipLaunchKernelGGL((k_gmres_a<JMV, R>), grid, block, 0, s, ka, V, ldv, w, j);                  \
+  if (pc == KC_GMRES_A) probe_end(s);                                                       \
+  hipLaunchKernelGGL(k_gmres_fin_a, dim3(j + 2), block, 0, s, ka.ctl, ka.partials, nb, j);  \
+  if (pc == KC_GMRES_B) probe_begin(s);                                                     \
+  hipLaunchKernelGGL((k_gmres_b<JMV, R>), grid, block, 0, s, ka, V, ldv, w, j);                  \
+  if (pc == KC_GMRES_B) probe_end(s);                                                       \
+  hipLaunchKernelGGL(k_gmres_fin_b, dim3(j + 1), block, 0, s, ka.ctl, ka.partials, nb, j);  \
+  if (pc == KC_GMRES_C) probe_begin(s);                                                     \
+  hipLaunchKernelGGL((k_gmres_c<JMV, R>), grid, block, 0, s, ka, V, ldv, w, j);                  \
+  if (pc == KC_GMRES_C) probe_end(s);                                                       \
+  hipLaunchKernelGGL(k_gmres_fin_c, dim3(1), block, 0, s, ka.ctl, ka.partials, nb, j);
+  switch (jm) {
+    case 8: GSK_STEP(8) break;
+    case 16: GSK_STEP(16) break;
+    case 32: GSK_STEP(32) break;
+    default: GSK_STEP(64) break;
+  }
+#undef GSK_STEP
+  return hipGetLastError();
+}
+
+static void launch_residual(const KArgs& ka, int nb, const double* b, const double* x,
+                            const double* W, double* u0, const int* flags, hipStream_t s) {
+  const bool pr = probe_class() == KC_RESIDUAL;
+  if (pr) probe_begin(s);
+  hipLaunchKernelGGL(k_gmres_residual, dim3(nb), dim3(BS), 0, s, ka, b, x, W, u0, flags);
+  if (pr) probe_end(s);
+  hipLaunchKernelGGL(k_gmres_fin_residual, dim3(1), dim3(BS), 0, s, ka.ctl,
+                     (const double*)ka.partials, nb, W ? 1 : 0, flags);
+}
+
+static SolveResult fail(int code) {
+  SolveResult r;
+  r.code = code;
+  r.sum = Summary{};
+  return r;
+}
+
+template <class R>
+static SolveResult gmres_run(const Csr& A, const double* b, double* x, int m,
+                             const SolveParams& prm, void* ws, hipStream_t s) {
+  Workspace W = carve(ws, A.n);
+  const Geom g = make_geom(A.n);
+  const size_t ldv = vec_ld(A.n);
+  double* V = W.vecs;
+  double* w = V + (size_t)(m + 1) * ldv;
+  KArgs ka{A.rp, A.ci, A.val, A.n, g.rpb, W.ctl, W.partials, csr_bytes(A)};
+  dim3 grid(g.nb), block(BS);
+  if (launch_clear_flags(W.flags, s) != hipSuccess) return fail(-5);
+  if (launch_validate(A, W.flags, s) != hipSuccess) return fail(-5);
+  hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, s, W.ctl, prm.maxit, m, prm.tol, prm.eps_b,
+                     prm.weights ? 1 : 0);
+  launch_residual(ka, g.nb, b, x, prm.weights, V, W.flags, s);
+  if (hipGetLastError() != hipSuccess) return fail(-5);
+
+  Summary* hs = pinned_summaries();
+  if (!hs) return fail(-5);
+  hipEvent_t ev[2];
+  if (hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) != hipSuccess) return fail(-5);
+  if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return fail(-5);
+  }
+  SolveResult res;
+  res.code = 0;
+  int slot = 0;
+  bool pending = false, done = false;
+  const long max_cycles = (long)prm.maxit + 8;
+  for (long cyc = 0; cyc <= max_cycles && !done; ++cyc) {
+    for (int j = 0; j < m; ++j)
+      if (launch_step<R>(ka, g.nb, V, ldv, w, j, s) != hipSuccess) { res.code = -5; break; }
+    if (res.code) break;
+    if (probe_class() == KC_GMRES_X) probe_begin(s);
+    hipLaunchKernelGGL(k_gmres_x<R>, grid, block, 0, s, ka, (const double*)V, ldv, x);
+    if (probe_class() == KC_GMRES_X) probe_end(s);
+    launch_residual(ka, g.nb, b, x, prm.weights, V, W.flags, s);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(&hs[slot], &W.ctl->sum, sizeof(Summary), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipEventRecord(ev[slot], s) != hipSuccess) {
+      res.code = -5;
+      break;
+    }
+    // Check the previous cycle while this one runs.
+    if (pending) {
+      if (hipEventSynchronize(ev[slot ^ 1]) != hipSuccess) { res.code = -5; break; }
+      if (hs[slot ^ 1].state == ST_DONE) done = true;
+    }
+    pending = true;
+    slot ^= 1;
+  }
+  if (hipStreamSynchronize(s) != hipSuccess && res.code == 0) res.code = -5;
+  if (res.code == 0 && probe_class() != KC_NONE) probe_collect(&W.ctl->work, s);
+  if (res.code == 0) {
+    res.sum = hs[slot ^ 1];   // the most recent copy (state no longer changes once done)
+    if (res.sum.state != ST_DONE) res.code = -5;
+    else if (res.sum.status < 0) res.code = -1;
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  return res;
+}
+
+template <class R>
+static SolveResult arnoldi_impl(const Csr& A, const double* r0, int m, double* V, int64_t ldv,
+                                double* H, void* ws, double eps_b, hipStream_t s) {
+  Workspace W = carve(ws, A.n);
+  const Geom g = make_geom(A.n);
+  double* w = W.vecs;
+  KArgs ka{A.rp, A.ci, A.val, A.n, g.rpb, W.ctl, W.partials, csr_bytes(A)};
+  dim3 grid(g.nb), block(BS);
+  if (launch_clear_flags(W.flags, s) != hipSuccess) return fail(-5);
+  if (launch_validate(A, W.flags, s) != hipSuccess) return fail(-5);
+  // tol < 0: the estimate never ends the cycle; maxit = m steps.
+  hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, s, W.ctl, m, m, -1.0, eps_b, 0);
+  hipLaunchKernelGGL(k_arnoldi_start, grid, block, 0, s, ka, r0, V, (const int*)W.flags);
+  hipLaunchKernelGGL(k_arnoldi_fin_start, dim3(1), block, 0, s, W.ctl,
+                     (const double*)W.partials, g.nb, (const int*)W.flags);
+  for (int j = 0; j < m; ++j)
+    if (launch_step<R>(ka, g.nb, V, (size_t)ldv, w, j, s) != hipSuccess) return fail(-5);
+  const int fin_blocks = 1024;
+  hipLaunchKernelGGL(k_arnoldi_finish, dim3(fin_blocks), block, 0, s, ka, V, (size_t)ldv, H, m);
+  hipLaunchKernelGGL(k_arnoldi_done, dim3(1), dim3(64), 0, s, W.ctl);
+  if (hipGetLastError() != hipSuccess) return fail(-5);
+  Summary* hs = pinned_summaries();
+  if (!hs) return fail(-5);
+  if (hipMemcpyAsync(&hs[0], &W.ctl->sum, sizeof(Summary), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(-5);
+  SolveResult res;
+  res.code = 0;
+  res.sum = hs[0];
+  if (res.sum.state != ST_DONE) res.code = -5;
+  else if (res.sum.status < 0) res.code = -1;
+  return res;
+}
+
+SolveResult gmres_solve(const Csr& A, const double* b, double* x, int m, const SolveParams& prm,
+                        void* ws, hipStream_t s) {
+  if (fits_buffer(vec_ld(A.n), m + 1)) return gmres_run<ColumnReader>(A, b, x, m, prm, ws, s);
+  return gmres_run<PointerReader>(A, b, x, m, prm, ws, s);
+}
+
+SolveResult arnoldi_run(const Csr& A, const double* r0, int m, double* V, int64_t ldv, double* H,
+                        void* ws, double eps_b, hipStream_t s) {
+  if (fits_buffer((size_t)ldv, m + 1)) return arnoldi_impl<ColumnReader>(A, r0, m, V, ldv, H, ws, eps_b, s);
+  return arnoldi_impl<PointerReader>(A, r0, m, V, ldv, H, ws, eps_b, s);
+}
+
+}  // namespace gsk

@@ -1,0 +1,339 @@
+// Device-side building blocks shared by the gsk kernels (gfx950, wave64).
+//
+//  * Launch geometry: every Krylov kernel runs one workgroup of BS threads per contiguous
+//    block of rows. The number of workgroups is a multiple of 8 and workgroup ids are
+//    remapped so that the 8 XCDs (which receive workgroups round-robin) each own one
+//    contiguous eighth of the rows; the neighbours a stencil row gathers then sit in the
+//    same XCD's L2.
+//  * Deterministic reductions without cross-workgroup synchronisation: per-thread partial
+//    sums -> wave butterfly -> LDS across the waves -> one partial per workgroup, stored with
+//    plain stores. A separate small "finalize" launch (one workgroup per reduced value) sums
+//    the partials in a fixed order after the kernel boundary has made them visible, and
+//    updates the solver's device-resident scalars. No fences, no atomics, no floating-point
+//    atomics: repeated runs are bitwise identical.
+//  * CSR tile product: a tile of BS rows stages val*x products in LDS with coalesced loads,
+//    then each thread sums its own row sequentially in storage order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gsk {
+
+constexpr int BS = 256;             // threads per workgroup (4 waves)
+constexpr int WAVES = BS / 64;
+constexpr int TILE_NNZ = BS * 8;    // LDS product slots per tile (8 per row on average)
+constexpr int MMAX = 64;            // largest GMRES restart length
+constexpr int NC_MAX = MMAX + 2;    // most values reduced in one launch
+
+// Solver state machine (Ctl::state)
+enum : int {
+  ST_INIT = 0,        // initial residual pending
+  ST_RUNNING = 1,     // iterating
+  ST_CYCLE_END = 2,   // GMRES: cycle finished, x update + true residual pending
+  ST_HALF = 3,        // Bi-CGSTAB: half-step exit, x += alpha p pending
+  ST_VERIFY = 4,      // true-residual check pending
+  ST_FINAL = 5,       // breakdown: final true residual pending, status already set
+  ST_DONE = 6,        // finished; status valid
+};
+
+enum : int { S_CONVERGED = 0, S_MAXIT = 1, S_BREAKDOWN = 2, S_STAGNATED = 3 };
+
+// Which breakdown test fired (Summary::brk)
+enum : int { BRK_NONE = 0, BRK_SIGMA = 1, BRK_OMEGA = 2, BRK_RHO = 3, BRK_GIVENS = 4 };
+
+// Kernel classes for the measurement hook (same numbering as GSK_KCLASS_* in gsk.h).
+enum : int {
+  KC_NONE = 0, KC_GMRES_A = 1, KC_GMRES_B = 2, KC_GMRES_C = 3, KC_BICG_P = 4, KC_BICG_S = 5,
+  KC_BICG_U = 6, KC_RESIDUAL = 7, KC_GMRES_X = 8, KC_COUNT = 9
+};
+
+// Per-class work counters: launches that did work, and their algorithmic bytes. Written by
+// thread 0 of workgroup 0 of each working launch (one writer per launch, launches serialised
+// on the stream).
+struct Work {
+  double bytes[KC_COUNT];
+  int busy[KC_COUNT];
+  int pad[16 - KC_COUNT % 16];
+};
+
+// Host-visible summary copied back after each cycle / chunk.
+struct Summary {
+  int state, status, iters, restarts, half, fails, steps, brk;
+  double relres_rec, relres_true;
+};
+
+// Control block living at the start of the workspace. Written only by the kernels
+// (its first fields are set by an init kernel, never by a memset).
+struct Ctl {
+  Summary sum;
+  Work work;
+  int maxit, m, j, k, claimed, first, parity, has_w;
+  int broke, happy, pad0, pad1;
+  double tol, eps_b, ref, ratio;
+  // Bi-CGSTAB scalars
+  double rho, rho_old, alpha, omega, beta, rh_norm;
+  // GMRES: lazy column scales, orthogonalisation coefficients, Hessenberg + Givens
+  double wnorm_pre;
+  double sigma[MMAX + 1];
+  double c1[MMAX + 1];
+  double c2[MMAX + 1];
+  double H[(MMAX + 1) * MMAX];   // column-major, ld MMAX+1, rotated in place
+  double Hraw[(MMAX + 1) * MMAX];// unrotated Hessenberg (for the Arnoldi entry point)
+  double cs[MMAX], sn[MMAX], g[MMAX + 1], y[MMAX];
+};
+
+__device__ inline void count_work(Ctl* c, int cls, double bytes) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    c->work.busy[cls] += 1;
+    c->work.bytes[cls] += bytes;
+  }
+}
+
+struct Geom {
+  int nb;    // workgroups (multiple of 8)
+  int rpb;   // rows per workgroup (multiple of BS)
+};
+
+// One tile of BS rows per workgroup, one row per thread; the workgroup count is rounded up to
+// a multiple of 8 (the trailing workgroups own no rows).
+inline Geom make_geom(int n) {
+  const int tiles = (n + BS - 1) / BS;
+  const int nb = (tiles + 7) / 8 * 8;
+  return Geom{nb, BS};
+}
+
+// Logical workgroup index: XCD x (= blockIdx.x % 8) owns logical blocks
+// [x*nb/8, (x+1)*nb/8), which are contiguous row ranges.
+__device__ inline int logical_block() {
+  const int nb = gridDim.x;
+  const int b = blockIdx.x;
+  return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Reduce NC per-thread values over the workgroup and store them as this workgroup's partial
+// (partials[c * nb + lb]). Only the first nc values are meaningful. lds must hold
+// NC*WAVES doubles. All threads must call.
+template <int NC>
+__device__ inline void block_partials(double (&acc)[NC], int nc, double* __restrict__ partials,
+                                      int nb, int lb, double* lds) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    if (c < nc) {
+      double v = wave_sum(acc[c]);
+      if (lane == 0) lds[c * WAVES + wave] = v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < nc) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) s += lds[threadIdx.x * WAVES + w];
+    partials[threadIdx.x * nb + lb] = s;
+  }
+}
+
+// Reduce NV per-lane values (NV a power of two, <= 64) over the 64 lanes of a wave by
+// recursive halving: at each step a lane keeps half of its values, sends the other half to
+// its partner and adds what it receives, so the wave exchanges NV-1 + (6 - log2 NV) values
+// instead of 6 NV. Afterwards lane l holds in v[0] the wave total of value number
+// l >> (6 - log2 NV) (the remaining low lane bits are summed by a plain butterfly).
+// Written as template recursion so that every array index is a compile-time constant and the
+// values stay in registers.
+template <int NV, int HALF, int BIT>
+struct Halving {
+  __device__ static inline void run(double (&v)[NV], int lane) {
+    const bool hi = (lane & BIT) != 0;
+#pragma unroll
+    for (int k = 0; k < HALF; ++k) {
+      const double send = hi ? v[k] : v[k + HALF];
+      const double keep = hi ? v[k + HALF] : v[k];
+      v[k] = keep + __shfl_xor(send, BIT, 64);
+    }
+    Halving<NV, HALF / 2, BIT / 2>::run(v, lane);
+  }
+};
+
+template <int NV, int BIT>
+struct Halving<NV, 0, BIT> {
+  __device__ static inline void run(double (&)[NV], int) {}
+};
+
+template <int NV>
+__device__ inline double wave_halving_sum(double (&v)[NV]) {
+  static_assert(NV >= 1 && NV <= 64 && (NV & (NV - 1)) == 0, "NV must be a power of two");
+  const int lane = threadIdx.x & 63;
+  Halving<NV, NV / 2, 32>::run(v, lane);
+  double r = v[0];
+#pragma unroll
+  for (int bit = 32 / (NV > 1 ? NV : 1); bit >= 1; bit >>= 1) r += __shfl_xor(r, bit, 64);
+  return r;
+}
+
+template <int NV>
+__device__ constexpr int halving_shift() {
+  return NV >= 64 ? 0 : NV >= 32 ? 1 : NV >= 16 ? 2 : NV >= 8 ? 3 : NV >= 4 ? 4 : NV >= 2 ? 5 : 6;
+}
+
+// Workgroup version: partials[c * nb + lb] = workgroup total of value c, for c < nc <= NV.
+// lds must hold NV*WAVES doubles. All threads must call.
+template <int NV>
+__device__ inline void block_halving_partials(double (&v)[NV], int nc,
+                                              double* __restrict__ partials, int nb, int lb,
+                                              double* lds) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  constexpr int SH = halving_shift<NV>();
+  const double r = wave_halving_sum<NV>(v);
+  if ((lane & ((1 << SH) - 1)) == 0) lds[(lane >> SH) * WAVES + wave] = r;
+  __syncthreads();
+  if ((int)threadIdx.x < nc) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) s += lds[threadIdx.x * WAVES + w];
+    partials[threadIdx.x * nb + lb] = s;
+  }
+}
+
+// Sum of partials[0..nb) in a fixed order (thread t takes t, t+BS, ...; then the workgroup
+// tree). Every thread of the workgroup must call; the result is returned to all threads.
+__device__ inline double column_sum(const double* __restrict__ partials, int nb, double* lds) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int l = threadIdx.x;
+  for (; l + 3 * BS < nb; l += 4 * BS) {
+    a0 += partials[l];
+    a1 += partials[l + BS];
+    a2 += partials[l + 2 * BS];
+    a3 += partials[l + 3 * BS];
+  }
+  for (; l < nb; l += BS) a0 += partials[l];
+  const double v = wave_sum((a0 + a1) + (a2 + a3));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < WAVES; ++w) s += lds[w];
+  return s;
+}
+
+// In a single-workgroup finalize launch: out[c] = sum of partial column c (c < NC <= 8), all
+// BS threads sweeping every column with independent loads; then the workgroup tree.
+template <int NC>
+__device__ inline void small_sums(const double* __restrict__ partials, int nb, double* out) {
+  __shared__ double lds[8 * WAVES];
+  double acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+  for (int l = threadIdx.x; l < nb; l += BS) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] += partials[c * nb + l];
+  }
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double v = wave_sum(acc[c]);
+    if (lane == 0) lds[c * WAVES + wave] = v;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < NC) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) s += lds[threadIdx.x * WAVES + w];
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------------------
+// CSR tile product. Rows [row0, row0+nrows) with nrows <= BS; thread t gets row row0+t.
+// gather(c) returns the (possibly recomputed) source-vector entry of column c.
+// Products are rounded before they are added and each row is summed in storage order.
+// Tiles whose nonzeros exceed the LDS slots fall back to a direct per-thread loop with
+// the same rounding and order.
+// ---------------------------------------------------------------------------------------
+struct TileLds {
+  int rp[BS + 1];
+  double prod[TILE_NNZ];
+};
+
+template <class G>
+__device__ inline double csr_tile(const int* __restrict__ row_ptr, const int* __restrict__ col,
+                                  const double* __restrict__ val, int row0, int nrows,
+                                  const G& gather, TileLds& L) {
+#pragma clang fp contract(off)
+  const int t = threadIdx.x;
+  for (int i = t; i <= nrows; i += BS) L.rp[i] = row_ptr[row0 + i];
+  __syncthreads();
+  const int p0 = L.rp[0];
+  const int cnt = L.rp[nrows] - p0;
+  double y = 0.0;
+  if (cnt <= TILE_NNZ) {
+    for (int k = t; k < cnt; k += BS) {
+      const double a = val[p0 + k];
+      const double xv = gather(col[p0 + k]);
+      L.prod[k] = a * xv;
+    }
+    __syncthreads();
+    if (t < nrows) {
+      const int e = L.rp[t + 1] - p0;
+      for (int k = L.rp[t] - p0; k < e; ++k) y += L.prod[k];
+    }
+  } else {
+    if (t < nrows) {
+      const int e = L.rp[t + 1];
+      for (int k = L.rp[t]; k < e; ++k) {
+        const double prod = val[k] * gather(col[k]);
+        y += prod;
+      }
+    }
+  }
+  __syncthreads();   // LDS is reused by the next tile
+  return y;
+}
+
+struct GatherX {
+  const double* __restrict__ x;
+  __device__ double operator()(int c) const { return x[c]; }
+};
+
+// Reads columns of a column-major n x k FP64 basis through one buffer descriptor: the column
+// offset is a uniform scalar (i * ldv * 8 bytes) and the row offset a single per-lane 32-bit
+// value, so a thread reading 30 columns of its row holds no per-column addresses. Requires
+// the basis to span fewer than 2^31 bytes (checked on the host); loads outside the described
+// range return 0.
+struct ColumnReader {
+  __amdgpu_buffer_rsrc_t rsrc;
+  int ld_bytes;
+  __device__ ColumnReader(const double* base, size_t ldv, int cols) {
+    rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0,
+                                             (int)(ldv * 8 * (size_t)cols), 0x00020000);
+    ld_bytes = (int)(ldv * 8);
+  }
+  __device__ double load(int col, int row) const {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    const u2 v = __builtin_amdgcn_raw_buffer_load_b64(rsrc, row * 8, col * ld_bytes, 0);
+    return __builtin_bit_cast(double, v);
+  }
+};
+
+// Same interface with plain 64-bit addressing, for bases of 2^31 bytes or more.
+struct PointerReader {
+  const double* base;
+  size_t ldv;
+  __device__ PointerReader(const double* b, size_t l, int) : base(b), ldv(l) {}
+  __device__ double load(int col, int row) const { return base[(size_t)col * ldv + row]; }
+};
+
+inline bool fits_buffer(size_t ldv, int cols) { return ldv * 8 * (size_t)cols < (size_t(1) << 31); }
+
+}  // namespace gsk

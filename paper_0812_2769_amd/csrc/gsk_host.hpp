@@ -1,0 +1,93 @@
+// Host-side interfaces between the C ABI layer (api.hip) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "gsk_dev.hpp"
+
+namespace gsk {
+
+struct Csr {
+  int n;
+  int64_t nnz;
+  const int* rp;
+  const int* ci;
+  const double* val;
+};
+
+struct SolveParams {
+  int maxit;
+  double tol;
+  double eps_b;
+  const double* weights;  // device [n] or nullptr
+  int check_every;        // Bi-CGSTAB chunk length
+};
+
+struct SolveResult {
+  int code;               // 0 ok, <0 error (GSK_ERR_*)
+  Summary sum;
+};
+
+// Workspace carve-up: [Ctl | flags | partials | vectors...], every piece 256-byte aligned.
+// The partials hold NC_MAX values per workgroup of the launch geometry.
+constexpr size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr size_t kCtlBytes = align256(sizeof(Ctl));
+constexpr size_t kFlagBytes = 256;
+inline size_t partial_bytes(int n) {
+  return align256(sizeof(double) * NC_MAX * (size_t)make_geom(n).nb);
+}
+inline size_t head_bytes(int n) { return kCtlBytes + kFlagBytes + partial_bytes(n); }
+
+inline size_t vec_ld(int n) { return (size_t)((n + 63) / 64 * 64); }  // doubles, 512 B steps
+
+struct Workspace {
+  Ctl* ctl;
+  int* flags;        // [0] invalid CSR, [1] zero row, [2] non-finite
+  double* partials;
+  double* vecs;      // method-specific vectors, each vec_ld(n) doubles
+};
+
+inline Workspace carve(void* ws, int n) {
+  char* p = static_cast<char*>(ws);
+  Workspace w;
+  w.ctl = reinterpret_cast<Ctl*>(p);
+  w.flags = reinterpret_cast<int*>(p + kCtlBytes);
+  w.partials = reinterpret_cast<double*>(p + kCtlBytes + kFlagBytes);
+  w.vecs = reinterpret_cast<double*>(p + head_bytes(n));
+  return w;
+}
+
+size_t workspace_bytes(int method, int n, int m);
+
+// Flat validity scan of a CSR matrix (no indirect loads): row_ptr[0] == 0, non-decreasing,
+// row_ptr[n] == nnz, every column index in [0, n). Sets flags[0] on failure.
+hipError_t launch_clear_flags(int* flags, hipStream_t s);
+hipError_t launch_validate(const Csr& A, int* flags, hipStream_t s);
+
+hipError_t launch_gs_scale(const Csr& A, const double* b, int p, double* val_out, double* b_out,
+                           double* norm, double* weight, int* flags, hipStream_t s);
+hipError_t launch_spmv(const Csr& A, const double* x, double* y, hipStream_t s);
+
+SolveResult gmres_solve(const Csr& A, const double* b, double* x, int m,
+                        const SolveParams& prm, void* ws, hipStream_t s);
+SolveResult arnoldi_run(const Csr& A, const double* r0, int m, double* V, int64_t ldv,
+                        double* H, void* ws, double eps_b, hipStream_t s);
+SolveResult bicgstab_solve(const Csr& A, const double* b, double* x, const SolveParams& prm,
+                           void* ws, hipStream_t s);
+
+// Small pinned host buffer for status read-back (one per thread, allocated on first use).
+Summary* pinned_summaries();
+
+inline double csr_bytes(const Csr& A) { return 12.0 * (double)A.nnz + 4.0 * ((double)A.n + 1); }
+
+// Measurement hook (gsk_probe_begin / gsk_probe_end): while a kernel class is selected, every
+// launch of that class is bracketed by a pair of HIP events on its stream, and at the end of
+// each solve the device work counters of that class are added to the running totals.
+int probe_class();
+void probe_begin(hipStream_t s);
+void probe_end(hipStream_t s);
+void probe_collect(const Work* device_work, hipStream_t s);
+
+}  // namespace gsk

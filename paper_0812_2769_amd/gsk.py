@@ -1,0 +1,306 @@
+"""ctypes binding of libgsk.so (include/gsk.h): argument marshalling only.
+
+Torch CUDA tensors supply device memory and the stream; every computation runs in the HIP
+library. Importing this module loads the library and raises ImportError if it has not been
+built (python -m paper_0812_2769_amd.build); there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgsk.so")
+
+# Return codes and outcomes (include/gsk.h)
+OK = 0
+ERR_INVALID_ARG, ERR_ZERO_ROW, ERR_NONFINITE, ERR_WORKSPACE, ERR_DEVICE = -1, -2, -3, -4, -5
+CONVERGED, MAXIT, BREAKDOWN, STAGNATED = 0, 1, 2, 3
+STATUS_NAMES = {CONVERGED: "converged", MAXIT: "maxit", BREAKDOWN: "breakdown",
+                STAGNATED: "stagnated"}
+METHOD_GS, METHOD_GMRES, METHOD_BICGSTAB, METHOD_ARNOLDI = 0, 1, 2, 3
+MAX_RESTART = 64
+BRK_NONE, BRK_SIGMA, BRK_OMEGA, BRK_RHO, BRK_GIVENS = 0, 1, 2, 3, 4
+
+
+class GskError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"gsk error {code}: {msg}")
+        self.code = code
+
+
+class Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("maxit", ctypes.c_int32), ("breakdown_eps", ctypes.c_double),
+                ("stop_weights", ctypes.c_void_p), ("check_every", ctypes.c_int32)]
+
+
+class InfoStruct(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("half_step", ctypes.c_int32),
+                ("verify_failures", ctypes.c_int32), ("breakdown_test", ctypes.c_int32),
+                ("relres_recursive", ctypes.c_double),
+                ("relres_true", ctypes.c_double)]
+
+
+class ProbeResult(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("busy_launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+KCLASS = {"gmres_a": 1, "gmres_b": 2, "gmres_c": 3, "bicg_p": 4, "bicg_s": 5, "bicg_u": 6,
+          "residual": 7, "gmres_x": 8}
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_0812_2769_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    lib.gsk_default_options.argtypes = [P(Options)]
+    lib.gsk_default_options.restype = None
+    lib.gsk_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.gsk_workspace_bytes.restype = sz
+    lib.gsk_gs_scale.argtypes = [P(Csr), vp, ctypes.c_int32, vp, vp, vp, vp, vp, sz, vp]
+    lib.gsk_gs_scale.restype = ctypes.c_int
+    lib.gsk_spmv.argtypes = [P(Csr), vp, vp, vp]
+    lib.gsk_spmv.restype = ctypes.c_int
+    lib.gsk_arnoldi.argtypes = [P(Csr), vp, ctypes.c_int32, vp, ctypes.c_int64, vp,
+                                P(ctypes.c_int32), vp, sz, vp]
+    lib.gsk_arnoldi.restype = ctypes.c_int
+    lib.gsk_gmres.argtypes = [P(Csr), vp, vp, ctypes.c_int32, ctypes.c_double, P(Options),
+                              P(InfoStruct), vp, sz, vp]
+    lib.gsk_gmres.restype = ctypes.c_int
+    lib.gsk_bicgstab.argtypes = [P(Csr), vp, vp, ctypes.c_double, P(Options), P(InfoStruct), vp,
+                                 sz, vp]
+    lib.gsk_bicgstab.restype = ctypes.c_int
+    lib.gsk_probe_begin.argtypes = [ctypes.c_int32]
+    lib.gsk_probe_begin.restype = ctypes.c_int
+    lib.gsk_probe_end.argtypes = [P(ProbeResult)]
+    lib.gsk_probe_end.restype = ctypes.c_int
+    lib.gsk_last_error.argtypes = []
+    lib.gsk_last_error.restype = ctypes.c_char_p
+    lib.gsk_version.argtypes = []
+    lib.gsk_version.restype = ctypes.c_int
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc: int) -> None:
+    if rc != OK:
+        raise GskError(rc, lib.gsk_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _vec(t: torch.Tensor, n: int, name: str) -> torch.Tensor:
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name} must be a contiguous CUDA float64 tensor of {n} elements")
+    return t
+
+
+@dataclasses.dataclass
+class Info:
+    iters: int
+    restarts: int
+    status: int
+    half_step: int
+    verify_failures: int
+    relres_recursive: float
+    relres_true: float
+    breakdown_test: int = 0
+
+    @property
+    def status_name(self) -> str:
+        return STATUS_NAMES.get(self.status, str(self.status))
+
+
+class CsrMatrix:
+    """A CSR matrix in device memory: int32 row_ptr/col_idx, float64 val (torch tensors)."""
+
+    def __init__(self, row_ptr: torch.Tensor, col_idx: torch.Tensor, val: torch.Tensor):
+        for name, t, dt in (("row_ptr", row_ptr, torch.int32), ("col_idx", col_idx, torch.int32),
+                            ("val", val, torch.float64)):
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous CUDA {dt} tensor")
+        if col_idx.numel() != val.numel():
+            raise ValueError("col_idx and val differ in length")
+        self.row_ptr, self.col_idx, self.val = row_ptr, col_idx, val
+        self.n = row_ptr.numel() - 1
+        self.nnz = val.numel()
+        self.device = val.device
+
+    @classmethod
+    def from_numpy(cls, row_ptr, col_idx, val, device="cuda") -> "CsrMatrix":
+        return cls(torch.as_tensor(row_ptr, dtype=torch.int32).to(device).contiguous(),
+                   torch.as_tensor(col_idx, dtype=torch.int32).to(device).contiguous(),
+                   torch.as_tensor(val, dtype=torch.float64).to(device).contiguous())
+
+    @classmethod
+    def from_problem(cls, problem, device="cuda") -> "CsrMatrix":
+        return cls.from_numpy(problem.row_ptr, problem.col_idx, problem.val, device)
+
+    def with_values(self, val: torch.Tensor) -> "CsrMatrix":
+        return CsrMatrix(self.row_ptr, self.col_idx, val)
+
+    def c_struct(self) -> Csr:
+        return Csr(self.n, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(),
+                   self.val.data_ptr())
+
+
+def workspace_bytes(method: int, n: int, m: int = 0) -> int:
+    return int(lib.gsk_workspace_bytes(method, n, m))
+
+
+def workspace(method: int, n: int, m: int = 0, device="cuda") -> torch.Tensor:
+    nbytes = workspace_bytes(method, n, m)
+    if nbytes == 0:
+        raise GskError(ERR_INVALID_ARG, f"no workspace size for method={method} n={n} m={m}")
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + nbytes]
+
+
+def default_options() -> Options:
+    o = Options()
+    lib.gsk_default_options(ctypes.byref(o))
+    return o
+
+
+def gs_scale(A: CsrMatrix, b: torch.Tensor, p: int = 2, *, inplace: bool = False,
+             want_norms: bool = True, want_weights: bool = False,
+             ws: Optional[torch.Tensor] = None):
+    """GS(p): returns (A_scaled, b_scaled, row_norms or None, stop_weights or None)."""
+    _vec(b, A.n, "b")
+    val_out = A.val if inplace else torch.empty_like(A.val)
+    b_out = b if inplace else torch.empty_like(b)
+    norms = torch.empty(A.n, dtype=torch.float64, device=A.device) if want_norms else None
+    weights = torch.empty(A.n, dtype=torch.float64, device=A.device) if want_weights else None
+    if ws is None:
+        ws = workspace(METHOD_GS, A.n, 0, A.device)
+    c = A.c_struct()
+    _check(lib.gsk_gs_scale(ctypes.byref(c), b.data_ptr(), int(p), val_out.data_ptr(),
+                            b_out.data_ptr(), _ptr(norms), _ptr(weights), ws.data_ptr(),
+                            ws.numel(), _stream(A.device)))
+    return A.with_values(val_out), b_out, norms, weights
+
+
+def spmv(A: CsrMatrix, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    _vec(x, A.n, "x")
+    y = torch.empty_like(x) if out is None else _vec(out, A.n, "out")
+    c = A.c_struct()
+    _check(lib.gsk_spmv(ctypes.byref(c), x.data_ptr(), y.data_ptr(), _stream(A.device)))
+    return y
+
+
+def arnoldi(A: CsrMatrix, r0: torch.Tensor, m: int, ws: Optional[torch.Tensor] = None):
+    """CGS2 Arnoldi: returns (V [n x (m+1)] column-major storage as a (m+1, n) tensor
+    transposed view, H [(m+1) x m], steps)."""
+    _vec(r0, A.n, "r0")
+    Vs = torch.zeros((m + 1, A.n), dtype=torch.float64, device=A.device)
+    Hs = torch.zeros((m, m + 1), dtype=torch.float64, device=A.device)
+    steps = ctypes.c_int32(0)
+    if ws is None:
+        ws = workspace(METHOD_ARNOLDI, A.n, m, A.device)
+    c = A.c_struct()
+    _check(lib.gsk_arnoldi(ctypes.byref(c), r0.data_ptr(), int(m), Vs.data_ptr(), A.n,
+                           Hs.data_ptr(), ctypes.byref(steps), ws.data_ptr(), ws.numel(),
+                           _stream(A.device)))
+    return Vs.t(), Hs.t(), int(steps.value)
+
+
+def _options(maxit, breakdown_eps, stop_weights, check_every, n) -> Options:
+    o = default_options()
+    if maxit is not None:
+        o.maxit = int(maxit)
+    if breakdown_eps is not None:
+        o.breakdown_eps = float(breakdown_eps)
+    if stop_weights is not None:
+        o.stop_weights = _vec(stop_weights, n, "stop_weights").data_ptr()
+    if check_every is not None:
+        o.check_every = int(check_every)
+    return o
+
+
+def _info(s: InfoStruct) -> Info:
+    return Info(s.iters, s.restarts, s.status, s.half_step, s.verify_failures,
+                s.relres_recursive, s.relres_true, s.breakdown_test)
+
+
+def gmres(A: CsrMatrix, b: torch.Tensor, x0: Optional[torch.Tensor] = None, m: int = 30,
+          tol: float = 1e-8, *, maxit: Optional[int] = None, breakdown_eps=None,
+          stop_weights: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
+          x_out: Optional[torch.Tensor] = None):
+    """Restarted GMRES(m) with CGS2 Arnoldi. Returns (x, Info)."""
+    _vec(b, A.n, "b")
+    if x_out is not None:
+        x = _vec(x_out, A.n, "x_out")
+        if x0 is None:
+            x.zero_()
+        elif x0.data_ptr() != x.data_ptr():
+            x.copy_(x0)
+    else:
+        x = torch.zeros_like(b) if x0 is None else _vec(x0, A.n, "x0").clone()
+    if ws is None:
+        ws = workspace(METHOD_GMRES, A.n, m, A.device)
+    o = _options(maxit, breakdown_eps, stop_weights, None, A.n)
+    info = InfoStruct()
+    c = A.c_struct()
+    _check(lib.gsk_gmres(ctypes.byref(c), b.data_ptr(), x.data_ptr(), int(m), float(tol),
+                         ctypes.byref(o), ctypes.byref(info), ws.data_ptr(), ws.numel(),
+                         _stream(A.device)))
+    return x, _info(info)
+
+
+def bicgstab(A: CsrMatrix, b: torch.Tensor, x0: Optional[torch.Tensor] = None,
+             tol: float = 1e-8, *, maxit: Optional[int] = None, breakdown_eps=None,
+             stop_weights: Optional[torch.Tensor] = None, check_every: Optional[int] = None,
+             ws: Optional[torch.Tensor] = None, x_out: Optional[torch.Tensor] = None):
+    """Bi-CGSTAB. Returns (x, Info)."""
+    _vec(b, A.n, "b")
+    if x_out is not None:
+        x = _vec(x_out, A.n, "x_out")
+        if x0 is None:
+            x.zero_()
+        elif x0.data_ptr() != x.data_ptr():
+            x.copy_(x0)
+    else:
+        x = torch.zeros_like(b) if x0 is None else _vec(x0, A.n, "x0").clone()
+    if ws is None:
+        ws = workspace(METHOD_BICGSTAB, A.n, 0, A.device)
+    o = _options(maxit, breakdown_eps, stop_weights, check_every, A.n)
+    info = InfoStruct()
+    c = A.c_struct()
+    _check(lib.gsk_bicgstab(ctypes.byref(c), b.data_ptr(), x.data_ptr(), float(tol),
+                            ctypes.byref(o), ctypes.byref(info), ws.data_ptr(), ws.numel(),
+                            _stream(A.device)))
+    return x, _info(info)
+
+
+def probe_begin(kernel_class: str) -> None:
+    """Start timing every launch of one kernel class (see gsk_probe_begin in gsk.h)."""
+    _check(lib.gsk_probe_begin(KCLASS[kernel_class]))
+
+
+def probe_end() -> dict:
+    r = ProbeResult()
+    _check(lib.gsk_probe_end(ctypes.byref(r)))
+    return {"launches": r.launches, "busy_launches": r.busy_launches, "total_ms": r.total_ms,
+            "bytes": r.bytes}

@@ -1,0 +1,141 @@
+"""The C ABI library loads and exports every symbol include/gsk.h declares; host-side argument
+checks reject bad calls before any device work. No GPU needed: nothing here launches a kernel."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gsk.h")
+LIB = os.path.join(ROOT, "paper_0812_2769_amd", "libgsk.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gsk_\w+)\s*\(", text)))
+
+
+def header_define(name):
+    m = re.search(rf"#define\s+{name}\s+\(?(-?\d+)\)?", open(HEADER).read())
+    return int(m.group(1))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_0812_2769_amd import build
+        build.build()
+    from paper_0812_2769_amd import gsk
+    return gsk
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert {"gsk_gs_scale", "gsk_gmres", "gsk_bicgstab", "gsk_spmv", "gsk_arnoldi",
+            "gsk_workspace_bytes"} <= set(names)
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT\s+(\w+)$", out, flags=re.M))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        getattr(lib.lib, n)
+
+
+def test_version_and_constants(lib):
+    assert lib.lib.gsk_version() == header_define("GSK_VERSION")
+    assert lib.MAX_RESTART == header_define("GSK_MAX_RESTART")
+    for name, val in (("GSK_ERR_INVALID_ARG", lib.ERR_INVALID_ARG),
+                      ("GSK_ERR_ZERO_ROW", lib.ERR_ZERO_ROW),
+                      ("GSK_ERR_NONFINITE", lib.ERR_NONFINITE),
+                      ("GSK_ERR_WORKSPACE", lib.ERR_WORKSPACE),
+                      ("GSK_CONVERGED", lib.CONVERGED), ("GSK_MAXIT", lib.MAXIT),
+                      ("GSK_BREAKDOWN", lib.BREAKDOWN), ("GSK_STAGNATED", lib.STAGNATED)):
+        assert header_define(name) == val, name
+
+
+def test_struct_layouts(lib):
+    # gsk_csr {int32; int64; 3 pointers}, gsk_options {int32; double; ptr; int32}, gsk_info
+    assert ctypes.sizeof(lib.Csr) == 40
+    assert ctypes.sizeof(lib.Options) == 32
+    assert ctypes.sizeof(lib.InfoStruct) == 40
+
+
+def test_defaults(lib):
+    o = lib.default_options()
+    assert o.maxit == 10000
+    assert o.breakdown_eps == pytest.approx(1e-16 * 2.220446049250313e-16, rel=1e-15)
+    assert o.check_every == 8 and not o.stop_weights
+
+
+def test_workspace_bytes(lib):
+    n = 512000
+    g30 = lib.workspace_bytes(lib.METHOD_GMRES, n, 30)
+    g20 = lib.workspace_bytes(lib.METHOD_GMRES, n, 20)
+    assert g30 - g20 == 10 * 8 * ((n + 63) // 64 * 64)
+    assert lib.workspace_bytes(lib.METHOD_BICGSTAB, n) > 7 * 8 * n
+    assert lib.workspace_bytes(lib.METHOD_GS, n) > 0
+    assert lib.workspace_bytes(lib.METHOD_GMRES, n, 0) == 0
+    assert lib.workspace_bytes(lib.METHOD_GMRES, n, 65) == 0
+    assert lib.workspace_bytes(lib.METHOD_GMRES, 0, 10) == 0
+    assert lib.workspace_bytes(99, n, 10) == 0
+
+
+def _fake_csr(lib, n=10, nnz=30):
+    # non-NULL placeholders: every call below is rejected before any device access
+    return lib.Csr(n, nnz, 0x1000, 0x2000, 0x3000)
+
+
+def test_host_side_rejections(lib):
+    L = lib.lib
+    c = _fake_csr(lib)
+    info = lib.InfoStruct()
+    o = lib.default_options()
+    ws_ok = 0x100000  # 256-aligned placeholder, paired with too small a size below
+    # NULL matrix
+    assert L.gsk_gs_scale(None, 0x10, 2, 0x20, 0x30, None, None, ws_ok, 1 << 30, None) == -1
+    assert b"NULL" in L.gsk_last_error()
+    # p < 1
+    assert L.gsk_gs_scale(ctypes.byref(c), 0x10, 0, 0x20, 0x30, None, None, ws_ok, 1 << 30, None) == -1
+    # bad n / nnz
+    bad = lib.Csr(0, 0, 0x1000, 0, 0)
+    assert L.gsk_spmv(ctypes.byref(bad), 0x10, 0x20, None) == -1
+    bad = lib.Csr(5, -1, 0x1000, 0x2000, 0x3000)
+    assert L.gsk_spmv(ctypes.byref(bad), 0x10, 0x20, None) == -1
+    # restart length out of range
+    assert L.gsk_gmres(ctypes.byref(c), 0x10, 0x20, 0, 1e-8, None, ctypes.byref(info), ws_ok,
+                       1 << 30, None) == -1
+    assert L.gsk_gmres(ctypes.byref(c), 0x10, 0x20, 65, 1e-8, None, ctypes.byref(info), ws_ok,
+                       1 << 30, None) == -1
+    # tol <= 0, maxit < 0, check_every out of range
+    assert L.gsk_bicgstab(ctypes.byref(c), 0x10, 0x20, 0.0, None, ctypes.byref(info), ws_ok,
+                          1 << 30, None) == -1
+    o.maxit = -1
+    assert L.gsk_bicgstab(ctypes.byref(c), 0x10, 0x20, 1e-8, ctypes.byref(o), ctypes.byref(info),
+                          ws_ok, 1 << 30, None) == -1
+    o = lib.default_options()
+    o.check_every = 0
+    assert L.gsk_bicgstab(ctypes.byref(c), 0x10, 0x20, 1e-8, ctypes.byref(o), ctypes.byref(info),
+                          ws_ok, 1 << 30, None) == -1
+    # workspace: NULL, misaligned, too small
+    assert L.gsk_bicgstab(ctypes.byref(c), 0x10, 0x20, 1e-8, None, ctypes.byref(info), None,
+                          1 << 30, None) == -4
+    assert L.gsk_bicgstab(ctypes.byref(c), 0x10, 0x20, 1e-8, None, ctypes.byref(info), ws_ok + 8,
+                          1 << 30, None) == -4
+    assert L.gsk_gmres(ctypes.byref(c), 0x10, 0x20, 10, 1e-8, None, ctypes.byref(info), ws_ok, 16,
+                       None) == -4
+    assert b"needed" in L.gsk_last_error()
+    # arnoldi: ldv < n
+    steps = ctypes.c_int32(0)
+    assert L.gsk_arnoldi(ctypes.byref(c), 0x10, 4, 0x20, 5, 0x30, ctypes.byref(steps), ws_ok,
+                         1 << 30, None) == -1
+
+
+def test_binding_refuses_cpu_tensors(lib):
+    import torch
+    with pytest.raises(ValueError):
+        lib.CsrMatrix(torch.zeros(3, dtype=torch.int32), torch.zeros(2, dtype=torch.int32),
+                      torch.zeros(2, dtype=torch.float64))
