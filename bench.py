@@ -69,7 +69,10 @@ def parse():
                     help="iterations per solver the CPU oracle runs for its baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe", default="gmres_a",
-                    help="kernel class timed with HIP events during the timed steps")
+                    help="kernel class timed with HIP events during the timed steps "
+                         "('none' to time nothing)")
+    ap.add_argument("--probe-every", type=int, default=4,
+                    help="time every k-th launch of the probed class (default 4)")
     ap.add_argument("--no-kernel-table", action="store_true",
                     help="skip the extra untimed step per kernel class")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -193,22 +196,23 @@ def main():
         step({k: [] for k in lat}, infos)
         print(f"bench: warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    gsk.probe_begin(args.probe)
+    if args.probe != "none":
+        gsk.probe_begin(args.probe, args.probe_every)
     t_start = time.perf_counter()
     for i in range(args.steps):
         step(lat, infos)
         print(f"bench: step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
-    probe = gsk.probe_end()
+    probe = gsk.probe_end() if args.probe != "none" else {"total_ms": 0, "busy_launches": 0}
 
     def achieved(pr):
         if pr["total_ms"] <= 0 or pr["busy_launches"] == 0:
             return None
         return {"achieved_GBs": round(pr["bytes"] / (pr["total_ms"] * 1e-3) / 1e9, 1),
-                "avg_launch_us": round(1e3 * pr["total_ms"] / pr["launches"], 3),
+                "avg_launch_us": round(1e3 * pr["total_ms"] / pr["busy_launches"], 3),
                 "bytes_per_launch": round(pr["bytes"] / pr["busy_launches"]),
-                "launches": pr["launches"], "busy_launches": pr["busy_launches"]}
+                "timed_launches": pr["launches"], "busy_launches": pr["busy_launches"]}
 
     kernels = {}
     if not args.no_kernel_table:
@@ -258,11 +262,12 @@ def main():
             "bound": "hbm", "achieved": a["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(a["achieved_GBs"] / HBM_PEAK_GBS, 4),
             "traffic": traffic_for(args.probe, args.grid),
-            "kernel": KERNEL_NAMES[args.probe], "avg_launch_us": a["avg_launch_us"],
-            "bytes_per_launch": a["bytes_per_launch"], "launches": a["launches"],
-            "busy_launches": a["busy_launches"],
-            "note": ("achieved = algorithmic bytes of the working launches / summed HIP-event "
-                     "duration of all launches of the class over the timed steps")}
+            "kernel": KERNEL_NAMES.get(args.probe), "avg_launch_us": a["avg_launch_us"],
+            "bytes_per_launch": a["bytes_per_launch"], "timed_launches": a["timed_launches"],
+            "busy_launches": a["busy_launches"], "sample_every": args.probe_every,
+            "note": ("achieved = algorithmic bytes / HIP-event duration, summed over the timed "
+                     "launches that did work (every k-th launch of the class during the timed "
+                     "steps)")}
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(P, {k: infos[k].iters for k in infos},

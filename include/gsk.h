@@ -187,12 +187,13 @@ int gsk_bicgstab(const gsk_csr* A, const double* b, double* x, double tol,
                  void* stream);
 
 /*
- * Measurement hook (not part of the method): between gsk_probe_begin(c) and gsk_probe_end,
- * every launch of kernel class c made by the solvers is bracketed by a pair of HIP events on
- * the solver's stream, and each launch that did work (rather than returning at once because
- * the solve had already finished) adds its algorithmic HBM bytes to a device counter, which
- * is collected at the end of each solve. Algorithmic bytes per launch, n rows, nnz nonzeros,
- * FP64 values, int32 indices, step j of an Arnoldi cycle (basis columns 0..j):
+ * Measurement hook (not part of the method). Between gsk_probe_begin(c, k) and gsk_probe_end,
+ * every k-th launch of kernel class c made by the solvers is timed: it is bracketed by a pair
+ * of HIP events (created without a system-scope fence) on the solver's stream, and it carries
+ * a device slot in which it stores its algorithmic HBM bytes if it does work (a launch that
+ * returns at once because the solve had already finished leaves it zero and is not counted).
+ * Algorithmic bytes per launch, n rows, nnz nonzeros, FP64 values, int32 indices, step j of an
+ * Arnoldi cycle (basis columns 0..j):
  *   GMRES_A   12 nnz + 4 (n+1) + 8 n (j+2)   CSR + basis columns 0..j (column j is also the
  *                                            product's source) + write w
  *   GMRES_B   8 n (j+3)                      basis columns 0..j, read and write w
@@ -200,11 +201,12 @@ int gsk_bicgstab(const gsk_csr* A, const double* b, double* x, double tol,
  *   BICG_P    12 nnz + 4 (n+1) + 48 n        CSR, r p v r^, write p v (32 n on the first
  *                                            iteration after a start: r r^, write p v)
  *   BICG_S    12 nnz + 4 (n+1) + 24 n        CSR, r v, write t (+8 n with stop weights)
- *   BICG_U    64 n                           r v p x t r^, write x r (+8 n with weights)
- *   RESIDUAL  12 nnz + 4 (n+1) + 32 n        CSR, x b, write r (and r^ in Bi-CGSTAB: +8 n)
+ *   BICG_U    64 n                           r v p x t r^, write x r (+8 n with weights;
+ *                                            24 n after a half-step exit)
+ *   RESIDUAL  12 nnz + 4 (n+1) + 24..40 n    CSR, x b, write r (and r^ in Bi-CGSTAB), weights
  *   GMRES_X   8 n (k+2)                      k basis columns, read and write x
  * Process-wide; not for concurrent use from several host threads. gsk_probe_end
- * synchronises the device. The event records themselves add a little time per launch.
+ * synchronises the device.
  */
 #define GSK_KCLASS_GMRES_A 1
 #define GSK_KCLASS_GMRES_B 2
@@ -216,13 +218,13 @@ int gsk_bicgstab(const gsk_csr* A, const double* b, double* x, double tol,
 #define GSK_KCLASS_GMRES_X 8
 
 typedef struct gsk_probe_result {
-    int64_t launches;       /* launches of the class that were timed                  */
-    int64_t busy_launches;  /* of those, launches that did work                       */
-    double total_ms;        /* sum of the event-measured durations of all launches    */
-    double bytes;           /* sum of the algorithmic bytes of the working launches   */
+    int64_t launches;       /* launches of the class that were timed                      */
+    int64_t busy_launches;  /* of those, launches that did work                           */
+    double total_ms;        /* summed event-measured durations of the working timed launches */
+    double bytes;           /* summed algorithmic bytes of the working timed launches     */
 } gsk_probe_result;
 
-int gsk_probe_begin(int32_t kernel_class);
+int gsk_probe_begin(int32_t kernel_class, int32_t sample_every);
 int gsk_probe_end(gsk_probe_result* out);
 
 /* Message for the last error returned on this thread ("" if none). */

@@ -107,8 +107,15 @@ void fill_info(gsk_info* info, const Summary& s) {
 struct Probe {
   std::mutex mu;
   std::atomic<int> cls{0};
+  int every = 1;
+  long long seen = 0;      // launches of the class since gsk_probe_begin
+  int next_slot = 0;       // slots handed out in the current solve
+  struct Timed {
+    hipEvent_t start, stop;
+    int slot;
+  };
   std::vector<hipEvent_t> pool;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pairs;
+  std::vector<Timed> timed;
   hipEvent_t open = nullptr;
   double total_ms = 0.0;
   long long launches = 0;
@@ -127,27 +134,39 @@ hipEvent_t take_event(Probe& p) {
     p.pool.pop_back();
     return e;
   }
+  // Timing events without the system-scope fence a default event performs when it is
+  // recorded; only their timestamps are used.
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
-// Adds the elapsed times of all recorded pairs (the caller has synchronised their streams)
-// and returns the events to the pool.
-void harvest(Probe& p) {
-  for (auto& pr : p.pairs) {
-    float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) p.total_ms += ms;
-    p.launches += 1;
-    p.pool.push_back(pr.first);
-    p.pool.push_back(pr.second);
+void recycle(Probe& p) {
+  for (auto& t : p.timed) {
+    p.pool.push_back(t.start);
+    p.pool.push_back(t.stop);
   }
-  p.pairs.clear();
+  p.timed.clear();
 }
 
 }  // namespace
 
-int probe_class() { return probe_state().cls.load(std::memory_order_relaxed); }
+void probe_solve_begin() {
+  Probe& p = probe_state();
+  if (p.cls.load(std::memory_order_relaxed) == KC_NONE) return;
+  std::lock_guard<std::mutex> g(p.mu);
+  recycle(p);   // pairs of an earlier solve that was never collected (an error path)
+  p.next_slot = 0;
+}
+
+int probe_slot(int kernel_class) {
+  Probe& p = probe_state();
+  if (p.cls.load(std::memory_order_relaxed) != kernel_class) return -1;
+  std::lock_guard<std::mutex> g(p.mu);
+  const long long k = p.seen++;
+  if (k % p.every != 0 || p.next_slot >= PROBE_SLOTS) return -1;
+  return p.next_slot++;
+}
 
 void probe_begin(hipStream_t s) {
   Probe& p = probe_state();
@@ -159,13 +178,13 @@ void probe_begin(hipStream_t s) {
   }
 }
 
-void probe_end(hipStream_t s) {
+void probe_end(hipStream_t s, int slot) {
   Probe& p = probe_state();
   std::lock_guard<std::mutex> g(p.mu);
   if (!p.open) return;
   hipEvent_t e = take_event(p);
   if (e && hipEventRecord(e, s) == hipSuccess) {
-    p.pairs.emplace_back(p.open, e);
+    p.timed.push_back(Probe::Timed{p.open, e, slot});
   } else {
     p.pool.push_back(p.open);
     if (e) p.pool.push_back(e);
@@ -173,18 +192,33 @@ void probe_end(hipStream_t s) {
   p.open = nullptr;
 }
 
-void probe_collect(const Work* device_work, hipStream_t s) {
-  Work w;
-  if (hipMemcpyAsync(&w, device_work, sizeof(Work), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return;
+// After a solve has synchronised its stream: add the durations and bytes of the timed
+// launches that did work (their slot holds their algorithmic bytes; zero means the launch
+// returned at once).
+void probe_collect(const ProbeSlots* device_slots, hipStream_t s) {
   Probe& p = probe_state();
+  if (p.cls.load(std::memory_order_relaxed) == KC_NONE) return;
   std::lock_guard<std::mutex> g(p.mu);
-  const int c = p.cls.load(std::memory_order_relaxed);
-  if (c <= KC_NONE || c >= KC_COUNT) return;
-  p.busy += w.busy[c];
-  p.bytes += w.bytes[c];
-  harvest(p);
+  if (p.timed.empty()) return;
+  std::vector<double> bytes((size_t)p.next_slot, 0.0);
+  if (p.next_slot > 0 &&
+      (hipMemcpyAsync(bytes.data(), device_slots->bytes, sizeof(double) * (size_t)p.next_slot,
+                      hipMemcpyDeviceToHost, s) != hipSuccess ||
+       hipStreamSynchronize(s) != hipSuccess)) {
+    recycle(p);
+    return;
+  }
+  for (auto& t : p.timed) {
+    p.launches += 1;
+    const double b = (t.slot >= 0 && t.slot < p.next_slot) ? bytes[(size_t)t.slot] : 0.0;
+    if (b <= 0.0) continue;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, t.start, t.stop) != hipSuccess) continue;
+    p.busy += 1;
+    p.total_ms += ms;
+    p.bytes += b;
+  }
+  recycle(p);
 }
 
 Summary* pinned_summaries() {
@@ -234,17 +268,21 @@ size_t gsk_workspace_bytes(int32_t method, int32_t n, int32_t m) {
 
 int gsk_version(void) { return GSK_VERSION; }
 
-int gsk_probe_begin(int32_t kernel_class) {
+int gsk_probe_begin(int32_t kernel_class, int32_t sample_every) {
   g_err.clear();
   if (kernel_class < GSK_KCLASS_GMRES_A || kernel_class > GSK_KCLASS_GMRES_X)
     return set_err(GSK_ERR_INVALID_ARG, "unknown kernel class %d", (int)kernel_class);
+  if (sample_every < 1) return set_err(GSK_ERR_INVALID_ARG, "sample_every must be >= 1");
   Probe& p = probe_state();
   std::lock_guard<std::mutex> g(p.mu);
   p.total_ms = 0.0;
   p.launches = 0;
   p.busy = 0;
   p.bytes = 0.0;
-  p.pairs.clear();
+  p.seen = 0;
+  p.next_slot = 0;
+  p.every = sample_every;
+  recycle(p);
   p.open = nullptr;
   p.cls.store(kernel_class, std::memory_order_relaxed);
   return GSK_OK;
@@ -255,7 +293,7 @@ int gsk_probe_end(gsk_probe_result* out) {
   Probe& p = probe_state();
   hipError_t e = hipDeviceSynchronize();
   std::lock_guard<std::mutex> g(p.mu);
-  harvest(p);
+  recycle(p);
   if (out) {
     out->launches = p.launches;
     out->busy_launches = p.busy;

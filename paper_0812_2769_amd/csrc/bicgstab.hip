@@ -37,6 +37,7 @@ struct BArgs {
   const double* b;
   const double* W;
   double csr_bytes;   // 12 nnz + 4 (n+1)
+  int pslot;          // measurement slot of this launch, or -1
 };
 
 __device__ inline void brange(const BArgs& a, int lb, int& begin, int& end) {
@@ -47,6 +48,7 @@ __device__ inline void brange(const BArgs& a, int lb, int& begin, int& end) {
 
 __global__ __launch_bounds__(64) void k_bicg_init_ctl(Ctl* c, int maxit, double tol, double eps_b,
                                                       int has_w) {
+  for (int i = threadIdx.x; i < PROBE_SLOTS; i += 64) c->probe.bytes[i] = 0.0;
   if (threadIdx.x != 0) return;
   c->sum.state = ST_INIT;
   c->sum.status = S_MAXIT;
@@ -58,10 +60,6 @@ __global__ __launch_bounds__(64) void k_bicg_init_ctl(Ctl* c, int maxit, double 
   c->sum.relres_rec = 1.0;
   c->sum.relres_true = 1.0;
   c->sum.brk = BRK_NONE;
-  for (int i = 0; i < KC_COUNT; ++i) {
-    c->work.bytes[i] = 0.0;
-    c->work.busy[i] = 0;
-  }
   c->maxit = maxit;
   c->m = 0;
   c->j = c->k = c->claimed = 0;
@@ -83,7 +81,7 @@ __global__ __launch_bounds__(BS) void k_bicg_residual(BArgs a, const int* flags)
   const int st = c->sum.state;
   if (st != ST_INIT && st != ST_VERIFY && st != ST_FINAL) return;
   if (flags[0]) return;
-  count_work(c, KC_RESIDUAL, a.csr_bytes + 8.0 * a.n * ((st != ST_FINAL ? 4 : 2) + (a.W ? 1 : 0)));
+  mark_work(c, a.pslot, a.csr_bytes + 8.0 * a.n * ((st != ST_FINAL ? 4 : 2) + (a.W ? 1 : 0)));
   __shared__ TileLds L;
   __shared__ double red[NC_MAX * WAVES];
   const int nb = gridDim.x;
@@ -205,7 +203,7 @@ struct GatherS {
 __global__ __launch_bounds__(BS) void k_bicg_p(BArgs a) {
   Ctl* c = a.ctl;
   if (c->sum.state != ST_RUNNING) return;
-  count_work(c, KC_BICG_P, a.csr_bytes + 8.0 * a.n * (c->first ? 4 : 6));
+  mark_work(c, a.pslot, a.csr_bytes + 8.0 * a.n * (c->first ? 4 : 6));
   const int q = c->parity;
   const double* pin = a.p[q];
   const double* vin = a.v[q];
@@ -254,7 +252,7 @@ __global__ __launch_bounds__(BS) void k_bicg_fin_p(Ctl* c, const double* partial
 __global__ __launch_bounds__(BS) void k_bicg_s(BArgs a) {
   Ctl* c = a.ctl;
   if (c->sum.state != ST_RUNNING) return;
-  count_work(c, KC_BICG_S, a.csr_bytes + 8.0 * a.n * (a.W ? 4 : 3));
+  mark_work(c, a.pslot, a.csr_bytes + 8.0 * a.n * (a.W ? 4 : 3));
   const int q = c->parity ^ 1;   // the v written by P in this iteration
   const GatherS G{a.r, a.v[q], c->alpha};
   __shared__ TileLds L;
@@ -315,7 +313,7 @@ __global__ __launch_bounds__(BS) void k_bicg_u(BArgs a) {
   Ctl* c = a.ctl;
   const int st = c->sum.state;
   if (st != ST_RUNNING && st != ST_HALF) return;
-  count_work(c, KC_BICG_U, 8.0 * a.n * (st == ST_HALF ? 3 : (a.W ? 9 : 8)));
+  mark_work(c, a.pslot, 8.0 * a.n * (st == ST_HALF ? 3 : (a.W ? 9 : 8)));
   const int q = c->parity ^ 1;
   const double* p = a.p[q];
   const double* v = a.v[q];
@@ -379,10 +377,11 @@ __global__ __launch_bounds__(BS) void k_bicg_fin_u(Ctl* c, const double* partial
 }
 
 static void launch_residual(const BArgs& a, int nb, const int* flags, hipStream_t s) {
-  const bool pr = probe_class() == KC_RESIDUAL;
-  if (pr) probe_begin(s);
-  hipLaunchKernelGGL(k_bicg_residual, dim3(nb), dim3(BS), 0, s, a, flags);
-  if (pr) probe_end(s);
+  BArgs ax = a;
+  ax.pslot = probe_slot(KC_RESIDUAL);
+  if (ax.pslot >= 0) probe_begin(s);
+  hipLaunchKernelGGL(k_bicg_residual, dim3(nb), dim3(BS), 0, s, ax, flags);
+  if (ax.pslot >= 0) probe_end(s, ax.pslot);
   hipLaunchKernelGGL(k_bicg_fin_residual, dim3(1), dim3(BS), 0, s, a.ctl,
                      (const double*)a.partials, nb, a.W ? 1 : 0, flags);
 }
@@ -390,18 +389,21 @@ static void launch_residual(const BArgs& a, int nb, const int* flags, hipStream_
 static void launch_iteration(const BArgs& a, int nb, hipStream_t s) {
   const int hw = a.W ? 1 : 0;
   const double* pt = a.partials;
-  const int pc = probe_class();
-  if (pc == KC_BICG_P) probe_begin(s);
-  hipLaunchKernelGGL(k_bicg_p, dim3(nb), dim3(BS), 0, s, a);
-  if (pc == KC_BICG_P) probe_end(s);
+  BArgs ax = a;
+  ax.pslot = probe_slot(KC_BICG_P);
+  if (ax.pslot >= 0) probe_begin(s);
+  hipLaunchKernelGGL(k_bicg_p, dim3(nb), dim3(BS), 0, s, ax);
+  if (ax.pslot >= 0) probe_end(s, ax.pslot);
   hipLaunchKernelGGL(k_bicg_fin_p, dim3(1), dim3(BS), 0, s, a.ctl, pt, nb);
-  if (pc == KC_BICG_S) probe_begin(s);
-  hipLaunchKernelGGL(k_bicg_s, dim3(nb), dim3(BS), 0, s, a);
-  if (pc == KC_BICG_S) probe_end(s);
+  ax.pslot = probe_slot(KC_BICG_S);
+  if (ax.pslot >= 0) probe_begin(s);
+  hipLaunchKernelGGL(k_bicg_s, dim3(nb), dim3(BS), 0, s, ax);
+  if (ax.pslot >= 0) probe_end(s, ax.pslot);
   hipLaunchKernelGGL(k_bicg_fin_s, dim3(1), dim3(BS), 0, s, a.ctl, pt, nb, hw);
-  if (pc == KC_BICG_U) probe_begin(s);
-  hipLaunchKernelGGL(k_bicg_u, dim3(nb), dim3(BS), 0, s, a);
-  if (pc == KC_BICG_U) probe_end(s);
+  ax.pslot = probe_slot(KC_BICG_U);
+  if (ax.pslot >= 0) probe_begin(s);
+  hipLaunchKernelGGL(k_bicg_u, dim3(nb), dim3(BS), 0, s, ax);
+  if (ax.pslot >= 0) probe_end(s, ax.pslot);
   hipLaunchKernelGGL(k_bicg_fin_u, dim3(1), dim3(BS), 0, s, a.ctl, pt, nb, hw);
 }
 
@@ -437,10 +439,12 @@ SolveResult bicgstab_solve(const Csr& A, const double* b, double* x, const Solve
   a.b = b;
   a.W = prm.weights;
   a.csr_bytes = csr_bytes(A);
+  a.pslot = -1;
   if (launch_clear_flags(Wk.flags, s) != hipSuccess) return bfail(-5);
   if (launch_validate(A, Wk.flags, s) != hipSuccess) return bfail(-5);
   hipLaunchKernelGGL(k_bicg_init_ctl, dim3(1), dim3(64), 0, s, Wk.ctl, prm.maxit, prm.tol,
                      prm.eps_b, prm.weights ? 1 : 0);
+  probe_solve_begin();
   launch_residual(a, g.nb, Wk.flags, s);
   if (hipGetLastError() != hipSuccess) return bfail(-5);
 
@@ -477,7 +481,7 @@ SolveResult bicgstab_solve(const Csr& A, const double* b, double* x, const Solve
     slot ^= 1;
   }
   if (hipStreamSynchronize(s) != hipSuccess && res.code == 0) res.code = -5;
-  if (res.code == 0 && probe_class() != KC_NONE) probe_collect(&Wk.ctl->work, s);
+  if (res.code == 0) probe_collect(&Wk.ctl->probe, s);
   if (res.code == 0) {
     res.sum = hs[slot ^ 1];
     if (res.sum.state != ST_DONE) res.code = -5;

@@ -37,10 +37,12 @@ struct KArgs {
   Ctl* ctl;
   double* partials;
   double csr_bytes;   // 12 nnz + 4 (n+1): one read of val, col_idx and row_ptr
+  int pslot;          // measurement slot of this launch, or -1
 };
 
 __global__ __launch_bounds__(64) void k_init_ctl(Ctl* c, int maxit, int m, double tol,
                                                  double eps_b, int has_w) {
+  for (int i = threadIdx.x; i < PROBE_SLOTS; i += 64) c->probe.bytes[i] = 0.0;
   if (threadIdx.x != 0) return;
   c->sum.state = ST_INIT;
   c->sum.status = S_MAXIT;
@@ -50,10 +52,6 @@ __global__ __launch_bounds__(64) void k_init_ctl(Ctl* c, int maxit, int m, doubl
   c->sum.fails = 0;
   c->sum.steps = 0;
   c->sum.brk = BRK_NONE;
-  for (int i = 0; i < KC_COUNT; ++i) {
-    c->work.bytes[i] = 0.0;
-    c->work.busy[i] = 0;
-  }
   c->sum.relres_rec = 1.0;
   c->sum.relres_true = 1.0;
   c->maxit = maxit;
@@ -103,7 +101,7 @@ __global__ __launch_bounds__(BS) void k_gmres_residual(KArgs a, const double* __
   const int st = c->sum.state;
   if (st != ST_INIT && st != ST_CYCLE_END) return;
   if (flags[0]) return;
-  count_work(c, KC_RESIDUAL, a.csr_bytes + 8.0 * a.n * (W ? 4 : 3));
+  mark_work(c, a.pslot, a.csr_bytes + 8.0 * a.n * (W ? 4 : 3));
   __shared__ TileLds L;
   __shared__ double red[NC_MAX * WAVES];
   const int nb = gridDim.x;
@@ -209,7 +207,7 @@ __global__ __launch_bounds__(BS) void k_gmres_a(KArgs a, const double* __restric
                                                 double* __restrict__ w, int j) {
   Ctl* c = a.ctl;
   if (c->sum.state != ST_RUNNING || c->j != j) return;
-  count_work(c, KC_GMRES_A, a.csr_bytes + 8.0 * a.n * (j + 2));
+  mark_work(c, a.pslot, a.csr_bytes + 8.0 * a.n * (j + 2));
   __shared__ TileLds L;
   __shared__ double red[NC_MAX * WAVES];
   __shared__ double red1[WAVES];
@@ -255,7 +253,7 @@ __global__ __launch_bounds__(BS) void k_gmres_b(KArgs a, const double* __restric
                                                 double* __restrict__ w, int j) {
   Ctl* c = a.ctl;
   if (c->sum.state != ST_RUNNING || c->j != j) return;
-  count_work(c, KC_GMRES_B, 8.0 * a.n * (j + 3));
+  mark_work(c, a.pslot, 8.0 * a.n * (j + 3));
   __shared__ double d[JM];
   __shared__ double red[NC_MAX * WAVES];
   const int t = threadIdx.x;
@@ -295,7 +293,7 @@ __global__ __launch_bounds__(BS) void k_gmres_c(KArgs a, double* __restrict__ V,
                                                 const double* __restrict__ w, int j) {
   Ctl* c = a.ctl;
   if (c->sum.state != ST_RUNNING || c->j != j) return;
-  count_work(c, KC_GMRES_C, 8.0 * a.n * (j + 3));
+  mark_work(c, a.pslot, 8.0 * a.n * (j + 3));
   __shared__ double d[JM];
   __shared__ double red[WAVES];
   const int t = threadIdx.x;
@@ -408,7 +406,7 @@ __global__ __launch_bounds__(BS) void k_gmres_x(KArgs a, const double* __restric
   if (c->sum.state != ST_CYCLE_END) return;
   __shared__ double s_y[MMAX];
   const int k = c->k;
-  count_work(c, KC_GMRES_X, 8.0 * a.n * (k + 2));
+  mark_work(c, a.pslot, 8.0 * a.n * (k + 2));
   const int t = threadIdx.x;
   if (t < k) s_y[t] = c->y[t];
   __syncthreads();
@@ -507,19 +505,21 @@ static hipError_t launch_step(const KArgs& ka, int nb, double* V, size_t ldv, do
                               hipStream_t s) {
   const int jm = pick_jm(j + 1);
   dim3 grid(nb), block(BS);
-  const int pc = probe_class();
-#define GSK_STEP(JMV)                                                                       \
-  if (pc == KC_GMRES_A) probe_begin(s);                                                     \
-  hipLaunchKernelGGL((k_gmres_a<JMV, R>), grid, block, 0, s, ka, V, ldv, w, j);                  \
-  if (pc == KC_GMRES_A) probe_end(s);                                                       \
-  hipLaunchKernelGGL(k_gmres_fin_a, dim3(j + 2), block, 0, s, ka.ctl, ka.partials, nb, j);  \
-  if (pc == KC_GMRES_B) probe_begin(s);                                                     \
-  hipLaunchKernelGGL((k_gmres_b<JMV, R>), grid, block, 0, s, ka, V, ldv, w, j);                  \
-  if (pc == KC_GMRES_B) probe_end(s);                                                       \
-  hipLaunchKernelGGL(k_gmres_fin_b, dim3(j + 1), block, 0, s, ka.ctl, ka.partials, nb, j);  \
-  if (pc == KC_GMRES_C) probe_begin(s);                                                     \
-  hipLaunchKernelGGL((k_gmres_c<JMV, R>), grid, block, 0, s, ka, V, ldv, w, j);                  \
-  if (pc == KC_GMRES_C) probe_end(s);                                                       \
+  KArgs kx = ka;
+#define GSK_TIMED(CLS, LAUNCH)           \
+  kx.pslot = probe_slot(CLS);            \
+  if (kx.pslot >= 0) probe_begin(s);     \
+  LAUNCH;                                \
+  if (kx.pslot >= 0) probe_end(s, kx.pslot);
+#define GSK_STEP(JMV)                                                                          \
+  GSK_TIMED(KC_GMRES_A,                                                                        \
+            hipLaunchKernelGGL((k_gmres_a<JMV, R>), grid, block, 0, s, kx, V, ldv, w, j))      \
+  hipLaunchKernelGGL(k_gmres_fin_a, dim3(j + 2), block, 0, s, ka.ctl, ka.partials, nb, j);     \
+  GSK_TIMED(KC_GMRES_B,                                                                        \
+            hipLaunchKernelGGL((k_gmres_b<JMV, R>), grid, block, 0, s, kx, V, ldv, w, j))      \
+  hipLaunchKernelGGL(k_gmres_fin_b, dim3(j + 1), block, 0, s, ka.ctl, ka.partials, nb, j);     \
+  GSK_TIMED(KC_GMRES_C,                                                                        \
+            hipLaunchKernelGGL((k_gmres_c<JMV, R>), grid, block, 0, s, kx, V, ldv, w, j))      \
   hipLaunchKernelGGL(k_gmres_fin_c, dim3(1), block, 0, s, ka.ctl, ka.partials, nb, j);
   switch (jm) {
     case 8: GSK_STEP(8) break;
@@ -528,15 +528,17 @@ static hipError_t launch_step(const KArgs& ka, int nb, double* V, size_t ldv, do
     default: GSK_STEP(64) break;
   }
 #undef GSK_STEP
+#undef GSK_TIMED
   return hipGetLastError();
 }
 
 static void launch_residual(const KArgs& ka, int nb, const double* b, const double* x,
                             const double* W, double* u0, const int* flags, hipStream_t s) {
-  const bool pr = probe_class() == KC_RESIDUAL;
-  if (pr) probe_begin(s);
-  hipLaunchKernelGGL(k_gmres_residual, dim3(nb), dim3(BS), 0, s, ka, b, x, W, u0, flags);
-  if (pr) probe_end(s);
+  KArgs kx = ka;
+  kx.pslot = probe_slot(KC_RESIDUAL);
+  if (kx.pslot >= 0) probe_begin(s);
+  hipLaunchKernelGGL(k_gmres_residual, dim3(nb), dim3(BS), 0, s, kx, b, x, W, u0, flags);
+  if (kx.pslot >= 0) probe_end(s, kx.pslot);
   hipLaunchKernelGGL(k_gmres_fin_residual, dim3(1), dim3(BS), 0, s, ka.ctl,
                      (const double*)ka.partials, nb, W ? 1 : 0, flags);
 }
@@ -556,12 +558,13 @@ static SolveResult gmres_run(const Csr& A, const double* b, double* x, int m,
   const size_t ldv = vec_ld(A.n);
   double* V = W.vecs;
   double* w = V + (size_t)(m + 1) * ldv;
-  KArgs ka{A.rp, A.ci, A.val, A.n, g.rpb, W.ctl, W.partials, csr_bytes(A)};
+  KArgs ka{A.rp, A.ci, A.val, A.n, g.rpb, W.ctl, W.partials, csr_bytes(A), -1};
   dim3 grid(g.nb), block(BS);
   if (launch_clear_flags(W.flags, s) != hipSuccess) return fail(-5);
   if (launch_validate(A, W.flags, s) != hipSuccess) return fail(-5);
   hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, s, W.ctl, prm.maxit, m, prm.tol, prm.eps_b,
                      prm.weights ? 1 : 0);
+  probe_solve_begin();
   launch_residual(ka, g.nb, b, x, prm.weights, V, W.flags, s);
   if (hipGetLastError() != hipSuccess) return fail(-5);
 
@@ -582,9 +585,11 @@ static SolveResult gmres_run(const Csr& A, const double* b, double* x, int m,
     for (int j = 0; j < m; ++j)
       if (launch_step<R>(ka, g.nb, V, ldv, w, j, s) != hipSuccess) { res.code = -5; break; }
     if (res.code) break;
-    if (probe_class() == KC_GMRES_X) probe_begin(s);
-    hipLaunchKernelGGL(k_gmres_x<R>, grid, block, 0, s, ka, (const double*)V, ldv, x);
-    if (probe_class() == KC_GMRES_X) probe_end(s);
+    KArgs kx = ka;
+    kx.pslot = probe_slot(KC_GMRES_X);
+    if (kx.pslot >= 0) probe_begin(s);
+    hipLaunchKernelGGL(k_gmres_x<R>, grid, block, 0, s, kx, (const double*)V, ldv, x);
+    if (kx.pslot >= 0) probe_end(s, kx.pslot);
     launch_residual(ka, g.nb, b, x, prm.weights, V, W.flags, s);
     if (hipGetLastError() != hipSuccess ||
         hipMemcpyAsync(&hs[slot], &W.ctl->sum, sizeof(Summary), hipMemcpyDeviceToHost, s) !=
@@ -602,7 +607,7 @@ static SolveResult gmres_run(const Csr& A, const double* b, double* x, int m,
     slot ^= 1;
   }
   if (hipStreamSynchronize(s) != hipSuccess && res.code == 0) res.code = -5;
-  if (res.code == 0 && probe_class() != KC_NONE) probe_collect(&W.ctl->work, s);
+  if (res.code == 0) probe_collect(&W.ctl->probe, s);
   if (res.code == 0) {
     res.sum = hs[slot ^ 1];   // the most recent copy (state no longer changes once done)
     if (res.sum.state != ST_DONE) res.code = -5;
@@ -619,12 +624,13 @@ static SolveResult arnoldi_impl(const Csr& A, const double* r0, int m, double* V
   Workspace W = carve(ws, A.n);
   const Geom g = make_geom(A.n);
   double* w = W.vecs;
-  KArgs ka{A.rp, A.ci, A.val, A.n, g.rpb, W.ctl, W.partials, csr_bytes(A)};
+  KArgs ka{A.rp, A.ci, A.val, A.n, g.rpb, W.ctl, W.partials, csr_bytes(A), -1};
   dim3 grid(g.nb), block(BS);
   if (launch_clear_flags(W.flags, s) != hipSuccess) return fail(-5);
   if (launch_validate(A, W.flags, s) != hipSuccess) return fail(-5);
   // tol < 0: the estimate never ends the cycle; maxit = m steps.
   hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, s, W.ctl, m, m, -1.0, eps_b, 0);
+  probe_solve_begin();
   hipLaunchKernelGGL(k_arnoldi_start, grid, block, 0, s, ka, r0, V, (const int*)W.flags);
   hipLaunchKernelGGL(k_arnoldi_fin_start, dim3(1), block, 0, s, W.ctl,
                      (const double*)W.partials, g.nb, (const int*)W.flags);
@@ -640,6 +646,7 @@ static SolveResult arnoldi_impl(const Csr& A, const double* r0, int m, double* V
           hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return fail(-5);
+  probe_collect(&W.ctl->probe, s);
   SolveResult res;
   res.code = 0;
   res.sum = hs[0];

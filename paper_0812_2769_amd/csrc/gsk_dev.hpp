@@ -48,13 +48,12 @@ enum : int {
   KC_BICG_U = 6, KC_RESIDUAL = 7, KC_GMRES_X = 8, KC_COUNT = 9
 };
 
-// Per-class work counters: launches that did work, and their algorithmic bytes. Written by
-// thread 0 of workgroup 0 of each working launch (one writer per launch, launches serialised
-// on the stream).
-struct Work {
-  double bytes[KC_COUNT];
-  int busy[KC_COUNT];
-  int pad[16 - KC_COUNT % 16];
+// Measurement slots: a launch that the host chose to time carries a slot number; if it does
+// work (rather than returning at once because the solve has moved on), thread 0 of workgroup 0
+// stores its algorithmic bytes there. Zeroed by the init kernel.
+constexpr int PROBE_SLOTS = 2048;
+struct ProbeSlots {
+  double bytes[PROBE_SLOTS];
 };
 
 // Host-visible summary copied back after each cycle / chunk.
@@ -67,7 +66,7 @@ struct Summary {
 // (its first fields are set by an init kernel, never by a memset).
 struct Ctl {
   Summary sum;
-  Work work;
+  ProbeSlots probe;
   int maxit, m, j, k, claimed, first, parity, has_w;
   int broke, happy, pad0, pad1;
   double tol, eps_b, ref, ratio;
@@ -83,11 +82,8 @@ struct Ctl {
   double cs[MMAX], sn[MMAX], g[MMAX + 1], y[MMAX];
 };
 
-__device__ inline void count_work(Ctl* c, int cls, double bytes) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    c->work.busy[cls] += 1;
-    c->work.bytes[cls] += bytes;
-  }
+__device__ inline void mark_work(Ctl* c, int slot, double bytes) {
+  if (slot >= 0 && blockIdx.x == 0 && threadIdx.x == 0) c->probe.bytes[slot] = bytes;
 }
 
 struct Geom {

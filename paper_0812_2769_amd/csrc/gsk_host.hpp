@@ -82,12 +82,14 @@ Summary* pinned_summaries();
 
 inline double csr_bytes(const Csr& A) { return 12.0 * (double)A.nnz + 4.0 * ((double)A.n + 1); }
 
-// Measurement hook (gsk_probe_begin / gsk_probe_end): while a kernel class is selected, every
-// launch of that class is bracketed by a pair of HIP events on its stream, and at the end of
-// each solve the device work counters of that class are added to the running totals.
-int probe_class();
+// Measurement hook (gsk_probe_begin / gsk_probe_end). While a kernel class is selected, every
+// sample_every-th launch of that class gets a slot number: the host brackets it with a pair
+// of HIP events and the kernel records its algorithmic bytes in the slot if it did work. At
+// the end of each solve the working launches' durations and bytes are added to the totals.
+void probe_solve_begin();                  // a new solve starts: slots restart at 0
+int probe_slot(int kernel_class);          // -1 if this launch is not timed
 void probe_begin(hipStream_t s);
-void probe_end(hipStream_t s);
-void probe_collect(const Work* device_work, hipStream_t s);
+void probe_end(hipStream_t s, int slot);
+void probe_collect(const ProbeSlots* device_slots, hipStream_t s);
 
 }  // namespace gsk

@@ -83,7 +83,7 @@ def _load() -> ctypes.CDLL:
     lib.gsk_bicgstab.argtypes = [P(Csr), vp, vp, ctypes.c_double, P(Options), P(InfoStruct), vp,
                                  sz, vp]
     lib.gsk_bicgstab.restype = ctypes.c_int
-    lib.gsk_probe_begin.argtypes = [ctypes.c_int32]
+    lib.gsk_probe_begin.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.gsk_probe_begin.restype = ctypes.c_int
     lib.gsk_probe_end.argtypes = [P(ProbeResult)]
     lib.gsk_probe_end.restype = ctypes.c_int
@@ -294,9 +294,9 @@ def bicgstab(A: CsrMatrix, b: torch.Tensor, x0: Optional[torch.Tensor] = None,
     return x, _info(info)
 
 
-def probe_begin(kernel_class: str) -> None:
-    """Start timing every launch of one kernel class (see gsk_probe_begin in gsk.h)."""
-    _check(lib.gsk_probe_begin(KCLASS[kernel_class]))
+def probe_begin(kernel_class: str, sample_every: int = 1) -> None:
+    """Start timing every sample_every-th launch of one kernel class (gsk_probe_begin)."""
+    _check(lib.gsk_probe_begin(KCLASS[kernel_class], int(sample_every)))
 
 
 def probe_end() -> dict:
