@@ -5,10 +5,11 @@ grid, 7-point central differences in flux form, diffusion piecewise constant ove
 with values 10^U(0,6) (numpy default_rng(1002)), convection (20,-10,5), b = A u* with
 u* = sin(pi x) sin(pi y) sin(pi z); n = 512,000, nnz = 3,545,600, FP64 CSR with int32 indices.
 
-One step = the workload's four solves, each from the unscaled matrix resident in HBM:
-GS(p) (out of place) then the Krylov solve from x0 = 0 to a relative residual below 1e-10
-(measured on the GS(2)-scaled system), for p in {2, 1} and solver in {Bi-CGSTAB, GMRES(30)}.
-`value` = solves per second over the timed steps.
+One step = the workload's four solves, each from the unscaled CSR matrix resident in HBM:
+GS(p) (out of place), with --operator stencil (the default) the packing of the scaled CSR
+matrix into 7-point coefficient planes, then the Krylov solve from x0 = 0 to a relative
+residual below 1e-10 (measured on the GS(2)-scaled system), for p in {2, 1} and solver in
+{Bi-CGSTAB, GMRES(30)}. `value` = solves per second over the timed steps.
 
 Prints one JSON line. Also reports iterations/s, per-variant p50/p99 latency, the achieved
 bandwidth of the dominant kernel against the HBM roofline, and the CPU oracle's rate on a
@@ -47,10 +48,10 @@ TRAFFIC_SOURCES = ["paper_0812_2769_amd/csrc/gmres.hip", "paper_0812_2769_amd/cs
                    "paper_0812_2769_amd/csrc/gsk_host.hpp"]
 
 
-def traffic_for(probe, grid):
+def traffic_for(probe, grid, operator):
     import hashlib
     rec = TRAFFIC.get(probe)
-    if rec is None or rec["grid"] != grid:
+    if rec is None or rec["grid"] != grid or rec.get("operator", "csr") != operator:
         return None
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
@@ -65,6 +66,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--grid", type=int, default=80, help="N of the N^3 grid (default 80)")
+    ap.add_argument("--operator", choices=["stencil", "csr"], default="stencil",
+                    help="matrix form the solvers read: 7-point coefficient planes packed from "
+                         "the scaled CSR matrix inside each solve (default), or the CSR matrix")
     ap.add_argument("--cpu-sample-iters", type=int, default=120,
                     help="iterations per solver the CPU oracle runs for its baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -166,8 +170,21 @@ def main():
     ws_bi = gsk.workspace(gsk.METHOD_BICGSTAB, n, 0, dev)
     As = A.with_values(val_s)
     c_A = A.c_struct()
+    c_As = As.c_struct()
     import ctypes
     stream = torch.cuda.current_stream(dev).cuda_stream
+    stencil = args.operator == "stencil"
+    if stencil:
+        coef = torch.empty(7 * n, dtype=torch.float64, device=dev)
+        Ss = gsk.StencilMatrix(args.grid, args.grid, args.grid, coef)
+    M = Ss if stencil else As
+
+    def pack():
+        rc = gsk.lib.gsk_stencil_from_csr(ctypes.byref(c_As), args.grid, args.grid, args.grid,
+                                          coef.data_ptr(), ws_gs.data_ptr(), ws_gs.numel(),
+                                          stream)
+        if rc != 0:
+            raise gsk.GskError(rc, gsk.lib.gsk_last_error().decode())
 
     def gs(p):
         rc = gsk.lib.gsk_gs_scale(ctypes.byref(c_A), b.data_ptr(), p, val_s.data_ptr(),
@@ -178,10 +195,12 @@ def main():
 
     def solve(p, method):
         gs(p)
+        if stencil:
+            pack()
         w = None if p == 2 else weights
         if method == "bicgstab":
-            return gsk.bicgstab(As, b_s, tol=TOL, stop_weights=w, ws=ws_bi, x_out=x)[1]
-        return gsk.gmres(As, b_s, m=30, tol=TOL, stop_weights=w, ws=ws_gm, x_out=x)[1]
+            return gsk.bicgstab(M, b_s, tol=TOL, stop_weights=w, ws=ws_bi, x_out=x)[1]
+        return gsk.gmres(M, b_s, m=30, tol=TOL, stop_weights=w, ws=ws_gm, x_out=x)[1]
 
     def step(lat, infos):
         for p, method in VARIANTS:
@@ -247,7 +266,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"config2: {args.grid}^3 7-point convection-diffusion, 8 random "
                                f"slabs, FP64 CSR; GS(1|2) x (Bi-CGSTAB | GMRES(30)), tol 1e-10",
-                   "n": n, "nnz": P.nnz, "solves_per_step": len(VARIANTS), "tol": TOL},
+                   "n": n, "nnz": P.nnz, "solves_per_step": len(VARIANTS), "tol": TOL,
+                   "operator": args.operator},
         "iterations_per_s": round(iters_step * args.steps / elapsed, 1),
         "latency_p50_ms": round(1e3 * pct(all_lat, 0.5), 3),
         "latency_p99_ms": round(1e3 * pct(all_lat, 0.99), 3),
@@ -261,7 +281,7 @@ def main():
         out["roofline"] = {
             "bound": "hbm", "achieved": a["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(a["achieved_GBs"] / HBM_PEAK_GBS, 4),
-            "traffic": traffic_for(args.probe, args.grid),
+            "traffic": traffic_for(args.probe, args.grid, args.operator),
             "kernel": KERNEL_NAMES.get(args.probe), "avg_launch_us": a["avg_launch_us"],
             "bytes_per_launch": a["bytes_per_launch"], "timed_launches": a["timed_launches"],
             "busy_launches": a["busy_launches"], "sample_every": args.probe_every,

@@ -19,8 +19,9 @@
  *  - The return value is GSK_OK (0) or a negative GSK_ERR_* code; gsk_last_error() then
  *    gives a message (thread-local, valid until the next call from the same thread).
  *    Non-convergence of a solver is not an error: it is reported in gsk_info.status.
- *  - Matrices are CSR with int32 row pointers and column indices (0-based, columns sorted
- *    ascending within each row, no duplicates) and FP64 values.
+ *  - CSR matrices have int32 row pointers and column indices (0-based, columns sorted
+ *    ascending within each row, no duplicates) and FP64 values. The solvers and gsk_spmv also
+ *    take structured stencil matrices (gsk_matrix, gsk_stencil).
  *  - Nothing is thrown across the ABI.
  */
 #ifndef GSK_H
@@ -73,6 +74,28 @@ typedef struct gsk_csr {
     const int32_t* col_idx;  /* device [nnz], each in [0, n)                          */
     const double* val;       /* device [nnz]                                          */
 } gsk_csr;
+
+/* A matrix as the solvers and gsk_spmv take it. */
+#define GSK_MATRIX_CSR 0
+#define GSK_MATRIX_STENCIL 1
+
+/* Structured 5-point (nz = 1) or 7-point stencil matrix on an nx x ny x nz grid (x fastest:
+ * row i = ix + nx (iy + ny iz), n = nx ny nz; nx, ny >= 2, nz >= 1). coef holds one plane of
+ * n FP64 values per stencil position, in the CSR column order -z, -y, -x, centre, +x, +y, +z
+ * (7 planes; 5 planes -y, -x, centre, +x, +y when nz = 1): coef[q*n + i] multiplies the q-th
+ * neighbour of row i. Neighbours outside the grid are skipped (their plane entries are never
+ * read). This is the layout of the paper's 5/7-point central-difference matrices (section
+ * 2.1); gsk_stencil_from_csr builds it from a CSR matrix. */
+typedef struct gsk_stencil {
+    int32_t nx, ny, nz;
+    const double* coef;      /* device [7 n] (3D) or [5 n] (2D)                       */
+} gsk_stencil;
+
+typedef struct gsk_matrix {
+    int32_t kind;            /* GSK_MATRIX_CSR or GSK_MATRIX_STENCIL                  */
+    gsk_csr csr;             /* used when kind == GSK_MATRIX_CSR                      */
+    gsk_stencil stencil;     /* used when kind == GSK_MATRIX_STENCIL                  */
+} gsk_matrix;
 
 typedef struct gsk_options {
     int32_t maxit;              /* iteration cap (GMRES: Arnoldi steps; Bi-CGSTAB:
@@ -134,12 +157,25 @@ int gsk_gs_scale(const gsk_csr* A, const double* b, int32_t p, double* val_out, 
                  void* stream);
 
 /*
- * y = A x, FP64. Each row is summed in storage order with every product rounded before it
- * is added (so the result equals a sequential CPU loop without fused multiply-add).
- * x and y must not overlap. Asynchronous: enqueued on `stream`, no synchronisation.
- * This is the sparse product inside every Krylov step of section 2's solvers.
+ * y = A x, FP64. Each row is summed in storage order (CSR) or in the CSR column order of the
+ * stencil positions (stencil), with every product rounded before it is added, so the result
+ * equals a sequential CPU loop without fused multiply-add, and a stencil matrix gives the same
+ * bits as the CSR matrix it was packed from. x and y must not overlap. Asynchronous: enqueued
+ * on `stream`, no synchronisation. This is the sparse product inside every Krylov step of
+ * section 2's solvers.
  */
-int gsk_spmv(const gsk_csr* A, const double* x, double* y, void* stream);
+int gsk_spmv(const gsk_matrix* A, const double* x, double* y, void* stream);
+
+/*
+ * Packs a CSR matrix whose pattern is a subset of the 5-point (nz = 1) or 7-point stencil of
+ * an nx x ny x nz grid into coefficient planes (gsk_stencil layout). Positions a row does not
+ * store get 0. A->n must equal nx ny nz. coef: device [7 n] or [5 n], written.
+ * ws, ws_bytes: workspace of gsk_workspace_bytes(GSK_METHOD_GS, n, 0) bytes.
+ * Errors: GSK_ERR_INVALID_ARG for bad dimensions, an invalid CSR structure, or an entry that is
+ * not a stencil position of its row (or repeats one). Synchronises `stream`.
+ */
+int gsk_stencil_from_csr(const gsk_csr* A, int32_t nx, int32_t ny, int32_t nz, double* coef,
+                         void* ws, size_t ws_bytes, void* stream);
 
 /*
  * m steps of Arnoldi with double classical Gram-Schmidt (section 2: AZTEC's GMRES
@@ -155,7 +191,7 @@ int gsk_spmv(const gsk_csr* A, const double* x, double* y, void* stream);
  *   ws, ws_bytes : workspace of gsk_workspace_bytes(GSK_METHOD_ARNOLDI, n, m) bytes.
  * 1 <= m <= GSK_MAX_RESTART. Synchronises `stream`.
  */
-int gsk_arnoldi(const gsk_csr* A, const double* r0, int32_t m, double* V, int64_t ldv,
+int gsk_arnoldi(const gsk_matrix* A, const double* r0, int32_t m, double* V, int64_t ldv,
                 double* H, int32_t* steps, void* ws, size_t ws_bytes, void* stream);
 
 /*
@@ -173,7 +209,7 @@ int gsk_arnoldi(const gsk_csr* A, const double* r0, int32_t m, double* V, int64_
  * residual estimate stay on the device; the host reads a small status block once per cycle.
  * Synchronises `stream`.
  */
-int gsk_gmres(const gsk_csr* A, const double* b, double* x, int32_t m, double tol,
+int gsk_gmres(const gsk_matrix* A, const double* b, double* x, int32_t m, double tol,
               const gsk_options* opt, gsk_info* info, void* ws, size_t ws_bytes, void* stream);
 
 /*
@@ -182,7 +218,7 @@ int gsk_gmres(const gsk_csr* A, const double* b, double* x, int32_t m, double to
  * n, 0). All scalars (rho, alpha, omega, beta) stay on the device; the host reads a status
  * block every opt->check_every iterations. Synchronises `stream`.
  */
-int gsk_bicgstab(const gsk_csr* A, const double* b, double* x, double tol,
+int gsk_bicgstab(const gsk_matrix* A, const double* b, double* x, double tol,
                  const gsk_options* opt, gsk_info* info, void* ws, size_t ws_bytes,
                  void* stream);
 
@@ -205,6 +241,8 @@ int gsk_bicgstab(const gsk_csr* A, const double* b, double* x, double tol,
  *                                            24 n after a half-step exit)
  *   RESIDUAL  12 nnz + 4 (n+1) + 24..40 n    CSR, x b, write r (and r^ in Bi-CGSTAB), weights
  *   GMRES_X   8 n (k+2)                      k basis columns, read and write x
+ * For a stencil matrix the matrix term 12 nnz + 4 (n+1) becomes 8 n per coefficient plane
+ * (40 n for 5 points, 56 n for 7).
  * Process-wide; not for concurrent use from several host threads. gsk_probe_end
  * synchronises the device.
  */

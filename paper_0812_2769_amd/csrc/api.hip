@@ -74,6 +74,36 @@ Csr to_csr(const gsk_csr* A) {
   return Csr{A->n, A->nnz, A->row_ptr, A->col_idx, A->val};
 }
 
+int check_matrix(const gsk_matrix* A, Mat& out) {
+  if (!A) return set_err(GSK_ERR_INVALID_ARG, "matrix is NULL");
+  out = Mat{};
+  if (A->kind == GSK_MATRIX_CSR) {
+    int rc = check_csr(&A->csr);
+    if (rc) return rc;
+    out.kind = MAT_CSR;
+    out.n = A->csr.n;
+    out.csr = to_csr(&A->csr);
+    return GSK_OK;
+  }
+  if (A->kind == GSK_MATRIX_STENCIL) {
+    const gsk_stencil& S = A->stencil;
+    if (S.nx < 2 || S.ny < 2 || S.nz < 1)
+      return set_err(GSK_ERR_INVALID_ARG, "stencil grid %d x %d x %d: need nx, ny >= 2, nz >= 1",
+                     (int)S.nx, (int)S.ny, (int)S.nz);
+    const int64_t n = (int64_t)S.nx * S.ny * S.nz;
+    if (n > INT32_MAX) return set_err(GSK_ERR_INVALID_ARG, "stencil grid too large");
+    if (!S.coef) return set_err(GSK_ERR_INVALID_ARG, "stencil coef is NULL");
+    out.kind = MAT_STENCIL;
+    out.n = (int)n;
+    out.nx = S.nx;
+    out.ny = S.ny;
+    out.nz = S.nz;
+    out.coef = S.coef;
+    return GSK_OK;
+  }
+  return set_err(GSK_ERR_INVALID_ARG, "unknown matrix kind %d", (int)A->kind);
+}
+
 int params_from(const gsk_options* opt, SolveParams& prm, double tol) {
   gsk_options o;
   gsk_default_options(&o);
@@ -342,28 +372,65 @@ int gsk_gs_scale(const gsk_csr* A, const double* b, int32_t p, double* val_out, 
   return GSK_OK;
 }
 
-int gsk_spmv(const gsk_csr* A, const double* x, double* y, void* stream) {
+int gsk_spmv(const gsk_matrix* A, const double* x, double* y, void* stream) {
   g_err.clear();
-  int rc = check_csr(A);
+  Mat M;
+  int rc = check_matrix(A, M);
   if (rc) return rc;
   if (!x || !y) return set_err(GSK_ERR_INVALID_ARG, "x or y is NULL");
-  hipError_t e = launch_spmv(to_csr(A), x, y, static_cast<hipStream_t>(stream));
+  hipError_t e = launch_spmv(M, x, y, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_err(e, "spmv launch");
   return GSK_OK;
 }
 
-int gsk_arnoldi(const gsk_csr* A, const double* r0, int32_t m, double* V, int64_t ldv, double* H,
-                int32_t* steps, void* ws, size_t ws_bytes, void* stream) {
+int gsk_stencil_from_csr(const gsk_csr* A, int32_t nx, int32_t ny, int32_t nz, double* coef,
+                         void* ws, size_t ws_bytes, void* stream) {
   g_err.clear();
   int rc = check_csr(A);
+  if (rc) return rc;
+  if (nx < 2 || ny < 2 || nz < 1 || (int64_t)nx * ny * nz != (int64_t)A->n)
+    return set_err(GSK_ERR_INVALID_ARG, "grid %d x %d x %d does not match n = %d (need nx, ny "
+                   ">= 2, nz >= 1)", (int)nx, (int)ny, (int)nz, (int)A->n);
+  if (!coef) return set_err(GSK_ERR_INVALID_ARG, "coef is NULL");
+  rc = check_ws(ws, ws_bytes, gsk::workspace_bytes(GSK_METHOD_GS, A->n, 0));
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace W = carve(ws, A->n);
+  Csr C = to_csr(A);
+  hipError_t e;
+  if ((e = launch_clear_flags(W.flags, s)) != hipSuccess) return hip_err(e, "clear flags");
+  if ((e = launch_validate(C, W.flags, s)) != hipSuccess) return hip_err(e, "validate");
+  if ((e = launch_stencil_from_csr(C, nx, ny, nz, coef, W.flags, s)) != hipSuccess)
+    return hip_err(e, "stencil_from_csr launch");
+  Pinned* pin = pinned();
+  if (!pin) return set_err(GSK_ERR_DEVICE, "pinned host buffer allocation failed");
+  if ((e = hipMemcpyAsync(pin->flags, W.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s)) !=
+      hipSuccess)
+    return hip_err(e, "flag read-back");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_err(e, "stencil_from_csr");
+  if (pin->flags[0])
+    return set_err(GSK_ERR_INVALID_ARG,
+                   "CSR structure invalid (row_ptr not monotone from 0 to nnz, or a column "
+                   "index outside [0, n))");
+  if (pin->flags[3])
+    return set_err(GSK_ERR_INVALID_ARG,
+                   "an entry is not a 5/7-point stencil position of its row, or repeats one");
+  return GSK_OK;
+}
+
+int gsk_arnoldi(const gsk_matrix* A, const double* r0, int32_t m, double* V, int64_t ldv,
+                double* H, int32_t* steps, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  Mat M;
+  int rc = check_matrix(A, M);
   if (rc) return rc;
   if (m < 1 || m > GSK_MAX_RESTART)
     return set_err(GSK_ERR_INVALID_ARG, "m = %d must be in [1, %d]", (int)m, GSK_MAX_RESTART);
   if (!r0 || !V || !H || !steps) return set_err(GSK_ERR_INVALID_ARG, "NULL argument");
-  if (ldv < A->n) return set_err(GSK_ERR_INVALID_ARG, "ldv < n");
-  rc = check_ws(ws, ws_bytes, gsk::workspace_bytes(GSK_METHOD_ARNOLDI, A->n, m));
+  if (ldv < M.n) return set_err(GSK_ERR_INVALID_ARG, "ldv < n");
+  rc = check_ws(ws, ws_bytes, gsk::workspace_bytes(GSK_METHOD_ARNOLDI, M.n, m));
   if (rc) return rc;
-  SolveResult r = arnoldi_run(to_csr(A), r0, m, V, ldv, H, ws, 1e-16 * DBL_EPSILON,
+  SolveResult r = arnoldi_run(M, r0, m, V, ldv, H, ws, 1e-16 * DBL_EPSILON,
                               static_cast<hipStream_t>(stream));
   if (r.code == -1)
     return set_err(GSK_ERR_INVALID_ARG, "invalid CSR structure or zero/non-finite r0");
@@ -373,11 +440,12 @@ int gsk_arnoldi(const gsk_csr* A, const double* r0, int32_t m, double* V, int64_
   return GSK_OK;
 }
 
-static int solve_common(bool is_gmres, const gsk_csr* A, const double* b, double* x, int32_t m,
-                        double tol, const gsk_options* opt, gsk_info* info, void* ws,
+static int solve_common(bool is_gmres, const gsk_matrix* A, const double* b, double* x,
+                        int32_t m, double tol, const gsk_options* opt, gsk_info* info, void* ws,
                         size_t ws_bytes, void* stream) {
   g_err.clear();
-  int rc = check_csr(A);
+  Mat M;
+  int rc = check_matrix(A, M);
   if (rc) return rc;
   if (!b || !x) return set_err(GSK_ERR_INVALID_ARG, "b or x is NULL");
   if (is_gmres && (m < 1 || m > GSK_MAX_RESTART))
@@ -386,11 +454,11 @@ static int solve_common(bool is_gmres, const gsk_csr* A, const double* b, double
   rc = params_from(opt, prm, tol);
   if (rc) return rc;
   rc = check_ws(ws, ws_bytes,
-                gsk::workspace_bytes(is_gmres ? GSK_METHOD_GMRES : GSK_METHOD_BICGSTAB, A->n, m));
+                gsk::workspace_bytes(is_gmres ? GSK_METHOD_GMRES : GSK_METHOD_BICGSTAB, M.n, m));
   if (rc) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  SolveResult r = is_gmres ? gmres_solve(to_csr(A), b, x, m, prm, ws, s)
-                           : bicgstab_solve(to_csr(A), b, x, prm, ws, s);
+  SolveResult r = is_gmres ? gmres_solve(M, b, x, m, prm, ws, s)
+                           : bicgstab_solve(M, b, x, prm, ws, s);
   if (r.code == -1)
     return set_err(GSK_ERR_INVALID_ARG,
                    "CSR structure invalid (row_ptr not monotone from 0 to nnz, or a column "
@@ -401,12 +469,12 @@ static int solve_common(bool is_gmres, const gsk_csr* A, const double* b, double
   return GSK_OK;
 }
 
-int gsk_gmres(const gsk_csr* A, const double* b, double* x, int32_t m, double tol,
+int gsk_gmres(const gsk_matrix* A, const double* b, double* x, int32_t m, double tol,
               const gsk_options* opt, gsk_info* info, void* ws, size_t ws_bytes, void* stream) {
   return solve_common(true, A, b, x, m, tol, opt, info, ws, ws_bytes, stream);
 }
 
-int gsk_bicgstab(const gsk_csr* A, const double* b, double* x, double tol,
+int gsk_bicgstab(const gsk_matrix* A, const double* b, double* x, double tol,
                  const gsk_options* opt, gsk_info* info, void* ws, size_t ws_bytes,
                  void* stream) {
   return solve_common(false, A, b, x, 0, tol, opt, info, ws, ws_bytes, stream);

@@ -21,9 +21,6 @@
 namespace gsk {
 
 struct BArgs {
-  const int* rp;
-  const int* ci;
-  const double* val;
   int n;
   int rpb;
   Ctl* ctl;
@@ -36,7 +33,7 @@ struct BArgs {
   double* x;
   const double* b;
   const double* W;
-  double csr_bytes;   // 12 nnz + 4 (n+1)
+  double mat_bytes;   // algorithmic bytes of one read of A
   int pslot;          // measurement slot of this launch, or -1
 };
 
@@ -76,13 +73,14 @@ __global__ __launch_bounds__(64) void k_bicg_init_ctl(Ctl* c, int maxit, double 
 
 // R: r = b - A x, r^ = r (initial residual, verification, or final residual after a
 // breakdown); partials ||r||^2, ||W r||^2.
-__global__ __launch_bounds__(BS) void k_bicg_residual(BArgs a, const int* flags) {
+template <class Op>
+__global__ __launch_bounds__(BS) void k_bicg_residual(BArgs a, Op op, const int* flags) {
   Ctl* c = a.ctl;
   const int st = c->sum.state;
   if (st != ST_INIT && st != ST_VERIFY && st != ST_FINAL) return;
   if (flags[0]) return;
-  mark_work(c, a.pslot, a.csr_bytes + 8.0 * a.n * ((st != ST_FINAL ? 4 : 2) + (a.W ? 1 : 0)));
-  __shared__ TileLds L;
+  mark_work(c, a.pslot, a.mat_bytes + 8.0 * a.n * ((st != ST_FINAL ? 4 : 2) + (a.W ? 1 : 0)));
+  __shared__ typename Op::Lds L;
   __shared__ double red[NC_MAX * WAVES];
   const int nb = gridDim.x;
   const int lb = logical_block();
@@ -91,7 +89,7 @@ __global__ __launch_bounds__(BS) void k_bicg_residual(BArgs a, const int* flags)
   double acc[2] = {0.0, 0.0};
   for (int row0 = rb; row0 < re; row0 += BS) {
     const int nrows = min(BS, re - row0);
-    const double y = csr_tile(a.rp, a.ci, a.val, row0, nrows, GatherX{a.x}, L);
+    const double y = op.tile(row0, nrows, GatherX{a.x}, L);
     if ((int)threadIdx.x < nrows) {
       const int row = row0 + threadIdx.x;
       const double r = a.b[row] - y;
@@ -200,17 +198,18 @@ struct GatherS {
 };
 
 // P: new p, v = A p; partials (r^, v), ||v||^2.
-__global__ __launch_bounds__(BS) void k_bicg_p(BArgs a) {
+template <class Op>
+__global__ __launch_bounds__(BS) void k_bicg_p(BArgs a, Op op) {
   Ctl* c = a.ctl;
   if (c->sum.state != ST_RUNNING) return;
-  mark_work(c, a.pslot, a.csr_bytes + 8.0 * a.n * (c->first ? 4 : 6));
+  mark_work(c, a.pslot, a.mat_bytes + 8.0 * a.n * (c->first ? 4 : 6));
   const int q = c->parity;
   const double* pin = a.p[q];
   const double* vin = a.v[q];
   double* pout = a.p[q ^ 1];
   double* vout = a.v[q ^ 1];
   const GatherP G{a.r, pin, vin, c->beta, c->omega, c->first};
-  __shared__ TileLds L;
+  __shared__ typename Op::Lds L;
   __shared__ double red[NC_MAX * WAVES];
   const int nb = gridDim.x;
   const int lb = logical_block();
@@ -219,7 +218,7 @@ __global__ __launch_bounds__(BS) void k_bicg_p(BArgs a) {
   double acc[2] = {0.0, 0.0};
   for (int row0 = rb; row0 < re; row0 += BS) {
     const int nrows = min(BS, re - row0);
-    const double y = csr_tile(a.rp, a.ci, a.val, row0, nrows, G, L);
+    const double y = op.tile(row0, nrows, G, L);
     if ((int)threadIdx.x < nrows) {
       const int row = row0 + threadIdx.x;
       pout[row] = G(row);
@@ -249,13 +248,14 @@ __global__ __launch_bounds__(BS) void k_bicg_fin_p(Ctl* c, const double* partial
 }
 
 // S: t = A s with s = r - alpha v; partials (t,s), (t,t), ||s||^2, ||W s||^2.
-__global__ __launch_bounds__(BS) void k_bicg_s(BArgs a) {
+template <class Op>
+__global__ __launch_bounds__(BS) void k_bicg_s(BArgs a, Op op) {
   Ctl* c = a.ctl;
   if (c->sum.state != ST_RUNNING) return;
-  mark_work(c, a.pslot, a.csr_bytes + 8.0 * a.n * (a.W ? 4 : 3));
+  mark_work(c, a.pslot, a.mat_bytes + 8.0 * a.n * (a.W ? 4 : 3));
   const int q = c->parity ^ 1;   // the v written by P in this iteration
   const GatherS G{a.r, a.v[q], c->alpha};
-  __shared__ TileLds L;
+  __shared__ typename Op::Lds L;
   __shared__ double red[NC_MAX * WAVES];
   const int nb = gridDim.x;
   const int lb = logical_block();
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(BS) void k_bicg_s(BArgs a) {
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int row0 = rb; row0 < re; row0 += BS) {
     const int nrows = min(BS, re - row0);
-    const double y = csr_tile(a.rp, a.ci, a.val, row0, nrows, G, L);
+    const double y = op.tile(row0, nrows, G, L);
     if ((int)threadIdx.x < nrows) {
       const int row = row0 + threadIdx.x;
       const double s = G(row);
@@ -376,28 +376,31 @@ __global__ __launch_bounds__(BS) void k_bicg_fin_u(Ctl* c, const double* partial
   c->parity ^= 1;
 }
 
-static void launch_residual(const BArgs& a, int nb, const int* flags, hipStream_t s) {
+template <class Op>
+static void launch_residual(const BArgs& a, const Op& op, int nb, const int* flags,
+                            hipStream_t s) {
   BArgs ax = a;
   ax.pslot = probe_slot(KC_RESIDUAL);
   if (ax.pslot >= 0) probe_begin(s);
-  hipLaunchKernelGGL(k_bicg_residual, dim3(nb), dim3(BS), 0, s, ax, flags);
+  hipLaunchKernelGGL(k_bicg_residual<Op>, dim3(nb), dim3(BS), 0, s, ax, op, flags);
   if (ax.pslot >= 0) probe_end(s, ax.pslot);
   hipLaunchKernelGGL(k_bicg_fin_residual, dim3(1), dim3(BS), 0, s, a.ctl,
                      (const double*)a.partials, nb, a.W ? 1 : 0, flags);
 }
 
-static void launch_iteration(const BArgs& a, int nb, hipStream_t s) {
+template <class Op>
+static void launch_iteration(const BArgs& a, const Op& op, int nb, hipStream_t s) {
   const int hw = a.W ? 1 : 0;
   const double* pt = a.partials;
   BArgs ax = a;
   ax.pslot = probe_slot(KC_BICG_P);
   if (ax.pslot >= 0) probe_begin(s);
-  hipLaunchKernelGGL(k_bicg_p, dim3(nb), dim3(BS), 0, s, ax);
+  hipLaunchKernelGGL(k_bicg_p<Op>, dim3(nb), dim3(BS), 0, s, ax, op);
   if (ax.pslot >= 0) probe_end(s, ax.pslot);
   hipLaunchKernelGGL(k_bicg_fin_p, dim3(1), dim3(BS), 0, s, a.ctl, pt, nb);
   ax.pslot = probe_slot(KC_BICG_S);
   if (ax.pslot >= 0) probe_begin(s);
-  hipLaunchKernelGGL(k_bicg_s, dim3(nb), dim3(BS), 0, s, ax);
+  hipLaunchKernelGGL(k_bicg_s<Op>, dim3(nb), dim3(BS), 0, s, ax, op);
   if (ax.pslot >= 0) probe_end(s, ax.pslot);
   hipLaunchKernelGGL(k_bicg_fin_s, dim3(1), dim3(BS), 0, s, a.ctl, pt, nb, hw);
   ax.pslot = probe_slot(KC_BICG_U);
@@ -414,16 +417,14 @@ static SolveResult bfail(int code) {
   return r;
 }
 
-SolveResult bicgstab_solve(const Csr& A, const double* b, double* x, const SolveParams& prm,
-                           void* ws, hipStream_t s) {
+template <class Op>
+static SolveResult bicgstab_run(const Mat& A, const Op& op, const double* b, double* x,
+                                const SolveParams& prm, void* ws, hipStream_t s) {
   Workspace Wk = carve(ws, A.n);
   const Geom g = make_geom(A.n);
   const size_t ld = vec_ld(A.n);
   double* base = Wk.vecs;
   BArgs a;
-  a.rp = A.rp;
-  a.ci = A.ci;
-  a.val = A.val;
   a.n = A.n;
   a.rpb = g.rpb;
   a.ctl = Wk.ctl;
@@ -438,14 +439,14 @@ SolveResult bicgstab_solve(const Csr& A, const double* b, double* x, const Solve
   a.x = x;
   a.b = b;
   a.W = prm.weights;
-  a.csr_bytes = csr_bytes(A);
+  a.mat_bytes = A.bytes();
   a.pslot = -1;
   if (launch_clear_flags(Wk.flags, s) != hipSuccess) return bfail(-5);
-  if (launch_validate(A, Wk.flags, s) != hipSuccess) return bfail(-5);
+  if (A.kind == MAT_CSR && launch_validate(A.csr, Wk.flags, s) != hipSuccess) return bfail(-5);
   hipLaunchKernelGGL(k_bicg_init_ctl, dim3(1), dim3(64), 0, s, Wk.ctl, prm.maxit, prm.tol,
                      prm.eps_b, prm.weights ? 1 : 0);
   probe_solve_begin();
-  launch_residual(a, g.nb, Wk.flags, s);
+  launch_residual(a, op, g.nb, Wk.flags, s);
   if (hipGetLastError() != hipSuccess) return bfail(-5);
 
   Summary* hs = pinned_summaries();
@@ -464,8 +465,8 @@ SolveResult bicgstab_solve(const Csr& A, const double* b, double* x, const Solve
   // Every chunk either advances the iteration count or finishes; bound the loop generously.
   const long max_chunks = (long)prm.maxit * 4 + 16;
   for (long ch = 0; ch <= max_chunks && !done; ++ch) {
-    for (int it = 0; it < k; ++it) launch_iteration(a, g.nb, s);
-    launch_residual(a, g.nb, Wk.flags, s);
+    for (int it = 0; it < k; ++it) launch_iteration(a, op, g.nb, s);
+    launch_residual(a, op, g.nb, Wk.flags, s);
     if (hipGetLastError() != hipSuccess ||
         hipMemcpyAsync(&hs[slot], &Wk.ctl->sum, sizeof(Summary), hipMemcpyDeviceToHost, s) !=
             hipSuccess ||
@@ -490,6 +491,12 @@ SolveResult bicgstab_solve(const Csr& A, const double* b, double* x, const Solve
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);
   return res;
+}
+
+SolveResult bicgstab_solve(const Mat& A, const double* b, double* x, const SolveParams& prm,
+                           void* ws, hipStream_t s) {
+  if (A.kind == MAT_STENCIL) return bicgstab_run(A, A.stencil_op(), b, x, prm, ws, s);
+  return bicgstab_run(A, A.csr_op(), b, x, prm, ws, s);
 }
 
 }  // namespace gsk

@@ -29,14 +29,11 @@
 namespace gsk {
 
 struct KArgs {
-  const int* rp;
-  const int* ci;
-  const double* val;
   int n;
   int rpb;
   Ctl* ctl;
   double* partials;
-  double csr_bytes;   // 12 nnz + 4 (n+1): one read of val, col_idx and row_ptr
+  double mat_bytes;   // algorithmic bytes of one read of A (CSR: 12 nnz + 4 (n+1))
   int pslot;          // measurement slot of this launch, or -1
 };
 
@@ -92,7 +89,8 @@ __device__ inline void block_single_partial(double v, double* __restrict__ parti
 }
 
 // R: r = b - A x into u_0; partials ||r||^2 (column 0), ||W r||^2 (column 1).
-__global__ __launch_bounds__(BS) void k_gmres_residual(KArgs a, const double* __restrict__ b,
+template <class Op>
+__global__ __launch_bounds__(BS) void k_gmres_residual(KArgs a, Op op, const double* __restrict__ b,
                                                        const double* __restrict__ x,
                                                        const double* __restrict__ W,
                                                        double* __restrict__ u0,
@@ -101,8 +99,8 @@ __global__ __launch_bounds__(BS) void k_gmres_residual(KArgs a, const double* __
   const int st = c->sum.state;
   if (st != ST_INIT && st != ST_CYCLE_END) return;
   if (flags[0]) return;
-  mark_work(c, a.pslot, a.csr_bytes + 8.0 * a.n * (W ? 4 : 3));
-  __shared__ TileLds L;
+  mark_work(c, a.pslot, a.mat_bytes + 8.0 * a.n * (W ? 4 : 3));
+  __shared__ typename Op::Lds L;
   __shared__ double red[NC_MAX * WAVES];
   const int nb = gridDim.x;
   const int lb = logical_block();
@@ -110,7 +108,7 @@ __global__ __launch_bounds__(BS) void k_gmres_residual(KArgs a, const double* __
   const int nrows = tile_rows(a.n, row0);
   double acc[2] = {0.0, 0.0};
   if (nrows > 0) {
-    const double y = csr_tile(a.rp, a.ci, a.val, row0, nrows, GatherX{x}, L);
+    const double y = op.tile(row0, nrows, GatherX{x}, L);
     if ((int)threadIdx.x < nrows) {
       const int row = row0 + threadIdx.x;
       const double r = b[row] - y;
@@ -202,13 +200,13 @@ __global__ __launch_bounds__(BS) void k_gmres_fin_residual(Ctl* c, const double*
 // A: w = sigma_j A u_j; partials of u_i . w (columns 0..j) and ||w||^2 (column j+1).
 // The basis values of the thread's row are loaded before the product so that their latency
 // overlaps it.
-template <int JM, class R>
-__global__ __launch_bounds__(BS) void k_gmres_a(KArgs a, const double* __restrict__ V, size_t ldv,
-                                                double* __restrict__ w, int j) {
+template <int JM, class R, class Op>
+__global__ __launch_bounds__(BS) void k_gmres_a(KArgs a, Op op, const double* __restrict__ V,
+                                                size_t ldv, double* __restrict__ w, int j) {
   Ctl* c = a.ctl;
   if (c->sum.state != ST_RUNNING || c->j != j) return;
-  mark_work(c, a.pslot, a.csr_bytes + 8.0 * a.n * (j + 2));
-  __shared__ TileLds L;
+  mark_work(c, a.pslot, a.mat_bytes + 8.0 * a.n * (j + 2));
+  __shared__ typename Op::Lds L;
   __shared__ double red[NC_MAX * WAVES];
   __shared__ double red1[WAVES];
   const int nb = gridDim.x;
@@ -223,7 +221,7 @@ __global__ __launch_bounds__(BS) void k_gmres_a(KArgs a, const double* __restric
   for (int i = 0; i < JM; ++i) u[i] = (i <= j && mine) ? rd.load(i, row) : 0.0;
   double wr = 0.0;
   if (nrows > 0) {
-    const double y = csr_tile(a.rp, a.ci, a.val, row0, nrows, GatherX{V + (size_t)j * ldv}, L);
+    const double y = op.tile(row0, nrows, GatherX{V + (size_t)j * ldv}, L);
     if (mine) {
       wr = c->sigma[j] * y;
       w[row] = wr;
@@ -500,9 +498,9 @@ __global__ __launch_bounds__(64) void k_arnoldi_done(Ctl* c) {
 // ---------------------------------------------------------------------------------------
 static int pick_jm(int cols) { return cols <= 8 ? 8 : cols <= 16 ? 16 : cols <= 32 ? 32 : 64; }
 
-template <class R>
-static hipError_t launch_step(const KArgs& ka, int nb, double* V, size_t ldv, double* w, int j,
-                              hipStream_t s) {
+template <class R, class Op>
+static hipError_t launch_step(const KArgs& ka, const Op& op, int nb, double* V, size_t ldv,
+                              double* w, int j, hipStream_t s) {
   const int jm = pick_jm(j + 1);
   dim3 grid(nb), block(BS);
   KArgs kx = ka;
@@ -513,7 +511,7 @@ static hipError_t launch_step(const KArgs& ka, int nb, double* V, size_t ldv, do
   if (kx.pslot >= 0) probe_end(s, kx.pslot);
 #define GSK_STEP(JMV)                                                                          \
   GSK_TIMED(KC_GMRES_A,                                                                        \
-            hipLaunchKernelGGL((k_gmres_a<JMV, R>), grid, block, 0, s, kx, V, ldv, w, j))      \
+            hipLaunchKernelGGL((k_gmres_a<JMV, R, Op>), grid, block, 0, s, kx, op, V, ldv, w, j)) \
   hipLaunchKernelGGL(k_gmres_fin_a, dim3(j + 2), block, 0, s, ka.ctl, ka.partials, nb, j);     \
   GSK_TIMED(KC_GMRES_B,                                                                        \
             hipLaunchKernelGGL((k_gmres_b<JMV, R>), grid, block, 0, s, kx, V, ldv, w, j))      \
@@ -532,12 +530,14 @@ static hipError_t launch_step(const KArgs& ka, int nb, double* V, size_t ldv, do
   return hipGetLastError();
 }
 
-static void launch_residual(const KArgs& ka, int nb, const double* b, const double* x,
-                            const double* W, double* u0, const int* flags, hipStream_t s) {
+template <class Op>
+static void launch_residual(const KArgs& ka, const Op& op, int nb, const double* b,
+                            const double* x, const double* W, double* u0, const int* flags,
+                            hipStream_t s) {
   KArgs kx = ka;
   kx.pslot = probe_slot(KC_RESIDUAL);
   if (kx.pslot >= 0) probe_begin(s);
-  hipLaunchKernelGGL(k_gmres_residual, dim3(nb), dim3(BS), 0, s, kx, b, x, W, u0, flags);
+  hipLaunchKernelGGL(k_gmres_residual<Op>, dim3(nb), dim3(BS), 0, s, kx, op, b, x, W, u0, flags);
   if (kx.pslot >= 0) probe_end(s, kx.pslot);
   hipLaunchKernelGGL(k_gmres_fin_residual, dim3(1), dim3(BS), 0, s, ka.ctl,
                      (const double*)ka.partials, nb, W ? 1 : 0, flags);
@@ -550,22 +550,22 @@ static SolveResult fail(int code) {
   return r;
 }
 
-template <class R>
-static SolveResult gmres_run(const Csr& A, const double* b, double* x, int m,
+template <class R, class Op>
+static SolveResult gmres_run(const Mat& A, const Op& op, const double* b, double* x, int m,
                              const SolveParams& prm, void* ws, hipStream_t s) {
   Workspace W = carve(ws, A.n);
   const Geom g = make_geom(A.n);
   const size_t ldv = vec_ld(A.n);
   double* V = W.vecs;
   double* w = V + (size_t)(m + 1) * ldv;
-  KArgs ka{A.rp, A.ci, A.val, A.n, g.rpb, W.ctl, W.partials, csr_bytes(A), -1};
+  KArgs ka{A.n, g.rpb, W.ctl, W.partials, A.bytes(), -1};
   dim3 grid(g.nb), block(BS);
   if (launch_clear_flags(W.flags, s) != hipSuccess) return fail(-5);
-  if (launch_validate(A, W.flags, s) != hipSuccess) return fail(-5);
+  if (A.kind == MAT_CSR && launch_validate(A.csr, W.flags, s) != hipSuccess) return fail(-5);
   hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, s, W.ctl, prm.maxit, m, prm.tol, prm.eps_b,
                      prm.weights ? 1 : 0);
   probe_solve_begin();
-  launch_residual(ka, g.nb, b, x, prm.weights, V, W.flags, s);
+  launch_residual(ka, op, g.nb, b, x, prm.weights, V, W.flags, s);
   if (hipGetLastError() != hipSuccess) return fail(-5);
 
   Summary* hs = pinned_summaries();
@@ -583,14 +583,14 @@ static SolveResult gmres_run(const Csr& A, const double* b, double* x, int m,
   const long max_cycles = (long)prm.maxit + 8;
   for (long cyc = 0; cyc <= max_cycles && !done; ++cyc) {
     for (int j = 0; j < m; ++j)
-      if (launch_step<R>(ka, g.nb, V, ldv, w, j, s) != hipSuccess) { res.code = -5; break; }
+      if (launch_step<R>(ka, op, g.nb, V, ldv, w, j, s) != hipSuccess) { res.code = -5; break; }
     if (res.code) break;
     KArgs kx = ka;
     kx.pslot = probe_slot(KC_GMRES_X);
     if (kx.pslot >= 0) probe_begin(s);
     hipLaunchKernelGGL(k_gmres_x<R>, grid, block, 0, s, kx, (const double*)V, ldv, x);
     if (kx.pslot >= 0) probe_end(s, kx.pslot);
-    launch_residual(ka, g.nb, b, x, prm.weights, V, W.flags, s);
+    launch_residual(ka, op, g.nb, b, x, prm.weights, V, W.flags, s);
     if (hipGetLastError() != hipSuccess ||
         hipMemcpyAsync(&hs[slot], &W.ctl->sum, sizeof(Summary), hipMemcpyDeviceToHost, s) !=
             hipSuccess ||
@@ -618,16 +618,16 @@ static SolveResult gmres_run(const Csr& A, const double* b, double* x, int m,
   return res;
 }
 
-template <class R>
-static SolveResult arnoldi_impl(const Csr& A, const double* r0, int m, double* V, int64_t ldv,
-                                double* H, void* ws, double eps_b, hipStream_t s) {
+template <class R, class Op>
+static SolveResult arnoldi_impl(const Mat& A, const Op& op, const double* r0, int m, double* V,
+                                int64_t ldv, double* H, void* ws, double eps_b, hipStream_t s) {
   Workspace W = carve(ws, A.n);
   const Geom g = make_geom(A.n);
   double* w = W.vecs;
-  KArgs ka{A.rp, A.ci, A.val, A.n, g.rpb, W.ctl, W.partials, csr_bytes(A), -1};
+  KArgs ka{A.n, g.rpb, W.ctl, W.partials, A.bytes(), -1};
   dim3 grid(g.nb), block(BS);
   if (launch_clear_flags(W.flags, s) != hipSuccess) return fail(-5);
-  if (launch_validate(A, W.flags, s) != hipSuccess) return fail(-5);
+  if (A.kind == MAT_CSR && launch_validate(A.csr, W.flags, s) != hipSuccess) return fail(-5);
   // tol < 0: the estimate never ends the cycle; maxit = m steps.
   hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, s, W.ctl, m, m, -1.0, eps_b, 0);
   probe_solve_begin();
@@ -635,7 +635,7 @@ static SolveResult arnoldi_impl(const Csr& A, const double* r0, int m, double* V
   hipLaunchKernelGGL(k_arnoldi_fin_start, dim3(1), block, 0, s, W.ctl,
                      (const double*)W.partials, g.nb, (const int*)W.flags);
   for (int j = 0; j < m; ++j)
-    if (launch_step<R>(ka, g.nb, V, (size_t)ldv, w, j, s) != hipSuccess) return fail(-5);
+    if (launch_step<R>(ka, op, g.nb, V, (size_t)ldv, w, j, s) != hipSuccess) return fail(-5);
   const int fin_blocks = 1024;
   hipLaunchKernelGGL(k_arnoldi_finish, dim3(fin_blocks), block, 0, s, ka, V, (size_t)ldv, H, m);
   hipLaunchKernelGGL(k_arnoldi_done, dim3(1), dim3(64), 0, s, W.ctl);
@@ -655,16 +655,33 @@ static SolveResult arnoldi_impl(const Csr& A, const double* r0, int m, double* V
   return res;
 }
 
-SolveResult gmres_solve(const Csr& A, const double* b, double* x, int m, const SolveParams& prm,
-                        void* ws, hipStream_t s) {
-  if (fits_buffer(vec_ld(A.n), m + 1)) return gmres_run<ColumnReader>(A, b, x, m, prm, ws, s);
-  return gmres_run<PointerReader>(A, b, x, m, prm, ws, s);
+template <class Op>
+static SolveResult gmres_dispatch(const Mat& A, const Op& op, const double* b, double* x, int m,
+                                  const SolveParams& prm, void* ws, hipStream_t s) {
+  if (fits_buffer(vec_ld(A.n), m + 1))
+    return gmres_run<ColumnReader>(A, op, b, x, m, prm, ws, s);
+  return gmres_run<PointerReader>(A, op, b, x, m, prm, ws, s);
 }
 
-SolveResult arnoldi_run(const Csr& A, const double* r0, int m, double* V, int64_t ldv, double* H,
+SolveResult gmres_solve(const Mat& A, const double* b, double* x, int m, const SolveParams& prm,
+                        void* ws, hipStream_t s) {
+  if (A.kind == MAT_STENCIL) return gmres_dispatch(A, A.stencil_op(), b, x, m, prm, ws, s);
+  return gmres_dispatch(A, A.csr_op(), b, x, m, prm, ws, s);
+}
+
+template <class Op>
+static SolveResult arnoldi_dispatch(const Mat& A, const Op& op, const double* r0, int m,
+                                    double* V, int64_t ldv, double* H, void* ws, double eps_b,
+                                    hipStream_t s) {
+  if (fits_buffer((size_t)ldv, m + 1))
+    return arnoldi_impl<ColumnReader>(A, op, r0, m, V, ldv, H, ws, eps_b, s);
+  return arnoldi_impl<PointerReader>(A, op, r0, m, V, ldv, H, ws, eps_b, s);
+}
+
+SolveResult arnoldi_run(const Mat& A, const double* r0, int m, double* V, int64_t ldv, double* H,
                         void* ws, double eps_b, hipStream_t s) {
-  if (fits_buffer((size_t)ldv, m + 1)) return arnoldi_impl<ColumnReader>(A, r0, m, V, ldv, H, ws, eps_b, s);
-  return arnoldi_impl<PointerReader>(A, r0, m, V, ldv, H, ws, eps_b, s);
+  if (A.kind == MAT_STENCIL) return arnoldi_dispatch(A, A.stencil_op(), r0, m, V, ldv, H, ws, eps_b, s);
+  return arnoldi_dispatch(A, A.csr_op(), r0, m, V, ldv, H, ws, eps_b, s);
 }
 
 }  // namespace gsk

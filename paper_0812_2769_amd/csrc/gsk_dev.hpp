@@ -302,6 +302,71 @@ struct GatherX {
   __device__ double operator()(int c) const { return x[c]; }
 };
 
+// ---------------------------------------------------------------------------------------
+// Matrix operators. Every kernel that multiplies by A is templated on one of these:
+//   typename Lds                                per-workgroup shared scratch
+//   double tile(row0, nrows, gather, lds)       (A g)_row for row = row0 + threadIdx.x, valid
+//                                               when threadIdx.x < nrows; all threads call it
+//   double bytes                                 algorithmic bytes of one read of A
+// ---------------------------------------------------------------------------------------
+struct CsrOp {
+  const int* rp;
+  const int* ci;
+  const double* val;
+  typedef TileLds Lds;
+  template <class G>
+  __device__ double tile(int row0, int nrows, const G& g, Lds& L) const {
+    return csr_tile(rp, ci, val, row0, nrows, g, L);
+  }
+};
+
+struct EmptyLds {
+  int unused;
+};
+
+// Structured 5-point (nz == 1) or 7-point stencil on an nx x ny x nz grid, x fastest.
+// coef holds one plane of n values per stencil position, in the CSR column order
+// -z, -y, -x, centre, +x, +y, +z (-z and +z absent in 2D); neighbours outside the grid are
+// skipped. Each row is summed in that order with every product rounded before it is added,
+// so the result equals the CSR product of the same matrix bit for bit.
+struct StencilOp {
+  const double* coef;
+  int n, nx, ny, nz;
+  typedef EmptyLds Lds;
+  template <class G>
+  __device__ double tile(int row0, int nrows, const G& g, Lds&) const {
+#pragma clang fp contract(off)
+    const int t = threadIdx.x;
+    if (t >= nrows) return 0.0;
+    const int i = row0 + t;
+    const int ix = i % nx;
+    const int rest = i / nx;
+    const int iy = rest % ny;
+    const int iz = rest / ny;
+    const int nxy = nx * ny;
+    const double* c = coef;
+    double s = 0.0;
+    if (nz > 1) {
+      if (iz > 0) s += c[i] * g(i - nxy);
+      c += n;
+    }
+    if (iy > 0) s += c[i] * g(i - nx);
+    c += n;
+    if (ix > 0) s += c[i] * g(i - 1);
+    c += n;
+    s += c[i] * g(i);
+    c += n;
+    if (ix < nx - 1) s += c[i] * g(i + 1);
+    c += n;
+    if (iy < ny - 1) s += c[i] * g(i + nx);
+    if (nz > 1) {
+      c += n;
+      if (iz < nz - 1) s += c[i] * g(i + nxy);
+    }
+    return s;
+  }
+};
+
 // Reads columns of a column-major n x k FP64 basis through one buffer descriptor: the column
 // offset is a uniform scalar (i * ldv * 8 bytes) and the row offset a single per-lane 32-bit
 // value, so a thread reading 30 columns of its row holds no per-column addresses. Requires

@@ -17,6 +17,25 @@ struct Csr {
   const double* val;
 };
 
+enum : int { MAT_CSR = 0, MAT_STENCIL = 1 };
+
+// A matrix as the solvers see it: CSR, or a structured 5/7-point stencil (coefficient planes).
+struct Mat {
+  int kind;
+  int n;
+  Csr csr;                 // MAT_CSR
+  int nx, ny, nz;          // MAT_STENCIL (nz == 1: 5-point 2D)
+  const double* coef;      // MAT_STENCIL: planes of n values
+  int planes() const { return nz > 1 ? 7 : 5; }
+  // Algorithmic bytes of one read of the matrix.
+  double bytes() const {
+    if (kind == MAT_STENCIL) return 8.0 * planes() * (double)n;
+    return 12.0 * (double)csr.nnz + 4.0 * ((double)csr.n + 1);
+  }
+  CsrOp csr_op() const { return CsrOp{csr.rp, csr.ci, csr.val}; }
+  StencilOp stencil_op() const { return StencilOp{coef, n, nx, ny, nz}; }
+};
+
 struct SolveParams {
   int maxit;
   double tol;
@@ -68,19 +87,21 @@ hipError_t launch_validate(const Csr& A, int* flags, hipStream_t s);
 
 hipError_t launch_gs_scale(const Csr& A, const double* b, int p, double* val_out, double* b_out,
                            double* norm, double* weight, int* flags, hipStream_t s);
-hipError_t launch_spmv(const Csr& A, const double* x, double* y, hipStream_t s);
+hipError_t launch_spmv(const Mat& A, const double* x, double* y, hipStream_t s);
+// Pack a CSR matrix with the 5/7-point pattern of an nx x ny x nz grid into coefficient
+// planes; sets flags[3] if some entry is not a stencil position of its row (or repeats one).
+hipError_t launch_stencil_from_csr(const Csr& A, int nx, int ny, int nz, double* coef,
+                                   int* flags, hipStream_t s);
 
-SolveResult gmres_solve(const Csr& A, const double* b, double* x, int m,
+SolveResult gmres_solve(const Mat& A, const double* b, double* x, int m,
                         const SolveParams& prm, void* ws, hipStream_t s);
-SolveResult arnoldi_run(const Csr& A, const double* r0, int m, double* V, int64_t ldv,
+SolveResult arnoldi_run(const Mat& A, const double* r0, int m, double* V, int64_t ldv,
                         double* H, void* ws, double eps_b, hipStream_t s);
-SolveResult bicgstab_solve(const Csr& A, const double* b, double* x, const SolveParams& prm,
+SolveResult bicgstab_solve(const Mat& A, const double* b, double* x, const SolveParams& prm,
                            void* ws, hipStream_t s);
 
 // Small pinned host buffer for status read-back (one per thread, allocated on first use).
 Summary* pinned_summaries();
-
-inline double csr_bytes(const Csr& A) { return 12.0 * (double)A.nnz + 4.0 * ((double)A.n + 1); }
 
 // Measurement hook (gsk_probe_begin / gsk_probe_end). While a kernel class is selected, every
 // sample_every-th launch of that class gets a slot number: the host brackets it with a pair

@@ -37,6 +37,18 @@ class Csr(ctypes.Structure):
                 ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
 
 
+class Stencil(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("coef", ctypes.c_void_p)]
+
+
+class Matrix(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("csr", Csr), ("stencil", Stencil)]
+
+
+MATRIX_CSR, MATRIX_STENCIL = 0, 1
+
+
 class Options(ctypes.Structure):
     _fields_ = [("maxit", ctypes.c_int32), ("breakdown_eps", ctypes.c_double),
                 ("stop_weights", ctypes.c_void_p), ("check_every", ctypes.c_int32)]
@@ -72,16 +84,19 @@ def _load() -> ctypes.CDLL:
     lib.gsk_workspace_bytes.restype = sz
     lib.gsk_gs_scale.argtypes = [P(Csr), vp, ctypes.c_int32, vp, vp, vp, vp, vp, sz, vp]
     lib.gsk_gs_scale.restype = ctypes.c_int
-    lib.gsk_spmv.argtypes = [P(Csr), vp, vp, vp]
+    lib.gsk_spmv.argtypes = [P(Matrix), vp, vp, vp]
     lib.gsk_spmv.restype = ctypes.c_int
-    lib.gsk_arnoldi.argtypes = [P(Csr), vp, ctypes.c_int32, vp, ctypes.c_int64, vp,
+    lib.gsk_stencil_from_csr.argtypes = [P(Csr), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         vp, vp, sz, vp]
+    lib.gsk_stencil_from_csr.restype = ctypes.c_int
+    lib.gsk_arnoldi.argtypes = [P(Matrix), vp, ctypes.c_int32, vp, ctypes.c_int64, vp,
                                 P(ctypes.c_int32), vp, sz, vp]
     lib.gsk_arnoldi.restype = ctypes.c_int
-    lib.gsk_gmres.argtypes = [P(Csr), vp, vp, ctypes.c_int32, ctypes.c_double, P(Options),
+    lib.gsk_gmres.argtypes = [P(Matrix), vp, vp, ctypes.c_int32, ctypes.c_double, P(Options),
                               P(InfoStruct), vp, sz, vp]
     lib.gsk_gmres.restype = ctypes.c_int
-    lib.gsk_bicgstab.argtypes = [P(Csr), vp, vp, ctypes.c_double, P(Options), P(InfoStruct), vp,
-                                 sz, vp]
+    lib.gsk_bicgstab.argtypes = [P(Matrix), vp, vp, ctypes.c_double, P(Options), P(InfoStruct),
+                                 vp, sz, vp]
     lib.gsk_bicgstab.restype = ctypes.c_int
     lib.gsk_probe_begin.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.gsk_probe_begin.restype = ctypes.c_int
@@ -164,6 +179,29 @@ class CsrMatrix:
         return Csr(self.n, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(),
                    self.val.data_ptr())
 
+    def c_matrix(self) -> Matrix:
+        return Matrix(MATRIX_CSR, self.c_struct(), Stencil(0, 0, 0, None))
+
+
+class StencilMatrix:
+    """A structured 5/7-point stencil matrix in device memory (gsk_stencil): an nx x ny x nz
+    grid (nz = 1 for 2D) and coefficient planes coef[planes, n] in the CSR column order
+    -z, -y, -x, centre, +x, +y, +z."""
+
+    def __init__(self, nx: int, ny: int, nz: int, coef: torch.Tensor):
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.n = self.nx * self.ny * self.nz
+        planes = 7 if self.nz > 1 else 5
+        if (coef.dtype != torch.float64 or not coef.is_cuda or not coef.is_contiguous()
+                or coef.numel() != planes * self.n):
+            raise ValueError(f"coef must be a contiguous CUDA float64 tensor of {planes}*n values")
+        self.coef = coef
+        self.device = coef.device
+
+    def c_matrix(self) -> Matrix:
+        return Matrix(MATRIX_STENCIL, Csr(0, 0, None, None, None),
+                      Stencil(self.nx, self.ny, self.nz, self.coef.data_ptr()))
+
 
 def workspace_bytes(method: int, n: int, m: int = 0) -> int:
     return int(lib.gsk_workspace_bytes(method, n, m))
@@ -202,15 +240,31 @@ def gs_scale(A: CsrMatrix, b: torch.Tensor, p: int = 2, *, inplace: bool = False
     return A.with_values(val_out), b_out, norms, weights
 
 
-def spmv(A: CsrMatrix, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+def spmv(A, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """y = A x for a CsrMatrix or StencilMatrix."""
     _vec(x, A.n, "x")
     y = torch.empty_like(x) if out is None else _vec(out, A.n, "out")
-    c = A.c_struct()
+    c = A.c_matrix()
     _check(lib.gsk_spmv(ctypes.byref(c), x.data_ptr(), y.data_ptr(), _stream(A.device)))
     return y
 
 
-def arnoldi(A: CsrMatrix, r0: torch.Tensor, m: int, ws: Optional[torch.Tensor] = None):
+def stencil_from_csr(A: CsrMatrix, nx: int, ny: int, nz: int = 1,
+                     out: Optional[torch.Tensor] = None,
+                     ws: Optional[torch.Tensor] = None) -> StencilMatrix:
+    """Pack a CSR matrix with a 5/7-point pattern into a StencilMatrix."""
+    planes = 7 if nz > 1 else 5
+    coef = (torch.empty(planes * A.n, dtype=torch.float64, device=A.device) if out is None
+            else out)
+    if ws is None:
+        ws = workspace(METHOD_GS, A.n, 0, A.device)
+    c = A.c_struct()
+    _check(lib.gsk_stencil_from_csr(ctypes.byref(c), int(nx), int(ny), int(nz), coef.data_ptr(),
+                                    ws.data_ptr(), ws.numel(), _stream(A.device)))
+    return StencilMatrix(nx, ny, nz, coef)
+
+
+def arnoldi(A, r0: torch.Tensor, m: int, ws: Optional[torch.Tensor] = None):
     """CGS2 Arnoldi: returns (V [n x (m+1)] column-major storage as a (m+1, n) tensor
     transposed view, H [(m+1) x m], steps)."""
     _vec(r0, A.n, "r0")
@@ -219,7 +273,7 @@ def arnoldi(A: CsrMatrix, r0: torch.Tensor, m: int, ws: Optional[torch.Tensor] =
     steps = ctypes.c_int32(0)
     if ws is None:
         ws = workspace(METHOD_ARNOLDI, A.n, m, A.device)
-    c = A.c_struct()
+    c = A.c_matrix()
     _check(lib.gsk_arnoldi(ctypes.byref(c), r0.data_ptr(), int(m), Vs.data_ptr(), A.n,
                            Hs.data_ptr(), ctypes.byref(steps), ws.data_ptr(), ws.numel(),
                            _stream(A.device)))
@@ -244,7 +298,7 @@ def _info(s: InfoStruct) -> Info:
                 s.relres_recursive, s.relres_true, s.breakdown_test)
 
 
-def gmres(A: CsrMatrix, b: torch.Tensor, x0: Optional[torch.Tensor] = None, m: int = 30,
+def gmres(A, b: torch.Tensor, x0: Optional[torch.Tensor] = None, m: int = 30,
           tol: float = 1e-8, *, maxit: Optional[int] = None, breakdown_eps=None,
           stop_weights: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
           x_out: Optional[torch.Tensor] = None):
@@ -262,14 +316,14 @@ def gmres(A: CsrMatrix, b: torch.Tensor, x0: Optional[torch.Tensor] = None, m: i
         ws = workspace(METHOD_GMRES, A.n, m, A.device)
     o = _options(maxit, breakdown_eps, stop_weights, None, A.n)
     info = InfoStruct()
-    c = A.c_struct()
+    c = A.c_matrix()
     _check(lib.gsk_gmres(ctypes.byref(c), b.data_ptr(), x.data_ptr(), int(m), float(tol),
                          ctypes.byref(o), ctypes.byref(info), ws.data_ptr(), ws.numel(),
                          _stream(A.device)))
     return x, _info(info)
 
 
-def bicgstab(A: CsrMatrix, b: torch.Tensor, x0: Optional[torch.Tensor] = None,
+def bicgstab(A, b: torch.Tensor, x0: Optional[torch.Tensor] = None,
              tol: float = 1e-8, *, maxit: Optional[int] = None, breakdown_eps=None,
              stop_weights: Optional[torch.Tensor] = None, check_every: Optional[int] = None,
              ws: Optional[torch.Tensor] = None, x_out: Optional[torch.Tensor] = None):
@@ -287,7 +341,7 @@ def bicgstab(A: CsrMatrix, b: torch.Tensor, x0: Optional[torch.Tensor] = None,
         ws = workspace(METHOD_BICGSTAB, A.n, 0, A.device)
     o = _options(maxit, breakdown_eps, stop_weights, check_every, A.n)
     info = InfoStruct()
-    c = A.c_struct()
+    c = A.c_matrix()
     _check(lib.gsk_bicgstab(ctypes.byref(c), b.data_ptr(), x.data_ptr(), float(tol),
                             ctypes.byref(o), ctypes.byref(info), ws.data_ptr(), ws.numel(),
                             _stream(A.device)))

@@ -58,10 +58,14 @@ def test_version_and_constants(lib):
 
 
 def test_struct_layouts(lib):
-    # gsk_csr {int32; int64; 3 pointers}, gsk_options {int32; double; ptr; int32}, gsk_info
+    # gsk_csr {int32; int64; 3 pointers}, gsk_options {int32; double; ptr; int32}, gsk_info,
+    # gsk_stencil {3 int32; ptr}, gsk_matrix {int32; gsk_csr; gsk_stencil}
     assert ctypes.sizeof(lib.Csr) == 40
     assert ctypes.sizeof(lib.Options) == 32
     assert ctypes.sizeof(lib.InfoStruct) == 40
+    assert ctypes.sizeof(lib.Stencil) == 24
+    assert ctypes.sizeof(lib.Matrix) == 72
+    assert lib.Matrix.csr.offset == 8 and lib.Matrix.stencil.offset == 48
 
 
 def test_defaults(lib):
@@ -89,9 +93,14 @@ def _fake_csr(lib, n=10, nnz=30):
     return lib.Csr(n, nnz, 0x1000, 0x2000, 0x3000)
 
 
+def _fake_matrix(lib, n=10, nnz=30):
+    return lib.Matrix(lib.MATRIX_CSR, _fake_csr(lib, n, nnz), lib.Stencil(0, 0, 0, None))
+
+
 def test_host_side_rejections(lib):
     L = lib.lib
     c = _fake_csr(lib)
+    mtx = _fake_matrix(lib)
     info = lib.InfoStruct()
     o = lib.default_options()
     ws_ok = 0x100000  # 256-aligned placeholder, paired with too small a size below
@@ -101,36 +110,46 @@ def test_host_side_rejections(lib):
     # p < 1
     assert L.gsk_gs_scale(ctypes.byref(c), 0x10, 0, 0x20, 0x30, None, None, ws_ok, 1 << 30, None) == -1
     # bad n / nnz
-    bad = lib.Csr(0, 0, 0x1000, 0, 0)
+    bad = lib.Matrix(lib.MATRIX_CSR, lib.Csr(0, 0, 0x1000, 0, 0), lib.Stencil(0, 0, 0, None))
     assert L.gsk_spmv(ctypes.byref(bad), 0x10, 0x20, None) == -1
-    bad = lib.Csr(5, -1, 0x1000, 0x2000, 0x3000)
+    bad = lib.Matrix(lib.MATRIX_CSR, lib.Csr(5, -1, 0x1000, 0x2000, 0x3000),
+                     lib.Stencil(0, 0, 0, None))
     assert L.gsk_spmv(ctypes.byref(bad), 0x10, 0x20, None) == -1
+    # stencil matrices: grid too small, NULL planes, unknown kind
+    bad = lib.Matrix(lib.MATRIX_STENCIL, lib.Csr(0, 0, None, None, None), lib.Stencil(1, 4, 4, 0x10))
+    assert L.gsk_spmv(ctypes.byref(bad), 0x10, 0x20, None) == -1
+    bad = lib.Matrix(lib.MATRIX_STENCIL, lib.Csr(0, 0, None, None, None), lib.Stencil(4, 4, 4, None))
+    assert L.gsk_spmv(ctypes.byref(bad), 0x10, 0x20, None) == -1
+    bad = lib.Matrix(7, lib.Csr(0, 0, None, None, None), lib.Stencil(4, 4, 4, 0x10))
+    assert L.gsk_spmv(ctypes.byref(bad), 0x10, 0x20, None) == -1
+    # stencil packing: grid does not match n
+    assert L.gsk_stencil_from_csr(ctypes.byref(c), 3, 3, 1, 0x40, ws_ok, 1 << 30, None) == -1
     # restart length out of range
-    assert L.gsk_gmres(ctypes.byref(c), 0x10, 0x20, 0, 1e-8, None, ctypes.byref(info), ws_ok,
+    assert L.gsk_gmres(ctypes.byref(mtx), 0x10, 0x20, 0, 1e-8, None, ctypes.byref(info), ws_ok,
                        1 << 30, None) == -1
-    assert L.gsk_gmres(ctypes.byref(c), 0x10, 0x20, 65, 1e-8, None, ctypes.byref(info), ws_ok,
+    assert L.gsk_gmres(ctypes.byref(mtx), 0x10, 0x20, 65, 1e-8, None, ctypes.byref(info), ws_ok,
                        1 << 30, None) == -1
     # tol <= 0, maxit < 0, check_every out of range
-    assert L.gsk_bicgstab(ctypes.byref(c), 0x10, 0x20, 0.0, None, ctypes.byref(info), ws_ok,
+    assert L.gsk_bicgstab(ctypes.byref(mtx), 0x10, 0x20, 0.0, None, ctypes.byref(info), ws_ok,
                           1 << 30, None) == -1
     o.maxit = -1
-    assert L.gsk_bicgstab(ctypes.byref(c), 0x10, 0x20, 1e-8, ctypes.byref(o), ctypes.byref(info),
+    assert L.gsk_bicgstab(ctypes.byref(mtx), 0x10, 0x20, 1e-8, ctypes.byref(o), ctypes.byref(info),
                           ws_ok, 1 << 30, None) == -1
     o = lib.default_options()
     o.check_every = 0
-    assert L.gsk_bicgstab(ctypes.byref(c), 0x10, 0x20, 1e-8, ctypes.byref(o), ctypes.byref(info),
+    assert L.gsk_bicgstab(ctypes.byref(mtx), 0x10, 0x20, 1e-8, ctypes.byref(o), ctypes.byref(info),
                           ws_ok, 1 << 30, None) == -1
     # workspace: NULL, misaligned, too small
-    assert L.gsk_bicgstab(ctypes.byref(c), 0x10, 0x20, 1e-8, None, ctypes.byref(info), None,
+    assert L.gsk_bicgstab(ctypes.byref(mtx), 0x10, 0x20, 1e-8, None, ctypes.byref(info), None,
                           1 << 30, None) == -4
-    assert L.gsk_bicgstab(ctypes.byref(c), 0x10, 0x20, 1e-8, None, ctypes.byref(info), ws_ok + 8,
+    assert L.gsk_bicgstab(ctypes.byref(mtx), 0x10, 0x20, 1e-8, None, ctypes.byref(info), ws_ok + 8,
                           1 << 30, None) == -4
-    assert L.gsk_gmres(ctypes.byref(c), 0x10, 0x20, 10, 1e-8, None, ctypes.byref(info), ws_ok, 16,
+    assert L.gsk_gmres(ctypes.byref(mtx), 0x10, 0x20, 10, 1e-8, None, ctypes.byref(info), ws_ok, 16,
                        None) == -4
     assert b"needed" in L.gsk_last_error()
     # arnoldi: ldv < n
     steps = ctypes.c_int32(0)
-    assert L.gsk_arnoldi(ctypes.byref(c), 0x10, 4, 0x20, 5, 0x30, ctypes.byref(steps), ws_ok,
+    assert L.gsk_arnoldi(ctypes.byref(mtx), 0x10, 4, 0x20, 5, 0x30, ctypes.byref(steps), ws_ok,
                          1 << 30, None) == -1
 
 
