@@ -230,21 +230,23 @@ __global__ __launch_bounds__(BS) void k_bicg_p(BArgs a, Op op) {
   block_partials<2>(acc, 2, a.partials, nb, lb, red);
 }
 
-// FP: alpha = rho / (r^, v), or breakdown.
+// FP: alpha = rho / (r^, v), or breakdown. (The finalize launches read their control words
+// together with the partials, one memory round trip, and only the stores depend on them.)
 __global__ __launch_bounds__(BS) void k_bicg_fin_p(Ctl* c, const double* partials, int nb) {
-  if (c->sum.state != ST_RUNNING) return;
+  const int state = c->sum.state;
+  const double eps_b = c->eps_b, rh_norm = c->rh_norm, rho = c->rho;
   __shared__ double out[8];
   small_sums<2>(partials, nb, out);
-  if (threadIdx.x != 0) return;
+  if (state != ST_RUNNING || threadIdx.x != 0) return;
   const double sigma = out[0];
   const double vn = sqrt(out[1]);
-  if (fabs(sigma) <= c->eps_b * c->rh_norm * vn) {
+  if (fabs(sigma) <= eps_b * rh_norm * vn) {
     c->sum.status = S_BREAKDOWN;
     c->sum.brk = BRK_SIGMA;
     c->sum.state = ST_FINAL;
     return;
   }
-  c->alpha = c->rho / sigma;
+  c->alpha = rho / sigma;
 }
 
 // S: t = A s with s = r - alpha v; partials (t,s), (t,t), ||s||^2, ||W s||^2.
@@ -284,21 +286,22 @@ __global__ __launch_bounds__(BS) void k_bicg_s(BArgs a, Op op) {
 // FS: iteration count, half-step test on ||W s||, omega = (t,s)/(t,t), or breakdown.
 __global__ __launch_bounds__(BS) void k_bicg_fin_s(Ctl* c, const double* partials, int nb,
                                                    int has_w) {
-  if (c->sum.state != ST_RUNNING) return;
+  const int state = c->sum.state, iters = c->sum.iters;
+  const double ref = c->ref, tol = c->tol, eps_b = c->eps_b;
   __shared__ double out[8];
   small_sums<4>(partials, nb, out);
-  if (threadIdx.x != 0) return;
-  c->sum.iters += 1;
+  if (state != ST_RUNNING || threadIdx.x != 0) return;
+  c->sum.iters = iters + 1;
   const double sn = sqrt(out[2]);
-  const double est = (has_w ? sqrt(out[3]) : sn) / c->ref;
+  const double est = (has_w ? sqrt(out[3]) : sn) / ref;
   c->sum.relres_rec = est;
-  if (est < c->tol) {
+  if (est < tol) {
     c->sum.half = 1;
     c->sum.state = ST_HALF;
     return;
   }
   const double ts = out[0], tt = out[1];
-  if (fabs(ts) <= c->eps_b * sqrt(tt) * sn) {
+  if (fabs(ts) <= eps_b * sqrt(tt) * sn) {
     c->sum.status = S_BREAKDOWN;
     c->sum.brk = BRK_OMEGA;
     c->sum.state = ST_FINAL;
@@ -346,34 +349,36 @@ __global__ __launch_bounds__(BS) void k_bicg_u(BArgs a) {
 // FU: stop test on ||W r|| (or the iteration cap), then rho, beta, or breakdown.
 __global__ __launch_bounds__(BS) void k_bicg_fin_u(Ctl* c, const double* partials, int nb,
                                                    int has_w) {
-  const int st = c->sum.state;
-  if (st != ST_RUNNING && st != ST_HALF) return;
-  if (st == ST_HALF) {
-    if (threadIdx.x == 0) c->sum.state = ST_VERIFY;
-    return;
-  }
+  const int st = c->sum.state, iters = c->sum.iters, maxit = c->maxit, parity = c->parity;
+  const double ref = c->ref, tol = c->tol, eps_b = c->eps_b, rh_norm = c->rh_norm;
+  const double rho = c->rho, alpha = c->alpha, omega = c->omega;
   __shared__ double out[8];
   small_sums<3>(partials, nb, out);
   if (threadIdx.x != 0) return;
+  if (st == ST_HALF) {
+    c->sum.state = ST_VERIFY;
+    return;
+  }
+  if (st != ST_RUNNING) return;
   const double rn = sqrt(out[1]);
-  const double est = (has_w ? sqrt(out[2]) : rn) / c->ref;
+  const double est = (has_w ? sqrt(out[2]) : rn) / ref;
   c->sum.relres_rec = est;
-  if (est < c->tol || c->sum.iters >= c->maxit) {
+  if (est < tol || iters >= maxit) {
     c->sum.state = ST_VERIFY;
     return;
   }
   const double rho_new = out[0];
-  if (fabs(rho_new) <= c->eps_b * c->rh_norm * rn) {
+  if (fabs(rho_new) <= eps_b * rh_norm * rn) {
     c->sum.status = S_BREAKDOWN;
     c->sum.brk = BRK_RHO;
     c->sum.state = ST_FINAL;
     return;
   }
-  c->beta = (rho_new / c->rho) * (c->alpha / c->omega);
-  c->rho_old = c->rho;
+  c->beta = (rho_new / rho) * (alpha / omega);
+  c->rho_old = rho;
   c->rho = rho_new;
   c->first = 0;
-  c->parity ^= 1;
+  c->parity = parity ^ 1;
 }
 
 template <class Op>

@@ -198,14 +198,15 @@ __global__ __launch_bounds__(BS) void k_gmres_fin_residual(Ctl* c, const double*
 }
 
 // A: w = sigma_j A u_j; partials of u_i . w (columns 0..j) and ||w||^2 (column j+1).
-// The basis values of the thread's row are loaded before the product so that their latency
-// overlaps it.
+// Loads are issued in the order they are needed (stencil operands, then the basis values of
+// the thread's row) before the launch tests whether it has work: the control block is read
+// alongside, so the test costs no round trip of its own. A launch without work stores nothing.
 template <int JM, class R, class Op>
 __global__ __launch_bounds__(BS) void k_gmres_a(KArgs a, Op op, const double* __restrict__ V,
                                                 size_t ldv, double* __restrict__ w, int j) {
   Ctl* c = a.ctl;
-  if (c->sum.state != ST_RUNNING || c->j != j) return;
-  mark_work(c, a.pslot, a.mat_bytes + 8.0 * a.n * (j + 2));
+  const int state = c->sum.state, cj = c->j;
+  const double sg = c->sigma[j];
   __shared__ typename Op::Lds L;
   __shared__ double red[NC_MAX * WAVES];
   __shared__ double red1[WAVES];
@@ -215,18 +216,19 @@ __global__ __launch_bounds__(BS) void k_gmres_a(KArgs a, Op op, const double* __
   const int nrows = tile_rows(a.n, row0);
   const int row = row0 + threadIdx.x;
   const bool mine = (int)threadIdx.x < nrows;
+  const GatherX gx{V + (size_t)j * ldv};
+  typename Op::Pre pre{};
+  if (nrows > 0) pre = op.load(row0, nrows, gx);
   const R rd(V, ldv, j + 1);
   double u[JM];
 #pragma unroll
   for (int i = 0; i < JM; ++i) u[i] = (i <= j && mine) ? rd.load(i, row) : 0.0;
-  double wr = 0.0;
-  if (nrows > 0) {
-    const double y = op.tile(row0, nrows, GatherX{V + (size_t)j * ldv}, L);
-    if (mine) {
-      wr = c->sigma[j] * y;
-      w[row] = wr;
-    }
-  }
+  const double y = nrows > 0 ? op.finish(pre, row0, nrows, gx, L) : 0.0;
+  asm volatile("" ::: "memory");   // keeps the loads above ahead of the test below
+  if (state != ST_RUNNING || cj != j) return;
+  mark_work(c, a.pslot, a.mat_bytes + 8.0 * a.n * (j + 2));
+  const double wr = mine ? sg * y : 0.0;
+  if (mine) w[row] = wr;
 #pragma unroll
   for (int i = 0; i < JM; ++i) u[i] *= wr;
   block_halving_partials<JM>(u, j + 1, a.partials, nb, lb, red);
@@ -234,38 +236,49 @@ __global__ __launch_bounds__(BS) void k_gmres_a(KArgs a, Op op, const double* __
 }
 
 // FA (j+2 workgroups): workgroup i <= j -> c1_i = sigma_i (u_i . w); workgroup j+1 -> ||A v_j||.
+// The control words are read together with the partials (one memory round trip) and only the
+// store depends on them.
 __global__ __launch_bounds__(BS) void k_gmres_fin_a(Ctl* c, const double* partials, int nb,
                                                     int j) {
-  if (c->sum.state != ST_RUNNING || c->j != j) return;
   __shared__ double lds[WAVES];
   const int col = blockIdx.x;
+  const int state = c->sum.state, cj = c->j;
+  const double sg = c->sigma[col];
   const double s = column_sum(partials + (size_t)col * nb, nb, lds);
-  if (threadIdx.x != 0) return;
-  if (col == j + 1) c->wnorm_pre = sqrt(s);
-  else c->c1[col] = c->sigma[col] * s;
+  if (state != ST_RUNNING || cj != j || threadIdx.x != 0) return;
+  if (col == j + 1) {
+    c->wnorm_pre = sqrt(s);
+  } else {
+    const double c1 = sg * s;
+    c->c1[col] = c1;
+    c->d1[col] = c1 * sg;
+  }
 }
 
-// B: w -= sum_i c1_i v_i, then partials of u_i . w, sharing one read of the basis.
+// B: w -= sum_i c1_i v_i (weights d1_i = c1_i sigma_i on the stored columns), then partials of
+// u_i . w, sharing one read of the basis. Operands are requested before the work test, as in A.
 template <int JM, class R>
 __global__ __launch_bounds__(BS) void k_gmres_b(KArgs a, const double* __restrict__ V, size_t ldv,
                                                 double* __restrict__ w, int j) {
   Ctl* c = a.ctl;
-  if (c->sum.state != ST_RUNNING || c->j != j) return;
-  mark_work(c, a.pslot, 8.0 * a.n * (j + 3));
-  __shared__ double d[JM];
+  const int state = c->sum.state, cj = c->j;
   __shared__ double red[NC_MAX * WAVES];
   const int t = threadIdx.x;
-  if (t <= j && t < JM) d[t] = c->c1[t] * c->sigma[t];
   const int nb = gridDim.x;
   const int lb = logical_block();
   const int row = lb * BS + t;
   const bool mine = row < a.n;
+  double d[JM];   // uniform across the launch: scalar loads
+#pragma unroll
+  for (int i = 0; i < JM; ++i) d[i] = c->d1[i];
   const R rd(V, ldv, j + 1);
   double u[JM];
 #pragma unroll
   for (int i = 0; i < JM; ++i) u[i] = (i <= j && mine) ? rd.load(i, row) : 0.0;
   double wr = mine ? w[row] : 0.0;
-  __syncthreads();
+  asm volatile("" ::: "memory");
+  if (state != ST_RUNNING || cj != j) return;
+  mark_work(c, a.pslot, 8.0 * a.n * (j + 3));
 #pragma unroll
   for (int i = 0; i < JM; ++i)
     if (i <= j) wr = fma(-d[i], u[i], wr);
@@ -278,34 +291,41 @@ __global__ __launch_bounds__(BS) void k_gmres_b(KArgs a, const double* __restric
 // FB (j+1 workgroups): c2_i = sigma_i (u_i . w).
 __global__ __launch_bounds__(BS) void k_gmres_fin_b(Ctl* c, const double* partials, int nb,
                                                     int j) {
-  if (c->sum.state != ST_RUNNING || c->j != j) return;
   __shared__ double lds[WAVES];
   const int col = blockIdx.x;
+  const int state = c->sum.state, cj = c->j;
+  const double sg = c->sigma[col];
   const double s = column_sum(partials + (size_t)col * nb, nb, lds);
-  if (threadIdx.x == 0) c->c2[col] = c->sigma[col] * s;
+  if (state != ST_RUNNING || cj != j || threadIdx.x != 0) return;
+  const double c2 = sg * s;
+  c->c2[col] = c2;
+  c->d2[col] = c2 * sg;
 }
 
-// C: w -= sum_i c2_i v_i, u_{j+1} = w, partial ||w||^2.
+// C: w -= sum_i c2_i v_i (weights d2_i = c2_i sigma_i), u_{j+1} = w, partial ||w||^2.
+// Operands are requested before the work test, as in A.
 template <int JM, class R>
 __global__ __launch_bounds__(BS) void k_gmres_c(KArgs a, double* __restrict__ V, size_t ldv,
                                                 const double* __restrict__ w, int j) {
   Ctl* c = a.ctl;
-  if (c->sum.state != ST_RUNNING || c->j != j) return;
-  mark_work(c, a.pslot, 8.0 * a.n * (j + 3));
-  __shared__ double d[JM];
+  const int state = c->sum.state, cj = c->j;
   __shared__ double red[WAVES];
   const int t = threadIdx.x;
-  if (t <= j && t < JM) d[t] = c->c2[t] * c->sigma[t];
   const int nb = gridDim.x;
   const int lb = logical_block();
   const int row = lb * BS + t;
   const bool mine = row < a.n;
+  double d[JM];   // uniform across the launch: scalar loads
+#pragma unroll
+  for (int i = 0; i < JM; ++i) d[i] = c->d2[i];
   const R rd(V, ldv, j + 1);
   double u[JM];
 #pragma unroll
   for (int i = 0; i < JM; ++i) u[i] = (i <= j && mine) ? rd.load(i, row) : 0.0;
   double wr = mine ? w[row] : 0.0;
-  __syncthreads();
+  asm volatile("" ::: "memory");
+  if (state != ST_RUNNING || cj != j) return;
+  mark_work(c, a.pslot, 8.0 * a.n * (j + 3));
 #pragma unroll
   for (int i = 0; i < JM; ++i)
     if (i <= j) wr = fma(-d[i], u[i], wr);
@@ -314,66 +334,74 @@ __global__ __launch_bounds__(BS) void k_gmres_c(KArgs a, double* __restrict__ V,
 }
 
 // FC (1 workgroup): Hessenberg column, Givens rotations, residual estimate; at the end of a
-// cycle the k x k triangular solve H y = g (y stored pre-multiplied by sigma).
+// cycle the k x k triangular solve H y = g (y stored pre-multiplied by sigma). Every control
+// word the launch needs is requested before the first wait; the old rotations are applied in
+// registers by one thread.
 __global__ __launch_bounds__(BS) void k_gmres_fin_c(Ctl* c, const double* partials, int nb,
                                                     int j) {
-  if (c->sum.state != ST_RUNNING || c->j != j) return;
   __shared__ double lds[WAVES];
   __shared__ double s_h[MMAX + 2];
   __shared__ double s_cs[MMAX], s_sn[MMAX];
   __shared__ int s_end, s_k;
   constexpr int LDH = MMAX + 1;
   const int t = threadIdx.x;
-  const double nrm2 = column_sum(partials, nb, lds);
+  const int state = c->sum.state, cj = c->j;
+  const int iters = c->sum.iters, maxit = c->maxit, m = c->m;
+  const double eps_b = c->eps_b, wpre = c->wnorm_pre, gj = c->g[j];
+  const double ratio = c->ratio, ref = c->ref, tol = c->tol;
   if (t <= j) {
     s_h[t] = c->c1[t] + c->c2[t];
     s_cs[t] = c->cs[t];
     s_sn[t] = c->sn[t];
   }
-  __syncthreads();
+  const double nrm2 = column_sum(partials, nb, lds);   // also orders the LDS writes above
+  if (state != ST_RUNNING || cj != j) return;
+  const double hn = sqrt(nrm2);
+  if (t <= j) c->Hraw[(size_t)j * LDH + t] = s_h[t];
+  if (t == j + 1) c->Hraw[(size_t)j * LDH + t] = hn;
   if (t == 0) {
-    const double hn = sqrt(nrm2);
-    s_h[j + 1] = hn;
-    for (int i = 0; i <= j + 1; ++i) c->Hraw[(size_t)j * LDH + i] = s_h[i];
-    const int happy = hn <= c->eps_b * c->wnorm_pre;
+    const int happy = hn <= eps_b * wpre;
     c->happy = happy;
     if (!happy) c->sigma[j + 1] = 1.0 / hn;
+    double hi = s_h[0];
     for (int i = 0; i < j; ++i) {
-      const double tmp = s_cs[i] * s_h[i] + s_sn[i] * s_h[i + 1];
-      s_h[i + 1] = -s_sn[i] * s_h[i] + s_cs[i] * s_h[i + 1];
-      s_h[i] = tmp;
+      const double hnext = s_h[i + 1];
+      s_h[i] = s_cs[i] * hi + s_sn[i] * hnext;
+      hi = -s_sn[i] * hi + s_cs[i] * hnext;
     }
-    const double dd = hypot(s_h[j], s_h[j + 1]);
-    c->sum.iters += 1;
+    const double dd = hypot(hi, hn);
+    c->sum.iters = iters + 1;
     int end = 0, k = j + 1;
     if (dd == 0.0) {
       c->broke = 1;
       c->sum.brk = BRK_GIVENS;
       k = j;
       end = 1;
+      s_h[j] = hi;
+      s_h[j + 1] = hn;
     } else {
-      const double cj = s_h[j] / dd;
-      const double sj = s_h[j + 1] / dd;
+      const double cjr = hi / dd;
+      const double sjr = hn / dd;
       s_h[j] = dd;
       s_h[j + 1] = 0.0;
-      const double gj = c->g[j];
-      c->g[j + 1] = -sj * gj;
-      c->g[j] = cj * gj;
-      c->cs[j] = cj;
-      c->sn[j] = sj;
-      const double est = fabs(c->g[j + 1]) * c->ratio / c->ref;
+      const double g1 = -sjr * gj;
+      c->g[j + 1] = g1;
+      c->g[j] = cjr * gj;
+      c->cs[j] = cjr;
+      c->sn[j] = sjr;
+      const double est = fabs(g1) * ratio / ref;
       c->sum.relres_rec = est;
-      const int claimed = (est < c->tol) || happy;
+      const int claimed = (est < tol) || happy;
       c->claimed = claimed;
-      end = claimed || (c->sum.iters >= c->maxit) || (j + 1 == c->m);
+      end = claimed || (iters + 1 >= maxit) || (j + 1 == m);
     }
-    for (int i = 0; i <= j + 1; ++i) c->H[(size_t)j * LDH + i] = s_h[i];
     c->j = j + 1;
     c->k = k;
     s_end = end;
     s_k = k;
   }
   __syncthreads();
+  if (t <= j + 1) c->H[(size_t)j * LDH + t] = s_h[t];
   if (!s_end) return;
 
   __shared__ double s_H[MMAX][MMAX + 1];   // s_H[col][row]

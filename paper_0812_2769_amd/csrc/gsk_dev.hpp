@@ -25,6 +25,7 @@ constexpr int WAVES = BS / 64;
 constexpr int TILE_NNZ = BS * 8;    // LDS product slots per tile (8 per row on average)
 constexpr int MMAX = 64;            // largest GMRES restart length
 constexpr int NC_MAX = MMAX + 2;    // most values reduced in one launch
+constexpr int SUM_BATCH = 8;        // partials one thread of a finalize launch loads at once
 
 // Solver state machine (Ctl::state)
 enum : int {
@@ -77,6 +78,8 @@ struct Ctl {
   double sigma[MMAX + 1];
   double c1[MMAX + 1];
   double c2[MMAX + 1];
+  double d1[MMAX + 1];     // c1_i sigma_i and c2_i sigma_i: the update weights of the stored
+  double d2[MMAX + 1];     // (unnormalised) basis columns in the two CGS passes
   double H[(MMAX + 1) * MMAX];   // column-major, ld MMAX+1, rotated in place
   double Hraw[(MMAX + 1) * MMAX];// unrotated Hessenberg (for the Arnoldi entry point)
   double cs[MMAX], sn[MMAX], g[MMAX + 1], y[MMAX];
@@ -199,19 +202,23 @@ __device__ inline void block_halving_partials(double (&v)[NV], int nc,
   }
 }
 
-// Sum of partials[0..nb) in a fixed order (thread t takes t, t+BS, ...; then the workgroup
-// tree). Every thread of the workgroup must call; the result is returned to all threads.
+// Sum of partials[0..nb) in a fixed order (thread t adds t, t+BS, ... in turn; then the wave
+// and workgroup trees). Every thread of the workgroup must call; all threads get the result.
 __device__ inline double column_sum(const double* __restrict__ partials, int nb, double* lds) {
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int l = threadIdx.x;
-  for (; l + 3 * BS < nb; l += 4 * BS) {
-    a0 += partials[l];
-    a1 += partials[l + BS];
-    a2 += partials[l + 2 * BS];
-    a3 += partials[l + 3 * BS];
+  // Each thread requests SUM_BATCH partials before it adds any of them, so a column of up to
+  // SUM_BATCH * BS partials costs one memory round trip.
+  double acc = 0.0;
+  for (int base = 0; base < nb; base += SUM_BATCH * BS) {
+    double v[SUM_BATCH];
+#pragma unroll
+    for (int q = 0; q < SUM_BATCH; ++q) {
+      const int l = base + q * BS + (int)threadIdx.x;
+      v[q] = l < nb ? partials[l] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < SUM_BATCH; ++q) acc += v[q];
   }
-  for (; l < nb; l += BS) a0 += partials[l];
-  const double v = wave_sum((a0 + a1) + (a2 + a3));
+  const double v = wave_sum(acc);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
   __syncthreads();
@@ -229,9 +236,18 @@ __device__ inline void small_sums(const double* __restrict__ partials, int nb, d
   double acc[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-  for (int l = threadIdx.x; l < nb; l += BS) {
+  for (int base = 0; base < nb; base += SUM_BATCH * BS) {
+    double v[NC][SUM_BATCH];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) acc[c] += partials[c * nb + l];
+    for (int q = 0; q < SUM_BATCH; ++q) {
+      const int l = base + q * BS + (int)threadIdx.x;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[c][q] = l < nb ? partials[c * nb + l] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int q = 0; q < SUM_BATCH; ++q) acc[c] += v[c][q];
   }
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -309,14 +325,25 @@ struct GatherX {
 //                                               when threadIdx.x < nrows; all threads call it
 //   double bytes                                 algorithmic bytes of one read of A
 // ---------------------------------------------------------------------------------------
+//
+// Besides tile(), an operator offers the product in two phases, load() and finish(), so a
+// kernel can put other loads between the two (see k_gmres_a); finish(load(...)) == tile().
+// nrows >= 1 in every call.
 struct CsrOp {
   const int* rp;
   const int* ci;
   const double* val;
   typedef TileLds Lds;
+  struct Pre {};   // a CSR tile stages its nonzeros through LDS behind barriers: nothing ahead
   template <class G>
   __device__ double tile(int row0, int nrows, const G& g, Lds& L) const {
     return csr_tile(rp, ci, val, row0, nrows, g, L);
+  }
+  template <class G>
+  __device__ Pre load(int, int, const G&) const { return Pre{}; }
+  template <class G>
+  __device__ double finish(const Pre&, int row0, int nrows, const G& g, Lds& L) const {
+    return tile(row0, nrows, g, L);
   }
 };
 
@@ -333,37 +360,54 @@ struct StencilOp {
   const double* coef;
   int n, nx, ny, nz;
   typedef EmptyLds Lds;
+  // Position q of a row: -z, -y, -x, centre, +x, +y, +z. load() fetches every coefficient and
+  // neighbour without a branch, so that all loads are in flight together: the neighbour index
+  // is i + offset clamped to [0, n), a valid address whatever the position, and a position
+  // outside the grid (or -z/+z in 2D) is flagged absent and its values are never used.
+  struct Pre {
+    double c[7], x[7];
+    unsigned present;
+  };
   template <class G>
-  __device__ double tile(int row0, int nrows, const G& g, Lds&) const {
-#pragma clang fp contract(off)
+  __device__ Pre load(int row0, int nrows, const G& g) const {
+    Pre p;
     const int t = threadIdx.x;
-    if (t >= nrows) return 0.0;
-    const int i = row0 + t;
+    const int i = row0 + min(t, nrows - 1);   // rows past the tile repeat its last row
     const int ix = i % nx;
     const int rest = i / nx;
     const int iy = rest % ny;
     const int iz = rest / ny;
     const int nxy = nx * ny;
-    const double* c = coef;
+    const bool three = nz > 1;
+    const bool in[7] = {three && iz > 0, iy > 0,      ix > 0, true,
+                        ix < nx - 1,     iy < ny - 1, three && iz < nz - 1};
+    const int off[7] = {-nxy, -nx, -1, 0, 1, nx, nxy};
+    p.present = 0;
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+      const int plane = three ? q : (q == 0 ? 0 : q == 6 ? 4 : q - 1);
+      p.c[q] = coef[(size_t)plane * n + i];
+      const long long k = (long long)i + off[q];
+      p.x[q] = g((int)(k < 0 ? 0 : k >= n ? n - 1 : k));
+      p.present |= in[q] ? 1u << q : 0u;
+    }
+    return p;
+  }
+  // Sum in position order with every product rounded; an absent position adds +0.0, which
+  // leaves the sum unchanged (a sum that starts at +0.0 never becomes -0.0), so the result
+  // equals the CSR product of the same matrix bit for bit.
+  template <class G>
+  __device__ double finish(const Pre& p, int, int nrows, const G&, Lds&) const {
+#pragma clang fp contract(off)
+    if ((int)threadIdx.x >= nrows) return 0.0;
     double s = 0.0;
-    if (nz > 1) {
-      if (iz > 0) s += c[i] * g(i - nxy);
-      c += n;
-    }
-    if (iy > 0) s += c[i] * g(i - nx);
-    c += n;
-    if (ix > 0) s += c[i] * g(i - 1);
-    c += n;
-    s += c[i] * g(i);
-    c += n;
-    if (ix < nx - 1) s += c[i] * g(i + 1);
-    c += n;
-    if (iy < ny - 1) s += c[i] * g(i + nx);
-    if (nz > 1) {
-      c += n;
-      if (iz < nz - 1) s += c[i] * g(i + nxy);
-    }
+#pragma unroll
+    for (int q = 0; q < 7; ++q) s += (p.present >> q) & 1u ? p.c[q] * p.x[q] : 0.0;
     return s;
+  }
+  template <class G>
+  __device__ double tile(int row0, int nrows, const G& g, Lds& L) const {
+    return finish(load(row0, nrows, g), row0, nrows, g, L);
   }
 };
 

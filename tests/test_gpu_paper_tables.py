@@ -1,0 +1,96 @@
+"""The paper's convergence tables reproduced through the HIP path (stencil operator).
+
+Problem 1 at 128x128 (Table 1) and Problem 4 at 80x80x80 (the iteration table of section
+"Problem 4"): which runs converge and which do not must agree with the printed table, and
+converged iteration counts must lie within 10% of the printed ones (the paper's runs used
+AZTEC, whose rounding differs; restarted GMRES and Bi-CGSTAB amplify such differences). Runs
+without GS are measured on the GS(2)-scaled residual through stop weights, as the paper does.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_0812_2769_amd import problems
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOLS = (1e-4, 1e-7, 1e-10)
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0812_2769_amd import gsk
+    return gsk
+
+
+def _golden(name):
+    rows = {}
+    with open(os.path.join(HERE, "golden", name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                parts = line.split()
+                rows[parts[0]] = parts[1:]
+    return rows
+
+
+def _setup(G, P):
+    """Unscaled and GS(2)-scaled stencil operators, right-hand sides and the stop weights
+    1/||a_i||_2 that put unscaled runs on the scaled residual."""
+    import torch
+    A = G.CsrMatrix.from_problem(P)
+    b = torch.from_numpy(np.ascontiguousarray(P.b)).cuda()
+    S, bs, nrm, _ = G.gs_scale(A, b, 2)
+    return (G.stencil_from_csr(A, *P.dims), b, 1.0 / nrm), (G.stencil_from_csr(S, *P.dims), bs,
+                                                             None)
+
+
+def _runs(G, P, tol):
+    plain, scaled = _setup(G, P)
+    out = {}
+    for key, (M, rhs, w) in (("", plain), ("_gs", scaled)):
+        out["bicgstab" + key] = G.bicgstab(M, rhs, tol=tol, maxit=10000, stop_weights=w)[1]
+        out["gmres10" + key] = G.gmres(M, rhs, m=10, tol=tol, maxit=10000, stop_weights=w)[1]
+    return out
+
+
+def _check(G, printed, info, what):
+    if printed == "nc":
+        assert info.status != G.CONVERGED, what
+    else:
+        assert info.status == G.CONVERGED, what
+        assert info.iters == pytest.approx(int(printed), rel=0.10), (what, info.iters, printed)
+
+
+@pytest.mark.parametrize("D,col0", [(1e4, 0), (1e6, 1)])
+def test_problem4_80cube_table(G, D, col0):
+    gold = _golden("table_problem4_80cube_iterations.txt")
+    P = problems.problem4(80, D=D)
+    for t, tol in enumerate(TOLS):
+        runs = _runs(G, P, tol)
+        for method, info in runs.items():
+            _check(G, gold[method][col0 + 2 * t], info, (D, tol, method))
+
+
+def test_table1_problem1(G):
+    gold = _golden("table1_problem1_iterations.txt")
+    P = problems.problem1(128)
+    for t, tol in enumerate(TOLS):
+        runs = _runs(G, P, tol)
+        _check(G, gold["bicgstab"][t], runs["bicgstab"], ("bicgstab", tol))
+        _check(G, gold["bicgstab_gs"][t], runs["bicgstab_gs"], ("bicgstab_gs", tol))
+        for method in ("gmres10", "gmres10_gs"):
+            printed, info = gold[method][t], runs[method]
+            if printed.startswith("->"):
+                # stagnation: the cap is reached at a level near the printed one (factor 2
+                # with GS, 10 without, where the level is set by rounding in the restarts)
+                level = float(printed[2:])
+                f = 2.0 if method.endswith("_gs") else 10.0
+                assert info.status != G.CONVERGED, (method, tol)
+                assert level / f < info.relres_true < level * f, (method, tol, info)
+            else:
+                _check(G, printed, info, (method, tol))

@@ -419,10 +419,16 @@ def test_c2_full_size_gs_and_spmv_sampled(G, c2):
     x = np.random.default_rng(5).standard_normal(P.n)
     y = host(G.spmv(A, torch.from_numpy(x).cuda()))
     np.testing.assert_array_equal(y[rows], oracle.spmv(sub, x))
+    St = G.stencil_from_csr(A, *P.dims)
+    y = host(G.spmv(St, torch.from_numpy(x).cuda()))
+    np.testing.assert_array_equal(y[rows], oracle.spmv(sub, x))
 
 
+@pytest.mark.parametrize("operator", ["stencil", "csr"])
 @pytest.mark.parametrize("key", ["gs2_bicgstab", "gs2_gmres30", "gs1_bicgstab", "gs1_gmres30"])
-def test_c2_full_size_solves_match_oracle(G, c2, key):
+def test_c2_full_size_solves_match_oracle(G, c2, key, operator):
+    """The bench's four solves at full size, in the bench's launch configuration (GS(p) out of
+    place, then, for the stencil operator, packing of the scaled matrix)."""
     import torch
     gold = _golden_c2()
     run = gold["runs"][key]
@@ -431,6 +437,8 @@ def test_c2_full_size_solves_match_oracle(G, c2, key):
     P = c2
     A, b = up(G, P)
     As, bs, _, w = G.gs_scale(A, b, p, want_weights=True)
+    if operator == "stencil":
+        As = G.stencil_from_csr(As, *P.dims)
     weights = None if p == 2 else w
     if key.endswith("bicgstab"):
         x, info = G.bicgstab(As, bs, tol=1e-10, stop_weights=weights)
