@@ -12,8 +12,12 @@
 //   U  x += alpha p + omega s, r = s - omega t; (r^, r), ||r||, ||W r||
 //      FU -> stop test, rho, beta
 //
-// p and v are double-buffered (parity bit in the control block) because P reads the old p
-// and v of neighbouring rows while it writes the new ones. The residual launch R computes
+// p and v are double-buffered because P reads the old p and v of neighbouring rows while it
+// writes the new ones. The host gives every enqueued iteration its buffer parity (the
+// iteration's enqueue count mod 2): within a run of working iterations the parities
+// alternate, and the first iteration after a (re)start reads no old p or v. The step
+// launches request all their operands before they read the control block to learn whether
+// they have work (a launch without work stores nothing). The residual launch R computes
 // r = b - A x for the initial residual and for every verification of a recursive
 // convergence claim; a failed verification restarts the recurrence from the true residual.
 #include "gsk_host.hpp"
@@ -35,6 +39,7 @@ struct BArgs {
   const double* W;
   double mat_bytes;   // algorithmic bytes of one read of A
   int pslot;          // measurement slot of this launch, or -1
+  int par;            // buffer parity of this iteration: reads p[par], v[par]
 };
 
 __device__ inline void brange(const BArgs& a, int lb, int& begin, int& end) {
@@ -61,7 +66,6 @@ __global__ __launch_bounds__(64) void k_bicg_init_ctl(Ctl* c, int maxit, double 
   c->m = 0;
   c->j = c->k = c->claimed = 0;
   c->first = 1;
-  c->parity = 0;
   c->has_w = has_w;
   c->broke = c->happy = 0;
   c->tol = tol;
@@ -185,47 +189,60 @@ struct GatherP {
   const double* __restrict__ v;
   double beta, omega;
   int first;
-  __device__ double operator()(int col) const {
-    return first ? r[col] : fma(beta, fma(-omega, v[col], p[col]), r[col]);
+  struct Raw {
+    double r, p, v;
+  };
+  __device__ Raw load(int col) const { return Raw{r[col], p[col], v[col]}; }
+  __device__ double value(const Raw& a) const {
+    return first ? a.r : fma(beta, fma(-omega, a.v, a.p), a.r);
   }
+  __device__ double operator()(int col) const { return value(load(col)); }
 };
 
 struct GatherS {
   const double* __restrict__ r;
   const double* __restrict__ v;
   double alpha;
-  __device__ double operator()(int col) const { return fma(-alpha, v[col], r[col]); }
+  struct Raw {
+    double r, v;
+  };
+  __device__ Raw load(int col) const { return Raw{r[col], v[col]}; }
+  __device__ double value(const Raw& a) const { return fma(-alpha, a.v, a.r); }
+  __device__ double operator()(int col) const { return value(load(col)); }
 };
 
 // P: new p, v = A p; partials (r^, v), ||v||^2.
 template <class Op>
 __global__ __launch_bounds__(BS) void k_bicg_p(BArgs a, Op op) {
   Ctl* c = a.ctl;
-  if (c->sum.state != ST_RUNNING) return;
-  mark_work(c, a.pslot, a.mat_bytes + 8.0 * a.n * (c->first ? 4 : 6));
-  const int q = c->parity;
-  const double* pin = a.p[q];
-  const double* vin = a.v[q];
-  double* pout = a.p[q ^ 1];
-  double* vout = a.v[q ^ 1];
-  const GatherP G{a.r, pin, vin, c->beta, c->omega, c->first};
+  const int state = c->sum.state, first = c->first;
+  const double beta = c->beta, omega = c->omega;
+  const int q = a.par;
+  const GatherP G{a.r, a.p[q], a.v[q], beta, omega, first};
   __shared__ typename Op::Lds L;
   __shared__ double red[NC_MAX * WAVES];
   const int nb = gridDim.x;
   const int lb = logical_block();
-  int rb, re;
-  brange(a, lb, rb, re);
+  const int row0 = lb * BS;
+  const int nrows = max(0, min(BS, a.n - row0));
+  const int t = threadIdx.x;
+  const bool mine = t < nrows;
+  const int row = mine ? row0 + t : 0;
+  const double rhv = a.rh[row];
+  typename Op::template Pre<GatherP> pre{};
+  if (nrows > 0) pre = op.load(row0, nrows, G);
+  const GatherP::Raw own = G.load(row);
+  asm volatile("" ::: "memory");   // every load above is issued before anything is combined
+  const double y = nrows > 0 ? op.finish(pre, row0, nrows, G, L) : 0.0;
+  const double pn = G.value(own);
+  if (state != ST_RUNNING) return;
+  mark_work(c, a.pslot, a.mat_bytes + 8.0 * a.n * (first ? 4 : 6));
   double acc[2] = {0.0, 0.0};
-  for (int row0 = rb; row0 < re; row0 += BS) {
-    const int nrows = min(BS, re - row0);
-    const double y = op.tile(row0, nrows, G, L);
-    if ((int)threadIdx.x < nrows) {
-      const int row = row0 + threadIdx.x;
-      pout[row] = G(row);
-      vout[row] = y;
-      acc[0] += a.rh[row] * y;
-      acc[1] += y * y;
-    }
+  if (mine) {
+    a.p[q ^ 1][row] = pn;
+    a.v[q ^ 1][row] = y;
+    acc[0] = rhv * y;
+    acc[1] = y * y;
   }
   block_partials<2>(acc, 2, a.partials, nb, lb, red);
 }
@@ -253,31 +270,36 @@ __global__ __launch_bounds__(BS) void k_bicg_fin_p(Ctl* c, const double* partial
 template <class Op>
 __global__ __launch_bounds__(BS) void k_bicg_s(BArgs a, Op op) {
   Ctl* c = a.ctl;
-  if (c->sum.state != ST_RUNNING) return;
-  mark_work(c, a.pslot, a.mat_bytes + 8.0 * a.n * (a.W ? 4 : 3));
-  const int q = c->parity ^ 1;   // the v written by P in this iteration
-  const GatherS G{a.r, a.v[q], c->alpha};
+  const int state = c->sum.state;
+  const double alpha = c->alpha;
+  const GatherS G{a.r, a.v[a.par ^ 1], alpha};   // the v written by P in this iteration
   __shared__ typename Op::Lds L;
   __shared__ double red[NC_MAX * WAVES];
   const int nb = gridDim.x;
   const int lb = logical_block();
-  int rb, re;
-  brange(a, lb, rb, re);
+  const int row0 = lb * BS;
+  const int nrows = max(0, min(BS, a.n - row0));
+  const int t = threadIdx.x;
+  const bool mine = t < nrows;
+  const int row = mine ? row0 + t : 0;
+  const double wv = a.W ? a.W[row] : 0.0;
+  typename Op::template Pre<GatherS> pre{};
+  if (nrows > 0) pre = op.load(row0, nrows, G);
+  const GatherS::Raw own = G.load(row);
+  asm volatile("" ::: "memory");
+  const double y = nrows > 0 ? op.finish(pre, row0, nrows, G, L) : 0.0;
+  const double sv = G.value(own);
+  if (state != ST_RUNNING) return;
+  mark_work(c, a.pslot, a.mat_bytes + 8.0 * a.n * (a.W ? 4 : 3));
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int row0 = rb; row0 < re; row0 += BS) {
-    const int nrows = min(BS, re - row0);
-    const double y = op.tile(row0, nrows, G, L);
-    if ((int)threadIdx.x < nrows) {
-      const int row = row0 + threadIdx.x;
-      const double s = G(row);
-      a.t[row] = y;
-      acc[0] += y * s;
-      acc[1] += y * y;
-      acc[2] += s * s;
-      if (a.W) {
-        const double ws = a.W[row] * s;
-        acc[3] += ws * ws;
-      }
+  if (mine) {
+    a.t[row] = y;
+    acc[0] = y * sv;
+    acc[1] = y * y;
+    acc[2] = sv * sv;
+    if (a.W) {
+      const double ws = wv * sv;
+      acc[3] = ws * ws;
     }
   }
   block_partials<4>(acc, 4, a.partials, nb, lb, red);
@@ -315,32 +337,35 @@ __global__ __launch_bounds__(BS) void k_bicg_fin_s(Ctl* c, const double* partial
 __global__ __launch_bounds__(BS) void k_bicg_u(BArgs a) {
   Ctl* c = a.ctl;
   const int st = c->sum.state;
-  if (st != ST_RUNNING && st != ST_HALF) return;
-  mark_work(c, a.pslot, 8.0 * a.n * (st == ST_HALF ? 3 : (a.W ? 9 : 8)));
-  const int q = c->parity ^ 1;
-  const double* p = a.p[q];
-  const double* v = a.v[q];
   const double alpha = c->alpha, omega = c->omega;
+  const int q = a.par ^ 1;   // p and v written by P in this iteration
   __shared__ double red[NC_MAX * WAVES];
   const int nb = gridDim.x;
   const int lb = logical_block();
-  int rb, re;
-  brange(a, lb, rb, re);
+  const int row0 = lb * BS;
+  const int t = threadIdx.x;
+  const bool mine = row0 + t < a.n;
+  const int row = mine ? row0 + t : 0;
+  const double pv = a.p[q][row], vv = a.v[q][row], xv = a.x[row], rv = a.r[row];
+  const double tv = a.t[row], rhv = a.rh[row], wv = a.W ? a.W[row] : 0.0;
+  asm volatile("" ::: "memory");
+  if (st != ST_RUNNING && st != ST_HALF) return;
+  mark_work(c, a.pslot, 8.0 * a.n * (st == ST_HALF ? 3 : (a.W ? 9 : 8)));
   if (st == ST_HALF) {
-    for (int row = rb + threadIdx.x; row < re; row += BS) a.x[row] = fma(alpha, p[row], a.x[row]);
+    if (mine) a.x[row] = fma(alpha, pv, xv);
     return;
   }
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int row = rb + threadIdx.x; row < re; row += BS) {
-    const double s = fma(-alpha, v[row], a.r[row]);
-    a.x[row] = fma(omega, s, fma(alpha, p[row], a.x[row]));
-    const double r = fma(-omega, a.t[row], s);
+  if (mine) {
+    const double s = fma(-alpha, vv, rv);
+    a.x[row] = fma(omega, s, fma(alpha, pv, xv));
+    const double r = fma(-omega, tv, s);
     a.r[row] = r;
-    acc[0] += a.rh[row] * r;
-    acc[1] += r * r;
+    acc[0] = rhv * r;
+    acc[1] = r * r;
     if (a.W) {
-      const double wr = a.W[row] * r;
-      acc[2] += wr * wr;
+      const double wr = wv * r;
+      acc[2] = wr * wr;
     }
   }
   block_partials<3>(acc, 3, a.partials, nb, lb, red);
@@ -349,7 +374,7 @@ __global__ __launch_bounds__(BS) void k_bicg_u(BArgs a) {
 // FU: stop test on ||W r|| (or the iteration cap), then rho, beta, or breakdown.
 __global__ __launch_bounds__(BS) void k_bicg_fin_u(Ctl* c, const double* partials, int nb,
                                                    int has_w) {
-  const int st = c->sum.state, iters = c->sum.iters, maxit = c->maxit, parity = c->parity;
+  const int st = c->sum.state, iters = c->sum.iters, maxit = c->maxit;
   const double ref = c->ref, tol = c->tol, eps_b = c->eps_b, rh_norm = c->rh_norm;
   const double rho = c->rho, alpha = c->alpha, omega = c->omega;
   __shared__ double out[8];
@@ -378,7 +403,6 @@ __global__ __launch_bounds__(BS) void k_bicg_fin_u(Ctl* c, const double* partial
   c->rho_old = rho;
   c->rho = rho_new;
   c->first = 0;
-  c->parity = parity ^ 1;
 }
 
 template <class Op>
@@ -394,10 +418,11 @@ static void launch_residual(const BArgs& a, const Op& op, int nb, const int* fla
 }
 
 template <class Op>
-static void launch_iteration(const BArgs& a, const Op& op, int nb, hipStream_t s) {
+static void launch_iteration(const BArgs& a, const Op& op, int nb, int par, hipStream_t s) {
   const int hw = a.W ? 1 : 0;
   const double* pt = a.partials;
   BArgs ax = a;
+  ax.par = par;
   ax.pslot = probe_slot(KC_BICG_P);
   if (ax.pslot >= 0) probe_begin(s);
   hipLaunchKernelGGL(k_bicg_p<Op>, dim3(nb), dim3(BS), 0, s, ax, op);
@@ -446,6 +471,7 @@ static SolveResult bicgstab_run(const Mat& A, const Op& op, const double* b, dou
   a.W = prm.weights;
   a.mat_bytes = A.bytes();
   a.pslot = -1;
+  a.par = 0;
   if (launch_clear_flags(Wk.flags, s) != hipSuccess) return bfail(-5);
   if (A.kind == MAT_CSR && launch_validate(A.csr, Wk.flags, s) != hipSuccess) return bfail(-5);
   hipLaunchKernelGGL(k_bicg_init_ctl, dim3(1), dim3(64), 0, s, Wk.ctl, prm.maxit, prm.tol,
@@ -467,23 +493,44 @@ static SolveResult bicgstab_run(const Mat& A, const Op& op, const double* b, dou
   int slot = 0;
   bool pending = false, done = false;
   const int k = prm.check_every;
+  Pacer pace{prm.tol, prm.maxit, k};
+  if ((long)2 * k >= prm.maxit) pace.cautious = true;
+  long launched = 0;   // iterations enqueued so far: gives each its buffer parity
+  auto chunk = [&](int count) {
+    for (int it = 0; it < count; ++it, ++launched)
+      launch_iteration(a, op, g.nb, (int)(launched & 1), s);
+    launch_residual(a, op, g.nb, Wk.flags, s);
+    return hipGetLastError() == hipSuccess;
+  };
+  auto record = [&](int sl) {
+    return hipMemcpyAsync(&hs[sl], &Wk.ctl->sum, sizeof(Summary), hipMemcpyDeviceToHost, s) ==
+               hipSuccess &&
+           hipEventRecord(ev[sl], s) == hipSuccess;
+  };
+  auto check = [&](int sl) {
+    if (hipEventSynchronize(ev[sl]) != hipSuccess) return false;
+    if (hs[sl].state == ST_DONE) done = true;
+    else pace.update(hs[sl].iters, hs[sl].relres_rec);
+    return true;
+  };
   // Every chunk either advances the iteration count or finishes; bound the loop generously.
   const long max_chunks = (long)prm.maxit * 4 + 16;
   for (long ch = 0; ch <= max_chunks && !done; ++ch) {
-    for (int it = 0; it < k; ++it) launch_iteration(a, op, g.nb, s);
-    launch_residual(a, op, g.nb, Wk.flags, s);
-    if (hipGetLastError() != hipSuccess ||
-        hipMemcpyAsync(&hs[slot], &Wk.ctl->sum, sizeof(Summary), hipMemcpyDeviceToHost, s) !=
-            hipSuccess ||
-        hipEventRecord(ev[slot], s) != hipSuccess) {
-      res.code = -5;
-      break;
+    if (!pace.cautious) {
+      // Enqueue a chunk, then read the previous chunk's status while it runs.
+      if (!chunk(k) || !record(slot)) { res.code = -5; break; }
+      if (pending && !check(slot ^ 1)) { res.code = -5; break; }
+      pending = true;
+      slot ^= 1;
+      continue;
     }
-    if (pending) {
-      if (hipEventSynchronize(ev[slot ^ 1]) != hipSuccess) { res.code = -5; break; }
-      if (hs[slot ^ 1].state == ST_DONE) done = true;
+    if (pending) {   // first wait for the chunk still in flight
+      if (!check(slot ^ 1)) { res.code = -5; break; }
+      pending = false;
+      if (done) break;
     }
-    pending = true;
+    // Near the end: half chunks, each waited for before the next is enqueued.
+    if (!chunk(k > 1 ? k / 2 : 1) || !record(slot) || !check(slot)) { res.code = -5; break; }
     slot ^= 1;
   }
   if (hipStreamSynchronize(s) != hipSuccess && res.code == 0) res.code = -5;

@@ -57,7 +57,6 @@ __global__ __launch_bounds__(64) void k_init_ctl(Ctl* c, int maxit, int m, doubl
   c->k = 0;
   c->claimed = 0;
   c->first = 1;
-  c->parity = 0;
   c->has_w = has_w;
   c->broke = 0;
   c->happy = 0;
@@ -217,7 +216,7 @@ __global__ __launch_bounds__(BS) void k_gmres_a(KArgs a, Op op, const double* __
   const int row = row0 + threadIdx.x;
   const bool mine = (int)threadIdx.x < nrows;
   const GatherX gx{V + (size_t)j * ldv};
-  typename Op::Pre pre{};
+  typename Op::template Pre<GatherX> pre{};
   if (nrows > 0) pre = op.load(row0, nrows, gx);
   const R rd(V, ldv, j + 1);
   double u[JM];
@@ -609,29 +608,59 @@ static SolveResult gmres_run(const Mat& A, const Op& op, const double* b, double
   int slot = 0;
   bool pending = false, done = false;
   const long max_cycles = (long)prm.maxit + 8;
-  for (long cyc = 0; cyc <= max_cycles && !done; ++cyc) {
-    for (int j = 0; j < m; ++j)
-      if (launch_step<R>(ka, op, g.nb, V, ldv, w, j, s) != hipSuccess) { res.code = -5; break; }
-    if (res.code) break;
+  Pacer pace{prm.tol, prm.maxit, m};
+  if ((long)2 * m >= prm.maxit) pace.cautious = true;
+  constexpr int kPiece = 10;   // steps per piece of a cycle in cautious mode
+  auto steps = [&](int j0, int j1) {
+    for (int j = j0; j < j1; ++j)
+      if (launch_step<R>(ka, op, g.nb, V, ldv, w, j, s) != hipSuccess) return false;
+    return true;
+  };
+  auto tail = [&]() {
     KArgs kx = ka;
     kx.pslot = probe_slot(KC_GMRES_X);
     if (kx.pslot >= 0) probe_begin(s);
     hipLaunchKernelGGL(k_gmres_x<R>, grid, block, 0, s, kx, (const double*)V, ldv, x);
     if (kx.pslot >= 0) probe_end(s, kx.pslot);
     launch_residual(ka, op, g.nb, b, x, prm.weights, V, W.flags, s);
-    if (hipGetLastError() != hipSuccess ||
-        hipMemcpyAsync(&hs[slot], &W.ctl->sum, sizeof(Summary), hipMemcpyDeviceToHost, s) !=
-            hipSuccess ||
-        hipEventRecord(ev[slot], s) != hipSuccess) {
-      res.code = -5;
-      break;
+    return hipGetLastError() == hipSuccess;
+  };
+  auto record = [&](int sl) {
+    return hipMemcpyAsync(&hs[sl], &W.ctl->sum, sizeof(Summary), hipMemcpyDeviceToHost, s) ==
+               hipSuccess &&
+           hipEventRecord(ev[sl], s) == hipSuccess;
+  };
+  // Reads the status recorded in slot sl; false on a device error.
+  auto check = [&](int sl) {
+    if (hipEventSynchronize(ev[sl]) != hipSuccess) return false;
+    if (hs[sl].state == ST_DONE) done = true;
+    else pace.update(hs[sl].iters, hs[sl].relres_true);
+    return true;
+  };
+  for (long cyc = 0; cyc <= max_cycles && !done; ++cyc) {
+    if (!pace.cautious) {
+      // Enqueue the whole cycle, then read the previous cycle's status while it runs.
+      if (!steps(0, m) || !tail() || !record(slot)) { res.code = -5; break; }
+      if (pending && !check(slot ^ 1)) { res.code = -5; break; }
+      pending = true;
+      slot ^= 1;
+      continue;
     }
-    // Check the previous cycle while this one runs.
-    if (pending) {
-      if (hipEventSynchronize(ev[slot ^ 1]) != hipSuccess) { res.code = -5; break; }
-      if (hs[slot ^ 1].state == ST_DONE) done = true;
+    if (pending) {   // first wait for the cycle still in flight
+      if (!check(slot ^ 1)) { res.code = -5; break; }
+      pending = false;
+      if (done) break;
     }
-    pending = true;
+    bool ok = true;
+    for (int j0 = 0; j0 < m && ok; j0 += kPiece) {
+      const int j1 = j0 + kPiece < m ? j0 + kPiece : m;
+      ok = steps(j0, j1);
+      if (!ok || j1 == m) break;
+      // stop enqueueing this cycle once it has ended (convergence claimed, breakdown, cap)
+      ok = record(slot) && hipEventSynchronize(ev[slot]) == hipSuccess;
+      if (ok && hs[slot].state != ST_RUNNING) break;
+    }
+    if (!ok || !tail() || !record(slot) || !check(slot)) { res.code = -5; break; }
     slot ^= 1;
   }
   if (hipStreamSynchronize(s) != hipSuccess && res.code == 0) res.code = -5;

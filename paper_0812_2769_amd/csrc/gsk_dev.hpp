@@ -68,7 +68,7 @@ struct Summary {
 struct Ctl {
   Summary sum;
   ProbeSlots probe;
-  int maxit, m, j, k, claimed, first, parity, has_w;
+  int maxit, m, j, k, claimed, first, has_w;
   int broke, happy, pad0, pad1;
   double tol, eps_b, ref, ratio;
   // Bi-CGSTAB scalars
@@ -313,8 +313,14 @@ __device__ inline double csr_tile(const int* __restrict__ row_ptr, const int* __
   return y;
 }
 
+// A gather supplies the source-vector entry of a column in two steps: load(col) fetches the
+// raw operands (Raw), value(raw) combines them; g(col) == value(load(col)). Splitting the two
+// lets a kernel issue every load before it combines anything.
 struct GatherX {
   const double* __restrict__ x;
+  typedef double Raw;
+  __device__ Raw load(int c) const { return x[c]; }
+  __device__ double value(Raw v) const { return v; }
   __device__ double operator()(int c) const { return x[c]; }
 };
 
@@ -334,15 +340,16 @@ struct CsrOp {
   const int* ci;
   const double* val;
   typedef TileLds Lds;
+  template <class G>
   struct Pre {};   // a CSR tile stages its nonzeros through LDS behind barriers: nothing ahead
   template <class G>
   __device__ double tile(int row0, int nrows, const G& g, Lds& L) const {
     return csr_tile(rp, ci, val, row0, nrows, g, L);
   }
   template <class G>
-  __device__ Pre load(int, int, const G&) const { return Pre{}; }
+  __device__ Pre<G> load(int, int, const G&) const { return Pre<G>{}; }
   template <class G>
-  __device__ double finish(const Pre&, int row0, int nrows, const G& g, Lds& L) const {
+  __device__ double finish(const Pre<G>&, int row0, int nrows, const G& g, Lds& L) const {
     return tile(row0, nrows, g, L);
   }
 };
@@ -364,13 +371,15 @@ struct StencilOp {
   // neighbour without a branch, so that all loads are in flight together: the neighbour index
   // is i + offset clamped to [0, n), a valid address whatever the position, and a position
   // outside the grid (or -z/+z in 2D) is flagged absent and its values are never used.
+  template <class G>
   struct Pre {
-    double c[7], x[7];
+    double c[7];
+    typename G::Raw x[7];
     unsigned present;
   };
   template <class G>
-  __device__ Pre load(int row0, int nrows, const G& g) const {
-    Pre p;
+  __device__ Pre<G> load(int row0, int nrows, const G& g) const {
+    Pre<G> p;
     const int t = threadIdx.x;
     const int i = row0 + min(t, nrows - 1);   // rows past the tile repeat its last row
     const int ix = i % nx;
@@ -388,7 +397,7 @@ struct StencilOp {
       const int plane = three ? q : (q == 0 ? 0 : q == 6 ? 4 : q - 1);
       p.c[q] = coef[(size_t)plane * n + i];
       const long long k = (long long)i + off[q];
-      p.x[q] = g((int)(k < 0 ? 0 : k >= n ? n - 1 : k));
+      p.x[q] = g.load((int)(k < 0 ? 0 : k >= n ? n - 1 : k));
       p.present |= in[q] ? 1u << q : 0u;
     }
     return p;
@@ -397,12 +406,12 @@ struct StencilOp {
   // leaves the sum unchanged (a sum that starts at +0.0 never becomes -0.0), so the result
   // equals the CSR product of the same matrix bit for bit.
   template <class G>
-  __device__ double finish(const Pre& p, int, int nrows, const G&, Lds&) const {
+  __device__ double finish(const Pre<G>& p, int, int nrows, const G& g, Lds&) const {
 #pragma clang fp contract(off)
     if ((int)threadIdx.x >= nrows) return 0.0;
     double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < 7; ++q) s += (p.present >> q) & 1u ? p.c[q] * p.x[q] : 0.0;
+    for (int q = 0; q < 7; ++q) s += (p.present >> q) & 1u ? p.c[q] * g.value(p.x[q]) : 0.0;
     return s;
   }
   template <class G>

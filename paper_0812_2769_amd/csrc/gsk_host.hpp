@@ -103,6 +103,30 @@ SolveResult bicgstab_solve(const Mat& A, const double* b, double* x, const Solve
 // Small pinned host buffer for status read-back (one per thread, allocated on first use).
 Summary* pinned_summaries();
 
+// How far ahead of the device the host enqueues. The solvers enqueue a cycle (GMRES) or a
+// chunk of iterations (Bi-CGSTAB) without waiting, one ahead of the status the host has read;
+// launches enqueued past the end of a solve find it finished and store nothing, but they
+// still take time. Once the residual history predicts that the work in flight may finish the
+// solve (the last relative residual times the last reduction factor is within `margin` of
+// the tolerance), or the iteration cap is near, the pacer turns cautious and stays so: the
+// host then waits for each result before it enqueues more, and enqueues in smaller pieces.
+struct Pacer {
+  double tol;
+  long maxit;
+  int span;               // iterations one cycle or chunk can add
+  double margin = 4.0;
+  double last = -1.0;
+  bool cautious = false;
+  void update(int iters, double relres) {
+    if (last > 0.0 && relres > 0.0) {
+      const double ratio = relres < last ? relres / last : 1.0;
+      if (relres * ratio < margin * tol) cautious = true;
+    }
+    if (relres < margin * tol || (long)iters + 2L * span >= maxit) cautious = true;
+    last = relres;
+  }
+};
+
 // Measurement hook (gsk_probe_begin / gsk_probe_end). While a kernel class is selected, every
 // sample_every-th launch of that class gets a slot number: the host brackets it with a pair
 // of HIP events and the kernel records its algorithmic bytes in the slot if it did work. At
