@@ -42,8 +42,8 @@ TOL = 1e-10
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; FETCH_SIZE scaled by 2.000 and WRITE_SIZE by
 # 1.000 from a plain 512 MiB copy), recorded with the hash of the kernel sources they were
 # measured on. A source change makes the figure stale and it is reported as null.
-TRAFFIC = {"gmres_a": {"bytes_per_launch": 110244984, "grid": 80,
-                       "sources_sha256_16": "bcf25e856ee3c518"}}
+TRAFFIC = {"gmres_a": {"bytes_per_launch": 96267111, "grid": 80, "operator": "stencil",
+                       "sources_sha256_16": "27262f17b66e070e"}}
 TRAFFIC_SOURCES = ["paper_0812_2769_amd/csrc/gmres.hip", "paper_0812_2769_amd/csrc/gsk_dev.hpp",
                    "paper_0812_2769_amd/csrc/gsk_host.hpp"]
 
