@@ -364,6 +364,156 @@ done:
 }
 
 /* ---------------------------------------------------------------------------------------
+ * Mixed-precision restarted GMRES(m): classical iterative refinement (not in the paper,
+ * which solves in FP64 throughout) in which every correction is one GMRES(m) cycle whose
+ * data are stored in single precision.
+ *   1. r = b - A x in double with the double matrix; stop if ||W r|| / ||W r0|| < tol.
+ *   2. One GMRES(m) cycle on A d = r (started from d = 0) in which the matrix values, the
+ *      basis vectors and the work vector are stored as float: every stored value is rounded
+ *      to float, and each product, dot product and update is computed in double from the
+ *      stored floats. The Hessenberg matrix, the Givens rotations, g and y stay double. The
+ *      cycle ends early when its estimate |g_{j+1}| (in the norm of the stored r) times
+ *      ||W r|| / ||r_stored|| / ||W r0|| drops below tol, on a happy breakdown, or at maxit.
+ *   3. x = x + V_k y in double, and back to 1.
+ * Stagnation: a cycle that claimed convergence which step 1 does not confirm counts as a
+ * failure only if it did not halve the relative true residual; three failures in a row end
+ * the solve as STAGNATED.
+ * ------------------------------------------------------------------------------------- */
+static double fdot(int n, const float* x, const float* y) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += (double)x[i] * (double)y[i];
+    return s;
+}
+
+int orc_gmres_ir(int n, const int* rp, const int* ci, const double* val, const double* b,
+                 double* x, int m, double tol, int maxit, double eps_b, const double* wts,
+                 int* info_i, double* info_d) {
+    if (n <= 0 || m <= 0 || maxit < 0 || !(tol > 0.0)) return ORC_ERR_ARG;
+    size_t nn = (size_t)n;
+    int nnz = rp[n];
+    float* fval = (float*)malloc(sizeof(float) * (size_t)(nnz > 0 ? nnz : 1));
+    float* V = (float*)malloc(sizeof(float) * nn * (size_t)(m + 1));
+    float* w = (float*)malloc(sizeof(float) * nn);
+    double* H = (double*)malloc(sizeof(double) * (size_t)(m + 1) * (size_t)m);
+    double* r = (double*)malloc(sizeof(double) * nn);
+    double* c = (double*)malloc(sizeof(double) * (size_t)(m + 1));
+    double* cs = (double*)malloc(sizeof(double) * (size_t)m);
+    double* sn = (double*)malloc(sizeof(double) * (size_t)m);
+    double* g = (double*)malloc(sizeof(double) * (size_t)(m + 1));
+    double* y = (double*)malloc(sizeof(double) * (size_t)m);
+    if (!fval || !V || !w || !H || !r || !c || !cs || !sn || !g || !y) {
+        free(fval); free(V); free(w); free(H); free(r); free(c); free(cs); free(sn); free(g);
+        free(y);
+        return ORC_ERR_ALLOC;
+    }
+    for (int k = 0; k < nnz; ++k) fval[k] = (float)val[k];
+    int iters = 0, restarts = 0, status = ORC_MAXIT, fails = 0, brk = 0;
+    double est = 1.0, relres_true = 1.0, last = 1.0;
+    const int ldh = m + 1;
+
+    residual(n, rp, ci, val, b, x, r);
+    double ref = wnrm2(n, wts, r);
+    if (ref == 0.0) {
+        status = ORC_CONVERGED;
+        est = 0.0;
+        relres_true = 0.0;
+        goto done;
+    }
+    if (maxit == 0) goto done;
+    for (;;) {
+        /* step 2: one cycle on A d = r with float storage */
+        for (int i = 0; i < n; ++i) w[i] = (float)r[i];            /* stored right-hand side */
+        double beta = sqrt(fdot(n, w, w));
+        double ratio = wnrm2(n, wts, r) / beta;
+        last = wnrm2(n, wts, r) / ref;
+        for (int i = 0; i < n; ++i) V[i] = (float)((double)w[i] / beta);
+        for (int i = 0; i <= m; ++i) g[i] = 0.0;
+        g[0] = beta;
+        int k = 0, claimed = 0;
+        for (int j = 0; j < m; ++j) {
+            /* w = A v_j with the float matrix, sums in double, stored as float */
+            const float* vj = V + (size_t)j * n;
+            for (int row = 0; row < n; ++row) {
+                double s = 0.0;
+                for (int q = rp[row]; q < rp[row + 1]; ++q)
+                    s += (double)fval[q] * (double)vj[ci[q]];
+                w[row] = (float)s;
+            }
+            double nw = sqrt(fdot(n, w, w));
+            double* h = H + (size_t)j * ldh;
+            for (int i = 0; i <= j + 1; ++i) h[i] = 0.0;
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int i = 0; i <= j; ++i) c[i] = fdot(n, V + (size_t)i * n, w);
+                for (int row = 0; row < n; ++row) {
+                    double t = (double)w[row];
+                    for (int i = 0; i <= j; ++i) t -= c[i] * (double)V[(size_t)i * n + row];
+                    w[row] = (float)t;
+                }
+                for (int i = 0; i <= j; ++i) h[i] += c[i];
+            }
+            h[j + 1] = sqrt(fdot(n, w, w));
+            int happy = h[j + 1] <= eps_b * nw;
+            if (!happy) {
+                float* vn = V + (size_t)(j + 1) * n;
+                for (int row = 0; row < n; ++row) vn[row] = (float)((double)w[row] / h[j + 1]);
+            }
+            ++iters;
+            for (int i = 0; i < j; ++i) {
+                double t = cs[i] * h[i] + sn[i] * h[i + 1];
+                h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+                h[i] = t;
+            }
+            double d = hypot(h[j], h[j + 1]);
+            if (d == 0.0) { status = ORC_BREAKDOWN; brk = 4; k = j; goto update; }
+            cs[j] = h[j] / d;
+            sn[j] = h[j + 1] / d;
+            h[j] = d;
+            h[j + 1] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            est = fabs(g[j + 1]) * ratio / ref;
+            k = j + 1;
+            if (est < tol) { claimed = 1; break; }
+            if (happy) { claimed = 1; break; }
+            if (iters >= maxit) break;
+        }
+    update:
+        /* step 3: x = x + V_k y in double */
+        for (int i = k - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int l = i + 1; l < k; ++l) s -= H[(size_t)l * ldh + i] * y[l];
+            y[i] = s / H[(size_t)i * ldh + i];
+        }
+        for (int row = 0; row < n; ++row) {
+            double d = 0.0;
+            for (int l = 0; l < k; ++l) d += y[l] * (double)V[(size_t)l * n + row];
+            x[row] = x[row] + d;
+        }
+        /* step 1 of the next refinement step */
+        residual(n, rp, ci, val, b, x, r);
+        relres_true = wnrm2(n, wts, r) / ref;
+        if (status == ORC_BREAKDOWN) goto done;
+        if (relres_true < tol) { status = ORC_CONVERGED; goto done; }
+        if (iters >= maxit) { status = ORC_MAXIT; goto done; }
+        if (claimed && !(relres_true < 0.5 * last)) {
+            ++fails;
+            if (fails >= 3) { status = ORC_STAGNATED; goto done; }
+        } else {
+            fails = 0;
+        }
+        ++restarts;
+    }
+done:
+    if (info_i) {
+        info_i[0] = iters; info_i[1] = restarts; info_i[2] = status; info_i[3] = 0;
+        info_i[4] = fails; info_i[5] = brk;
+    }
+    if (info_d) { info_d[0] = est; info_d[1] = relres_true; }
+    free(fval); free(V); free(w); free(H); free(r); free(c); free(cs); free(sn); free(g); free(y);
+    return ORC_OK;
+}
+
+/* ---------------------------------------------------------------------------------------
  * Bi-CGSTAB on A x = b (van der Vorst), optionally right-preconditioned by ILU(0).
  * x holds x0 on entry and the result on return. hist (nullable, capacity maxit) receives
  * ||W r||/ref (or ||W s||/ref at a half-step exit) after every iteration.
