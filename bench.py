@@ -14,6 +14,14 @@ residual below 1e-10 (measured on the GS(2)-scaled system), for p in {2, 1} and 
 Prints one JSON line. Also reports iterations/s, per-variant p50/p99 latency, the achieved
 bandwidth of the dominant kernel against the HBM roofline, and the CPU oracle's rate on a
 bounded sample of the same work.
+
+Other modes (not the default line):
+  --precision mixed   the GMRES(30) solves use gsk_gmres_mixed (FP32 Arnoldi cycles, FP64
+                      restarts) at the same tolerance; Bi-CGSTAB stays FP64.
+  --workload config3  the 160^3 checkerboard system (n = 4,096,000): GS(2) then GMRES(30)
+                      bounded at 600 Arnoldi steps per solve (restarted GMRES(30) does not reach
+                      the configuration's 1e-8 within the 10,000-step cap); `value` is Arnoldi
+                      steps per second.
 """
 import argparse
 import json
@@ -37,6 +45,7 @@ KERNEL_NAMES = {"gmres_a": "k_gmres_a (CSR product + CGS2 pass-1 dots)",
                 "residual": "k_*_residual (true residual)",
                 "gmres_x": "k_gmres_x (x += V y)"}
 TOL = 1e-10
+METRIC_C3 = "Arnoldi steps/s, GMRES(30) on the 160^3 checkerboard system"
 
 # Fabric (HBM + Infinity Cache) bytes per working launch of a kernel class, from two
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; FETCH_SIZE scaled by 2.000 and WRITE_SIZE by
@@ -65,7 +74,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--grid", type=int, default=80, help="N of the N^3 grid (default 80)")
+    ap.add_argument("--workload", choices=["config2", "config3"], default="config2")
+    ap.add_argument("--grid", type=int, default=0,
+                    help="N of the N^3 grid (default 80 for config2, 160 for config3)")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
+                    help="GMRES solves in FP64 (default) or mixed precision")
+    ap.add_argument("--c3-steps", type=int, default=600,
+                    help="Arnoldi steps per config3 solve (default 600)")
     ap.add_argument("--operator", choices=["stencil", "csr"], default="stencil",
                     help="matrix form the solvers read: 7-point coefficient planes packed from "
                          "the scaled CSR matrix inside each solve (default), or the CSR matrix")
@@ -95,14 +110,14 @@ def pct(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def cpu_baseline(P, gpu_iters, sample_iters):
-    """Time the FP64 oracle (single thread) on a bounded sample of the step: GS(p) in full and
+def cpu_baseline(P, gpu_iters, sample_iters, variants, tol, precision):
+    """Time the oracle (single thread) on a bounded sample of the step: GS(p) in full and
     `sample_iters` iterations of each solver; scale to one full step with the iteration
-    counts of the GPU run (the same algorithm takes the same number of iterations)."""
+    counts of the GPU run (the same algorithm takes about the same number of iterations)."""
     import oracle
     t_total = 0.0
     detail = {}
-    for p, method in VARIANTS:
+    for p, method in variants:
         t0 = time.perf_counter()
         vo, bo, nrm, w = oracle.gs_scale(P, P.b, p)
         t_gs = time.perf_counter() - t0
@@ -111,20 +126,22 @@ def cpu_baseline(P, gpu_iters, sample_iters):
         W = None if p == 2 else w
         t0 = time.perf_counter()
         if method == "bicgstab":
-            _, info = oracle.bicgstab(S, bo, tol=TOL, weights=W, maxit=sample_iters)
+            _, info = oracle.bicgstab(S, bo, tol=tol, weights=W, maxit=sample_iters)
+        elif precision == "mixed":
+            _, info = oracle.gmres_ir(S, bo, m=30, tol=tol, weights=W, maxit=sample_iters)
         else:
-            _, info = oracle.gmres(S, bo, m=30, tol=TOL, weights=W, maxit=sample_iters)
+            _, info = oracle.gmres(S, bo, m=30, tol=tol, weights=W, maxit=sample_iters)
         t_it = (time.perf_counter() - t0) / max(info.iters, 1)
         key = f"gs{p}_{method}"
         est = t_gs + t_it * gpu_iters[key]
         detail[key] = {"gs_s": round(t_gs, 4), "s_per_iter": round(t_it, 5),
                        "sampled_iters": info.iters, "est_solve_s": round(est, 3)}
         t_total += est
-    return {"value": round(len(VARIANTS) / t_total, 4), "unit": "solves/s", "cores": 1,
+    return {"value": round(len(variants) / t_total, 4), "unit": "solves/s", "cores": 1,
             "kind": "oracle",
             "sample": (f"GS(p) in full plus the first {sample_iters} iterations of each of the "
-                       f"4 solves, single-threaded FP64 C oracle; seconds/iteration scaled by "
-                       f"the GPU run's iteration counts"),
+                       f"{len(variants)} solves, single-threaded C oracle; seconds/iteration "
+                       f"scaled by the GPU run's iteration counts"),
             "per_variant": detail}
 
 
@@ -153,8 +170,13 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    c3 = args.workload == "config3"
+    grid = args.grid or (160 if c3 else 80)
+    variants = [(2, "gmres30")] if c3 else VARIANTS
+    tol = 1e-8 if c3 else TOL
+    maxit = args.c3_steps if c3 else None
     t0 = time.perf_counter()
-    P = problems.config2(args.grid)
+    P = problems.config3(grid) if c3 else problems.config2(grid)
     print(f"bench: generated {P.name} n={P.n} nnz={P.nnz} in {time.perf_counter() - t0:.1f}s",
           file=sys.stderr, flush=True)
     A = gsk.CsrMatrix.from_problem(P, dev)
@@ -166,7 +188,8 @@ def main():
     weights = torch.empty(n, dtype=torch.float64, device=dev)
     x = torch.empty(n, dtype=torch.float64, device=dev)
     ws_gs = gsk.workspace(gsk.METHOD_GS, n, 0, dev)
-    ws_gm = gsk.workspace(gsk.METHOD_GMRES, n, 30, dev)
+    mixed = args.precision == "mixed"
+    ws_gm = gsk.workspace(gsk.METHOD_GMRES_MIXED if mixed else gsk.METHOD_GMRES, n, 30, dev)
     ws_bi = gsk.workspace(gsk.METHOD_BICGSTAB, n, 0, dev)
     As = A.with_values(val_s)
     c_A = A.c_struct()
@@ -176,11 +199,11 @@ def main():
     stencil = args.operator == "stencil"
     if stencil:
         coef = torch.empty(7 * n, dtype=torch.float64, device=dev)
-        Ss = gsk.StencilMatrix(args.grid, args.grid, args.grid, coef)
+        Ss = gsk.StencilMatrix(grid, grid, grid, coef)
     M = Ss if stencil else As
 
     def pack():
-        rc = gsk.lib.gsk_stencil_from_csr(ctypes.byref(c_As), args.grid, args.grid, args.grid,
+        rc = gsk.lib.gsk_stencil_from_csr(ctypes.byref(c_As), grid, grid, grid,
                                           coef.data_ptr(), ws_gs.data_ptr(), ws_gs.numel(),
                                           stream)
         if rc != 0:
@@ -199,17 +222,18 @@ def main():
             pack()
         w = None if p == 2 else weights
         if method == "bicgstab":
-            return gsk.bicgstab(M, b_s, tol=TOL, stop_weights=w, ws=ws_bi, x_out=x)[1]
-        return gsk.gmres(M, b_s, m=30, tol=TOL, stop_weights=w, ws=ws_gm, x_out=x)[1]
+            return gsk.bicgstab(M, b_s, tol=tol, stop_weights=w, ws=ws_bi, x_out=x)[1]
+        fn = gsk.gmres_mixed if mixed else gsk.gmres
+        return fn(M, b_s, m=30, tol=tol, maxit=maxit, stop_weights=w, ws=ws_gm, x_out=x)[1]
 
     def step(lat, infos):
-        for p, method in VARIANTS:
+        for p, method in variants:
             t = time.perf_counter()
             info = solve(p, method)
             lat[f"gs{p}_{method}"].append(time.perf_counter() - t)
             infos[f"gs{p}_{method}"] = info
 
-    lat = {f"gs{p}_{m}": [] for p, m in VARIANTS}
+    lat = {f"gs{p}_{m}": [] for p, m in variants}
     infos = {}
     for i in range(args.warmup):
         step({k: [] for k in lat}, infos)
@@ -241,10 +265,10 @@ def main():
             kernels[cls] = achieved(gsk.probe_end())
 
     for key, info in infos.items():
-        if info.status != gsk.CONVERGED:
+        if info.status != gsk.CONVERGED and not c3:
             print(f"bench: WARNING {key} ended {info.status_name} at relres "
                   f"{info.relres_true:.2e}", file=sys.stderr, flush=True)
-    solves = len(VARIANTS) * args.steps
+    solves = len(variants) * args.steps
     iters_step = sum(i.iters for i in infos.values())
     per_variant = {k: {"iters": infos[k].iters, "status": infos[k].status_name,
                        "relres_true": infos[k].relres_true,
@@ -252,9 +276,9 @@ def main():
                        "p99_ms": round(1e3 * pct(lat[k], 0.99), 3)} for k in lat}
     all_lat = [v for k in lat for v in lat[k]]
     out = {
-        "metric": METRIC,
-        "value": round(solves / elapsed, 4),
-        "unit": "solves/s",
+        "metric": METRIC_C3 if c3 else METRIC,
+        "value": round((iters_step * args.steps if c3 else solves) / elapsed, 4),
+        "unit": "Arnoldi steps/s" if c3 else "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -262,12 +286,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32 inner / f64 restarts" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": f"config2: {args.grid}^3 7-point convection-diffusion, 8 random "
-                               f"slabs, FP64 CSR; GS(1|2) x (Bi-CGSTAB | GMRES(30)), tol 1e-10",
-                   "n": n, "nnz": P.nnz, "solves_per_step": len(VARIANTS), "tol": TOL,
-                   "operator": args.operator},
+        "config": {"workload": (
+                       f"config3: {grid}^3 7-point, 16^3-block checkerboard a in {{1, 1e4}}, "
+                       f"FP64 CSR; GS(2) x GMRES(30) bounded at {args.c3_steps} steps" if c3 else
+                       f"config2: {grid}^3 7-point convection-diffusion, 8 random slabs, FP64 "
+                       f"CSR; GS(1|2) x (Bi-CGSTAB | GMRES(30)), tol 1e-10"),
+                   "n": n, "nnz": P.nnz, "solves_per_step": len(variants), "tol": tol,
+                   "operator": args.operator, "precision": args.precision},
         "iterations_per_s": round(iters_step * args.steps / elapsed, 1),
         "latency_p50_ms": round(1e3 * pct(all_lat, 0.5), 3),
         "latency_p99_ms": round(1e3 * pct(all_lat, 0.99), 3),
@@ -281,7 +308,8 @@ def main():
         out["roofline"] = {
             "bound": "hbm", "achieved": a["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(a["achieved_GBs"] / HBM_PEAK_GBS, 4),
-            "traffic": traffic_for(args.probe, args.grid, args.operator),
+            "traffic": (traffic_for(args.probe, grid, args.operator)
+                        if not mixed and not c3 else None),
             "kernel": KERNEL_NAMES.get(args.probe), "avg_launch_us": a["avg_launch_us"],
             "bytes_per_launch": a["bytes_per_launch"], "timed_launches": a["timed_launches"],
             "busy_launches": a["busy_launches"], "sample_every": args.probe_every,
@@ -291,7 +319,8 @@ def main():
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(P, {k: infos[k].iters for k in infos},
-                                           args.cpu_sample_iters)
+                                           args.cpu_sample_iters if not c3 else 10, variants,
+                                           tol, args.precision)
     print(json.dumps(out), flush=True)
 
 

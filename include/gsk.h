@@ -63,6 +63,7 @@ extern "C" {
 #define GSK_METHOD_GMRES 1
 #define GSK_METHOD_BICGSTAB 2
 #define GSK_METHOD_ARNOLDI 3
+#define GSK_METHOD_GMRES_MIXED 4
 
 /* Largest restart length supported by gsk_gmres / gsk_arnoldi. */
 #define GSK_MAX_RESTART 64
@@ -129,10 +130,17 @@ typedef struct gsk_info {
 void gsk_default_options(gsk_options* opt);
 
 /* Bytes of device workspace an entry point needs for a system of n rows (m: restart length
- * for GSK_METHOD_GMRES / GSK_METHOD_ARNOLDI, ignored otherwise). Returns 0 for invalid
- * arguments. The workspace must be 256-byte aligned; its contents need no initialisation
- * and are garbage afterwards. */
+ * for GSK_METHOD_GMRES / GSK_METHOD_GMRES_MIXED / GSK_METHOD_ARNOLDI, ignored otherwise).
+ * For GSK_METHOD_GMRES_MIXED the figure assumes a 7-point stencil matrix (its FP32 copy
+ * lives in the workspace); use gsk_workspace_bytes_for for any other matrix. Returns 0 for
+ * invalid arguments. The workspace must be 256-byte aligned; its contents need no
+ * initialisation and are garbage afterwards. */
 size_t gsk_workspace_bytes(int32_t method, int32_t n, int32_t m);
+
+/* Exact workspace bytes of `method` for matrix *A (host-side checks only; nothing is read
+ * from device memory). Returns 0, with the reason in gsk_last_error(), for invalid
+ * arguments. */
+size_t gsk_workspace_bytes_for(const gsk_matrix* A, int32_t method, int32_t m);
 
 /*
  * GS(p) geometric scaling (section 1; section 2, eq. (2)): for each row i,
@@ -213,6 +221,26 @@ int gsk_gmres(const gsk_matrix* A, const double* b, double* x, int32_t m, double
               const gsk_options* opt, gsk_info* info, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * GMRES(m) with FP32 Arnoldi cycles and FP64 restarts: iterative refinement in which each
+ * correction is one GMRES(m) cycle. The paper's solver is FP64 GMRES (section 2); this form
+ * keeps its algorithm and stop test and changes only the storage precision inside a cycle.
+ *   - Inside a cycle the matrix values (an FP32 copy the call makes in the workspace), the
+ *     basis and w are stored in FP32; products, dot products, the Hessenberg matrix, the
+ *     Givens rotations and y are computed in FP64.
+ *   - At every restart r = b - A x is computed in FP64 with the caller's matrix and x is
+ *     updated in FP64, so the final accuracy is that of FP64 GMRES; `tol` and the stop test
+ *     are those of gsk_gmres, verified in FP64.
+ *   - A cycle whose FP32 estimate claims convergence that the FP64 residual does not confirm
+ *     counts towards STAGNATED only if it did not halve the true residual.
+ * Arguments as for gsk_gmres; workspace gsk_workspace_bytes_for(A, GSK_METHOD_GMRES_MIXED, m)
+ * bytes (FP32 matrix copy, basis and w: about half the FP64 solver's). info->iters counts
+ * Arnoldi steps and info->restarts the FP64 restarts. Synchronises `stream`.
+ */
+int gsk_gmres_mixed(const gsk_matrix* A, const double* b, double* x, int32_t m, double tol,
+                    const gsk_options* opt, gsk_info* info, void* ws, size_t ws_bytes,
+                    void* stream);
+
+/*
  * Bi-CGSTAB (section 2: van der Vorst's Bi-CGSTAB) on A x = b, shadow residual r^ = r0.
  * Arguments as for gsk_gmres without m; workspace gsk_workspace_bytes(GSK_METHOD_BICGSTAB,
  * n, 0). All scalars (rho, alpha, omega, beta) stay on the device; the host reads a status
@@ -242,7 +270,10 @@ int gsk_bicgstab(const gsk_matrix* A, const double* b, double* x, double tol,
  *   RESIDUAL  12 nnz + 4 (n+1) + 24..40 n    CSR, x b, write r (and r^ in Bi-CGSTAB), weights
  *   GMRES_X   8 n (k+2)                      k basis columns, read and write x
  * For a stencil matrix the matrix term 12 nnz + 4 (n+1) becomes 8 n per coefficient plane
- * (40 n for 5 points, 56 n for 7).
+ * (40 n for 5 points, 56 n for 7). In gsk_gmres_mixed the basis and w terms count 4 bytes per
+ * value, the GMRES_A matrix term is that of the FP32 copy (4 n per plane, or 8 nnz + 4 (n+1)),
+ * GMRES_X moves 4 n k + 16 n, and RESIDUAL (FP64 matrix, x, b, FP32 u_0) moves the FP64
+ * matrix term + 20 n (+ 8 n with weights).
  * Process-wide; not for concurrent use from several host threads. gsk_probe_end
  * synchronises the device.
  */

@@ -271,9 +271,20 @@ size_t workspace_bytes(int method, int n, int m) {
       return head + ld;
     case GSK_METHOD_BICGSTAB:
       return head + 7 * ld;
+    case GSK_METHOD_GMRES_MIXED:   // sized for a 7-point stencil matrix
+      if (m < 1 || m > GSK_MAX_RESTART) return 0;
+      return head + align256(sizeof(float) * 7 * vec_ld(n)) +
+             (size_t)(m + 2) * vec_ld(n) * sizeof(float);
     default:
       return 0;
   }
+}
+
+size_t workspace_bytes_for(const Mat& A, int method, int m) {
+  if (method != GSK_METHOD_GMRES_MIXED) return workspace_bytes(method, A.n, m);
+  if (A.n < 1 || m < 1 || m > GSK_MAX_RESTART) return 0;
+  return head_bytes(A.n) + align256(sizeof(float) * mixed_matrix_floats(A)) +
+         (size_t)(m + 2) * vec_ld(A.n) * sizeof(float);
 }
 
 }  // namespace gsk
@@ -294,6 +305,13 @@ void gsk_default_options(gsk_options* opt) {
 
 size_t gsk_workspace_bytes(int32_t method, int32_t n, int32_t m) {
   return gsk::workspace_bytes(method, n, m);
+}
+
+size_t gsk_workspace_bytes_for(const gsk_matrix* A, int32_t method, int32_t m) {
+  g_err.clear();
+  Mat M;
+  if (check_matrix(A, M)) return 0;   // the reason is left in gsk_last_error()
+  return gsk::workspace_bytes_for(M, method, m);
 }
 
 int gsk_version(void) { return GSK_VERSION; }
@@ -440,7 +458,7 @@ int gsk_arnoldi(const gsk_matrix* A, const double* r0, int32_t m, double* V, int
   return GSK_OK;
 }
 
-static int solve_common(bool is_gmres, const gsk_matrix* A, const double* b, double* x,
+static int solve_common(int method, const gsk_matrix* A, const double* b, double* x,
                         int32_t m, double tol, const gsk_options* opt, gsk_info* info, void* ws,
                         size_t ws_bytes, void* stream) {
   g_err.clear();
@@ -448,17 +466,18 @@ static int solve_common(bool is_gmres, const gsk_matrix* A, const double* b, dou
   int rc = check_matrix(A, M);
   if (rc) return rc;
   if (!b || !x) return set_err(GSK_ERR_INVALID_ARG, "b or x is NULL");
+  const bool is_gmres = method != GSK_METHOD_BICGSTAB;
   if (is_gmres && (m < 1 || m > GSK_MAX_RESTART))
     return set_err(GSK_ERR_INVALID_ARG, "m = %d must be in [1, %d]", (int)m, GSK_MAX_RESTART);
   SolveParams prm;
   rc = params_from(opt, prm, tol);
   if (rc) return rc;
-  rc = check_ws(ws, ws_bytes,
-                gsk::workspace_bytes(is_gmres ? GSK_METHOD_GMRES : GSK_METHOD_BICGSTAB, M.n, m));
+  rc = check_ws(ws, ws_bytes, gsk::workspace_bytes_for(M, method, m));
   if (rc) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  SolveResult r = is_gmres ? gmres_solve(M, b, x, m, prm, ws, s)
-                           : bicgstab_solve(M, b, x, prm, ws, s);
+  SolveResult r = method == GSK_METHOD_GMRES         ? gmres_solve(M, b, x, m, prm, ws, s)
+                  : method == GSK_METHOD_GMRES_MIXED ? gmres_mixed_solve(M, b, x, m, prm, ws, s)
+                                                     : bicgstab_solve(M, b, x, prm, ws, s);
   if (r.code == -1)
     return set_err(GSK_ERR_INVALID_ARG,
                    "CSR structure invalid (row_ptr not monotone from 0 to nnz, or a column "
@@ -471,13 +490,19 @@ static int solve_common(bool is_gmres, const gsk_matrix* A, const double* b, dou
 
 int gsk_gmres(const gsk_matrix* A, const double* b, double* x, int32_t m, double tol,
               const gsk_options* opt, gsk_info* info, void* ws, size_t ws_bytes, void* stream) {
-  return solve_common(true, A, b, x, m, tol, opt, info, ws, ws_bytes, stream);
+  return solve_common(GSK_METHOD_GMRES, A, b, x, m, tol, opt, info, ws, ws_bytes, stream);
+}
+
+int gsk_gmres_mixed(const gsk_matrix* A, const double* b, double* x, int32_t m, double tol,
+                    const gsk_options* opt, gsk_info* info, void* ws, size_t ws_bytes,
+                    void* stream) {
+  return solve_common(GSK_METHOD_GMRES_MIXED, A, b, x, m, tol, opt, info, ws, ws_bytes, stream);
 }
 
 int gsk_bicgstab(const gsk_matrix* A, const double* b, double* x, double tol,
                  const gsk_options* opt, gsk_info* info, void* ws, size_t ws_bytes,
                  void* stream) {
-  return solve_common(false, A, b, x, 0, tol, opt, info, ws, ws_bytes, stream);
+  return solve_common(GSK_METHOD_BICGSTAB, A, b, x, 0, tol, opt, info, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

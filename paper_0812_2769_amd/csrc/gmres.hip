@@ -21,9 +21,18 @@
 // recomputes the true residual r = b - A x, which either ends the solve or starts the next
 // cycle with u_0 = r.
 //
-// Every launch first checks the device-resident state and returns at once if the solve has
-// moved on, so a whole cycle can be enqueued (or replayed from a graph) blindly; the host
-// reads a small summary once per cycle.
+// Every launch checks the device-resident state and stores nothing if the solve has moved on,
+// so a whole cycle can be enqueued blindly; the host reads a small summary once per cycle.
+//
+// Storage precision. The kernels are templated on T, the type the basis and w are stored in,
+// and on the operator of the inner product. With T = double and the caller's matrix this is
+// the FP64 solver. With T = float and an FP32 copy of the matrix it is the mixed-precision
+// solver (gsk_gmres_mixed): each cycle's Arnoldi process reads and writes FP32 data while all
+// arithmetic, the Hessenberg matrix, the rotations and y stay FP64, and every restart
+// computes the true residual r = b - A x and updates x in FP64 with the caller's matrix. That
+// is iterative refinement with one GMRES(m) cycle per correction. Every value a kernel uses
+// after storing it is the stored (rounded) value, so the Arnoldi relation holds for the data
+// in memory.
 #include "gsk_host.hpp"
 
 namespace gsk {
@@ -33,8 +42,13 @@ struct KArgs {
   int rpb;
   Ctl* ctl;
   double* partials;
-  double mat_bytes;   // algorithmic bytes of one read of A (CSR: 12 nnz + 4 (n+1))
-  int pslot;          // measurement slot of this launch, or -1
+  double mat_bytes;     // algorithmic bytes of one read of A (CSR: 12 nnz + 4 (n+1))
+  int pslot;            // measurement slot of this launch, or -1
+  double inner_bytes;   // bytes of one read of the matrix the Arnoldi product uses
+  // 0.0, passed at run time: the value of a basis entry that is not loaded. As a constant
+  // the compiler would move the later FP32 -> FP64 widening into the conditional load's
+  // block, which makes each load wait for its data before the next one is issued.
+  double zero;
 };
 
 __global__ __launch_bounds__(64) void k_init_ctl(Ctl* c, int maxit, int m, double tol,
@@ -66,6 +80,7 @@ __global__ __launch_bounds__(64) void k_init_ctl(Ctl* c, int maxit, int m, doubl
   c->ratio = 1.0;
   c->rho = c->rho_old = c->alpha = c->omega = c->beta = c->rh_norm = 0.0;
   c->wnorm_pre = 0.0;
+  c->last_rt = 0.0;
 }
 
 // Every streaming kernel below works on one tile of BS rows per workgroup, one row per
@@ -87,44 +102,50 @@ __device__ inline void block_single_partial(double v, double* __restrict__ parti
   }
 }
 
-// R: r = b - A x into u_0; partials ||r||^2 (column 0), ||W r||^2 (column 1).
-template <class Op>
+// R: r = b - A x (FP64, the caller's matrix) into u_0 stored as T; partials ||r||^2
+// (column 0), ||W r||^2 (column 1) and ||u_0||^2 of the stored values (column 2).
+template <class Op, class T>
 __global__ __launch_bounds__(BS) void k_gmres_residual(KArgs a, Op op, const double* __restrict__ b,
                                                        const double* __restrict__ x,
                                                        const double* __restrict__ W,
-                                                       double* __restrict__ u0,
-                                                       const int* flags) {
+                                                       T* __restrict__ u0, const int* flags) {
   Ctl* c = a.ctl;
   const int st = c->sum.state;
   if (st != ST_INIT && st != ST_CYCLE_END) return;
   if (flags[0]) return;
-  mark_work(c, a.pslot, a.mat_bytes + 8.0 * a.n * (W ? 4 : 3));
+  mark_work(c, a.pslot, a.mat_bytes + a.n * (16.0 + sizeof(T) + (W ? 8.0 : 0.0)));
   __shared__ typename Op::Lds L;
   __shared__ double red[NC_MAX * WAVES];
   const int nb = gridDim.x;
   const int lb = logical_block();
   const int row0 = lb * BS;
   const int nrows = tile_rows(a.n, row0);
-  double acc[2] = {0.0, 0.0};
+  double acc[3] = {0.0, 0.0, 0.0};
   if (nrows > 0) {
     const double y = op.tile(row0, nrows, GatherX{x}, L);
     if ((int)threadIdx.x < nrows) {
       const int row = row0 + threadIdx.x;
       const double r = b[row] - y;
-      u0[row] = r;
+      const T rs = (T)r;
+      u0[row] = rs;
       acc[0] = r * r;
       if (W) {
         const double wr = W[row] * r;
         acc[1] = wr * wr;
       }
+      acc[2] = (double)rs * (double)rs;
     }
   }
-  block_partials<2>(acc, 2, a.partials, nb, lb, red);
+  block_partials<3>(acc, 3, a.partials, nb, lb, red);
 }
 
 // FR: convergence / restart decision after the true residual (see file comment).
+// In the mixed-precision solver (mixed = 1) an FP32 cycle may claim convergence that the
+// FP64 residual does not confirm simply because FP32 data cannot resolve the last digits; such
+// a cycle still counts as progress when it halved the true residual, and only claims without
+// progress count towards STAGNATED.
 __global__ __launch_bounds__(BS) void k_gmres_fin_residual(Ctl* c, const double* partials,
-                                                           int nb, int has_w,
+                                                           int nb, int has_w, int mixed,
                                                            const int* flags) {
   const int st = c->sum.state;
   if (st != ST_INIT && st != ST_CYCLE_END) return;
@@ -136,10 +157,11 @@ __global__ __launch_bounds__(BS) void k_gmres_fin_residual(Ctl* c, const double*
     return;
   }
   __shared__ double out[8];
-  small_sums<2>(partials, nb, out);
+  small_sums<3>(partials, nb, out);
   if (threadIdx.x != 0) return;
   const double nr = sqrt(out[0]);
   const double nwr = has_w ? sqrt(out[1]) : nr;
+  const double ns = sqrt(out[2]);   // norm of the stored u_0 (equals nr in FP64)
   if (st == ST_INIT) {
     c->ref = nwr;
     if (nwr == 0.0) {
@@ -172,7 +194,8 @@ __global__ __launch_bounds__(BS) void k_gmres_fin_residual(Ctl* c, const double*
       c->sum.state = ST_DONE;
       return;
     }
-    if (c->claimed) {
+    const int progress = mixed && rt < 0.5 * c->last_rt;
+    if (c->claimed && !progress) {
       c->sum.fails += 1;
       if (c->sum.fails >= 3) {
         c->sum.status = S_STAGNATED;
@@ -184,11 +207,13 @@ __global__ __launch_bounds__(BS) void k_gmres_fin_residual(Ctl* c, const double*
     }
     c->sum.restarts += 1;
   }
-  // start a cycle: v_0 = r / ||r||, g = ||r|| e_1
-  c->sigma[0] = 1.0 / nr;
-  c->g[0] = nr;
+  // start a cycle: v_0 = u_0 / ||u_0||, g = ||u_0|| e_1; the cycle's estimates are in the
+  // norm of the stored u_0 and are converted to the stop-test metric by nwr / ns
+  c->last_rt = nwr / c->ref;
+  c->sigma[0] = 1.0 / ns;
+  c->g[0] = ns;
   for (int i = 1; i <= c->m; ++i) c->g[i] = 0.0;
-  c->ratio = has_w ? nwr / nr : 1.0;
+  c->ratio = nwr / ns;
   c->j = 0;
   c->k = 0;
   c->claimed = 0;
@@ -196,13 +221,29 @@ __global__ __launch_bounds__(BS) void k_gmres_fin_residual(Ctl* c, const double*
   c->sum.state = ST_RUNNING;
 }
 
+// Rows per thread. A workgroup owns RPT consecutive tiles of BS rows and thread t the rows
+// row0 + q BS + t, q < RPT. FP32 data use RPT = 2, so that a thread keeps as many bytes of
+// loads in flight as an FP64 thread; a CSR product stages one tile at a time through LDS and
+// keeps RPT = 1.
+template <class T>
+constexpr int rpt_of() { return 8 / (int)sizeof(T); }
+
+// (double)x for a value the kernel has already widened once. The empty asm makes the two
+// conversions distinct to the compiler, so it keeps the narrow value (one register for a
+// float) alive instead of the widened one (two registers), which would halve occupancy.
+template <class T>
+__device__ inline double widen_again(T x) {
+  if constexpr (sizeof(T) == 4) asm("" : "+v"(x));
+  return (double)x;
+}
+
 // A: w = sigma_j A u_j; partials of u_i . w (columns 0..j) and ||w||^2 (column j+1).
 // Loads are issued in the order they are needed (stencil operands, then the basis values of
-// the thread's row) before the launch tests whether it has work: the control block is read
+// the thread's rows) before the launch tests whether it has work: the control block is read
 // alongside, so the test costs no round trip of its own. A launch without work stores nothing.
-template <int JM, class R, class Op>
-__global__ __launch_bounds__(BS) void k_gmres_a(KArgs a, Op op, const double* __restrict__ V,
-                                                size_t ldv, double* __restrict__ w, int j) {
+template <int JM, int RPT, class R, class Op, class T>
+__global__ __launch_bounds__(BS) void k_gmres_a(KArgs a, Op op, const T* __restrict__ V,
+                                                size_t ldv, T* __restrict__ w, int j) {
   Ctl* c = a.ctl;
   const int state = c->sum.state, cj = c->j;
   const double sg = c->sigma[j];
@@ -211,27 +252,48 @@ __global__ __launch_bounds__(BS) void k_gmres_a(KArgs a, Op op, const double* __
   __shared__ double red1[WAVES];
   const int nb = gridDim.x;
   const int lb = logical_block();
-  const int row0 = lb * BS;
-  const int nrows = tile_rows(a.n, row0);
-  const int row = row0 + threadIdx.x;
-  const bool mine = (int)threadIdx.x < nrows;
-  const GatherX gx{V + (size_t)j * ldv};
-  typename Op::template Pre<GatherX> pre{};
-  if (nrows > 0) pre = op.load(row0, nrows, gx);
+  const T zero = (T)a.zero;
+  const int t = threadIdx.x;
+  const GatherXT<T> gx{V + (size_t)j * ldv};
   const R rd(V, ldv, j + 1);
-  double u[JM];
+  int rq[RPT], nq[RPT];
+  typename Op::template Pre<GatherXT<T>> pre[RPT];
 #pragma unroll
-  for (int i = 0; i < JM; ++i) u[i] = (i <= j && mine) ? rd.load(i, row) : 0.0;
-  const double y = nrows > 0 ? op.finish(pre, row0, nrows, gx, L) : 0.0;
+  for (int q = 0; q < RPT; ++q) {
+    rq[q] = (lb * RPT + q) * BS;
+    nq[q] = tile_rows(a.n, rq[q]);
+    pre[q] = op.load(rq[q], nq[q], gx);   // unconditional: valid rows for any tile
+  }
+  T u[JM][RPT];
+#pragma unroll
+  for (int i = 0; i < JM; ++i)
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+      u[i][q] = (i <= j && t < nq[q]) ? rd.raw(i, rq[q] + t) : zero;
+  double y[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) y[q] = nq[q] > 0 ? op.finish(pre[q], rq[q], nq[q], gx, L) : 0.0;
   asm volatile("" ::: "memory");   // keeps the loads above ahead of the test below
   if (state != ST_RUNNING || cj != j) return;
-  mark_work(c, a.pslot, a.mat_bytes + 8.0 * a.n * (j + 2));
-  const double wr = mine ? sg * y : 0.0;
-  if (mine) w[row] = wr;
+  mark_work(c, a.pslot, a.inner_bytes + (double)sizeof(T) * a.n * (j + 2));
+  double wr[RPT], nrm = 0.0;
 #pragma unroll
-  for (int i = 0; i < JM; ++i) u[i] *= wr;
-  block_halving_partials<JM>(u, j + 1, a.partials, nb, lb, red);
-  block_single_partial(wr * wr, a.partials, j + 1, nb, lb, red1);
+  for (int q = 0; q < RPT; ++q) {
+    const T ws = (T)(sg * y[q]);
+    const bool mine = t < nq[q];
+    wr[q] = mine ? (double)ws : 0.0;
+    if (mine) w[rq[q] + t] = ws;
+    nrm += wr[q] * wr[q];
+  }
+  double v[JM];
+#pragma unroll
+  for (int i = 0; i < JM; ++i) {
+    v[i] = 0.0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) v[i] += widen_again(u[i][q]) * wr[q];
+  }
+  block_halving_partials<JM>(v, j + 1, a.partials, nb, lb, red);
+  block_single_partial(nrm, a.partials, j + 1, nb, lb, red1);
 }
 
 // FA (j+2 workgroups): workgroup i <= j -> c1_i = sigma_i (u_i . w); workgroup j+1 -> ||A v_j||.
@@ -256,35 +318,57 @@ __global__ __launch_bounds__(BS) void k_gmres_fin_a(Ctl* c, const double* partia
 
 // B: w -= sum_i c1_i v_i (weights d1_i = c1_i sigma_i on the stored columns), then partials of
 // u_i . w, sharing one read of the basis. Operands are requested before the work test, as in A.
-template <int JM, class R>
-__global__ __launch_bounds__(BS) void k_gmres_b(KArgs a, const double* __restrict__ V, size_t ldv,
-                                                double* __restrict__ w, int j) {
+template <int JM, int RPT, class R, class T>
+__global__ __launch_bounds__(BS) void k_gmres_b(KArgs a, const T* __restrict__ V, size_t ldv,
+                                                T* __restrict__ w, int j) {
   Ctl* c = a.ctl;
   const int state = c->sum.state, cj = c->j;
   __shared__ double red[NC_MAX * WAVES];
   const int t = threadIdx.x;
   const int nb = gridDim.x;
   const int lb = logical_block();
-  const int row = lb * BS + t;
-  const bool mine = row < a.n;
+  const T zero = (T)a.zero;
   double d[JM];   // uniform across the launch: scalar loads
 #pragma unroll
   for (int i = 0; i < JM; ++i) d[i] = c->d1[i];
   const R rd(V, ldv, j + 1);
-  double u[JM];
+  int row[RPT];
+  bool mine[RPT];
 #pragma unroll
-  for (int i = 0; i < JM; ++i) u[i] = (i <= j && mine) ? rd.load(i, row) : 0.0;
-  double wr = mine ? w[row] : 0.0;
-  asm volatile("" ::: "memory");
-  if (state != ST_RUNNING || cj != j) return;
-  mark_work(c, a.pslot, 8.0 * a.n * (j + 3));
+  for (int q = 0; q < RPT; ++q) {
+    row[q] = (lb * RPT + q) * BS + t;
+    mine[q] = row[q] < a.n;
+  }
+  T u[JM][RPT];
 #pragma unroll
   for (int i = 0; i < JM; ++i)
-    if (i <= j) wr = fma(-d[i], u[i], wr);
-  if (mine) w[row] = wr;
 #pragma unroll
-  for (int i = 0; i < JM; ++i) u[i] *= wr;
-  block_halving_partials<JM>(u, j + 1, a.partials, nb, lb, red);
+    for (int q = 0; q < RPT; ++q) u[i][q] = (i <= j && mine[q]) ? rd.raw(i, row[q]) : zero;
+  T wv[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) wv[q] = mine[q] ? w[row[q]] : zero;
+  asm volatile("" ::: "memory");
+  if (state != ST_RUNNING || cj != j) return;
+  mark_work(c, a.pslot, (double)sizeof(T) * a.n * (j + 3));
+  double wr[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    double x = (double)wv[q];
+#pragma unroll
+    for (int i = 0; i < JM; ++i)
+      if (i <= j) x = fma(-d[i], (double)u[i][q], x);
+    const T ws = (T)x;
+    wr[q] = mine[q] ? (double)ws : 0.0;
+    if (mine[q]) w[row[q]] = ws;
+  }
+  double v[JM];
+#pragma unroll
+  for (int i = 0; i < JM; ++i) {
+    v[i] = 0.0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) v[i] += widen_again(u[i][q]) * wr[q];
+  }
+  block_halving_partials<JM>(v, j + 1, a.partials, nb, lb, red);
 }
 
 // FB (j+1 workgroups): c2_i = sigma_i (u_i . w).
@@ -303,33 +387,51 @@ __global__ __launch_bounds__(BS) void k_gmres_fin_b(Ctl* c, const double* partia
 
 // C: w -= sum_i c2_i v_i (weights d2_i = c2_i sigma_i), u_{j+1} = w, partial ||w||^2.
 // Operands are requested before the work test, as in A.
-template <int JM, class R>
-__global__ __launch_bounds__(BS) void k_gmres_c(KArgs a, double* __restrict__ V, size_t ldv,
-                                                const double* __restrict__ w, int j) {
+template <int JM, int RPT, class R, class T>
+__global__ __launch_bounds__(BS) void k_gmres_c(KArgs a, T* __restrict__ V, size_t ldv,
+                                                const T* __restrict__ w, int j) {
   Ctl* c = a.ctl;
   const int state = c->sum.state, cj = c->j;
   __shared__ double red[WAVES];
   const int t = threadIdx.x;
   const int nb = gridDim.x;
   const int lb = logical_block();
-  const int row = lb * BS + t;
-  const bool mine = row < a.n;
+  const T zero = (T)a.zero;
   double d[JM];   // uniform across the launch: scalar loads
 #pragma unroll
   for (int i = 0; i < JM; ++i) d[i] = c->d2[i];
   const R rd(V, ldv, j + 1);
-  double u[JM];
+  int row[RPT];
+  bool mine[RPT];
 #pragma unroll
-  for (int i = 0; i < JM; ++i) u[i] = (i <= j && mine) ? rd.load(i, row) : 0.0;
-  double wr = mine ? w[row] : 0.0;
-  asm volatile("" ::: "memory");
-  if (state != ST_RUNNING || cj != j) return;
-  mark_work(c, a.pslot, 8.0 * a.n * (j + 3));
+  for (int q = 0; q < RPT; ++q) {
+    row[q] = (lb * RPT + q) * BS + t;
+    mine[q] = row[q] < a.n;
+  }
+  T u[JM][RPT];
 #pragma unroll
   for (int i = 0; i < JM; ++i)
-    if (i <= j) wr = fma(-d[i], u[i], wr);
-  if (mine) V[(size_t)(j + 1) * ldv + row] = wr;
-  block_single_partial(wr * wr, a.partials, 0, nb, lb, red);
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) u[i][q] = (i <= j && mine[q]) ? rd.raw(i, row[q]) : zero;
+  T wv[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) wv[q] = mine[q] ? w[row[q]] : zero;
+  asm volatile("" ::: "memory");
+  if (state != ST_RUNNING || cj != j) return;
+  mark_work(c, a.pslot, (double)sizeof(T) * a.n * (j + 3));
+  double nrm = 0.0;
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    double x = (double)wv[q];
+#pragma unroll
+    for (int i = 0; i < JM; ++i)
+      if (i <= j) x = fma(-d[i], (double)u[i][q], x);
+    const T ws = (T)x;
+    const double wr = mine[q] ? (double)ws : 0.0;
+    if (mine[q]) V[(size_t)(j + 1) * ldv + row[q]] = ws;
+    nrm += wr * wr;
+  }
+  block_single_partial(nrm, a.partials, 0, nb, lb, red);
 }
 
 // FC (1 workgroup): Hessenberg column, Givens rotations, residual estimate; at the end of a
@@ -424,23 +526,27 @@ __global__ __launch_bounds__(BS) void k_gmres_fin_c(Ctl* c, const double* partia
 }
 
 // X: x += sum_{l<k} y_l v_l (y already carries sigma).
-template <class R>
-__global__ __launch_bounds__(BS) void k_gmres_x(KArgs a, const double* __restrict__ V, size_t ldv,
+template <int RPT, class R, class T>
+__global__ __launch_bounds__(BS) void k_gmres_x(KArgs a, const T* __restrict__ V, size_t ldv,
                                                 double* __restrict__ x) {
   Ctl* c = a.ctl;
   if (c->sum.state != ST_CYCLE_END) return;
   __shared__ double s_y[MMAX];
   const int k = c->k;
-  mark_work(c, a.pslot, 8.0 * a.n * (k + 2));
+  mark_work(c, a.pslot, a.n * ((double)sizeof(T) * k + 16.0));
   const int t = threadIdx.x;
   if (t < k) s_y[t] = c->y[t];
   __syncthreads();
-  const int row = logical_block() * BS + t;
-  if (row >= a.n) return;
+  const int lb = logical_block();
   const R rd(V, ldv, k > 0 ? k : 1);
-  double acc = 0.0;
-  for (int l = 0; l < k; ++l) acc = fma(s_y[l], rd.load(l, row), acc);
-  x[row] = x[row] + acc;
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int row = (lb * RPT + q) * BS + t;
+    if (row >= a.n) continue;
+    double acc = 0.0;
+    for (int l = 0; l < k; ++l) acc = fma(s_y[l], rd.load(l, row), acc);
+    x[row] = x[row] + acc;
+  }
 }
 
 // Arnoldi entry point: u_0 = r0, partial ||r0||^2.
@@ -525,11 +631,14 @@ __global__ __launch_bounds__(64) void k_arnoldi_done(Ctl* c) {
 // ---------------------------------------------------------------------------------------
 static int pick_jm(int cols) { return cols <= 8 ? 8 : cols <= 16 ? 16 : cols <= 32 ? 32 : 64; }
 
-template <class R, class Op>
-static hipError_t launch_step(const KArgs& ka, const Op& op, int nb, double* V, size_t ldv,
-                              double* w, int j, hipStream_t s) {
+template <class R, class Op, class T>
+static hipError_t launch_step(const KArgs& ka, const Op& op, int n, T* V, size_t ldv, T* w,
+                              int j, hipStream_t s) {
+  constexpr int RV = rpt_of<T>();                  // B, C: rows per thread
+  constexpr int RA = Op::kRowwise ? RV : 1;        // A
+  const int ga = grid_for(n, RA), gv = grid_for(n, RV);
   const int jm = pick_jm(j + 1);
-  dim3 grid(nb), block(BS);
+  dim3 block(BS);
   KArgs kx = ka;
 #define GSK_TIMED(CLS, LAUNCH)           \
   kx.pslot = probe_slot(CLS);            \
@@ -537,15 +646,15 @@ static hipError_t launch_step(const KArgs& ka, const Op& op, int nb, double* V, 
   LAUNCH;                                \
   if (kx.pslot >= 0) probe_end(s, kx.pslot);
 #define GSK_STEP(JMV)                                                                          \
-  GSK_TIMED(KC_GMRES_A,                                                                        \
-            hipLaunchKernelGGL((k_gmres_a<JMV, R, Op>), grid, block, 0, s, kx, op, V, ldv, w, j)) \
-  hipLaunchKernelGGL(k_gmres_fin_a, dim3(j + 2), block, 0, s, ka.ctl, ka.partials, nb, j);     \
-  GSK_TIMED(KC_GMRES_B,                                                                        \
-            hipLaunchKernelGGL((k_gmres_b<JMV, R>), grid, block, 0, s, kx, V, ldv, w, j))      \
-  hipLaunchKernelGGL(k_gmres_fin_b, dim3(j + 1), block, 0, s, ka.ctl, ka.partials, nb, j);     \
-  GSK_TIMED(KC_GMRES_C,                                                                        \
-            hipLaunchKernelGGL((k_gmres_c<JMV, R>), grid, block, 0, s, kx, V, ldv, w, j))      \
-  hipLaunchKernelGGL(k_gmres_fin_c, dim3(1), block, 0, s, ka.ctl, ka.partials, nb, j);
+  GSK_TIMED(KC_GMRES_A, hipLaunchKernelGGL((k_gmres_a<JMV, RA, R, Op, T>), dim3(ga), block, 0, \
+                                           s, kx, op, (const T*)V, ldv, w, j))                 \
+  hipLaunchKernelGGL(k_gmres_fin_a, dim3(j + 2), block, 0, s, ka.ctl, ka.partials, ga, j);     \
+  GSK_TIMED(KC_GMRES_B, hipLaunchKernelGGL((k_gmres_b<JMV, RV, R, T>), dim3(gv), block, 0, s,  \
+                                           kx, (const T*)V, ldv, w, j))                        \
+  hipLaunchKernelGGL(k_gmres_fin_b, dim3(j + 1), block, 0, s, ka.ctl, ka.partials, gv, j);     \
+  GSK_TIMED(KC_GMRES_C, hipLaunchKernelGGL((k_gmres_c<JMV, RV, R, T>), dim3(gv), block, 0, s,  \
+                                           kx, V, ldv, (const T*)w, j))                        \
+  hipLaunchKernelGGL(k_gmres_fin_c, dim3(1), block, 0, s, ka.ctl, ka.partials, gv, j);
   switch (jm) {
     case 8: GSK_STEP(8) break;
     case 16: GSK_STEP(16) break;
@@ -557,17 +666,31 @@ static hipError_t launch_step(const KArgs& ka, const Op& op, int nb, double* V, 
   return hipGetLastError();
 }
 
-template <class Op>
+template <class Op, class T>
 static void launch_residual(const KArgs& ka, const Op& op, int nb, const double* b,
-                            const double* x, const double* W, double* u0, const int* flags,
+                            const double* x, const double* W, T* u0, const int* flags, int mixed,
                             hipStream_t s) {
   KArgs kx = ka;
   kx.pslot = probe_slot(KC_RESIDUAL);
   if (kx.pslot >= 0) probe_begin(s);
-  hipLaunchKernelGGL(k_gmres_residual<Op>, dim3(nb), dim3(BS), 0, s, kx, op, b, x, W, u0, flags);
+  hipLaunchKernelGGL((k_gmres_residual<Op, T>), dim3(nb), dim3(BS), 0, s, kx, op, b, x, W, u0,
+                     flags);
   if (kx.pslot >= 0) probe_end(s, kx.pslot);
   hipLaunchKernelGGL(k_gmres_fin_residual, dim3(1), dim3(BS), 0, s, ka.ctl,
-                     (const double*)ka.partials, nb, W ? 1 : 0, flags);
+                     (const double*)ka.partials, nb, W ? 1 : 0, mixed, flags);
+}
+
+// FP64 -> FP32 copy of matrix values (the mixed-precision solver's inner matrix): `segs`
+// segments of `len` values, read with stride src_ld and written with stride dst_ld.
+__global__ __launch_bounds__(BS) void k_to_f32(const double* __restrict__ src, size_t src_ld,
+                                               float* __restrict__ dst, size_t dst_ld,
+                                               int64_t len, int segs) {
+  const int64_t total = len * segs;
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * BS) {
+    const int64_t sg = i / len, k = i - sg * len;
+    dst[sg * dst_ld + k] = (float)src[sg * src_ld + k];
+  }
 }
 
 static SolveResult fail(int code) {
@@ -577,22 +700,25 @@ static SolveResult fail(int code) {
   return r;
 }
 
-template <class R, class Op>
-static SolveResult gmres_run(const Mat& A, const Op& op, const double* b, double* x, int m,
-                             const SolveParams& prm, void* ws, hipStream_t s) {
+// Restarted GMRES(m): Op64 is the caller's FP64 matrix (true residuals), OpT the matrix the
+// Arnoldi products use (the same one, or its FP32 copy), T the storage type of V (m+1 columns
+// of ld values) and w. mixed selects the refinement form of the stagnation rule.
+template <class R, class Op64, class OpT, class T>
+static SolveResult gmres_run(const Mat& A, const Op64& op, const OpT& opT, double inner_bytes,
+                             const double* b, double* x, int m, const SolveParams& prm,
+                             void* ws, T* V, int mixed, hipStream_t s) {
   Workspace W = carve(ws, A.n);
   const Geom g = make_geom(A.n);
   const size_t ldv = vec_ld(A.n);
-  double* V = W.vecs;
-  double* w = V + (size_t)(m + 1) * ldv;
-  KArgs ka{A.n, g.rpb, W.ctl, W.partials, A.bytes(), -1};
+  T* w = V + (size_t)(m + 1) * ldv;
+  KArgs ka{A.n, g.rpb, W.ctl, W.partials, A.bytes(), -1, inner_bytes, 0.0};
   dim3 grid(g.nb), block(BS);
   if (launch_clear_flags(W.flags, s) != hipSuccess) return fail(-5);
   if (A.kind == MAT_CSR && launch_validate(A.csr, W.flags, s) != hipSuccess) return fail(-5);
   hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, s, W.ctl, prm.maxit, m, prm.tol, prm.eps_b,
                      prm.weights ? 1 : 0);
   probe_solve_begin();
-  launch_residual(ka, op, g.nb, b, x, prm.weights, V, W.flags, s);
+  launch_residual(ka, op, g.nb, b, x, prm.weights, V, W.flags, mixed, s);
   if (hipGetLastError() != hipSuccess) return fail(-5);
 
   Summary* hs = pinned_summaries();
@@ -613,16 +739,17 @@ static SolveResult gmres_run(const Mat& A, const Op& op, const double* b, double
   constexpr int kPiece = 10;   // steps per piece of a cycle in cautious mode
   auto steps = [&](int j0, int j1) {
     for (int j = j0; j < j1; ++j)
-      if (launch_step<R>(ka, op, g.nb, V, ldv, w, j, s) != hipSuccess) return false;
+      if (launch_step<R>(ka, opT, A.n, V, ldv, w, j, s) != hipSuccess) return false;
     return true;
   };
   auto tail = [&]() {
     KArgs kx = ka;
     kx.pslot = probe_slot(KC_GMRES_X);
     if (kx.pslot >= 0) probe_begin(s);
-    hipLaunchKernelGGL(k_gmres_x<R>, grid, block, 0, s, kx, (const double*)V, ldv, x);
+    hipLaunchKernelGGL((k_gmres_x<rpt_of<T>(), R, T>), dim3(grid_for(A.n, rpt_of<T>())), block,
+                       0, s, kx, (const T*)V, ldv, x);
     if (kx.pslot >= 0) probe_end(s, kx.pslot);
-    launch_residual(ka, op, g.nb, b, x, prm.weights, V, W.flags, s);
+    launch_residual(ka, op, g.nb, b, x, prm.weights, V, W.flags, mixed, s);
     return hipGetLastError() == hipSuccess;
   };
   auto record = [&](int sl) {
@@ -681,7 +808,7 @@ static SolveResult arnoldi_impl(const Mat& A, const Op& op, const double* r0, in
   Workspace W = carve(ws, A.n);
   const Geom g = make_geom(A.n);
   double* w = W.vecs;
-  KArgs ka{A.n, g.rpb, W.ctl, W.partials, A.bytes(), -1};
+  KArgs ka{A.n, g.rpb, W.ctl, W.partials, A.bytes(), -1, A.bytes(), 0.0};
   dim3 grid(g.nb), block(BS);
   if (launch_clear_flags(W.flags, s) != hipSuccess) return fail(-5);
   if (A.kind == MAT_CSR && launch_validate(A.csr, W.flags, s) != hipSuccess) return fail(-5);
@@ -692,7 +819,7 @@ static SolveResult arnoldi_impl(const Mat& A, const Op& op, const double* r0, in
   hipLaunchKernelGGL(k_arnoldi_fin_start, dim3(1), block, 0, s, W.ctl,
                      (const double*)W.partials, g.nb, (const int*)W.flags);
   for (int j = 0; j < m; ++j)
-    if (launch_step<R>(ka, op, g.nb, V, (size_t)ldv, w, j, s) != hipSuccess) return fail(-5);
+    if (launch_step<R>(ka, op, A.n, V, (size_t)ldv, w, j, s) != hipSuccess) return fail(-5);
   const int fin_blocks = 1024;
   hipLaunchKernelGGL(k_arnoldi_finish, dim3(fin_blocks), block, 0, s, ka, V, (size_t)ldv, H, m);
   hipLaunchKernelGGL(k_arnoldi_done, dim3(1), dim3(64), 0, s, W.ctl);
@@ -715,9 +842,10 @@ static SolveResult arnoldi_impl(const Mat& A, const Op& op, const double* r0, in
 template <class Op>
 static SolveResult gmres_dispatch(const Mat& A, const Op& op, const double* b, double* x, int m,
                                   const SolveParams& prm, void* ws, hipStream_t s) {
-  if (fits_buffer(vec_ld(A.n), m + 1))
-    return gmres_run<ColumnReader>(A, op, b, x, m, prm, ws, s);
-  return gmres_run<PointerReader>(A, op, b, x, m, prm, ws, s);
+  double* V = carve(ws, A.n).vecs;
+  if (fits_buffer<double>(vec_ld(A.n), m + 1))
+    return gmres_run<ColumnReader>(A, op, op, A.bytes(), b, x, m, prm, ws, V, 0, s);
+  return gmres_run<PointerReader>(A, op, op, A.bytes(), b, x, m, prm, ws, V, 0, s);
 }
 
 SolveResult gmres_solve(const Mat& A, const double* b, double* x, int m, const SolveParams& prm,
@@ -726,11 +854,51 @@ SolveResult gmres_solve(const Mat& A, const double* b, double* x, int m, const S
   return gmres_dispatch(A, A.csr_op(), b, x, m, prm, ws, s);
 }
 
+// Mixed precision: [head | FP32 copy of the matrix values | V (m+1 columns) | w], FP32.
+// The FP32 planes are padded to vec_ld(n) values each, so every plane starts 256-byte aligned.
+size_t mixed_matrix_floats(const Mat& A) {
+  return A.kind == MAT_STENCIL ? (size_t)A.planes() * vec_ld(A.n) : (size_t)A.csr.nnz;
+}
+
+template <class Op64, class OpT>
+static SolveResult gmres_mixed_dispatch(const Mat& A, const Op64& op, const OpT& opT,
+                                        double inner_bytes, float* V, const double* b, double* x,
+                                        int m, const SolveParams& prm, void* ws, hipStream_t s) {
+  if (fits_buffer<float>(vec_ld(A.n), m + 1))
+    return gmres_run<ColumnReaderT<float>>(A, op, opT, inner_bytes, b, x, m, prm, ws, V, 1, s);
+  return gmres_run<PointerReaderT<float>>(A, op, opT, inner_bytes, b, x, m, prm, ws, V, 1, s);
+}
+
+SolveResult gmres_mixed_solve(const Mat& A, const double* b, double* x, int m,
+                              const SolveParams& prm, void* ws, hipStream_t s) {
+  char* base = reinterpret_cast<char*>(carve(ws, A.n).vecs);
+  float* vals = reinterpret_cast<float*>(base);
+  float* V = reinterpret_cast<float*>(base + align256(sizeof(float) * mixed_matrix_floats(A)));
+  const bool st = A.kind == MAT_STENCIL;
+  const int64_t len = st ? (int64_t)A.n : (int64_t)A.csr.nnz;
+  const int segs = st ? A.planes() : 1;
+  int64_t blocks = (len * segs + BS - 1) / BS;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_to_f32, dim3((unsigned)blocks), dim3(BS), 0, s,
+                     st ? A.coef : A.csr.val, (size_t)len, vals, st ? vec_ld(A.n) : (size_t)len,
+                     len, segs);
+  if (hipGetLastError() != hipSuccess) return fail(-5);
+  if (A.kind == MAT_STENCIL) {
+    const StencilOpT<float> opT{vals, A.n, A.nx, A.ny, A.nz, vec_ld(A.n)};
+    return gmres_mixed_dispatch(A, A.stencil_op(), opT, 4.0 * A.planes() * A.n, V, b, x, m,
+                                prm, ws, s);
+  }
+  const CsrOpT<float> opT{A.csr.rp, A.csr.ci, vals};
+  return gmres_mixed_dispatch(A, A.csr_op(), opT, 8.0 * A.csr.nnz + 4.0 * (A.n + 1.0), V, b, x,
+                              m, prm, ws, s);
+}
+
 template <class Op>
 static SolveResult arnoldi_dispatch(const Mat& A, const Op& op, const double* r0, int m,
                                     double* V, int64_t ldv, double* H, void* ws, double eps_b,
                                     hipStream_t s) {
-  if (fits_buffer((size_t)ldv, m + 1))
+  if (fits_buffer<double>((size_t)ldv, m + 1))
     return arnoldi_impl<ColumnReader>(A, op, r0, m, V, ldv, H, ws, eps_b, s);
   return arnoldi_impl<PointerReader>(A, op, r0, m, V, ldv, H, ws, eps_b, s);
 }

@@ -71,6 +71,7 @@ struct Ctl {
   int maxit, m, j, k, claimed, first, has_w;
   int broke, happy, pad0, pad1;
   double tol, eps_b, ref, ratio;
+  double last_rt;            // GMRES: relative true residual at the start of the cycle
   // Bi-CGSTAB scalars
   double rho, rho_old, alpha, omega, beta, rh_norm;
   // GMRES: lazy column scales, orthogonalisation coefficients, Hessenberg + Givens
@@ -100,6 +101,12 @@ inline Geom make_geom(int n) {
   const int tiles = (n + BS - 1) / BS;
   const int nb = (tiles + 7) / 8 * 8;
   return Geom{nb, BS};
+}
+
+// Workgroups of a launch whose workgroups own rpt consecutive tiles (rows_per_thread).
+inline int grid_for(int n, int rpt) {
+  const int tiles = (n + BS * rpt - 1) / (BS * rpt);
+  return (tiles + 7) / 8 * 8;
 }
 
 // Logical workgroup index: XCD x (= blockIdx.x % 8) owns logical blocks
@@ -278,9 +285,9 @@ struct TileLds {
   double prod[TILE_NNZ];
 };
 
-template <class G>
+template <class G, class V>
 __device__ inline double csr_tile(const int* __restrict__ row_ptr, const int* __restrict__ col,
-                                  const double* __restrict__ val, int row0, int nrows,
+                                  const V* __restrict__ val, int row0, int nrows,
                                   const G& gather, TileLds& L) {
 #pragma clang fp contract(off)
   const int t = threadIdx.x;
@@ -291,7 +298,7 @@ __device__ inline double csr_tile(const int* __restrict__ row_ptr, const int* __
   double y = 0.0;
   if (cnt <= TILE_NNZ) {
     for (int k = t; k < cnt; k += BS) {
-      const double a = val[p0 + k];
+      const double a = (double)val[p0 + k];
       const double xv = gather(col[p0 + k]);
       L.prod[k] = a * xv;
     }
@@ -304,7 +311,7 @@ __device__ inline double csr_tile(const int* __restrict__ row_ptr, const int* __
     if (t < nrows) {
       const int e = L.rp[t + 1];
       for (int k = L.rp[t]; k < e; ++k) {
-        const double prod = val[k] * gather(col[k]);
+        const double prod = (double)val[k] * gather(col[k]);
         y += prod;
       }
     }
@@ -315,14 +322,17 @@ __device__ inline double csr_tile(const int* __restrict__ row_ptr, const int* __
 
 // A gather supplies the source-vector entry of a column in two steps: load(col) fetches the
 // raw operands (Raw), value(raw) combines them; g(col) == value(load(col)). Splitting the two
-// lets a kernel issue every load before it combines anything.
-struct GatherX {
-  const double* __restrict__ x;
-  typedef double Raw;
+// lets a kernel issue every load before it combines anything. T is the storage type of the
+// vector (double, or float for the FP32 inner solves); arithmetic is in double.
+template <class T>
+struct GatherXT {
+  const T* __restrict__ x;
+  typedef T Raw;
   __device__ Raw load(int c) const { return x[c]; }
-  __device__ double value(Raw v) const { return v; }
-  __device__ double operator()(int c) const { return x[c]; }
+  __device__ double value(Raw v) const { return (double)v; }
+  __device__ double operator()(int c) const { return (double)x[c]; }
 };
+using GatherX = GatherXT<double>;
 
 // ---------------------------------------------------------------------------------------
 // Matrix operators. Every kernel that multiplies by A is templated on one of these:
@@ -334,12 +344,15 @@ struct GatherX {
 //
 // Besides tile(), an operator offers the product in two phases, load() and finish(), so a
 // kernel can put other loads between the two (see k_gmres_a); finish(load(...)) == tile().
-// nrows >= 1 in every call.
-struct CsrOp {
+// nrows >= 1 in every call. V is the storage type of the matrix values (double, or float for
+// the FP32 copy the mixed-precision GMRES multiplies by); products and sums are in double.
+template <class V>
+struct CsrOpT {
   const int* rp;
   const int* ci;
-  const double* val;
+  const V* val;
   typedef TileLds Lds;
+  static constexpr bool kRowwise = false;   // tiles share LDS: one tile at a time
   template <class G>
   struct Pre {};   // a CSR tile stages its nonzeros through LDS behind barriers: nothing ahead
   template <class G>
@@ -354,6 +367,8 @@ struct CsrOp {
   }
 };
 
+using CsrOp = CsrOpT<double>;
+
 struct EmptyLds {
   int unused;
 };
@@ -363,17 +378,20 @@ struct EmptyLds {
 // -z, -y, -x, centre, +x, +y, +z (-z and +z absent in 2D); neighbours outside the grid are
 // skipped. Each row is summed in that order with every product rounded before it is added,
 // so the result equals the CSR product of the same matrix bit for bit.
-struct StencilOp {
-  const double* coef;
+template <class V>
+struct StencilOpT {
+  const V* coef;
   int n, nx, ny, nz;
+  size_t ldp;    // stride between coefficient planes (n for a caller's matrix)
   typedef EmptyLds Lds;
+  static constexpr bool kRowwise = true;    // rows are independent: several tiles at once
   // Position q of a row: -z, -y, -x, centre, +x, +y, +z. load() fetches every coefficient and
   // neighbour without a branch, so that all loads are in flight together: the neighbour index
   // is i + offset clamped to [0, n), a valid address whatever the position, and a position
   // outside the grid (or -z/+z in 2D) is flagged absent and its values are never used.
   template <class G>
   struct Pre {
-    double c[7];
+    V c[7];
     typename G::Raw x[7];
     unsigned present;
   };
@@ -381,7 +399,8 @@ struct StencilOp {
   __device__ Pre<G> load(int row0, int nrows, const G& g) const {
     Pre<G> p;
     const int t = threadIdx.x;
-    const int i = row0 + min(t, nrows - 1);   // rows past the tile repeat its last row
+    // rows past the tile repeat its last row; a tile past the end of the matrix reads row n-1
+    const int i = min(row0 + max(0, min(t, nrows - 1)), n - 1);
     const int ix = i % nx;
     const int rest = i / nx;
     const int iy = rest % ny;
@@ -395,7 +414,7 @@ struct StencilOp {
 #pragma unroll
     for (int q = 0; q < 7; ++q) {
       const int plane = three ? q : (q == 0 ? 0 : q == 6 ? 4 : q - 1);
-      p.c[q] = coef[(size_t)plane * n + i];
+      p.c[q] = coef[(size_t)plane * ldp + i];
       const long long k = (long long)i + off[q];
       p.x[q] = g.load((int)(k < 0 ? 0 : k >= n ? n - 1 : k));
       p.present |= in[q] ? 1u << q : 0u;
@@ -411,7 +430,8 @@ struct StencilOp {
     if ((int)threadIdx.x >= nrows) return 0.0;
     double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < 7; ++q) s += (p.present >> q) & 1u ? p.c[q] * g.value(p.x[q]) : 0.0;
+    for (int q = 0; q < 7; ++q)
+      s += (p.present >> q) & 1u ? (double)p.c[q] * g.value(p.x[q]) : 0.0;
     return s;
   }
   template <class G>
@@ -420,34 +440,51 @@ struct StencilOp {
   }
 };
 
-// Reads columns of a column-major n x k FP64 basis through one buffer descriptor: the column
-// offset is a uniform scalar (i * ldv * 8 bytes) and the row offset a single per-lane 32-bit
-// value, so a thread reading 30 columns of its row holds no per-column addresses. Requires
-// the basis to span fewer than 2^31 bytes (checked on the host); loads outside the described
-// range return 0.
-struct ColumnReader {
+using StencilOp = StencilOpT<double>;
+
+// Reads columns of a column-major n x k basis stored as T (double or float) through one buffer
+// descriptor: the column offset is a uniform scalar (i * ldv * sizeof(T) bytes) and the row
+// offset a single per-lane 32-bit value, so a thread reading 30 columns of its row holds no
+// per-column addresses. Requires the basis to span fewer than 2^31 bytes (checked on the
+// host). Values are returned as double.
+template <class T>
+struct ColumnReaderT {
   __amdgpu_buffer_rsrc_t rsrc;
   int ld_bytes;
-  __device__ ColumnReader(const double* base, size_t ldv, int cols) {
-    rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0,
-                                             (int)(ldv * 8 * (size_t)cols), 0x00020000);
-    ld_bytes = (int)(ldv * 8);
+  __device__ ColumnReaderT(const T* base, size_t ldv, int cols) {
+    rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0,
+                                             (int)(ldv * sizeof(T) * (size_t)cols), 0x00020000);
+    ld_bytes = (int)(ldv * sizeof(T));
   }
-  __device__ double load(int col, int row) const {
-    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
-    const u2 v = __builtin_amdgcn_raw_buffer_load_b64(rsrc, row * 8, col * ld_bytes, 0);
-    return __builtin_bit_cast(double, v);
+  __device__ T raw(int col, int row) const {
+    if constexpr (sizeof(T) == 8) {
+      typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+      const u2 v = __builtin_amdgcn_raw_buffer_load_b64(rsrc, row * 8, col * ld_bytes, 0);
+      return __builtin_bit_cast(double, v);
+    } else {
+      const unsigned int v = __builtin_amdgcn_raw_buffer_load_b32(rsrc, row * 4, col * ld_bytes, 0);
+      return __builtin_bit_cast(float, v);
+    }
   }
+  __device__ double load(int col, int row) const { return (double)raw(col, row); }
 };
 
 // Same interface with plain 64-bit addressing, for bases of 2^31 bytes or more.
-struct PointerReader {
-  const double* base;
+template <class T>
+struct PointerReaderT {
+  const T* base;
   size_t ldv;
-  __device__ PointerReader(const double* b, size_t l, int) : base(b), ldv(l) {}
-  __device__ double load(int col, int row) const { return base[(size_t)col * ldv + row]; }
+  __device__ PointerReaderT(const T* b, size_t l, int) : base(b), ldv(l) {}
+  __device__ T raw(int col, int row) const { return base[(size_t)col * ldv + row]; }
+  __device__ double load(int col, int row) const { return (double)raw(col, row); }
 };
 
-inline bool fits_buffer(size_t ldv, int cols) { return ldv * 8 * (size_t)cols < (size_t(1) << 31); }
+using ColumnReader = ColumnReaderT<double>;
+using PointerReader = PointerReaderT<double>;
+
+template <class T>
+inline bool fits_buffer(size_t ldv, int cols) {
+  return ldv * sizeof(T) * (size_t)cols < (size_t(1) << 31);
+}
 
 }  // namespace gsk

@@ -33,7 +33,7 @@ struct Mat {
     return 12.0 * (double)csr.nnz + 4.0 * ((double)csr.n + 1);
   }
   CsrOp csr_op() const { return CsrOp{csr.rp, csr.ci, csr.val}; }
-  StencilOp stencil_op() const { return StencilOp{coef, n, nx, ny, nz}; }
+  StencilOp stencil_op() const { return StencilOp{coef, n, nx, ny, nz, (size_t)n}; }
 };
 
 struct SolveParams {
@@ -79,6 +79,9 @@ inline Workspace carve(void* ws, int n) {
 }
 
 size_t workspace_bytes(int method, int n, int m);
+// Exact size for a given matrix (the mixed-precision GMRES keeps an FP32 copy of its values).
+size_t workspace_bytes_for(const Mat& A, int method, int m);
+size_t mixed_matrix_floats(const Mat& A);
 
 // Flat validity scan of a CSR matrix (no indirect loads): row_ptr[0] == 0, non-decreasing,
 // row_ptr[n] == nnz, every column index in [0, n). Sets flags[0] on failure.
@@ -99,6 +102,9 @@ SolveResult arnoldi_run(const Mat& A, const double* r0, int m, double* V, int64_
                         double* H, void* ws, double eps_b, hipStream_t s);
 SolveResult bicgstab_solve(const Mat& A, const double* b, double* x, const SolveParams& prm,
                            void* ws, hipStream_t s);
+// GMRES(m) with FP32 Arnoldi cycles and FP64 restarts (iterative refinement).
+SolveResult gmres_mixed_solve(const Mat& A, const double* b, double* x, int m,
+                              const SolveParams& prm, void* ws, hipStream_t s);
 
 // Small pinned host buffer for status read-back (one per thread, allocated on first use).
 Summary* pinned_summaries();

@@ -21,7 +21,7 @@ ERR_INVALID_ARG, ERR_ZERO_ROW, ERR_NONFINITE, ERR_WORKSPACE, ERR_DEVICE = -1, -2
 CONVERGED, MAXIT, BREAKDOWN, STAGNATED = 0, 1, 2, 3
 STATUS_NAMES = {CONVERGED: "converged", MAXIT: "maxit", BREAKDOWN: "breakdown",
                 STAGNATED: "stagnated"}
-METHOD_GS, METHOD_GMRES, METHOD_BICGSTAB, METHOD_ARNOLDI = 0, 1, 2, 3
+METHOD_GS, METHOD_GMRES, METHOD_BICGSTAB, METHOD_ARNOLDI, METHOD_GMRES_MIXED = 0, 1, 2, 3, 4
 MAX_RESTART = 64
 BRK_NONE, BRK_SIGMA, BRK_OMEGA, BRK_RHO, BRK_GIVENS = 0, 1, 2, 3, 4
 
@@ -82,6 +82,8 @@ def _load() -> ctypes.CDLL:
     lib.gsk_default_options.restype = None
     lib.gsk_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     lib.gsk_workspace_bytes.restype = sz
+    lib.gsk_workspace_bytes_for.argtypes = [P(Matrix), ctypes.c_int32, ctypes.c_int32]
+    lib.gsk_workspace_bytes_for.restype = sz
     lib.gsk_gs_scale.argtypes = [P(Csr), vp, ctypes.c_int32, vp, vp, vp, vp, vp, sz, vp]
     lib.gsk_gs_scale.restype = ctypes.c_int
     lib.gsk_spmv.argtypes = [P(Matrix), vp, vp, vp]
@@ -95,6 +97,9 @@ def _load() -> ctypes.CDLL:
     lib.gsk_gmres.argtypes = [P(Matrix), vp, vp, ctypes.c_int32, ctypes.c_double, P(Options),
                               P(InfoStruct), vp, sz, vp]
     lib.gsk_gmres.restype = ctypes.c_int
+    lib.gsk_gmres_mixed.argtypes = [P(Matrix), vp, vp, ctypes.c_int32, ctypes.c_double,
+                                    P(Options), P(InfoStruct), vp, sz, vp]
+    lib.gsk_gmres_mixed.restype = ctypes.c_int
     lib.gsk_bicgstab.argtypes = [P(Matrix), vp, vp, ctypes.c_double, P(Options), P(InfoStruct),
                                  vp, sz, vp]
     lib.gsk_bicgstab.restype = ctypes.c_int
@@ -207,13 +212,32 @@ def workspace_bytes(method: int, n: int, m: int = 0) -> int:
     return int(lib.gsk_workspace_bytes(method, n, m))
 
 
+def workspace_bytes_for(A, method: int, m: int = 0) -> int:
+    """Exact workspace bytes of `method` for the matrix A (CsrMatrix or StencilMatrix)."""
+    c = A.c_matrix()
+    return int(lib.gsk_workspace_bytes_for(ctypes.byref(c), method, m))
+
+
+def _aligned(nbytes: int, device) -> torch.Tensor:
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + nbytes]
+
+
 def workspace(method: int, n: int, m: int = 0, device="cuda") -> torch.Tensor:
     nbytes = workspace_bytes(method, n, m)
     if nbytes == 0:
         raise GskError(ERR_INVALID_ARG, f"no workspace size for method={method} n={n} m={m}")
-    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
-    off = (-ws.data_ptr()) % 256
-    return ws[off:off + nbytes]
+    return _aligned(nbytes, device)
+
+
+def workspace_for(A, method: int, m: int = 0) -> torch.Tensor:
+    """A 256-byte aligned workspace of workspace_bytes_for(A, method, m) bytes."""
+    nbytes = workspace_bytes_for(A, method, m)
+    if nbytes == 0:
+        raise GskError(ERR_INVALID_ARG, lib.gsk_last_error().decode() or
+                       f"no workspace size for method={method} m={m}")
+    return _aligned(nbytes, A.device)
 
 
 def default_options() -> Options:
@@ -298,20 +322,24 @@ def _info(s: InfoStruct) -> Info:
                 s.relres_recursive, s.relres_true, s.breakdown_test)
 
 
+def _x_start(b, x0, x_out, n):
+    if x_out is not None:
+        x = _vec(x_out, n, "x_out")
+        if x0 is None:
+            x.zero_()
+        elif x0.data_ptr() != x.data_ptr():
+            x.copy_(x0)
+        return x
+    return torch.zeros_like(b) if x0 is None else _vec(x0, n, "x0").clone()
+
+
 def gmres(A, b: torch.Tensor, x0: Optional[torch.Tensor] = None, m: int = 30,
           tol: float = 1e-8, *, maxit: Optional[int] = None, breakdown_eps=None,
           stop_weights: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
           x_out: Optional[torch.Tensor] = None):
     """Restarted GMRES(m) with CGS2 Arnoldi. Returns (x, Info)."""
     _vec(b, A.n, "b")
-    if x_out is not None:
-        x = _vec(x_out, A.n, "x_out")
-        if x0 is None:
-            x.zero_()
-        elif x0.data_ptr() != x.data_ptr():
-            x.copy_(x0)
-    else:
-        x = torch.zeros_like(b) if x0 is None else _vec(x0, A.n, "x0").clone()
+    x = _x_start(b, x0, x_out, A.n)
     if ws is None:
         ws = workspace(METHOD_GMRES, A.n, m, A.device)
     o = _options(maxit, breakdown_eps, stop_weights, None, A.n)
@@ -323,20 +351,32 @@ def gmres(A, b: torch.Tensor, x0: Optional[torch.Tensor] = None, m: int = 30,
     return x, _info(info)
 
 
+def gmres_mixed(A, b: torch.Tensor, x0: Optional[torch.Tensor] = None, m: int = 30,
+                tol: float = 1e-8, *, maxit: Optional[int] = None, breakdown_eps=None,
+                stop_weights: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
+                x_out: Optional[torch.Tensor] = None):
+    """GMRES(m) with FP32 Arnoldi cycles and FP64 restarts (iterative refinement). x, b and
+    the matrix stay FP64; the FP32 copies live in the workspace. Returns (x, Info)."""
+    _vec(b, A.n, "b")
+    x = _x_start(b, x0, x_out, A.n)
+    if ws is None:
+        ws = workspace_for(A, METHOD_GMRES_MIXED, m)
+    o = _options(maxit, breakdown_eps, stop_weights, None, A.n)
+    info = InfoStruct()
+    c = A.c_matrix()
+    _check(lib.gsk_gmres_mixed(ctypes.byref(c), b.data_ptr(), x.data_ptr(), int(m), float(tol),
+                               ctypes.byref(o), ctypes.byref(info), ws.data_ptr(), ws.numel(),
+                               _stream(A.device)))
+    return x, _info(info)
+
+
 def bicgstab(A, b: torch.Tensor, x0: Optional[torch.Tensor] = None,
              tol: float = 1e-8, *, maxit: Optional[int] = None, breakdown_eps=None,
              stop_weights: Optional[torch.Tensor] = None, check_every: Optional[int] = None,
              ws: Optional[torch.Tensor] = None, x_out: Optional[torch.Tensor] = None):
     """Bi-CGSTAB. Returns (x, Info)."""
     _vec(b, A.n, "b")
-    if x_out is not None:
-        x = _vec(x_out, A.n, "x_out")
-        if x0 is None:
-            x.zero_()
-        elif x0.data_ptr() != x.data_ptr():
-            x.copy_(x0)
-    else:
-        x = torch.zeros_like(b) if x0 is None else _vec(x0, A.n, "x0").clone()
+    x = _x_start(b, x0, x_out, A.n)
     if ws is None:
         ws = workspace(METHOD_BICGSTAB, A.n, 0, A.device)
     o = _options(maxit, breakdown_eps, stop_weights, check_every, A.n)

@@ -1,0 +1,190 @@
+"""Mixed-precision GMRES(m) (FP32 Arnoldi cycles, FP64 restarts) through the C ABI.
+
+Bars: against the oracle's mixed-precision GMRES on the same seeded systems, equal status,
+Arnoldi steps within one cycle (m) or 5%, and at tol 1e-10 a solution within 1e-8 of the
+oracle's; the FP64 refinement must reach residuals far below float precision; stencil and
+CSR operators agree to rounding. At the full 160^3 size the residual of the returned solution
+is recomputed independently by the oracle's FP64 product.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_0812_2769_amd import problems
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0812_2769_amd import gsk
+    return gsk
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def grid_of(P):
+    d = list(P.dims) + [1] * (3 - len(P.dims))
+    return d[0], d[1], d[2]
+
+
+def oracle_scaled(P, p=2):
+    vo, bo, nrm, w = oracle.gs_scale(P, P.b, p)
+    S = P.copy()
+    S.val, S.b = vo, bo
+    return S, w
+
+
+def gpu_scaled(G, P, p=2, stencil=True):
+    A = G.CsrMatrix.from_problem(P)
+    As, bs, _, w = G.gs_scale(A, dev(P.b), p, want_weights=(p != 2))
+    M = G.stencil_from_csr(As, *grid_of(P)) if stencil else As
+    return M, bs, w
+
+
+CASES = {
+    "c2_16_gs2": (lambda: problems.config2(16), 2, 30, 1e-10),
+    "c2_16_gs1": (lambda: problems.config2(16), 1, 30, 1e-10),
+    "c3_32": (lambda: problems.config3(32, blocks_per_axis=4), 2, 30, 1e-8),
+    "lap_ragged": (lambda: problems.laplacian((13, 11, 7), conv=(40.0, -25.0, 10.0)), 2, 20,
+                   1e-10),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_mixed_matches_oracle(G, case):
+    maker, p, m, tol = CASES[case]
+    P = maker()
+    S, w_o = oracle_scaled(P, p)
+    xo, io = oracle.gmres_ir(S, S.b, m=m, tol=tol, weights=None if p == 2 else w_o)
+    M, bs, w = gpu_scaled(G, P, p)
+    xg, ig = G.gmres_mixed(M, bs, m=m, tol=tol, stop_weights=w)
+    assert ig.status == io.status == G.CONVERGED, (ig, io)
+    assert abs(ig.iters - io.iters) <= max(m, 0.05 * io.iters), (ig.iters, io.iters)
+    assert ig.relres_true < tol
+    xg = host(xg)
+    cond_bar = 1e-8 if tol <= 1e-10 else 1e-5
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= cond_bar
+
+
+def test_mixed_rounding_sensitive_case_matches_oracle_spread(G):
+    """Restarted GMRES on the 2D jump problem is chaotic under rounding: perturbing A at
+    float level (relative 2^-23) spreads the oracle's mixed-precision step count over
+    478-604 and the GPU's over 400-602, so single runs cannot be compared step for step.
+    Both sides solve the same 21 perturbed systems; all must converge and the medians agree
+    within 10%. (FP64-ulp perturbations would not do: the FP32 copy of A erases most of them
+    on the GPU while the oracle still sees them through its FP64 residual.)"""
+    P = problems.config1(24)
+    S, _ = oracle_scaled(P)
+    rng = np.random.default_rng(0)
+    it_o, it_g = [], []
+    A = G.CsrMatrix.from_problem(P)
+    for k in range(21):
+        val = S.val if k == 0 else S.val * (1 + 2.0 ** -23 * rng.integers(-2, 3, size=S.val.shape))
+        T = S.copy()
+        T.val = val
+        _, io = oracle.gmres_ir(T, T.b, m=40, tol=1e-8)
+        Mg = G.stencil_from_csr(A.with_values(dev(val)), *grid_of(P))
+        _, ig = G.gmres_mixed(Mg, dev(T.b), m=40, tol=1e-8)
+        assert io.status == ig.status == G.CONVERGED
+        it_o.append(io.iters)
+        it_g.append(ig.iters)
+    assert np.median(it_g) == pytest.approx(np.median(it_o), rel=0.10), (it_g, it_o)
+
+
+def test_mixed_reaches_fp64_accuracy(G):
+    # 1e-13 is far below float precision: only the FP64 residual and update reach it.
+    P = problems.laplacian((24, 20, 6), conv=(30.0, 10.0, 5.0))
+    M, bs, _ = gpu_scaled(G, P)
+    x, info = G.gmres_mixed(M, bs, m=30, tol=1e-13)
+    assert info.status == G.CONVERGED and info.relres_true < 1e-13
+    S, _ = oracle_scaled(P)
+    r = S.b - oracle.spmv(S, host(x))
+    assert np.linalg.norm(r) / np.linalg.norm(S.b) < 1e-13
+
+
+def test_mixed_stencil_and_csr_agree(G):
+    # The FP32 copies hold the same values, but the stencil product runs two tiles per
+    # workgroup (RPT = 2) and the CSR product one, so the dot products group their partial
+    # sums differently: the runs agree to rounding, not bit for bit.
+    P = problems.config2(14)
+    Ms, bs, _ = gpu_scaled(G, P, stencil=True)
+    Mc, bc, _ = gpu_scaled(G, P, stencil=False)
+    xs, i_s = G.gmres_mixed(Ms, bs, m=30, tol=1e-10)
+    xc, i_c = G.gmres_mixed(Mc, bc, m=30, tol=1e-10)
+    assert i_s.status == i_c.status == G.CONVERGED
+    assert abs(i_s.iters - i_c.iters) <= 30
+    assert np.linalg.norm(host(xs) - host(xc)) / np.linalg.norm(host(xc)) <= 1e-8
+
+
+def test_mixed_close_to_fp64_gpu(G):
+    P = problems.config2(20)
+    M, bs, _ = gpu_scaled(G, P)
+    x64, i64 = G.gmres(M, bs, m=30, tol=1e-10)
+    xm, im = G.gmres_mixed(M, bs, m=30, tol=1e-10)
+    assert i64.status == im.status == G.CONVERGED
+    assert abs(im.iters - i64.iters) <= 30
+    assert np.linalg.norm(host(xm) - host(x64)) / np.linalg.norm(host(x64)) <= 1e-8
+
+
+def test_mixed_workspace_and_errors(G):
+    P = problems.config2(10)
+    A = G.CsrMatrix.from_problem(P)
+    M = G.stencil_from_csr(A, *grid_of(P))
+    n = P.n
+    # stencil: equals the generic figure; CSR: holds nnz floats instead of 7 n
+    assert G.workspace_bytes_for(M, G.METHOD_GMRES_MIXED, 30) == \
+        G.workspace_bytes(G.METHOD_GMRES_MIXED, n, 30)
+    assert G.workspace_bytes_for(A, G.METHOD_GMRES_MIXED, 30) > 0
+    assert G.workspace_bytes_for(M, G.METHOD_GMRES, 30) == G.workspace_bytes(G.METHOD_GMRES, n, 30)
+    full = G.workspace_for(M, G.METHOD_GMRES_MIXED, 30)
+    small = full[: full.numel() - 256]
+    with pytest.raises(G.GskError) as e:
+        G.gmres_mixed(M, dev(P.b), m=30, tol=1e-8, ws=small)
+    assert e.value.code == G.ERR_WORKSPACE
+    with pytest.raises(G.GskError):
+        G.gmres_mixed(M, dev(P.b), m=0, tol=1e-8)
+
+
+def test_mixed_repeatable(G):
+    P = problems.config2(12)
+    M, bs, _ = gpu_scaled(G, P)
+    x1, i1 = G.gmres_mixed(M, bs, m=20, tol=1e-10)
+    x2, i2 = G.gmres_mixed(M, bs, m=20, tol=1e-10)
+    assert (i1.iters, i1.restarts) == (i2.iters, i2.restarts)
+    assert np.array_equal(host(x1), host(x2))
+
+
+@pytest.fixture(scope="module")
+def c3():
+    return problems.config3()
+
+
+def test_c3_full_size_mixed_vs_fp64(G, c3):
+    """160^3 checkerboard system (n = 4,096,000), GS(2) then GMRES(30), the configuration's
+    own workload. Unpreconditioned restarted GMRES(30) needs far more than the paper's
+    10,000-step cap to reach 1e-8 here (about 6e-5 after 3,000 steps), so the check runs 20
+    cycles: the mixed solver must track FP64 GMRES(30) (true residuals within a factor 2 after
+    the same 600 steps), and the residual it reports must equal the FP64 residual of the
+    returned solution recomputed independently by the oracle."""
+    P = c3
+    M, bs, _ = gpu_scaled(G, P)
+    x64, i64 = G.gmres(M, bs, m=30, tol=1e-8, maxit=600)
+    xm, im = G.gmres_mixed(M, bs, m=30, tol=1e-8, maxit=600)
+    assert i64.status == im.status == G.MAXIT and i64.iters == im.iters == 600
+    assert 0.5 < im.relres_true / i64.relres_true < 2.0, (im, i64)
+    S, _ = oracle_scaled(P)
+    for x, info in ((xm, im), (x64, i64)):
+        r = S.b - oracle.spmv(S, host(x))
+        rel = np.linalg.norm(r) / np.linalg.norm(S.b)   # x0 = 0
+        assert rel == pytest.approx(info.relres_true, rel=1e-6)
