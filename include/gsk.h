@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define GSK_VERSION 1
+#define GSK_VERSION 2
 
 /* Return codes */
 #define GSK_OK 0
@@ -295,6 +295,86 @@ typedef struct gsk_probe_result {
 
 int gsk_probe_begin(int32_t kernel_class, int32_t sample_every);
 int gsk_probe_end(gsk_probe_result* out);
+
+/*
+ * Batched Bi-CGSTAB and the solve engine (continuous batching). The paper solves one system
+ * at a time (section 2); GS scaling makes every row independent and Bi-CGSTAB needs only
+ * products and dot products (section 3 calls it inherently parallel), so many independent
+ * systems can share every launch. Each system is solved exactly as gsk_bicgstab solves it
+ * (same operations, same per-tile partial sums in the same order), so it returns bit for
+ * bit the same x and gsk_info alone, in a batch, or admitted while others run.
+ *
+ * The engine works in a caller-owned device workspace of gsk_engine_workspace_bytes(max_rows,
+ * max_systems) bytes: room for max_rows rows of solver vectors (each system takes its n rows
+ * rounded up to a multiple of 256) and max_systems control blocks. A system's matrix (CSR or
+ * stencil), b, x and stop weights stay in the caller's device memory, untouched except for
+ * x, until the system is reported done. The engine object itself is a host allocation.
+ *
+ * Time runs in chunks: gsk_engine_run(e, c) enqueues c chunks on the engine's stream, each
+ * the residual launch (which starts newly submitted systems and verifies convergence claims)
+ * followed by check_every Bi-CGSTAB iterations of every admitted system; systems that are
+ * done simply skip. gsk_engine_poll reads every system's status after the last enqueued chunk
+ * and retires the finished ones, freeing their rows and slots for new submissions.
+ * With flags & GSK_ENGINE_GRAPH the first chunk is captured in a HIP graph and every chunk
+ * is a replay of it (needs a non-default stream and an even check_every).
+ * An engine is not thread-safe; use one per host thread and stream.
+ */
+typedef struct gsk_engine gsk_engine;
+
+#define GSK_ENGINE_GRAPH 1
+/* gsk_engine_submit: the system did not fit (no free slot or not enough contiguous rows). */
+#define GSK_FULL 1
+
+typedef struct gsk_result {
+    int64_t tag;        /* the tag given at submission                                    */
+    gsk_info info;      /* as gsk_bicgstab would return it; status < 0: invalid CSR        */
+} gsk_result;
+
+typedef struct gsk_engine_usage {
+    int32_t active;             /* systems admitted and not yet retired                    */
+    int32_t max_systems;
+    int64_t max_rows;
+    int64_t free_rows;          /* rows not held by any system                             */
+    int64_t largest_free_rows;  /* largest system (in rows) that fits now                  */
+} gsk_engine_usage;
+
+size_t gsk_engine_workspace_bytes(int64_t max_rows, int32_t max_systems);
+
+/* Errors: GSK_ERR_INVALID_ARG (sizes, check_every out of [1, 256], GRAPH with the default
+ * stream or an odd check_every), GSK_ERR_WORKSPACE (NULL, misaligned or too small). */
+int gsk_engine_create(void* ws, size_t ws_bytes, int64_t max_rows, int32_t max_systems,
+                      int32_t check_every, int32_t flags, void* stream, gsk_engine** out);
+
+/* Admits one system A x = b (normally GS-scaled); x holds x0 and receives the solution.
+ * tol and opt as for gsk_bicgstab (opt->check_every is ignored: the engine's applies).
+ * Returns GSK_OK, GSK_FULL (nothing changed; retry after a poll has retired systems), or an
+ * error for invalid arguments. Enqueues a small initialisation on the engine's stream. */
+int gsk_engine_submit(gsk_engine* e, const gsk_matrix* A, const double* b, double* x,
+                      double tol, const gsk_options* opt, int64_t tag);
+
+/* Enqueues `chunks` chunks (asynchronous). */
+int gsk_engine_run(gsk_engine* e, int32_t chunks);
+
+/* Retires the systems finished at the end of the last enqueued chunk. wait != 0 blocks until
+ * that chunk has run; wait == 0 returns *n_out = 0 if it has not. At most max_out results are
+ * returned per call (the rest stay admitted and are reported by the next poll after another
+ * run). */
+int gsk_engine_poll(gsk_engine* e, int32_t wait, gsk_result* out, int32_t max_out,
+                    int32_t* n_out);
+
+int gsk_engine_get_usage(gsk_engine* e, gsk_engine_usage* u);
+
+/* Synchronises the engine's stream and frees the host object. */
+int gsk_engine_destroy(gsk_engine* e);
+
+/* Solves count independent systems in one batch (an engine created in ws, every system
+ * submitted, chunks run until all are done). b[i], x[i]: device pointers of system i; info:
+ * host array of count. Workspace: gsk_bicgstab_batch_workspace_bytes(count, n) with n the
+ * host array of the systems' row counts. */
+size_t gsk_bicgstab_batch_workspace_bytes(int32_t count, const int32_t* n);
+int gsk_bicgstab_batch(int32_t count, const gsk_matrix* A, const double* const* b,
+                       double* const* x, double tol, const gsk_options* opt, gsk_info* info,
+                       void* ws, size_t ws_bytes, void* stream);
 
 /* Message for the last error returned on this thread ("" if none). */
 const char* gsk_last_error(void);

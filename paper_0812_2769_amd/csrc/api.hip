@@ -355,6 +355,187 @@ int gsk_probe_end(gsk_probe_result* out) {
 
 const char* gsk_last_error(void) { return g_err.c_str(); }
 
+// ---------------------------------------------------------------------------------------
+// Engine (batched Bi-CGSTAB)
+// ---------------------------------------------------------------------------------------
+struct gsk_engine {
+  gsk::Engine* impl;
+  int64_t max_rows;
+  int32_t max_systems;
+};
+
+size_t gsk_engine_workspace_bytes(int64_t max_rows, int32_t max_systems) {
+  return gsk::engine_workspace_bytes(max_rows, max_systems);
+}
+
+int gsk_engine_create(void* ws, size_t ws_bytes, int64_t max_rows, int32_t max_systems,
+                      int32_t check_every, int32_t flags, void* stream, gsk_engine** out) {
+  g_err.clear();
+  if (!out) return set_err(GSK_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (max_rows < 1 || max_rows > ((int64_t)1 << 40) || max_systems < 1 ||
+      max_systems > (1 << 20))
+    return set_err(GSK_ERR_INVALID_ARG, "max_rows and max_systems must be positive");
+  if (check_every < 1 || check_every > 256)
+    return set_err(GSK_ERR_INVALID_ARG, "check_every must be in [1, 256]");
+  const bool graph = (flags & GSK_ENGINE_GRAPH) != 0;
+  if (graph && (!stream || (check_every & 1)))
+    return set_err(GSK_ERR_INVALID_ARG,
+                   "GSK_ENGINE_GRAPH needs a non-default stream and an even check_every");
+  int rc = check_ws(ws, ws_bytes, gsk::engine_workspace_bytes(max_rows, max_systems));
+  if (rc) return rc;
+  gsk::Engine* impl = nullptr;
+  rc = gsk::engine_create(ws, ws_bytes, max_rows, max_systems, check_every, graph,
+                          static_cast<hipStream_t>(stream), &impl);
+  if (rc == -4) return set_err(GSK_ERR_WORKSPACE, "engine workspace too small");
+  if (rc) return set_err(GSK_ERR_DEVICE, "engine: pinned host buffers or events unavailable");
+  *out = new gsk_engine{impl, max_rows, max_systems};
+  return GSK_OK;
+}
+
+int gsk_engine_submit(gsk_engine* e, const gsk_matrix* A, const double* b, double* x,
+                      double tol, const gsk_options* opt, int64_t tag) {
+  g_err.clear();
+  if (!e) return set_err(GSK_ERR_INVALID_ARG, "engine is NULL");
+  Mat M;
+  int rc = check_matrix(A, M);
+  if (rc) return rc;
+  if (!b || !x) return set_err(GSK_ERR_INVALID_ARG, "b or x is NULL");
+  SolveParams prm;
+  rc = params_from(opt, prm, tol);
+  if (rc) return rc;
+  rc = gsk::engine_submit(e->impl, M, b, x, prm, tag);
+  if (rc == 1) return GSK_FULL;
+  if (rc) return set_err(GSK_ERR_DEVICE, "engine submit: HIP failure");
+  return GSK_OK;
+}
+
+int gsk_engine_run(gsk_engine* e, int32_t chunks) {
+  g_err.clear();
+  if (!e) return set_err(GSK_ERR_INVALID_ARG, "engine is NULL");
+  if (chunks < 0) return set_err(GSK_ERR_INVALID_ARG, "chunks must be >= 0");
+  if (chunks == 0) return GSK_OK;
+  if (gsk::engine_run(e->impl, chunks))
+    return set_err(GSK_ERR_DEVICE, "engine run: HIP failure (%s)",
+                   hipGetErrorString(hipGetLastError()));
+  return GSK_OK;
+}
+
+int gsk_engine_poll(gsk_engine* e, int32_t wait, gsk_result* out, int32_t max_out,
+                    int32_t* n_out) {
+  g_err.clear();
+  if (!e || !n_out || (max_out > 0 && !out) || max_out < 0)
+    return set_err(GSK_ERR_INVALID_ARG, "engine, out or n_out invalid");
+  *n_out = 0;
+  std::vector<gsk::EngineDone> done((size_t)(max_out > 0 ? max_out : 0));
+  int n = 0;
+  if (gsk::engine_poll(e->impl, wait != 0, done.data(), max_out, &n))
+    return set_err(GSK_ERR_DEVICE, "engine poll: HIP failure");
+  for (int i = 0; i < n; ++i) {
+    out[i].tag = done[i].tag;
+    fill_info(&out[i].info, done[i].sum);
+  }
+  *n_out = n;
+  return GSK_OK;
+}
+
+int gsk_engine_get_usage(gsk_engine* e, gsk_engine_usage* u) {
+  g_err.clear();
+  if (!e || !u) return set_err(GSK_ERR_INVALID_ARG, "engine or usage is NULL");
+  int active = 0;
+  int64_t free_rows = 0, largest = 0;
+  gsk::engine_usage(e->impl, &active, &free_rows, &largest);
+  u->active = active;
+  u->max_systems = e->max_systems;
+  u->max_rows = e->max_rows;
+  u->free_rows = free_rows;
+  u->largest_free_rows = largest;
+  return GSK_OK;
+}
+
+int gsk_engine_destroy(gsk_engine* e) {
+  g_err.clear();
+  if (!e) return GSK_OK;
+  gsk::engine_destroy(e->impl);
+  delete e;
+  return GSK_OK;
+}
+
+static int64_t batch_rows(int32_t count, const int32_t* n) {
+  int64_t rows = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    if (n[i] < 1) return -1;
+    rows += ((int64_t)n[i] + BS - 1) / BS * BS;
+  }
+  return rows;
+}
+
+size_t gsk_bicgstab_batch_workspace_bytes(int32_t count, const int32_t* n) {
+  if (count < 1 || !n) return 0;
+  const int64_t rows = batch_rows(count, n);
+  if (rows < 1) return 0;
+  return gsk::engine_workspace_bytes(rows, count);
+}
+
+int gsk_bicgstab_batch(int32_t count, const gsk_matrix* A, const double* const* b,
+                       double* const* x, double tol, const gsk_options* opt, gsk_info* info,
+                       void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (count < 1 || !A || !b || !x || !info)
+    return set_err(GSK_ERR_INVALID_ARG, "count < 1 or a NULL array");
+  std::vector<int32_t> n(count);
+  for (int32_t i = 0; i < count; ++i) {
+    Mat M;
+    int rc = check_matrix(&A[i], M);
+    if (rc) return rc;
+    if (!b[i] || !x[i]) return set_err(GSK_ERR_INVALID_ARG, "b[%d] or x[%d] is NULL", i, i);
+    n[i] = M.n;
+  }
+  SolveParams prm;
+  int rc = params_from(opt, prm, tol);
+  if (rc) return rc;
+  const int64_t rows = batch_rows(count, n.data());
+  rc = check_ws(ws, ws_bytes, gsk::engine_workspace_bytes(rows, count));
+  if (rc) return rc;
+  gsk::Engine* e = nullptr;
+  if (gsk::engine_create(ws, ws_bytes, rows, count, prm.check_every, false,
+                         static_cast<hipStream_t>(stream), &e))
+    return set_err(GSK_ERR_DEVICE, "batch: engine creation failed");
+  for (int32_t i = 0; i < count; ++i) {
+    Mat M;
+    check_matrix(&A[i], M);
+    if (gsk::engine_submit(e, M, b[i], x[i], prm, i) != 0) {
+      gsk::engine_destroy(e);
+      return set_err(GSK_ERR_DEVICE, "batch: submission failed");
+    }
+  }
+  std::vector<gsk::EngineDone> done(count);
+  std::vector<char> seen(count, 0);
+  int left = count, bad = 0;
+  // Every system finishes within 4 maxit + 16 chunks (as in gsk_bicgstab).
+  const long max_chunks = (long)prm.maxit * 4 + 16;
+  for (long ch = 0; ch <= max_chunks && left > 0; ++ch) {
+    int got = 0;
+    if (gsk::engine_run(e, 1) || gsk::engine_poll(e, true, done.data(), count, &got)) {
+      gsk::engine_destroy(e);
+      return set_err(GSK_ERR_DEVICE, "batch: HIP failure");
+    }
+    for (int i = 0; i < got; ++i) {
+      const int k = (int)done[i].tag;
+      fill_info(&info[k], done[i].sum);
+      seen[k] = 1;
+      if (done[i].sum.status < 0) bad = 1;
+    }
+    left -= got;
+  }
+  gsk::engine_destroy(e);
+  if (left > 0) return set_err(GSK_ERR_DEVICE, "batch: systems did not finish");
+  if (bad)
+    return set_err(GSK_ERR_INVALID_ARG,
+                   "a system's CSR structure is invalid (its info.status is negative)");
+  return GSK_OK;
+}
+
 int gsk_gs_scale(const gsk_csr* A, const double* b, int32_t p, double* val_out, double* b_out,
                  double* row_norm, double* stop_weight, void* ws, size_t ws_bytes,
                  void* stream) {

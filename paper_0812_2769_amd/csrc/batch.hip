@@ -1,0 +1,753 @@
+// Batched Bi-CGSTAB and the solve engine: many independent systems share every launch.
+//
+// Each system is one Bi-CGSTAB solve of section 2 (shadow residual r^ = r0, the stop test of
+// section 2.2), exactly as in bicgstab.hip: the same kernels' arithmetic, the same tile
+// partition of its rows, the same per-tile partials summed in the same order. A system
+// therefore returns bit for bit the result it returns when solved alone with gsk_bicgstab,
+// whatever else shares the batch.
+//
+// Layout. The engine owns a workspace with room for max_rows rows of vectors (r, r^, p x2,
+// v x2, t) and max_systems control blocks. A system of n rows gets ceil(n / BS) consecutive
+// tiles of that row space (first fit over free tiles); its matrix, b, x and stop weights stay
+// in the caller's memory. A device table maps every tile to its system (or -1), so one
+// launch over all tiles serves every system; a finalize launch has one workgroup per system
+// slot and sums that system's tile partials.
+//
+// Time. The host enqueues chunks: the residual launch (which starts newly admitted systems
+// and verifies convergence claims), then check_every iterations. A chunk has fixed launch
+// shapes and arguments, so it can be captured once in a HIP graph and replayed. Between
+// chunks the host reads every slot's status and retires finished systems; new systems are
+// admitted between chunks (continuous batching).
+#include <map>
+#include <vector>
+
+#include "gsk_host.hpp"
+
+namespace gsk {
+
+// Per-system control block (the Bi-CGSTAB part of Ctl).
+struct BCtl {
+  Summary sum;
+  int maxit, first, has_w, bad;
+  double tol, eps_b, ref;
+  double rho, rho_old, alpha, omega, beta, rh_norm;
+};
+
+struct SysDesc {
+  int n, kind, nx, ny, nz, tile_off, ntiles, pad;
+  int64_t row_off;
+  const int* rp;
+  const int* ci;
+  const double* val;
+  const double* coef;
+  const double* b;
+  double* x;
+  const double* W;
+};
+
+struct BArgsB {
+  const SysDesc* sys;
+  const int* tile_sys;   // [max_tiles]: slot of each tile, -1 if free
+  BCtl* ctl;             // [max_systems]
+  double* partials;      // [4][max_tiles]
+  int max_tiles;
+  double* r;
+  double* rh;
+  double* p[2];
+  double* v[2];
+  double* t;
+  int par;               // buffer parity of this iteration
+};
+
+__device__ inline int batch_tile(const BArgsB& a, int& s) {
+  const int tile = logical_block();
+  s = tile < a.max_tiles ? a.tile_sys[tile] : -1;
+  return tile;
+}
+
+struct GatherPB {
+  const double* __restrict__ r;
+  const double* __restrict__ p;
+  const double* __restrict__ v;
+  double beta, omega;
+  int first;
+  struct Raw {
+    double r, p, v;
+  };
+  __device__ Raw load(int col) const { return Raw{r[col], p[col], v[col]}; }
+  __device__ double value(const Raw& a) const {
+    return first ? a.r : fma(beta, fma(-omega, a.v, a.p), a.r);
+  }
+  __device__ double operator()(int col) const { return value(load(col)); }
+};
+
+struct GatherSB {
+  const double* __restrict__ r;
+  const double* __restrict__ v;
+  double alpha;
+  struct Raw {
+    double r, v;
+  };
+  __device__ Raw load(int col) const { return Raw{r[col], v[col]}; }
+  __device__ double value(const Raw& a) const { return fma(-alpha, a.v, a.r); }
+  __device__ double operator()(int col) const { return value(load(col)); }
+};
+
+// The system's product over one tile (CSR or stencil, chosen per system).
+template <class G>
+__device__ inline double sys_tile(const SysDesc& d, int row0, int nrows, const G& g,
+                                  TileLds& L) {
+  if (d.kind == MAT_STENCIL) {
+    EmptyLds e;
+    const StencilOp op{d.coef, d.n, d.nx, d.ny, d.nz, (size_t)d.n};
+    return op.tile(row0, nrows, g, e);
+  }
+  const CsrOp op{d.rp, d.ci, d.val};
+  return op.tile(row0, nrows, g, L);
+}
+
+__global__ __launch_bounds__(64) void k_batch_init(BCtl* c, int maxit, double tol, double eps_b,
+                                                   int has_w) {
+  if (threadIdx.x != 0) return;
+  c->sum.state = ST_INIT;
+  c->sum.status = S_MAXIT;
+  c->sum.iters = 0;
+  c->sum.restarts = 0;
+  c->sum.half = 0;
+  c->sum.fails = 0;
+  c->sum.steps = 0;
+  c->sum.relres_rec = 1.0;
+  c->sum.relres_true = 1.0;
+  c->sum.brk = BRK_NONE;
+  c->maxit = maxit;
+  c->first = 1;
+  c->has_w = has_w;
+  c->bad = 0;
+  c->tol = tol;
+  c->eps_b = eps_b;
+  c->ref = 0.0;
+  c->rho = c->rho_old = c->alpha = c->omega = c->beta = c->rh_norm = 0.0;
+}
+
+// Flat validity scan of one system's CSR structure (no indirect loads): row_ptr[0] == 0,
+// non-decreasing, row_ptr[n] == nnz, every column index in [0, n). Marks the control block.
+__global__ __launch_bounds__(BS) void k_batch_validate(const int* __restrict__ rp,
+                                                       const int* __restrict__ ci, int n,
+                                                       int64_t nnz, BCtl* c) {
+  const int64_t stride = (int64_t)gridDim.x * BS;
+  const int64_t gid = (int64_t)blockIdx.x * BS + threadIdx.x;
+  bool bad = false;
+  for (int64_t i = gid; i <= n; i += stride) {
+    const int r = rp[i];
+    if (i == 0 && r != 0) bad = true;
+    if (i < n && r > rp[i + 1]) bad = true;
+    if (i == n && (int64_t)r != nnz) bad = true;
+  }
+  for (int64_t k = gid; k < nnz; k += stride) {
+    const int col = ci[k];
+    if (col < 0 || col >= n) bad = true;
+  }
+  if (bad) atomicOr(&c->bad, 1);
+}
+
+// R: r = b - A x, r^ = r for systems starting, verifying or finishing; ||r||^2, ||W r||^2.
+__global__ __launch_bounds__(BS) void k_batch_residual(BArgsB a) {
+  int s;
+  const int tile = batch_tile(a, s);
+  if (s < 0) return;
+  const SysDesc d = a.sys[s];
+  BCtl* c = a.ctl + s;
+  const int st = c->sum.state;
+  if (st != ST_INIT && st != ST_VERIFY && st != ST_FINAL) return;
+  if (c->bad) return;
+  __shared__ TileLds L;
+  __shared__ double red[NC_MAX * WAVES];
+  const int row0 = (tile - d.tile_off) * BS;
+  const int nrows = min(BS, d.n - row0);
+  const int t = threadIdx.x;
+  double acc[2] = {0.0, 0.0};
+  const double y = sys_tile(d, row0, nrows, GatherX{d.x}, L);
+  if (t < nrows) {
+    const int row = row0 + t;
+    const double r = d.b[row] - y;
+    if (st != ST_FINAL) {
+      a.r[d.row_off + row] = r;
+      a.rh[d.row_off + row] = r;
+    }
+    acc[0] = r * r;
+    if (d.W) {
+      const double wr = d.W[row] * r;
+      acc[1] = wr * wr;
+    }
+  }
+  block_partials<2>(acc, 2, a.partials, a.max_tiles, tile, red);
+}
+
+__global__ __launch_bounds__(BS) void k_batch_fin_residual(BArgsB a) {
+  const int s = blockIdx.x;
+  const SysDesc d = a.sys[s];
+  if (d.ntiles == 0) return;
+  BCtl* c = a.ctl + s;
+  const int st = c->sum.state;
+  if (st != ST_INIT && st != ST_VERIFY && st != ST_FINAL) return;
+  if (c->bad) {
+    if (threadIdx.x == 0) {
+      c->sum.state = ST_DONE;
+      c->sum.status = -1;
+    }
+    return;
+  }
+  __shared__ double out[8];
+  small_sums_strided<2>(a.partials + d.tile_off, d.ntiles, a.max_tiles, out);
+  if (threadIdx.x != 0) return;
+  const double nr = sqrt(out[0]);
+  const double nwr = d.W ? sqrt(out[1]) : nr;
+  if (st == ST_INIT) {
+    c->ref = nwr;
+    if (nwr == 0.0) {
+      c->sum.status = S_CONVERGED;
+      c->sum.relres_rec = 0.0;
+      c->sum.relres_true = 0.0;
+      c->sum.state = ST_DONE;
+      return;
+    }
+    if (c->maxit == 0) {
+      c->sum.status = S_MAXIT;
+      c->sum.state = ST_DONE;
+      return;
+    }
+  } else {
+    const double rt = nwr / c->ref;
+    c->sum.relres_true = rt;
+    if (st == ST_FINAL) {
+      c->sum.state = ST_DONE;
+      return;
+    }
+    if (rt < c->tol) {
+      c->sum.status = S_CONVERGED;
+      c->sum.state = ST_DONE;
+      return;
+    }
+    if (c->sum.iters >= c->maxit) {
+      c->sum.status = S_MAXIT;
+      c->sum.state = ST_DONE;
+      return;
+    }
+    c->sum.fails += 1;
+    if (c->sum.fails >= 3) {
+      c->sum.status = S_STAGNATED;
+      c->sum.state = ST_DONE;
+      return;
+    }
+    c->sum.restarts += 1;
+  }
+  c->rh_norm = nr;
+  c->rho = out[0];
+  c->sum.half = 0;
+  if (fabs(c->rho) <= c->eps_b * nr * nr) {
+    c->sum.status = S_BREAKDOWN;
+    c->sum.brk = BRK_RHO;
+    c->sum.state = ST_DONE;
+    return;
+  }
+  c->first = 1;
+  c->sum.state = ST_RUNNING;
+}
+
+// P: new p, v = A p; partials (r^, v), ||v||^2.
+__global__ __launch_bounds__(BS) void k_batch_p(BArgsB a) {
+  int s;
+  const int tile = batch_tile(a, s);
+  if (s < 0) return;
+  const SysDesc d = a.sys[s];
+  BCtl* c = a.ctl + s;
+  if (c->sum.state != ST_RUNNING) return;
+  const int q = a.par;
+  const int64_t o = d.row_off;
+  const GatherPB G{a.r + o, a.p[q] + o, a.v[q] + o, c->beta, c->omega, c->first};
+  __shared__ TileLds L;
+  __shared__ double red[NC_MAX * WAVES];
+  const int row0 = (tile - d.tile_off) * BS;
+  const int nrows = min(BS, d.n - row0);
+  const int t = threadIdx.x;
+  const double y = sys_tile(d, row0, nrows, G, L);
+  double acc[2] = {0.0, 0.0};
+  if (t < nrows) {
+    const int row = row0 + t;
+    a.p[q ^ 1][o + row] = G(row);
+    a.v[q ^ 1][o + row] = y;
+    acc[0] = a.rh[o + row] * y;
+    acc[1] = y * y;
+  }
+  block_partials<2>(acc, 2, a.partials, a.max_tiles, tile, red);
+}
+
+__global__ __launch_bounds__(BS) void k_batch_fin_p(BArgsB a) {
+  const int s = blockIdx.x;
+  const SysDesc d = a.sys[s];
+  if (d.ntiles == 0) return;
+  BCtl* c = a.ctl + s;
+  if (c->sum.state != ST_RUNNING) return;
+  __shared__ double out[8];
+  small_sums_strided<2>(a.partials + d.tile_off, d.ntiles, a.max_tiles, out);
+  if (threadIdx.x != 0) return;
+  const double sigma = out[0];
+  const double vn = sqrt(out[1]);
+  if (fabs(sigma) <= c->eps_b * c->rh_norm * vn) {
+    c->sum.status = S_BREAKDOWN;
+    c->sum.brk = BRK_SIGMA;
+    c->sum.state = ST_FINAL;
+    return;
+  }
+  c->alpha = c->rho / sigma;
+}
+
+// S: t = A s with s = r - alpha v; partials (t,s), (t,t), ||s||^2, ||W s||^2.
+__global__ __launch_bounds__(BS) void k_batch_s(BArgsB a) {
+  int s;
+  const int tile = batch_tile(a, s);
+  if (s < 0) return;
+  const SysDesc d = a.sys[s];
+  BCtl* c = a.ctl + s;
+  if (c->sum.state != ST_RUNNING) return;
+  const int64_t o = d.row_off;
+  const GatherSB G{a.r + o, a.v[a.par ^ 1] + o, c->alpha};
+  __shared__ TileLds L;
+  __shared__ double red[NC_MAX * WAVES];
+  const int row0 = (tile - d.tile_off) * BS;
+  const int nrows = min(BS, d.n - row0);
+  const int t = threadIdx.x;
+  const double y = sys_tile(d, row0, nrows, G, L);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (t < nrows) {
+    const int row = row0 + t;
+    const double sv = G(row);
+    a.t[o + row] = y;
+    acc[0] = y * sv;
+    acc[1] = y * y;
+    acc[2] = sv * sv;
+    if (d.W) {
+      const double ws = d.W[row] * sv;
+      acc[3] = ws * ws;
+    }
+  }
+  block_partials<4>(acc, 4, a.partials, a.max_tiles, tile, red);
+}
+
+__global__ __launch_bounds__(BS) void k_batch_fin_s(BArgsB a) {
+  const int s = blockIdx.x;
+  const SysDesc d = a.sys[s];
+  if (d.ntiles == 0) return;
+  BCtl* c = a.ctl + s;
+  if (c->sum.state != ST_RUNNING) return;
+  __shared__ double out[8];
+  small_sums_strided<4>(a.partials + d.tile_off, d.ntiles, a.max_tiles, out);
+  if (threadIdx.x != 0) return;
+  c->sum.iters += 1;
+  const double sn = sqrt(out[2]);
+  const double est = (d.W ? sqrt(out[3]) : sn) / c->ref;
+  c->sum.relres_rec = est;
+  if (est < c->tol) {
+    c->sum.half = 1;
+    c->sum.state = ST_HALF;
+    return;
+  }
+  const double ts = out[0], tt = out[1];
+  if (fabs(ts) <= c->eps_b * sqrt(tt) * sn) {
+    c->sum.status = S_BREAKDOWN;
+    c->sum.brk = BRK_OMEGA;
+    c->sum.state = ST_FINAL;
+    return;
+  }
+  c->omega = ts / tt;
+}
+
+// U: x += alpha p + omega s, r = s - omega t; partials (r^, r), ||r||^2, ||W r||^2.
+// After a half-step exit only x += alpha p is done.
+__global__ __launch_bounds__(BS) void k_batch_u(BArgsB a) {
+  int s;
+  const int tile = batch_tile(a, s);
+  if (s < 0) return;
+  const SysDesc d = a.sys[s];
+  BCtl* c = a.ctl + s;
+  const int st = c->sum.state;
+  if (st != ST_RUNNING && st != ST_HALF) return;
+  const int q = a.par ^ 1;
+  const int64_t o = d.row_off;
+  const double* p = a.p[q] + o;
+  const double* v = a.v[q] + o;
+  const double alpha = c->alpha, omega = c->omega;
+  __shared__ double red[NC_MAX * WAVES];
+  const int row = (tile - d.tile_off) * BS + threadIdx.x;
+  const bool mine = row < d.n;
+  if (st == ST_HALF) {
+    if (mine) d.x[row] = fma(alpha, p[row], d.x[row]);
+    return;
+  }
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (mine) {
+    const double sv = fma(-alpha, v[row], a.r[o + row]);
+    d.x[row] = fma(omega, sv, fma(alpha, p[row], d.x[row]));
+    const double r = fma(-omega, a.t[o + row], sv);
+    a.r[o + row] = r;
+    acc[0] = a.rh[o + row] * r;
+    acc[1] = r * r;
+    if (d.W) {
+      const double wr = d.W[row] * r;
+      acc[2] = wr * wr;
+    }
+  }
+  block_partials<3>(acc, 3, a.partials, a.max_tiles, tile, red);
+}
+
+__global__ __launch_bounds__(BS) void k_batch_fin_u(BArgsB a) {
+  const int s = blockIdx.x;
+  const SysDesc d = a.sys[s];
+  if (d.ntiles == 0) return;
+  BCtl* c = a.ctl + s;
+  const int st = c->sum.state;
+  if (st != ST_RUNNING && st != ST_HALF) return;
+  if (st == ST_HALF) {
+    if (threadIdx.x == 0) c->sum.state = ST_VERIFY;
+    return;
+  }
+  __shared__ double out[8];
+  small_sums_strided<3>(a.partials + d.tile_off, d.ntiles, a.max_tiles, out);
+  if (threadIdx.x != 0) return;
+  const double rn = sqrt(out[1]);
+  const double est = (d.W ? sqrt(out[2]) : rn) / c->ref;
+  c->sum.relres_rec = est;
+  if (est < c->tol || c->sum.iters >= c->maxit) {
+    c->sum.state = ST_VERIFY;
+    return;
+  }
+  const double rho_new = out[0];
+  if (fabs(rho_new) <= c->eps_b * c->rh_norm * rn) {
+    c->sum.status = S_BREAKDOWN;
+    c->sum.brk = BRK_RHO;
+    c->sum.state = ST_FINAL;
+    return;
+  }
+  c->beta = (rho_new / c->rho) * (c->alpha / c->omega);
+  c->rho_old = c->rho;
+  c->rho = rho_new;
+  c->first = 0;
+}
+
+// ---------------------------------------------------------------------------------------
+// Host side: the engine.
+// ---------------------------------------------------------------------------------------
+constexpr int kBatchVectors = 7;
+
+struct EngineLayout {
+  size_t sys, tiles, ctl, partials, vecs, total;
+};
+
+static EngineLayout engine_layout(int64_t max_rows, int max_sys) {
+  const int64_t max_tiles = (max_rows + BS - 1) / BS;
+  const int64_t grid_tiles = (max_tiles + 7) / 8 * 8;
+  EngineLayout L;
+  size_t off = 0;
+  L.sys = off;
+  off += align256(sizeof(SysDesc) * (size_t)max_sys);
+  L.tiles = off;
+  off += align256(sizeof(int) * (size_t)grid_tiles);
+  L.ctl = off;
+  off += align256(sizeof(BCtl) * (size_t)max_sys);
+  L.partials = off;
+  off += align256(sizeof(double) * 4 * (size_t)grid_tiles);
+  L.vecs = off;
+  off += (size_t)kBatchVectors * align256(sizeof(double) * (size_t)grid_tiles * BS);
+  L.total = off;
+  return L;
+}
+
+size_t engine_workspace_bytes(int64_t max_rows, int max_sys) {
+  if (max_rows < 1 || max_sys < 1) return 0;
+  return engine_layout(max_rows, max_sys).total;
+}
+
+struct Engine {
+  hipStream_t s = nullptr;
+  int64_t max_rows = 0;
+  int max_sys = 0, max_tiles = 0, grid_tiles = 0, check_every = 8;
+  bool use_graph = false;
+  BArgsB args{};
+  // host state
+  std::vector<SysDesc> h_sys;
+  std::vector<int64_t> tags;
+  std::vector<char> active;
+  std::vector<int> tile_sys;
+  std::map<int, int> free_tiles;   // start -> length
+  bool dirty = true;
+  int64_t launched = 0;
+  // pinned staging and status
+  SysDesc* p_sys = nullptr;
+  int* p_tiles = nullptr;
+  BCtl* p_ctl = nullptr;
+  hipEvent_t ev_upload = nullptr, ev_chunk = nullptr;
+  bool upload_pending = false, chunk_pending = false;
+  hipGraphExec_t graph = nullptr;
+  int graph_k = 0;
+};
+
+static bool alloc_tiles(Engine& e, int need, int& start) {
+  for (auto it = e.free_tiles.begin(); it != e.free_tiles.end(); ++it) {
+    if (it->second >= need) {
+      start = it->first;
+      const int rest = it->second - need;
+      e.free_tiles.erase(it);
+      if (rest > 0) e.free_tiles[start + need] = rest;
+      return true;
+    }
+  }
+  return false;
+}
+
+static void free_tiles_range(Engine& e, int start, int len) {
+  auto it = e.free_tiles.emplace(start, len).first;
+  auto next = std::next(it);
+  if (next != e.free_tiles.end() && it->first + it->second == next->first) {
+    it->second += next->second;
+    e.free_tiles.erase(next);
+  }
+  if (it != e.free_tiles.begin()) {
+    auto prev = std::prev(it);
+    if (prev->first + prev->second == it->first) {
+      prev->second += it->second;
+      e.free_tiles.erase(it);
+    }
+  }
+}
+
+int engine_create(void* ws, size_t ws_bytes, int64_t max_rows, int max_sys, int check_every,
+                  bool use_graph, hipStream_t s, Engine** out) {
+  const EngineLayout L = engine_layout(max_rows, max_sys);
+  if (ws_bytes < L.total) return -4;
+  if (use_graph && (s == nullptr || (check_every & 1))) return -1;
+  Engine* e = new Engine();
+  e->s = s;
+  e->max_rows = max_rows;
+  e->max_sys = max_sys;
+  e->max_tiles = (int)((max_rows + BS - 1) / BS);
+  e->grid_tiles = (e->max_tiles + 7) / 8 * 8;
+  e->check_every = check_every;
+  e->use_graph = use_graph;
+  char* base = static_cast<char*>(ws);
+  BArgsB& a = e->args;
+  a.sys = reinterpret_cast<const SysDesc*>(base + L.sys);
+  a.tile_sys = reinterpret_cast<const int*>(base + L.tiles);
+  a.ctl = reinterpret_cast<BCtl*>(base + L.ctl);
+  a.partials = reinterpret_cast<double*>(base + L.partials);
+  a.max_tiles = e->grid_tiles;
+  const size_t vb = align256(sizeof(double) * (size_t)e->grid_tiles * BS);
+  double* v[kBatchVectors];
+  for (int i = 0; i < kBatchVectors; ++i) v[i] = reinterpret_cast<double*>(base + L.vecs + i * vb);
+  a.r = v[0];
+  a.rh = v[1];
+  a.p[0] = v[2];
+  a.p[1] = v[3];
+  a.v[0] = v[4];
+  a.v[1] = v[5];
+  a.t = v[6];
+  a.par = 0;
+  e->h_sys.assign(max_sys, SysDesc{});
+  e->tags.assign(max_sys, 0);
+  e->active.assign(max_sys, 0);
+  e->tile_sys.assign(e->grid_tiles, -1);
+  e->free_tiles[0] = e->max_tiles;
+  bool ok = hipHostMalloc((void**)&e->p_sys, sizeof(SysDesc) * max_sys, hipHostMallocDefault) ==
+                hipSuccess &&
+            hipHostMalloc((void**)&e->p_tiles, sizeof(int) * e->grid_tiles, hipHostMallocDefault) ==
+                hipSuccess &&
+            hipHostMalloc((void**)&e->p_ctl, sizeof(BCtl) * max_sys, hipHostMallocDefault) ==
+                hipSuccess &&
+            hipEventCreateWithFlags(&e->ev_upload, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&e->ev_chunk, hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    engine_destroy(e);
+    return -5;
+  }
+  *out = e;
+  return 0;
+}
+
+void engine_destroy(Engine* e) {
+  if (!e) return;
+  if (e->s) (void)hipStreamSynchronize(e->s);
+  if (e->graph) (void)hipGraphExecDestroy(e->graph);
+  if (e->ev_upload) (void)hipEventDestroy(e->ev_upload);
+  if (e->ev_chunk) (void)hipEventDestroy(e->ev_chunk);
+  if (e->p_sys) (void)hipHostFree(e->p_sys);
+  if (e->p_tiles) (void)hipHostFree(e->p_tiles);
+  if (e->p_ctl) (void)hipHostFree(e->p_ctl);
+  delete e;
+}
+
+// The pinned staging buffers may be rewritten only after the previous upload has run.
+static int wait_upload(Engine& e) {
+  if (e.upload_pending) {
+    if (hipEventSynchronize(e.ev_upload) != hipSuccess) return -5;
+    e.upload_pending = false;
+  }
+  return 0;
+}
+
+int engine_submit(Engine* e, const Mat& A, const double* b, double* x, const SolveParams& prm,
+                  int64_t tag) {
+  int slot = -1;
+  for (int i = 0; i < e->max_sys; ++i)
+    if (!e->active[i]) {
+      slot = i;
+      break;
+    }
+  if (slot < 0) return 1;   // no free slot
+  const int need = (A.n + BS - 1) / BS;
+  int start = 0;
+  if (!alloc_tiles(*e, need, start)) return 1;   // no room
+  SysDesc d{};
+  d.n = A.n;
+  d.kind = A.kind;
+  d.nx = A.nx;
+  d.ny = A.ny;
+  d.nz = A.nz;
+  d.tile_off = start;
+  d.ntiles = need;
+  d.row_off = (int64_t)start * BS;
+  d.rp = A.csr.rp;
+  d.ci = A.csr.ci;
+  d.val = A.csr.val;
+  d.coef = A.coef;
+  d.b = b;
+  d.x = x;
+  d.W = prm.weights;
+  e->h_sys[slot] = d;
+  e->tags[slot] = tag;
+  e->active[slot] = 1;
+  for (int t = 0; t < need; ++t) e->tile_sys[start + t] = slot;
+  e->dirty = true;
+  BCtl* c = e->args.ctl + slot;
+  hipLaunchKernelGGL(k_batch_init, dim3(1), dim3(64), 0, e->s, c, prm.maxit, prm.tol, prm.eps_b,
+                     prm.weights ? 1 : 0);
+  if (A.kind == MAT_CSR) {
+    int64_t blocks = ((int64_t)A.csr.nnz + A.n + BS) / BS;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_batch_validate, dim3((unsigned)blocks), dim3(BS), 0, e->s, A.csr.rp,
+                       A.csr.ci, A.n, A.csr.nnz, c);
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+static int upload(Engine& e) {
+  if (!e.dirty) return 0;
+  if (wait_upload(e)) return -5;
+  for (int i = 0; i < e.max_sys; ++i) {
+    e.p_sys[i] = e.h_sys[i];
+    if (!e.active[i]) e.p_sys[i].ntiles = 0;
+  }
+  for (int t = 0; t < e.grid_tiles; ++t) e.p_tiles[t] = e.tile_sys[t];
+  if (hipMemcpyAsync(const_cast<SysDesc*>(e.args.sys), e.p_sys, sizeof(SysDesc) * e.max_sys,
+                     hipMemcpyHostToDevice, e.s) != hipSuccess ||
+      hipMemcpyAsync(const_cast<int*>(e.args.tile_sys), e.p_tiles, sizeof(int) * e.grid_tiles,
+                     hipMemcpyHostToDevice, e.s) != hipSuccess ||
+      hipEventRecord(e.ev_upload, e.s) != hipSuccess)
+    return -5;
+  e.upload_pending = true;
+  e.dirty = false;
+  return 0;
+}
+
+static void enqueue_chunk(Engine& e, int k, int64_t first_iter) {
+  const dim3 gt(e.grid_tiles), gs(e.max_sys), block(BS);
+  BArgsB a = e.args;
+  hipLaunchKernelGGL(k_batch_residual, gt, block, 0, e.s, a);
+  hipLaunchKernelGGL(k_batch_fin_residual, gs, block, 0, e.s, a);
+  for (int it = 0; it < k; ++it) {
+    a.par = (int)((first_iter + it) & 1);
+    hipLaunchKernelGGL(k_batch_p, gt, block, 0, e.s, a);
+    hipLaunchKernelGGL(k_batch_fin_p, gs, block, 0, e.s, a);
+    hipLaunchKernelGGL(k_batch_s, gt, block, 0, e.s, a);
+    hipLaunchKernelGGL(k_batch_fin_s, gs, block, 0, e.s, a);
+    hipLaunchKernelGGL(k_batch_u, gt, block, 0, e.s, a);
+    hipLaunchKernelGGL(k_batch_fin_u, gs, block, 0, e.s, a);
+  }
+}
+
+int engine_run(Engine* e, int chunks) {
+  if (upload(*e)) return -5;
+  const int k = e->check_every;
+  for (int c = 0; c < chunks; ++c) {
+    if (e->use_graph) {
+      // Every chunk starts at an even iteration (k is even), so one captured chunk serves all.
+      if (!e->graph) {
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(e->s, hipStreamCaptureModeThreadLocal) != hipSuccess) return -5;
+        enqueue_chunk(*e, k, 0);
+        if (hipStreamEndCapture(e->s, &g) != hipSuccess) return -5;
+        const hipError_t r = hipGraphInstantiate(&e->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (r != hipSuccess) {
+          e->graph = nullptr;
+          return -5;
+        }
+        e->graph_k = k;
+      }
+      if (hipGraphLaunch(e->graph, e->s) != hipSuccess) return -5;
+    } else {
+      enqueue_chunk(*e, k, e->launched);
+    }
+    e->launched += k;
+  }
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(e->p_ctl, e->args.ctl, sizeof(BCtl) * e->max_sys, hipMemcpyDeviceToHost,
+                     e->s) != hipSuccess ||
+      hipEventRecord(e->ev_chunk, e->s) != hipSuccess)
+    return -5;
+  e->chunk_pending = true;
+  return 0;
+}
+
+// Waits for the last enqueued chunk (if wait, or if it has already finished) and retires the
+// systems that are done: fills out[] (up to max_out), frees their rows and slots.
+int engine_poll(Engine* e, bool wait, EngineDone* out, int max_out, int* n_out) {
+  *n_out = 0;
+  if (!e->chunk_pending) return 0;
+  if (!wait) {
+    const hipError_t q = hipEventQuery(e->ev_chunk);
+    if (q == hipErrorNotReady) return 0;
+    if (q != hipSuccess) return -5;
+  } else if (hipEventSynchronize(e->ev_chunk) != hipSuccess) {
+    return -5;
+  }
+  e->chunk_pending = false;
+  int n = 0;
+  for (int i = 0; i < e->max_sys && n < max_out; ++i) {
+    if (!e->active[i] || e->p_ctl[i].sum.state != ST_DONE) continue;
+    out[n].tag = e->tags[i];
+    out[n].sum = e->p_ctl[i].sum;
+    ++n;
+    e->active[i] = 0;
+    const SysDesc& d = e->h_sys[i];
+    for (int t = 0; t < d.ntiles; ++t) e->tile_sys[d.tile_off + t] = -1;
+    free_tiles_range(*e, d.tile_off, d.ntiles);
+    e->dirty = true;
+  }
+  *n_out = n;
+  return 0;
+}
+
+void engine_usage(const Engine* e, int* active, int64_t* free_rows, int64_t* largest_free_rows) {
+  int a = 0;
+  for (int i = 0; i < e->max_sys; ++i) a += e->active[i] ? 1 : 0;
+  int64_t f = 0, big = 0;
+  for (const auto& kv : e->free_tiles) {
+    f += kv.second;
+    if (kv.second > big) big = kv.second;
+  }
+  *active = a;
+  *free_rows = f * BS;
+  *largest_free_rows = big * BS;
+}
+
+}  // namespace gsk

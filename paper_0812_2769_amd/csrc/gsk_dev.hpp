@@ -237,19 +237,24 @@ __device__ inline double column_sum(const double* __restrict__ partials, int nb,
 
 // In a single-workgroup finalize launch: out[c] = sum of partial column c (c < NC <= 8), all
 // BS threads sweeping every column with independent loads; then the workgroup tree.
+// out[c] = sum of the `count` partials of column c (column c starts at partials + c * stride),
+// for c < NC <= 8, by one workgroup: every thread requests SUM_BATCH values per column before
+// it adds any, then the wave and workgroup trees. The result depends only on the column
+// values and count, so a system's sums are the same wherever its partials sit.
 template <int NC>
-__device__ inline void small_sums(const double* __restrict__ partials, int nb, double* out) {
+__device__ inline void small_sums_strided(const double* __restrict__ partials, int count,
+                                          int stride, double* out) {
   __shared__ double lds[8 * WAVES];
   double acc[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-  for (int base = 0; base < nb; base += SUM_BATCH * BS) {
+  for (int base = 0; base < count; base += SUM_BATCH * BS) {
     double v[NC][SUM_BATCH];
 #pragma unroll
     for (int q = 0; q < SUM_BATCH; ++q) {
       const int l = base + q * BS + (int)threadIdx.x;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) v[c][q] = l < nb ? partials[c * nb + l] : 0.0;
+      for (int c = 0; c < NC; ++c) v[c][q] = l < count ? partials[(size_t)c * stride + l] : 0.0;
     }
 #pragma unroll
     for (int c = 0; c < NC; ++c)
@@ -271,6 +276,11 @@ __device__ inline void small_sums(const double* __restrict__ partials, int nb, d
     out[threadIdx.x] = s;
   }
   __syncthreads();
+}
+
+template <int NC>
+__device__ inline void small_sums(const double* __restrict__ partials, int nb, double* out) {
+  small_sums_strided<NC>(partials, nb, nb, out);
 }
 
 // ---------------------------------------------------------------------------------------

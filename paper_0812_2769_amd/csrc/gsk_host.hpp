@@ -106,6 +106,24 @@ SolveResult bicgstab_solve(const Mat& A, const double* b, double* x, const Solve
 SolveResult gmres_mixed_solve(const Mat& A, const double* b, double* x, int m,
                               const SolveParams& prm, void* ws, hipStream_t s);
 
+// Batched Bi-CGSTAB engine (batch.hip): many independent systems share every launch.
+struct Engine;
+struct EngineDone {
+  int64_t tag;
+  Summary sum;
+};
+size_t engine_workspace_bytes(int64_t max_rows, int max_sys);
+// 0 ok, -4 workspace too small, -1 invalid arguments, -5 HIP failure.
+int engine_create(void* ws, size_t ws_bytes, int64_t max_rows, int max_sys, int check_every,
+                  bool use_graph, hipStream_t s, Engine** out);
+void engine_destroy(Engine* e);
+// 0 admitted, 1 no free slot or rows (try again after a poll), -5 HIP failure.
+int engine_submit(Engine* e, const Mat& A, const double* b, double* x, const SolveParams& prm,
+                  int64_t tag);
+int engine_run(Engine* e, int chunks);
+int engine_poll(Engine* e, bool wait, EngineDone* out, int max_out, int* n_out);
+void engine_usage(const Engine* e, int* active, int64_t* free_rows, int64_t* largest_free_rows);
+
 // Small pinned host buffer for status read-back (one per thread, allocated on first use).
 Summary* pinned_summaries();
 

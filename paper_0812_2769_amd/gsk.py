@@ -67,6 +67,19 @@ class ProbeResult(ctypes.Structure):
                 ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
+class Result(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_int64), ("info", InfoStruct)]
+
+
+class EngineUsage(ctypes.Structure):
+    _fields_ = [("active", ctypes.c_int32), ("max_systems", ctypes.c_int32),
+                ("max_rows", ctypes.c_int64), ("free_rows", ctypes.c_int64),
+                ("largest_free_rows", ctypes.c_int64)]
+
+
+ENGINE_GRAPH = 1
+FULL = 1
+
 KCLASS = {"gmres_a": 1, "gmres_b": 2, "gmres_c": 3, "bicg_p": 4, "bicg_s": 5, "bicg_u": 6,
           "residual": 7, "gmres_x": 8}
 
@@ -111,6 +124,28 @@ def _load() -> ctypes.CDLL:
     lib.gsk_last_error.restype = ctypes.c_char_p
     lib.gsk_version.argtypes = []
     lib.gsk_version.restype = ctypes.c_int
+    lib.gsk_engine_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32]
+    lib.gsk_engine_workspace_bytes.restype = sz
+    lib.gsk_engine_create.argtypes = [vp, sz, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_int32, vp, P(vp)]
+    lib.gsk_engine_create.restype = ctypes.c_int
+    lib.gsk_engine_submit.argtypes = [vp, P(Matrix), vp, vp, ctypes.c_double, P(Options),
+                                      ctypes.c_int64]
+    lib.gsk_engine_submit.restype = ctypes.c_int
+    lib.gsk_engine_run.argtypes = [vp, ctypes.c_int32]
+    lib.gsk_engine_run.restype = ctypes.c_int
+    lib.gsk_engine_poll.argtypes = [vp, ctypes.c_int32, P(Result), ctypes.c_int32,
+                                    P(ctypes.c_int32)]
+    lib.gsk_engine_poll.restype = ctypes.c_int
+    lib.gsk_engine_get_usage.argtypes = [vp, P(EngineUsage)]
+    lib.gsk_engine_get_usage.restype = ctypes.c_int
+    lib.gsk_engine_destroy.argtypes = [vp]
+    lib.gsk_engine_destroy.restype = ctypes.c_int
+    lib.gsk_bicgstab_batch_workspace_bytes.argtypes = [ctypes.c_int32, P(ctypes.c_int32)]
+    lib.gsk_bicgstab_batch_workspace_bytes.restype = sz
+    lib.gsk_bicgstab_batch.argtypes = [ctypes.c_int32, P(Matrix), P(vp), P(vp), ctypes.c_double,
+                                       P(Options), P(InfoStruct), vp, sz, vp]
+    lib.gsk_bicgstab_batch.restype = ctypes.c_int
     return lib
 
 
@@ -398,3 +433,111 @@ def probe_end() -> dict:
     _check(lib.gsk_probe_end(ctypes.byref(r)))
     return {"launches": r.launches, "busy_launches": r.busy_launches, "total_ms": r.total_ms,
             "bytes": r.bytes}
+
+
+class Engine:
+    """Batched Bi-CGSTAB with continuous admission (gsk_engine_*). Systems are submitted with
+    device tensors that must stay alive until the system is reported by poll(); results are
+    (tag, Info) pairs. The engine's vectors live in a workspace tensor it owns."""
+
+    def __init__(self, max_rows: int, max_systems: int, check_every: int = 8,
+                 graph: bool = False, device="cuda", stream=None):
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else (
+            torch.cuda.Stream(self.device) if graph else torch.cuda.current_stream(self.device))
+        nbytes = int(lib.gsk_engine_workspace_bytes(int(max_rows), int(max_systems)))
+        if nbytes == 0:
+            raise GskError(ERR_INVALID_ARG, "no engine workspace size for these limits")
+        self.ws = _aligned(nbytes, self.device)
+        h = ctypes.c_void_p()
+        _check(lib.gsk_engine_create(self.ws.data_ptr(), self.ws.numel(), int(max_rows),
+                                     int(max_systems), int(check_every),
+                                     ENGINE_GRAPH if graph else 0, self.stream.cuda_stream,
+                                     ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+        self._opts = {}
+        self.max_systems = int(max_systems)
+
+    def submit(self, A, b: torch.Tensor, x: torch.Tensor, tol: float = 1e-8, *, tag: int,
+               maxit: Optional[int] = None, breakdown_eps=None,
+               stop_weights: Optional[torch.Tensor] = None) -> bool:
+        """Admit one system; False if it does not fit now (retry after poll())."""
+        _vec(b, A.n, "b")
+        _vec(x, A.n, "x")
+        if stop_weights is not None:
+            _vec(stop_weights, A.n, "stop_weights")
+        o = _options(maxit, breakdown_eps, stop_weights, None, A.n)
+        c = A.c_matrix()
+        # order with the caller's stream: inputs are ready when the engine's stream runs
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        rc = lib.gsk_engine_submit(self._h, ctypes.byref(c), b.data_ptr(), x.data_ptr(),
+                                   float(tol), ctypes.byref(o), int(tag))
+        if rc == FULL:
+            return False
+        _check(rc)
+        self._keep[int(tag)] = (A, b, x, stop_weights)
+        return True
+
+    def run(self, chunks: int = 1) -> None:
+        _check(lib.gsk_engine_run(self._h, int(chunks)))
+
+    def poll(self, wait: bool = True):
+        """Results [(tag, Info)] of the systems finished by the last run()."""
+        out = (Result * self.max_systems)()
+        n = ctypes.c_int32(0)
+        _check(lib.gsk_engine_poll(self._h, 1 if wait else 0, out, self.max_systems,
+                                   ctypes.byref(n)))
+        res = []
+        for i in range(n.value):
+            tag = int(out[i].tag)
+            self._keep.pop(tag, None)
+            res.append((tag, _info(out[i].info)))
+        if res:
+            torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return res
+
+    def usage(self) -> dict:
+        u = EngineUsage()
+        _check(lib.gsk_engine_get_usage(self._h, ctypes.byref(u)))
+        return {"active": u.active, "max_systems": u.max_systems, "max_rows": u.max_rows,
+                "free_rows": u.free_rows, "largest_free_rows": u.largest_free_rows}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib.gsk_engine_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def engine_workspace_bytes(max_rows: int, max_systems: int) -> int:
+    return int(lib.gsk_engine_workspace_bytes(int(max_rows), int(max_systems)))
+
+
+def bicgstab_batch(As, bs, tol: float = 1e-8, *, xs=None, maxit: Optional[int] = None,
+                   breakdown_eps=None, check_every: Optional[int] = None):
+    """Solve independent systems As[i] x = bs[i] in one batch. Returns (xs, [Info])."""
+    count = len(As)
+    if count == 0 or len(bs) != count:
+        raise ValueError("As and bs must be non-empty and of equal length")
+    if xs is None:
+        xs = [torch.zeros_like(b) for b in bs]
+    for A, b, x in zip(As, bs, xs):
+        _vec(b, A.n, "b")
+        _vec(x, A.n, "x")
+    mats = (Matrix * count)(*[A.c_matrix() for A in As])
+    bp = (ctypes.c_void_p * count)(*[b.data_ptr() for b in bs])
+    xp = (ctypes.c_void_p * count)(*[x.data_ptr() for x in xs])
+    ns = (ctypes.c_int32 * count)(*[A.n for A in As])
+    nbytes = int(lib.gsk_bicgstab_batch_workspace_bytes(count, ns))
+    ws = _aligned(nbytes, As[0].device)
+    o = _options(maxit, breakdown_eps, None, check_every, As[0].n)
+    infos = (InfoStruct * count)()
+    _check(lib.gsk_bicgstab_batch(count, mats, bp, xp, float(tol), ctypes.byref(o), infos,
+                                  ws.data_ptr(), ws.numel(), _stream(As[0].device)))
+    return xs, [_info(i) for i in infos]

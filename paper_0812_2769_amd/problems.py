@@ -327,6 +327,45 @@ def config3(N: int = 160, seed: int = 1003, blocks_per_axis: int = 16, prob: flo
                     name=f"config3_N{N}_seed{seed}")
 
 
+def config4_specs(count: int = 512, seed: int = 1004, n_min: int = 32, n_max: int = 96):
+    """Recipe of the batch workload: for system i, in order, from numpy's default_rng(seed):
+    dimension d uniform in {2, 3}; side N uniform in [n_min, n_max] (N^d interior nodes);
+    jump a_hi = 10^U(2, 6); convection components U(0, 30) (d of them); a box (each axis an
+    interval with endpoints drawn U(0, 1) and sorted, integer positions over 1000) where
+    a = a_hi, a = 1 elsewhere. Returns a list of dicts (no matrices), so sizes and memory can
+    be planned before any system is assembled."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(count):
+        d = int(rng.integers(2, 4))
+        N = int(rng.integers(n_min, n_max + 1))
+        jump = float(10.0 ** rng.uniform(2.0, 6.0))
+        conv = tuple(float(c) for c in rng.uniform(0.0, 30.0, size=d))
+        box = [tuple(sorted(int(v) for v in rng.integers(0, 1001, size=2))) for _ in range(d)]
+        specs.append({"index": i, "dims": (N,) * d, "jump": jump, "conv": conv, "box": box,
+                      "seed": seed})
+    return specs
+
+
+def config4_system(spec) -> Problem:
+    """Assemble one batch system from its spec: a = jump inside the box (the open interval of
+    each axis, tested exactly with integers: lo/1000 < q/den < hi/1000), 1 elsewhere;
+    b = A u* with u* the sine product."""
+    d = len(spec["dims"])
+    jump = spec["jump"]
+    box = spec["box"]
+
+    def diff(q, den):
+        inside = np.ones(np.broadcast_shapes(*[x.shape for x in q]), dtype=bool)
+        for a in range(d):
+            lo, hi = box[a]
+            inside &= (1000 * q[a] > lo * den[a]) & (1000 * q[a] < hi * den[a])
+        return np.where(inside, jump, 1.0)
+
+    return assemble(spec["dims"], diff, spec["conv"], u_star_fn=_sine_product,
+                    name=f"config4_{spec['seed']}_{spec['index']}")
+
+
 # ---------------------------------------------------------------------------------------
 # Small generic systems for unit tests
 # ---------------------------------------------------------------------------------------

@@ -158,3 +158,29 @@ def test_binding_refuses_cpu_tensors(lib):
     with pytest.raises(ValueError):
         lib.CsrMatrix(torch.zeros(3, dtype=torch.int32), torch.zeros(2, dtype=torch.int32),
                       torch.zeros(2, dtype=torch.float64))
+
+
+def test_engine_struct_layouts_and_rejections(lib):
+    # gsk_result {int64; gsk_info}, gsk_engine_usage {2 int32; 3 int64}
+    assert ctypes.sizeof(lib.Result) == 48
+    assert ctypes.sizeof(lib.EngineUsage) == 32
+    L = lib.lib
+    assert lib.engine_workspace_bytes(0, 4) == 0
+    assert lib.engine_workspace_bytes(1000, 0) == 0
+    assert lib.engine_workspace_bytes(1 << 20, 64) > 7 * 8 * (1 << 20)
+    h = ctypes.c_void_p()
+    # graph mode needs a non-default stream and an even check_every; sizes must be positive
+    assert L.gsk_engine_create(0x100000, 1 << 30, 1000, 4, 8, lib.ENGINE_GRAPH, None,
+                               ctypes.byref(h)) == -1
+    assert L.gsk_engine_create(0x100000, 1 << 30, 0, 4, 8, 0, None, ctypes.byref(h)) == -1
+    assert L.gsk_engine_create(0x100000, 1 << 30, 1000, 4, 0, 0, None, ctypes.byref(h)) == -1
+    assert L.gsk_engine_create(0x100000, 16, 1000, 4, 8, 0, None, ctypes.byref(h)) == -4
+    assert L.gsk_engine_create(None, 1 << 30, 1000, 4, 8, 0, None, ctypes.byref(h)) == -4
+    n = ctypes.c_int32(0)
+    assert L.gsk_engine_poll(None, 1, None, 0, ctypes.byref(n)) == -1
+    assert L.gsk_engine_run(None, 1) == -1
+    assert L.gsk_engine_destroy(None) == 0
+    ns = (ctypes.c_int32 * 2)(300, 0)
+    assert L.gsk_bicgstab_batch_workspace_bytes(2, ns) == 0
+    ns = (ctypes.c_int32 * 2)(300, 100)
+    assert L.gsk_bicgstab_batch_workspace_bytes(2, ns) == lib.engine_workspace_bytes(768, 2)

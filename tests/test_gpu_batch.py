@@ -1,0 +1,184 @@
+"""Batched Bi-CGSTAB and the continuous-batching engine through the C ABI.
+
+Each system in a batch is solved exactly as gsk_bicgstab solves it alone (same operations,
+same per-tile partial sums in the same order), so the bar is bit-for-bit equality with the
+single solve: x, iteration counts, statuses and residuals. That holds in one batch, when
+systems are admitted while others run (the engine), and when every chunk is a replay of a
+captured HIP graph. The single solver itself is checked against the oracle elsewhere; one
+batch system is also compared with the oracle here directly.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_0812_2769_amd import problems
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0812_2769_amd import gsk
+    return gsk
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def grid_of(P):
+    d = list(P.dims) + [1] * (3 - len(P.dims))
+    return d[0], d[1], d[2]
+
+
+def scaled(G, P, p=2, stencil=True):
+    A = G.CsrMatrix.from_problem(P)
+    As, bs, _, w = G.gs_scale(A, dev(P.b), p, want_weights=(p != 2))
+    M = G.stencil_from_csr(As, *grid_of(P)) if stencil else As
+    return M, bs, (w if p != 2 else None)
+
+
+def systems(G):
+    """A mix of kinds and sizes: 3D and 2D stencils, a CSR system, GS(1) with stop weights,
+    ragged row counts, a tiny system."""
+    specs = problems.config4_specs(6, seed=7, n_min=6, n_max=20)
+    out = []
+    for i, sp in enumerate(specs):
+        P = problems.config4_system(sp)
+        out.append(scaled(G, P, p=1 if i == 2 else 2, stencil=(i != 3)))
+    out.append(scaled(G, problems.laplacian((13, 11, 7), conv=(40.0, -25.0, 10.0))))
+    out.append(scaled(G, problems.laplacian((3, 2)), stencil=False))
+    return out
+
+
+def solo(G, syst, tol=1e-10):
+    res = []
+    for M, b, w in syst:
+        x, info = G.bicgstab(M, b, tol=tol, stop_weights=w)
+        res.append((host(x), info))
+    return res
+
+
+def same(a, b):
+    (xa, ia), (xb, ib) = a, b
+    assert ia == ib, (ia, ib)
+    assert np.array_equal(xa, xb)
+
+
+def test_batch_equals_solo(G):
+    syst = systems(G)
+    ref = solo(G, syst)
+    assert all(i.status == G.CONVERGED for _, i in ref)
+    # bicgstab_batch takes one tol and no per-system weights: compare the unweighted ones
+    idx = [k for k, (_, _, w) in enumerate(syst) if w is None]
+    xs, infos = G.bicgstab_batch([syst[k][0] for k in idx], [syst[k][1] for k in idx],
+                                 tol=1e-10)
+    for j, k in enumerate(idx):
+        same((host(xs[j]), infos[j]), ref[k])
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_engine_continuous_admission_equals_solo(G, graph):
+    import torch
+    syst = systems(G)
+    ref = solo(G, syst)
+    # room for only part of the set at a time: later systems wait for rows and slots
+    rows = sorted(((M.n + 255) // 256 * 256 for M, _, _ in syst), reverse=True)
+    eng = G.Engine(max_rows=rows[0] + rows[1], max_systems=3, check_every=8, graph=graph)
+    xs = [torch.zeros_like(b) for _, b, _ in syst]
+    pending = list(range(len(syst)))
+    results = {}
+    admitted_late = False
+    chunks = 0
+    while len(results) < len(syst):
+        while pending:
+            k = pending[0]
+            M, b, w = syst[k]
+            if not eng.submit(M, b, xs[k], tol=1e-10, tag=k, stop_weights=w):
+                break
+            admitted_late = admitted_late or chunks > 0
+            pending.pop(0)
+        eng.run(1)
+        chunks += 1
+        for tag, info in eng.poll(wait=True):
+            results[tag] = info
+        assert chunks < 5000
+    assert admitted_late   # some systems joined while others were running
+    torch.cuda.synchronize()
+    for k in range(len(syst)):
+        same((host(xs[k]), results[k]), ref[k])
+    u = eng.usage()
+    assert u["active"] == 0 and u["free_rows"] == u["max_rows"] // 256 * 256
+    eng.close()
+
+
+def test_engine_full_and_usage(G):
+    import torch
+    P = problems.laplacian((20, 20))
+    M, b, _ = scaled(G, P)
+    eng = G.Engine(max_rows=512, max_systems=4)
+    x1, x2 = torch.zeros_like(b), torch.zeros_like(b)
+    assert eng.submit(M, b, x1, tol=1e-8, tag=1)          # 400 rows -> 2 tiles of 256
+    assert not eng.submit(M, b, x2, tol=1e-8, tag=2)      # no rows left
+    u = eng.usage()
+    assert u["active"] == 1 and u["free_rows"] == 0
+    done = {}
+    for _ in range(200):
+        eng.run(1)
+        done.update(dict(eng.poll()))
+        if 1 in done:
+            break
+    assert done[1].status == G.CONVERGED
+    assert eng.submit(M, b, x2, tol=1e-8, tag=2)          # rows were freed
+    eng.close()
+
+
+def test_engine_invalid_csr_system_reported(G):
+    import torch
+    P = problems.laplacian((8, 8))
+    rp = P.row_ptr.copy()
+    rp[5] = rp[6] + 1        # not monotone
+    bad = G.CsrMatrix.from_numpy(rp, P.col_idx, P.val)
+    good, bg, _ = scaled(G, P)
+    eng = G.Engine(max_rows=1024, max_systems=4)
+    xb, xg = torch.zeros(P.n, dtype=torch.float64, device="cuda"), torch.zeros_like(bg)
+    assert eng.submit(bad, dev(P.b), xb, tol=1e-8, tag=0)
+    assert eng.submit(good, bg, xg, tol=1e-8, tag=1)
+    done = {}
+    for _ in range(200):
+        eng.run(1)
+        done.update(dict(eng.poll()))
+        if len(done) == 2:
+            break
+    assert done[0].status < 0
+    assert done[1].status == G.CONVERGED
+    assert not xb.any()      # an invalid system's x is left alone
+    eng.close()
+
+
+def test_batch_system_matches_oracle(G):
+    P = problems.config4_system(problems.config4_specs(1, seed=11, n_min=14, n_max=14)[0])
+    vo, bo, _, _ = oracle.gs_scale(P, P.b, 2)
+    S = P.copy()
+    S.val, S.b = vo, bo
+    xo, io = oracle.bicgstab(S, bo, tol=1e-10)
+    M, b, _ = scaled(G, P)
+    xs, infos = G.bicgstab_batch([M], [b], tol=1e-10)
+    assert infos[0].status == io.status == G.CONVERGED
+    assert abs(infos[0].iters - io.iters) <= max(1, 0.05 * io.iters)
+    assert np.max(np.abs(host(xs[0]) - xo)) <= 1e-8 * np.max(np.abs(xo))
+
+
+def test_engine_argument_errors(G):
+    with pytest.raises(G.GskError):
+        G.Engine(max_rows=0, max_systems=4)
+    with pytest.raises(G.GskError):
+        G.Engine(max_rows=1024, max_systems=4, check_every=7, graph=True)
