@@ -74,7 +74,18 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["config2", "config3"], default="config2")
+    ap.add_argument("--workload", choices=["config2", "config3", "config4", "config5"],
+                    default="config2")
+    ap.add_argument("--batch-count", type=int, default=512,
+                    help="config4: systems per batch (default 512)")
+    ap.add_argument("--no-solo", action="store_true",
+                    help="config4: skip the one-at-a-time comparison")
+    ap.add_argument("--rates", default="50,200,1000,2000",
+                    help="config5: Poisson arrival rates to sweep (requests/s)")
+    ap.add_argument("--serve-requests", type=int, default=400,
+                    help="config5: requests per rate")
+    ap.add_argument("--gmres-share", type=float, default=0.2,
+                    help="config5: fraction of GMRES(20) requests (the rest Bi-CGSTAB)")
     ap.add_argument("--grid", type=int, default=0,
                     help="N of the N^3 grid (default 80 for config2, 160 for config3)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
@@ -145,6 +156,182 @@ def cpu_baseline(P, gpu_iters, sample_iters, variants, tol, precision):
             "per_variant": detail}
 
 
+def log(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def build_batch_systems(gsk, problems, dev, specs):
+    """Upload each system unscaled: CSR (kept for the one-at-a-time path) and 5/7-point
+    planes (what the engine scales and solves)."""
+    systems = []
+    t0 = time.perf_counter()
+    for i, sp in enumerate(specs):
+        P = problems.config4_system(sp)
+        A = gsk.CsrMatrix.from_problem(P, dev)
+        d = list(P.dims) + [1] * (3 - len(P.dims))
+        S = gsk.stencil_from_csr(A, *d)
+        b = torch_from(P.b, dev)
+        systems.append({"A": A, "S": S, "b": b, "n": P.n, "grid": tuple(d), "dim": len(P.dims)})
+        if (i + 1) % 64 == 0:
+            log(f"built {i + 1}/{len(specs)} systems ({time.perf_counter() - t0:.1f}s)")
+    return systems
+
+
+def torch_from(a, dev):
+    import torch
+    return torch.from_numpy(a).to(dev)
+
+
+def bench_batch(args, gsk, problems, dev):
+    """config4: a batch of independent GS(2) + Bi-CGSTAB solves, tol 1e-8, run by the engine
+    with every chunk replayed from a HIP graph. value = systems solved per second."""
+    import torch
+    specs = problems.config4_specs(args.batch_count)
+    systems = build_batch_systems(gsk, problems, dev, specs)
+    rows = sum((s["n"] + 255) // 256 * 256 for s in systems)
+    eng = gsk.Engine(rows, len(systems), check_every=8, graph=True, device=dev)
+    xbuf = torch.zeros(sum(s["n"] for s in systems), dtype=torch.float64, device=dev)
+    offs = [0]
+    for s in systems:
+        offs.append(offs[-1] + s["n"])
+    xs = [xbuf[offs[i]:offs[i + 1]] for i in range(len(systems))]
+    tol = 1e-8
+
+    def step():
+        xbuf.zero_()
+        t0 = time.perf_counter()
+        for i, s in enumerate(systems):
+            assert eng.submit_gs(s["S"], s["b"], xs[i], p=2, tol=tol, tag=i)
+        lat, infos = {}, {}
+        while len(infos) < len(systems):
+            eng.run(1)
+            for tag, info in eng.poll():
+                infos[tag] = info
+                lat[tag] = time.perf_counter() - t0
+        return lat, infos
+
+    for i in range(args.warmup):
+        step()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    lats, infos = [], {}
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        lat, infos = step()
+        lats.extend(lat.values())
+        log(f"step {i + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    its = [infos[k].iters for k in infos]
+    status = collections_count(infos)
+    out = {
+        "metric": "systems solved/s, batch of GS(2) + Bi-CGSTAB, tol 1e-8",
+        "value": round(len(systems) * args.steps / elapsed, 3),
+        "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"config4: {len(systems)} systems, d in {{2,3}}, N in [32,96], "
+                               f"box jump 10^U(2,6), convection U(0,30); GS(2) + Bi-CGSTAB in "
+                               f"the engine (HIP-graph chunks of 8 iterations), tol 1e-8",
+                   "rows": sum(s["n"] for s in systems), "systems": len(systems),
+                   "dims_3d": sum(1 for s in systems if s["dim"] == 3)},
+        "latency_p50_ms": round(1e3 * pct(lats, 0.5), 3),
+        "latency_p99_ms": round(1e3 * pct(lats, 0.99), 3),
+        "iterations": {"total": int(sum(its)), "max": int(max(its)), "median": pct(its, 0.5)},
+        "status": status,
+        "roofline": None, "cpu_baseline": None,
+    }
+    if not args.no_solo:
+        # the same solves one at a time: gsk_gs_scale + packing + gsk_bicgstab per system
+        log("timing the one-at-a-time path")
+        ws_gs = gsk.workspace(gsk.METHOD_GS, 1, 0, dev)
+        nmax = max(s["n"] for s in systems)
+        ws_bi = gsk.workspace(gsk.METHOD_BICGSTAB, nmax, 0, dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        same = True
+        for i, s in enumerate(systems):
+            As, bs, _, _ = gsk.gs_scale(s["A"], s["b"], 2, want_norms=False, ws=ws_gs)
+            M = gsk.stencil_from_csr(As, *s["grid"], ws=ws_gs)
+            x, info = gsk.bicgstab(M, bs, tol=tol,
+                                   ws=ws_bi[: gsk.workspace_bytes(gsk.METHOD_BICGSTAB, s["n"])])
+            same = same and info == infos[i] and bool(torch.equal(x, xs[i]))
+        torch.cuda.synchronize()
+        t_solo = time.perf_counter() - t0
+        out["one_at_a_time"] = {"solves_per_s": round(len(systems) / t_solo, 3),
+                                "seconds": round(t_solo, 3),
+                                "results_bitwise_equal_to_batch": same}
+    print(json.dumps(out), flush=True)
+
+
+def collections_count(infos):
+    c = {}
+    for info in infos.values():
+        c[info.status_name] = c.get(info.status_name, 0) + 1
+    return c
+
+
+def bench_serve(args, gsk, problems, dev):
+    """config5: Poisson arrivals of solves drawn from the config4 distribution (a pool of 64
+    systems), a GMRES(20) / Bi-CGSTAB mix, tol 1e-8, served with continuous batching; one run
+    per arrival rate. value = completed solves/s at the highest rate."""
+    import numpy as np
+    import torch
+    from paper_0812_2769_amd import serve
+    rates = [float(r) for r in args.rates.split(",") if r]
+    pool_specs = problems.config4_specs(64, seed=1005)
+    pool = build_batch_systems(gsk, problems, dev, pool_specs)
+    nmax = max(s["n"] for s in pool)
+    rng = np.random.default_rng(1006)
+    # engine room for about 48 of the pool's systems at once
+    rows = int(sum((s["n"] + 255) // 256 * 256 for s in pool) * 0.75)
+    srv = serve.Server(rows, 256, check_every=8, graph=True, gmres_rows=nmax, m_max=20,
+                       device=dev)
+    results = []
+    for rate in rates:
+        gaps = rng.exponential(1.0 / rate, size=args.serve_requests)
+        arrivals = np.cumsum(gaps)
+        picks = rng.integers(0, len(pool), size=args.serve_requests)
+        kinds = rng.random(args.serve_requests) < args.gmres_share
+        reqs = []
+        for k in range(args.serve_requests):
+            s = pool[int(picks[k])]
+            reqs.append(serve.Request(tag=k, arrival=float(arrivals[k]), A=s["S"], b=s["b"],
+                                      method="gmres" if kinds[k] else "bicgstab", m=20,
+                                      tol=1e-8, csr=s["A"], grid=s["grid"]))
+        t0 = time.perf_counter()
+        done = srv.serve(reqs)
+        wall = time.perf_counter() - t0
+        lat = [d.latency for d in done]
+        lat_b = [d.latency for d in done if d.method == "bicgstab"]
+        lat_g = [d.latency for d in done if d.method == "gmres"]
+        span = max(d.finished for d in done) - min(d.arrival for d in done)
+        conv = sum(1 for d in done if d.info.status == gsk.CONVERGED)
+        results.append({"rate": rate, "requests": len(done), "completed_per_s": round(len(done) / span, 2),
+                        "wall_s": round(wall, 3),
+                        "latency_p50_ms": round(1e3 * pct(lat, 0.5), 2),
+                        "latency_p99_ms": round(1e3 * pct(lat, 0.99), 2),
+                        "bicgstab_p50_ms": round(1e3 * pct(lat_b, 0.5), 2) if lat_b else None,
+                        "gmres_p50_ms": round(1e3 * pct(lat_g, 0.5), 2) if lat_g else None,
+                        "converged": conv})
+        log(f"rate {rate}: {results[-1]}")
+    srv.close()
+    best = results[-1]
+    out = {
+        "metric": "completed solves/s under Poisson arrivals, p50/p99 latency",
+        "value": best["completed_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "steps": len(rates), "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"config5: Poisson arrivals at {args.rates} req/s, "
+                               f"{args.serve_requests} requests per rate from a pool of 64 "
+                               f"config4-distribution systems, {args.gmres_share:.0%} GMRES(20), "
+                               f"the rest Bi-CGSTAB, tol 1e-8, GS(2) per request"},
+        "latency_p50_ms": best["latency_p50_ms"], "latency_p99_ms": best["latency_p99_ms"],
+        "rates": results, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -170,6 +357,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "config4":
+        return bench_batch(args, gsk, problems, dev)
+    if args.workload == "config5":
+        return bench_serve(args, gsk, problems, dev)
     c3 = args.workload == "config3"
     grid = args.grid or (160 if c3 else 80)
     variants = [(2, "gmres30")] if c3 else VARIANTS

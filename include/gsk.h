@@ -327,7 +327,8 @@ typedef struct gsk_engine gsk_engine;
 
 typedef struct gsk_result {
     int64_t tag;        /* the tag given at submission                                    */
-    gsk_info info;      /* as gsk_bicgstab would return it; status < 0: invalid CSR        */
+    gsk_info info;      /* as gsk_bicgstab would return it; status -1: invalid CSR,
+                           -2: zero row, -3: non-finite data (GS stage)                     */
 } gsk_result;
 
 typedef struct gsk_engine_usage {
@@ -351,6 +352,19 @@ int gsk_engine_create(void* ws, size_t ws_bytes, int64_t max_rows, int32_t max_s
  * error for invalid arguments. Enqueues a small initialisation on the engine's stream. */
 int gsk_engine_submit(gsk_engine* e, const gsk_matrix* A, const double* b, double* x,
                       double tol, const gsk_options* opt, int64_t tag);
+
+/* Admits one unscaled system with a GS(p) stage (section 2, eq. (2)): the engine's first chunk
+ * writes the GS(p)-scaled matrix values to val_out (nnz doubles for CSR, the planes' count
+ * for a stencil matrix, same layout as A's values), the scaled right-hand side to b_out [n]
+ * and, for p != 2, the stop-test weights ||a_i||_p / ||a_i||_2 to stop_weight_out [n]
+ * (required then; ignored for p = 2), all with the arithmetic of gsk_gs_scale. The solve then
+ * runs on the scaled system with the GS(2)-metric stop test (section 2.2), exactly as
+ * gsk_gs_scale followed by gsk_bicgstab would. opt->stop_weights must be NULL. A zero row or
+ * non-finite data ends the system with info.status -2 or -3. Outputs must stay allocated
+ * until the system is reported done. */
+int gsk_engine_submit_gs(gsk_engine* e, const gsk_matrix* A, const double* b, int32_t p,
+                         double* val_out, double* b_out, double* stop_weight_out, double* x,
+                         double tol, const gsk_options* opt, int64_t tag);
 
 /* Enqueues `chunks` chunks (asynchronous). */
 int gsk_engine_run(gsk_engine* e, int32_t chunks);

@@ -410,6 +410,30 @@ int gsk_engine_submit(gsk_engine* e, const gsk_matrix* A, const double* b, doubl
   return GSK_OK;
 }
 
+int gsk_engine_submit_gs(gsk_engine* e, const gsk_matrix* A, const double* b, int32_t p,
+                         double* val_out, double* b_out, double* stop_weight_out, double* x,
+                         double tol, const gsk_options* opt, int64_t tag) {
+  g_err.clear();
+  if (!e) return set_err(GSK_ERR_INVALID_ARG, "engine is NULL");
+  Mat M;
+  int rc = check_matrix(A, M);
+  if (rc) return rc;
+  if (!b || !x || !val_out || !b_out) return set_err(GSK_ERR_INVALID_ARG, "NULL pointer");
+  if (p < 1) return set_err(GSK_ERR_INVALID_ARG, "p must be >= 1");
+  if (p != 2 && !stop_weight_out)
+    return set_err(GSK_ERR_INVALID_ARG, "p != 2 needs stop_weight_out");
+  if (opt && opt->stop_weights)
+    return set_err(GSK_ERR_INVALID_ARG, "opt->stop_weights must be NULL with a GS stage");
+  SolveParams prm;
+  rc = params_from(opt, prm, tol);
+  if (rc) return rc;
+  gsk::GsStage gs{p, val_out, b_out, p != 2 ? stop_weight_out : nullptr};
+  rc = gsk::engine_submit(e->impl, M, b, x, prm, tag, &gs);
+  if (rc == 1) return GSK_FULL;
+  if (rc) return set_err(GSK_ERR_DEVICE, "engine submit: HIP failure");
+  return GSK_OK;
+}
+
 int gsk_engine_run(gsk_engine* e, int32_t chunks) {
   g_err.clear();
   if (!e) return set_err(GSK_ERR_INVALID_ARG, "engine is NULL");

@@ -13,8 +13,13 @@
 // launch over all tiles serves every system; a finalize launch has one workgroup per system
 // slot and sums that system's tile partials.
 //
-// Time. The host enqueues chunks: the residual launch (which starts newly admitted systems
-// and verifies convergence claims), then check_every iterations. A chunk has fixed launch
+// A system may be submitted unscaled with a GS(p) stage (section 2, eq. (2)): the first chunk
+// scales its rows into caller-provided outputs (with the arithmetic of gsk_gs_scale) and the
+// solve then runs on the scaled system, so GS(p) and Bi-CGSTAB run in the same launches.
+//
+// Time. The host enqueues chunks: the GS launch (scales newly admitted systems that asked for
+// it), the residual launch (starts newly admitted systems and verifies convergence claims),
+// then check_every iterations. A chunk has fixed launch
 // shapes and arguments, so it can be captured once in a HIP graph and replayed. Between
 // chunks the host reads every slot's status and retires finished systems; new systems are
 // admitted between chunks (continuous batching).
@@ -34,16 +39,21 @@ struct BCtl {
 };
 
 struct SysDesc {
-  int n, kind, nx, ny, nz, tile_off, ntiles, pad;
+  int n, kind, nx, ny, nz, tile_off, ntiles, gs_p;
   int64_t row_off;
   const int* rp;
   const int* ci;
-  const double* val;
-  const double* coef;
-  const double* b;
+  const double* val;      // CSR values the solve reads (the GS output with a GS stage)
+  const double* coef;     // stencil planes the solve reads (likewise)
+  const double* b;        // right-hand side the solve reads (likewise)
   double* x;
-  const double* W;
+  const double* W;        // stop weights (written by the GS stage for p != 2)
+  const double* gs_val;   // GS stage input: unscaled values or planes
+  const double* gs_b;     // GS stage input: unscaled b
 };
+
+// BCtl::bad bits: invalid CSR structure, zero row, non-finite data (GS stage).
+enum : int { BAD_CSR = 1, BAD_ZERO = 2, BAD_NONFINITE = 4 };
 
 struct BArgsB {
   const SysDesc* sys;
@@ -107,9 +117,9 @@ __device__ inline double sys_tile(const SysDesc& d, int row0, int nrows, const G
 }
 
 __global__ __launch_bounds__(64) void k_batch_init(BCtl* c, int maxit, double tol, double eps_b,
-                                                   int has_w) {
+                                                   int has_w, int scale) {
   if (threadIdx.x != 0) return;
-  c->sum.state = ST_INIT;
+  c->sum.state = scale ? ST_SCALE : ST_INIT;
   c->sum.status = S_MAXIT;
   c->sum.iters = 0;
   c->sum.restarts = 0;
@@ -147,7 +157,41 @@ __global__ __launch_bounds__(BS) void k_batch_validate(const int* __restrict__ r
     const int col = ci[k];
     if (col < 0 || col >= n) bad = true;
   }
-  if (bad) atomicOr(&c->bad, 1);
+  if (bad) atomicOr(&c->bad, BAD_CSR);
+}
+
+// G: GS(p) of the systems whose stage is pending (same arithmetic as k_gs_scale).
+__global__ __launch_bounds__(BS) void k_batch_gs(BArgsB a) {
+  int s;
+  const int tile = batch_tile(a, s);
+  if (s < 0) return;
+  const SysDesc d = a.sys[s];
+  BCtl* c = a.ctl + s;
+  if (c->sum.state != ST_SCALE || (c->bad & BAD_CSR)) return;
+  __shared__ GsLds L;
+  const int row0 = (tile - d.tile_off) * BS;
+  const int nrows = min(BS, d.n - row0);
+  bool zero = false, nonfinite = false;
+  if (d.kind == MAT_STENCIL) {
+    if ((int)threadIdx.x < nrows)
+      gs_stencil_row(d.gs_val, (size_t)d.n, d.n, d.nx, d.ny, d.nz, d.gs_b, d.gs_p,
+                     row0 + threadIdx.x, const_cast<double*>(d.coef), const_cast<double*>(d.b),
+                     const_cast<double*>(d.W), zero, nonfinite);
+  } else {
+    gs_csr_tile(d.rp, d.gs_val, d.gs_b, d.gs_p, row0, nrows, const_cast<double*>(d.val),
+                const_cast<double*>(d.b), nullptr, const_cast<double*>(d.W), L, zero,
+                nonfinite);
+  }
+  if (zero) atomicOr(&c->bad, BAD_ZERO);
+  if (nonfinite) atomicOr(&c->bad, BAD_NONFINITE);
+}
+
+__global__ __launch_bounds__(64) void k_batch_fin_gs(BArgsB a) {
+  const int s = blockIdx.x;
+  if (threadIdx.x != 0 || a.sys[s].ntiles == 0) return;
+  BCtl* c = a.ctl + s;
+  if (c->sum.state != ST_SCALE) return;
+  c->sum.state = ST_INIT;   // a GS error (c->bad) is reported by the residual stage
 }
 
 // R: r = b - A x, r^ = r for systems starting, verifying or finishing; ||r||^2, ||W r||^2.
@@ -193,7 +237,7 @@ __global__ __launch_bounds__(BS) void k_batch_fin_residual(BArgsB a) {
   if (c->bad) {
     if (threadIdx.x == 0) {
       c->sum.state = ST_DONE;
-      c->sum.status = -1;
+      c->sum.status = (c->bad & BAD_CSR) ? -1 : (c->bad & BAD_ZERO) ? -2 : -3;
     }
     return;
   }
@@ -594,7 +638,7 @@ static int wait_upload(Engine& e) {
 }
 
 int engine_submit(Engine* e, const Mat& A, const double* b, double* x, const SolveParams& prm,
-                  int64_t tag) {
+                  int64_t tag, const GsStage* gs) {
   int slot = -1;
   for (int i = 0; i < e->max_sys; ++i)
     if (!e->active[i]) {
@@ -621,6 +665,16 @@ int engine_submit(Engine* e, const Mat& A, const double* b, double* x, const Sol
   d.b = b;
   d.x = x;
   d.W = prm.weights;
+  d.gs_p = 0;
+  if (gs) {   // the solve reads the GS outputs
+    d.gs_p = gs->p;
+    d.gs_val = A.kind == MAT_STENCIL ? A.coef : A.csr.val;
+    d.gs_b = b;
+    if (A.kind == MAT_STENCIL) d.coef = gs->val_out;
+    else d.val = gs->val_out;
+    d.b = gs->b_out;
+    d.W = gs->weight_out;
+  }
   e->h_sys[slot] = d;
   e->tags[slot] = tag;
   e->active[slot] = 1;
@@ -628,7 +682,7 @@ int engine_submit(Engine* e, const Mat& A, const double* b, double* x, const Sol
   e->dirty = true;
   BCtl* c = e->args.ctl + slot;
   hipLaunchKernelGGL(k_batch_init, dim3(1), dim3(64), 0, e->s, c, prm.maxit, prm.tol, prm.eps_b,
-                     prm.weights ? 1 : 0);
+                     d.W ? 1 : 0, gs ? 1 : 0);
   if (A.kind == MAT_CSR) {
     int64_t blocks = ((int64_t)A.csr.nnz + A.n + BS) / BS;
     if (blocks > 2048) blocks = 2048;
@@ -661,6 +715,8 @@ static int upload(Engine& e) {
 static void enqueue_chunk(Engine& e, int k, int64_t first_iter) {
   const dim3 gt(e.grid_tiles), gs(e.max_sys), block(BS);
   BArgsB a = e.args;
+  hipLaunchKernelGGL(k_batch_gs, gt, block, 0, e.s, a);
+  hipLaunchKernelGGL(k_batch_fin_gs, gs, dim3(64), 0, e.s, a);
   hipLaunchKernelGGL(k_batch_residual, gt, block, 0, e.s, a);
   hipLaunchKernelGGL(k_batch_fin_residual, gs, block, 0, e.s, a);
   for (int it = 0; it < k; ++it) {

@@ -1,11 +1,8 @@
 // GS(p) row scaling, CSR validation and the standalone sparse product y = A x.
 //
-// GS(p) (section 1; section 2, eq. (2)): row i of A and b_i are divided by
-// ||a_i||_p = (sum_j |a_ij|^p)^(1/p). One pass over the values: a tile of BS rows stages its
-// values in LDS with coalesced loads, each thread sums its own row in storage order (the same
-// order and rounding as a sequential loop: p = 1 adds |a|, p = 2 adds a*a rounded), and the
-// scaled values are written back coalesced. HBM traffic per row: read val (8/entry) and
-// row_ptr (4), read b (8), write val (8/entry), b (8), and the optional norm/weight (8 each).
+// GS(p) (section 1; section 2, eq. (2)) is gs_csr_tile (gsk_dev.hpp) over one tile of rows per
+// workgroup. HBM traffic per row: read val (8/entry) and row_ptr (4), read b (8), write val
+// (8/entry), b (8), and the optional norm/weight (8 each).
 #include "gsk_host.hpp"
 
 namespace gsk {
@@ -48,19 +45,6 @@ hipError_t launch_validate(const Csr& A, int* flags, hipStream_t s) {
   return hipGetLastError();
 }
 
-// |a|^p for integer p >= 1 (p = 1 and p = 2 exactly as a sequential loop would round them).
-__device__ inline double abs_pow(double a, int p) {
-  if (p == 1) return fabs(a);
-  if (p == 2) return a * a;
-  return pow(fabs(a), (double)p);
-}
-
-__device__ inline double root_p(double s, int p) {
-  if (p == 1) return s;
-  if (p == 2) return sqrt(s);
-  return pow(s, 1.0 / (double)p);
-}
-
 __global__ __launch_bounds__(BS) void k_gs_scale(const int* __restrict__ rp,
                                                  const int* __restrict__ ci,
                                                  const double* __restrict__ val,
@@ -68,65 +52,17 @@ __global__ __launch_bounds__(BS) void k_gs_scale(const int* __restrict__ rp,
                                                  int tiles, double* val_out, double* b_out,
                                                  double* __restrict__ norm_out,
                                                  double* __restrict__ weight_out, int* flags) {
-#pragma clang fp contract(off)
   (void)ci;
   if (flags[0]) return;  // invalid CSR: touch nothing
   const int tile = logical_block();
   if (tile >= tiles) return;
-  __shared__ int s_rp[BS + 1];
-  __shared__ double s_val[TILE_NNZ];
-  __shared__ int s_row[TILE_NNZ];
-  __shared__ double s_scale[BS];
-  const int t = threadIdx.x;
+  __shared__ GsLds L;
   const int row0 = tile * BS;
-  const int nrows = min(BS, n - row0);
-  for (int i = t; i <= nrows; i += BS) s_rp[i] = rp[row0 + i];
-  __syncthreads();
-  const int p0 = s_rp[0];
-  const int cnt = s_rp[nrows] - p0;
-  const bool staged = cnt <= TILE_NNZ;
-  if (staged) {
-    for (int k = t; k < cnt; k += BS) s_val[k] = val[p0 + k];
-    __syncthreads();
-  }
   bool zero = false, nonfinite = false;
-  double nrm = 0.0;
-  if (t < nrows) {
-    const int ks = s_rp[t] - p0, ke = s_rp[t + 1] - p0;
-    double sp = 0.0, s2 = 0.0;
-    for (int k = ks; k < ke; ++k) {
-      const double a = staged ? s_val[k] : val[p0 + k];
-      if (!isfinite(a)) nonfinite = true;
-      sp += abs_pow(a, p);
-      s2 += a * a;
-      if (staged) s_row[k] = t;
-    }
-    const double bi = b[row0 + t];
-    if (!isfinite(bi)) nonfinite = true;
-    if (sp == 0.0) zero = true;
-    if (!nonfinite && !zero) {
-      nrm = root_p(sp, p);
-      if (!isfinite(nrm) || !isfinite(s2)) nonfinite = true;
-    }
-    const bool ok = !nonfinite && !zero;
-    if (ok) {
-      b_out[row0 + t] = bi / nrm;
-      if (norm_out) norm_out[row0 + t] = nrm;
-      if (weight_out) weight_out[row0 + t] = nrm / sqrt(s2);
-      if (!staged)
-        for (int k = ks; k < ke; ++k) val_out[p0 + k] = val[p0 + k] / nrm;
-    }
-    s_scale[t] = ok ? nrm : 0.0;
-  }
+  gs_csr_tile(rp, val, b, p, row0, min(BS, n - row0), val_out, b_out, norm_out, weight_out, L,
+              zero, nonfinite);
   if (zero) atomicOr(&flags[1], 1);
   if (nonfinite) atomicOr(&flags[2], 1);
-  if (staged) {
-    __syncthreads();
-    for (int k = t; k < cnt; k += BS) {
-      const double d = s_scale[s_row[k]];
-      if (d != 0.0) val_out[p0 + k] = s_val[k] / d;
-    }
-  }
 }
 
 hipError_t launch_gs_scale(const Csr& A, const double* b, int p, double* val_out, double* b_out,

@@ -36,6 +36,7 @@ enum : int {
   ST_VERIFY = 4,      // true-residual check pending
   ST_FINAL = 5,       // breakdown: final true residual pending, status already set
   ST_DONE = 6,        // finished; status valid
+  ST_SCALE = 7,       // batch engine: GS(p) of the system pending
 };
 
 enum : int { S_CONVERGED = 0, S_MAXIT = 1, S_BREAKDOWN = 2, S_STAGNATED = 3 };
@@ -328,6 +329,139 @@ __device__ inline double csr_tile(const int* __restrict__ row_ptr, const int* __
   }
   __syncthreads();   // LDS is reused by the next tile
   return y;
+}
+
+// ---------------------------------------------------------------------------------------
+// GS(p) row scaling (section 1; section 2, eq. (2)): row i of A and b_i are divided by
+// ||a_i||_p = (sum_j |a_ij|^p)^(1/p). Each row is summed in storage order, the same order and
+// rounding as a sequential loop (p = 1 adds |a|, p = 2 adds a*a rounded); the stop-test weight
+// of the row is ||a_i||_p / ||a_i||_2.
+// ---------------------------------------------------------------------------------------
+__device__ inline double abs_pow(double a, int p) {
+  if (p == 1) return fabs(a);
+  if (p == 2) return a * a;
+  return pow(fabs(a), (double)p);
+}
+
+__device__ inline double root_p(double s, int p) {
+  if (p == 1) return s;
+  if (p == 2) return sqrt(s);
+  return pow(s, 1.0 / (double)p);
+}
+
+struct GsLds {
+  int rp[BS + 1];
+  double val[TILE_NNZ];
+  int row[TILE_NNZ];
+  double scale[BS];
+};
+
+// One tile of a CSR matrix (rows row0 .. row0+nrows-1, thread t owns row row0+t): the tile's
+// values are staged in LDS with coalesced loads, each thread sums its row, and the scaled
+// values are written back coalesced. A row that is zero or non-finite sets the flag and leaves
+// its outputs unwritten. All threads of the workgroup must call.
+__device__ inline void gs_csr_tile(const int* __restrict__ rp, const double* __restrict__ val,
+                                   const double* __restrict__ b, int p, int row0, int nrows,
+                                   double* val_out, double* b_out, double* __restrict__ norm_out,
+                                   double* __restrict__ weight_out, GsLds& L, bool& zero,
+                                   bool& nonfinite) {
+#pragma clang fp contract(off)
+  const int t = threadIdx.x;
+  for (int i = t; i <= nrows; i += BS) L.rp[i] = rp[row0 + i];
+  __syncthreads();
+  const int p0 = L.rp[0];
+  const int cnt = L.rp[nrows] - p0;
+  const bool staged = cnt <= TILE_NNZ;
+  if (staged) {
+    for (int k = t; k < cnt; k += BS) L.val[k] = val[p0 + k];
+    __syncthreads();
+  }
+  double nrm = 0.0;
+  if (t < nrows) {
+    const int ks = L.rp[t] - p0, ke = L.rp[t + 1] - p0;
+    double sp = 0.0, s2 = 0.0;
+    for (int k = ks; k < ke; ++k) {
+      const double a = staged ? L.val[k] : val[p0 + k];
+      if (!isfinite(a)) nonfinite = true;
+      sp += abs_pow(a, p);
+      s2 += a * a;
+      if (staged) L.row[k] = t;
+    }
+    const double bi = b[row0 + t];
+    if (!isfinite(bi)) nonfinite = true;
+    if (sp == 0.0) zero = true;
+    if (!nonfinite && !zero) {
+      nrm = root_p(sp, p);
+      if (!isfinite(nrm) || !isfinite(s2)) nonfinite = true;
+    }
+    const bool ok = !nonfinite && !zero;
+    if (ok) {
+      b_out[row0 + t] = bi / nrm;
+      if (norm_out) norm_out[row0 + t] = nrm;
+      if (weight_out) weight_out[row0 + t] = nrm / sqrt(s2);
+      if (!staged)
+        for (int k = ks; k < ke; ++k) val_out[p0 + k] = val[p0 + k] / nrm;
+    }
+    L.scale[t] = ok ? nrm : 0.0;
+  }
+  if (staged) {
+    __syncthreads();
+    for (int k = t; k < cnt; k += BS) {
+      const double d = L.scale[L.row[k]];
+      if (d != 0.0) val_out[p0 + k] = L.val[k] / d;
+    }
+  }
+  __syncthreads();   // LDS is reused by the caller's next tile
+}
+
+// One row i of a 5/7-point stencil matrix held as coefficient planes (stride ldp): the present
+// positions are summed in the CSR column order, so the norm, weight and scaled values equal
+// those of the CSR form bit for bit (an absent position's coefficient, 0, is scaled to 0).
+__device__ inline void gs_stencil_row(const double* __restrict__ coef, size_t ldp, int n,
+                                      int nx, int ny, int nz, const double* __restrict__ b,
+                                      int p, int i, double* coef_out, double* b_out,
+                                      double* __restrict__ weight_out, bool& zero,
+                                      bool& nonfinite) {
+#pragma clang fp contract(off)
+  const int ix = i % nx;
+  const int rest = i / nx;
+  const int iy = rest % ny;
+  const int iz = rest / ny;
+  const bool three = nz > 1;
+  const bool in[7] = {three && iz > 0, iy > 0,      ix > 0, true,
+                      ix < nx - 1,     iy < ny - 1, three && iz < nz - 1};
+  const int planes = three ? 7 : 5;
+  double c[7];
+  double sp = 0.0, s2 = 0.0;
+  bool bad = false;
+#pragma unroll
+  for (int q = 0; q < 7; ++q) {
+    const int plane = three ? q : q - 1;
+    c[q] = (plane >= 0 && plane < planes) ? coef[(size_t)plane * ldp + i] : 0.0;
+    if (plane >= 0 && plane < planes && !isfinite(c[q])) bad = true;
+    if (in[q]) {
+      sp += abs_pow(c[q], p);
+      s2 += c[q] * c[q];
+    }
+  }
+  const double bi = b[i];
+  if (!isfinite(bi)) bad = true;
+  bool z = sp == 0.0;
+  double nrm = 0.0;
+  if (!bad && !z) {
+    nrm = root_p(sp, p);
+    if (!isfinite(nrm) || !isfinite(s2)) bad = true;
+  }
+  if (bad) nonfinite = true;
+  if (z) zero = true;
+  if (bad || z) return;
+  b_out[i] = bi / nrm;
+  if (weight_out) weight_out[i] = nrm / sqrt(s2);
+#pragma unroll
+  for (int q = 0; q < 7; ++q) {
+    const int plane = three ? q : q - 1;
+    if (plane >= 0 && plane < planes) coef_out[(size_t)plane * ldp + i] = c[q] / nrm;
+  }
 }
 
 // A gather supplies the source-vector entry of a column in two steps: load(col) fetches the

@@ -117,9 +117,17 @@ size_t engine_workspace_bytes(int64_t max_rows, int max_sys);
 int engine_create(void* ws, size_t ws_bytes, int64_t max_rows, int max_sys, int check_every,
                   bool use_graph, hipStream_t s, Engine** out);
 void engine_destroy(Engine* e);
+// Optional GS(p) stage of a submitted system: outputs of the scaled matrix values (CSR values
+// or planes, same layout as the input), b and (p != 2) stop weights.
+struct GsStage {
+  int p;
+  double* val_out;
+  double* b_out;
+  double* weight_out;
+};
 // 0 admitted, 1 no free slot or rows (try again after a poll), -5 HIP failure.
 int engine_submit(Engine* e, const Mat& A, const double* b, double* x, const SolveParams& prm,
-                  int64_t tag);
+                  int64_t tag, const GsStage* gs = nullptr);
 int engine_run(Engine* e, int chunks);
 int engine_poll(Engine* e, bool wait, EngineDone* out, int max_out, int* n_out);
 void engine_usage(const Engine* e, int* active, int64_t* free_rows, int64_t* largest_free_rows);

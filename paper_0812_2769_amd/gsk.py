@@ -132,6 +132,9 @@ def _load() -> ctypes.CDLL:
     lib.gsk_engine_submit.argtypes = [vp, P(Matrix), vp, vp, ctypes.c_double, P(Options),
                                       ctypes.c_int64]
     lib.gsk_engine_submit.restype = ctypes.c_int
+    lib.gsk_engine_submit_gs.argtypes = [vp, P(Matrix), vp, ctypes.c_int32, vp, vp, vp, vp,
+                                         ctypes.c_double, P(Options), ctypes.c_int64]
+    lib.gsk_engine_submit_gs.restype = ctypes.c_int
     lib.gsk_engine_run.argtypes = [vp, ctypes.c_int32]
     lib.gsk_engine_run.restype = ctypes.c_int
     lib.gsk_engine_poll.argtypes = [vp, ctypes.c_int32, P(Result), ctypes.c_int32,
@@ -477,6 +480,29 @@ class Engine:
             return False
         _check(rc)
         self._keep[int(tag)] = (A, b, x, stop_weights)
+        return True
+
+    def submit_gs(self, A, b: torch.Tensor, x: torch.Tensor, p: int = 2, tol: float = 1e-8, *,
+                  tag: int, maxit: Optional[int] = None, breakdown_eps=None) -> bool:
+        """Admit an unscaled system with a GS(p) stage; the engine scales it in its first chunk
+        (outputs allocated here and kept until the system is reported). False if it does not
+        fit now."""
+        _vec(b, A.n, "b")
+        _vec(x, A.n, "x")
+        src = A.coef if isinstance(A, StencilMatrix) else A.val
+        val_out = torch.empty_like(src)
+        b_out = torch.empty_like(b)
+        w_out = torch.empty_like(b) if p != 2 else None
+        o = _options(maxit, breakdown_eps, None, None, A.n)
+        c = A.c_matrix()
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        rc = lib.gsk_engine_submit_gs(self._h, ctypes.byref(c), b.data_ptr(), int(p),
+                                      val_out.data_ptr(), b_out.data_ptr(), _ptr(w_out),
+                                      x.data_ptr(), float(tol), ctypes.byref(o), int(tag))
+        if rc == FULL:
+            return False
+        _check(rc)
+        self._keep[int(tag)] = (A, b, x, val_out, b_out, w_out)
         return True
 
     def run(self, chunks: int = 1) -> None:

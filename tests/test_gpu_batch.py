@@ -182,3 +182,51 @@ def test_engine_argument_errors(G):
         G.Engine(max_rows=0, max_systems=4)
     with pytest.raises(G.GskError):
         G.Engine(max_rows=1024, max_systems=4, check_every=7, graph=True)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_engine_gs_stage_equals_solo(G, graph):
+    """GS(p) inside the engine (first chunk) + Bi-CGSTAB == gsk_gs_scale (+ stencil packing)
+    + gsk_bicgstab, bit for bit, for stencil and CSR systems, p = 2 and p = 1."""
+    import torch
+    specs = problems.config4_specs(5, seed=9, n_min=8, n_max=24)
+    eng = G.Engine(max_rows=1 << 17, max_systems=8, graph=graph)
+    ref, xs = {}, {}
+    for i, sp in enumerate(specs):
+        P = problems.config4_system(sp)
+        p = 1 if i == 1 else 2
+        stencil = i != 2
+        A = G.CsrMatrix.from_problem(P)
+        b = dev(P.b)
+        As, bs, _, w = G.gs_scale(A, b, p, want_weights=(p != 2))
+        Ms = G.stencil_from_csr(As, *grid_of(P)) if stencil else As
+        x, info = G.bicgstab(Ms, bs, tol=1e-10, stop_weights=w if p != 2 else None)
+        ref[i] = (host(x), info)
+        M = G.stencil_from_csr(A, *grid_of(P)) if stencil else A
+        xs[i] = torch.zeros_like(b)
+        assert eng.submit_gs(M, b, xs[i], p=p, tol=1e-10, tag=i)
+    done = {}
+    for _ in range(2000):
+        eng.run(1)
+        done.update(dict(eng.poll()))
+        if len(done) == len(specs):
+            break
+    torch.cuda.synchronize()
+    for i in ref:
+        same((host(xs[i]), done[i]), ref[i])
+    eng.close()
+
+
+def test_engine_gs_stage_zero_row(G):
+    import torch
+    P = problems.laplacian((6, 6))
+    val = P.val.copy()
+    val[P.row_ptr[7]:P.row_ptr[8]] = 0.0      # row 7 all zero
+    A = G.CsrMatrix.from_numpy(P.row_ptr, P.col_idx, val)
+    eng = G.Engine(max_rows=256, max_systems=2)
+    x = torch.zeros(P.n, dtype=torch.float64, device="cuda")
+    assert eng.submit_gs(A, dev(P.b), x, p=2, tol=1e-8, tag=5)
+    eng.run(1)
+    done = dict(eng.poll())
+    assert done[5].status == -2 and not x.any()
+    eng.close()

@@ -1,0 +1,81 @@
+"""Serving with continuous batching: every result equals the same solve done alone.
+
+Requests (a Bi-CGSTAB / GMRES(20) mix, GS(2) per request) arrive while others are on the GPU
+and are admitted as the engine's rows and slots free up. Each Bi-CGSTAB result must equal
+gsk_gs_scale + stencil packing + gsk_bicgstab on the same system alone, bit for bit (x, info);
+each GMRES result must equal the single GMRES solve.
+"""
+import numpy as np
+import pytest
+
+from paper_0812_2769_amd import problems
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0812_2769_amd import gsk
+    return gsk
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def pool(G, count=6):
+    out = []
+    for sp in problems.config4_specs(count, seed=21, n_min=8, n_max=28):
+        P = problems.config4_system(sp)
+        A = G.CsrMatrix.from_problem(P)
+        d = list(P.dims) + [1] * (3 - len(P.dims))
+        out.append({"A": A, "S": G.stencil_from_csr(A, *d), "b": dev(P.b), "grid": tuple(d),
+                    "n": P.n})
+    return out
+
+
+def alone(G, s, method):
+    As, bs, _, _ = G.gs_scale(s["A"], s["b"], 2, want_norms=False)
+    M = G.stencil_from_csr(As, *s["grid"])
+    if method == "gmres":
+        return G.gmres(M, bs, m=20, tol=1e-8)
+    return G.bicgstab(M, bs, tol=1e-8)
+
+
+@pytest.mark.parametrize("realtime", [False, True])
+def test_serving_results_equal_solo(G, realtime):
+    import torch
+    from paper_0812_2769_amd import serve
+    systems = pool(G)
+    rng = np.random.default_rng(3)
+    n_req = 24
+    arrivals = np.cumsum(rng.exponential(1 / 400.0, size=n_req))
+    picks = rng.integers(0, len(systems), size=n_req)
+    kinds = rng.random(n_req) < 0.25
+    reqs = [serve.Request(tag=k, arrival=float(arrivals[k]), A=systems[picks[k]]["S"],
+                          b=systems[picks[k]]["b"], method="gmres" if kinds[k] else "bicgstab",
+                          m=20, tol=1e-8, csr=systems[picks[k]]["A"],
+                          grid=systems[picks[k]]["grid"]) for k in range(n_req)]
+    # room for about two systems at a time: admission has to wait for retirements
+    rows = sorted(((s["n"] + 255) // 256 * 256 for s in systems), reverse=True)
+    srv = serve.Server(rows[0] + rows[1], 4, check_every=8, graph=True,
+                       gmres_rows=max(s["n"] for s in systems), m_max=20)
+    done = srv.serve(reqs, realtime=realtime)
+    srv.close()
+    assert sorted(d.tag for d in done) == list(range(n_req))
+    # admissions were spread over the run (requests joined while others were on the GPU)
+    assert len({round(d.admitted, 6) for d in done if d.method == "bicgstab"}) > 1
+    torch.cuda.synchronize()
+    ref = {}
+    for d in done:
+        key = (int(picks[d.tag]), d.method)
+        if key not in ref:
+            x, info = alone(G, systems[key[0]], key[1])
+            ref[key] = (x.cpu().numpy(), info)
+        xr, ir = ref[key]
+        assert d.info == ir, (d.tag, d.method, d.info, ir)
+        assert np.array_equal(d.x.cpu().numpy(), xr), (d.tag, d.method)
