@@ -9,9 +9,11 @@
 // Layout. The engine owns a workspace with room for max_rows rows of vectors (r, r^, p x2,
 // v x2, t) and max_systems control blocks. A system of n rows gets ceil(n / BS) consecutive
 // tiles of that row space (first fit over free tiles); its matrix, b, x and stop weights stay
-// in the caller's memory. A device table maps every tile to its system (or -1), so one
-// launch over all tiles serves every system; a finalize launch has one workgroup per system
-// slot and sums that system's tile partials.
+// in the caller's memory. A device list holds the tiles of the admitted systems (with each
+// tile's system); a streaming launch has one workgroup per list entry (the grid rounded up
+// to a few sizes, each with its own captured graph), so it costs work only for admitted
+// systems; a finalize launch has one workgroup per system slot and sums that
+// system's tile partials.
 //
 // A system may be submitted unscaled with a GS(p) stage (section 2, eq. (2)): the first chunk
 // scales its rows into caller-provided outputs (with the arithmetic of gsk_gs_scale) and the
@@ -19,8 +21,8 @@
 //
 // Time. The host enqueues chunks: the GS launch (scales newly admitted systems that asked for
 // it), the residual launch (starts newly admitted systems and verifies convergence claims),
-// then check_every iterations. A chunk has fixed launch
-// shapes and arguments, so it can be captured once in a HIP graph and replayed. Between
+// then check_every iterations. For a given grid size a chunk has fixed launch shapes and
+// arguments, so it can be captured once in a HIP graph and replayed. Between
 // chunks the host reads every slot's status and retires finished systems; new systems are
 // admitted between chunks (continuous batching).
 #include <map>
@@ -57,7 +59,8 @@ enum : int { BAD_CSR = 1, BAD_ZERO = 2, BAD_NONFINITE = 4 };
 
 struct BArgsB {
   const SysDesc* sys;
-  const int* tile_sys;   // [max_tiles]: slot of each tile, -1 if free
+  const int* act;        // [2][max_tiles]: tiles of the admitted systems, then their slots
+  const int* n_act;      // number of entries in act
   BCtl* ctl;             // [max_systems]
   double* partials;      // [4][max_tiles]
   int max_tiles;
@@ -69,10 +72,13 @@ struct BArgsB {
   int par;               // buffer parity of this iteration
 };
 
-__device__ inline int batch_tile(const BArgsB& a, int& s) {
-  const int tile = logical_block();
-  s = tile < a.max_tiles ? a.tile_sys[tile] : -1;
-  return tile;
+// Calls body(tile, slot) for the list entry of this workgroup (logical block k takes entry k;
+// consecutive entries, adjacent rows of one system, go to one XCD). Workgroups past the end of
+// the list (the launch grid is the list length rounded up) return at once.
+template <class Body>
+__device__ inline void for_active_tiles(const BArgsB& a, Body body) {
+  const int k = logical_block();
+  if (k < *a.n_act) body(a.act[k], a.act[a.max_tiles + k]);
 }
 
 struct GatherPB {
@@ -162,28 +168,27 @@ __global__ __launch_bounds__(BS) void k_batch_validate(const int* __restrict__ r
 
 // G: GS(p) of the systems whose stage is pending (same arithmetic as k_gs_scale).
 __global__ __launch_bounds__(BS) void k_batch_gs(BArgsB a) {
-  int s;
-  const int tile = batch_tile(a, s);
-  if (s < 0) return;
-  const SysDesc d = a.sys[s];
-  BCtl* c = a.ctl + s;
-  if (c->sum.state != ST_SCALE || (c->bad & BAD_CSR)) return;
   __shared__ GsLds L;
-  const int row0 = (tile - d.tile_off) * BS;
-  const int nrows = min(BS, d.n - row0);
-  bool zero = false, nonfinite = false;
-  if (d.kind == MAT_STENCIL) {
-    if ((int)threadIdx.x < nrows)
-      gs_stencil_row(d.gs_val, (size_t)d.n, d.n, d.nx, d.ny, d.nz, d.gs_b, d.gs_p,
-                     row0 + threadIdx.x, const_cast<double*>(d.coef), const_cast<double*>(d.b),
-                     const_cast<double*>(d.W), zero, nonfinite);
-  } else {
-    gs_csr_tile(d.rp, d.gs_val, d.gs_b, d.gs_p, row0, nrows, const_cast<double*>(d.val),
-                const_cast<double*>(d.b), nullptr, const_cast<double*>(d.W), L, zero,
-                nonfinite);
-  }
-  if (zero) atomicOr(&c->bad, BAD_ZERO);
-  if (nonfinite) atomicOr(&c->bad, BAD_NONFINITE);
+  for_active_tiles(a, [&](int tile, int s) {
+    const SysDesc d = a.sys[s];
+    BCtl* c = a.ctl + s;
+    if (c->sum.state != ST_SCALE || (c->bad & BAD_CSR)) return;
+    const int row0 = (tile - d.tile_off) * BS;
+    const int nrows = min(BS, d.n - row0);
+    bool zero = false, nonfinite = false;
+    if (d.kind == MAT_STENCIL) {
+      if ((int)threadIdx.x < nrows)
+        gs_stencil_row(d.gs_val, (size_t)d.n, d.n, d.nx, d.ny, d.nz, d.gs_b, d.gs_p,
+                       row0 + threadIdx.x, const_cast<double*>(d.coef), const_cast<double*>(d.b),
+                       const_cast<double*>(d.W), zero, nonfinite);
+    } else {
+      gs_csr_tile(d.rp, d.gs_val, d.gs_b, d.gs_p, row0, nrows, const_cast<double*>(d.val),
+                  const_cast<double*>(d.b), nullptr, const_cast<double*>(d.W), L, zero,
+                  nonfinite);
+    }
+    if (zero) atomicOr(&c->bad, BAD_ZERO);
+    if (nonfinite) atomicOr(&c->bad, BAD_NONFINITE);
+  });
 }
 
 __global__ __launch_bounds__(64) void k_batch_fin_gs(BArgsB a) {
@@ -196,35 +201,34 @@ __global__ __launch_bounds__(64) void k_batch_fin_gs(BArgsB a) {
 
 // R: r = b - A x, r^ = r for systems starting, verifying or finishing; ||r||^2, ||W r||^2.
 __global__ __launch_bounds__(BS) void k_batch_residual(BArgsB a) {
-  int s;
-  const int tile = batch_tile(a, s);
-  if (s < 0) return;
-  const SysDesc d = a.sys[s];
-  BCtl* c = a.ctl + s;
-  const int st = c->sum.state;
-  if (st != ST_INIT && st != ST_VERIFY && st != ST_FINAL) return;
-  if (c->bad) return;
   __shared__ TileLds L;
   __shared__ double red[NC_MAX * WAVES];
-  const int row0 = (tile - d.tile_off) * BS;
-  const int nrows = min(BS, d.n - row0);
-  const int t = threadIdx.x;
-  double acc[2] = {0.0, 0.0};
-  const double y = sys_tile(d, row0, nrows, GatherX{d.x}, L);
-  if (t < nrows) {
-    const int row = row0 + t;
-    const double r = d.b[row] - y;
-    if (st != ST_FINAL) {
-      a.r[d.row_off + row] = r;
-      a.rh[d.row_off + row] = r;
+  for_active_tiles(a, [&](int tile, int s) {
+    const SysDesc d = a.sys[s];
+    BCtl* c = a.ctl + s;
+    const int st = c->sum.state;
+    if (st != ST_INIT && st != ST_VERIFY && st != ST_FINAL) return;
+    if (c->bad) return;
+    const int row0 = (tile - d.tile_off) * BS;
+    const int nrows = min(BS, d.n - row0);
+    const int t = threadIdx.x;
+    double acc[2] = {0.0, 0.0};
+    const double y = sys_tile(d, row0, nrows, GatherX{d.x}, L);
+    if (t < nrows) {
+      const int row = row0 + t;
+      const double r = d.b[row] - y;
+      if (st != ST_FINAL) {
+        a.r[d.row_off + row] = r;
+        a.rh[d.row_off + row] = r;
+      }
+      acc[0] = r * r;
+      if (d.W) {
+        const double wr = d.W[row] * r;
+        acc[1] = wr * wr;
+      }
     }
-    acc[0] = r * r;
-    if (d.W) {
-      const double wr = d.W[row] * r;
-      acc[1] = wr * wr;
-    }
-  }
-  block_partials<2>(acc, 2, a.partials, a.max_tiles, tile, red);
+    block_partials<2>(acc, 2, a.partials, a.max_tiles, tile, red);
+  });
 }
 
 __global__ __launch_bounds__(BS) void k_batch_fin_residual(BArgsB a) {
@@ -300,30 +304,29 @@ __global__ __launch_bounds__(BS) void k_batch_fin_residual(BArgsB a) {
 
 // P: new p, v = A p; partials (r^, v), ||v||^2.
 __global__ __launch_bounds__(BS) void k_batch_p(BArgsB a) {
-  int s;
-  const int tile = batch_tile(a, s);
-  if (s < 0) return;
-  const SysDesc d = a.sys[s];
-  BCtl* c = a.ctl + s;
-  if (c->sum.state != ST_RUNNING) return;
-  const int q = a.par;
-  const int64_t o = d.row_off;
-  const GatherPB G{a.r + o, a.p[q] + o, a.v[q] + o, c->beta, c->omega, c->first};
   __shared__ TileLds L;
   __shared__ double red[NC_MAX * WAVES];
-  const int row0 = (tile - d.tile_off) * BS;
-  const int nrows = min(BS, d.n - row0);
-  const int t = threadIdx.x;
-  const double y = sys_tile(d, row0, nrows, G, L);
-  double acc[2] = {0.0, 0.0};
-  if (t < nrows) {
-    const int row = row0 + t;
-    a.p[q ^ 1][o + row] = G(row);
-    a.v[q ^ 1][o + row] = y;
-    acc[0] = a.rh[o + row] * y;
-    acc[1] = y * y;
-  }
-  block_partials<2>(acc, 2, a.partials, a.max_tiles, tile, red);
+  for_active_tiles(a, [&](int tile, int s) {
+    const SysDesc d = a.sys[s];
+    BCtl* c = a.ctl + s;
+    if (c->sum.state != ST_RUNNING) return;
+    const int q = a.par;
+    const int64_t o = d.row_off;
+    const GatherPB G{a.r + o, a.p[q] + o, a.v[q] + o, c->beta, c->omega, c->first};
+    const int row0 = (tile - d.tile_off) * BS;
+    const int nrows = min(BS, d.n - row0);
+    const int t = threadIdx.x;
+    const double y = sys_tile(d, row0, nrows, G, L);
+    double acc[2] = {0.0, 0.0};
+    if (t < nrows) {
+      const int row = row0 + t;
+      a.p[q ^ 1][o + row] = G(row);
+      a.v[q ^ 1][o + row] = y;
+      acc[0] = a.rh[o + row] * y;
+      acc[1] = y * y;
+    }
+    block_partials<2>(acc, 2, a.partials, a.max_tiles, tile, red);
+  });
 }
 
 __global__ __launch_bounds__(BS) void k_batch_fin_p(BArgsB a) {
@@ -348,34 +351,33 @@ __global__ __launch_bounds__(BS) void k_batch_fin_p(BArgsB a) {
 
 // S: t = A s with s = r - alpha v; partials (t,s), (t,t), ||s||^2, ||W s||^2.
 __global__ __launch_bounds__(BS) void k_batch_s(BArgsB a) {
-  int s;
-  const int tile = batch_tile(a, s);
-  if (s < 0) return;
-  const SysDesc d = a.sys[s];
-  BCtl* c = a.ctl + s;
-  if (c->sum.state != ST_RUNNING) return;
-  const int64_t o = d.row_off;
-  const GatherSB G{a.r + o, a.v[a.par ^ 1] + o, c->alpha};
   __shared__ TileLds L;
   __shared__ double red[NC_MAX * WAVES];
-  const int row0 = (tile - d.tile_off) * BS;
-  const int nrows = min(BS, d.n - row0);
-  const int t = threadIdx.x;
-  const double y = sys_tile(d, row0, nrows, G, L);
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  if (t < nrows) {
-    const int row = row0 + t;
-    const double sv = G(row);
-    a.t[o + row] = y;
-    acc[0] = y * sv;
-    acc[1] = y * y;
-    acc[2] = sv * sv;
-    if (d.W) {
-      const double ws = d.W[row] * sv;
-      acc[3] = ws * ws;
+  for_active_tiles(a, [&](int tile, int s) {
+    const SysDesc d = a.sys[s];
+    BCtl* c = a.ctl + s;
+    if (c->sum.state != ST_RUNNING) return;
+    const int64_t o = d.row_off;
+    const GatherSB G{a.r + o, a.v[a.par ^ 1] + o, c->alpha};
+    const int row0 = (tile - d.tile_off) * BS;
+    const int nrows = min(BS, d.n - row0);
+    const int t = threadIdx.x;
+    const double y = sys_tile(d, row0, nrows, G, L);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (t < nrows) {
+      const int row = row0 + t;
+      const double sv = G(row);
+      a.t[o + row] = y;
+      acc[0] = y * sv;
+      acc[1] = y * y;
+      acc[2] = sv * sv;
+      if (d.W) {
+        const double ws = d.W[row] * sv;
+        acc[3] = ws * ws;
+      }
     }
-  }
-  block_partials<4>(acc, 4, a.partials, a.max_tiles, tile, red);
+    block_partials<4>(acc, 4, a.partials, a.max_tiles, tile, red);
+  });
 }
 
 __global__ __launch_bounds__(BS) void k_batch_fin_s(BArgsB a) {
@@ -409,39 +411,38 @@ __global__ __launch_bounds__(BS) void k_batch_fin_s(BArgsB a) {
 // U: x += alpha p + omega s, r = s - omega t; partials (r^, r), ||r||^2, ||W r||^2.
 // After a half-step exit only x += alpha p is done.
 __global__ __launch_bounds__(BS) void k_batch_u(BArgsB a) {
-  int s;
-  const int tile = batch_tile(a, s);
-  if (s < 0) return;
-  const SysDesc d = a.sys[s];
-  BCtl* c = a.ctl + s;
-  const int st = c->sum.state;
-  if (st != ST_RUNNING && st != ST_HALF) return;
-  const int q = a.par ^ 1;
-  const int64_t o = d.row_off;
-  const double* p = a.p[q] + o;
-  const double* v = a.v[q] + o;
-  const double alpha = c->alpha, omega = c->omega;
   __shared__ double red[NC_MAX * WAVES];
-  const int row = (tile - d.tile_off) * BS + threadIdx.x;
-  const bool mine = row < d.n;
-  if (st == ST_HALF) {
-    if (mine) d.x[row] = fma(alpha, p[row], d.x[row]);
-    return;
-  }
-  double acc[3] = {0.0, 0.0, 0.0};
-  if (mine) {
-    const double sv = fma(-alpha, v[row], a.r[o + row]);
-    d.x[row] = fma(omega, sv, fma(alpha, p[row], d.x[row]));
-    const double r = fma(-omega, a.t[o + row], sv);
-    a.r[o + row] = r;
-    acc[0] = a.rh[o + row] * r;
-    acc[1] = r * r;
-    if (d.W) {
-      const double wr = d.W[row] * r;
-      acc[2] = wr * wr;
+  for_active_tiles(a, [&](int tile, int s) {
+    const SysDesc d = a.sys[s];
+    BCtl* c = a.ctl + s;
+    const int st = c->sum.state;
+    if (st != ST_RUNNING && st != ST_HALF) return;
+    const int q = a.par ^ 1;
+    const int64_t o = d.row_off;
+    const double* p = a.p[q] + o;
+    const double* v = a.v[q] + o;
+    const double alpha = c->alpha, omega = c->omega;
+    const int row = (tile - d.tile_off) * BS + threadIdx.x;
+    const bool mine = row < d.n;
+    if (st == ST_HALF) {
+      if (mine) d.x[row] = fma(alpha, p[row], d.x[row]);
+      return;
     }
-  }
-  block_partials<3>(acc, 3, a.partials, a.max_tiles, tile, red);
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (mine) {
+      const double sv = fma(-alpha, v[row], a.r[o + row]);
+      d.x[row] = fma(omega, sv, fma(alpha, p[row], d.x[row]));
+      const double r = fma(-omega, a.t[o + row], sv);
+      a.r[o + row] = r;
+      acc[0] = a.rh[o + row] * r;
+      acc[1] = r * r;
+      if (d.W) {
+        const double wr = d.W[row] * r;
+        acc[2] = wr * wr;
+      }
+    }
+    block_partials<3>(acc, 3, a.partials, a.max_tiles, tile, red);
+  });
 }
 
 __global__ __launch_bounds__(BS) void k_batch_fin_u(BArgsB a) {
@@ -495,7 +496,7 @@ static EngineLayout engine_layout(int64_t max_rows, int max_sys) {
   L.sys = off;
   off += align256(sizeof(SysDesc) * (size_t)max_sys);
   L.tiles = off;
-  off += align256(sizeof(int) * (size_t)grid_tiles);
+  off += align256(sizeof(int) * (2 * (size_t)grid_tiles + 1));
   L.ctl = off;
   off += align256(sizeof(BCtl) * (size_t)max_sys);
   L.partials = off;
@@ -521,7 +522,7 @@ struct Engine {
   std::vector<SysDesc> h_sys;
   std::vector<int64_t> tags;
   std::vector<char> active;
-  std::vector<int> tile_sys;
+  std::vector<int> tile_sys;       // slot of every tile, -1 if free
   std::map<int, int> free_tiles;   // start -> length
   bool dirty = true;
   int64_t launched = 0;
@@ -531,9 +532,24 @@ struct Engine {
   BCtl* p_ctl = nullptr;
   hipEvent_t ev_upload = nullptr, ev_chunk = nullptr;
   bool upload_pending = false, chunk_pending = false;
-  hipGraphExec_t graph = nullptr;
-  int graph_k = 0;
+  int n_listed = 0;                          // entries of the device tile list
+  std::map<int, hipGraphExec_t> graphs;      // captured chunk per streaming grid size
 };
+
+// Streaming grid for a list of n tiles: n rounded up to a multiple of 8 (the XCD mapping of
+// logical_block needs it) and, from 32 on, to two significant bits (4..7 times a power of two),
+// so that the grid, and the captured graph that holds it, changes only when the list has grown
+// or shrunk by about a quarter; the surplus workgroups exit at once.
+static int stream_grid(int n) {
+  int g = n < 8 ? 8 : (n + 7) / 8 * 8;
+  int top = 1;
+  while (top * 2 <= g) top *= 2;
+  if (top >= 32) {
+    const int step = top / 4;
+    g = (g + step - 1) / step * step;
+  }
+  return g;
+}
 
 static bool alloc_tiles(Engine& e, int need, int& start) {
   for (auto it = e.free_tiles.begin(); it != e.free_tiles.end(); ++it) {
@@ -580,7 +596,8 @@ int engine_create(void* ws, size_t ws_bytes, int64_t max_rows, int max_sys, int 
   char* base = static_cast<char*>(ws);
   BArgsB& a = e->args;
   a.sys = reinterpret_cast<const SysDesc*>(base + L.sys);
-  a.tile_sys = reinterpret_cast<const int*>(base + L.tiles);
+  a.act = reinterpret_cast<const int*>(base + L.tiles);
+  a.n_act = a.act + 2 * (size_t)e->grid_tiles;
   a.ctl = reinterpret_cast<BCtl*>(base + L.ctl);
   a.partials = reinterpret_cast<double*>(base + L.partials);
   a.max_tiles = e->grid_tiles;
@@ -602,7 +619,8 @@ int engine_create(void* ws, size_t ws_bytes, int64_t max_rows, int max_sys, int 
   e->free_tiles[0] = e->max_tiles;
   bool ok = hipHostMalloc((void**)&e->p_sys, sizeof(SysDesc) * max_sys, hipHostMallocDefault) ==
                 hipSuccess &&
-            hipHostMalloc((void**)&e->p_tiles, sizeof(int) * e->grid_tiles, hipHostMallocDefault) ==
+            hipHostMalloc((void**)&e->p_tiles, sizeof(int) * (2 * (size_t)e->grid_tiles + 1),
+                          hipHostMallocDefault) ==
                 hipSuccess &&
             hipHostMalloc((void**)&e->p_ctl, sizeof(BCtl) * max_sys, hipHostMallocDefault) ==
                 hipSuccess &&
@@ -619,7 +637,7 @@ int engine_create(void* ws, size_t ws_bytes, int64_t max_rows, int max_sys, int 
 void engine_destroy(Engine* e) {
   if (!e) return;
   if (e->s) (void)hipStreamSynchronize(e->s);
-  if (e->graph) (void)hipGraphExecDestroy(e->graph);
+  for (auto& kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
   if (e->ev_upload) (void)hipEventDestroy(e->ev_upload);
   if (e->ev_chunk) (void)hipEventDestroy(e->ev_chunk);
   if (e->p_sys) (void)hipHostFree(e->p_sys);
@@ -700,11 +718,20 @@ static int upload(Engine& e) {
     e.p_sys[i] = e.h_sys[i];
     if (!e.active[i]) e.p_sys[i].ntiles = 0;
   }
-  for (int t = 0; t < e.grid_tiles; ++t) e.p_tiles[t] = e.tile_sys[t];
+  int n = 0;
+  for (int t = 0; t < e.grid_tiles; ++t) {
+    if (e.tile_sys[t] < 0) continue;
+    e.p_tiles[n] = t;
+    e.p_tiles[e.grid_tiles + n] = e.tile_sys[t];
+    ++n;
+  }
+  e.p_tiles[2 * (size_t)e.grid_tiles] = n;
+  e.n_listed = n;
   if (hipMemcpyAsync(const_cast<SysDesc*>(e.args.sys), e.p_sys, sizeof(SysDesc) * e.max_sys,
                      hipMemcpyHostToDevice, e.s) != hipSuccess ||
-      hipMemcpyAsync(const_cast<int*>(e.args.tile_sys), e.p_tiles, sizeof(int) * e.grid_tiles,
-                     hipMemcpyHostToDevice, e.s) != hipSuccess ||
+      hipMemcpyAsync(const_cast<int*>(e.args.act), e.p_tiles,
+                     sizeof(int) * (2 * (size_t)e.grid_tiles + 1), hipMemcpyHostToDevice,
+                     e.s) != hipSuccess ||
       hipEventRecord(e.ev_upload, e.s) != hipSuccess)
     return -5;
   e.upload_pending = true;
@@ -712,8 +739,8 @@ static int upload(Engine& e) {
   return 0;
 }
 
-static void enqueue_chunk(Engine& e, int k, int64_t first_iter) {
-  const dim3 gt(e.grid_tiles), gs(e.max_sys), block(BS);
+static void enqueue_chunk(Engine& e, int k, int64_t first_iter, int grid) {
+  const dim3 gt(grid), gs(e.max_sys), block(BS);
   BArgsB a = e.args;
   hipLaunchKernelGGL(k_batch_gs, gt, block, 0, e.s, a);
   hipLaunchKernelGGL(k_batch_fin_gs, gs, dim3(64), 0, e.s, a);
@@ -733,25 +760,30 @@ static void enqueue_chunk(Engine& e, int k, int64_t first_iter) {
 int engine_run(Engine* e, int chunks) {
   if (upload(*e)) return -5;
   const int k = e->check_every;
-  for (int c = 0; c < chunks; ++c) {
-    if (e->use_graph) {
-      // Every chunk starts at an even iteration (k is even), so one captured chunk serves all.
-      if (!e->graph) {
-        hipGraph_t g = nullptr;
-        if (hipStreamBeginCapture(e->s, hipStreamCaptureModeThreadLocal) != hipSuccess) return -5;
-        enqueue_chunk(*e, k, 0);
-        if (hipStreamEndCapture(e->s, &g) != hipSuccess) return -5;
-        const hipError_t r = hipGraphInstantiate(&e->graph, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (r != hipSuccess) {
-          e->graph = nullptr;
-          return -5;
-        }
-        e->graph_k = k;
-      }
-      if (hipGraphLaunch(e->graph, e->s) != hipSuccess) return -5;
+  const int grid = stream_grid(e->n_listed);
+  hipGraphExec_t exec = nullptr;
+  if (e->use_graph) {
+    // Every chunk starts at an even iteration (k is even), so one captured chunk per grid size
+    // serves all; the chunk reads the tile list and control blocks from device memory.
+    auto it = e->graphs.find(grid);
+    if (it != e->graphs.end()) {
+      exec = it->second;
     } else {
-      enqueue_chunk(*e, k, e->launched);
+      hipGraph_t g = nullptr;
+      if (hipStreamBeginCapture(e->s, hipStreamCaptureModeThreadLocal) != hipSuccess) return -5;
+      enqueue_chunk(*e, k, 0, grid);
+      if (hipStreamEndCapture(e->s, &g) != hipSuccess) return -5;
+      const hipError_t r = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (r != hipSuccess) return -5;
+      e->graphs[grid] = exec;
+    }
+  }
+  for (int c = 0; c < chunks; ++c) {
+    if (exec) {
+      if (hipGraphLaunch(exec, e->s) != hipSuccess) return -5;
+    } else {
+      enqueue_chunk(*e, k, e->launched, grid);
     }
     e->launched += k;
   }
