@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", choices=["config2", "config3", "config4", "config5"],
                     default="config2")
+    ap.add_argument("--gmres-lanes", type=int, default=4,
+                    help="config5: host threads (each with its own stream) serving GMRES")
     ap.add_argument("--batch-count", type=int, default=512,
                     help="config4: systems per batch (default 512)")
     ap.add_argument("--no-solo", action="store_true",
@@ -223,6 +225,18 @@ def bench_batch(args, gsk, problems, dev):
     elapsed = time.perf_counter() - t_start
     its = [infos[k].iters for k in infos]
     status = collections_count(infos)
+    # Algorithmic bytes of the Bi-CGSTAB iterations of the last step (P, S and U launches, the
+    # per-row figures of the kernel-class table in gsk.h for a stencil matrix of 5 or 7
+    # planes): a full iteration moves 2 M + 136 n bytes with M = 8 n planes; the first P after
+    # a start or restart moves 16 n less, and a half-step exit skips 40 n of U.
+    iter_bytes = 0.0
+    for i, s in enumerate(systems):
+        info, n = infos[i], s["n"]
+        mat = 8.0 * n * (7 if s["dim"] == 3 else 5)
+        iter_bytes += info.iters * (2 * mat + 136.0 * n)
+        if info.iters > 0:
+            iter_bytes -= 16.0 * n * (1 + info.restarts) + (40.0 * n if info.half_step else 0.0)
+    row_iters = sum(infos[i].iters * s["n"] for i, s in enumerate(systems))
     out = {
         "metric": "systems solved/s, batch of GS(2) + Bi-CGSTAB, tol 1e-8",
         "value": round(len(systems) * args.steps / elapsed, 3),
@@ -236,7 +250,14 @@ def bench_batch(args, gsk, problems, dev):
                    "dims_3d": sum(1 for s in systems if s["dim"] == 3)},
         "latency_p50_ms": round(1e3 * pct(lats, 0.5), 3),
         "latency_p99_ms": round(1e3 * pct(lats, 0.99), 3),
-        "iterations": {"total": int(sum(its)), "max": int(max(its)), "median": pct(its, 0.5)},
+        "iterations": {"total": int(sum(its)), "max": int(max(its)), "median": pct(its, 0.5),
+                       "row_iterations": int(row_iters)},
+        "iteration_bandwidth": {
+            "GB": round(iter_bytes / 1e9, 3),
+            "GBs": round(iter_bytes / 1e9 / (elapsed / args.steps), 1),
+            "frac_of_8TBs": round(iter_bytes / 1e9 / (elapsed / args.steps) / 8000.0, 4),
+            "note": "algorithmic bytes of every Bi-CGSTAB iteration of a step / whole step "
+                    "time (GS, residual and finalize launches, host polls included)"},
         "status": status,
         "roofline": None, "cpu_baseline": None,
     }
@@ -285,7 +306,7 @@ def bench_serve(args, gsk, problems, dev):
     # engine room for about 48 of the pool's systems at once
     rows = int(sum((s["n"] + 255) // 256 * 256 for s in pool) * 0.75)
     srv = serve.Server(rows, 256, check_every=8, graph=True, gmres_rows=nmax, m_max=20,
-                       device=dev)
+                       device=dev, gmres_lanes=args.gmres_lanes)
     results = []
     for rate in rates:
         gaps = rng.exponential(1.0 / rate, size=args.serve_requests)
@@ -324,7 +345,8 @@ def bench_serve(args, gsk, problems, dev):
         "config": {"workload": f"config5: Poisson arrivals at {args.rates} req/s, "
                                f"{args.serve_requests} requests per rate from a pool of 64 "
                                f"config4-distribution systems, {args.gmres_share:.0%} GMRES(20), "
-                               f"the rest Bi-CGSTAB, tol 1e-8, GS(2) per request"},
+                               f"the rest Bi-CGSTAB, tol 1e-8, GS(2) per request; Bi-CGSTAB "
+                               f"in the engine, GMRES on {args.gmres_lanes} lanes"},
         "latency_p50_ms": best["latency_p50_ms"], "latency_p99_ms": best["latency_p99_ms"],
         "rates": results, "roofline": None, "cpu_baseline": None,
     }

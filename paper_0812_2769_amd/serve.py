@@ -4,8 +4,9 @@ Requests arrive over time (each an unscaled system, a method and a tolerance). T
 - admits Bi-CGSTAB requests into the batched engine (gsk_engine_*) as soon as its workspace
   has room (rows and a slot), GS(2) included, so requests that arrive while others are on the
   GPU join the running batch at the next chunk;
-- runs GMRES(m) requests one at a time on a lane of its own (a host thread and a stream of
-  its own), so their launches overlap the engine's on the device;
+- runs GMRES(m) requests on a few lanes (each a host thread with a stream and workspaces of
+  its own) that take requests from one queue, so GMRES solves overlap each other and the
+  engine's launches on the device;
 - keeps every request's Krylov state on the device until it is done, and records arrival,
   admission and completion times.
 
@@ -53,11 +54,14 @@ class Done:
 
 
 class GmresLane(threading.Thread):
-    """Solves GMRES requests one at a time on its own stream: GS(2), packing, GMRES(m)."""
+    """Solves GMRES requests from a shared queue one at a time on its own stream: GS(2),
+    packing, GMRES(m)."""
 
-    def __init__(self, device, t0: float, max_rows: int, m_max: int, on_done: Callable):
+    def __init__(self, q: queue.Queue, device, t0: float, max_rows: int, m_max: int,
+                 on_done: Callable):
         super().__init__(daemon=True)
-        self.q = queue.Queue()
+        self.q = q
+        self.error = None
         self.stream = torch.cuda.Stream(device)
         self.t0 = t0
         self.on_done = on_done
@@ -65,34 +69,39 @@ class GmresLane(threading.Thread):
         with torch.cuda.stream(self.stream):
             self.ws_gs = gsk.workspace(gsk.METHOD_GS, max_rows, 0, device)
             self.ws = gsk.workspace(gsk.METHOD_GMRES, max_rows, m_max, device)
-        self.busy = threading.Event()
 
     def run(self):
         while True:
             item = self.q.get()
             if item is None:
                 return
-            req, admitted = item
-            with torch.cuda.stream(self.stream):
-                A = req.csr
-                As, bs, _, _ = gsk.gs_scale(A, req.b, 2, want_norms=False, ws=self.ws_gs)
-                M = gsk.stencil_from_csr(As, *req.grid, ws=self.ws_gs) if req.grid else As
-                ws = self.ws[: gsk.workspace_bytes(gsk.METHOD_GMRES, A.n, req.m)]
-                x, info = gsk.gmres(M, bs, m=req.m, tol=req.tol, ws=ws)
-            self.stream.synchronize()
-            self.on_done(Done(req.tag, "gmres", req.arrival, admitted,
-                              time.perf_counter() - self.t0, info, x))
-            self.q.task_done()
+            try:
+                req, admitted = item
+                with torch.cuda.stream(self.stream):
+                    A = req.csr
+                    As, bs, _, _ = gsk.gs_scale(A, req.b, 2, want_norms=False, ws=self.ws_gs)
+                    M = gsk.stencil_from_csr(As, *req.grid, ws=self.ws_gs) if req.grid else As
+                    ws = self.ws[: gsk.workspace_bytes(gsk.METHOD_GMRES, A.n, req.m)]
+                    x, info = gsk.gmres(M, bs, m=req.m, tol=req.tol, ws=ws)
+                self.stream.synchronize()
+                self.on_done(Done(req.tag, "gmres", req.arrival, admitted,
+                                  time.perf_counter() - self.t0, info, x))
+            except BaseException as e:   # reported by the server loop
+                self.error = e
+            finally:
+                self.q.task_done()
 
 
 class Server:
     def __init__(self, max_rows: int, max_systems: int, check_every: int = 8,
-                 graph: bool = True, gmres_rows: int = 0, m_max: int = 20, device="cuda"):
+                 graph: bool = True, gmres_rows: int = 0, m_max: int = 20, device="cuda",
+                 gmres_lanes: int = 4):
         self.device = torch.device(device)
         self.engine = gsk.Engine(max_rows, max_systems, check_every=check_every, graph=graph,
                                  device=self.device)
         self.gmres_rows = gmres_rows
         self.m_max = m_max
+        self.gmres_lanes = max(1, int(gmres_lanes))
 
     def serve(self, requests: List[Request], realtime: bool = True) -> List[Done]:
         """Serve the requests (sorted by arrival). With realtime, a request is visible only
@@ -102,11 +111,16 @@ class Server:
         done: List[Done] = []
         lock = threading.Lock()
         t0 = time.perf_counter()
-        lane = None
+        lanes = []
+        gq = queue.Queue()
         if any(r.method == "gmres" for r in reqs):
-            lane = GmresLane(self.device, t0, max(self.gmres_rows, 1), self.m_max,
-                             lambda d: (lock.acquire(), done.append(d), lock.release()))
-            lane.start()
+            def finished(d):
+                with lock:
+                    done.append(d)
+            lanes = [GmresLane(gq, self.device, t0, max(self.gmres_rows, 1), self.m_max,
+                               finished) for _ in range(self.gmres_lanes)]
+            for lane in lanes:
+                lane.start()
         inflight = {}     # engine tag -> (request, admitted time, x)
         n_total = len(reqs)
         try:
@@ -118,7 +132,7 @@ class Server:
                 while waiting:
                     r = waiting[0]
                     if r.method == "gmres":
-                        lane.q.put((r, now))
+                        gq.put((r, now))
                         waiting.popleft()
                         continue
                     x = torch.zeros_like(r.b)
@@ -135,19 +149,23 @@ class Server:
                                              time.perf_counter() - t0, info, x))
                 else:
                     if not reqs and not waiting:
-                        if lane is not None:
-                            lane.q.join()
+                        if lanes:
+                            gq.join()   # every lane calls task_done, also after an error
                         with lock:
                             if len(done) >= n_total:
                                 break
                     if reqs and realtime:
                         time.sleep(max(0.0, min(1e-3, reqs[0].arrival - now)))
+                for lane in lanes:
+                    if lane.error is not None:
+                        raise RuntimeError("GMRES lane failed") from lane.error
                 with lock:
                     if len(done) >= n_total:
                         break
         finally:
-            if lane is not None:
-                lane.q.put(None)
+            for _ in lanes:
+                gq.put(None)
+            for lane in lanes:
                 lane.join(timeout=60)
         return done
 
