@@ -52,6 +52,10 @@ def _load():
         lib.orc_gmres_ir.argtypes = [ctypes.c_int, _ip, _ip, _dp, _dp, _dp, ctypes.c_int,
                                      ctypes.c_double, ctypes.c_int, ctypes.c_double, _dp, _ip,
                                      _dp]
+        lib.orc_bicgstab_ir.restype = ctypes.c_int
+        lib.orc_bicgstab_ir.argtypes = [ctypes.c_int, _ip, _ip, _dp, _dp, _dp, ctypes.c_double,
+                                        ctypes.c_int, ctypes.c_double, _dp, ctypes.c_double,
+                                        _ip, _dp]
         lib.orc_default_breakdown_eps.argtypes = []
         _lib = lib
     return _lib
@@ -219,3 +223,23 @@ def bicgstab(A, b, x0=None, tol: float = 1e-8, maxit: int = 10000,
     if history:
         return x, info, hist[: min(info.iters, maxit)]
     return x, info
+
+
+def bicgstab_ir(A, b, x0=None, tol: float = 1e-8, maxit: int = 10000,
+                eps_b: Optional[float] = None, weights=None, delta: float = 2.0 ** -14):
+    """Mixed-precision Bi-CGSTAB: FP64 residuals and x, Bi-CGSTAB runs with float storage
+    between them, each ending at a reduction by delta of the residual it started from.
+    Returns (x, Info)."""
+    rp, ci, val = _csr(A)
+    n = rp.shape[0] - 1
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
+    ii = np.zeros(6, dtype=np.int32)
+    dd = np.zeros(2)
+    eps = default_breakdown_eps() if eps_b is None else eps_b
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+    rc = _load().orc_bicgstab_ir(n, _i(rp), _i(ci), _d(val), _d(b), _d(x), float(tol),
+                                 int(maxit), eps, _d(w), float(delta), _i(ii), _d(dd))
+    if rc != OK:
+        raise OracleError(rc)
+    return x, _info(ii, dd)

@@ -618,5 +618,146 @@ done:
     return ORC_OK;
 }
 
+/* ---------------------------------------------------------------------------------------
+ * Mixed-precision Bi-CGSTAB: classical iterative refinement (not in the paper, which solves
+ * in FP64 throughout) whose corrections are Bi-CGSTAB runs with single-precision storage.
+ *   1. r = b - A x in double with the double matrix; rt = ||W r|| / ||W r0||; stop if
+ *      rt < tol.
+ *   2. Restart the Bi-CGSTAB recurrence from r: the stored residual r~ and the shadow
+ *      residual r^ are r rounded to float. The matrix values, r~, r^, p, v and t are stored
+ *      as float; every product, dot product and update is computed in double from the stored
+ *      floats, and a value is rounded to float when it is stored. s = r~ - alpha v is not
+ *      stored and stays double; x stays double.
+ *   3. The run ends (and goes back to 1) when its estimate ||W s|| / ||W r0|| (half step) or
+ *      ||W r~|| / ||W r0|| drops below max(tol, delta * rt): a reduction by delta of the
+ *      residual it started from is as far as float storage is trusted to go.
+ * Stagnation: a refinement step that does not halve rt counts as a failure; three failures
+ * in a row end the solve as STAGNATED. Breakdown tests as in Bi-CGSTAB (R6), on the stored
+ * vectors.
+ * ------------------------------------------------------------------------------------- */
+int orc_bicgstab_ir(int n, const int* rp, const int* ci, const double* val, const double* b,
+                    double* x, double tol, int maxit, double eps_b, const double* wts,
+                    double delta, int* info_i, double* info_d) {
+    if (n <= 0 || maxit < 0 || !(tol > 0.0) || !(delta > 0.0) || !(delta < 1.0))
+        return ORC_ERR_ARG;
+    size_t nn = (size_t)n;
+    int nnz = rp[n];
+    float* fval = (float*)malloc(sizeof(float) * (size_t)(nnz > 0 ? nnz : 1));
+    float* rs = (float*)malloc(sizeof(float) * nn);    /* stored residual r~ */
+    float* rh = (float*)malloc(sizeof(float) * nn);
+    float* p = (float*)malloc(sizeof(float) * nn);
+    float* v = (float*)malloc(sizeof(float) * nn);
+    float* t = (float*)malloc(sizeof(float) * nn);
+    double* r = (double*)malloc(sizeof(double) * nn);  /* true residual, double */
+    double* s = (double*)malloc(sizeof(double) * nn);
+    if (!fval || !rs || !rh || !p || !v || !t || !r || !s) {
+        free(fval); free(rs); free(rh); free(p); free(v); free(t); free(r); free(s);
+        return ORC_ERR_ALLOC;
+    }
+    for (int k = 0; k < nnz; ++k) fval[k] = (float)val[k];
+    int iters = 0, restarts = 0, status = ORC_MAXIT, fails = 0, half = 0, brk = 0;
+    double est = 1.0, relres_true = 1.0;
+
+    residual(n, rp, ci, val, b, x, r);
+    double ref = wnrm2(n, wts, r);
+    if (ref == 0.0) {
+        status = ORC_CONVERGED;
+        est = relres_true = 0.0;
+        goto done;
+    }
+    if (maxit == 0) goto done;
+    double rt = 1.0;
+    for (;;) {
+        /* step 2: restart from the true residual */
+        double target = delta * rt > tol ? delta * rt : tol;
+        for (int i = 0; i < n; ++i) rs[i] = (float)r[i];
+        memcpy(rh, rs, sizeof(float) * nn);
+        double rh_norm = sqrt(fdot(n, rh, rh));
+        double rho = fdot(n, rh, rs);
+        double rho_old = 1.0, alpha = 1.0, omega = 1.0;
+        int first = 1;
+        half = 0;
+        for (;;) {
+            if (fabs(rho) <= eps_b * rh_norm * sqrt(fdot(n, rs, rs))) {
+                status = ORC_BREAKDOWN; brk = 3; goto final_check;
+            }
+            if (first) {
+                memcpy(p, rs, sizeof(float) * nn);
+            } else {
+                double beta = (rho / rho_old) * (alpha / omega);
+                for (int i = 0; i < n; ++i)
+                    p[i] = (float)((double)rs[i] + beta * ((double)p[i] - omega * (double)v[i]));
+            }
+            first = 0;
+            for (int row = 0; row < n; ++row) {          /* v = A p, float matrix */
+                double acc = 0.0;
+                for (int q = rp[row]; q < rp[row + 1]; ++q)
+                    acc += (double)fval[q] * (double)p[ci[q]];
+                v[row] = (float)acc;
+            }
+            double sigma = fdot(n, rh, v);
+            if (fabs(sigma) <= eps_b * rh_norm * sqrt(fdot(n, v, v))) {
+                status = ORC_BREAKDOWN; brk = 1; goto final_check;
+            }
+            alpha = rho / sigma;
+            for (int i = 0; i < n; ++i) s[i] = (double)rs[i] - alpha * (double)v[i];
+            ++iters;
+            est = wnrm2(n, wts, s) / ref;
+            if (est < target) {                            /* half-step exit */
+                for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * (double)p[i];
+                half = 1;
+                break;
+            }
+            for (int row = 0; row < n; ++row) {          /* t = A s, float matrix */
+                double acc = 0.0;
+                for (int q = rp[row]; q < rp[row + 1]; ++q) acc += (double)fval[q] * s[ci[q]];
+                t[row] = (float)acc;
+            }
+            double ts = 0.0;
+            for (int i = 0; i < n; ++i) ts += (double)t[i] * s[i];
+            double tt = fdot(n, t, t);
+            if (fabs(ts) <= eps_b * sqrt(tt) * nrm2(n, s)) {
+                status = ORC_BREAKDOWN; brk = 2; goto final_check;
+            }
+            omega = ts / tt;
+            for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * (double)p[i] + omega * s[i];
+            for (int i = 0; i < n; ++i) rs[i] = (float)(s[i] - omega * (double)t[i]);
+            double ws = 0.0;
+            for (int i = 0; i < n; ++i) {
+                double e = wts ? wts[i] * (double)rs[i] : (double)rs[i];
+                ws += e * e;
+            }
+            est = sqrt(ws) / ref;
+            if (est < target || iters >= maxit) break;
+            rho_old = rho;
+            rho = fdot(n, rh, rs);
+        }
+        /* step 1 of the next refinement step */
+        residual(n, rp, ci, val, b, x, r);
+        relres_true = wnrm2(n, wts, r) / ref;
+        if (relres_true < tol) { status = ORC_CONVERGED; goto done; }
+        if (iters >= maxit) { status = ORC_MAXIT; goto done; }
+        if (!(relres_true < 0.5 * rt)) {
+            ++fails;
+            if (fails >= 3) { status = ORC_STAGNATED; goto done; }
+        } else {
+            fails = 0;
+        }
+        rt = relres_true;
+        ++restarts;
+    }
+final_check:
+    residual(n, rp, ci, val, b, x, r);
+    relres_true = wnrm2(n, wts, r) / ref;
+done:
+    if (info_i) {
+        info_i[0] = iters; info_i[1] = restarts; info_i[2] = status; info_i[3] = half;
+        info_i[4] = fails; info_i[5] = brk;
+    }
+    if (info_d) { info_d[0] = est; info_d[1] = relres_true; }
+    free(fval); free(rs); free(rh); free(p); free(v); free(t); free(r); free(s);
+    return ORC_OK;
+}
+
 /* Default breakdown tolerance: DBL_EPSILON relaxed by 1e-16 (section 2.2). */
 double orc_default_breakdown_eps(void) { return 1e-16 * DBL_EPSILON; }

@@ -1,0 +1,84 @@
+"""Pins of the oracle's mixed-precision Bi-CGSTAB (iterative refinement whose corrections are
+Bi-CGSTAB runs with float storage). The closed-form case must take the steps its algebra
+gives, the FP64 refinement must reach accuracy that float data cannot, and the measured cost
+of float storage on the batch workload's jump problems is recorded (it is why the GPU engine
+keeps Bi-CGSTAB in FP64)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_0812_2769_amd import problems
+
+F32_EPS = 2.0 ** -24
+
+
+def identity(n, seed):
+    rng = np.random.default_rng(seed)
+    rp = np.arange(n + 1, dtype=np.int32)
+    return problems.Problem("I", (n,), rp, np.arange(n, dtype=np.int32), np.ones(n),
+                            rng.standard_normal(n))
+
+
+def scaled(P, p=2):
+    vo, bo, nrm, w = oracle.gs_scale(P, P.b, p)
+    S = P.copy()
+    S.val, S.b = vo, bo
+    return S, w
+
+
+def test_identity_takes_two_half_steps():
+    # A = I: p = r~ = fl(b), v = p, alpha = 1, s = r~ - v = 0, so every run ends at its first
+    # half step with x += fl(r). Run 1 leaves a residual of at most 2^-24 per entry, run 2
+    # squares it: two iterations, one refinement, far below 1e-12.
+    P = identity(400, 2)
+    x, info = oracle.bicgstab_ir(P, P.b, tol=1e-12)
+    assert info.status == oracle.CONVERGED
+    assert (info.iters, info.restarts, info.half_step) == (2, 1, 1)
+    assert np.max(np.abs(x - P.b)) <= 4 * F32_EPS ** 2 * np.max(np.abs(P.b))
+
+
+def test_reaches_fp64_accuracy_beyond_float_precision():
+    S, _ = scaled(problems.laplacian((12, 10), conv=(40.0, 15.0)))
+    x, info = oracle.bicgstab_ir(S, S.b, tol=1e-13, delta=1e-6)
+    assert info.status == oracle.CONVERGED and info.relres_true < 1e-13
+    assert info.restarts >= 1            # float storage alone cannot get there
+    A = S.dense()
+    xs = np.linalg.solve(A, S.b)
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= 10 * np.linalg.cond(A) * 1e-13
+    assert np.linalg.norm(S.b - A @ x) / np.linalg.norm(S.b) < 1e-13
+
+
+def test_weights_measure_the_gs2_metric():
+    # GS(1) scaling with the weights ||a_i||_1/||a_i||_2 must stop on the same GS(2)-scaled
+    # residual as the FP64 solver does: the returned true residual is below tol in that metric.
+    P = problems.laplacian((14, 9), conv=(25.0, -10.0))
+    S1, w = scaled(P, 1)
+    x, info = oracle.bicgstab_ir(S1, S1.b, tol=1e-10, weights=w)
+    assert info.status == oracle.CONVERGED
+    r = S1.b - S1.dense() @ x
+    r0 = np.linalg.norm(w * S1.b)
+    assert np.linalg.norm(w * r) / r0 == pytest.approx(info.relres_true, rel=1e-9)
+    assert info.relres_true < 1e-10
+
+
+def test_arguments():
+    P = identity(10, 3)
+    for d in (0.0, 1.0, -1e-3):
+        with pytest.raises(oracle.OracleError):
+            oracle.bicgstab_ir(P, P.b, tol=1e-8, delta=d)
+
+
+def test_float_storage_costs_iterations_on_jump_problems():
+    # Measured, not a property of the method: on the batch recipe's jump problems (GS(2),
+    # tol 1e-8), float storage with refinement takes clearly more Bi-CGSTAB iterations than
+    # FP64 Bi-CGSTAB, more than the 1.9x fewer bytes per iteration could pay for.
+    specs = problems.config4_specs(6, seed=1004, n_min=20, n_max=32)
+    it64 = itir = 0
+    for sp in specs:
+        S, _ = scaled(problems.config4_system(sp))
+        _, i64 = oracle.bicgstab(S, S.b, tol=1e-8)
+        _, iir = oracle.bicgstab_ir(S, S.b, tol=1e-8, delta=1e-6)
+        assert i64.status == oracle.CONVERGED
+        it64 += i64.iters
+        itir += iir.iters
+    assert itir > 1.2 * it64, (itir, it64)
