@@ -77,6 +77,12 @@ def parse():
                     default="config2")
     ap.add_argument("--gmres-lanes", type=int, default=4,
                     help="config5: host threads (each with its own stream) serving GMRES")
+    ap.add_argument("--gmres-mode", choices=["lanes", "engine"], default="engine",
+                    help="config5: GMRES requests on lanes or in a GMRES engine")
+    ap.add_argument("--gmres-precision", choices=["fp64", "mixed"], default="fp64",
+                    help="config5 with --gmres-mode engine: the GMRES engine's precision")
+    ap.add_argument("--batch-method", choices=["bicgstab", "gmres"], default="bicgstab",
+                    help="config4: the engine's solver (GMRES(20) with --precision)")
     ap.add_argument("--batch-count", type=int, default=512,
                     help="config4: systems per batch (default 512)")
     ap.add_argument("--no-solo", action="store_true",
@@ -189,8 +195,14 @@ def bench_batch(args, gsk, problems, dev):
     import torch
     specs = problems.config4_specs(args.batch_count)
     systems = build_batch_systems(gsk, problems, dev, specs)
-    rows = sum((s["n"] + 255) // 256 * 256 for s in systems)
-    eng = gsk.Engine(rows, len(systems), check_every=8, graph=True, device=dev)
+    gmres = args.batch_method == "gmres"
+    mixed = gmres and args.precision == "mixed"
+    unit = 512 if mixed else 256
+    rows = sum((s["n"] + unit - 1) // unit * unit for s in systems)
+    eng = gsk.Engine(rows, len(systems), check_every=8, graph=True, device=dev,
+                     method=args.batch_method, m=20, precision="mixed" if mixed else "fp64")
+    solver = (f"GMRES(20) {'mixed precision' if mixed else 'FP64'}" if gmres
+              else "Bi-CGSTAB")
     xbuf = torch.zeros(sum(s["n"] for s in systems), dtype=torch.float64, device=dev)
     offs = [0]
     for s in systems:
@@ -232,20 +244,33 @@ def bench_batch(args, gsk, problems, dev):
     iter_bytes = 0.0
     for i, s in enumerate(systems):
         info, n = infos[i], s["n"]
-        mat = 8.0 * n * (7 if s["dim"] == 3 else 5)
-        iter_bytes += info.iters * (2 * mat + 136.0 * n)
-        if info.iters > 0:
-            iter_bytes -= 16.0 * n * (1 + info.restarts) + (40.0 * n if info.half_step else 0.0)
+        planes = 7 if s["dim"] == 3 else 5
+        if gmres:
+            # Arnoldi step j: A reads the inner matrix and columns 0..j (column j twice) and
+            # writes w; B and C read columns 0..j and w and write w or u_{j+1}
+            vb = 4.0 if mixed else 8.0
+            mat = vb * planes * n
+            steps, m = info.iters, 20
+            full, last = divmod(steps, m)
+            js = [j for j in range(m)] * full + list(range(last))
+            iter_bytes += sum(mat + vb * n * (j + 2) + 2 * vb * n * (j + 3) for j in js)
+        else:
+            mat = 8.0 * n * planes
+            iter_bytes += info.iters * (2 * mat + 136.0 * n)
+            if info.iters > 0:
+                iter_bytes -= (16.0 * n * (1 + info.restarts)
+                               + (40.0 * n if info.half_step else 0.0))
     row_iters = sum(infos[i].iters * s["n"] for i, s in enumerate(systems))
     out = {
-        "metric": "systems solved/s, batch of GS(2) + Bi-CGSTAB, tol 1e-8",
+        "metric": f"systems solved/s, batch of GS(2) + {solver}, tol 1e-8",
         "value": round(len(systems) * args.steps / elapsed, 3),
         "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"config4: {len(systems)} systems, d in {{2,3}}, N in [32,96], "
-                               f"box jump 10^U(2,6), convection U(0,30); GS(2) + Bi-CGSTAB in "
-                               f"the engine (HIP-graph chunks of 8 iterations), tol 1e-8",
+                               f"box jump 10^U(2,6), convection U(0,30); GS(2) + {solver} in "
+                               f"the engine (HIP-graph chunks of "
+                               f"{'one cycle' if gmres else '8 iterations'}), tol 1e-8",
                    "rows": sum(s["n"] for s in systems), "systems": len(systems),
                    "dims_3d": sum(1 for s in systems if s["dim"] == 3)},
         "latency_p50_ms": round(1e3 * pct(lats, 0.5), 3),
@@ -256,25 +281,31 @@ def bench_batch(args, gsk, problems, dev):
             "GB": round(iter_bytes / 1e9, 3),
             "GBs": round(iter_bytes / 1e9 / (elapsed / args.steps), 1),
             "frac_of_8TBs": round(iter_bytes / 1e9 / (elapsed / args.steps) / 8000.0, 4),
-            "note": "algorithmic bytes of every Bi-CGSTAB iteration of a step / whole step "
-                    "time (GS, residual and finalize launches, host polls included)"},
+            "note": "algorithmic bytes of every Krylov iteration (Arnoldi step) of a step / "
+                    "whole step time (GS, residual and finalize launches, host polls "
+                    "included)"},
         "status": status,
         "roofline": None, "cpu_baseline": None,
     }
     if not args.no_solo:
-        # the same solves one at a time: gsk_gs_scale + packing + gsk_bicgstab per system
+        # the same solves one at a time: gsk_gs_scale + packing + the single solver per system
         log("timing the one-at-a-time path")
         ws_gs = gsk.workspace(gsk.METHOD_GS, 1, 0, dev)
         nmax = max(s["n"] for s in systems)
-        ws_bi = gsk.workspace(gsk.METHOD_BICGSTAB, nmax, 0, dev)
+        meth = (gsk.METHOD_GMRES_MIXED if mixed else gsk.METHOD_GMRES) if gmres \
+            else gsk.METHOD_BICGSTAB
+        ws_so = gsk.workspace(meth, nmax, 20 if gmres else 0, dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         same = True
         for i, s in enumerate(systems):
             As, bs, _, _ = gsk.gs_scale(s["A"], s["b"], 2, want_norms=False, ws=ws_gs)
             M = gsk.stencil_from_csr(As, *s["grid"], ws=ws_gs)
-            x, info = gsk.bicgstab(M, bs, tol=tol,
-                                   ws=ws_bi[: gsk.workspace_bytes(gsk.METHOD_BICGSTAB, s["n"])])
+            ws = ws_so[: gsk.workspace_bytes_for(M, meth, 20 if gmres else 0)]
+            if gmres:
+                x, info = (gsk.gmres_mixed if mixed else gsk.gmres)(M, bs, m=20, tol=tol, ws=ws)
+            else:
+                x, info = gsk.bicgstab(M, bs, tol=tol, ws=ws)
             same = same and info == infos[i] and bool(torch.equal(x, xs[i]))
         torch.cuda.synchronize()
         t_solo = time.perf_counter() - t0
@@ -306,7 +337,9 @@ def bench_serve(args, gsk, problems, dev):
     # engine room for about 48 of the pool's systems at once
     rows = int(sum((s["n"] + 255) // 256 * 256 for s in pool) * 0.75)
     srv = serve.Server(rows, 256, check_every=8, graph=True, gmres_rows=nmax, m_max=20,
-                       device=dev, gmres_lanes=args.gmres_lanes)
+                       device=dev, gmres_lanes=args.gmres_lanes, gmres_mode=args.gmres_mode,
+                       gmres_precision=args.gmres_precision, gmres_engine_rows=rows,
+                       gmres_engine_systems=128)
     results = []
     for rate in rates:
         gaps = rng.exponential(1.0 / rate, size=args.serve_requests)
@@ -346,7 +379,10 @@ def bench_serve(args, gsk, problems, dev):
                                f"{args.serve_requests} requests per rate from a pool of 64 "
                                f"config4-distribution systems, {args.gmres_share:.0%} GMRES(20), "
                                f"the rest Bi-CGSTAB, tol 1e-8, GS(2) per request; Bi-CGSTAB "
-                               f"in the engine, GMRES on {args.gmres_lanes} lanes"},
+                               f"in the engine, GMRES "
+                               + (f"in a GMRES(20) engine ({args.gmres_precision})"
+                                  if args.gmres_mode == "engine"
+                                  else f"on {args.gmres_lanes} lanes")},
         "latency_p50_ms": best["latency_p50_ms"], "latency_p99_ms": best["latency_p99_ms"],
         "rates": results, "roofline": None, "cpu_baseline": None,
     }

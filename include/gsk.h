@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define GSK_VERSION 2
+#define GSK_VERSION 3
 
 /* Return codes */
 #define GSK_OK 0
@@ -365,6 +365,68 @@ int gsk_engine_submit(gsk_engine* e, const gsk_matrix* A, const double* b, doubl
 int gsk_engine_submit_gs(gsk_engine* e, const gsk_matrix* A, const double* b, int32_t p,
                          double* val_out, double* b_out, double* stop_weight_out, double* x,
                          double tol, const gsk_options* opt, int64_t tag);
+
+/*
+ * GMRES(m) engines. The same engine runs restarted GMRES(m) with CGS2 Arnoldi (section 2) for
+ * many systems at once, in FP64 or with FP32 Arnoldi cycles and FP64 restarts (the iterative
+ * refinement of gsk_gmres_mixed). Each system returns bit for bit what gsk_gmres (or
+ * gsk_gmres_mixed) returns for it alone. A chunk is one restart cycle: systems start their
+ * cycles together at a chunk's start, run up to m Arnoldi steps, and at the chunk's end get
+ * x += V y and the true residual (convergence test and the next cycle's start). A system
+ * submitted between chunks starts at the next chunk.
+ * Rows: a system of n rows takes ceil(n / 256) tiles of 256 rows, rounded up to an even
+ * number in a mixed engine (two tiles per workgroup for FP32 data).
+ * Workspace: gsk_engine_workspace_bytes_ex; it holds the basis (m+1 columns of max_rows values,
+ * 8 or 4 bytes each) and one control block (about 70 KB) per system slot.
+ */
+#define GSK_PRECISION_FP64 0
+#define GSK_PRECISION_MIXED 1
+
+typedef struct gsk_engine_config {
+    int64_t max_rows;      /* rows of vectors the engine holds                              */
+    int32_t max_systems;   /* system slots                                                  */
+    int32_t method;        /* GSK_METHOD_BICGSTAB or GSK_METHOD_GMRES                       */
+    int32_t m;             /* GMRES restart length, 1..GSK_MAX_RESTART (ignored otherwise)  */
+    int32_t precision;     /* GMRES: GSK_PRECISION_FP64 or GSK_PRECISION_MIXED; Bi-CGSTAB:
+                              GSK_PRECISION_FP64 (float storage does not pay for Bi-CGSTAB
+                              on these problems; see the design notes)                      */
+    int32_t check_every;   /* Bi-CGSTAB: iterations per chunk (1..256, even with
+                              GSK_ENGINE_GRAPH); GMRES: ignored (a chunk is one cycle)      */
+    int32_t flags;         /* GSK_ENGINE_GRAPH                                              */
+} gsk_engine_config;
+
+/* 0 for an invalid configuration. */
+size_t gsk_engine_workspace_bytes_ex(const gsk_engine_config* cfg);
+
+/* As gsk_engine_create, for any configuration. GSK_ENGINE_GRAPH needs a non-default stream;
+ * GMRES chunks are captured once per streaming grid size like Bi-CGSTAB chunks. */
+int gsk_engine_create_ex(const gsk_engine_config* cfg, void* ws, size_t ws_bytes, void* stream,
+                         gsk_engine** out);
+
+/* One system for gsk_engine_submit_ex.
+ * gs_p = 0: A and b are already scaled (as for gsk_engine_submit); gs_p >= 1: the GS(p) stage
+ * of gsk_engine_submit_gs with its outputs val_out, b_out, stop_weight_out.
+ * mat32 (mixed GMRES engines: required; otherwise NULL): device buffer for the FP32 copy of
+ * the scaled matrix, which the engine writes in the system's first chunk: for a stencil matrix
+ * planes of mat32_ld >= n floats (a multiple of 64 keeps every plane 256-byte aligned), for
+ * CSR nnz floats. It must stay allocated until the system is reported done. */
+typedef struct gsk_engine_request {
+    const gsk_matrix* A;
+    const double* b;
+    double* x;              /* x0 on entry, the solution when reported done                 */
+    double tol;
+    const gsk_options* opt; /* nullable; opt->stop_weights must be NULL when gs_p >= 1       */
+    int64_t tag;
+    int32_t gs_p;
+    double* val_out;
+    double* b_out;
+    double* stop_weight_out;
+    float* mat32;
+    int64_t mat32_ld;
+} gsk_engine_request;
+
+/* Returns GSK_OK, GSK_FULL, or GSK_ERR_INVALID_ARG (also for a mixed engine without mat32). */
+int gsk_engine_submit_ex(gsk_engine* e, const gsk_engine_request* r);
 
 /* Enqueues `chunks` chunks (asynchronous). */
 int gsk_engine_run(gsk_engine* e, int32_t chunks);

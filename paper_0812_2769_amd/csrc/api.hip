@@ -362,76 +362,134 @@ struct gsk_engine {
   gsk::Engine* impl;
   int64_t max_rows;
   int32_t max_systems;
+  int32_t method;
+  int32_t precision;
 };
 
+static int engine_cfg(const gsk_engine_config* c, gsk::EngineConfig& cfg) {
+  if (!c) return set_err(GSK_ERR_INVALID_ARG, "config is NULL");
+  if (c->max_rows < 1 || c->max_rows > ((int64_t)1 << 40) || c->max_systems < 1 ||
+      c->max_systems > (1 << 20))
+    return set_err(GSK_ERR_INVALID_ARG, "max_rows and max_systems must be positive");
+  if (c->method != GSK_METHOD_BICGSTAB && c->method != GSK_METHOD_GMRES)
+    return set_err(GSK_ERR_INVALID_ARG, "method must be GSK_METHOD_BICGSTAB or GSK_METHOD_GMRES");
+  if (c->precision != GSK_PRECISION_FP64 && c->precision != GSK_PRECISION_MIXED)
+    return set_err(GSK_ERR_INVALID_ARG, "unknown precision");
+  const bool gmres = c->method == GSK_METHOD_GMRES;
+  if (!gmres && c->precision != GSK_PRECISION_FP64)
+    return set_err(GSK_ERR_INVALID_ARG, "Bi-CGSTAB engines run in FP64");
+  if (gmres && (c->m < 1 || c->m > GSK_MAX_RESTART))
+    return set_err(GSK_ERR_INVALID_ARG, "m must be in [1, %d]", GSK_MAX_RESTART);
+  if (!gmres && (c->check_every < 1 || c->check_every > 256))
+    return set_err(GSK_ERR_INVALID_ARG, "check_every must be in [1, 256]");
+  cfg.max_rows = c->max_rows;
+  cfg.max_sys = c->max_systems;
+  cfg.method = gmres ? 1 : 0;
+  cfg.m = gmres ? c->m : 0;
+  cfg.mixed = gmres && c->precision == GSK_PRECISION_MIXED;
+  cfg.check_every = gmres ? 0 : c->check_every;
+  cfg.use_graph = (c->flags & GSK_ENGINE_GRAPH) != 0;
+  return GSK_OK;
+}
+
+size_t gsk_engine_workspace_bytes_ex(const gsk_engine_config* c) {
+  gsk::EngineConfig cfg;
+  const std::string saved = g_err;
+  const int rc = engine_cfg(c, cfg);
+  g_err = saved;
+  return rc ? 0 : gsk::engine_workspace_bytes(cfg);
+}
+
 size_t gsk_engine_workspace_bytes(int64_t max_rows, int32_t max_systems) {
-  return gsk::engine_workspace_bytes(max_rows, max_systems);
+  const gsk_engine_config c{max_rows, max_systems, GSK_METHOD_BICGSTAB, 0, GSK_PRECISION_FP64,
+                            8, 0};
+  return gsk_engine_workspace_bytes_ex(&c);
+}
+
+int gsk_engine_create_ex(const gsk_engine_config* c, void* ws, size_t ws_bytes, void* stream,
+                         gsk_engine** out) {
+  g_err.clear();
+  if (!out) return set_err(GSK_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  gsk::EngineConfig cfg;
+  int rc = engine_cfg(c, cfg);
+  if (rc) return rc;
+  if (cfg.use_graph && (!stream || (cfg.method == 0 && (cfg.check_every & 1))))
+    return set_err(GSK_ERR_INVALID_ARG,
+                   "GSK_ENGINE_GRAPH needs a non-default stream (and, for Bi-CGSTAB, an even "
+                   "check_every)");
+  rc = check_ws(ws, ws_bytes, gsk::engine_workspace_bytes(cfg));
+  if (rc) return rc;
+  gsk::Engine* impl = nullptr;
+  rc = gsk::engine_create(ws, ws_bytes, cfg, static_cast<hipStream_t>(stream), &impl);
+  if (rc == -4) return set_err(GSK_ERR_WORKSPACE, "engine workspace too small");
+  if (rc == -1) return set_err(GSK_ERR_INVALID_ARG, "invalid engine configuration");
+  if (rc) return set_err(GSK_ERR_DEVICE, "engine: pinned host buffers or events unavailable");
+  *out = new gsk_engine{impl, c->max_rows, c->max_systems, c->method, c->precision};
+  return GSK_OK;
 }
 
 int gsk_engine_create(void* ws, size_t ws_bytes, int64_t max_rows, int32_t max_systems,
                       int32_t check_every, int32_t flags, void* stream, gsk_engine** out) {
+  const gsk_engine_config c{max_rows, max_systems, GSK_METHOD_BICGSTAB, 0, GSK_PRECISION_FP64,
+                            check_every, flags};
+  return gsk_engine_create_ex(&c, ws, ws_bytes, stream, out);
+}
+
+int gsk_engine_submit_ex(gsk_engine* e, const gsk_engine_request* r) {
   g_err.clear();
-  if (!out) return set_err(GSK_ERR_INVALID_ARG, "out is NULL");
-  *out = nullptr;
-  if (max_rows < 1 || max_rows > ((int64_t)1 << 40) || max_systems < 1 ||
-      max_systems > (1 << 20))
-    return set_err(GSK_ERR_INVALID_ARG, "max_rows and max_systems must be positive");
-  if (check_every < 1 || check_every > 256)
-    return set_err(GSK_ERR_INVALID_ARG, "check_every must be in [1, 256]");
-  const bool graph = (flags & GSK_ENGINE_GRAPH) != 0;
-  if (graph && (!stream || (check_every & 1)))
-    return set_err(GSK_ERR_INVALID_ARG,
-                   "GSK_ENGINE_GRAPH needs a non-default stream and an even check_every");
-  int rc = check_ws(ws, ws_bytes, gsk::engine_workspace_bytes(max_rows, max_systems));
+  if (!e) return set_err(GSK_ERR_INVALID_ARG, "engine is NULL");
+  if (!r) return set_err(GSK_ERR_INVALID_ARG, "request is NULL");
+  Mat M;
+  int rc = check_matrix(r->A, M);
   if (rc) return rc;
-  gsk::Engine* impl = nullptr;
-  rc = gsk::engine_create(ws, ws_bytes, max_rows, max_systems, check_every, graph,
-                          static_cast<hipStream_t>(stream), &impl);
-  if (rc == -4) return set_err(GSK_ERR_WORKSPACE, "engine workspace too small");
-  if (rc) return set_err(GSK_ERR_DEVICE, "engine: pinned host buffers or events unavailable");
-  *out = new gsk_engine{impl, max_rows, max_systems};
+  if (!r->b || !r->x) return set_err(GSK_ERR_INVALID_ARG, "b or x is NULL");
+  const int p = r->gs_p;
+  if (p < 0) return set_err(GSK_ERR_INVALID_ARG, "gs_p must be >= 0");
+  if (p > 0) {
+    if (!r->val_out || !r->b_out) return set_err(GSK_ERR_INVALID_ARG, "GS outputs are NULL");
+    if (p != 2 && !r->stop_weight_out)
+      return set_err(GSK_ERR_INVALID_ARG, "p != 2 needs stop_weight_out");
+    if (r->opt && r->opt->stop_weights)
+      return set_err(GSK_ERR_INVALID_ARG, "opt->stop_weights must be NULL with a GS stage");
+  }
+  const bool mixed = e->method == GSK_METHOD_GMRES && e->precision == GSK_PRECISION_MIXED;
+  if (mixed) {
+    if (!r->mat32) return set_err(GSK_ERR_INVALID_ARG, "a mixed engine needs mat32");
+    if (M.kind == gsk::MAT_STENCIL && r->mat32_ld < M.n)
+      return set_err(GSK_ERR_INVALID_ARG, "mat32_ld must be >= n");
+  } else if (r->mat32) {
+    return set_err(GSK_ERR_INVALID_ARG, "mat32 is only for mixed GMRES engines");
+  }
+  SolveParams prm;
+  rc = params_from(r->opt, prm, r->tol);
+  if (rc) return rc;
+  gsk::GsStage gs{p, r->val_out, r->b_out, p != 2 ? r->stop_weight_out : nullptr, r->mat32,
+                  (size_t)(r->mat32_ld > 0 ? r->mat32_ld : 0)};
+  rc = gsk::engine_submit(e->impl, M, r->b, r->x, prm, r->tag,
+                          (p > 0 || mixed) ? &gs : nullptr);
+  if (rc == 1) return GSK_FULL;
+  if (rc == -1) return set_err(GSK_ERR_INVALID_ARG, "invalid request");
+  if (rc) return set_err(GSK_ERR_DEVICE, "engine submit: HIP failure");
   return GSK_OK;
 }
 
 int gsk_engine_submit(gsk_engine* e, const gsk_matrix* A, const double* b, double* x,
                       double tol, const gsk_options* opt, int64_t tag) {
-  g_err.clear();
-  if (!e) return set_err(GSK_ERR_INVALID_ARG, "engine is NULL");
-  Mat M;
-  int rc = check_matrix(A, M);
-  if (rc) return rc;
-  if (!b || !x) return set_err(GSK_ERR_INVALID_ARG, "b or x is NULL");
-  SolveParams prm;
-  rc = params_from(opt, prm, tol);
-  if (rc) return rc;
-  rc = gsk::engine_submit(e->impl, M, b, x, prm, tag);
-  if (rc == 1) return GSK_FULL;
-  if (rc) return set_err(GSK_ERR_DEVICE, "engine submit: HIP failure");
-  return GSK_OK;
+  const gsk_engine_request r{A, b, x, tol, opt, tag, 0, nullptr, nullptr, nullptr, nullptr, 0};
+  return gsk_engine_submit_ex(e, &r);
 }
 
 int gsk_engine_submit_gs(gsk_engine* e, const gsk_matrix* A, const double* b, int32_t p,
                          double* val_out, double* b_out, double* stop_weight_out, double* x,
                          double tol, const gsk_options* opt, int64_t tag) {
-  g_err.clear();
-  if (!e) return set_err(GSK_ERR_INVALID_ARG, "engine is NULL");
-  Mat M;
-  int rc = check_matrix(A, M);
-  if (rc) return rc;
-  if (!b || !x || !val_out || !b_out) return set_err(GSK_ERR_INVALID_ARG, "NULL pointer");
-  if (p < 1) return set_err(GSK_ERR_INVALID_ARG, "p must be >= 1");
-  if (p != 2 && !stop_weight_out)
-    return set_err(GSK_ERR_INVALID_ARG, "p != 2 needs stop_weight_out");
-  if (opt && opt->stop_weights)
-    return set_err(GSK_ERR_INVALID_ARG, "opt->stop_weights must be NULL with a GS stage");
-  SolveParams prm;
-  rc = params_from(opt, prm, tol);
-  if (rc) return rc;
-  gsk::GsStage gs{p, val_out, b_out, p != 2 ? stop_weight_out : nullptr};
-  rc = gsk::engine_submit(e->impl, M, b, x, prm, tag, &gs);
-  if (rc == 1) return GSK_FULL;
-  if (rc) return set_err(GSK_ERR_DEVICE, "engine submit: HIP failure");
-  return GSK_OK;
+  if (p < 1) {
+    g_err.clear();
+    return set_err(GSK_ERR_INVALID_ARG, "p must be >= 1");
+  }
+  const gsk_engine_request r{A, b, x, tol, opt, tag, p, val_out, b_out, stop_weight_out,
+                             nullptr, 0};
+  return gsk_engine_submit_ex(e, &r);
 }
 
 int gsk_engine_run(gsk_engine* e, int32_t chunks) {
@@ -498,7 +556,7 @@ size_t gsk_bicgstab_batch_workspace_bytes(int32_t count, const int32_t* n) {
   if (count < 1 || !n) return 0;
   const int64_t rows = batch_rows(count, n);
   if (rows < 1) return 0;
-  return gsk::engine_workspace_bytes(rows, count);
+  return gsk_engine_workspace_bytes(rows, count);
 }
 
 int gsk_bicgstab_batch(int32_t count, const gsk_matrix* A, const double* const* b,
@@ -519,11 +577,11 @@ int gsk_bicgstab_batch(int32_t count, const gsk_matrix* A, const double* const* 
   int rc = params_from(opt, prm, tol);
   if (rc) return rc;
   const int64_t rows = batch_rows(count, n.data());
-  rc = check_ws(ws, ws_bytes, gsk::engine_workspace_bytes(rows, count));
+  const gsk::EngineConfig cfg{rows, count, 0, 0, false, prm.check_every, false};
+  rc = check_ws(ws, ws_bytes, gsk::engine_workspace_bytes(cfg));
   if (rc) return rc;
   gsk::Engine* e = nullptr;
-  if (gsk::engine_create(ws, ws_bytes, rows, count, prm.check_every, false,
-                         static_cast<hipStream_t>(stream), &e))
+  if (gsk::engine_create(ws, ws_bytes, cfg, static_cast<hipStream_t>(stream), &e))
     return set_err(GSK_ERR_DEVICE, "batch: engine creation failed");
   for (int32_t i = 0; i < count; ++i) {
     Mat M;

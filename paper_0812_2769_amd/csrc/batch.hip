@@ -28,7 +28,7 @@
 #include <map>
 #include <vector>
 
-#include "gsk_host.hpp"
+#include "batch.hpp"
 
 namespace gsk {
 
@@ -39,23 +39,6 @@ struct BCtl {
   double tol, eps_b, ref;
   double rho, rho_old, alpha, omega, beta, rh_norm;
 };
-
-struct SysDesc {
-  int n, kind, nx, ny, nz, tile_off, ntiles, gs_p;
-  int64_t row_off;
-  const int* rp;
-  const int* ci;
-  const double* val;      // CSR values the solve reads (the GS output with a GS stage)
-  const double* coef;     // stencil planes the solve reads (likewise)
-  const double* b;        // right-hand side the solve reads (likewise)
-  double* x;
-  const double* W;        // stop weights (written by the GS stage for p != 2)
-  const double* gs_val;   // GS stage input: unscaled values or planes
-  const double* gs_b;     // GS stage input: unscaled b
-};
-
-// BCtl::bad bits: invalid CSR structure, zero row, non-finite data (GS stage).
-enum : int { BAD_CSR = 1, BAD_ZERO = 2, BAD_NONFINITE = 4 };
 
 struct BArgsB {
   const SysDesc* sys;
@@ -146,10 +129,10 @@ __global__ __launch_bounds__(64) void k_batch_init(BCtl* c, int maxit, double to
 }
 
 // Flat validity scan of one system's CSR structure (no indirect loads): row_ptr[0] == 0,
-// non-decreasing, row_ptr[n] == nnz, every column index in [0, n). Marks the control block.
+// non-decreasing, row_ptr[n] == nnz, every column index in [0, n). Sets BAD_CSR in *bad_bits.
 __global__ __launch_bounds__(BS) void k_batch_validate(const int* __restrict__ rp,
                                                        const int* __restrict__ ci, int n,
-                                                       int64_t nnz, BCtl* c) {
+                                                       int64_t nnz, int* bad_bits) {
   const int64_t stride = (int64_t)gridDim.x * BS;
   const int64_t gid = (int64_t)blockIdx.x * BS + threadIdx.x;
   bool bad = false;
@@ -163,7 +146,7 @@ __global__ __launch_bounds__(BS) void k_batch_validate(const int* __restrict__ r
     const int col = ci[k];
     if (col < 0 || col >= n) bad = true;
   }
-  if (bad) atomicOr(&c->bad, BAD_CSR);
+  if (bad) atomicOr(bad_bits, BAD_CSR);
 }
 
 // G: GS(p) of the systems whose stage is pending (same arithmetic as k_gs_scale).
@@ -173,21 +156,7 @@ __global__ __launch_bounds__(BS) void k_batch_gs(BArgsB a) {
     const SysDesc d = a.sys[s];
     BCtl* c = a.ctl + s;
     if (c->sum.state != ST_SCALE || (c->bad & BAD_CSR)) return;
-    const int row0 = (tile - d.tile_off) * BS;
-    const int nrows = min(BS, d.n - row0);
-    bool zero = false, nonfinite = false;
-    if (d.kind == MAT_STENCIL) {
-      if ((int)threadIdx.x < nrows)
-        gs_stencil_row(d.gs_val, (size_t)d.n, d.n, d.nx, d.ny, d.nz, d.gs_b, d.gs_p,
-                       row0 + threadIdx.x, const_cast<double*>(d.coef), const_cast<double*>(d.b),
-                       const_cast<double*>(d.W), zero, nonfinite);
-    } else {
-      gs_csr_tile(d.rp, d.gs_val, d.gs_b, d.gs_p, row0, nrows, const_cast<double*>(d.val),
-                  const_cast<double*>(d.b), nullptr, const_cast<double*>(d.W), L, zero,
-                  nonfinite);
-    }
-    if (zero) atomicOr(&c->bad, BAD_ZERO);
-    if (nonfinite) atomicOr(&c->bad, BAD_NONFINITE);
+    prepare_tile(d, tile - d.tile_off, L, &c->bad);
   });
 }
 
@@ -241,7 +210,7 @@ __global__ __launch_bounds__(BS) void k_batch_fin_residual(BArgsB a) {
   if (c->bad) {
     if (threadIdx.x == 0) {
       c->sum.state = ST_DONE;
-      c->sum.status = (c->bad & BAD_CSR) ? -1 : (c->bad & BAD_ZERO) ? -2 : -3;
+      c->sum.status = bad_status(c->bad);
     }
     return;
   }
@@ -485,31 +454,52 @@ __global__ __launch_bounds__(BS) void k_batch_fin_u(BArgsB a) {
 constexpr int kBatchVectors = 7;
 
 struct EngineLayout {
-  size_t sys, tiles, ctl, partials, vecs, total;
+  size_t sys, tiles, ctl, sums, partials, vecs, total;
 };
 
-static EngineLayout engine_layout(int64_t max_rows, int max_sys) {
-  const int64_t max_tiles = (max_rows + BS - 1) / BS;
+static int units_of(const EngineConfig& cfg) { return cfg.method == 1 && cfg.mixed ? 2 : 1; }
+
+// Workspace carve-up. Bi-CGSTAB: system table, unit list, control blocks, partials (4 per
+// tile), the 7 vectors. GMRES: system table, unit list, control blocks, status copies,
+// partials (max(m+1, 3) per tile), basis (m+1 columns) and w, in FP64 or FP32.
+static EngineLayout engine_layout(const EngineConfig& cfg) {
+  const int64_t max_tiles = (cfg.max_rows + BS - 1) / BS;
   const int64_t grid_tiles = (max_tiles + 7) / 8 * 8;
+  const size_t ns = (size_t)cfg.max_sys;
   EngineLayout L;
   size_t off = 0;
   L.sys = off;
-  off += align256(sizeof(SysDesc) * (size_t)max_sys);
+  off += align256(sizeof(SysDesc) * ns);
   L.tiles = off;
   off += align256(sizeof(int) * (2 * (size_t)grid_tiles + 1));
   L.ctl = off;
-  off += align256(sizeof(BCtl) * (size_t)max_sys);
-  L.partials = off;
-  off += align256(sizeof(double) * 4 * (size_t)grid_tiles);
-  L.vecs = off;
-  off += (size_t)kBatchVectors * align256(sizeof(double) * (size_t)grid_tiles * BS);
+  if (cfg.method == 1) {
+    off += align256(sizeof(Ctl) * ns);
+    L.sums = off;
+    off += align256(sizeof(Summary) * ns);
+    L.partials = off;
+    const int cols = cfg.m + 1 > 3 ? cfg.m + 1 : 3;
+    off += align256(sizeof(double) * (size_t)cols * (size_t)grid_tiles);
+    L.vecs = off;
+    const size_t tb = cfg.mixed ? sizeof(float) : sizeof(double);
+    off += align256(tb * (size_t)grid_tiles * BS * (size_t)(cfg.m + 1));
+    off += align256(tb * (size_t)grid_tiles * BS);
+  } else {
+    off += align256(sizeof(BCtl) * ns);
+    L.sums = off;
+    L.partials = off;
+    off += align256(sizeof(double) * 4 * (size_t)grid_tiles);
+    L.vecs = off;
+    off += (size_t)kBatchVectors * align256(sizeof(double) * (size_t)grid_tiles * BS);
+  }
   L.total = off;
   return L;
 }
 
-size_t engine_workspace_bytes(int64_t max_rows, int max_sys) {
-  if (max_rows < 1 || max_sys < 1) return 0;
-  return engine_layout(max_rows, max_sys).total;
+size_t engine_workspace_bytes(const EngineConfig& cfg) {
+  if (cfg.max_rows < 1 || cfg.max_sys < 1) return 0;
+  if (cfg.method == 1 && (cfg.m < 1 || cfg.m > MMAX)) return 0;
+  return engine_layout(cfg).total;
 }
 
 struct Engine {
@@ -517,7 +507,14 @@ struct Engine {
   int64_t max_rows = 0;
   int max_sys = 0, max_tiles = 0, grid_tiles = 0, check_every = 8;
   bool use_graph = false;
+  int method = 0;                  // 0 Bi-CGSTAB, 1 GMRES(m)
+  int m = 0;
+  bool mixed = false;
+  int rv = 1;                      // tiles per unit
+  int max_units = 0;
+  bool column = true;              // GMRES basis fits one buffer descriptor
   BArgsB args{};
+  GArgs gargs{};
   // host state
   std::vector<SysDesc> h_sys;
   std::vector<int64_t> tags;
@@ -530,11 +527,16 @@ struct Engine {
   SysDesc* p_sys = nullptr;
   int* p_tiles = nullptr;
   BCtl* p_ctl = nullptr;
+  Summary* p_sums = nullptr;
   hipEvent_t ev_upload = nullptr, ev_chunk = nullptr;
   bool upload_pending = false, chunk_pending = false;
   int n_listed = 0;                          // entries of the device tile list
   std::map<int, hipGraphExec_t> graphs;      // captured chunk per streaming grid size
 };
+
+static const Summary& status_of(const Engine& e, int slot) {
+  return e.method == 1 ? e.p_sums[slot] : e.p_ctl[slot].sum;
+}
 
 // Streaming grid for a list of n tiles: n rounded up to a multiple of 8 (the XCD mapping of
 // logical_block needs it) and, from 32 on, to two significant bits (4..7 times a power of two),
@@ -580,38 +582,67 @@ static void free_tiles_range(Engine& e, int start, int len) {
   }
 }
 
-int engine_create(void* ws, size_t ws_bytes, int64_t max_rows, int max_sys, int check_every,
-                  bool use_graph, hipStream_t s, Engine** out) {
-  const EngineLayout L = engine_layout(max_rows, max_sys);
+int engine_create(void* ws, size_t ws_bytes, const EngineConfig& cfg, hipStream_t s,
+                  Engine** out) {
+  if (cfg.max_rows < 1 || cfg.max_sys < 1) return -1;
+  if (cfg.method == 1 && (cfg.m < 1 || cfg.m > MMAX)) return -1;
+  const EngineLayout L = engine_layout(cfg);
   if (ws_bytes < L.total) return -4;
-  if (use_graph && (s == nullptr || (check_every & 1))) return -1;
+  if (cfg.use_graph && (s == nullptr || (cfg.method == 0 && (cfg.check_every & 1)))) return -1;
   Engine* e = new Engine();
   e->s = s;
-  e->max_rows = max_rows;
-  e->max_sys = max_sys;
-  e->max_tiles = (int)((max_rows + BS - 1) / BS);
+  e->max_rows = cfg.max_rows;
+  e->max_sys = cfg.max_sys;
+  e->max_tiles = (int)((cfg.max_rows + BS - 1) / BS);
   e->grid_tiles = (e->max_tiles + 7) / 8 * 8;
-  e->check_every = check_every;
-  e->use_graph = use_graph;
+  e->check_every = cfg.check_every;
+  e->use_graph = cfg.use_graph;
+  e->method = cfg.method;
+  e->m = cfg.m;
+  e->mixed = cfg.method == 1 && cfg.mixed;
+  e->rv = units_of(cfg);
+  e->max_units = e->grid_tiles / e->rv;
+  const int max_sys = cfg.max_sys;
   char* base = static_cast<char*>(ws);
-  BArgsB& a = e->args;
-  a.sys = reinterpret_cast<const SysDesc*>(base + L.sys);
-  a.act = reinterpret_cast<const int*>(base + L.tiles);
-  a.n_act = a.act + 2 * (size_t)e->grid_tiles;
-  a.ctl = reinterpret_cast<BCtl*>(base + L.ctl);
-  a.partials = reinterpret_cast<double*>(base + L.partials);
-  a.max_tiles = e->grid_tiles;
-  const size_t vb = align256(sizeof(double) * (size_t)e->grid_tiles * BS);
-  double* v[kBatchVectors];
-  for (int i = 0; i < kBatchVectors; ++i) v[i] = reinterpret_cast<double*>(base + L.vecs + i * vb);
-  a.r = v[0];
-  a.rh = v[1];
-  a.p[0] = v[2];
-  a.p[1] = v[3];
-  a.v[0] = v[4];
-  a.v[1] = v[5];
-  a.t = v[6];
-  a.par = 0;
+  if (e->method == 1) {
+    GArgs& g = e->gargs;
+    g.sys = reinterpret_cast<const SysDesc*>(base + L.sys);
+    g.act = reinterpret_cast<const int*>(base + L.tiles);
+    g.n_act = g.act + 2 * (size_t)e->max_units;
+    g.ctl = reinterpret_cast<Ctl*>(base + L.ctl);
+    g.sums = reinterpret_cast<Summary*>(base + L.sums);
+    g.partials = reinterpret_cast<double*>(base + L.partials);
+    g.pstride = e->grid_tiles;
+    g.max_units = e->max_units;
+    g.ldv = (size_t)e->grid_tiles * BS;
+    const size_t tb = e->mixed ? sizeof(float) : sizeof(double);
+    g.V = base + L.vecs;
+    g.w = base + L.vecs + align256(tb * g.ldv * (size_t)(cfg.m + 1));
+    g.zero = 0.0;
+    g.mixed = e->mixed ? 1 : 0;
+    e->column = e->mixed ? fits_buffer<float>(g.ldv, cfg.m + 1)
+                         : fits_buffer<double>(g.ldv, cfg.m + 1);
+  } else {
+    BArgsB& a = e->args;
+    a.sys = reinterpret_cast<const SysDesc*>(base + L.sys);
+    a.act = reinterpret_cast<const int*>(base + L.tiles);
+    a.n_act = a.act + 2 * (size_t)e->grid_tiles;
+    a.ctl = reinterpret_cast<BCtl*>(base + L.ctl);
+    a.partials = reinterpret_cast<double*>(base + L.partials);
+    a.max_tiles = e->grid_tiles;
+    const size_t vb = align256(sizeof(double) * (size_t)e->grid_tiles * BS);
+    double* v[kBatchVectors];
+    for (int i = 0; i < kBatchVectors; ++i)
+      v[i] = reinterpret_cast<double*>(base + L.vecs + i * vb);
+    a.r = v[0];
+    a.rh = v[1];
+    a.p[0] = v[2];
+    a.p[1] = v[3];
+    a.v[0] = v[4];
+    a.v[1] = v[5];
+    a.t = v[6];
+    a.par = 0;
+  }
   e->h_sys.assign(max_sys, SysDesc{});
   e->tags.assign(max_sys, 0);
   e->active.assign(max_sys, 0);
@@ -620,12 +651,15 @@ int engine_create(void* ws, size_t ws_bytes, int64_t max_rows, int max_sys, int 
   bool ok = hipHostMalloc((void**)&e->p_sys, sizeof(SysDesc) * max_sys, hipHostMallocDefault) ==
                 hipSuccess &&
             hipHostMalloc((void**)&e->p_tiles, sizeof(int) * (2 * (size_t)e->grid_tiles + 1),
-                          hipHostMallocDefault) ==
-                hipSuccess &&
-            hipHostMalloc((void**)&e->p_ctl, sizeof(BCtl) * max_sys, hipHostMallocDefault) ==
-                hipSuccess &&
+                          hipHostMallocDefault) == hipSuccess &&
             hipEventCreateWithFlags(&e->ev_upload, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&e->ev_chunk, hipEventDisableTiming) == hipSuccess;
+  if (ok && e->method == 1)
+    ok = hipHostMalloc((void**)&e->p_sums, sizeof(Summary) * max_sys, hipHostMallocDefault) ==
+         hipSuccess;
+  if (ok && e->method == 0)
+    ok = hipHostMalloc((void**)&e->p_ctl, sizeof(BCtl) * max_sys, hipHostMallocDefault) ==
+         hipSuccess;
   if (!ok) {
     engine_destroy(e);
     return -5;
@@ -643,6 +677,7 @@ void engine_destroy(Engine* e) {
   if (e->p_sys) (void)hipHostFree(e->p_sys);
   if (e->p_tiles) (void)hipHostFree(e->p_tiles);
   if (e->p_ctl) (void)hipHostFree(e->p_ctl);
+  if (e->p_sums) (void)hipHostFree(e->p_sums);
   delete e;
 }
 
@@ -664,9 +699,11 @@ int engine_submit(Engine* e, const Mat& A, const double* b, double* x, const Sol
       break;
     }
   if (slot < 0) return 1;   // no free slot
+  if (e->mixed && (!gs || !gs->mat32)) return -1;
   const int need = (A.n + BS - 1) / BS;
+  const int held = (need + e->rv - 1) / e->rv * e->rv;   // whole units
   int start = 0;
-  if (!alloc_tiles(*e, need, start)) return 1;   // no room
+  if (!alloc_tiles(*e, held, start)) return 1;   // no room
   SysDesc d{};
   d.n = A.n;
   d.kind = A.kind;
@@ -675,6 +712,8 @@ int engine_submit(Engine* e, const Mat& A, const double* b, double* x, const Sol
   d.nz = A.nz;
   d.tile_off = start;
   d.ntiles = need;
+  d.unit_off = start / e->rv;
+  d.nunits = held / e->rv;
   d.row_off = (int64_t)start * BS;
   d.rp = A.csr.rp;
   d.ci = A.csr.ci;
@@ -684,7 +723,9 @@ int engine_submit(Engine* e, const Mat& A, const double* b, double* x, const Sol
   d.x = x;
   d.W = prm.weights;
   d.gs_p = 0;
-  if (gs) {   // the solve reads the GS outputs
+  d.mat32 = nullptr;
+  d.ldp32 = 0;
+  if (gs && gs->p > 0) {   // the solve reads the GS outputs
     d.gs_p = gs->p;
     d.gs_val = A.kind == MAT_STENCIL ? A.coef : A.csr.val;
     d.gs_b = b;
@@ -693,20 +734,35 @@ int engine_submit(Engine* e, const Mat& A, const double* b, double* x, const Sol
     d.b = gs->b_out;
     d.W = gs->weight_out;
   }
+  if (e->mixed) {
+    d.mat32 = gs->mat32;
+    d.ldp32 = gs->ldp32;
+  }
+  const bool prepare = d.gs_p > 0 || d.mat32 != nullptr;
   e->h_sys[slot] = d;
   e->tags[slot] = tag;
   e->active[slot] = 1;
-  for (int t = 0; t < need; ++t) e->tile_sys[start + t] = slot;
+  for (int t = 0; t < held; ++t) e->tile_sys[start + t] = slot;
   e->dirty = true;
-  BCtl* c = e->args.ctl + slot;
-  hipLaunchKernelGGL(k_batch_init, dim3(1), dim3(64), 0, e->s, c, prm.maxit, prm.tol, prm.eps_b,
-                     d.W ? 1 : 0, gs ? 1 : 0);
+  int* bad = nullptr;
+  if (e->method == 1) {
+    Ctl* c = e->gargs.ctl + slot;
+    bad = &c->bad;
+    if (launch_gmres_init(c, prm.maxit, e->m, prm.tol, prm.eps_b, d.W ? 1 : 0, prepare ? 1 : 0,
+                          e->s) != hipSuccess)
+      return -5;
+  } else {
+    BCtl* c = e->args.ctl + slot;
+    bad = &c->bad;
+    hipLaunchKernelGGL(k_batch_init, dim3(1), dim3(64), 0, e->s, c, prm.maxit, prm.tol,
+                       prm.eps_b, d.W ? 1 : 0, prepare ? 1 : 0);
+  }
   if (A.kind == MAT_CSR) {
     int64_t blocks = ((int64_t)A.csr.nnz + A.n + BS) / BS;
     if (blocks > 2048) blocks = 2048;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_batch_validate, dim3((unsigned)blocks), dim3(BS), 0, e->s, A.csr.rp,
-                       A.csr.ci, A.n, A.csr.nnz, c);
+                       A.csr.ci, A.n, A.csr.nnz, bad);
   }
   return hipGetLastError() == hipSuccess ? 0 : -5;
 }
@@ -719,18 +775,19 @@ static int upload(Engine& e) {
     if (!e.active[i]) e.p_sys[i].ntiles = 0;
   }
   int n = 0;
-  for (int t = 0; t < e.grid_tiles; ++t) {
+  for (int t = 0; t < e.grid_tiles; t += e.rv) {
     if (e.tile_sys[t] < 0) continue;
-    e.p_tiles[n] = t;
-    e.p_tiles[e.grid_tiles + n] = e.tile_sys[t];
+    e.p_tiles[n] = t / e.rv;
+    e.p_tiles[e.max_units + n] = e.tile_sys[t];
     ++n;
   }
-  e.p_tiles[2 * (size_t)e.grid_tiles] = n;
+  e.p_tiles[2 * (size_t)e.max_units] = n;
   e.n_listed = n;
-  if (hipMemcpyAsync(const_cast<SysDesc*>(e.args.sys), e.p_sys, sizeof(SysDesc) * e.max_sys,
+  if (hipMemcpyAsync(const_cast<SysDesc*>(e.method == 1 ? e.gargs.sys : e.args.sys), e.p_sys,
+                     sizeof(SysDesc) * e.max_sys,
                      hipMemcpyHostToDevice, e.s) != hipSuccess ||
-      hipMemcpyAsync(const_cast<int*>(e.args.act), e.p_tiles,
-                     sizeof(int) * (2 * (size_t)e.grid_tiles + 1), hipMemcpyHostToDevice,
+      hipMemcpyAsync(const_cast<int*>(e.method == 1 ? e.gargs.act : e.args.act), e.p_tiles,
+                     sizeof(int) * (2 * (size_t)e.max_units + 1), hipMemcpyHostToDevice,
                      e.s) != hipSuccess ||
       hipEventRecord(e.ev_upload, e.s) != hipSuccess)
     return -5;
@@ -740,6 +797,10 @@ static int upload(Engine& e) {
 }
 
 static void enqueue_chunk(Engine& e, int k, int64_t first_iter, int grid) {
+  if (e.method == 1) {
+    (void)launch_gmres_chunk(e.gargs, e.m, grid, e.max_sys, e.column, e.s);
+    return;
+  }
   const dim3 gt(grid), gs(e.max_sys), block(BS);
   BArgsB a = e.args;
   hipLaunchKernelGGL(k_batch_gs, gt, block, 0, e.s, a);
@@ -763,8 +824,9 @@ int engine_run(Engine* e, int chunks) {
   const int grid = stream_grid(e->n_listed);
   hipGraphExec_t exec = nullptr;
   if (e->use_graph) {
-    // Every chunk starts at an even iteration (k is even), so one captured chunk per grid size
-    // serves all; the chunk reads the tile list and control blocks from device memory.
+    // Every Bi-CGSTAB chunk starts at an even iteration (k is even) and every GMRES chunk at
+    // the start of a cycle, so one captured chunk per grid size serves all; the chunk reads
+    // the unit list and control blocks from device memory.
     auto it = e->graphs.find(grid);
     if (it != e->graphs.end()) {
       exec = it->second;
@@ -787,11 +849,14 @@ int engine_run(Engine* e, int chunks) {
     }
     e->launched += k;
   }
-  if (hipGetLastError() != hipSuccess ||
-      hipMemcpyAsync(e->p_ctl, e->args.ctl, sizeof(BCtl) * e->max_sys, hipMemcpyDeviceToHost,
-                     e->s) != hipSuccess ||
-      hipEventRecord(e->ev_chunk, e->s) != hipSuccess)
-    return -5;
+  if (hipGetLastError() != hipSuccess) return -5;
+  const hipError_t cp =
+      e->method == 1
+          ? hipMemcpyAsync(e->p_sums, e->gargs.sums, sizeof(Summary) * e->max_sys,
+                           hipMemcpyDeviceToHost, e->s)
+          : hipMemcpyAsync(e->p_ctl, e->args.ctl, sizeof(BCtl) * e->max_sys,
+                           hipMemcpyDeviceToHost, e->s);
+  if (cp != hipSuccess || hipEventRecord(e->ev_chunk, e->s) != hipSuccess) return -5;
   e->chunk_pending = true;
   return 0;
 }
@@ -811,14 +876,15 @@ int engine_poll(Engine* e, bool wait, EngineDone* out, int max_out, int* n_out) 
   e->chunk_pending = false;
   int n = 0;
   for (int i = 0; i < e->max_sys && n < max_out; ++i) {
-    if (!e->active[i] || e->p_ctl[i].sum.state != ST_DONE) continue;
+    if (!e->active[i] || status_of(*e, i).state != ST_DONE) continue;
     out[n].tag = e->tags[i];
-    out[n].sum = e->p_ctl[i].sum;
+    out[n].sum = status_of(*e, i);
     ++n;
     e->active[i] = 0;
     const SysDesc& d = e->h_sys[i];
-    for (int t = 0; t < d.ntiles; ++t) e->tile_sys[d.tile_off + t] = -1;
-    free_tiles_range(*e, d.tile_off, d.ntiles);
+    const int held = d.nunits * e->rv;
+    for (int t = 0; t < held; ++t) e->tile_sys[d.tile_off + t] = -1;
+    free_tiles_range(*e, d.tile_off, held);
     e->dirty = true;
   }
   *n_out = n;

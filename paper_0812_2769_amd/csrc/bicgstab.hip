@@ -233,6 +233,10 @@ __global__ __launch_bounds__(BS) void k_bicg_p(BArgs a, Op op) {
   if (nrows > 0) pre = op.load(row0, nrows, G);
   const GatherP::Raw own = G.load(row);
   asm volatile("" ::: "memory");   // every load above is issued before anything is combined
+  // A CSR product follows indices that are trusted only while the solve runs: test first.
+  if constexpr (!Op::kRowwise) {
+    if (state != ST_RUNNING) return;
+  }
   const double y = nrows > 0 ? op.finish(pre, row0, nrows, G, L) : 0.0;
   const double pn = G.value(own);
   if (state != ST_RUNNING) return;
@@ -287,6 +291,9 @@ __global__ __launch_bounds__(BS) void k_bicg_s(BArgs a, Op op) {
   if (nrows > 0) pre = op.load(row0, nrows, G);
   const GatherS::Raw own = G.load(row);
   asm volatile("" ::: "memory");
+  if constexpr (!Op::kRowwise) {
+    if (state != ST_RUNNING) return;
+  }
   const double y = nrows > 0 ? op.finish(pre, row0, nrows, G, L) : 0.0;
   const double sv = G.value(own);
   if (state != ST_RUNNING) return;

@@ -33,6 +33,7 @@
 // is iterative refinement with one GMRES(m) cycle per correction. Every value a kernel uses
 // after storing it is the stored (rounded) value, so the Arnoldi relation holds for the data
 // in memory.
+#include "gmres_body.hpp"
 #include "gsk_host.hpp"
 
 namespace gsk {
@@ -83,24 +84,9 @@ __global__ __launch_bounds__(64) void k_init_ctl(Ctl* c, int maxit, int m, doubl
   c->last_rt = 0.0;
 }
 
-// Every streaming kernel below works on one tile of BS rows per workgroup, one row per
-// thread (workgroup lb of the XCD-aware numbering owns rows [lb*BS, lb*BS + BS)).
-__device__ inline int tile_rows(int n, int row0) { return max(0, min(BS, n - row0)); }
-
-// Workgroup total of one per-thread value into partials[col * nb + lb].
-__device__ inline void block_single_partial(double v, double* __restrict__ partials, int col,
-                                            int nb, int lb, double* lds) {
-  v = wave_sum(v);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-#pragma unroll
-    for (int q = 0; q < WAVES; ++q) s += lds[q];
-    partials[(size_t)col * nb + lb] = s;
-  }
-}
+// The workgroup bodies of the kernels below are in gmres_body.hpp (shared with the batch
+// engine). Here each workgroup takes the rows of its XCD-aware index (one tile of BS rows per
+// workgroup, or RPT tiles), and the partials have one entry per workgroup of the grid.
 
 // R: r = b - A x (FP64, the caller's matrix) into u_0 stored as T; partials ||r||^2
 // (column 0), ||W r||^2 (column 1) and ||u_0||^2 of the stored values (column 2).
@@ -109,34 +95,10 @@ __global__ __launch_bounds__(BS) void k_gmres_residual(KArgs a, Op op, const dou
                                                        const double* __restrict__ x,
                                                        const double* __restrict__ W,
                                                        T* __restrict__ u0, const int* flags) {
-  Ctl* c = a.ctl;
-  const int st = c->sum.state;
-  if (st != ST_INIT && st != ST_CYCLE_END) return;
-  if (flags[0]) return;
-  mark_work(c, a.pslot, a.mat_bytes + a.n * (16.0 + sizeof(T) + (W ? 8.0 : 0.0)));
   __shared__ typename Op::Lds L;
   __shared__ double red[NC_MAX * WAVES];
-  const int nb = gridDim.x;
-  const int lb = logical_block();
-  const int row0 = lb * BS;
-  const int nrows = tile_rows(a.n, row0);
-  double acc[3] = {0.0, 0.0, 0.0};
-  if (nrows > 0) {
-    const double y = op.tile(row0, nrows, GatherX{x}, L);
-    if ((int)threadIdx.x < nrows) {
-      const int row = row0 + threadIdx.x;
-      const double r = b[row] - y;
-      const T rs = (T)r;
-      u0[row] = rs;
-      acc[0] = r * r;
-      if (W) {
-        const double wr = W[row] * r;
-        acc[1] = wr * wr;
-      }
-      acc[2] = (double)rs * (double)rs;
-    }
-  }
-  block_partials<3>(acc, 3, a.partials, nb, lb, red);
+  gmres_residual_tile<Op, T>(a.ctl, op, a.n, b, x, W, u0, flags[0], logical_block(), a.partials,
+                             gridDim.x, a.pslot, a.mat_bytes, L, red);
 }
 
 // FR: convergence / restart decision after the true residual (see file comment).
@@ -147,228 +109,35 @@ __global__ __launch_bounds__(BS) void k_gmres_residual(KArgs a, Op op, const dou
 __global__ __launch_bounds__(BS) void k_gmres_fin_residual(Ctl* c, const double* partials,
                                                            int nb, int has_w, int mixed,
                                                            const int* flags) {
-  const int st = c->sum.state;
-  if (st != ST_INIT && st != ST_CYCLE_END) return;
-  if (flags[0]) {
-    if (threadIdx.x == 0) {
-      c->sum.state = ST_DONE;
-      c->sum.status = -1;
-    }
-    return;
-  }
-  __shared__ double out[8];
-  small_sums<3>(partials, nb, out);
-  if (threadIdx.x != 0) return;
-  const double nr = sqrt(out[0]);
-  const double nwr = has_w ? sqrt(out[1]) : nr;
-  const double ns = sqrt(out[2]);   // norm of the stored u_0 (equals nr in FP64)
-  if (st == ST_INIT) {
-    c->ref = nwr;
-    if (nwr == 0.0) {
-      c->sum.status = S_CONVERGED;
-      c->sum.relres_rec = 0.0;
-      c->sum.relres_true = 0.0;
-      c->sum.state = ST_DONE;
-      return;
-    }
-    if (c->maxit == 0) {
-      c->sum.status = S_MAXIT;
-      c->sum.state = ST_DONE;
-      return;
-    }
-  } else {
-    const double rt = nwr / c->ref;
-    c->sum.relres_true = rt;
-    if (c->broke) {
-      c->sum.status = S_BREAKDOWN;
-      c->sum.state = ST_DONE;
-      return;
-    }
-    if (rt < c->tol) {
-      c->sum.status = S_CONVERGED;
-      c->sum.state = ST_DONE;
-      return;
-    }
-    if (c->sum.iters >= c->maxit) {
-      c->sum.status = S_MAXIT;
-      c->sum.state = ST_DONE;
-      return;
-    }
-    const int progress = mixed && rt < 0.5 * c->last_rt;
-    if (c->claimed && !progress) {
-      c->sum.fails += 1;
-      if (c->sum.fails >= 3) {
-        c->sum.status = S_STAGNATED;
-        c->sum.state = ST_DONE;
-        return;
-      }
-    } else {
-      c->sum.fails = 0;
-    }
-    c->sum.restarts += 1;
-  }
-  // start a cycle: v_0 = u_0 / ||u_0||, g = ||u_0|| e_1; the cycle's estimates are in the
-  // norm of the stored u_0 and are converted to the stop-test metric by nwr / ns
-  c->last_rt = nwr / c->ref;
-  c->sigma[0] = 1.0 / ns;
-  c->g[0] = ns;
-  for (int i = 1; i <= c->m; ++i) c->g[i] = 0.0;
-  c->ratio = nwr / ns;
-  c->j = 0;
-  c->k = 0;
-  c->claimed = 0;
-  c->happy = 0;
-  c->sum.state = ST_RUNNING;
-}
-
-// Rows per thread. A workgroup owns RPT consecutive tiles of BS rows and thread t the rows
-// row0 + q BS + t, q < RPT. FP32 data use RPT = 2, so that a thread keeps as many bytes of
-// loads in flight as an FP64 thread; a CSR product stages one tile at a time through LDS and
-// keeps RPT = 1.
-template <class T>
-constexpr int rpt_of() { return 8 / (int)sizeof(T); }
-
-// (double)x for a value the kernel has already widened once. The empty asm makes the two
-// conversions distinct to the compiler, so it keeps the narrow value (one register for a
-// float) alive instead of the widened one (two registers), which would halve occupancy.
-template <class T>
-__device__ inline double widen_again(T x) {
-  if constexpr (sizeof(T) == 4) asm("" : "+v"(x));
-  return (double)x;
+  gmres_fin_residual_body(c, partials, nb, nb, has_w, mixed, flags[0] ? -1 : 0);
 }
 
 // A: w = sigma_j A u_j; partials of u_i . w (columns 0..j) and ||w||^2 (column j+1).
-// Loads are issued in the order they are needed (stencil operands, then the basis values of
-// the thread's rows) before the launch tests whether it has work: the control block is read
-// alongside, so the test costs no round trip of its own. A launch without work stores nothing.
 template <int JM, int RPT, class R, class Op, class T>
 __global__ __launch_bounds__(BS) void k_gmres_a(KArgs a, Op op, const T* __restrict__ V,
                                                 size_t ldv, T* __restrict__ w, int j) {
-  Ctl* c = a.ctl;
-  const int state = c->sum.state, cj = c->j;
-  const double sg = c->sigma[j];
   __shared__ typename Op::Lds L;
   __shared__ double red[NC_MAX * WAVES];
   __shared__ double red1[WAVES];
-  const int nb = gridDim.x;
-  const int lb = logical_block();
-  const T zero = (T)a.zero;
-  const int t = threadIdx.x;
-  const GatherXT<T> gx{V + (size_t)j * ldv};
-  const R rd(V, ldv, j + 1);
-  int rq[RPT], nq[RPT];
-  typename Op::template Pre<GatherXT<T>> pre[RPT];
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    rq[q] = (lb * RPT + q) * BS;
-    nq[q] = tile_rows(a.n, rq[q]);
-    pre[q] = op.load(rq[q], nq[q], gx);   // unconditional: valid rows for any tile
-  }
-  T u[JM][RPT];
-#pragma unroll
-  for (int i = 0; i < JM; ++i)
-#pragma unroll
-    for (int q = 0; q < RPT; ++q)
-      u[i][q] = (i <= j && t < nq[q]) ? rd.raw(i, rq[q] + t) : zero;
-  double y[RPT];
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) y[q] = nq[q] > 0 ? op.finish(pre[q], rq[q], nq[q], gx, L) : 0.0;
-  asm volatile("" ::: "memory");   // keeps the loads above ahead of the test below
-  if (state != ST_RUNNING || cj != j) return;
-  mark_work(c, a.pslot, a.inner_bytes + (double)sizeof(T) * a.n * (j + 2));
-  double wr[RPT], nrm = 0.0;
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const T ws = (T)(sg * y[q]);
-    const bool mine = t < nq[q];
-    wr[q] = mine ? (double)ws : 0.0;
-    if (mine) w[rq[q] + t] = ws;
-    nrm += wr[q] * wr[q];
-  }
-  double v[JM];
-#pragma unroll
-  for (int i = 0; i < JM; ++i) {
-    v[i] = 0.0;
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) v[i] += widen_again(u[i][q]) * wr[q];
-  }
-  block_halving_partials<JM>(v, j + 1, a.partials, nb, lb, red);
-  block_single_partial(nrm, a.partials, j + 1, nb, lb, red1);
+  gmres_a_tile<JM, RPT, R, Op, T>(a.ctl, op, a.n, V, ldv, w, j, logical_block(), a.partials,
+                                  gridDim.x, (T)a.zero, a.pslot, a.inner_bytes, L, red, red1);
 }
 
 // FA (j+2 workgroups): workgroup i <= j -> c1_i = sigma_i (u_i . w); workgroup j+1 -> ||A v_j||.
-// The control words are read together with the partials (one memory round trip) and only the
-// store depends on them.
 __global__ __launch_bounds__(BS) void k_gmres_fin_a(Ctl* c, const double* partials, int nb,
                                                     int j) {
   __shared__ double lds[WAVES];
   const int col = blockIdx.x;
-  const int state = c->sum.state, cj = c->j;
-  const double sg = c->sigma[col];
-  const double s = column_sum(partials + (size_t)col * nb, nb, lds);
-  if (state != ST_RUNNING || cj != j || threadIdx.x != 0) return;
-  if (col == j + 1) {
-    c->wnorm_pre = sqrt(s);
-  } else {
-    const double c1 = sg * s;
-    c->c1[col] = c1;
-    c->d1[col] = c1 * sg;
-  }
+  gmres_fin_a_body(c, partials + (size_t)col * nb, nb, j, col, lds);
 }
 
-// B: w -= sum_i c1_i v_i (weights d1_i = c1_i sigma_i on the stored columns), then partials of
-// u_i . w, sharing one read of the basis. Operands are requested before the work test, as in A.
+// B: w -= sum_i c1_i v_i, then partials of u_i . w, sharing one read of the basis.
 template <int JM, int RPT, class R, class T>
 __global__ __launch_bounds__(BS) void k_gmres_b(KArgs a, const T* __restrict__ V, size_t ldv,
                                                 T* __restrict__ w, int j) {
-  Ctl* c = a.ctl;
-  const int state = c->sum.state, cj = c->j;
   __shared__ double red[NC_MAX * WAVES];
-  const int t = threadIdx.x;
-  const int nb = gridDim.x;
-  const int lb = logical_block();
-  const T zero = (T)a.zero;
-  double d[JM];   // uniform across the launch: scalar loads
-#pragma unroll
-  for (int i = 0; i < JM; ++i) d[i] = c->d1[i];
-  const R rd(V, ldv, j + 1);
-  int row[RPT];
-  bool mine[RPT];
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    row[q] = (lb * RPT + q) * BS + t;
-    mine[q] = row[q] < a.n;
-  }
-  T u[JM][RPT];
-#pragma unroll
-  for (int i = 0; i < JM; ++i)
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) u[i][q] = (i <= j && mine[q]) ? rd.raw(i, row[q]) : zero;
-  T wv[RPT];
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) wv[q] = mine[q] ? w[row[q]] : zero;
-  asm volatile("" ::: "memory");
-  if (state != ST_RUNNING || cj != j) return;
-  mark_work(c, a.pslot, (double)sizeof(T) * a.n * (j + 3));
-  double wr[RPT];
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    double x = (double)wv[q];
-#pragma unroll
-    for (int i = 0; i < JM; ++i)
-      if (i <= j) x = fma(-d[i], (double)u[i][q], x);
-    const T ws = (T)x;
-    wr[q] = mine[q] ? (double)ws : 0.0;
-    if (mine[q]) w[row[q]] = ws;
-  }
-  double v[JM];
-#pragma unroll
-  for (int i = 0; i < JM; ++i) {
-    v[i] = 0.0;
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) v[i] += widen_again(u[i][q]) * wr[q];
-  }
-  block_halving_partials<JM>(v, j + 1, a.partials, nb, lb, red);
+  gmres_b_tile<JM, RPT, R, T>(a.ctl, a.n, V, ldv, w, j, logical_block(), a.partials, gridDim.x,
+                              (T)a.zero, a.pslot, red);
 }
 
 // FB (j+1 workgroups): c2_i = sigma_i (u_i . w).
@@ -376,177 +145,31 @@ __global__ __launch_bounds__(BS) void k_gmres_fin_b(Ctl* c, const double* partia
                                                     int j) {
   __shared__ double lds[WAVES];
   const int col = blockIdx.x;
-  const int state = c->sum.state, cj = c->j;
-  const double sg = c->sigma[col];
-  const double s = column_sum(partials + (size_t)col * nb, nb, lds);
-  if (state != ST_RUNNING || cj != j || threadIdx.x != 0) return;
-  const double c2 = sg * s;
-  c->c2[col] = c2;
-  c->d2[col] = c2 * sg;
+  gmres_fin_b_body(c, partials + (size_t)col * nb, nb, j, col, lds);
 }
 
-// C: w -= sum_i c2_i v_i (weights d2_i = c2_i sigma_i), u_{j+1} = w, partial ||w||^2.
-// Operands are requested before the work test, as in A.
+// C: w -= sum_i c2_i v_i, u_{j+1} = w, partial ||w||^2.
 template <int JM, int RPT, class R, class T>
 __global__ __launch_bounds__(BS) void k_gmres_c(KArgs a, T* __restrict__ V, size_t ldv,
                                                 const T* __restrict__ w, int j) {
-  Ctl* c = a.ctl;
-  const int state = c->sum.state, cj = c->j;
   __shared__ double red[WAVES];
-  const int t = threadIdx.x;
-  const int nb = gridDim.x;
-  const int lb = logical_block();
-  const T zero = (T)a.zero;
-  double d[JM];   // uniform across the launch: scalar loads
-#pragma unroll
-  for (int i = 0; i < JM; ++i) d[i] = c->d2[i];
-  const R rd(V, ldv, j + 1);
-  int row[RPT];
-  bool mine[RPT];
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    row[q] = (lb * RPT + q) * BS + t;
-    mine[q] = row[q] < a.n;
-  }
-  T u[JM][RPT];
-#pragma unroll
-  for (int i = 0; i < JM; ++i)
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) u[i][q] = (i <= j && mine[q]) ? rd.raw(i, row[q]) : zero;
-  T wv[RPT];
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) wv[q] = mine[q] ? w[row[q]] : zero;
-  asm volatile("" ::: "memory");
-  if (state != ST_RUNNING || cj != j) return;
-  mark_work(c, a.pslot, (double)sizeof(T) * a.n * (j + 3));
-  double nrm = 0.0;
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    double x = (double)wv[q];
-#pragma unroll
-    for (int i = 0; i < JM; ++i)
-      if (i <= j) x = fma(-d[i], (double)u[i][q], x);
-    const T ws = (T)x;
-    const double wr = mine[q] ? (double)ws : 0.0;
-    if (mine[q]) V[(size_t)(j + 1) * ldv + row[q]] = ws;
-    nrm += wr * wr;
-  }
-  block_single_partial(nrm, a.partials, 0, nb, lb, red);
+  gmres_c_tile<JM, RPT, R, T>(a.ctl, a.n, V, ldv, w, j, logical_block(), a.partials, gridDim.x,
+                              (T)a.zero, a.pslot, red);
 }
 
 // FC (1 workgroup): Hessenberg column, Givens rotations, residual estimate; at the end of a
-// cycle the k x k triangular solve H y = g (y stored pre-multiplied by sigma). Every control
-// word the launch needs is requested before the first wait; the old rotations are applied in
-// registers by one thread.
+// cycle the triangular solve for y.
 __global__ __launch_bounds__(BS) void k_gmres_fin_c(Ctl* c, const double* partials, int nb,
                                                     int j) {
-  __shared__ double lds[WAVES];
-  __shared__ double s_h[MMAX + 2];
-  __shared__ double s_cs[MMAX], s_sn[MMAX];
-  __shared__ int s_end, s_k;
-  constexpr int LDH = MMAX + 1;
-  const int t = threadIdx.x;
-  const int state = c->sum.state, cj = c->j;
-  const int iters = c->sum.iters, maxit = c->maxit, m = c->m;
-  const double eps_b = c->eps_b, wpre = c->wnorm_pre, gj = c->g[j];
-  const double ratio = c->ratio, ref = c->ref, tol = c->tol;
-  if (t <= j) {
-    s_h[t] = c->c1[t] + c->c2[t];
-    s_cs[t] = c->cs[t];
-    s_sn[t] = c->sn[t];
-  }
-  const double nrm2 = column_sum(partials, nb, lds);   // also orders the LDS writes above
-  if (state != ST_RUNNING || cj != j) return;
-  const double hn = sqrt(nrm2);
-  if (t <= j) c->Hraw[(size_t)j * LDH + t] = s_h[t];
-  if (t == j + 1) c->Hraw[(size_t)j * LDH + t] = hn;
-  if (t == 0) {
-    const int happy = hn <= eps_b * wpre;
-    c->happy = happy;
-    if (!happy) c->sigma[j + 1] = 1.0 / hn;
-    double hi = s_h[0];
-    for (int i = 0; i < j; ++i) {
-      const double hnext = s_h[i + 1];
-      s_h[i] = s_cs[i] * hi + s_sn[i] * hnext;
-      hi = -s_sn[i] * hi + s_cs[i] * hnext;
-    }
-    const double dd = hypot(hi, hn);
-    c->sum.iters = iters + 1;
-    int end = 0, k = j + 1;
-    if (dd == 0.0) {
-      c->broke = 1;
-      c->sum.brk = BRK_GIVENS;
-      k = j;
-      end = 1;
-      s_h[j] = hi;
-      s_h[j + 1] = hn;
-    } else {
-      const double cjr = hi / dd;
-      const double sjr = hn / dd;
-      s_h[j] = dd;
-      s_h[j + 1] = 0.0;
-      const double g1 = -sjr * gj;
-      c->g[j + 1] = g1;
-      c->g[j] = cjr * gj;
-      c->cs[j] = cjr;
-      c->sn[j] = sjr;
-      const double est = fabs(g1) * ratio / ref;
-      c->sum.relres_rec = est;
-      const int claimed = (est < tol) || happy;
-      c->claimed = claimed;
-      end = claimed || (iters + 1 >= maxit) || (j + 1 == m);
-    }
-    c->j = j + 1;
-    c->k = k;
-    s_end = end;
-    s_k = k;
-  }
-  __syncthreads();
-  if (t <= j + 1) c->H[(size_t)j * LDH + t] = s_h[t];
-  if (!s_end) return;
-
-  __shared__ double s_H[MMAX][MMAX + 1];   // s_H[col][row]
-  __shared__ double s_g[MMAX + 1], s_y[MMAX];
-  const int k = s_k;
-  for (int idx = t; idx < k * k; idx += BS) {
-    const int col = idx / k, row = idx % k;
-    s_H[col][row] = (col == j) ? s_h[row] : c->H[(size_t)col * LDH + row];
-  }
-  if (t < k) s_g[t] = c->g[t];
-  __syncthreads();
-  for (int i = k - 1; i >= 0; --i) {
-    if (t == 0) s_y[i] = s_g[i] / s_H[i][i];
-    __syncthreads();
-    if (t < i) s_g[t] -= s_H[i][t] * s_y[i];
-    __syncthreads();
-  }
-  if (t < k) c->y[t] = s_y[t] * c->sigma[t];
-  __syncthreads();
-  if (t == 0) c->sum.state = ST_CYCLE_END;
+  gmres_fin_c_body(c, partials, nb, j);
 }
 
 // X: x += sum_{l<k} y_l v_l (y already carries sigma).
 template <int RPT, class R, class T>
 __global__ __launch_bounds__(BS) void k_gmres_x(KArgs a, const T* __restrict__ V, size_t ldv,
                                                 double* __restrict__ x) {
-  Ctl* c = a.ctl;
-  if (c->sum.state != ST_CYCLE_END) return;
   __shared__ double s_y[MMAX];
-  const int k = c->k;
-  mark_work(c, a.pslot, a.n * ((double)sizeof(T) * k + 16.0));
-  const int t = threadIdx.x;
-  if (t < k) s_y[t] = c->y[t];
-  __syncthreads();
-  const int lb = logical_block();
-  const R rd(V, ldv, k > 0 ? k : 1);
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int row = (lb * RPT + q) * BS + t;
-    if (row >= a.n) continue;
-    double acc = 0.0;
-    for (int l = 0; l < k; ++l) acc = fma(s_y[l], rd.load(l, row), acc);
-    x[row] = x[row] + acc;
-  }
+  gmres_x_tile<RPT, R, T>(a.ctl, a.n, V, ldv, x, logical_block(), a.pslot, s_y);
 }
 
 // Arnoldi entry point: u_0 = r0, partial ||r0||^2.

@@ -70,7 +70,9 @@ struct Ctl {
   Summary sum;
   ProbeSlots probe;
   int maxit, m, j, k, claimed, first, has_w;
-  int broke, happy, pad0, pad1;
+  int broke, happy;
+  int bad;                   // batch engine: BAD_* bits of rejected system data
+  int pad1;
   double tol, eps_b, ref, ratio;
   double last_rt;            // GMRES: relative true residual at the start of the cycle
   // Bi-CGSTAB scalars
@@ -358,13 +360,14 @@ struct GsLds {
 
 // One tile of a CSR matrix (rows row0 .. row0+nrows-1, thread t owns row row0+t): the tile's
 // values are staged in LDS with coalesced loads, each thread sums its row, and the scaled
-// values are written back coalesced. A row that is zero or non-finite sets the flag and leaves
-// its outputs unwritten. All threads of the workgroup must call.
+// values are written back coalesced (and, if val32 is given, also rounded to FP32). A row that
+// is zero or non-finite sets the flag and leaves its outputs unwritten. All threads of the
+// workgroup must call.
 __device__ inline void gs_csr_tile(const int* __restrict__ rp, const double* __restrict__ val,
                                    const double* __restrict__ b, int p, int row0, int nrows,
                                    double* val_out, double* b_out, double* __restrict__ norm_out,
                                    double* __restrict__ weight_out, GsLds& L, bool& zero,
-                                   bool& nonfinite) {
+                                   bool& nonfinite, float* __restrict__ val32 = nullptr) {
 #pragma clang fp contract(off)
   const int t = threadIdx.x;
   for (int i = t; i <= nrows; i += BS) L.rp[i] = rp[row0 + i];
@@ -400,7 +403,11 @@ __device__ inline void gs_csr_tile(const int* __restrict__ rp, const double* __r
       if (norm_out) norm_out[row0 + t] = nrm;
       if (weight_out) weight_out[row0 + t] = nrm / sqrt(s2);
       if (!staged)
-        for (int k = ks; k < ke; ++k) val_out[p0 + k] = val[p0 + k] / nrm;
+        for (int k = ks; k < ke; ++k) {
+          const double a = val[p0 + k] / nrm;
+          val_out[p0 + k] = a;
+          if (val32) val32[p0 + k] = (float)a;
+        }
     }
     L.scale[t] = ok ? nrm : 0.0;
   }
@@ -408,7 +415,11 @@ __device__ inline void gs_csr_tile(const int* __restrict__ rp, const double* __r
     __syncthreads();
     for (int k = t; k < cnt; k += BS) {
       const double d = L.scale[L.row[k]];
-      if (d != 0.0) val_out[p0 + k] = L.val[k] / d;
+      if (d != 0.0) {
+        const double a = L.val[k] / d;
+        val_out[p0 + k] = a;
+        if (val32) val32[p0 + k] = (float)a;
+      }
     }
   }
   __syncthreads();   // LDS is reused by the caller's next tile
@@ -417,11 +428,14 @@ __device__ inline void gs_csr_tile(const int* __restrict__ rp, const double* __r
 // One row i of a 5/7-point stencil matrix held as coefficient planes (stride ldp): the present
 // positions are summed in the CSR column order, so the norm, weight and scaled values equal
 // those of the CSR form bit for bit (an absent position's coefficient, 0, is scaled to 0).
+// If c32 is given, the scaled coefficients are also stored rounded to FP32 (planes of stride
+// ldp32).
 __device__ inline void gs_stencil_row(const double* __restrict__ coef, size_t ldp, int n,
                                       int nx, int ny, int nz, const double* __restrict__ b,
                                       int p, int i, double* coef_out, double* b_out,
                                       double* __restrict__ weight_out, bool& zero,
-                                      bool& nonfinite) {
+                                      bool& nonfinite, float* __restrict__ c32 = nullptr,
+                                      size_t ldp32 = 0) {
 #pragma clang fp contract(off)
   const int ix = i % nx;
   const int rest = i / nx;
@@ -460,7 +474,11 @@ __device__ inline void gs_stencil_row(const double* __restrict__ coef, size_t ld
 #pragma unroll
   for (int q = 0; q < 7; ++q) {
     const int plane = three ? q : q - 1;
-    if (plane >= 0 && plane < planes) coef_out[(size_t)plane * ldp + i] = c[q] / nrm;
+    if (plane >= 0 && plane < planes) {
+      const double a = c[q] / nrm;
+      coef_out[(size_t)plane * ldp + i] = a;
+      if (c32) c32[(size_t)plane * ldp32 + i] = (float)a;
+    }
   }
 }
 

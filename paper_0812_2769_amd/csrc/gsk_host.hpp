@@ -106,26 +106,40 @@ SolveResult bicgstab_solve(const Mat& A, const double* b, double* x, const Solve
 SolveResult gmres_mixed_solve(const Mat& A, const double* b, double* x, int m,
                               const SolveParams& prm, void* ws, hipStream_t s);
 
-// Batched Bi-CGSTAB engine (batch.hip): many independent systems share every launch.
+// The batch engine (batch.hip, batch_gmres.hip): many independent systems share every launch.
 struct Engine;
 struct EngineDone {
   int64_t tag;
   Summary sum;
 };
-size_t engine_workspace_bytes(int64_t max_rows, int max_sys);
+struct EngineConfig {
+  int64_t max_rows;
+  int max_sys;
+  int method;        // 0 Bi-CGSTAB, 1 GMRES(m)
+  int m;             // GMRES restart length
+  bool mixed;        // GMRES: FP32 Arnoldi cycles, FP64 restarts
+  int check_every;   // Bi-CGSTAB: iterations per chunk
+  bool use_graph;
+};
+size_t engine_workspace_bytes(const EngineConfig& cfg);
 // 0 ok, -4 workspace too small, -1 invalid arguments, -5 HIP failure.
-int engine_create(void* ws, size_t ws_bytes, int64_t max_rows, int max_sys, int check_every,
-                  bool use_graph, hipStream_t s, Engine** out);
+int engine_create(void* ws, size_t ws_bytes, const EngineConfig& cfg, hipStream_t s,
+                  Engine** out);
 void engine_destroy(Engine* e);
-// Optional GS(p) stage of a submitted system: outputs of the scaled matrix values (CSR values
-// or planes, same layout as the input), b and (p != 2) stop weights.
+// Optional stage of a submitted system run by its first chunk. p > 0: GS(p), with outputs of
+// the scaled matrix values (CSR values or planes, same layout as the input), b and (p != 2)
+// stop weights. mat32 (mixed GMRES engines, required there): the FP32 copy of the scaled
+// matrix (planes of stride ldp32, or nnz values).
 struct GsStage {
   int p;
   double* val_out;
   double* b_out;
   double* weight_out;
+  float* mat32;
+  size_t ldp32;
 };
-// 0 admitted, 1 no free slot or rows (try again after a poll), -5 HIP failure.
+// 0 admitted, 1 no free slot or rows (try again after a poll), -1 invalid arguments (a mixed
+// engine without an FP32 matrix buffer), -5 HIP failure.
 int engine_submit(Engine* e, const Mat& A, const double* b, double* x, const SolveParams& prm,
                   int64_t tag, const GsStage* gs = nullptr);
 int engine_run(Engine* e, int chunks);

@@ -9,7 +9,7 @@ from __future__ import annotations
 import ctypes
 import dataclasses
 import os
-from typing import Optional
+from typing import Optional, Tuple
 
 import torch
 
@@ -79,6 +79,21 @@ class EngineUsage(ctypes.Structure):
 
 ENGINE_GRAPH = 1
 FULL = 1
+PRECISION_FP64, PRECISION_MIXED = 0, 1
+
+
+class EngineConfig(ctypes.Structure):
+    _fields_ = [("max_rows", ctypes.c_int64), ("max_systems", ctypes.c_int32),
+                ("method", ctypes.c_int32), ("m", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class EngineRequest(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("b", ctypes.c_void_p), ("x", ctypes.c_void_p),
+                ("tol", ctypes.c_double), ("opt", ctypes.c_void_p), ("tag", ctypes.c_int64),
+                ("gs_p", ctypes.c_int32), ("val_out", ctypes.c_void_p),
+                ("b_out", ctypes.c_void_p), ("stop_weight_out", ctypes.c_void_p),
+                ("mat32", ctypes.c_void_p), ("mat32_ld", ctypes.c_int64)]
 
 KCLASS = {"gmres_a": 1, "gmres_b": 2, "gmres_c": 3, "bicg_p": 4, "bicg_s": 5, "bicg_u": 6,
           "residual": 7, "gmres_x": 8}
@@ -135,6 +150,12 @@ def _load() -> ctypes.CDLL:
     lib.gsk_engine_submit_gs.argtypes = [vp, P(Matrix), vp, ctypes.c_int32, vp, vp, vp, vp,
                                          ctypes.c_double, P(Options), ctypes.c_int64]
     lib.gsk_engine_submit_gs.restype = ctypes.c_int
+    lib.gsk_engine_workspace_bytes_ex.argtypes = [P(EngineConfig)]
+    lib.gsk_engine_workspace_bytes_ex.restype = sz
+    lib.gsk_engine_create_ex.argtypes = [P(EngineConfig), vp, sz, vp, P(vp)]
+    lib.gsk_engine_create_ex.restype = ctypes.c_int
+    lib.gsk_engine_submit_ex.argtypes = [vp, P(EngineRequest)]
+    lib.gsk_engine_submit_ex.restype = ctypes.c_int
     lib.gsk_engine_run.argtypes = [vp, ctypes.c_int32]
     lib.gsk_engine_run.restype = ctypes.c_int
     lib.gsk_engine_poll.argtypes = [vp, ctypes.c_int32, P(Result), ctypes.c_int32,
@@ -240,6 +261,10 @@ class StencilMatrix:
             raise ValueError(f"coef must be a contiguous CUDA float64 tensor of {planes}*n values")
         self.coef = coef
         self.device = coef.device
+
+    @property
+    def planes(self) -> int:
+        return 7 if self.nz > 1 else 5
 
     def c_matrix(self) -> Matrix:
         return Matrix(MATRIX_STENCIL, Csr(0, 0, None, None, None),
@@ -438,49 +463,77 @@ def probe_end() -> dict:
             "bytes": r.bytes}
 
 
+def _vec_ld(n: int) -> int:
+    return (n + 63) // 64 * 64
+
+
 class Engine:
-    """Batched Bi-CGSTAB with continuous admission (gsk_engine_*). Systems are submitted with
-    device tensors that must stay alive until the system is reported by poll(); results are
+    """The batch engine with continuous admission (gsk_engine_*): Bi-CGSTAB, or GMRES(m) in FP64
+    or mixed precision (FP32 Arnoldi cycles, FP64 restarts). Systems are submitted with device
+    tensors that must stay alive until the system is reported by poll(); results are
     (tag, Info) pairs. The engine's vectors live in a workspace tensor it owns."""
 
     def __init__(self, max_rows: int, max_systems: int, check_every: int = 8,
-                 graph: bool = False, device="cuda", stream=None):
+                 graph: bool = False, device="cuda", stream=None, method: str = "bicgstab",
+                 m: int = 20, precision: str = "fp64"):
         self.device = torch.device(device)
         self.stream = stream if stream is not None else (
             torch.cuda.Stream(self.device) if graph else torch.cuda.current_stream(self.device))
-        nbytes = int(lib.gsk_engine_workspace_bytes(int(max_rows), int(max_systems)))
+        if method not in ("bicgstab", "gmres") or precision not in ("fp64", "mixed"):
+            raise ValueError("method must be 'bicgstab' or 'gmres', precision 'fp64' or 'mixed'")
+        self.method, self.m = method, int(m)
+        self.mixed = precision == "mixed"
+        cfg = EngineConfig(int(max_rows), int(max_systems),
+                           METHOD_GMRES if method == "gmres" else METHOD_BICGSTAB,
+                           self.m if method == "gmres" else 0,
+                           PRECISION_MIXED if self.mixed else PRECISION_FP64,
+                           int(check_every), ENGINE_GRAPH if graph else 0)
+        nbytes = int(lib.gsk_engine_workspace_bytes_ex(ctypes.byref(cfg)))
         if nbytes == 0:
-            raise GskError(ERR_INVALID_ARG, "no engine workspace size for these limits")
+            raise GskError(ERR_INVALID_ARG, "no engine workspace size for this configuration")
         self.ws = _aligned(nbytes, self.device)
         h = ctypes.c_void_p()
-        _check(lib.gsk_engine_create(self.ws.data_ptr(), self.ws.numel(), int(max_rows),
-                                     int(max_systems), int(check_every),
-                                     ENGINE_GRAPH if graph else 0, self.stream.cuda_stream,
-                                     ctypes.byref(h)))
+        _check(lib.gsk_engine_create_ex(ctypes.byref(cfg), self.ws.data_ptr(), self.ws.numel(),
+                                        self.stream.cuda_stream, ctypes.byref(h)))
         self._h = h
         self._keep = {}
-        self._opts = {}
         self.max_systems = int(max_systems)
+
+    def _mat32(self, A) -> Tuple[Optional[torch.Tensor], int]:
+        if not self.mixed:
+            return None, 0
+        if isinstance(A, StencilMatrix):
+            ld = _vec_ld(A.n)
+            return torch.empty(A.planes * ld, dtype=torch.float32, device=self.device), ld
+        return torch.empty(A.nnz, dtype=torch.float32, device=self.device), 0
+
+    def _submit(self, A, b, x, tol, tag, o, gs_p=0, val_out=None, b_out=None, w_out=None,
+                keep=()):
+        c = A.c_matrix()
+        m32, ld = self._mat32(A)
+        r = EngineRequest(ctypes.addressof(c), b.data_ptr(), x.data_ptr(), float(tol),
+                          ctypes.addressof(o), int(tag), int(gs_p), _ptr(val_out), _ptr(b_out),
+                          _ptr(w_out), _ptr(m32), int(ld))
+        # order with the caller's stream: inputs are ready when the engine's stream runs
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        rc = lib.gsk_engine_submit_ex(self._h, ctypes.byref(r))
+        if rc == FULL:
+            return False
+        _check(rc)
+        self._keep[int(tag)] = (A, b, x, val_out, b_out, w_out, m32) + tuple(keep)
+        return True
 
     def submit(self, A, b: torch.Tensor, x: torch.Tensor, tol: float = 1e-8, *, tag: int,
                maxit: Optional[int] = None, breakdown_eps=None,
                stop_weights: Optional[torch.Tensor] = None) -> bool:
-        """Admit one system; False if it does not fit now (retry after poll())."""
+        """Admit one (already scaled) system; False if it does not fit now (retry after
+        poll())."""
         _vec(b, A.n, "b")
         _vec(x, A.n, "x")
         if stop_weights is not None:
             _vec(stop_weights, A.n, "stop_weights")
         o = _options(maxit, breakdown_eps, stop_weights, None, A.n)
-        c = A.c_matrix()
-        # order with the caller's stream: inputs are ready when the engine's stream runs
-        self.stream.wait_stream(torch.cuda.current_stream(self.device))
-        rc = lib.gsk_engine_submit(self._h, ctypes.byref(c), b.data_ptr(), x.data_ptr(),
-                                   float(tol), ctypes.byref(o), int(tag))
-        if rc == FULL:
-            return False
-        _check(rc)
-        self._keep[int(tag)] = (A, b, x, stop_weights)
-        return True
+        return self._submit(A, b, x, tol, tag, o, keep=(stop_weights,))
 
     def submit_gs(self, A, b: torch.Tensor, x: torch.Tensor, p: int = 2, tol: float = 1e-8, *,
                   tag: int, maxit: Optional[int] = None, breakdown_eps=None) -> bool:
@@ -489,21 +542,14 @@ class Engine:
         fit now."""
         _vec(b, A.n, "b")
         _vec(x, A.n, "x")
+        if p < 1:
+            raise GskError(ERR_INVALID_ARG, "p must be >= 1")
         src = A.coef if isinstance(A, StencilMatrix) else A.val
         val_out = torch.empty_like(src)
         b_out = torch.empty_like(b)
         w_out = torch.empty_like(b) if p != 2 else None
         o = _options(maxit, breakdown_eps, None, None, A.n)
-        c = A.c_matrix()
-        self.stream.wait_stream(torch.cuda.current_stream(self.device))
-        rc = lib.gsk_engine_submit_gs(self._h, ctypes.byref(c), b.data_ptr(), int(p),
-                                      val_out.data_ptr(), b_out.data_ptr(), _ptr(w_out),
-                                      x.data_ptr(), float(tol), ctypes.byref(o), int(tag))
-        if rc == FULL:
-            return False
-        _check(rc)
-        self._keep[int(tag)] = (A, b, x, val_out, b_out, w_out)
-        return True
+        return self._submit(A, b, x, tol, tag, o, p, val_out, b_out, w_out)
 
     def run(self, chunks: int = 1) -> None:
         _check(lib.gsk_engine_run(self._h, int(chunks)))

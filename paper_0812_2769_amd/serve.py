@@ -4,9 +4,10 @@ Requests arrive over time (each an unscaled system, a method and a tolerance). T
 - admits Bi-CGSTAB requests into the batched engine (gsk_engine_*) as soon as its workspace
   has room (rows and a slot), GS(2) included, so requests that arrive while others are on the
   GPU join the running batch at the next chunk;
-- runs GMRES(m) requests on a few lanes (each a host thread with a stream and workspaces of
-  its own) that take requests from one queue, so GMRES solves overlap each other and the
-  engine's launches on the device;
+- runs GMRES(m) requests either on a few lanes (each a host thread with a stream and
+  workspaces of its own, one solve at a time) that take requests from one queue, or in a
+  GMRES engine of their own (FP64 or mixed precision) on its own stream and host thread, so
+  GMRES solves overlap each other and the Bi-CGSTAB engine's launches on the device;
 - keeps every request's Krylov state on the device until it is done, and records arrival,
   admission and completion times.
 
@@ -92,16 +93,86 @@ class GmresLane(threading.Thread):
                 self.q.task_done()
 
 
+class GmresEngineWorker(threading.Thread):
+    """Serves GMRES(m) requests through a GMRES engine of its own (its own stream): admits them
+    as rows and slots free up (GS(2) inside the engine), runs one cycle per chunk, and reports
+    each finished request. Results equal gsk_gmres (or gsk_gmres_mixed) on the same system."""
+
+    def __init__(self, q: queue.Queue, device, t0: float, max_rows: int, max_systems: int,
+                 m: int, precision: str, graph: bool, on_done: Callable):
+        super().__init__(daemon=True)
+        self.q = q
+        self.error = None
+        self.t0 = t0
+        self.on_done = on_done
+        self.m = m
+        self.engine = gsk.Engine(max_rows, max_systems, graph=graph, device=device,
+                                 method="gmres", m=m, precision=precision)
+
+    def run(self):
+        waiting = collections.deque()
+        inflight = {}
+        closing = False
+        try:
+            while not (closing and not waiting and not inflight):
+                # take new requests; block only when there is nothing else to do
+                block = not waiting and not inflight and not closing
+                while True:
+                    try:
+                        item = self.q.get(block=block, timeout=0.05 if block else None)
+                    except queue.Empty:
+                        break
+                    block = False
+                    if item is None:
+                        closing = True
+                        continue
+                    waiting.append(item)
+                while waiting:
+                    req, admitted = waiting[0]
+                    if req.m != self.m:
+                        raise ValueError(f"request m={req.m} on a GMRES({self.m}) engine")
+                    x = torch.zeros_like(req.b)
+                    if not self.engine.submit_gs(req.A, req.b, x, p=2, tol=req.tol,
+                                                 tag=req.tag):
+                        break
+                    inflight[req.tag] = (req, admitted, x)
+                    waiting.popleft()
+                if inflight:
+                    self.engine.run(1)
+                    for tag, info in self.engine.poll(wait=True):
+                        req, adm, x = inflight.pop(tag)
+                        self.on_done(Done(tag, "gmres", req.arrival, adm,
+                                          time.perf_counter() - self.t0, info, x))
+        except BaseException as e:   # reported by the server loop
+            self.error = e
+
+    def close(self):
+        self.engine.close()
+
+
 class Server:
     def __init__(self, max_rows: int, max_systems: int, check_every: int = 8,
                  graph: bool = True, gmres_rows: int = 0, m_max: int = 20, device="cuda",
-                 gmres_lanes: int = 4):
+                 gmres_lanes: int = 4, gmres_mode: str = "lanes",
+                 gmres_precision: str = "fp64", gmres_engine_rows: int = 0,
+                 gmres_engine_systems: int = 64):
+        """gmres_mode "lanes": GMRES requests run one at a time on gmres_lanes host threads
+        (workspaces for gmres_rows rows, any m <= m_max). "engine": they run in a GMRES(m_max)
+        engine (gmres_precision "fp64" or "mixed") with room for gmres_engine_rows rows and
+        gmres_engine_systems systems."""
         self.device = torch.device(device)
         self.engine = gsk.Engine(max_rows, max_systems, check_every=check_every, graph=graph,
                                  device=self.device)
         self.gmres_rows = gmres_rows
         self.m_max = m_max
         self.gmres_lanes = max(1, int(gmres_lanes))
+        if gmres_mode not in ("lanes", "engine"):
+            raise ValueError("gmres_mode must be 'lanes' or 'engine'")
+        self.gmres_mode = gmres_mode
+        self.gmres_precision = gmres_precision
+        self.gmres_engine_rows = gmres_engine_rows or max(gmres_rows, 1)
+        self.gmres_engine_systems = gmres_engine_systems
+        self.graph = graph
 
     def serve(self, requests: List[Request], realtime: bool = True) -> List[Done]:
         """Serve the requests (sorted by arrival). With realtime, a request is visible only
@@ -117,8 +188,13 @@ class Server:
             def finished(d):
                 with lock:
                     done.append(d)
-            lanes = [GmresLane(gq, self.device, t0, max(self.gmres_rows, 1), self.m_max,
-                               finished) for _ in range(self.gmres_lanes)]
+            if self.gmres_mode == "engine":
+                lanes = [GmresEngineWorker(gq, self.device, t0, self.gmres_engine_rows,
+                                           self.gmres_engine_systems, self.m_max,
+                                           self.gmres_precision, self.graph, finished)]
+            else:
+                lanes = [GmresLane(gq, self.device, t0, max(self.gmres_rows, 1), self.m_max,
+                                   finished) for _ in range(self.gmres_lanes)]
             for lane in lanes:
                 lane.start()
         inflight = {}     # engine tag -> (request, admitted time, x)
@@ -149,11 +225,10 @@ class Server:
                                              time.perf_counter() - t0, info, x))
                 else:
                     if not reqs and not waiting:
-                        if lanes:
-                            gq.join()   # every lane calls task_done, also after an error
                         with lock:
                             if len(done) >= n_total:
                                 break
+                        time.sleep(1e-3)   # the GMRES workers are still solving
                     if reqs and realtime:
                         time.sleep(max(0.0, min(1e-3, reqs[0].arrival - now)))
                 for lane in lanes:
@@ -167,6 +242,8 @@ class Server:
                 gq.put(None)
             for lane in lanes:
                 lane.join(timeout=60)
+                if isinstance(lane, GmresEngineWorker):
+                    lane.close()
         return done
 
     def close(self):

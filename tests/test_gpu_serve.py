@@ -3,7 +3,8 @@
 Requests (a Bi-CGSTAB / GMRES(20) mix, GS(2) per request) arrive while others are on the GPU
 and are admitted as the engine's rows and slots free up. Each Bi-CGSTAB result must equal
 gsk_gs_scale + stencil packing + gsk_bicgstab on the same system alone, bit for bit (x, info);
-each GMRES result must equal the single GMRES solve.
+each GMRES result, whether it ran on a lane or in a GMRES engine (FP64 or mixed precision),
+must equal the single GMRES solve of that precision.
 """
 import numpy as np
 import pytest
@@ -38,16 +39,17 @@ def pool(G, count=6):
     return out
 
 
-def alone(G, s, method):
+def alone(G, s, method, mixed=False):
     As, bs, _, _ = G.gs_scale(s["A"], s["b"], 2, want_norms=False)
     M = G.stencil_from_csr(As, *s["grid"])
     if method == "gmres":
-        return G.gmres(M, bs, m=20, tol=1e-8)
+        return (G.gmres_mixed if mixed else G.gmres)(M, bs, m=20, tol=1e-8)
     return G.bicgstab(M, bs, tol=1e-8)
 
 
-@pytest.mark.parametrize("realtime", [False, True])
-def test_serving_results_equal_solo(G, realtime):
+@pytest.mark.parametrize("realtime,mode", [(False, "lanes"), (True, "lanes"),
+                                           (True, "engine"), (False, "engine-mixed")])
+def test_serving_results_equal_solo(G, realtime, mode):
     import torch
     from paper_0812_2769_amd import serve
     systems = pool(G)
@@ -62,8 +64,12 @@ def test_serving_results_equal_solo(G, realtime):
                           grid=systems[picks[k]]["grid"]) for k in range(n_req)]
     # room for about two systems at a time: admission has to wait for retirements
     rows = sorted(((s["n"] + 255) // 256 * 256 for s in systems), reverse=True)
+    mixed = mode == "engine-mixed"
     srv = serve.Server(rows[0] + rows[1], 4, check_every=8, graph=True,
-                       gmres_rows=max(s["n"] for s in systems), m_max=20)
+                       gmres_rows=max(s["n"] for s in systems), m_max=20,
+                       gmres_mode="lanes" if mode == "lanes" else "engine",
+                       gmres_precision="mixed" if mixed else "fp64",
+                       gmres_engine_rows=2 * (rows[0] + rows[1]), gmres_engine_systems=4)
     done = srv.serve(reqs, realtime=realtime)
     srv.close()
     assert sorted(d.tag for d in done) == list(range(n_req))
@@ -74,7 +80,7 @@ def test_serving_results_equal_solo(G, realtime):
     for d in done:
         key = (int(picks[d.tag]), d.method)
         if key not in ref:
-            x, info = alone(G, systems[key[0]], key[1])
+            x, info = alone(G, systems[key[0]], key[1], mixed)
             ref[key] = (x.cpu().numpy(), info)
         xr, ir = ref[key]
         assert d.info == ir, (d.tag, d.method, d.info, ir)
