@@ -81,6 +81,8 @@ def parse():
                     help="config5: GMRES requests on lanes or in a GMRES engine")
     ap.add_argument("--gmres-precision", choices=["fp64", "mixed"], default="fp64",
                     help="config5 with --gmres-mode engine: the GMRES engine's precision")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="config4: keep the chunk length at 8 instead of measuring it")
     ap.add_argument("--batch-method", choices=["bicgstab", "gmres"], default="bicgstab",
                     help="config4: the engine's solver (GMRES(20) with --precision)")
     ap.add_argument("--batch-count", type=int, default=512,
@@ -199,7 +201,16 @@ def bench_batch(args, gsk, problems, dev):
     mixed = gmres and args.precision == "mixed"
     unit = 512 if mixed else 256
     rows = sum((s["n"] + unit - 1) // unit * unit for s in systems)
-    eng = gsk.Engine(rows, len(systems), check_every=8, graph=True, device=dev,
+    tuned = None
+    check_every = 8
+    if not gmres and not args.no_tune:
+        # chunk length measured on a sample of the batch, before (and outside) the timing
+        from paper_0812_2769_amd import tune
+        tuned = tune.tune_check_every(systems, sample=64, device=dev)
+        check_every = tuned["best"]
+        log(f"chunk length tuned on {tuned['sample']} systems: {tuned['seconds']} -> "
+            f"{check_every}")
+    eng = gsk.Engine(rows, len(systems), check_every=check_every, graph=True, device=dev,
                      method=args.batch_method, m=20, precision="mixed" if mixed else "fp64")
     solver = (f"GMRES(20) {'mixed precision' if mixed else 'FP64'}" if gmres
               else "Bi-CGSTAB")
@@ -270,7 +281,8 @@ def bench_batch(args, gsk, problems, dev):
         "config": {"workload": f"config4: {len(systems)} systems, d in {{2,3}}, N in [32,96], "
                                f"box jump 10^U(2,6), convection U(0,30); GS(2) + {solver} in "
                                f"the engine (HIP-graph chunks of "
-                               f"{'one cycle' if gmres else '8 iterations'}), tol 1e-8",
+                               f"{'one cycle' if gmres else f'{check_every} iterations'}), "
+                               f"tol 1e-8",
                    "rows": sum(s["n"] for s in systems), "systems": len(systems),
                    "dims_3d": sum(1 for s in systems if s["dim"] == 3)},
         "latency_p50_ms": round(1e3 * pct(lats, 0.5), 3),
@@ -285,6 +297,9 @@ def bench_batch(args, gsk, problems, dev):
                     "whole step time (GS, residual and finalize launches, host polls "
                     "included)"},
         "status": status,
+        "chunk_tuning": None if tuned is None else {
+            "chosen": tuned["best"], "sample_systems": tuned["sample"],
+            "seconds": {str(k): round(v, 4) for k, v in tuned["seconds"].items()}},
         "roofline": None, "cpu_baseline": None,
     }
     if not args.no_solo:

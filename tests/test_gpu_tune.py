@@ -1,0 +1,64 @@
+"""The engine's chunk length is a pure scheduling choice: every length gives the same bits, so
+the measured choice (paper_0812_2769_amd.tune) can only change the time, never the result."""
+import numpy as np
+import pytest
+
+from paper_0812_2769_amd import problems
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0812_2769_amd import gsk
+    return gsk
+
+
+def batch(G, count=6):
+    import torch
+    out = []
+    for sp in problems.config4_specs(count, seed=31, n_min=8, n_max=24):
+        P = problems.config4_system(sp)
+        A = G.CsrMatrix.from_problem(P)
+        d = list(P.dims) + [1] * (3 - len(P.dims))
+        out.append({"S": G.stencil_from_csr(A, *d), "b": torch.from_numpy(P.b).cuda(),
+                    "n": P.n})
+    return out
+
+
+def solve(G, systems, k):
+    import torch
+    rows = sum((s["n"] + 255) // 256 * 256 for s in systems)
+    eng = G.Engine(rows, len(systems), check_every=k, graph=True)
+    xs = [torch.zeros_like(s["b"]) for s in systems]
+    for i, s in enumerate(systems):
+        assert eng.submit_gs(s["S"], s["b"], xs[i], p=2, tol=1e-10, tag=i)
+    res = {}
+    while len(res) < len(systems):
+        eng.run(1)
+        res.update(dict(eng.poll(wait=True)))
+    torch.cuda.synchronize()
+    eng.close()
+    return [x.cpu().numpy() for x in xs], res
+
+
+def test_chunk_length_does_not_change_results(G):
+    systems = batch(G)
+    x4, r4 = solve(G, systems, 4)
+    x16, r16 = solve(G, systems, 16)
+    assert r4 == r16
+    for a, b in zip(x4, x16):
+        assert np.array_equal(a, b)
+
+
+def test_tuner_picks_a_candidate(G):
+    from paper_0812_2769_amd import tune
+    systems = batch(G, 4)
+    t = tune.tune_check_every(systems, candidates=(4, 8), sample=4)
+    assert t["best"] in (4, 8) and set(t["seconds"]) == {4, 8}
+    assert all(v > 0 for v in t["seconds"].values())
+    with pytest.raises(ValueError):
+        tune.tune_check_every(systems, candidates=(3,), sample=2)
