@@ -231,7 +231,9 @@ __global__ __launch_bounds__(BS) void k_bicg_p(BArgs a, Op op) {
   const double rhv = a.rh[row];
   typename Op::template Pre<GatherP> pre{};
   if (nrows > 0) pre = op.load(row0, nrows, G);
-  const GatherP::Raw own = G.load(row);
+  GatherP::Raw own;
+  if constexpr (Op::kRowwise) own = pre.centre();   // a stencil row gathers its own entries
+  else own = G.load(row);
   asm volatile("" ::: "memory");   // every load above is issued before anything is combined
   // A CSR product follows indices that are trusted only while the solve runs: test first.
   if constexpr (!Op::kRowwise) {
@@ -289,7 +291,9 @@ __global__ __launch_bounds__(BS) void k_bicg_s(BArgs a, Op op) {
   const double wv = a.W ? a.W[row] : 0.0;
   typename Op::template Pre<GatherS> pre{};
   if (nrows > 0) pre = op.load(row0, nrows, G);
-  const GatherS::Raw own = G.load(row);
+  GatherS::Raw own;
+  if constexpr (Op::kRowwise) own = pre.centre();   // a stencil row gathers its own entries
+  else own = G.load(row);
   asm volatile("" ::: "memory");
   if constexpr (!Op::kRowwise) {
     if (state != ST_RUNNING) return;

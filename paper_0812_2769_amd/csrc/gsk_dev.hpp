@@ -556,6 +556,8 @@ struct StencilOpT {
     V c[7];
     typename G::Raw x[7];
     unsigned present;
+    // The gathered operands of the centre position: a row's own entries (rows of the tile).
+    __device__ const typename G::Raw& centre() const { return x[3]; }
   };
   template <class G>
   __device__ Pre<G> load(int row0, int nrows, const G& g) const {
