@@ -51,9 +51,10 @@ METRIC_C3 = "Arnoldi steps/s, GMRES(30) on the 160^3 checkerboard system"
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; FETCH_SIZE scaled by 2.000 and WRITE_SIZE by
 # 1.000 from a plain 512 MiB copy), recorded with the hash of the kernel sources they were
 # measured on. A source change makes the figure stale and it is reported as null.
-TRAFFIC = {"gmres_a": {"bytes_per_launch": 96180752, "grid": 80, "operator": "stencil",
-                       "sources_sha256_16": "2d3cbe93245f49f5"}}
-TRAFFIC_SOURCES = ["paper_0812_2769_amd/csrc/gmres.hip", "paper_0812_2769_amd/csrc/gsk_dev.hpp"]
+TRAFFIC = {"gmres_a": {"bytes_per_launch": 96119418, "grid": 80, "operator": "stencil",
+                       "sources_sha256_16": "4ce2b697ee4c7e70"}}
+TRAFFIC_SOURCES = ["paper_0812_2769_amd/csrc/gmres.hip", "paper_0812_2769_amd/csrc/gmres_body.hpp",
+                   "paper_0812_2769_amd/csrc/gsk_dev.hpp"]
 
 
 def traffic_for(probe, grid, operator):
