@@ -199,12 +199,12 @@ def bench_batch(args, gsk, problems, dev):
     specs = problems.config4_specs(args.batch_count)
     systems = build_batch_systems(gsk, problems, dev, specs)
     gmres = args.batch_method == "gmres"
-    mixed = gmres and args.precision == "mixed"
+    mixed = args.precision == "mixed"
     unit = 512 if mixed else 256
     rows = sum((s["n"] + unit - 1) // unit * unit for s in systems)
     tuned = None
     check_every = 8
-    if not gmres and not args.no_tune:
+    if not gmres and not mixed and not args.no_tune:
         # chunk length measured on a sample of the batch, before (and outside) the timing
         from paper_0812_2769_amd import tune
         tuned = tune.tune_check_every(systems, sample=64, device=dev)
@@ -214,7 +214,7 @@ def bench_batch(args, gsk, problems, dev):
     eng = gsk.Engine(rows, len(systems), check_every=check_every, graph=True, device=dev,
                      method=args.batch_method, m=20, precision="mixed" if mixed else "fp64")
     solver = (f"GMRES(20) {'mixed precision' if mixed else 'FP64'}" if gmres
-              else "Bi-CGSTAB")
+              else f"Bi-CGSTAB {'mixed precision' if mixed else 'FP64'}")
     xbuf = torch.zeros(sum(s["n"] for s in systems), dtype=torch.float64, device=dev)
     offs = [0]
     for s in systems:
@@ -266,6 +266,13 @@ def bench_batch(args, gsk, problems, dev):
             full, last = divmod(steps, m)
             js = [j for j in range(m)] * full + list(range(last))
             iter_bytes += sum(mat + vb * n * (j + 2) + 2 * vb * n * (j + 3) for j in js)
+        elif mixed:
+            # FP32 planes and r~ r^ p v t, FP64 x: P M + 24 n, S M + 12 n, U 40 n
+            mat = 4.0 * n * planes
+            iter_bytes += info.iters * (2 * mat + 76.0 * n)
+            if info.iters > 0:
+                iter_bytes -= (8.0 * n * (1 + info.restarts)
+                               + (20.0 * n if info.half_step else 0.0))
         else:
             mat = 8.0 * n * planes
             iter_bytes += info.iters * (2 * mat + 136.0 * n)
@@ -303,7 +310,7 @@ def bench_batch(args, gsk, problems, dev):
             "seconds": {str(k): round(v, 4) for k, v in tuned["seconds"].items()}},
         "roofline": None, "cpu_baseline": None,
     }
-    if not args.no_solo:
+    if not args.no_solo and not (mixed and not gmres):
         # the same solves one at a time: gsk_gs_scale + packing + the single solver per system
         log("timing the one-at-a-time path")
         ws_gs = gsk.workspace(gsk.METHOD_GS, 1, 0, dev)

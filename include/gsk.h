@@ -367,6 +367,14 @@ int gsk_engine_submit_gs(gsk_engine* e, const gsk_matrix* A, const double* b, in
                          double tol, const gsk_options* opt, int64_t tag);
 
 /*
+ * Mixed-precision Bi-CGSTAB engines (GSK_METHOD_BICGSTAB with GSK_PRECISION_MIXED): iterative
+ * refinement whose corrections are Bi-CGSTAB runs with FP32 storage of the matrix (a copy the
+ * engine writes into the request's mat32) and of r, r^, p, v, t; x, the true residual
+ * r = b - A x (with the FP64 matrix) and every sum stay FP64. A run ends at a reduction by
+ * inner_reduction of the residual it started from; a refinement step that does not halve the
+ * true residual counts towards GSK_STAGNATED. Not in the paper. Rows are handed out in pairs
+ * of 256-row tiles.
+ *
  * GMRES(m) engines. The same engine runs restarted GMRES(m) with CGS2 Arnoldi (section 2) for
  * many systems at once, in FP64 or with FP32 Arnoldi cycles and FP64 restarts (the iterative
  * refinement of gsk_gmres_mixed). Each system returns bit for bit what gsk_gmres (or
@@ -387,12 +395,16 @@ typedef struct gsk_engine_config {
     int32_t max_systems;   /* system slots                                                  */
     int32_t method;        /* GSK_METHOD_BICGSTAB or GSK_METHOD_GMRES                       */
     int32_t m;             /* GMRES restart length, 1..GSK_MAX_RESTART (ignored otherwise)  */
-    int32_t precision;     /* GMRES: GSK_PRECISION_FP64 or GSK_PRECISION_MIXED; Bi-CGSTAB:
-                              GSK_PRECISION_FP64 (float storage does not pay for Bi-CGSTAB
-                              on these problems; see the design notes)                      */
+    int32_t precision;     /* GSK_PRECISION_FP64, or GSK_PRECISION_MIXED: FP32 storage with
+                              FP64 iterative refinement (GMRES: FP32 Arnoldi cycles; Bi-CGSTAB:
+                              FP32 runs, see inner_reduction)                               */
     int32_t check_every;   /* Bi-CGSTAB: iterations per chunk (1..256, even with
                               GSK_ENGINE_GRAPH); GMRES: ignored (a chunk is one cycle)      */
     int32_t flags;         /* GSK_ENGINE_GRAPH                                              */
+    double inner_reduction; /* mixed Bi-CGSTAB: a run with FP32 storage ends (and the FP64
+                              residual is recomputed) once its estimate has dropped by this
+                              factor below the residual it started from, or below tol;
+                              0 selects 1e-6; otherwise in (0, 1)                           */
 } gsk_engine_config;
 
 /* 0 for an invalid configuration. */

@@ -630,7 +630,10 @@ done:
  *      stored and stays double; x stays double.
  *   3. The run ends (and goes back to 1) when its estimate ||W s|| / ||W r0|| (half step) or
  *      ||W r~|| / ||W r0|| drops below max(tol, delta * rt): a reduction by delta of the
- *      residual it started from is as far as float storage is trusted to go.
+ *      residual it started from is as far as float storage is trusted to go. It also ends
+ *      when the estimate ||W r~|| / ||W r0|| exceeds rt / delta or is not finite: the float
+ *      recurrences have diverged, and the refinement step decides (reading of this build;
+ *      float-storage Bi-CGSTAB can diverge to overflow on the jump problems).
  * Stagnation: a refinement step that does not halve rt counts as a failure; three failures
  * in a row end the solve as STAGNATED. Breakdown tests as in Bi-CGSTAB (R6), on the stored
  * vectors.
@@ -728,7 +731,7 @@ int orc_bicgstab_ir(int n, const int* rp, const int* ci, const double* val, cons
                 ws += e * e;
             }
             est = sqrt(ws) / ref;
-            if (est < target || iters >= maxit) break;
+            if (est < target || iters >= maxit || !(est <= rt / delta)) break;
             rho_old = rho;
             rho = fdot(n, rh, rs);
         }

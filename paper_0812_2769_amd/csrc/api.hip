@@ -376,8 +376,9 @@ static int engine_cfg(const gsk_engine_config* c, gsk::EngineConfig& cfg) {
   if (c->precision != GSK_PRECISION_FP64 && c->precision != GSK_PRECISION_MIXED)
     return set_err(GSK_ERR_INVALID_ARG, "unknown precision");
   const bool gmres = c->method == GSK_METHOD_GMRES;
-  if (!gmres && c->precision != GSK_PRECISION_FP64)
-    return set_err(GSK_ERR_INVALID_ARG, "Bi-CGSTAB engines run in FP64");
+  const double delta = c->inner_reduction == 0.0 ? 1e-6 : c->inner_reduction;
+  if (!gmres && c->precision == GSK_PRECISION_MIXED && !(delta > 0.0 && delta < 1.0))
+    return set_err(GSK_ERR_INVALID_ARG, "inner_reduction must be in (0, 1)");
   if (gmres && (c->m < 1 || c->m > GSK_MAX_RESTART))
     return set_err(GSK_ERR_INVALID_ARG, "m must be in [1, %d]", GSK_MAX_RESTART);
   if (!gmres && (c->check_every < 1 || c->check_every > 256))
@@ -386,9 +387,10 @@ static int engine_cfg(const gsk_engine_config* c, gsk::EngineConfig& cfg) {
   cfg.max_sys = c->max_systems;
   cfg.method = gmres ? 1 : 0;
   cfg.m = gmres ? c->m : 0;
-  cfg.mixed = gmres && c->precision == GSK_PRECISION_MIXED;
+  cfg.mixed = c->precision == GSK_PRECISION_MIXED;
   cfg.check_every = gmres ? 0 : c->check_every;
   cfg.use_graph = (c->flags & GSK_ENGINE_GRAPH) != 0;
+  cfg.delta = delta;
   return GSK_OK;
 }
 
@@ -402,7 +404,7 @@ size_t gsk_engine_workspace_bytes_ex(const gsk_engine_config* c) {
 
 size_t gsk_engine_workspace_bytes(int64_t max_rows, int32_t max_systems) {
   const gsk_engine_config c{max_rows, max_systems, GSK_METHOD_BICGSTAB, 0, GSK_PRECISION_FP64,
-                            8, 0};
+                            8, 0, 0.0};
   return gsk_engine_workspace_bytes_ex(&c);
 }
 
@@ -432,7 +434,7 @@ int gsk_engine_create_ex(const gsk_engine_config* c, void* ws, size_t ws_bytes, 
 int gsk_engine_create(void* ws, size_t ws_bytes, int64_t max_rows, int32_t max_systems,
                       int32_t check_every, int32_t flags, void* stream, gsk_engine** out) {
   const gsk_engine_config c{max_rows, max_systems, GSK_METHOD_BICGSTAB, 0, GSK_PRECISION_FP64,
-                            check_every, flags};
+                            check_every, flags, 0.0};
   return gsk_engine_create_ex(&c, ws, ws_bytes, stream, out);
 }
 
@@ -453,13 +455,13 @@ int gsk_engine_submit_ex(gsk_engine* e, const gsk_engine_request* r) {
     if (r->opt && r->opt->stop_weights)
       return set_err(GSK_ERR_INVALID_ARG, "opt->stop_weights must be NULL with a GS stage");
   }
-  const bool mixed = e->method == GSK_METHOD_GMRES && e->precision == GSK_PRECISION_MIXED;
+  const bool mixed = e->precision == GSK_PRECISION_MIXED;
   if (mixed) {
     if (!r->mat32) return set_err(GSK_ERR_INVALID_ARG, "a mixed engine needs mat32");
     if (M.kind == gsk::MAT_STENCIL && r->mat32_ld < M.n)
       return set_err(GSK_ERR_INVALID_ARG, "mat32_ld must be >= n");
   } else if (r->mat32) {
-    return set_err(GSK_ERR_INVALID_ARG, "mat32 is only for mixed GMRES engines");
+    return set_err(GSK_ERR_INVALID_ARG, "mat32 is only for mixed-precision engines");
   }
   SolveParams prm;
   rc = params_from(r->opt, prm, r->tol);
@@ -577,7 +579,7 @@ int gsk_bicgstab_batch(int32_t count, const gsk_matrix* A, const double* const* 
   int rc = params_from(opt, prm, tol);
   if (rc) return rc;
   const int64_t rows = batch_rows(count, n.data());
-  const gsk::EngineConfig cfg{rows, count, 0, 0, false, prm.check_every, false};
+  const gsk::EngineConfig cfg{rows, count, 0, 0, false, prm.check_every, false, 1e-6};
   rc = check_ws(ws, ws_bytes, gsk::engine_workspace_bytes(cfg));
   if (rc) return rc;
   gsk::Engine* e = nullptr;

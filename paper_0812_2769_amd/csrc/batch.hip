@@ -32,14 +32,6 @@
 
 namespace gsk {
 
-// Per-system control block (the Bi-CGSTAB part of Ctl).
-struct BCtl {
-  Summary sum;
-  int maxit, first, has_w, bad;
-  double tol, eps_b, ref;
-  double rho, rho_old, alpha, omega, beta, rh_norm;
-};
-
 struct BArgsB {
   const SysDesc* sys;
   const int* act;        // [2][max_tiles]: tiles of the admitted systems, then their slots
@@ -126,6 +118,8 @@ __global__ __launch_bounds__(64) void k_batch_init(BCtl* c, int maxit, double to
   c->eps_b = eps_b;
   c->ref = 0.0;
   c->rho = c->rho_old = c->alpha = c->omega = c->beta = c->rh_norm = 0.0;
+  c->target = tol;
+  c->last_rt = 1.0;
 }
 
 // Flat validity scan of one system's CSR structure (no indirect loads): row_ptr[0] == 0,
@@ -457,7 +451,7 @@ struct EngineLayout {
   size_t sys, tiles, ctl, sums, partials, vecs, total;
 };
 
-static int units_of(const EngineConfig& cfg) { return cfg.method == 1 && cfg.mixed ? 2 : 1; }
+static int units_of(const EngineConfig& cfg) { return cfg.mixed ? 2 : 1; }
 
 // Workspace carve-up. Bi-CGSTAB: system table, unit list, control blocks, partials (4 per
 // tile), the 7 vectors. GMRES: system table, unit list, control blocks, status copies,
@@ -515,6 +509,9 @@ struct Engine {
   bool column = true;              // GMRES basis fits one buffer descriptor
   BArgsB args{};
   GArgs gargs{};
+  MArgs margs{};
+  SysDesc* d_sys = nullptr;        // device system table and unit list (any method)
+  int* d_list = nullptr;
   // host state
   std::vector<SysDesc> h_sys;
   std::vector<int64_t> tags;
@@ -599,7 +596,7 @@ int engine_create(void* ws, size_t ws_bytes, const EngineConfig& cfg, hipStream_
   e->use_graph = cfg.use_graph;
   e->method = cfg.method;
   e->m = cfg.m;
-  e->mixed = cfg.method == 1 && cfg.mixed;
+  e->mixed = cfg.mixed;
   e->rv = units_of(cfg);
   e->max_units = e->grid_tiles / e->rv;
   const int max_sys = cfg.max_sys;
@@ -622,6 +619,28 @@ int engine_create(void* ws, size_t ws_bytes, const EngineConfig& cfg, hipStream_
     g.mixed = e->mixed ? 1 : 0;
     e->column = e->mixed ? fits_buffer<float>(g.ldv, cfg.m + 1)
                          : fits_buffer<double>(g.ldv, cfg.m + 1);
+  } else if (e->mixed) {
+    MArgs& a = e->margs;
+    a.sys = reinterpret_cast<const SysDesc*>(base + L.sys);
+    a.act = reinterpret_cast<const int*>(base + L.tiles);
+    a.n_act = a.act + 2 * (size_t)e->max_units;
+    a.ctl = reinterpret_cast<BCtl*>(base + L.ctl);
+    a.partials = reinterpret_cast<double*>(base + L.partials);
+    a.pstride = e->grid_tiles;
+    a.max_units = e->max_units;
+    const size_t vb = align256(sizeof(double) * (size_t)e->grid_tiles * BS);
+    float* v[kBatchVectors];
+    for (int i = 0; i < kBatchVectors; ++i) v[i] = reinterpret_cast<float*>(base + L.vecs + i * vb);
+    a.r = v[0];
+    a.rh = v[1];
+    a.p[0] = v[2];
+    a.p[1] = v[3];
+    a.v[0] = v[4];
+    a.v[1] = v[5];
+    a.t = v[6];
+    a.delta = cfg.delta;
+    a.par = 0;
+    e->args.ctl = a.ctl;   // status read-back
   } else {
     BArgsB& a = e->args;
     a.sys = reinterpret_cast<const SysDesc*>(base + L.sys);
@@ -643,6 +662,8 @@ int engine_create(void* ws, size_t ws_bytes, const EngineConfig& cfg, hipStream_
     a.t = v[6];
     a.par = 0;
   }
+  e->d_sys = reinterpret_cast<SysDesc*>(base + L.sys);
+  e->d_list = reinterpret_cast<int*>(base + L.tiles);
   e->h_sys.assign(max_sys, SysDesc{});
   e->tags.assign(max_sys, 0);
   e->active.assign(max_sys, 0);
@@ -657,7 +678,7 @@ int engine_create(void* ws, size_t ws_bytes, const EngineConfig& cfg, hipStream_
   if (ok && e->method == 1)
     ok = hipHostMalloc((void**)&e->p_sums, sizeof(Summary) * max_sys, hipHostMallocDefault) ==
          hipSuccess;
-  if (ok && e->method == 0)
+  if (ok && e->method == 0)   // FP64 and mixed Bi-CGSTAB share the control block layout
     ok = hipHostMalloc((void**)&e->p_ctl, sizeof(BCtl) * max_sys, hipHostMallocDefault) ==
          hipSuccess;
   if (!ok) {
@@ -783,10 +804,9 @@ static int upload(Engine& e) {
   }
   e.p_tiles[2 * (size_t)e.max_units] = n;
   e.n_listed = n;
-  if (hipMemcpyAsync(const_cast<SysDesc*>(e.method == 1 ? e.gargs.sys : e.args.sys), e.p_sys,
-                     sizeof(SysDesc) * e.max_sys,
+  if (hipMemcpyAsync(e.d_sys, e.p_sys, sizeof(SysDesc) * e.max_sys,
                      hipMemcpyHostToDevice, e.s) != hipSuccess ||
-      hipMemcpyAsync(const_cast<int*>(e.method == 1 ? e.gargs.act : e.args.act), e.p_tiles,
+      hipMemcpyAsync(e.d_list, e.p_tiles,
                      sizeof(int) * (2 * (size_t)e.max_units + 1), hipMemcpyHostToDevice,
                      e.s) != hipSuccess ||
       hipEventRecord(e.ev_upload, e.s) != hipSuccess)
@@ -799,6 +819,10 @@ static int upload(Engine& e) {
 static void enqueue_chunk(Engine& e, int k, int64_t first_iter, int grid) {
   if (e.method == 1) {
     (void)launch_gmres_chunk(e.gargs, e.m, grid, e.max_sys, e.column, e.s);
+    return;
+  }
+  if (e.mixed) {
+    (void)launch_bicg_mixed_chunk(e.margs, k, first_iter, grid, e.max_sys, e.s);
     return;
   }
   const dim3 gt(grid), gs(e.max_sys), block(BS);

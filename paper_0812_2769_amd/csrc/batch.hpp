@@ -26,6 +26,17 @@ struct SysDesc {
   size_t ldp32;           // plane stride of mat32 for a stencil matrix
 };
 
+// Per-system control block of a Bi-CGSTAB engine (the Bi-CGSTAB part of Ctl). target and
+// last_rt serve the mixed-precision form: the run's stop level max(tol, delta * rt) and the
+// relative true residual rt its run started from.
+struct BCtl {
+  Summary sum;
+  int maxit, first, has_w, bad;
+  double tol, eps_b, ref;
+  double rho, rho_old, alpha, omega, beta, rh_norm;
+  double target, last_rt;
+};
+
 // Bits of rejected system data: invalid CSR structure, zero row, non-finite data (GS stage).
 enum : int { BAD_CSR = 1, BAD_ZERO = 2, BAD_NONFINITE = 4 };
 
@@ -86,6 +97,29 @@ struct GArgs {
   double zero;           // 0.0, passed at run time (see gmres.hip)
   int mixed;             // FP32 data with FP64 restarts
 };
+
+// Arguments of the mixed-precision Bi-CGSTAB engine's launches (FP32 vectors in the engine's
+// row space, the FP32 matrix copy in the caller's memory).
+struct MArgs {
+  const SysDesc* sys;
+  const int* act;        // [2][max_units]
+  const int* n_act;
+  BCtl* ctl;
+  double* partials;      // [4][pstride], per tile
+  int pstride;
+  int max_units;
+  float* r;              // stored residual r~
+  float* rh;
+  float* p[2];
+  float* v[2];
+  float* t;
+  double delta;          // a run ends at a reduction by delta of the residual it started from
+  int par;
+};
+
+// Enqueues one mixed-precision Bi-CGSTAB chunk (preparation, residual, k iterations).
+hipError_t launch_bicg_mixed_chunk(MArgs a, int k, int64_t first_iter, int grid, int max_sys,
+                                   hipStream_t s);
 
 // Enqueues one GMRES chunk (one cycle of m steps for every running system, with the
 // preparation, start, x update and restart launches around it) with streaming grid `grid`.

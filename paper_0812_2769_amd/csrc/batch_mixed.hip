@@ -1,0 +1,459 @@
+// Mixed-precision Bi-CGSTAB in the batch engine: iterative refinement whose corrections are
+// Bi-CGSTAB runs with FP32 storage (not in the paper, which solves in FP64 throughout; the
+// oracle's orc_bicgstab_ir is the definition followed here).
+//
+//   1. r = b - A x in FP64 with the FP64 scaled matrix; rt = ||W r|| / ||W r0||; the solve
+//      stops when rt < tol.
+//   2. A run of Bi-CGSTAB restarts from r: the stored residual r~ and the shadow residual r^
+//      are r rounded to FP32. The matrix (an FP32 copy), r~, r^, p, v and t are stored as
+//      FP32; every product, dot product and update is computed in FP64 from the stored values
+//      and rounded to FP32 when it is stored. s = r~ - alpha v is not stored and stays FP64;
+//      x stays FP64.
+//   3. The run ends (back to 1) when its estimate ||W s|| / ||W r0|| (half step) or
+//      ||W r~|| / ||W r0|| drops below max(tol, delta rt), and also when ||W r~|| / ||W r0||
+//      exceeds rt / delta or is not finite (the float recurrences have diverged; they can,
+//      to overflow, on the jump problems).
+//   A refinement step that does not halve rt counts as a failure; three in a row end the solve
+//   as STAGNATED. Breakdown tests as in FP64 Bi-CGSTAB, on the stored vectors.
+//
+// Workgroups take units of two 256-row tiles (FP32 loads carry half the bytes, so a thread
+// keeps two rows' loads in flight); partial sums stay per tile, so each system's finalize
+// reduces its tiles in order. Float storage costs Bi-CGSTAB iterations on the paper's jump
+// problems (each restart discards the Krylov space); this form exists to measure that on the
+// device beside the FP64 engine.
+#include "batch.hpp"
+
+namespace gsk {
+
+template <class Body>
+__device__ inline void on_unit(const MArgs& a, Body body) {
+  const int k = logical_block();
+  if (k < *a.n_act) body(a.act[k], a.act[a.max_units + k]);
+}
+
+// p = fl(r~ + beta (p - omega v)), or r~ on the first iteration of a run.
+struct GatherPM {
+  const float* __restrict__ r;
+  const float* __restrict__ p;
+  const float* __restrict__ v;
+  double beta, omega;
+  int first;
+  struct Raw {
+    float r, p, v;
+  };
+  __device__ Raw load(int col) const { return Raw{r[col], p[col], v[col]}; }
+  __device__ double value(const Raw& a) const {
+    if (first) return (double)a.r;
+    return (double)(float)fma(beta, fma(-omega, (double)a.v, (double)a.p), (double)a.r);
+  }
+  __device__ double operator()(int col) const { return value(load(col)); }
+};
+
+// s = r~ - alpha v (FP64, not stored).
+struct GatherSM {
+  const float* __restrict__ r;
+  const float* __restrict__ v;
+  double alpha;
+  struct Raw {
+    float r, v;
+  };
+  __device__ Raw load(int col) const { return Raw{r[col], v[col]}; }
+  __device__ double value(const Raw& a) const { return fma(-alpha, (double)a.v, (double)a.r); }
+  __device__ double operator()(int col) const { return value(load(col)); }
+};
+
+// The FP32 product over the two tiles of a unit: y[k] for rows row0[k] .. row0[k] + nr[k].
+// Stencil: both tiles' operands are loaded before either sum; CSR: one tile at a time.
+template <class G>
+__device__ inline void unit_product(const SysDesc& d, const int (&row0)[2], const int (&nr)[2],
+                                    const G& g, TileLds& L, double (&y)[2]) {
+  if (d.kind == MAT_STENCIL) {
+    const StencilOpT<float> op{d.mat32, d.n, d.nx, d.ny, d.nz, d.ldp32};
+    typename StencilOpT<float>::template Pre<G> pre[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) pre[k] = op.load(row0[k], nr[k], g);
+    EmptyLds e;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) y[k] = op.finish(pre[k], row0[k], nr[k], g, e);
+  } else {
+    const CsrOpT<float> op{d.rp, d.ci, d.mat32};
+    for (int k = 0; k < 2; ++k) {
+      if (k) __syncthreads();
+      y[k] = nr[k] > 0 ? op.tile(row0[k], nr[k], g, L) : 0.0;
+    }
+  }
+}
+
+__device__ inline void unit_rows(const SysDesc& d, int unit, int& lt0, int (&row0)[2],
+                                 int (&nr)[2]) {
+  lt0 = (unit - d.unit_off) * 2;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    row0[k] = (lt0 + k) * BS;
+    nr[k] = max(0, min(BS, d.n - row0[k]));
+  }
+}
+
+__global__ __launch_bounds__(BS) void k_bm_prepare(MArgs a) {
+  __shared__ GsLds L;
+  on_unit(a, [&](int unit, int s) {
+    const SysDesc d = a.sys[s];
+    BCtl* c = a.ctl + s;
+    if (c->sum.state != ST_SCALE || (c->bad & BAD_CSR)) return;
+    const int lt0 = (unit - d.unit_off) * 2;
+    for (int k = 0; k < 2; ++k) {
+      if (lt0 + k >= d.ntiles) break;
+      prepare_tile(d, lt0 + k, L, &c->bad);
+      __syncthreads();
+    }
+  });
+}
+
+__global__ __launch_bounds__(64) void k_bm_fin_prepare(MArgs a) {
+  const int s = blockIdx.x;
+  if (threadIdx.x != 0 || a.sys[s].ntiles == 0) return;
+  BCtl* c = a.ctl + s;
+  if (c->sum.state == ST_SCALE) c->sum.state = ST_INIT;
+}
+
+// R: r = b - A x (FP64 matrix), r~ = r^ = fl(r) when a run starts; partials ||r||^2,
+// ||W r||^2, ||r~||^2 per tile.
+__global__ __launch_bounds__(BS) void k_bm_residual(MArgs a) {
+  __shared__ TileLds L;
+  __shared__ double red[NC_MAX * WAVES];
+  on_unit(a, [&](int unit, int s) {
+    const SysDesc d = a.sys[s];
+    BCtl* c = a.ctl + s;
+    const int st = c->sum.state;
+    if (st != ST_INIT && st != ST_VERIFY && st != ST_FINAL) return;
+    if (c->bad) return;
+    const int lt0 = (unit - d.unit_off) * 2;
+    const int t = threadIdx.x;
+    for (int k = 0; k < 2; ++k) {
+      const int row0 = (lt0 + k) * BS;
+      const int nrows = min(BS, d.n - row0);
+      if (nrows <= 0) break;
+      if (k) __syncthreads();
+      double y;
+      if (d.kind == MAT_STENCIL) {
+        EmptyLds e;
+        y = StencilOp{d.coef, d.n, d.nx, d.ny, d.nz, (size_t)d.n}.tile(row0, nrows, GatherX{d.x}, e);
+      } else {
+        y = CsrOp{d.rp, d.ci, d.val}.tile(row0, nrows, GatherX{d.x}, L);
+      }
+      double acc[3] = {0.0, 0.0, 0.0};
+      if (t < nrows) {
+        const int row = row0 + t;
+        const double r = d.b[row] - y;
+        const float rs = (float)r;
+        if (st != ST_FINAL) {
+          a.r[d.row_off + row] = rs;
+          a.rh[d.row_off + row] = rs;
+        }
+        acc[0] = r * r;
+        if (d.W) {
+          const double wr = d.W[row] * r;
+          acc[1] = wr * wr;
+        }
+        acc[2] = (double)rs * (double)rs;
+      }
+      block_partials<3>(acc, 3, a.partials, a.pstride, d.tile_off + lt0 + k, red);
+    }
+  });
+}
+
+// FR: convergence test on the FP64 residual, refinement bookkeeping, start of a run.
+__global__ __launch_bounds__(BS) void k_bm_fin_residual(MArgs a) {
+  const int s = blockIdx.x;
+  const SysDesc d = a.sys[s];
+  if (d.ntiles == 0) return;
+  BCtl* c = a.ctl + s;
+  const int st = c->sum.state;
+  if (st != ST_INIT && st != ST_VERIFY && st != ST_FINAL) return;
+  if (c->bad) {
+    if (threadIdx.x == 0) {
+      c->sum.state = ST_DONE;
+      c->sum.status = bad_status(c->bad);
+    }
+    return;
+  }
+  __shared__ double out[8];
+  small_sums_strided<3>(a.partials + d.tile_off, d.ntiles, a.pstride, out);
+  if (threadIdx.x != 0) return;
+  const double nr = sqrt(out[0]);
+  const double nwr = d.W ? sqrt(out[1]) : nr;
+  const double ns = sqrt(out[2]);
+  double rt = 1.0;
+  if (st == ST_INIT) {
+    c->ref = nwr;
+    if (nwr == 0.0) {
+      c->sum.status = S_CONVERGED;
+      c->sum.relres_rec = 0.0;
+      c->sum.relres_true = 0.0;
+      c->sum.state = ST_DONE;
+      return;
+    }
+    if (c->maxit == 0) {
+      c->sum.status = S_MAXIT;
+      c->sum.state = ST_DONE;
+      return;
+    }
+  } else {
+    rt = nwr / c->ref;
+    c->sum.relres_true = rt;
+    if (st == ST_FINAL) {
+      c->sum.state = ST_DONE;
+      return;
+    }
+    if (rt < c->tol) {
+      c->sum.status = S_CONVERGED;
+      c->sum.state = ST_DONE;
+      return;
+    }
+    if (c->sum.iters >= c->maxit) {
+      c->sum.status = S_MAXIT;
+      c->sum.state = ST_DONE;
+      return;
+    }
+    if (!(rt < 0.5 * c->last_rt)) {
+      c->sum.fails += 1;
+      if (c->sum.fails >= 3) {
+        c->sum.status = S_STAGNATED;
+        c->sum.state = ST_DONE;
+        return;
+      }
+    } else {
+      c->sum.fails = 0;
+    }
+    c->sum.restarts += 1;
+  }
+  c->last_rt = rt;
+  c->target = a.delta * rt > c->tol ? a.delta * rt : c->tol;
+  c->rh_norm = ns;
+  c->rho = out[2];
+  c->sum.half = 0;
+  if (fabs(c->rho) <= c->eps_b * ns * ns) {
+    c->sum.status = S_BREAKDOWN;
+    c->sum.brk = BRK_RHO;
+    c->sum.state = ST_DONE;
+    return;
+  }
+  c->first = 1;
+  c->sum.state = ST_RUNNING;
+}
+
+// P: p (stored FP32), v = fl(A p); partials (r^, v), ||v||^2.
+__global__ __launch_bounds__(BS) void k_bm_p(MArgs a) {
+  __shared__ TileLds L;
+  __shared__ double red[NC_MAX * WAVES];
+  on_unit(a, [&](int unit, int s) {
+    const SysDesc d = a.sys[s];
+    BCtl* c = a.ctl + s;
+    if (c->sum.state != ST_RUNNING) return;
+    const int q = a.par;
+    const int64_t o = d.row_off;
+    const GatherPM G{a.r + o, a.p[q] + o, a.v[q] + o, c->beta, c->omega, c->first};
+    int lt0, row0[2], nr[2];
+    unit_rows(d, unit, lt0, row0, nr);
+    double y[2];
+    unit_product(d, row0, nr, G, L, y);
+    const int t = threadIdx.x;
+    for (int k = 0; k < 2; ++k) {
+      if (nr[k] <= 0) break;
+      if (k) __syncthreads();
+      double acc[2] = {0.0, 0.0};
+      if (t < nr[k]) {
+        const int row = row0[k] + t;
+        a.p[q ^ 1][o + row] = (float)G(row);
+        const float vs = (float)y[k];
+        a.v[q ^ 1][o + row] = vs;
+        acc[0] = (double)a.rh[o + row] * (double)vs;
+        acc[1] = (double)vs * (double)vs;
+      }
+      block_partials<2>(acc, 2, a.partials, a.pstride, d.tile_off + lt0 + k, red);
+    }
+  });
+}
+
+__global__ __launch_bounds__(BS) void k_bm_fin_p(MArgs a) {
+  const int s = blockIdx.x;
+  const SysDesc d = a.sys[s];
+  if (d.ntiles == 0) return;
+  BCtl* c = a.ctl + s;
+  if (c->sum.state != ST_RUNNING) return;
+  __shared__ double out[8];
+  small_sums_strided<2>(a.partials + d.tile_off, d.ntiles, a.pstride, out);
+  if (threadIdx.x != 0) return;
+  const double sigma = out[0];
+  const double vn = sqrt(out[1]);
+  if (fabs(sigma) <= c->eps_b * c->rh_norm * vn) {
+    c->sum.status = S_BREAKDOWN;
+    c->sum.brk = BRK_SIGMA;
+    c->sum.state = ST_FINAL;
+    return;
+  }
+  c->alpha = c->rho / sigma;
+}
+
+// S: t = fl(A s) with s = r~ - alpha v; partials (t, s), (t, t), ||s||^2, ||W s||^2.
+__global__ __launch_bounds__(BS) void k_bm_s(MArgs a) {
+  __shared__ TileLds L;
+  __shared__ double red[NC_MAX * WAVES];
+  on_unit(a, [&](int unit, int s) {
+    const SysDesc d = a.sys[s];
+    BCtl* c = a.ctl + s;
+    if (c->sum.state != ST_RUNNING) return;
+    const int64_t o = d.row_off;
+    const GatherSM G{a.r + o, a.v[a.par ^ 1] + o, c->alpha};
+    int lt0, row0[2], nr[2];
+    unit_rows(d, unit, lt0, row0, nr);
+    double y[2];
+    unit_product(d, row0, nr, G, L, y);
+    const int t = threadIdx.x;
+    for (int k = 0; k < 2; ++k) {
+      if (nr[k] <= 0) break;
+      if (k) __syncthreads();
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      if (t < nr[k]) {
+        const int row = row0[k] + t;
+        const double sv = G(row);
+        const float ts = (float)y[k];
+        a.t[o + row] = ts;
+        acc[0] = (double)ts * sv;
+        acc[1] = (double)ts * (double)ts;
+        acc[2] = sv * sv;
+        if (d.W) {
+          const double ws = d.W[row] * sv;
+          acc[3] = ws * ws;
+        }
+      }
+      block_partials<4>(acc, 4, a.partials, a.pstride, d.tile_off + lt0 + k, red);
+    }
+  });
+}
+
+__global__ __launch_bounds__(BS) void k_bm_fin_s(MArgs a) {
+  const int s = blockIdx.x;
+  const SysDesc d = a.sys[s];
+  if (d.ntiles == 0) return;
+  BCtl* c = a.ctl + s;
+  if (c->sum.state != ST_RUNNING) return;
+  __shared__ double out[8];
+  small_sums_strided<4>(a.partials + d.tile_off, d.ntiles, a.pstride, out);
+  if (threadIdx.x != 0) return;
+  c->sum.iters += 1;
+  const double sn = sqrt(out[2]);
+  const double est = (d.W ? sqrt(out[3]) : sn) / c->ref;
+  c->sum.relres_rec = est;
+  if (est < c->target) {
+    c->sum.half = 1;
+    c->sum.state = ST_HALF;
+    return;
+  }
+  const double ts = out[0], tt = out[1];
+  if (fabs(ts) <= c->eps_b * sqrt(tt) * sn) {
+    c->sum.status = S_BREAKDOWN;
+    c->sum.brk = BRK_OMEGA;
+    c->sum.state = ST_FINAL;
+    return;
+  }
+  c->omega = ts / tt;
+}
+
+// U: x += alpha p + omega s (FP64 x), r~ = fl(s - omega t); partials (r^, r~), ||r~||^2,
+// ||W r~||^2. After a half-step exit only x += alpha p.
+__global__ __launch_bounds__(BS) void k_bm_u(MArgs a) {
+  __shared__ double red[NC_MAX * WAVES];
+  on_unit(a, [&](int unit, int s) {
+    const SysDesc d = a.sys[s];
+    BCtl* c = a.ctl + s;
+    const int st = c->sum.state;
+    if (st != ST_RUNNING && st != ST_HALF) return;
+    const int q = a.par ^ 1;
+    const int64_t o = d.row_off;
+    const float* p = a.p[q] + o;
+    const float* v = a.v[q] + o;
+    const double alpha = c->alpha, omega = c->omega;
+    const int lt0 = (unit - d.unit_off) * 2;
+    for (int k = 0; k < 2; ++k) {
+      const int r0 = (lt0 + k) * BS;
+      if (r0 >= d.n) break;
+      const int row = r0 + threadIdx.x;
+      const bool mine = row < d.n;
+      if (st == ST_HALF) {
+        if (mine) d.x[row] = fma(alpha, (double)p[row], d.x[row]);
+        continue;
+      }
+      if (k) __syncthreads();
+      double acc[3] = {0.0, 0.0, 0.0};
+      if (mine) {
+        const double sv = fma(-alpha, (double)v[row], (double)a.r[o + row]);
+        d.x[row] = fma(omega, sv, fma(alpha, (double)p[row], d.x[row]));
+        const float rs = (float)fma(-omega, (double)a.t[o + row], sv);
+        a.r[o + row] = rs;
+        acc[0] = (double)a.rh[o + row] * (double)rs;
+        acc[1] = (double)rs * (double)rs;
+        if (d.W) {
+          const double wr = d.W[row] * (double)rs;
+          acc[2] = wr * wr;
+        }
+      }
+      block_partials<3>(acc, 3, a.partials, a.pstride, d.tile_off + lt0 + k, red);
+    }
+  });
+}
+
+__global__ __launch_bounds__(BS) void k_bm_fin_u(MArgs a) {
+  const int s = blockIdx.x;
+  const SysDesc d = a.sys[s];
+  if (d.ntiles == 0) return;
+  BCtl* c = a.ctl + s;
+  const int st = c->sum.state;
+  if (st != ST_RUNNING && st != ST_HALF) return;
+  if (st == ST_HALF) {
+    if (threadIdx.x == 0) c->sum.state = ST_VERIFY;
+    return;
+  }
+  __shared__ double out[8];
+  small_sums_strided<3>(a.partials + d.tile_off, d.ntiles, a.pstride, out);
+  if (threadIdx.x != 0) return;
+  const double rn = sqrt(out[1]);
+  const double est = (d.W ? sqrt(out[2]) : rn) / c->ref;
+  c->sum.relres_rec = est;
+  if (est < c->target || c->sum.iters >= c->maxit || !(est <= c->last_rt / a.delta)) {
+    c->sum.state = ST_VERIFY;
+    return;
+  }
+  const double rho_new = out[0];
+  if (fabs(rho_new) <= c->eps_b * c->rh_norm * rn) {
+    c->sum.status = S_BREAKDOWN;
+    c->sum.brk = BRK_RHO;
+    c->sum.state = ST_FINAL;
+    return;
+  }
+  c->beta = (rho_new / c->rho) * (c->alpha / c->omega);
+  c->rho_old = c->rho;
+  c->rho = rho_new;
+  c->first = 0;
+}
+
+hipError_t launch_bicg_mixed_chunk(MArgs a, int k, int64_t first_iter, int grid, int max_sys,
+                                   hipStream_t s) {
+  const dim3 gt(grid), gs(max_sys), block(BS);
+  hipLaunchKernelGGL(k_bm_prepare, gt, block, 0, s, a);
+  hipLaunchKernelGGL(k_bm_fin_prepare, gs, dim3(64), 0, s, a);
+  hipLaunchKernelGGL(k_bm_residual, gt, block, 0, s, a);
+  hipLaunchKernelGGL(k_bm_fin_residual, gs, block, 0, s, a);
+  for (int it = 0; it < k; ++it) {
+    a.par = (int)((first_iter + it) & 1);
+    hipLaunchKernelGGL(k_bm_p, gt, block, 0, s, a);
+    hipLaunchKernelGGL(k_bm_fin_p, gs, block, 0, s, a);
+    hipLaunchKernelGGL(k_bm_s, gt, block, 0, s, a);
+    hipLaunchKernelGGL(k_bm_fin_s, gs, block, 0, s, a);
+    hipLaunchKernelGGL(k_bm_u, gt, block, 0, s, a);
+    hipLaunchKernelGGL(k_bm_fin_u, gs, block, 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gsk

@@ -117,9 +117,10 @@ struct EngineConfig {
   int max_sys;
   int method;        // 0 Bi-CGSTAB, 1 GMRES(m)
   int m;             // GMRES restart length
-  bool mixed;        // GMRES: FP32 Arnoldi cycles, FP64 restarts
+  bool mixed;        // FP32 storage with FP64 refinement (GMRES cycles or Bi-CGSTAB runs)
   int check_every;   // Bi-CGSTAB: iterations per chunk
   bool use_graph;
+  double delta;      // mixed Bi-CGSTAB: reduction that ends a run (refinement step)
 };
 size_t engine_workspace_bytes(const EngineConfig& cfg);
 // 0 ok, -4 workspace too small, -1 invalid arguments, -5 HIP failure.

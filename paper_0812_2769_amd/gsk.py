@@ -85,7 +85,8 @@ PRECISION_FP64, PRECISION_MIXED = 0, 1
 class EngineConfig(ctypes.Structure):
     _fields_ = [("max_rows", ctypes.c_int64), ("max_systems", ctypes.c_int32),
                 ("method", ctypes.c_int32), ("m", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("inner_reduction", ctypes.c_double)]
 
 
 class EngineRequest(ctypes.Structure):
@@ -468,14 +469,14 @@ def _vec_ld(n: int) -> int:
 
 
 class Engine:
-    """The batch engine with continuous admission (gsk_engine_*): Bi-CGSTAB, or GMRES(m) in FP64
-    or mixed precision (FP32 Arnoldi cycles, FP64 restarts). Systems are submitted with device
+    """The batch engine with continuous admission (gsk_engine_*): Bi-CGSTAB or GMRES(m), in FP64
+    or mixed precision (FP32 storage, FP64 refinement). Systems are submitted with device
     tensors that must stay alive until the system is reported by poll(); results are
     (tag, Info) pairs. The engine's vectors live in a workspace tensor it owns."""
 
     def __init__(self, max_rows: int, max_systems: int, check_every: int = 8,
                  graph: bool = False, device="cuda", stream=None, method: str = "bicgstab",
-                 m: int = 20, precision: str = "fp64"):
+                 m: int = 20, precision: str = "fp64", inner_reduction: float = 0.0):
         self.device = torch.device(device)
         self.stream = stream if stream is not None else (
             torch.cuda.Stream(self.device) if graph else torch.cuda.current_stream(self.device))
@@ -487,7 +488,8 @@ class Engine:
                            METHOD_GMRES if method == "gmres" else METHOD_BICGSTAB,
                            self.m if method == "gmres" else 0,
                            PRECISION_MIXED if self.mixed else PRECISION_FP64,
-                           int(check_every), ENGINE_GRAPH if graph else 0)
+                           int(check_every), ENGINE_GRAPH if graph else 0,
+                           float(inner_reduction))
         nbytes = int(lib.gsk_engine_workspace_bytes_ex(ctypes.byref(cfg)))
         if nbytes == 0:
             raise GskError(ERR_INVALID_ARG, "no engine workspace size for this configuration")

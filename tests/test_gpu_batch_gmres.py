@@ -195,4 +195,4 @@ def test_gmres_engine_arguments(G):
         G.Engine(1024, 4, method="gmres", m=G.MAX_RESTART + 1 if hasattr(G, "MAX_RESTART")
                  else 65)
     with pytest.raises(G.GskError):
-        G.Engine(1024, 4, method="bicgstab", precision="mixed")
+        G.Engine(1024, 4, method="bicgstab", precision="mixed", inner_reduction=1.5)

@@ -82,3 +82,17 @@ def test_float_storage_costs_iterations_on_jump_problems():
         it64 += i64.iters
         itir += iir.iters
     assert itir > 1.2 * it64, (itir, it64)
+
+
+def test_divergence_ends_runs_and_stagnates():
+    # Float-storage Bi-CGSTAB diverges to overflow on this GS(1)-scaled 2D jump system; the
+    # run ends once its estimate exceeds rt / delta, and three refinement steps without
+    # progress end the solve as stagnated with a finite residual (instead of 10,000 NaN
+    # iterations). FP64 Bi-CGSTAB converges on the same system.
+    P = problems.config4_system(problems.config4_specs(1, seed=47, n_min=12, n_max=20)[0])
+    S, w = scaled(P, 1)
+    _, i64 = oracle.bicgstab(S, S.b, tol=1e-10, weights=w)
+    assert i64.status == oracle.CONVERGED
+    _, iir = oracle.bicgstab_ir(S, S.b, tol=1e-10, delta=1e-6, weights=w)
+    assert iir.status == oracle.STAGNATED and iir.verify_failures == 3
+    assert np.isfinite(iir.relres_true) and iir.iters < 10000
