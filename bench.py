@@ -82,8 +82,12 @@ def parse():
                     help="config5: GMRES requests on lanes or in a GMRES engine")
     ap.add_argument("--gmres-precision", choices=["fp64", "mixed"], default="fp64",
                     help="config5 with --gmres-mode engine: the GMRES engine's precision")
+    ap.add_argument("--tile-units", type=int, default=0,
+                    help="config4: tiles per workgroup (1 or 2) instead of measuring")
+    ap.add_argument("--chunk", type=int, default=0,
+                    help="config4: iterations per chunk instead of measuring")
     ap.add_argument("--no-tune", action="store_true",
-                    help="config4: keep the chunk length at 8 instead of measuring it")
+                    help="config4: one tile per workgroup and chunks of 8 instead of measuring")
     ap.add_argument("--batch-method", choices=["bicgstab", "gmres"], default="bicgstab",
                     help="config4: the engine's solver (GMRES(20) with --precision)")
     ap.add_argument("--batch-count", type=int, default=512,
@@ -203,16 +207,25 @@ def bench_batch(args, gsk, problems, dev):
     unit = 512 if mixed else 256
     rows = sum((s["n"] + unit - 1) // unit * unit for s in systems)
     tuned = None
-    check_every = 8
-    if not gmres and not mixed and not args.no_tune:
-        # chunk length measured on a sample of the batch, before (and outside) the timing
+    check_every, tile_units = 8, 0
+    if args.tile_units or args.chunk:
+        tile_units, check_every = args.tile_units or 1, args.chunk or 8
+        unit = 256 * tile_units
+        rows = sum((s["n"] + unit - 1) // unit * unit for s in systems)
+    elif not gmres and not mixed and not args.no_tune:
+        # launch shape and chunk length measured on a sample of the batch, before (and
+        # outside) the timing
         from paper_0812_2769_amd import tune
-        tuned = tune.tune_check_every(systems, sample=64, device=dev)
-        check_every = tuned["best"]
-        log(f"chunk length tuned on {tuned['sample']} systems: {tuned['seconds']} -> "
-            f"{check_every}")
+        tuned = tune.tune_engine(systems, device=dev, maxit=48)
+        tile_units, check_every = tuned["best"]
+        unit = 256 * tile_units
+        rows = sum((s["n"] + unit - 1) // unit * unit for s in systems)
+        log(f"engine tuned on {tuned['sample']} systems x {tuned['maxit']} iterations: "
+            f"{ {f'{u}x{k}': round(v, 4) for (u, k), v in tuned['seconds'].items()} } -> "
+            f"{tile_units} tile(s) per workgroup, chunks of {check_every}")
     eng = gsk.Engine(rows, len(systems), check_every=check_every, graph=True, device=dev,
-                     method=args.batch_method, m=20, precision="mixed" if mixed else "fp64")
+                     method=args.batch_method, m=20, precision="mixed" if mixed else "fp64",
+                     tile_units=tile_units)
     solver = (f"GMRES(20) {'mixed precision' if mixed else 'FP64'}" if gmres
               else f"Bi-CGSTAB {'mixed precision' if mixed else 'FP64'}")
     xbuf = torch.zeros(sum(s["n"] for s in systems), dtype=torch.float64, device=dev)
@@ -305,9 +318,10 @@ def bench_batch(args, gsk, problems, dev):
                     "whole step time (GS, residual and finalize launches, host polls "
                     "included)"},
         "status": status,
-        "chunk_tuning": None if tuned is None else {
-            "chosen": tuned["best"], "sample_systems": tuned["sample"],
-            "seconds": {str(k): round(v, 4) for k, v in tuned["seconds"].items()}},
+        "engine_tuning": None if tuned is None else {
+            "tiles_per_workgroup": tuned["best"][0], "chunk": tuned["best"][1],
+            "sample_systems": tuned["sample"], "iterations_each": tuned["maxit"],
+            "seconds": {f"{u}x{k}": round(v, 4) for (u, k), v in tuned["seconds"].items()}},
         "roofline": None, "cpu_baseline": None,
     }
     if not args.no_solo and not (mixed and not gmres):

@@ -401,6 +401,9 @@ typedef struct gsk_engine_config {
     int32_t check_every;   /* Bi-CGSTAB: iterations per chunk (1..256, even with
                               GSK_ENGINE_GRAPH); GMRES: ignored (a chunk is one cycle)      */
     int32_t flags;         /* GSK_ENGINE_GRAPH                                              */
+    int32_t tile_units;    /* FP64 Bi-CGSTAB: 256-row tiles per workgroup of the streaming
+                              launches, 1 or 2 (0 selects 1); a shape choice only, the
+                              results are the same bits. Mixed engines use 2, FP64 GMRES 1. */
     double inner_reduction; /* mixed Bi-CGSTAB: a run with FP32 storage ends (and the FP64
                               residual is recomputed) once its estimate has dropped by this
                               factor below the residual it started from, or below tol;

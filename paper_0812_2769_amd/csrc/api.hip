@@ -391,6 +391,10 @@ static int engine_cfg(const gsk_engine_config* c, gsk::EngineConfig& cfg) {
   cfg.check_every = gmres ? 0 : c->check_every;
   cfg.use_graph = (c->flags & GSK_ENGINE_GRAPH) != 0;
   cfg.delta = delta;
+  if (c->tile_units < 0 || c->tile_units > 2 ||
+      (c->tile_units == 2 && (gmres || c->precision != GSK_PRECISION_FP64)))
+    return set_err(GSK_ERR_INVALID_ARG, "tile_units must be 0 or 1 (or 2 for FP64 Bi-CGSTAB)");
+  cfg.units = c->tile_units;
   return GSK_OK;
 }
 
@@ -404,7 +408,7 @@ size_t gsk_engine_workspace_bytes_ex(const gsk_engine_config* c) {
 
 size_t gsk_engine_workspace_bytes(int64_t max_rows, int32_t max_systems) {
   const gsk_engine_config c{max_rows, max_systems, GSK_METHOD_BICGSTAB, 0, GSK_PRECISION_FP64,
-                            8, 0, 0.0};
+                            8, 0, 0, 0.0};
   return gsk_engine_workspace_bytes_ex(&c);
 }
 
@@ -434,7 +438,7 @@ int gsk_engine_create_ex(const gsk_engine_config* c, void* ws, size_t ws_bytes, 
 int gsk_engine_create(void* ws, size_t ws_bytes, int64_t max_rows, int32_t max_systems,
                       int32_t check_every, int32_t flags, void* stream, gsk_engine** out) {
   const gsk_engine_config c{max_rows, max_systems, GSK_METHOD_BICGSTAB, 0, GSK_PRECISION_FP64,
-                            check_every, flags, 0.0};
+                            check_every, flags, 0, 0.0};
   return gsk_engine_create_ex(&c, ws, ws_bytes, stream, out);
 }
 
@@ -579,7 +583,7 @@ int gsk_bicgstab_batch(int32_t count, const gsk_matrix* A, const double* const* 
   int rc = params_from(opt, prm, tol);
   if (rc) return rc;
   const int64_t rows = batch_rows(count, n.data());
-  const gsk::EngineConfig cfg{rows, count, 0, 0, false, prm.check_every, false, 1e-6};
+  const gsk::EngineConfig cfg{rows, count, 0, 0, false, prm.check_every, false, 1e-6, 1};
   rc = check_ws(ws, ws_bytes, gsk::engine_workspace_bytes(cfg));
   if (rc) return rc;
   gsk::Engine* e = nullptr;

@@ -34,11 +34,13 @@ namespace gsk {
 
 struct BArgsB {
   const SysDesc* sys;
-  const int* act;        // [2][max_tiles]: tiles of the admitted systems, then their slots
+  const int* act;        // [2][max_units]: units of the admitted systems, then their slots
   const int* n_act;      // number of entries in act
   BCtl* ctl;             // [max_systems]
   double* partials;      // [4][max_tiles]
   int max_tiles;
+  int max_units;         // list capacity (its second half starts there)
+  int rv;                // tiles per list unit (1 or 2)
   double* r;
   double* rh;
   double* p[2];
@@ -53,7 +55,26 @@ struct BArgsB {
 template <class Body>
 __device__ inline void for_active_tiles(const BArgsB& a, Body body) {
   const int k = logical_block();
-  if (k < *a.n_act) body(a.act[k], a.act[a.max_tiles + k]);
+  if (k >= *a.n_act) return;
+  const int unit = a.act[k], s = a.act[a.max_units + k];
+  if (a.rv == 1) {
+    body(unit, s);
+    return;
+  }
+  // the unit's tiles in turn (the workgroup's LDS is reused between them)
+  const int t0 = a.sys[s].tile_off + (unit - a.sys[s].unit_off) * a.rv;
+  const int t1 = a.sys[s].tile_off + a.sys[s].ntiles;
+  for (int q = 0; q < a.rv && t0 + q < t1; ++q) {
+    if (q) __syncthreads();
+    body(t0 + q, s);
+  }
+}
+
+// Calls body(unit, slot) for the list entry of this workgroup (one unit of rv tiles).
+template <class Body>
+__device__ inline void for_active_units(const BArgsB& a, Body body) {
+  const int k = logical_block();
+  if (k < *a.n_act) body(a.act[k], a.act[a.max_units + k]);
 }
 
 struct GatherPB {
@@ -95,6 +116,40 @@ __device__ inline double sys_tile(const SysDesc& d, int row0, int nrows, const G
   }
   const CsrOp op{d.rp, d.ci, d.val};
   return op.tile(row0, nrows, g, L);
+}
+
+// The two tiles of a unit (system-local tile lt0 = first) and their rows.
+__device__ inline void unit_rows2(const SysDesc& d, int unit, int& lt0, int (&row0)[2],
+                                  int (&nr)[2]) {
+  lt0 = (unit - d.unit_off) * 2;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    row0[k] = (lt0 + k) * BS;
+    nr[k] = max(0, min(BS, d.n - row0[k]));
+  }
+}
+
+// The product over the two tiles of a unit. Stencil: both tiles' operands are loaded before
+// either sum (clamped addresses, so a tile past the end reads valid rows); CSR: one tile at a
+// time through LDS.
+template <class G>
+__device__ inline void unit_product2(const SysDesc& d, const int (&row0)[2], const int (&nr)[2],
+                                     const G& g, TileLds& L, double (&y)[2]) {
+  if (d.kind == MAT_STENCIL) {
+    const StencilOp op{d.coef, d.n, d.nx, d.ny, d.nz, (size_t)d.n};
+    StencilOp::Pre<G> pre[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) pre[k] = op.load(row0[k], nr[k], g);
+    EmptyLds e;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) y[k] = op.finish(pre[k], row0[k], nr[k], g, e);
+  } else {
+    const CsrOp op{d.rp, d.ci, d.val};
+    for (int k = 0; k < 2; ++k) {
+      if (k) __syncthreads();
+      y[k] = nr[k] > 0 ? op.tile(row0[k], nr[k], g, L) : 0.0;
+    }
+  }
 }
 
 __global__ __launch_bounds__(64) void k_batch_init(BCtl* c, int maxit, double tol, double eps_b,
@@ -266,30 +321,62 @@ __global__ __launch_bounds__(BS) void k_batch_fin_residual(BArgsB a) {
 }
 
 // P: new p, v = A p; partials (r^, v), ||v||^2.
+template <int RV>
 __global__ __launch_bounds__(BS) void k_batch_p(BArgsB a) {
   __shared__ TileLds L;
   __shared__ double red[NC_MAX * WAVES];
-  for_active_tiles(a, [&](int tile, int s) {
-    const SysDesc d = a.sys[s];
-    BCtl* c = a.ctl + s;
-    if (c->sum.state != ST_RUNNING) return;
-    const int q = a.par;
-    const int64_t o = d.row_off;
-    const GatherPB G{a.r + o, a.p[q] + o, a.v[q] + o, c->beta, c->omega, c->first};
-    const int row0 = (tile - d.tile_off) * BS;
-    const int nrows = min(BS, d.n - row0);
-    const int t = threadIdx.x;
-    const double y = sys_tile(d, row0, nrows, G, L);
-    double acc[2] = {0.0, 0.0};
-    if (t < nrows) {
-      const int row = row0 + t;
-      a.p[q ^ 1][o + row] = G(row);
-      a.v[q ^ 1][o + row] = y;
-      acc[0] = a.rh[o + row] * y;
-      acc[1] = y * y;
-    }
-    block_partials<2>(acc, 2, a.partials, a.max_tiles, tile, red);
-  });
+  if constexpr (RV == 1) {
+    for_active_tiles(a, [&](int tile, int s) {
+      const SysDesc d = a.sys[s];
+      BCtl* c = a.ctl + s;
+      if (c->sum.state != ST_RUNNING) return;
+      const int q = a.par;
+      const int64_t o = d.row_off;
+      const GatherPB G{a.r + o, a.p[q] + o, a.v[q] + o, c->beta, c->omega, c->first};
+      const int row0 = (tile - d.tile_off) * BS;
+      const int nrows = min(BS, d.n - row0);
+      const int t = threadIdx.x;
+      const double y = sys_tile(d, row0, nrows, G, L);
+      double acc[2] = {0.0, 0.0};
+      if (t < nrows) {
+        const int row = row0 + t;
+        a.p[q ^ 1][o + row] = G(row);
+        a.v[q ^ 1][o + row] = y;
+        acc[0] = a.rh[o + row] * y;
+        acc[1] = y * y;
+      }
+      block_partials<2>(acc, 2, a.partials, a.max_tiles, tile, red);
+    });
+  } else {
+    // two tiles per workgroup: a stencil product loads both tiles' operands before either
+    // sum; partials stay per tile
+    for_active_units(a, [&](int unit, int s) {
+      const SysDesc d = a.sys[s];
+      BCtl* c = a.ctl + s;
+      if (c->sum.state != ST_RUNNING) return;
+      const int q = a.par;
+      const int64_t o = d.row_off;
+      const GatherPB G{a.r + o, a.p[q] + o, a.v[q] + o, c->beta, c->omega, c->first};
+      int lt0, row0[2], nr[2];
+      unit_rows2(d, unit, lt0, row0, nr);
+      double y[2];
+      unit_product2(d, row0, nr, G, L, y);
+      const int t = threadIdx.x;
+      for (int k = 0; k < 2; ++k) {
+        if (nr[k] <= 0) break;
+        if (k) __syncthreads();
+        double acc[2] = {0.0, 0.0};
+        if (t < nr[k]) {
+          const int row = row0[k] + t;
+          a.p[q ^ 1][o + row] = G(row);
+          a.v[q ^ 1][o + row] = y[k];
+          acc[0] = a.rh[o + row] * y[k];
+          acc[1] = y[k] * y[k];
+        }
+        block_partials<2>(acc, 2, a.partials, a.max_tiles, d.tile_off + lt0 + k, red);
+      }
+    });
+  }
 }
 
 __global__ __launch_bounds__(BS) void k_batch_fin_p(BArgsB a) {
@@ -313,34 +400,68 @@ __global__ __launch_bounds__(BS) void k_batch_fin_p(BArgsB a) {
 }
 
 // S: t = A s with s = r - alpha v; partials (t,s), (t,t), ||s||^2, ||W s||^2.
+template <int RV>
 __global__ __launch_bounds__(BS) void k_batch_s(BArgsB a) {
   __shared__ TileLds L;
   __shared__ double red[NC_MAX * WAVES];
-  for_active_tiles(a, [&](int tile, int s) {
-    const SysDesc d = a.sys[s];
-    BCtl* c = a.ctl + s;
-    if (c->sum.state != ST_RUNNING) return;
-    const int64_t o = d.row_off;
-    const GatherSB G{a.r + o, a.v[a.par ^ 1] + o, c->alpha};
-    const int row0 = (tile - d.tile_off) * BS;
-    const int nrows = min(BS, d.n - row0);
-    const int t = threadIdx.x;
-    const double y = sys_tile(d, row0, nrows, G, L);
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (t < nrows) {
-      const int row = row0 + t;
-      const double sv = G(row);
-      a.t[o + row] = y;
-      acc[0] = y * sv;
-      acc[1] = y * y;
-      acc[2] = sv * sv;
-      if (d.W) {
-        const double ws = d.W[row] * sv;
-        acc[3] = ws * ws;
+  if constexpr (RV == 1) {
+    for_active_tiles(a, [&](int tile, int s) {
+      const SysDesc d = a.sys[s];
+      BCtl* c = a.ctl + s;
+      if (c->sum.state != ST_RUNNING) return;
+      const int64_t o = d.row_off;
+      const GatherSB G{a.r + o, a.v[a.par ^ 1] + o, c->alpha};
+      const int row0 = (tile - d.tile_off) * BS;
+      const int nrows = min(BS, d.n - row0);
+      const int t = threadIdx.x;
+      const double y = sys_tile(d, row0, nrows, G, L);
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      if (t < nrows) {
+        const int row = row0 + t;
+        const double sv = G(row);
+        a.t[o + row] = y;
+        acc[0] = y * sv;
+        acc[1] = y * y;
+        acc[2] = sv * sv;
+        if (d.W) {
+          const double ws = d.W[row] * sv;
+          acc[3] = ws * ws;
+        }
       }
-    }
-    block_partials<4>(acc, 4, a.partials, a.max_tiles, tile, red);
-  });
+      block_partials<4>(acc, 4, a.partials, a.max_tiles, tile, red);
+    });
+  } else {
+    for_active_units(a, [&](int unit, int s) {
+      const SysDesc d = a.sys[s];
+      BCtl* c = a.ctl + s;
+      if (c->sum.state != ST_RUNNING) return;
+      const int64_t o = d.row_off;
+      const GatherSB G{a.r + o, a.v[a.par ^ 1] + o, c->alpha};
+      int lt0, row0[2], nr[2];
+      unit_rows2(d, unit, lt0, row0, nr);
+      double y[2];
+      unit_product2(d, row0, nr, G, L, y);
+      const int t = threadIdx.x;
+      for (int k = 0; k < 2; ++k) {
+        if (nr[k] <= 0) break;
+        if (k) __syncthreads();
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        if (t < nr[k]) {
+          const int row = row0[k] + t;
+          const double sv = G(row);
+          a.t[o + row] = y[k];
+          acc[0] = y[k] * sv;
+          acc[1] = y[k] * y[k];
+          acc[2] = sv * sv;
+          if (d.W) {
+            const double ws = d.W[row] * sv;
+            acc[3] = ws * ws;
+          }
+        }
+        block_partials<4>(acc, 4, a.partials, a.max_tiles, d.tile_off + lt0 + k, red);
+      }
+    });
+  }
 }
 
 __global__ __launch_bounds__(BS) void k_batch_fin_s(BArgsB a) {
@@ -451,7 +572,10 @@ struct EngineLayout {
   size_t sys, tiles, ctl, sums, partials, vecs, total;
 };
 
-static int units_of(const EngineConfig& cfg) { return cfg.mixed ? 2 : 1; }
+static int units_of(const EngineConfig& cfg) {
+  if (cfg.mixed) return 2;
+  return cfg.method == 0 && cfg.units == 2 ? 2 : 1;   // FP64 Bi-CGSTAB may take two
+}
 
 // Workspace carve-up. Bi-CGSTAB: system table, unit list, control blocks, partials (4 per
 // tile), the 7 vectors. GMRES: system table, unit list, control blocks, status copies,
@@ -645,10 +769,12 @@ int engine_create(void* ws, size_t ws_bytes, const EngineConfig& cfg, hipStream_
     BArgsB& a = e->args;
     a.sys = reinterpret_cast<const SysDesc*>(base + L.sys);
     a.act = reinterpret_cast<const int*>(base + L.tiles);
-    a.n_act = a.act + 2 * (size_t)e->grid_tiles;
     a.ctl = reinterpret_cast<BCtl*>(base + L.ctl);
     a.partials = reinterpret_cast<double*>(base + L.partials);
     a.max_tiles = e->grid_tiles;
+    a.max_units = e->max_units;
+    a.rv = e->rv;
+    a.n_act = a.act + 2 * (size_t)e->max_units;
     const size_t vb = align256(sizeof(double) * (size_t)e->grid_tiles * BS);
     double* v[kBatchVectors];
     for (int i = 0; i < kBatchVectors; ++i)
@@ -833,9 +959,11 @@ static void enqueue_chunk(Engine& e, int k, int64_t first_iter, int grid) {
   hipLaunchKernelGGL(k_batch_fin_residual, gs, block, 0, e.s, a);
   for (int it = 0; it < k; ++it) {
     a.par = (int)((first_iter + it) & 1);
-    hipLaunchKernelGGL(k_batch_p, gt, block, 0, e.s, a);
+    if (e.rv == 2) hipLaunchKernelGGL(k_batch_p<2>, gt, block, 0, e.s, a);
+    else hipLaunchKernelGGL(k_batch_p<1>, gt, block, 0, e.s, a);
     hipLaunchKernelGGL(k_batch_fin_p, gs, block, 0, e.s, a);
-    hipLaunchKernelGGL(k_batch_s, gt, block, 0, e.s, a);
+    if (e.rv == 2) hipLaunchKernelGGL(k_batch_s<2>, gt, block, 0, e.s, a);
+    else hipLaunchKernelGGL(k_batch_s<1>, gt, block, 0, e.s, a);
     hipLaunchKernelGGL(k_batch_fin_s, gs, block, 0, e.s, a);
     hipLaunchKernelGGL(k_batch_u, gt, block, 0, e.s, a);
     hipLaunchKernelGGL(k_batch_fin_u, gs, block, 0, e.s, a);

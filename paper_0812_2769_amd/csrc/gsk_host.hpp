@@ -121,6 +121,7 @@ struct EngineConfig {
   int check_every;   // Bi-CGSTAB: iterations per chunk
   bool use_graph;
   double delta;      // mixed Bi-CGSTAB: reduction that ends a run (refinement step)
+  int units;         // FP64 Bi-CGSTAB: 256-row tiles per workgroup (1 or 2; 0 = 1)
 };
 size_t engine_workspace_bytes(const EngineConfig& cfg);
 // 0 ok, -4 workspace too small, -1 invalid arguments, -5 HIP failure.

@@ -86,7 +86,7 @@ class EngineConfig(ctypes.Structure):
     _fields_ = [("max_rows", ctypes.c_int64), ("max_systems", ctypes.c_int32),
                 ("method", ctypes.c_int32), ("m", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("inner_reduction", ctypes.c_double)]
+                ("tile_units", ctypes.c_int32), ("inner_reduction", ctypes.c_double)]
 
 
 class EngineRequest(ctypes.Structure):
@@ -476,7 +476,8 @@ class Engine:
 
     def __init__(self, max_rows: int, max_systems: int, check_every: int = 8,
                  graph: bool = False, device="cuda", stream=None, method: str = "bicgstab",
-                 m: int = 20, precision: str = "fp64", inner_reduction: float = 0.0):
+                 m: int = 20, precision: str = "fp64", inner_reduction: float = 0.0,
+                 tile_units: int = 0):
         self.device = torch.device(device)
         self.stream = stream if stream is not None else (
             torch.cuda.Stream(self.device) if graph else torch.cuda.current_stream(self.device))
@@ -488,7 +489,7 @@ class Engine:
                            METHOD_GMRES if method == "gmres" else METHOD_BICGSTAB,
                            self.m if method == "gmres" else 0,
                            PRECISION_MIXED if self.mixed else PRECISION_FP64,
-                           int(check_every), ENGINE_GRAPH if graph else 0,
+                           int(check_every), ENGINE_GRAPH if graph else 0, int(tile_units),
                            float(inner_reduction))
         nbytes = int(lib.gsk_engine_workspace_bytes_ex(ctypes.byref(cfg)))
         if nbytes == 0:
