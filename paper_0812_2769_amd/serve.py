@@ -134,6 +134,9 @@ class GmresEngineWorker(threading.Thread):
                     x = torch.zeros_like(req.b)
                     if not self.engine.submit_gs(req.A, req.b, x, p=2, tol=req.tol,
                                                  tag=req.tag):
+                        if not inflight:   # an empty engine that cannot take it never will
+                            raise ValueError(f"request {req.tag} ({req.A.n} rows) does not "
+                                             "fit the GMRES engine")
                         break
                     inflight[req.tag] = (req, admitted, x)
                     waiting.popleft()
@@ -213,6 +216,9 @@ class Server:
                         continue
                     x = torch.zeros_like(r.b)
                     if not self.engine.submit_gs(r.A, r.b, x, p=2, tol=r.tol, tag=r.tag):
+                        if not inflight:   # an empty engine that cannot take it never will
+                            raise ValueError(f"request {r.tag} ({r.A.n} rows) does not fit "
+                                             "the engine")
                         break
                     inflight[r.tag] = (r, now, x)
                     waiting.popleft()

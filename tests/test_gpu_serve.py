@@ -85,3 +85,15 @@ def test_serving_results_equal_solo(G, realtime, mode):
         xr, ir = ref[key]
         assert d.info == ir, (d.tag, d.method, d.info, ir)
         assert np.array_equal(d.x.cpu().numpy(), xr), (d.tag, d.method)
+
+
+def test_request_larger_than_engine_is_an_error(G):
+    from paper_0812_2769_amd import serve
+    systems = pool(G, count=2)
+    big = max(systems, key=lambda s: s["n"])
+    reqs = [serve.Request(tag=0, arrival=0.0, A=big["S"], b=big["b"], method="bicgstab",
+                          tol=1e-8, csr=big["A"], grid=big["grid"])]
+    srv = serve.Server(256, 2, graph=False)
+    with pytest.raises(ValueError):
+        srv.serve(reqs, realtime=False)
+    srv.close()
