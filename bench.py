@@ -542,6 +542,26 @@ def main():
                 "bytes_per_launch": round(pr["bytes"] / pr["busy_launches"]),
                 "timed_launches": pr["launches"], "busy_launches": pr["busy_launches"]}
 
+    # Mixed precision: every GMRES result against the FP64 solver on the same scaled system
+    # (untimed). The FP64 path is the one the oracle parity tests pin.
+    accuracy = None
+    if mixed:
+        accuracy = {}
+        ws64 = gsk.workspace(gsk.METHOD_GMRES, n, 30, dev)
+        for p, method in variants:
+            if method != "gmres30":
+                continue
+            im = solve(p, method)
+            xm = x.clone()
+            w = None if p == 2 else weights
+            x64, i64 = gsk.gmres(M, b_s, m=30, tol=tol, maxit=maxit, stop_weights=w, ws=ws64)
+            err = (torch.linalg.vector_norm(xm - x64) / torch.linalg.vector_norm(x64)).item()
+            accuracy[f"gs{p}_{method}"] = {
+                "x_rel_error_vs_fp64": err, "relres_true_mixed": im.relres_true,
+                "relres_true_fp64": i64.relres_true, "steps_mixed": im.iters,
+                "steps_fp64": i64.iters}
+        del ws64
+
     kernels = {}
     if not args.no_kernel_table:
         for cls in gsk.KCLASS:
@@ -584,6 +604,7 @@ def main():
         "latency_p50_ms": round(1e3 * pct(all_lat, 0.5), 3),
         "latency_p99_ms": round(1e3 * pct(all_lat, 0.99), 3),
         "per_variant": per_variant,
+        "accuracy_vs_fp64": accuracy,
         "roofline": None,
         "cpu_baseline": None,
         "kernels": kernels,
