@@ -184,3 +184,68 @@ def test_engine_struct_layouts_and_rejections(lib):
     assert L.gsk_bicgstab_batch_workspace_bytes(2, ns) == 0
     ns = (ctypes.c_int32 * 2)(300, 100)
     assert L.gsk_bicgstab_batch_workspace_bytes(2, ns) == lib.engine_workspace_bytes(768, 2)
+
+
+def test_struct_layouts_match_the_header(lib, tmp_path):
+    """sizeof and field offsets of every ABI struct, from a C program compiled against
+    include/gsk.h, equal those of the ctypes binding."""
+    checks = {
+        "gsk_csr": (lib.Csr, ["n", "nnz", "row_ptr", "col_idx", "val"]),
+        "gsk_options": (lib.Options, None),
+        "gsk_info": (lib.InfoStruct, None),
+        "gsk_matrix": (lib.Matrix, None),
+        "gsk_result": (lib.Result, ["tag", "info"]),
+        "gsk_engine_usage": (lib.EngineUsage, ["active", "max_systems", "max_rows",
+                                               "free_rows", "largest_free_rows"]),
+        "gsk_engine_config": (lib.EngineConfig, ["max_rows", "max_systems", "method", "m",
+                                                 "precision", "check_every", "flags",
+                                                 "tile_units", "inner_reduction"]),
+        "gsk_engine_request": (lib.EngineRequest, ["A", "b", "x", "tol", "opt", "tag", "gs_p",
+                                                   "val_out", "b_out", "stop_weight_out",
+                                                   "mat32", "mat32_ld"]),
+    }
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "gsk.h"', "int main(void) {"]
+    for cname, (_, fields) in checks.items():
+        src.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for f in fields or []:
+            src.append(f'  printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    src += ["  return 0;", "}"]
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), str(c), "-o", str(exe)],
+                   check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True,
+                                                       text=True, check=True).stdout.split("\n")
+               if line)
+    for cname, (ct, fields) in checks.items():
+        assert int(got[cname]) == ctypes.sizeof(ct), cname
+        for f in fields or []:
+            assert int(got[f"{cname}.{f}"]) == getattr(ct, f).offset, (cname, f)
+
+
+def test_engine_config_rejections(lib):
+    L = lib.lib
+    good = lib.EngineConfig(4096, 4, lib.METHOD_GMRES, 20, lib.PRECISION_MIXED, 8, 0, 0, 0.0)
+    assert L.gsk_engine_workspace_bytes_ex(ctypes.byref(good)) > 0
+    bad = [
+        lib.EngineConfig(4096, 4, lib.METHOD_GMRES, 0, 0, 8, 0, 0, 0.0),      # m = 0
+        lib.EngineConfig(4096, 4, lib.METHOD_GMRES, 65, 0, 8, 0, 0, 0.0),     # m > 64
+        lib.EngineConfig(4096, 4, lib.METHOD_ARNOLDI, 20, 0, 8, 0, 0, 0.0),   # method
+        lib.EngineConfig(4096, 4, lib.METHOD_BICGSTAB, 0, 0, 0, 0, 0, 0.0),   # check_every
+        lib.EngineConfig(4096, 4, lib.METHOD_BICGSTAB, 0, 1, 8, 0, 0, 1.5),   # reduction
+        lib.EngineConfig(4096, 4, lib.METHOD_GMRES, 20, 0, 8, 0, 2, 0.0),     # 2 tiles, GMRES
+        lib.EngineConfig(4096, 4, lib.METHOD_BICGSTAB, 0, 1, 8, 0, 2, 0.0),   # 2 tiles, mixed
+        lib.EngineConfig(0, 4, lib.METHOD_BICGSTAB, 0, 0, 8, 0, 0, 0.0),      # no rows
+        lib.EngineConfig(4096, 4, lib.METHOD_BICGSTAB, 0, 7, 8, 0, 0, 0.0),   # precision
+    ]
+    h = ctypes.c_void_p()
+    for cfg in bad:
+        assert L.gsk_engine_workspace_bytes_ex(ctypes.byref(cfg)) == 0
+        assert L.gsk_engine_create_ex(ctypes.byref(cfg), 0x100000, 1 << 30, None,
+                                      ctypes.byref(h)) == lib.ERR_INVALID_ARG
+    assert L.gsk_engine_create_ex(None, 0x100000, 1 << 30, None, ctypes.byref(h)) == \
+        lib.ERR_INVALID_ARG
+    # a valid configuration with too small a workspace fails before any device work
+    assert L.gsk_engine_create_ex(ctypes.byref(good), 0x100000, 256, None,
+                                  ctypes.byref(h)) == lib.ERR_WORKSPACE
