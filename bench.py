@@ -18,10 +18,12 @@ bounded sample of the same work.
 Other modes (not the default line):
   --precision mixed   the GMRES(30) solves use gsk_gmres_mixed (FP32 Arnoldi cycles, FP64
                       restarts) at the same tolerance; Bi-CGSTAB stays FP64.
-  --workload config3  the 160^3 checkerboard system (n = 4,096,000): GS(2) then GMRES(30)
-                      bounded at 600 Arnoldi steps per solve (restarted GMRES(30) does not reach
-                      the configuration's 1e-8 within the 10,000-step cap); `value` is Arnoldi
-                      steps per second.
+  --workload checker160  the 160^3 checkerboard system (n = 4,096,000): GS(2) then
+                      GMRES(30) bounded at 600 Arnoldi steps per solve (restarted GMRES(30) does
+                      not reach the workload's 1e-8 within the 10,000-step cap); `value` is
+                      Arnoldi steps per second.
+  --workload batch512    512 independent 2D/3D systems through the batch engine.
+  --workload serving     Poisson arrivals through the solve server.
 """
 import argparse
 import json
@@ -45,7 +47,7 @@ KERNEL_NAMES = {"gmres_a": "k_gmres_a (CSR product + CGS2 pass-1 dots)",
                 "residual": "k_*_residual (true residual)",
                 "gmres_x": "k_gmres_x (x += V y)"}
 TOL = 1e-10
-METRIC_C3 = "Arnoldi steps/s, GMRES(30) on the 160^3 checkerboard system"
+METRIC_CHECKER = "Arnoldi steps/s, GMRES(30) on the 160^3 checkerboard system"
 
 # Fabric (HBM + Infinity Cache) bytes per working launch of a kernel class, from two
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; FETCH_SIZE scaled by 2.000 and WRITE_SIZE by
@@ -74,38 +76,38 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["config2", "config3", "config4", "config5"],
-                    default="config2")
+    ap.add_argument("--workload", choices=["slabs80", "checker160", "batch512", "serving"],
+                    default="slabs80")
     ap.add_argument("--gmres-lanes", type=int, default=4,
-                    help="config5: host threads (each with its own stream) serving GMRES")
+                    help="serving: host threads (each with its own stream) serving GMRES")
     ap.add_argument("--gmres-mode", choices=["lanes", "engine"], default="engine",
-                    help="config5: GMRES requests on lanes or in a GMRES engine")
+                    help="serving: GMRES requests on lanes or in a GMRES engine")
     ap.add_argument("--gmres-precision", choices=["fp64", "mixed"], default="fp64",
-                    help="config5 with --gmres-mode engine: the GMRES engine's precision")
+                    help="serving with --gmres-mode engine: the GMRES engine's precision")
     ap.add_argument("--tile-units", type=int, default=0,
-                    help="config4: tiles per workgroup (1 or 2) instead of measuring")
+                    help="batch512: tiles per workgroup (1 or 2) instead of measuring")
     ap.add_argument("--chunk", type=int, default=0,
-                    help="config4: iterations per chunk instead of measuring")
+                    help="batch512: iterations per chunk instead of measuring")
     ap.add_argument("--no-tune", action="store_true",
-                    help="config4: one tile per workgroup and chunks of 8 instead of measuring")
+                    help="batch512: one tile per workgroup and chunks of 8 instead of measuring")
     ap.add_argument("--batch-method", choices=["bicgstab", "gmres"], default="bicgstab",
-                    help="config4: the engine's solver (GMRES(20) with --precision)")
+                    help="batch512: the engine's solver (GMRES(20) with --precision)")
     ap.add_argument("--batch-count", type=int, default=512,
-                    help="config4: systems per batch (default 512)")
+                    help="batch512: systems per batch (default 512)")
     ap.add_argument("--no-solo", action="store_true",
-                    help="config4: skip the one-at-a-time comparison")
+                    help="batch512: skip the one-at-a-time comparison")
     ap.add_argument("--rates", default="50,200,1000,2000",
-                    help="config5: Poisson arrival rates to sweep (requests/s)")
+                    help="serving: Poisson arrival rates to sweep (requests/s)")
     ap.add_argument("--serve-requests", type=int, default=400,
-                    help="config5: requests per rate")
+                    help="serving: requests per rate")
     ap.add_argument("--gmres-share", type=float, default=0.2,
-                    help="config5: fraction of GMRES(20) requests (the rest Bi-CGSTAB)")
+                    help="serving: fraction of GMRES(20) requests (the rest Bi-CGSTAB)")
     ap.add_argument("--grid", type=int, default=0,
-                    help="N of the N^3 grid (default 80 for config2, 160 for config3)")
+                    help="N of the N^3 grid (default 80 for slabs80, 160 for checker160)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="GMRES solves in FP64 (default) or mixed precision")
-    ap.add_argument("--c3-steps", type=int, default=600,
-                    help="Arnoldi steps per config3 solve (default 600)")
+    ap.add_argument("--checker-steps", type=int, default=600,
+                    help="Arnoldi steps per checker160 solve (default 600)")
     ap.add_argument("--operator", choices=["stencil", "csr"], default="stencil",
                     help="matrix form the solvers read: 7-point coefficient planes packed from "
                          "the scaled CSR matrix inside each solve (default), or the CSR matrix")
@@ -180,7 +182,7 @@ def build_batch_systems(gsk, problems, dev, specs):
     systems = []
     t0 = time.perf_counter()
     for i, sp in enumerate(specs):
-        P = problems.config4_system(sp)
+        P = problems.batch_system(sp)
         A = gsk.CsrMatrix.from_problem(P, dev)
         d = list(P.dims) + [1] * (3 - len(P.dims))
         S = gsk.stencil_from_csr(A, *d)
@@ -197,10 +199,10 @@ def torch_from(a, dev):
 
 
 def bench_batch(args, gsk, problems, dev):
-    """config4: a batch of independent GS(2) + Bi-CGSTAB solves, tol 1e-8, run by the engine
+    """batch512: a batch of independent GS(2) + Bi-CGSTAB solves, tol 1e-8, run by the engine
     with every chunk replayed from a HIP graph. value = systems solved per second."""
     import torch
-    specs = problems.config4_specs(args.batch_count)
+    specs = problems.batch_specs(args.batch_count)
     systems = build_batch_systems(gsk, problems, dev, specs)
     gmres = args.batch_method == "gmres"
     mixed = args.precision == "mixed"
@@ -299,7 +301,7 @@ def bench_batch(args, gsk, problems, dev):
         "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"config4: {len(systems)} systems, d in {{2,3}}, N in [32,96], "
+        "config": {"workload": f"batch of {len(systems)} systems, d in {{2,3}}, N in [32,96], "
                                f"box jump 10^U(2,6), convection U(0,30); GS(2) + {solver} in "
                                f"the engine (HIP-graph chunks of "
                                f"{'one cycle' if gmres else f'{check_every} iterations'}), "
@@ -360,14 +362,14 @@ def collections_count(infos):
 
 
 def bench_serve(args, gsk, problems, dev):
-    """config5: Poisson arrivals of solves drawn from the config4 distribution (a pool of 64
+    """serving: Poisson arrivals of solves drawn from the batch recipe (a pool of 64
     systems), a GMRES(20) / Bi-CGSTAB mix, tol 1e-8, served with continuous batching; one run
     per arrival rate. value = completed solves/s at the highest rate."""
     import numpy as np
     import torch
     from paper_0812_2769_amd import serve
     rates = [float(r) for r in args.rates.split(",") if r]
-    pool_specs = problems.config4_specs(64, seed=1005)
+    pool_specs = problems.batch_specs(64, seed=1005)
     pool = build_batch_systems(gsk, problems, dev, pool_specs)
     nmax = max(s["n"] for s in pool)
     rng = np.random.default_rng(1006)
@@ -412,9 +414,9 @@ def bench_serve(args, gsk, problems, dev):
         "value": best["completed_per_s"], "unit": "solves/s", "n_gpus": 1,
         "steps": len(rates), "warmup": 0, "ms_per_step": None, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"config5: Poisson arrivals at {args.rates} req/s, "
+        "config": {"workload": f"serving: Poisson arrivals at {args.rates} req/s, "
                                f"{args.serve_requests} requests per rate from a pool of 64 "
-                               f"config4-distribution systems, {args.gmres_share:.0%} GMRES(20), "
+                               f"batch-recipe systems, {args.gmres_share:.0%} GMRES(20), "
                                f"the rest Bi-CGSTAB, tol 1e-8, GS(2) per request; Bi-CGSTAB "
                                f"in the engine, GMRES "
                                + (f"in a GMRES(20) engine ({args.gmres_precision})"
@@ -451,17 +453,17 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    if args.workload == "config4":
+    if args.workload == "batch512":
         return bench_batch(args, gsk, problems, dev)
-    if args.workload == "config5":
+    if args.workload == "serving":
         return bench_serve(args, gsk, problems, dev)
-    c3 = args.workload == "config3"
-    grid = args.grid or (160 if c3 else 80)
-    variants = [(2, "gmres30")] if c3 else VARIANTS
-    tol = 1e-8 if c3 else TOL
-    maxit = args.c3_steps if c3 else None
+    checker = args.workload == "checker160"
+    grid = args.grid or (160 if checker else 80)
+    variants = [(2, "gmres30")] if checker else VARIANTS
+    tol = 1e-8 if checker else TOL
+    maxit = args.checker_steps if checker else None
     t0 = time.perf_counter()
-    P = problems.config3(grid) if c3 else problems.config2(grid)
+    P = problems.checkerboard_3d(grid) if checker else problems.slabs_3d(grid)
     print(f"bench: generated {P.name} n={P.n} nnz={P.nnz} in {time.perf_counter() - t0:.1f}s",
           file=sys.stderr, flush=True)
     A = gsk.CsrMatrix.from_problem(P, dev)
@@ -570,7 +572,7 @@ def main():
             kernels[cls] = achieved(gsk.probe_end())
 
     for key, info in infos.items():
-        if info.status != gsk.CONVERGED and not c3:
+        if info.status != gsk.CONVERGED and not checker:
             print(f"bench: WARNING {key} ended {info.status_name} at relres "
                   f"{info.relres_true:.2e}", file=sys.stderr, flush=True)
     solves = len(variants) * args.steps
@@ -581,9 +583,9 @@ def main():
                        "p99_ms": round(1e3 * pct(lat[k], 0.99), 3)} for k in lat}
     all_lat = [v for k in lat for v in lat[k]]
     out = {
-        "metric": METRIC_C3 if c3 else METRIC,
-        "value": round((iters_step * args.steps if c3 else solves) / elapsed, 4),
-        "unit": "Arnoldi steps/s" if c3 else "solves/s",
+        "metric": METRIC_CHECKER if checker else METRIC,
+        "value": round((iters_step * args.steps if checker else solves) / elapsed, 4),
+        "unit": "Arnoldi steps/s" if checker else "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -594,9 +596,9 @@ def main():
         "dtype": "f32 inner / f64 restarts" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": (
-                       f"config3: {grid}^3 7-point, 16^3-block checkerboard a in {{1, 1e4}}, "
-                       f"FP64 CSR; GS(2) x GMRES(30) bounded at {args.c3_steps} steps" if c3 else
-                       f"config2: {grid}^3 7-point convection-diffusion, 8 random slabs, FP64 "
+                       f"{grid}^3 7-point, 16^3-block checkerboard a in {{1, 1e4}}, "
+                       f"FP64 CSR; GS(2) x GMRES(30) bounded at {args.checker_steps} steps" if checker else
+                       f"{grid}^3 7-point convection-diffusion, 8 random slabs, FP64 "
                        f"CSR; GS(1|2) x (Bi-CGSTAB | GMRES(30)), tol 1e-10"),
                    "n": n, "nnz": P.nnz, "solves_per_step": len(variants), "tol": tol,
                    "operator": args.operator, "precision": args.precision},
@@ -615,7 +617,7 @@ def main():
             "bound": "hbm", "achieved": a["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(a["achieved_GBs"] / HBM_PEAK_GBS, 4),
             "traffic": (traffic_for(args.probe, grid, args.operator)
-                        if not mixed and not c3 else None),
+                        if not mixed and not checker else None),
             "kernel": KERNEL_NAMES.get(args.probe), "avg_launch_us": a["avg_launch_us"],
             "bytes_per_launch": a["bytes_per_launch"], "timed_launches": a["timed_launches"],
             "busy_launches": a["busy_launches"], "sample_every": args.probe_every,
@@ -625,7 +627,7 @@ def main():
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(P, {k: infos[k].iters for k in infos},
-                                           args.cpu_sample_iters if not c3 else 10, variants,
+                                           args.cpu_sample_iters if not checker else 10, variants,
                                            tol, args.precision)
     print(json.dumps(out), flush=True)
 

@@ -32,9 +32,9 @@ __all__ = [
     "assemble",
     "problem1",
     "problem4",
-    "config1",
-    "config2",
-    "config3",
+    "square_jump_2d",
+    "slabs_3d",
+    "checkerboard_3d",
     "laplacian",
     "random_sparse",
 ]
@@ -267,7 +267,7 @@ def problem4(N: int = 40, D: float = 1e4, conv: float = 100.0) -> Problem:
 # Benchmark workloads (synthetic, seeded)
 # ---------------------------------------------------------------------------------------
 
-def config1(N: int = 64) -> Problem:
+def square_jump_2d(N: int = 64) -> Problem:
     """2D, 64x64 interior, a = 1e3 on the open square (1/4,3/4)^2 else 1, convection (10,10),
     b = A u* with u* = x(1-x)y(1-y)e^(x+y) on the grid. Deterministic."""
 
@@ -281,7 +281,7 @@ def config1(N: int = 64) -> Problem:
         y = q[1] / den[1]
         return x * (1 - x) * y * (1 - y) * np.exp(x + y)
 
-    return assemble((N, N), diff, (10.0, 10.0), u_star_fn=u_star, name=f"config1_N{N}")
+    return assemble((N, N), diff, (10.0, 10.0), u_star_fn=u_star, name=f"square_jump_2d_N{N}")
 
 
 def _sine_product(q, den):
@@ -291,7 +291,7 @@ def _sine_product(q, den):
     return out
 
 
-def config2(N: int = 80, seed: int = 1002, slabs: int = 8) -> Problem:
+def slabs_3d(N: int = 80, seed: int = 1002, slabs: int = 8) -> Problem:
     """3D, N^3 interior, a piecewise constant on `slabs` equal slabs along z (half-open cells),
     slab values 10^U(0,6) drawn in slab order from numpy's default_rng(seed); convection
     (20,-10,5); b = A u* with u* = sin(pi x) sin(pi y) sin(pi z)."""
@@ -304,12 +304,12 @@ def config2(N: int = 80, seed: int = 1002, slabs: int = 8) -> Problem:
         return np.broadcast_to(slab_val[s], np.broadcast_shapes(*[x.shape for x in q]))
 
     p = assemble((N, N, N), diff, (20.0, -10.0, 5.0), u_star_fn=_sine_product,
-                 name=f"config2_N{N}_seed{seed}")
+                 name=f"slabs_3d_N{N}_seed{seed}")
     return p
 
 
-def config3(N: int = 160, seed: int = 1003, blocks_per_axis: int = 16, prob: float = 0.3,
-            high: float = 1e4) -> Problem:
+def checkerboard_3d(N: int = 160, seed: int = 1003, blocks_per_axis: int = 16,
+                    prob: float = 0.3, high: float = 1e4) -> Problem:
     """3D, N^3 interior, random checkerboard: blocks_per_axis^3 cubes (half-open cells), each
     cube a = `high` with probability `prob` else 1, drawn as default_rng(seed).random(
     (B,B,B)) < prob indexed [bz, by, bx]; convection (5,5,5); b = A u*, u* = sine product."""
@@ -324,10 +324,10 @@ def config3(N: int = 160, seed: int = 1003, blocks_per_axis: int = 16, prob: flo
         return field[bz, by, bx]
 
     return assemble((N, N, N), diff, (5.0, 5.0, 5.0), u_star_fn=_sine_product,
-                    name=f"config3_N{N}_seed{seed}")
+                    name=f"checkerboard_3d_N{N}_seed{seed}")
 
 
-def config4_specs(count: int = 512, seed: int = 1004, n_min: int = 32, n_max: int = 96):
+def batch_specs(count: int = 512, seed: int = 1004, n_min: int = 32, n_max: int = 96):
     """Recipe of the batch workload: for system i, in order, from numpy's default_rng(seed):
     dimension d uniform in {2, 3}; side N uniform in [n_min, n_max] (N^d interior nodes);
     jump a_hi = 10^U(2, 6); convection components U(0, 30) (d of them); a box (each axis an
@@ -347,7 +347,7 @@ def config4_specs(count: int = 512, seed: int = 1004, n_min: int = 32, n_max: in
     return specs
 
 
-def config4_system(spec) -> Problem:
+def batch_system(spec) -> Problem:
     """Assemble one batch system from its spec: a = jump inside the box (the open interval of
     each axis, tested exactly with integers: lo/1000 < q/den < hi/1000), 1 elsewhere;
     b = A u* with u* the sine product."""
@@ -363,7 +363,7 @@ def config4_system(spec) -> Problem:
         return np.where(inside, jump, 1.0)
 
     return assemble(spec["dims"], diff, spec["conv"], u_star_fn=_sine_product,
-                    name=f"config4_{spec['seed']}_{spec['index']}")
+                    name=f"batch_{spec['seed']}_{spec['index']}")
 
 
 # ---------------------------------------------------------------------------------------

@@ -1,7 +1,7 @@
-"""Write tests/golden/c2_oracle.json: the FP64 oracle's results on the 80^3 benchmark system.
+"""Write tests/golden/slabs80_oracle.json: the FP64 oracle's results on the 80^3 benchmark system.
 
 Calls only the oracle (and the seeded generator). Re-run after any change to the oracle's
-arithmetic or to the generator: `python tests/golden/make_c2_golden.py`. Takes ~2 minutes.
+arithmetic or to the generator: `python tests/golden/make_slabs80_golden.py`. Takes ~2 minutes.
 """
 import json
 import os
@@ -21,9 +21,9 @@ N_SAMPLE = 512
 
 
 def main():
-    P = problems.config2()
+    P = problems.slabs_3d()
     idx = np.sort(np.random.default_rng(SAMPLE_SEED).choice(P.n, size=N_SAMPLE, replace=False))
-    out = {"workload": "config2: 80^3, 8 log-uniform slabs (seed 1002), convection (20,-10,5)",
+    out = {"workload": "80^3, 8 log-uniform slabs (seed 1002), convection (20,-10,5)",
            "n": P.n, "nnz": P.nnz, "sample_seed": SAMPLE_SEED, "sample_idx": idx.tolist(),
            "runs": {}}
     for p in (2, 1):
@@ -45,7 +45,7 @@ def main():
                 "err_vs_u_star": float(np.linalg.norm(x - P.u_star) / np.linalg.norm(P.u_star)),
                 "oracle_seconds": time.time() - t}
             print(key, info, f"{time.time() - t:.1f}s", flush=True)
-    with open(os.path.join(HERE, "c2_oracle.json"), "w") as f:
+    with open(os.path.join(HERE, "slabs80_oracle.json"), "w") as f:
         json.dump(out, f, indent=1)
 
 

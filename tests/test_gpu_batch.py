@@ -49,10 +49,10 @@ def scaled(G, P, p=2, stencil=True):
 def systems(G):
     """A mix of kinds and sizes: 3D and 2D stencils, a CSR system, GS(1) with stop weights,
     ragged row counts, a tiny system."""
-    specs = problems.config4_specs(6, seed=7, n_min=6, n_max=20)
+    specs = problems.batch_specs(6, seed=7, n_min=6, n_max=20)
     out = []
     for i, sp in enumerate(specs):
-        P = problems.config4_system(sp)
+        P = problems.batch_system(sp)
         out.append(scaled(G, P, p=1 if i == 2 else 2, stencil=(i != 3)))
     out.append(scaled(G, problems.laplacian((13, 11, 7), conv=(40.0, -25.0, 10.0))))
     out.append(scaled(G, problems.laplacian((3, 2)), stencil=False))
@@ -165,7 +165,7 @@ def test_engine_invalid_csr_system_reported(G):
 
 
 def test_batch_system_matches_oracle(G):
-    P = problems.config4_system(problems.config4_specs(1, seed=11, n_min=14, n_max=14)[0])
+    P = problems.batch_system(problems.batch_specs(1, seed=11, n_min=14, n_max=14)[0])
     vo, bo, _, _ = oracle.gs_scale(P, P.b, 2)
     S = P.copy()
     S.val, S.b = vo, bo
@@ -189,11 +189,11 @@ def test_engine_gs_stage_equals_solo(G, graph):
     """GS(p) inside the engine (first chunk) + Bi-CGSTAB == gsk_gs_scale (+ stencil packing)
     + gsk_bicgstab, bit for bit, for stencil and CSR systems, p = 2 and p = 1."""
     import torch
-    specs = problems.config4_specs(5, seed=9, n_min=8, n_max=24)
+    specs = problems.batch_specs(5, seed=9, n_min=8, n_max=24)
     eng = G.Engine(max_rows=1 << 17, max_systems=8, graph=graph)
     ref, xs = {}, {}
     for i, sp in enumerate(specs):
-        P = problems.config4_system(sp)
+        P = problems.batch_system(sp)
         p = 1 if i == 1 else 2
         stencil = i != 2
         A = G.CsrMatrix.from_problem(P)

@@ -51,10 +51,10 @@ def scaled(G, P, p=2, stencil=True):
 
 def systems(G):
     """3D and 2D stencils, a CSR system, GS(1) with stop weights, ragged and tiny sizes."""
-    specs = problems.config4_specs(5, seed=17, n_min=6, n_max=18)
+    specs = problems.batch_specs(5, seed=17, n_min=6, n_max=18)
     out = []
     for i, sp in enumerate(specs):
-        P = problems.config4_system(sp)
+        P = problems.batch_system(sp)
         out.append(scaled(G, P, p=1 if i == 2 else 2, stencil=(i != 3)))
     out.append(scaled(G, problems.laplacian((13, 11, 7), conv=(40.0, -25.0, 10.0))))
     out.append(scaled(G, problems.laplacian((3, 2)), stencil=False))
@@ -122,13 +122,13 @@ def test_gmres_engine_equals_solo(G, precision, graph):
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_gmres_engine_gs_stage_equals_solo(G, precision):
     import torch
-    specs = problems.config4_specs(4, seed=23, n_min=8, n_max=20)
+    specs = problems.batch_specs(4, seed=23, n_min=8, n_max=20)
     mixed = precision == "mixed"
     f = G.gmres_mixed if mixed else G.gmres
     eng = G.Engine(1 << 17, 8, graph=True, method="gmres", m=M, precision=precision)
     ref, syst, ps = {}, [], []
     for i, sp in enumerate(specs):
-        P = problems.config4_system(sp)
+        P = problems.batch_system(sp)
         p = 1 if i == 1 else 2
         stencil = i != 2
         Ms, bs, w = scaled(G, P, p, stencil)
@@ -144,7 +144,7 @@ def test_gmres_engine_gs_stage_equals_solo(G, precision):
 
 
 def test_mixed_engine_matches_oracle(G):
-    P = problems.config4_system(problems.config4_specs(1, seed=29, n_min=14, n_max=14)[0])
+    P = problems.batch_system(problems.batch_specs(1, seed=29, n_min=14, n_max=14)[0])
     vo, bo, _, _ = oracle.gs_scale(P, P.b, 2)
     S = P.copy()
     S.val, S.b = vo, bo

@@ -86,7 +86,7 @@ def test_identity_two_half_steps(G):
 
 @pytest.mark.parametrize("seed,p,stencil", [(41, 2, True), (43, 2, False), (47, 1, True)])
 def test_mixed_bicgstab_matches_oracle(G, seed, p, stencil):
-    P = problems.config4_system(problems.config4_specs(1, seed=seed, n_min=12, n_max=20)[0])
+    P = problems.batch_system(problems.batch_specs(1, seed=seed, n_min=12, n_max=20)[0])
     S, w = oracle_scaled(P, p)
     xo, io = oracle.bicgstab_ir(S, S.b, tol=1e-10, delta=DELTA, weights=None if p == 2 else w)
     A = G.CsrMatrix.from_problem(P)
@@ -110,10 +110,10 @@ def test_mixed_bicgstab_matches_oracle(G, seed, p, stencil):
 
 
 def test_mixed_bicgstab_independent_of_batch_and_repeatable(G):
-    specs = problems.config4_specs(4, seed=53, n_min=8, n_max=22)
+    specs = problems.batch_specs(4, seed=53, n_min=8, n_max=22)
     items = []
     for sp in specs:
-        P = problems.config4_system(sp)
+        P = problems.batch_system(sp)
         A = G.CsrMatrix.from_problem(P)
         items.append((G.stencil_from_csr(A, *grid_of(P)), dev(P.b), 2))
     xs_all, inf_all = solve(G, items, 1e-9)

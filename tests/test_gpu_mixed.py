@@ -53,9 +53,9 @@ def gpu_scaled(G, P, p=2, stencil=True):
 
 
 CASES = {
-    "c2_16_gs2": (lambda: problems.config2(16), 2, 30, 1e-10),
-    "c2_16_gs1": (lambda: problems.config2(16), 1, 30, 1e-10),
-    "c3_32": (lambda: problems.config3(32, blocks_per_axis=4), 2, 30, 1e-8),
+    "c2_16_gs2": (lambda: problems.slabs_3d(16), 2, 30, 1e-10),
+    "c2_16_gs1": (lambda: problems.slabs_3d(16), 1, 30, 1e-10),
+    "c3_32": (lambda: problems.checkerboard_3d(32, blocks_per_axis=4), 2, 30, 1e-8),
     "lap_ragged": (lambda: problems.laplacian((13, 11, 7), conv=(40.0, -25.0, 10.0)), 2, 20,
                    1e-10),
 }
@@ -84,7 +84,7 @@ def test_mixed_rounding_sensitive_case_matches_oracle_spread(G):
     Both sides solve the same 21 perturbed systems; all must converge and the medians agree
     within 10%. (FP64-ulp perturbations would not do: the FP32 copy of A erases most of them
     on the GPU while the oracle still sees them through its FP64 residual.)"""
-    P = problems.config1(24)
+    P = problems.square_jump_2d(24)
     S, _ = oracle_scaled(P)
     rng = np.random.default_rng(0)
     it_o, it_g = [], []
@@ -117,7 +117,7 @@ def test_mixed_stencil_and_csr_agree(G):
     # The FP32 copies hold the same values, but the stencil product runs two tiles per
     # workgroup (RPT = 2) and the CSR product one, so the dot products group their partial
     # sums differently: the runs agree to rounding, not bit for bit.
-    P = problems.config2(14)
+    P = problems.slabs_3d(14)
     Ms, bs, _ = gpu_scaled(G, P, stencil=True)
     Mc, bc, _ = gpu_scaled(G, P, stencil=False)
     xs, i_s = G.gmres_mixed(Ms, bs, m=30, tol=1e-10)
@@ -128,7 +128,7 @@ def test_mixed_stencil_and_csr_agree(G):
 
 
 def test_mixed_close_to_fp64_gpu(G):
-    P = problems.config2(20)
+    P = problems.slabs_3d(20)
     M, bs, _ = gpu_scaled(G, P)
     x64, i64 = G.gmres(M, bs, m=30, tol=1e-10)
     xm, im = G.gmres_mixed(M, bs, m=30, tol=1e-10)
@@ -138,7 +138,7 @@ def test_mixed_close_to_fp64_gpu(G):
 
 
 def test_mixed_workspace_and_errors(G):
-    P = problems.config2(10)
+    P = problems.slabs_3d(10)
     A = G.CsrMatrix.from_problem(P)
     M = G.stencil_from_csr(A, *grid_of(P))
     n = P.n
@@ -157,7 +157,7 @@ def test_mixed_workspace_and_errors(G):
 
 
 def test_mixed_repeatable(G):
-    P = problems.config2(12)
+    P = problems.slabs_3d(12)
     M, bs, _ = gpu_scaled(G, P)
     x1, i1 = G.gmres_mixed(M, bs, m=20, tol=1e-10)
     x2, i2 = G.gmres_mixed(M, bs, m=20, tol=1e-10)
@@ -167,7 +167,7 @@ def test_mixed_repeatable(G):
 
 @pytest.fixture(scope="module")
 def c3():
-    return problems.config3()
+    return problems.checkerboard_3d()
 
 
 def test_c3_full_size_mixed_vs_fp64(G, c3):

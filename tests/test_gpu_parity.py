@@ -64,8 +64,8 @@ SPMV_CASES = {
     "n1": lambda: problems.random_sparse(1, 1, 4),
     "ragged257": lambda: problems.random_sparse(257, 7, 5),
     "empty_rows": lambda: with_empty_rows(1500, 6),
-    "stencil3d": lambda: problems.config2(14),
-    "stencil2d": lambda: problems.config1(33),
+    "stencil3d": lambda: problems.slabs_3d(14),
+    "stencil2d": lambda: problems.square_jump_2d(33),
 }
 
 
@@ -86,8 +86,8 @@ def test_spmv_bitwise(G, case):
 GS_CASES = {
     "random": lambda: problems.random_sparse(2500, 5, 11),
     "long_rows": lambda: problems.random_sparse(600, 30, 12, max_row=500),
-    "config1": lambda: problems.config1(40),
-    "config2_small": lambda: problems.config2(20),
+    "square_jump_2d_40": lambda: problems.square_jump_2d(40),
+    "slabs_3d_20": lambda: problems.slabs_3d(20),
     "problem4": lambda: problems.problem4(12, 1e6),
     "ragged": lambda: problems.random_sparse(1031, 3, 13),
 }
@@ -110,7 +110,7 @@ def test_gs_scale_parity(G, case, p):
 
 
 def test_gs_scale_in_place(G):
-    P = problems.config1(20)
+    P = problems.square_jump_2d(20)
     A, b = up(G, P)
     S, bs, _, _ = G.gs_scale(A, b, 2, inplace=True)
     assert S.val.data_ptr() == A.val.data_ptr() and bs.data_ptr() == b.data_ptr()
@@ -156,7 +156,7 @@ def test_gs_scale_errors(G):
 @pytest.mark.parametrize("m", [1, 7, 20, 33])
 def test_arnoldi_parity(G, m):
     import torch
-    S, _, _ = oracle_scaled(problems.config1(24), 2)
+    S, _, _ = oracle_scaled(problems.square_jump_2d(24), 2)
     A, b = up(G, S)
     V, H, k = G.arnoldi(A, b, m)
     torch.cuda.synchronize()
@@ -182,9 +182,9 @@ def _check_solver(info, o_info, x, x_o, tol, sol_rtol):
 
 SOLVE_CASES = {
     # name: (problem maker, p, m, tol, bicgstab_sensitive)
-    "c2_16_gs2": (lambda: problems.config2(16), 2, 30, 1e-10, False),
-    "c2_16_gs1": (lambda: problems.config2(16, seed=5), 1, 30, 1e-10, False),
-    "c1_24_gs2": (lambda: problems.config1(24), 2, 20, 1e-10, False),
+    "c2_16_gs2": (lambda: problems.slabs_3d(16), 2, 30, 1e-10, False),
+    "c2_16_gs1": (lambda: problems.slabs_3d(16, seed=5), 1, 30, 1e-10, False),
+    "c1_24_gs2": (lambda: problems.square_jump_2d(24), 2, 20, 1e-10, False),
     "p4_10": (lambda: problems.problem4(10, 1e4), 2, 10, 1e-4, True),
     "lap_conv_ragged": (lambda: problems.laplacian((37, 29), conv=(15.0, -7.0)), 2, 15, 1e-10,
                         True),
@@ -272,7 +272,7 @@ def test_gmres_stagnation_matches(G):
     # GMRES(20) stagnates on the 2D jump problem (the paper's observation for restarted
     # GMRES, Table 1); both sides end at the cap with the same residual level.
     import torch
-    P = problems.config1(32)
+    P = problems.square_jump_2d(32)
     S, _, _ = oracle_scaled(P, 2)
     A, b = up(G, S)
     x, info = G.gmres(A, b, m=20, tol=1e-8, maxit=600)
@@ -317,7 +317,7 @@ def test_edge_cases(G):
     _, o_info = oracle.bicgstab(R, R.b, tol=1e-12)
     assert o_info.breakdown_test == info.breakdown_test
     # zero right-hand side: x0 = 0 is exact
-    S, _, _ = oracle_scaled(problems.config1(12), 2)
+    S, _, _ = oracle_scaled(problems.square_jump_2d(12), 2)
     A, b = up(G, S)
     z = torch.zeros_like(b)
     for solve in (lambda **k: G.gmres(A, z, m=10, **k), lambda **k: G.bicgstab(A, z, **k)):
@@ -343,7 +343,7 @@ def test_edge_cases(G):
     x, info = G.bicgstab(A, b, tol=1e-12)
     assert info.status == G.CONVERGED and host(x)[0] == pytest.approx(2.0, rel=1e-15)
     # nonzero initial guess
-    S2, _, _ = oracle_scaled(problems.config2(12), 2)
+    S2, _, _ = oracle_scaled(problems.slabs_3d(12), 2)
     A, b = up(G, S2)
     x0 = torch.linspace(-1, 1, S2.n, dtype=torch.float64, device="cuda")
     x, info = G.gmres(A, b, x0, m=30, tol=1e-10)
@@ -369,7 +369,7 @@ def test_solver_rejects_invalid_structure(G):
 
 def test_repeat_runs_are_bitwise_identical(G):
     import torch
-    S, _, _ = oracle_scaled(problems.config2(18), 2)
+    S, _, _ = oracle_scaled(problems.slabs_3d(18), 2)
     A, b = up(G, S)
     x1, i1 = G.bicgstab(A, b, tol=1e-10)
     x2, i2 = G.bicgstab(A, b, tol=1e-10)
@@ -384,11 +384,11 @@ def test_repeat_runs_are_bitwise_identical(G):
 
 @pytest.fixture(scope="module")
 def c2():
-    return problems.config2()
+    return problems.slabs_3d()
 
 
 def _golden_c2():
-    with open(os.path.join(HERE, "golden", "c2_oracle.json")) as f:
+    with open(os.path.join(HERE, "golden", "slabs80_oracle.json")) as f:
         return json.load(f)
 
 

@@ -30,8 +30,8 @@ def dev(a):
 
 def pool(G, count=6):
     out = []
-    for sp in problems.config4_specs(count, seed=21, n_min=8, n_max=28):
-        P = problems.config4_system(sp)
+    for sp in problems.batch_specs(count, seed=21, n_min=8, n_max=28):
+        P = problems.batch_system(sp)
         A = G.CsrMatrix.from_problem(P)
         d = list(P.dims) + [1] * (3 - len(P.dims))
         out.append({"A": A, "S": G.stencil_from_csr(A, *d), "b": dev(P.b), "grid": tuple(d),

@@ -45,8 +45,8 @@ def oracle_planes(P):
 
 
 CASES = {
-    "c2_3d_14": lambda: problems.config2(14),
-    "c1_2d_33": lambda: problems.config1(33),
+    "c2_3d_14": lambda: problems.slabs_3d(14),
+    "c1_2d_33": lambda: problems.square_jump_2d(33),
     "ragged_3d": lambda: problems.laplacian((13, 11, 7), conv=(40.0, -25.0, 10.0)),
     "ragged_2d": lambda: problems.laplacian((37, 29), conv=(30.0, 5.0)),
     "thin_2x2x3": lambda: problems.laplacian((2, 2, 3)),
@@ -102,7 +102,7 @@ def test_arnoldi_identical_on_stencil(G):
 
 def test_stencil_solution_matches_oracle(G):
     """The stencil path against the oracle directly (same bar as the CSR solver parity)."""
-    P = problems.config2(16)
+    P = problems.slabs_3d(16)
     S_ref = P.copy()
     S_ref.val, S_ref.b, _, _ = oracle.gs_scale(P, P.b, 2)
     xo, io = oracle.gmres(S_ref, S_ref.b, m=30, tol=1e-10, maxit=3000)

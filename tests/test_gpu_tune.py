@@ -21,8 +21,8 @@ def G():
 def batch(G, count=6):
     import torch
     out = []
-    for sp in problems.config4_specs(count, seed=31, n_min=8, n_max=24):
-        P = problems.config4_system(sp)
+    for sp in problems.batch_specs(count, seed=31, n_min=8, n_max=24):
+        P = problems.batch_system(sp)
         A = G.CsrMatrix.from_problem(P)
         d = list(P.dims) + [1] * (3 - len(P.dims))
         out.append({"S": G.stencil_from_csr(A, *d), "b": torch.from_numpy(P.b).cuda(),

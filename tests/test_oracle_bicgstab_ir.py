@@ -72,10 +72,10 @@ def test_float_storage_costs_iterations_on_jump_problems():
     # Measured, not a property of the method: on the batch recipe's jump problems (GS(2),
     # tol 1e-8), float storage with refinement takes clearly more Bi-CGSTAB iterations than
     # FP64 Bi-CGSTAB, more than the 1.9x fewer bytes per iteration could pay for.
-    specs = problems.config4_specs(6, seed=1004, n_min=20, n_max=32)
+    specs = problems.batch_specs(6, seed=1004, n_min=20, n_max=32)
     it64 = itir = 0
     for sp in specs:
-        S, _ = scaled(problems.config4_system(sp))
+        S, _ = scaled(problems.batch_system(sp))
         _, i64 = oracle.bicgstab(S, S.b, tol=1e-8)
         _, iir = oracle.bicgstab_ir(S, S.b, tol=1e-8, delta=1e-6)
         assert i64.status == oracle.CONVERGED
@@ -89,7 +89,7 @@ def test_divergence_ends_runs_and_stagnates():
     # run ends once its estimate exceeds rt / delta, and three refinement steps without
     # progress end the solve as stagnated with a finite residual (instead of 10,000 NaN
     # iterations). FP64 Bi-CGSTAB converges on the same system.
-    P = problems.config4_system(problems.config4_specs(1, seed=47, n_min=12, n_max=20)[0])
+    P = problems.batch_system(problems.batch_specs(1, seed=47, n_min=12, n_max=20)[0])
     S, w = scaled(P, 1)
     _, i64 = oracle.bicgstab(S, S.b, tol=1e-10, weights=w)
     assert i64.status == oracle.CONVERGED

@@ -93,7 +93,7 @@ def test_positive_row_scaling_invariance(p):
 
 @pytest.mark.parametrize("p", [1, 2])
 def test_idempotent(p):
-    P = problems.config1(16)
+    P = problems.square_jump_2d(16)
     v1, b1, _, _ = oracle.gs_scale(P, P.b, p)
     Q = P.copy()
     Q.val, Q.b = v1, b1
@@ -102,8 +102,8 @@ def test_idempotent(p):
     np.testing.assert_allclose(v2, v1, rtol=4e-16, atol=0)
 
 
-@pytest.mark.parametrize("maker", [lambda: problems.config1(10), lambda: problems.problem4(5, 1e4),
-                                   lambda: problems.config2(5)])
+@pytest.mark.parametrize("maker", [lambda: problems.square_jump_2d(10), lambda: problems.problem4(5, 1e4),
+                                   lambda: problems.slabs_3d(5)])
 def test_scaling_keeps_the_solution(maker):
     # D A x = D b has the solution of A x = b (section 2, eq. (2)); dense LU as the referee.
     P = maker()
@@ -118,7 +118,7 @@ def test_scaling_keeps_the_solution(maker):
 
 
 def test_weights_convert_to_the_gs2_metric():
-    P = problems.config2(6)
+    P = problems.slabs_3d(6)
     _, _, n1, w1 = oracle.gs_scale(P, P.b, 1)
     _, _, n2, w2 = oracle.gs_scale(P, P.b, 2)
     np.testing.assert_array_equal(w2, np.ones(P.n))

@@ -46,7 +46,7 @@ def test_spmv_exact_on_integers():
 # ---------------------------------------------------------------------------- Arnoldi
 
 def test_arnoldi_orthonormal_and_relation():
-    P, _, _ = scaled(problems.config1(12))
+    P, _, _ = scaled(problems.square_jump_2d(12))
     A = P.dense()
     m = 20
     V, H, k = oracle.arnoldi(P, P.b, m)
@@ -111,7 +111,7 @@ def test_full_gmres_terminates_within_n():
 def test_gmres_residual_monotone():
     # within a cycle the estimate never increases; across restarts the true residual never
     # increases (each cycle minimises over a space that contains the zero update)
-    P, _, _ = scaled(problems.config1(16))
+    P, _, _ = scaled(problems.square_jump_2d(16))
     m = 8
     x, info, hist = oracle.gmres(P, P.b, m=m, tol=1e-12, maxit=400, history=True)
     for c0 in range(0, len(hist), m):
@@ -139,7 +139,7 @@ def test_gmres_distinct_eigenvalues_terminate():
     assert info.status == oracle.CONVERGED and info.iters == 3
 
 
-@pytest.mark.parametrize("maker", [lambda: problems.config1(8), lambda: problems.config2(5),
+@pytest.mark.parametrize("maker", [lambda: problems.square_jump_2d(8), lambda: problems.slabs_3d(5),
                                    lambda: problems.problem4(5, 1e6)])
 def test_solvers_agree_with_dense_lu(maker):
     # forward error bounded by cond(A) * relative residual
@@ -155,7 +155,7 @@ def test_solvers_agree_with_dense_lu(maker):
 
 
 def test_zero_residual_and_maxit_zero():
-    P, _, _ = scaled(problems.config1(6))
+    P, _, _ = scaled(problems.square_jump_2d(6))
     x_lu = np.linalg.solve(P.dense(), P.b)
     for solve in (lambda **k: oracle.gmres(P, P.b, m=5, **k), lambda **k: oracle.bicgstab(P, P.b, **k)):
         x, info = solve(x0=np.zeros(P.n), maxit=0)
@@ -171,7 +171,7 @@ def test_zero_residual_and_maxit_zero():
 
 def test_stop_weights_measure_the_gs2_residual():
     # GS(1) run, stop test weighted to the GS(2)-scaled residual (section 2.2)
-    P0 = problems.config2(8)
+    P0 = problems.slabs_3d(8)
     P1, n1, w1 = scaled(P0, 1)
     _, n2, _ = scaled(P0, 2)
     for solve in (lambda: oracle.bicgstab(P1, P1.b, tol=1e-9, weights=w1),
@@ -231,7 +231,7 @@ def test_bicgstab_first_iteration_conditions(seed):
 
 
 def test_bicgstab_recursive_residual_tracks_the_true_one():
-    P, _, _ = scaled(problems.config1(16))
+    P, _, _ = scaled(problems.square_jump_2d(16))
     x, info = oracle.bicgstab(P, P.b, tol=1e-10)
     assert info.status == oracle.CONVERGED
     assert info.relres_true == pytest.approx(info.relres_recursive, rel=1e-3)
@@ -256,7 +256,7 @@ def test_ilu0_is_exact_lu_without_fill():
 
 
 def test_ilu0_matches_a_on_its_pattern():
-    P = problems.config1(10)
+    P = problems.square_jump_2d(10)
     lu = oracle.ilu0(P)
     F = P.copy()
     F.val = lu

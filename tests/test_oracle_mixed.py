@@ -50,9 +50,9 @@ def test_reaches_fp64_accuracy_beyond_float_precision():
 
 
 @pytest.mark.parametrize("maker,m,tol", [
-    (lambda: scaled(problems.config2(12)), 20, 1e-10),
+    (lambda: scaled(problems.slabs_3d(12)), 20, 1e-10),
     (lambda: scaled(problems.laplacian((16, 16, 8), conv=(20.0, -10.0, 5.0))), 30, 1e-10),
-    (lambda: scaled(problems.config1(20)), 40, 1e-8),
+    (lambda: scaled(problems.square_jump_2d(20)), 40, 1e-8),
 ])
 def test_cycle_count_close_to_fp64(maker, m, tol):
     # Each cycle reduces the residual by a factor far above float precision, so float
@@ -73,7 +73,7 @@ def test_first_cycle_matches_float_storage_bound():
     # After one cycle the FP64 residual can fall no further than the float rounding of the
     # data allows: run with a cap of m steps and check that the first cycle's true residual
     # is within a few float ulps' worth of the FP64 cycle's (whichever is larger).
-    P = scaled(problems.config2(10))
+    P = scaled(problems.slabs_3d(10))
     _, i64 = oracle.gmres(P, P.b, m=30, tol=1e-30, maxit=30)
     _, iir = oracle.gmres_ir(P, P.b, m=30, tol=1e-30, maxit=30)
     assert i64.iters == iir.iters == 30
