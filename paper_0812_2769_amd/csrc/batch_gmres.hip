@@ -55,7 +55,7 @@ __global__ __launch_bounds__(64) void k_bg_init(Ctl* c, int maxit, int m, double
   c->eps_b = eps_b;
   c->ref = 0.0;
   c->ratio = 1.0;
-  c->wnorm_pre = 0.0;
+  c->wnorm_pre[0] = c->wnorm_pre[1] = 0.0;
   c->last_rt = 0.0;
 }
 
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(BS) void k_bg_a(GArgs a, int j) {
     if (d.kind == MAT_STENCIL) {
       EmptyLds e;
       const StencilOpT<T> op{inner_coef<T>(d), d.n, d.nx, d.ny, d.nz, inner_ldp<T>(d)};
-      gmres_a_tile<JM, RV, R, StencilOpT<T>, T>(c, op, d.n, V, a.ldv, w, j, u,
+      gmres_a_tile<JM, RV, R, StencilOpT<T>, T>(c, op, d.n, V, a.ldv, w, j, j, u,
                                                 a.partials + d.unit_off, a.pstride, zero, -1,
                                                 0.0, e, red, red1);
     } else {
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(BS) void k_bg_a(GArgs a, int j) {
         const int lt = u * RV + q;
         if (lt >= d.ntiles) break;
         if (q) __syncthreads();
-        gmres_a_tile<JM, 1, R, CsrOpT<T>, T>(c, op, d.n, V, a.ldv, w, j, lt,
+        gmres_a_tile<JM, 1, R, CsrOpT<T>, T>(c, op, d.n, V, a.ldv, w, j, j, lt,
                                              a.partials + d.tile_off, a.pstride, zero, -1, 0.0,
                                              L, red, red1);
       }

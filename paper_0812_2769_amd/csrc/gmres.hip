@@ -3,26 +3,33 @@
 //
 // Section 2 of the paper: restarted GMRES whose Arnoldi step orthogonalises with a double
 // classical Gram-Schmidt pass. One Arnoldi step j (basis columns u_0..u_j stored unnormalised
-// with scale factors sigma_i, so v_i = sigma_i u_i) is three streaming launches, each
-// followed by a small finalize launch that reduces the per-workgroup partials:
+// with scale factors sigma_i, so v_i = sigma_i u_i) is three streaming launches and the small
+// finalize launches that reduce their per-workgroup partials:
 //
-//   A  w = A v_j (CSR tile product), partial c1 = V_j^T w, ||w||^2   reads A, V_j; writes w
-//      FA: c1_i, ||A v_j||                                          (j+2 workgroups)
-//   B  w -= V_j c1, partial c2 = V_j^T w                             reads V_j, w; writes w
+//   A  w = A u_j (tile product), partial V_j^T w, ||w||^2           reads A, V_j; writes w
+//      FA: c1_i = sigma_i (u_i . w), ||w||                          (j+2 workgroups)
+//   B  w -= V_j c1, partial V_j^T w                                  reads V_j, w; writes w
 //      FB: c2_i                                                     (j+1 workgroups)
-//   C  w -= V_j c2, u_{j+1} = w, partial ||w||^2                     reads V_j, w; writes u
-//      FC: h_{j+1,j}, Givens rotations, residual estimate, and at the end of a cycle the
-//          triangular solve for y                                   (1 workgroup)
+//   C  u_{j+1} = sigma_j (w - V_j c2), partial ||u_{j+1}||^2          reads V_j, w; writes u
+//      FC: h_{.,j} = sigma_j (c1 + c2), h_{j+1,j} = ||u_{j+1}||, Givens rotations, residual
+//          estimate, and at the end of a cycle the triangular solve for y   (1 workgroup)
 //
 // The basis is read three times per step instead of four: the update of pass 1 and the dot
 // products of pass 2 share one read, with the basis values held in registers. The division
 // v_{j+1} = w / h_{j+1,j} is never materialised: sigma_{j+1} = 1/h_{j+1,j} is folded into the
-// coefficients of later passes. At the end of a cycle X adds V_k y to x and R (+ FR)
-// recomputes the true residual r = b - A x, which either ends the solve or starts the next
-// cycle with u_0 = r.
+// coefficients of later passes. A multiplies the stored column u_j, not v_j, so that it needs
+// nothing from FC of step j-1; the factor sigma_j is applied by C and FC. That lets one launch
+// run FC of step j-1 (workgroup 0) beside FA of step j (the other workgroups), after A of
+// step j: five launches per step instead of six. A then runs before it is known whether step
+// j-1 ended the cycle; if it did, the cycle's remaining launches find the cycle ended and
+// store nothing, and the sums of that step are never read. The first step of each enqueued
+// run of steps uses the plain FA, the last one the plain FC. At the end of a cycle X adds
+// V_k y to x and R (+ FR) recomputes the true residual r = b - A x, which either ends the
+// solve or starts the next cycle with u_0 = r.
 //
-// Every launch checks the device-resident state and stores nothing if the solve has moved on,
-// so a whole cycle can be enqueued blindly; the host reads a small summary once per cycle.
+// Every launch checks the device-resident state and stores nothing if the solve has moved on
+// (the merged launch's FA workgroups excepted, see gmres_fin_a_body), so a whole cycle can be
+// enqueued blindly; the host reads a small summary once per cycle.
 //
 // Storage precision. The kernels are templated on T, the type the basis and w are stored in,
 // and on the operator of the inner product. With T = double and the caller's matrix this is
@@ -50,6 +57,8 @@ struct KArgs {
   // the compiler would move the later FP32 -> FP64 widening into the conditional load's
   // block, which makes each load wait for its data before the next one is issued.
   double zero;
+  // C's partials, apart from A's columns: A of step j runs before FC of step j-1 reads them.
+  double* cpartials;
 };
 
 __global__ __launch_bounds__(64) void k_init_ctl(Ctl* c, int maxit, int m, double tol,
@@ -80,7 +89,7 @@ __global__ __launch_bounds__(64) void k_init_ctl(Ctl* c, int maxit, int m, doubl
   c->ref = 0.0;
   c->ratio = 1.0;
   c->rho = c->rho_old = c->alpha = c->omega = c->beta = c->rh_norm = 0.0;
-  c->wnorm_pre = 0.0;
+  c->wnorm_pre[0] = c->wnorm_pre[1] = 0.0;
   c->last_rt = 0.0;
 }
 
@@ -112,23 +121,38 @@ __global__ __launch_bounds__(BS) void k_gmres_fin_residual(Ctl* c, const double*
   gmres_fin_residual_body(c, partials, nb, nb, has_w, mixed, flags[0] ? -1 : 0);
 }
 
-// A: w = sigma_j A u_j; partials of u_i . w (columns 0..j) and ||w||^2 (column j+1).
+// A: w = A u_j; partials of u_i . w (columns 0..j) and ||w||^2 (column j+1). jexp: the step
+// counter the step runs at (j, or j-1 when the merged launch follows).
 template <int JM, int RPT, class R, class Op, class T>
 __global__ __launch_bounds__(BS) void k_gmres_a(KArgs a, Op op, const T* __restrict__ V,
-                                                size_t ldv, T* __restrict__ w, int j) {
+                                                size_t ldv, T* __restrict__ w, int j, int jexp) {
   __shared__ typename Op::Lds L;
   __shared__ double red[NC_MAX * WAVES];
   __shared__ double red1[WAVES];
-  gmres_a_tile<JM, RPT, R, Op, T>(a.ctl, op, a.n, V, ldv, w, j, logical_block(), a.partials,
-                                  gridDim.x, (T)a.zero, a.pslot, a.inner_bytes, L, red, red1);
+  gmres_a_tile<JM, RPT, R, Op, T>(a.ctl, op, a.n, V, ldv, w, j, jexp, logical_block(),
+                                  a.partials, gridDim.x, (T)a.zero, a.pslot, a.inner_bytes, L,
+                                  red, red1);
 }
 
-// FA (j+2 workgroups): workgroup i <= j -> c1_i = sigma_i (u_i . w); workgroup j+1 -> ||A v_j||.
+// FA (j+2 workgroups): workgroup i <= j -> c1_i = sigma_i (u_i . w); workgroup j+1 -> ||w||.
 __global__ __launch_bounds__(BS) void k_gmres_fin_a(Ctl* c, const double* partials, int nb,
                                                     int j) {
   __shared__ double lds[WAVES];
   const int col = blockIdx.x;
   gmres_fin_a_body(c, partials + (size_t)col * nb, nb, j, col, lds);
+}
+
+// FC of step j-1 and FA of step j (j >= 1) in one launch of j+3 workgroups: workgroup 0 runs
+// FC on C's nbc partials, workgroup 1+i the FA column i on A's nba partials.
+__global__ __launch_bounds__(BS) void k_gmres_fin_ca(Ctl* c, const double* pa, int nba,
+                                                     const double* pc, int nbc, int j) {
+  if (blockIdx.x == 0) {
+    gmres_fin_c_body(c, pc, nbc, j - 1);
+    return;
+  }
+  __shared__ double lds[WAVES];
+  const int col = blockIdx.x - 1;
+  gmres_fin_a_body<true>(c, pa + (size_t)col * nba, nba, j, col, lds, pc, nbc);
 }
 
 // B: w -= sum_i c1_i v_i, then partials of u_i . w, sharing one read of the basis.
@@ -148,13 +172,13 @@ __global__ __launch_bounds__(BS) void k_gmres_fin_b(Ctl* c, const double* partia
   gmres_fin_b_body(c, partials + (size_t)col * nb, nb, j, col, lds);
 }
 
-// C: w -= sum_i c2_i v_i, u_{j+1} = w, partial ||w||^2.
+// C: u_{j+1} = sigma_j (w - sum_i c2_i v_i), partial ||u_{j+1}||^2 (into cpartials).
 template <int JM, int RPT, class R, class T>
 __global__ __launch_bounds__(BS) void k_gmres_c(KArgs a, T* __restrict__ V, size_t ldv,
                                                 const T* __restrict__ w, int j) {
   __shared__ double red[WAVES];
-  gmres_c_tile<JM, RPT, R, T>(a.ctl, a.n, V, ldv, w, j, logical_block(), a.partials, gridDim.x,
-                              (T)a.zero, a.pslot, red);
+  gmres_c_tile<JM, RPT, R, T>(a.ctl, a.n, V, ldv, w, j, logical_block(), a.cpartials,
+                              gridDim.x, (T)a.zero, a.pslot, red);
 }
 
 // FC (1 workgroup): Hessenberg column, Givens rotations, residual estimate; at the end of a
@@ -254,9 +278,12 @@ __global__ __launch_bounds__(64) void k_arnoldi_done(Ctl* c) {
 // ---------------------------------------------------------------------------------------
 static int pick_jm(int cols) { return cols <= 8 ? 8 : cols <= 16 ? 16 : cols <= 32 ? 32 : 64; }
 
+// Step j. merged: FC of step j-1 has not run yet (it runs in the launch after A); else FC of
+// every earlier step has run. FC of step j itself is left to the next step or to
+// launch_fin_c.
 template <class R, class Op, class T>
 static hipError_t launch_step(const KArgs& ka, const Op& op, int n, T* V, size_t ldv, T* w,
-                              int j, hipStream_t s) {
+                              int j, bool merged, hipStream_t s) {
   constexpr int RV = rpt_of<T>();                  // B, C: rows per thread
   constexpr int RA = Op::kRowwise ? RV : 1;        // A
   const int ga = grid_for(n, RA), gv = grid_for(n, RV);
@@ -270,14 +297,18 @@ static hipError_t launch_step(const KArgs& ka, const Op& op, int n, T* V, size_t
   if (kx.pslot >= 0) probe_end(s, kx.pslot);
 #define GSK_STEP(JMV)                                                                          \
   GSK_TIMED(KC_GMRES_A, hipLaunchKernelGGL((k_gmres_a<JMV, RA, R, Op, T>), dim3(ga), block, 0, \
-                                           s, kx, op, (const T*)V, ldv, w, j))                 \
-  hipLaunchKernelGGL(k_gmres_fin_a, dim3(j + 2), block, 0, s, ka.ctl, ka.partials, ga, j);     \
+                                           s, kx, op, (const T*)V, ldv, w, j,                  \
+                                           merged ? j - 1 : j))                                \
+  if (merged)                                                                                  \
+    hipLaunchKernelGGL(k_gmres_fin_ca, dim3(j + 3), block, 0, s, ka.ctl,                       \
+                       (const double*)ka.partials, ga, (const double*)ka.cpartials, gv, j);    \
+  else                                                                                         \
+    hipLaunchKernelGGL(k_gmres_fin_a, dim3(j + 2), block, 0, s, ka.ctl, ka.partials, ga, j);   \
   GSK_TIMED(KC_GMRES_B, hipLaunchKernelGGL((k_gmres_b<JMV, RV, R, T>), dim3(gv), block, 0, s,  \
                                            kx, (const T*)V, ldv, w, j))                        \
   hipLaunchKernelGGL(k_gmres_fin_b, dim3(j + 1), block, 0, s, ka.ctl, ka.partials, gv, j);     \
   GSK_TIMED(KC_GMRES_C, hipLaunchKernelGGL((k_gmres_c<JMV, RV, R, T>), dim3(gv), block, 0, s,  \
-                                           kx, V, ldv, (const T*)w, j))                        \
-  hipLaunchKernelGGL(k_gmres_fin_c, dim3(1), block, 0, s, ka.ctl, ka.partials, gv, j);
+                                           kx, V, ldv, (const T*)w, j))
   switch (jm) {
     case 8: GSK_STEP(8) break;
     case 16: GSK_STEP(16) break;
@@ -287,6 +318,26 @@ static hipError_t launch_step(const KArgs& ka, const Op& op, int n, T* V, size_t
 #undef GSK_STEP
 #undef GSK_TIMED
   return hipGetLastError();
+}
+
+// The plain FC of step j (after the last step of an enqueued run of steps).
+template <class T>
+static hipError_t launch_fin_c(const KArgs& ka, int n, int j, hipStream_t s) {
+  hipLaunchKernelGGL(k_gmres_fin_c, dim3(1), dim3(BS), 0, s, ka.ctl,
+                     (const double*)ka.cpartials, grid_for(n, rpt_of<T>()), j);
+  return hipGetLastError();
+}
+
+// Steps j0..j1-1 (j0 < j1): the first with the plain FA, the others with the merged launch,
+// and the plain FC of step j1-1 last, so that no step is left unfinished.
+template <class R, class Op, class T>
+static hipError_t launch_steps(const KArgs& ka, const Op& op, int n, T* V, size_t ldv, T* w,
+                               int j0, int j1, hipStream_t s) {
+  for (int j = j0; j < j1; ++j) {
+    const hipError_t e = launch_step<R>(ka, op, n, V, ldv, w, j, j > j0, s);
+    if (e != hipSuccess) return e;
+  }
+  return launch_fin_c<T>(ka, n, j1 - 1, s);
 }
 
 template <class Op, class T>
@@ -334,7 +385,8 @@ static SolveResult gmres_run(const Mat& A, const Op64& op, const OpT& opT, doubl
   const Geom g = make_geom(A.n);
   const size_t ldv = vec_ld(A.n);
   T* w = V + (size_t)(m + 1) * ldv;
-  KArgs ka{A.n, g.rpb, W.ctl, W.partials, A.bytes(), -1, inner_bytes, 0.0};
+  KArgs ka{A.n, g.rpb, W.ctl, W.partials, A.bytes(), -1, inner_bytes, 0.0,
+           W.partials + (size_t)(NC_MAX - 1) * g.nb};
   dim3 grid(g.nb), block(BS);
   if (launch_clear_flags(W.flags, s) != hipSuccess) return fail(-5);
   if (A.kind == MAT_CSR && launch_validate(A.csr, W.flags, s) != hipSuccess) return fail(-5);
@@ -361,9 +413,7 @@ static SolveResult gmres_run(const Mat& A, const Op64& op, const OpT& opT, doubl
   if ((long)2 * m >= prm.maxit) pace.cautious = true;
   constexpr int kPiece = 10;   // steps per piece of a cycle in cautious mode
   auto steps = [&](int j0, int j1) {
-    for (int j = j0; j < j1; ++j)
-      if (launch_step<R>(ka, opT, A.n, V, ldv, w, j, s) != hipSuccess) return false;
-    return true;
+    return launch_steps<R>(ka, opT, A.n, V, ldv, w, j0, j1, s) == hipSuccess;
   };
   auto tail = [&]() {
     KArgs kx = ka;
@@ -431,7 +481,8 @@ static SolveResult arnoldi_impl(const Mat& A, const Op& op, const double* r0, in
   Workspace W = carve(ws, A.n);
   const Geom g = make_geom(A.n);
   double* w = W.vecs;
-  KArgs ka{A.n, g.rpb, W.ctl, W.partials, A.bytes(), -1, A.bytes(), 0.0};
+  KArgs ka{A.n, g.rpb, W.ctl, W.partials, A.bytes(), -1, A.bytes(), 0.0,
+           W.partials + (size_t)(NC_MAX - 1) * g.nb};
   dim3 grid(g.nb), block(BS);
   if (launch_clear_flags(W.flags, s) != hipSuccess) return fail(-5);
   if (A.kind == MAT_CSR && launch_validate(A.csr, W.flags, s) != hipSuccess) return fail(-5);
@@ -441,8 +492,7 @@ static SolveResult arnoldi_impl(const Mat& A, const Op& op, const double* r0, in
   hipLaunchKernelGGL(k_arnoldi_start, grid, block, 0, s, ka, r0, V, (const int*)W.flags);
   hipLaunchKernelGGL(k_arnoldi_fin_start, dim3(1), block, 0, s, W.ctl,
                      (const double*)W.partials, g.nb, (const int*)W.flags);
-  for (int j = 0; j < m; ++j)
-    if (launch_step<R>(ka, op, A.n, V, (size_t)ldv, w, j, s) != hipSuccess) return fail(-5);
+  if (launch_steps<R>(ka, op, A.n, V, (size_t)ldv, w, 0, m, s) != hipSuccess) return fail(-5);
   const int fin_blocks = 1024;
   hipLaunchKernelGGL(k_arnoldi_finish, dim3(fin_blocks), block, 0, s, ka, V, (size_t)ldv, H, m);
   hipLaunchKernelGGL(k_arnoldi_done, dim3(1), dim3(64), 0, s, W.ctl);

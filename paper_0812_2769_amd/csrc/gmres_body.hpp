@@ -159,19 +159,22 @@ __device__ inline void gmres_fin_residual_body(Ctl* c, const double* partials, i
   c->sum.state = ST_RUNNING;
 }
 
-// A (workgroup lb, RPT tiles): w = sigma_j A u_j; partials of u_i . w (columns 0..j) and
-// ||w||^2 (column j+1). Loads are issued in the order they are needed (stencil operands, then
-// the basis values of the thread's rows) before the body tests whether it has work: the
-// control block is read alongside, so the test costs no round trip of its own. A body without
-// work stores nothing.
+// A (workgroup lb, RPT tiles): w = A u_j of the stored (unnormalised) column, so that A
+// needs no scalar of step j-1 (sigma_j enters the finalize launches and C instead); partials
+// of u_i . w (columns 0..j) and ||w||^2 (column j+1). Loads are issued in the order they are
+// needed (stencil operands, then the basis values of the thread's rows) before the body tests
+// whether it has work: the control block is read alongside, so the test costs no round trip
+// of its own. The step runs while the solve runs and its step counter reads jexp: j when the
+// finalize of step j-1 has run, j-1 when it runs later (the single solver's merged launch,
+// which discards this step's sums if step j-1 ends the cycle). A body without work stores
+// nothing.
 template <int JM, int RPT, class R, class Op, class T>
 __device__ inline void gmres_a_tile(Ctl* c, const Op& op, int n, const T* __restrict__ V,
-                                    size_t ldv, T* __restrict__ w, int j, int lb,
+                                    size_t ldv, T* __restrict__ w, int j, int jexp, int lb,
                                     double* __restrict__ partials, int pstride, T zero,
                                     int pslot, double inner_bytes, typename Op::Lds& L,
                                     double* red, double* red1) {
   const int state = c->sum.state, cj = c->j;
-  const double sg = c->sigma[j];
   const int t = threadIdx.x;
   const GatherXT<T> gx{V + (size_t)j * ldv};
   const R rd(V, ldv, j + 1);
@@ -193,18 +196,18 @@ __device__ inline void gmres_a_tile(Ctl* c, const Op& op, int n, const T* __rest
   // the solve runs (structure rejected by validation ends it): test first. A stencil product
   // reads clamped addresses only and goes ahead of the test.
   if constexpr (!Op::kRowwise) {
-    if (state != ST_RUNNING || cj != j) return;
+    if (state != ST_RUNNING || cj != jexp) return;
   }
   double y[RPT];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) y[q] = nq[q] > 0 ? op.finish(pre[q], rq[q], nq[q], gx, L) : 0.0;
   asm volatile("" ::: "memory");   // keeps the loads above ahead of the test below
-  if (state != ST_RUNNING || cj != j) return;
+  if (state != ST_RUNNING || cj != jexp) return;
   mark_work(c, pslot, inner_bytes + (double)sizeof(T) * n * (j + 2));
   double wr[RPT], nrm = 0.0;
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const T ws = (T)(sg * y[q]);
+    const T ws = (T)y[q];
     const bool mine = t < nq[q];
     wr[q] = mine ? (double)ws : 0.0;
     if (mine) w[rq[q] + t] = ws;
@@ -221,21 +224,36 @@ __device__ inline void gmres_a_tile(Ctl* c, const Op& op, int n, const T* __rest
   block_single_partial(nrm, partials, j + 1, pstride, lb, red1);
 }
 
-// FA (one workgroup per column col): col <= j -> c1_col = sigma_col (u_col . w);
-// col = j+1 -> ||A v_j||. `col_partials` is that column's `count` partials. The control words
-// are read together with the partials (one memory round trip) and only the store depends on
-// them.
+// FA (one workgroup per column col): col <= j -> c1_col = sigma_col (u_col . w), the pass-1
+// coefficient in the scale of w = A u_j (the Hessenberg entry is sigma_j c1_col), and its
+// update weight d1_col = c1_col sigma_col; col = j+1 -> ||w||. `col_partials` is that column's
+// `count` partials. The control words are read together with the partials (one memory round
+// trip) and only the store depends on them.
+// kMerged: the single solver's launch that also runs FC of step j-1 (in another workgroup),
+// which writes sigma_j, the step counter and the state while this body runs. The body then
+// reads none of them: column j computes sigma_j itself from C's `ccount` partials `cpart`,
+// with FC's arithmetic, and the stores are unconditional (if step j-1 ends the cycle, nothing
+// reads them before the next cycle rewrites them).
+template <bool kMerged = false>
 __device__ inline void gmres_fin_a_body(Ctl* c, const double* col_partials, int count, int j,
-                                        int col, double* lds) {
-  const int state = c->sum.state, cj = c->j;
-  const double sg = c->sigma[col];
+                                        int col, double* lds, const double* cpart = nullptr,
+                                        int ccount = 0) {
+  int state = ST_RUNNING, cj = j;
+  if constexpr (!kMerged) {
+    state = c->sum.state;
+    cj = c->j;
+  }
+  const bool own = kMerged && col == j;
+  const double sg0 = (col <= j && !own) ? c->sigma[col] : 0.0;
   const double s = column_sum(col_partials, count, lds);
+  const double sg = own ? 1.0 / sqrt(column_sum(cpart, ccount, lds)) : sg0;
   if (state != ST_RUNNING || cj != j || threadIdx.x != 0) return;
+  const int par = j & 1;
   if (col == j + 1) {
-    c->wnorm_pre = sqrt(s);
+    c->wnorm_pre[par] = sqrt(s);
   } else {
     const double c1 = sg * s;
-    c->c1[col] = c1;
+    c->c1[par][col] = c1;
     c->d1[col] = c1 * sg;
   }
 }
@@ -304,14 +322,16 @@ __device__ inline void gmres_fin_b_body(Ctl* c, const double* col_partials, int 
   c->d2[col] = c2 * sg;
 }
 
-// C: w -= sum_i c2_i v_i (weights d2_i = c2_i sigma_i), u_{j+1} = w, partial ||w||^2.
-// Operands are requested before the work test, as in A.
+// C: w -= sum_i c2_i v_i (weights d2_i = c2_i sigma_i), u_{j+1} = sigma_j w (back in the
+// scale of v_j, so that the stored columns keep norms of the order of the Hessenberg entries),
+// partial ||u_{j+1}||^2. Operands are requested before the work test, as in A.
 template <int JM, int RPT, class R, class T>
 __device__ inline void gmres_c_tile(Ctl* c, int n, T* __restrict__ V, size_t ldv,
                                     const T* __restrict__ w, int j, int lb,
                                     double* __restrict__ partials, int pstride, T zero,
                                     int pslot, double* red) {
   const int state = c->sum.state, cj = c->j;
+  const double sg = c->sigma[j];
   const int t = threadIdx.x;
   double d[JM];   // uniform across the launch: scalar loads
 #pragma unroll
@@ -342,7 +362,7 @@ __device__ inline void gmres_c_tile(Ctl* c, int n, T* __restrict__ V, size_t ldv
 #pragma unroll
     for (int i = 0; i < JM; ++i)
       if (i <= j) x = fma(-d[i], (double)u[i][q], x);
-    const T ws = (T)x;
+    const T ws = (T)(sg * x);
     const double wr = mine[q] ? (double)ws : 0.0;
     if (mine[q]) V[(size_t)(j + 1) * ldv + row[q]] = ws;
     nrm += wr * wr;
@@ -350,9 +370,9 @@ __device__ inline void gmres_c_tile(Ctl* c, int n, T* __restrict__ V, size_t ldv
   block_single_partial(nrm, partials, 0, pstride, lb, red);
 }
 
-// FC (one workgroup): Hessenberg column, Givens rotations, residual estimate; at the end of a
-// cycle the k x k triangular solve H y = g (y stored pre-multiplied by sigma). `partials` are
-// the `count` partials of C. Every control word the body needs is requested before the first
+// FC (one workgroup): Hessenberg column (h_ij = sigma_j (c1_i + c2_i), h_{j+1,j} = ||u_{j+1}||),
+// Givens rotations, residual estimate; at the end of a cycle the k x k triangular solve
+// H y = g (y stored pre-multiplied by sigma). `partials` are the `count` partials of C. Every control word the body needs is requested before the first
 // wait; the old rotations are applied in registers by one thread.
 __device__ inline void gmres_fin_c_body(Ctl* c, const double* partials, int count, int j) {
   __shared__ double lds[WAVES];
@@ -363,10 +383,12 @@ __device__ inline void gmres_fin_c_body(Ctl* c, const double* partials, int coun
   const int t = threadIdx.x;
   const int state = c->sum.state, cj = c->j;
   const int iters = c->sum.iters, maxit = c->maxit, m = c->m;
-  const double eps_b = c->eps_b, wpre = c->wnorm_pre, gj = c->g[j];
+  const int par = j & 1;
+  const double sgj = c->sigma[j];
+  const double eps_b = c->eps_b, wpre = sgj * c->wnorm_pre[par], gj = c->g[j];
   const double ratio = c->ratio, ref = c->ref, tol = c->tol;
   if (t <= j) {
-    s_h[t] = c->c1[t] + c->c2[t];
+    s_h[t] = (c->c1[par][t] + c->c2[t]) * sgj;
     s_cs[t] = c->cs[t];
     s_sn[t] = c->sn[t];
   }

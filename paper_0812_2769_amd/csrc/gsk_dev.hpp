@@ -77,10 +77,12 @@ struct Ctl {
   double last_rt;            // GMRES: relative true residual at the start of the cycle
   // Bi-CGSTAB scalars
   double rho, rho_old, alpha, omega, beta, rh_norm;
-  // GMRES: lazy column scales, orthogonalisation coefficients, Hessenberg + Givens
-  double wnorm_pre;
+  // GMRES: lazy column scales, orthogonalisation coefficients, Hessenberg + Givens. The
+  // pass-1 values of step j sit in slot j % 2: the single solver finalises step j-1 in the
+  // launch that reduces the pass-1 sums of step j.
+  double wnorm_pre[2];
   double sigma[MMAX + 1];
-  double c1[MMAX + 1];
+  double c1[2][MMAX + 1];
   double c2[MMAX + 1];
   double d1[MMAX + 1];     // c1_i sigma_i and c2_i sigma_i: the update weights of the stored
   double d2[MMAX + 1];     // (unnormalised) basis columns in the two CGS passes
