@@ -38,11 +38,11 @@ sys.path.insert(0, ROOT)
 METRIC = "solves/s at 1e-8 rel. residual, Krylov HBM GB/s vs peak, p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 VARIANTS = [(2, "bicgstab"), (2, "gmres30"), (1, "bicgstab"), (1, "gmres30")]
-KERNEL_NAMES = {"gmres_a": "k_gmres_a (CSR product + CGS2 pass-1 dots)",
+KERNEL_NAMES = {"gmres_a": "k_gmres_a (matrix product + CGS2 pass-1 dots)",
                 "gmres_b": "k_gmres_b (CGS2 pass-1 update + pass-2 dots)",
                 "gmres_c": "k_gmres_c (CGS2 pass-2 update + norm)",
-                "bicg_p": "k_bicg_p (p update + CSR product + dots)",
-                "bicg_s": "k_bicg_s (s + CSR product + dots)",
+                "bicg_p": "k_bicg_p (p update + matrix product + dots)",
+                "bicg_s": "k_bicg_s (s + matrix product + dots)",
                 "bicg_u": "k_bicg_u (x, r update + dots)",
                 "residual": "k_*_residual (true residual)",
                 "gmres_x": "k_gmres_x (x += V y)"}
@@ -53,8 +53,8 @@ METRIC_CHECKER = "Arnoldi steps/s, GMRES(30) on the 160^3 checkerboard system"
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; FETCH_SIZE scaled by 2.000 and WRITE_SIZE by
 # 1.000 from a plain 512 MiB copy), recorded with the hash of the kernel sources they were
 # measured on. A source change makes the figure stale and it is reported as null.
-TRAFFIC = {"gmres_a": {"bytes_per_launch": 96119418, "grid": 80, "operator": "stencil",
-                       "sources_sha256_16": "4ce2b697ee4c7e70"}}
+TRAFFIC = {"gmres_a": {"bytes_per_launch": 96121174, "grid": 80, "operator": "stencil",
+                       "sources_sha256_16": "8c777ff2cff53f4f"}}
 TRAFFIC_SOURCES = ["paper_0812_2769_amd/csrc/gmres.hip", "paper_0812_2769_amd/csrc/gmres_body.hpp",
                    "paper_0812_2769_amd/csrc/gsk_dev.hpp"]
 
