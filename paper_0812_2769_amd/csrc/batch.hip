@@ -579,7 +579,8 @@ static int units_of(const EngineConfig& cfg) {
 
 // Workspace carve-up. Bi-CGSTAB: system table, unit list, control blocks, partials (4 per
 // tile), the 7 vectors. GMRES: system table, unit list, control blocks, status copies,
-// partials (max(m+1, 3) per tile), basis (m+1 columns) and w, in FP64 or FP32.
+// partials (max(m+1, 3) columns per tile and one more for C), basis (m+1 columns) and w, in
+// FP64 or FP32.
 static EngineLayout engine_layout(const EngineConfig& cfg) {
   const int64_t max_tiles = (cfg.max_rows + BS - 1) / BS;
   const int64_t grid_tiles = (max_tiles + 7) / 8 * 8;
@@ -596,8 +597,7 @@ static EngineLayout engine_layout(const EngineConfig& cfg) {
     L.sums = off;
     off += align256(sizeof(Summary) * ns);
     L.partials = off;
-    const int cols = cfg.m + 1 > 3 ? cfg.m + 1 : 3;
-    off += align256(sizeof(double) * (size_t)cols * (size_t)grid_tiles);
+    off += align256(sizeof(double) * (size_t)gmres_partial_cols(cfg.m) * (size_t)grid_tiles);
     L.vecs = off;
     const size_t tb = cfg.mixed ? sizeof(float) : sizeof(double);
     off += align256(tb * (size_t)grid_tiles * BS * (size_t)(cfg.m + 1));
@@ -734,6 +734,7 @@ int engine_create(void* ws, size_t ws_bytes, const EngineConfig& cfg, hipStream_
     g.sums = reinterpret_cast<Summary*>(base + L.sums);
     g.partials = reinterpret_cast<double*>(base + L.partials);
     g.pstride = e->grid_tiles;
+    g.ccol = gmres_partial_cols(cfg.m) - 1;
     g.max_units = e->max_units;
     g.ldv = (size_t)e->grid_tiles * BS;
     const size_t tb = e->mixed ? sizeof(float) : sizeof(double);

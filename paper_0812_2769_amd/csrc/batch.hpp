@@ -82,6 +82,9 @@ __device__ inline void prepare_tile(const SysDesc& d, int lt, GsLds& L, int* bad
 }
 
 // Arguments of the GMRES engine's launches.
+// Partial columns of a GMRES(m) engine: A's j+2 <= m+1 (three for the residual), then C's.
+inline int gmres_partial_cols(int m) { return (m + 1 > 3 ? m + 1 : 3) + 1; }
+
 struct GArgs {
   const SysDesc* sys;
   const int* act;        // [2][max_units]: units of the admitted systems, then their slots
@@ -90,6 +93,7 @@ struct GArgs {
   Summary* sums;         // [max_systems]: copies of the control blocks' summaries
   double* partials;      // [columns][pstride]
   int pstride;           // partials per column (the engine's tile count)
+  int ccol;              // the column of C's partials, apart from A's (see batch_gmres.hip)
   int max_units;
   void* V;               // basis: m+1 columns of ldv values (double or float)
   void* w;               // ldv values

@@ -13,8 +13,11 @@
 // at the chunk's start, so step j of the chunk is step j of every running cycle and its
 // launches are instantiated for j like the single solver's. Around the m steps:
 //   prepare (GS stage, FP32 copy) -> start (residual of newly admitted systems)
-//   -> m x (A, FA, B, FB, C, FC) -> X (x += V y at the cycle's end) -> restart (true
-//   residual: convergence test, next cycle) -> summaries (control block -> status array).
+//   -> A_0, FA_0, B_0, FB_0, C_0, then for j >= 1: A_j, FC_{j-1} beside FA_j, B_j, FB_j, C_j
+//   -> FC_{m-1} -> X (x += V y at the cycle's end) -> restart (true residual: convergence
+//   test, next cycle) -> summaries (control block -> status array).
+// As in the single solver, A_j runs before FC_{j-1} (A multiplies the stored column), so C
+// keeps its partials in a column of its own (GArgs::ccol) that A does not write.
 #include "batch.hpp"
 #include "gmres_body.hpp"
 
@@ -144,9 +147,10 @@ __device__ inline size_t inner_ldp(const SysDesc& d) {
 }
 
 // A_j. A stencil product takes the unit's RV tiles at once (partials per unit); a CSR product
-// stages one tile at a time through LDS (partials per tile), as in the single solver.
+// stages one tile at a time through LDS (partials per tile), as in the single solver. jexp:
+// the step counter of a running step (j, or j-1 when FC_{j-1} runs after A_j).
 template <int JM, class R, class T>
-__global__ __launch_bounds__(BS) void k_bg_a(GArgs a, int j) {
+__global__ __launch_bounds__(BS) void k_bg_a(GArgs a, int j, int jexp) {
   constexpr int RV = rpt_of<T>();
   __shared__ TileLds L;
   __shared__ double red[NC_MAX * WAVES];
@@ -161,7 +165,7 @@ __global__ __launch_bounds__(BS) void k_bg_a(GArgs a, int j) {
     if (d.kind == MAT_STENCIL) {
       EmptyLds e;
       const StencilOpT<T> op{inner_coef<T>(d), d.n, d.nx, d.ny, d.nz, inner_ldp<T>(d)};
-      gmres_a_tile<JM, RV, R, StencilOpT<T>, T>(c, op, d.n, V, a.ldv, w, j, j, u,
+      gmres_a_tile<JM, RV, R, StencilOpT<T>, T>(c, op, d.n, V, a.ldv, w, j, jexp, u,
                                                 a.partials + d.unit_off, a.pstride, zero, -1,
                                                 0.0, e, red, red1);
     } else {
@@ -171,7 +175,7 @@ __global__ __launch_bounds__(BS) void k_bg_a(GArgs a, int j) {
         const int lt = u * RV + q;
         if (lt >= d.ntiles) break;
         if (q) __syncthreads();
-        gmres_a_tile<JM, 1, R, CsrOpT<T>, T>(c, op, d.n, V, a.ldv, w, j, j, lt,
+        gmres_a_tile<JM, 1, R, CsrOpT<T>, T>(c, op, d.n, V, a.ldv, w, j, jexp, lt,
                                              a.partials + d.tile_off, a.pstride, zero, -1, 0.0,
                                              L, red, red1);
       }
@@ -191,6 +195,28 @@ __global__ __launch_bounds__(BS) void k_bg_fin_a(GArgs a, int j) {
   const int off = per_tile ? d.tile_off : d.unit_off;
   const int count = per_tile ? d.ntiles : d.nunits;
   gmres_fin_a_body(a.ctl + s, a.partials + off + (size_t)col * a.pstride, count, j, col, lds);
+}
+
+// FC_{j-1} beside FA_j (j >= 1): grid (slots, j + 3); blockIdx.y 0 runs FC, 1 + col the FA
+// column col (see gmres_fin_a_body for what the two may not share).
+template <class T>
+__global__ __launch_bounds__(BS) void k_bg_fin_ca(GArgs a, int j) {
+  constexpr int RV = rpt_of<T>();
+  const int s = blockIdx.x;
+  const SysDesc d = a.sys[s];
+  if (d.ntiles == 0) return;
+  const double* pc = a.partials + (size_t)a.ccol * a.pstride + d.unit_off;
+  if (blockIdx.y == 0) {
+    gmres_fin_c_body(a.ctl + s, pc, d.nunits, j - 1);
+    return;
+  }
+  __shared__ double lds[WAVES];
+  const int col = blockIdx.y - 1;
+  const bool per_tile = RV == 1 || d.kind != MAT_STENCIL;
+  const int off = per_tile ? d.tile_off : d.unit_off;
+  const int count = per_tile ? d.ntiles : d.nunits;
+  gmres_fin_a_body<true>(a.ctl + s, a.partials + off + (size_t)col * a.pstride, count, j, col,
+                         lds, pc, d.nunits);
 }
 
 template <int JM, class R, class T>
@@ -225,7 +251,8 @@ __global__ __launch_bounds__(BS) void k_bg_c(GArgs a, int j) {
     T* V = static_cast<T*>(a.V) + d.row_off;
     const T* w = static_cast<const T*>(a.w) + d.row_off;
     gmres_c_tile<JM, RV, R, T>(a.ctl + s, d.n, V, a.ldv, w, j, unit - d.unit_off,
-                               a.partials + d.unit_off, a.pstride, (T)a.zero, -1, red);
+                               a.partials + (size_t)a.ccol * a.pstride + d.unit_off, a.pstride,
+                               (T)a.zero, -1, red);
   });
 }
 
@@ -234,7 +261,7 @@ __global__ __launch_bounds__(BS) void k_bg_fin_c(GArgs a, int j) {
   const int s = blockIdx.x;
   const SysDesc d = a.sys[s];
   if (d.ntiles == 0) return;
-  gmres_fin_c_body(a.ctl + s, a.partials + d.unit_off, d.nunits, j);
+  gmres_fin_c_body(a.ctl + s, a.partials + (size_t)a.ccol * a.pstride + d.unit_off, d.nunits, j);
 }
 
 template <class R, class T>
@@ -264,12 +291,14 @@ static hipError_t gmres_chunk(const GArgs& a, int m, int grid, int max_sys, hipS
   hipLaunchKernelGGL(k_bg_fin_residual, gs, block, 0, s, a);
   for (int j = 0; j < m; ++j) {
 #define GSK_BG_STEP(JMV)                                                                     \
-  hipLaunchKernelGGL((k_bg_a<JMV, R, T>), gt, block, 0, s, a, j);                            \
-  hipLaunchKernelGGL(k_bg_fin_a<T>, dim3(max_sys, j + 2), block, 0, s, a, j);                \
+  hipLaunchKernelGGL((k_bg_a<JMV, R, T>), gt, block, 0, s, a, j, j > 0 ? j - 1 : 0);         \
+  if (j > 0)                                                                                 \
+    hipLaunchKernelGGL(k_bg_fin_ca<T>, dim3(max_sys, j + 3), block, 0, s, a, j);             \
+  else                                                                                       \
+    hipLaunchKernelGGL(k_bg_fin_a<T>, dim3(max_sys, j + 2), block, 0, s, a, j);              \
   hipLaunchKernelGGL((k_bg_b<JMV, R, T>), gt, block, 0, s, a, j);                            \
   hipLaunchKernelGGL(k_bg_fin_b, dim3(max_sys, j + 1), block, 0, s, a, j);                   \
-  hipLaunchKernelGGL((k_bg_c<JMV, R, T>), gt, block, 0, s, a, j);                            \
-  hipLaunchKernelGGL(k_bg_fin_c, gs, block, 0, s, a, j);
+  hipLaunchKernelGGL((k_bg_c<JMV, R, T>), gt, block, 0, s, a, j);
     switch (pick_jm(j + 1)) {
       case 8: GSK_BG_STEP(8) break;
       case 16: GSK_BG_STEP(16) break;
@@ -278,6 +307,7 @@ static hipError_t gmres_chunk(const GArgs& a, int m, int grid, int max_sys, hipS
     }
 #undef GSK_BG_STEP
   }
+  hipLaunchKernelGGL(k_bg_fin_c, gs, block, 0, s, a, m - 1);
   hipLaunchKernelGGL((k_bg_x<R, T>), gt, block, 0, s, a);
   hipLaunchKernelGGL(k_bg_residual<T>, gt, block, 0, s, a);
   hipLaunchKernelGGL(k_bg_fin_residual, gs, block, 0, s, a);
