@@ -252,8 +252,9 @@ int gsk_bicgstab(const gsk_matrix* A, const double* b, double* x, double tol,
 
 /*
  * Measurement hook (not part of the method). Between gsk_probe_begin(c, k) and gsk_probe_end,
- * every k-th launch of kernel class c made by the solvers is timed: it is bracketed by a pair
- * of HIP events (created without a system-scope fence) on the solver's stream, and it carries
+ * every k-th launch of kernel class c made by the solvers is timed: it is launched with a pair
+ * of HIP events (hipExtLaunchKernel on the solver's stream, so the events take the dispatch's
+ * own start and end times), and it carries
  * a device slot in which it stores its algorithmic HBM bytes if it does work (a launch that
  * returns at once because the solve had already finished leaves it zero and is not counted).
  * Algorithmic bytes per launch, n rows, nnz nonzeros, FP64 values, int32 indices, step j of an

@@ -146,7 +146,6 @@ struct Probe {
   };
   std::vector<hipEvent_t> pool;
   std::vector<Timed> timed;
-  hipEvent_t open = nullptr;
   double total_ms = 0.0;
   long long launches = 0;
   long long busy = 0;
@@ -198,28 +197,19 @@ int probe_slot(int kernel_class) {
   return p.next_slot++;
 }
 
-void probe_begin(hipStream_t s) {
+bool probe_pair(int slot, hipEvent_t* start, hipEvent_t* stop) {
   Probe& p = probe_state();
   std::lock_guard<std::mutex> g(p.mu);
-  p.open = take_event(p);
-  if (p.open && hipEventRecord(p.open, s) != hipSuccess) {
-    p.pool.push_back(p.open);
-    p.open = nullptr;
+  hipEvent_t a = take_event(p);
+  hipEvent_t b = a ? take_event(p) : nullptr;
+  if (!b) {
+    if (a) p.pool.push_back(a);
+    return false;
   }
-}
-
-void probe_end(hipStream_t s, int slot) {
-  Probe& p = probe_state();
-  std::lock_guard<std::mutex> g(p.mu);
-  if (!p.open) return;
-  hipEvent_t e = take_event(p);
-  if (e && hipEventRecord(e, s) == hipSuccess) {
-    p.timed.push_back(Probe::Timed{p.open, e, slot});
-  } else {
-    p.pool.push_back(p.open);
-    if (e) p.pool.push_back(e);
-  }
-  p.open = nullptr;
+  p.timed.push_back(Probe::Timed{a, b, slot});
+  *start = a;
+  *stop = b;
+  return true;
 }
 
 // After a solve has synchronised its stream: add the durations and bytes of the timed
@@ -331,7 +321,6 @@ int gsk_probe_begin(int32_t kernel_class, int32_t sample_every) {
   p.next_slot = 0;
   p.every = sample_every;
   recycle(p);
-  p.open = nullptr;
   p.cls.store(kernel_class, std::memory_order_relaxed);
   return GSK_OK;
 }

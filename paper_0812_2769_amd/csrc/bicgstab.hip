@@ -421,9 +421,7 @@ static void launch_residual(const BArgs& a, const Op& op, int nb, const int* fla
                             hipStream_t s) {
   BArgs ax = a;
   ax.pslot = probe_slot(KC_RESIDUAL);
-  if (ax.pslot >= 0) probe_begin(s);
-  hipLaunchKernelGGL(k_bicg_residual<Op>, dim3(nb), dim3(BS), 0, s, ax, op, flags);
-  if (ax.pslot >= 0) probe_end(s, ax.pslot);
+  launch_probed(k_bicg_residual<Op>, dim3(nb), s, ax.pslot, ax, op, flags);
   hipLaunchKernelGGL(k_bicg_fin_residual, dim3(1), dim3(BS), 0, s, a.ctl,
                      (const double*)a.partials, nb, a.W ? 1 : 0, flags);
 }
@@ -435,19 +433,13 @@ static void launch_iteration(const BArgs& a, const Op& op, int nb, int par, hipS
   BArgs ax = a;
   ax.par = par;
   ax.pslot = probe_slot(KC_BICG_P);
-  if (ax.pslot >= 0) probe_begin(s);
-  hipLaunchKernelGGL(k_bicg_p<Op>, dim3(nb), dim3(BS), 0, s, ax, op);
-  if (ax.pslot >= 0) probe_end(s, ax.pslot);
+  launch_probed(k_bicg_p<Op>, dim3(nb), s, ax.pslot, ax, op);
   hipLaunchKernelGGL(k_bicg_fin_p, dim3(1), dim3(BS), 0, s, a.ctl, pt, nb);
   ax.pslot = probe_slot(KC_BICG_S);
-  if (ax.pslot >= 0) probe_begin(s);
-  hipLaunchKernelGGL(k_bicg_s<Op>, dim3(nb), dim3(BS), 0, s, ax, op);
-  if (ax.pslot >= 0) probe_end(s, ax.pslot);
+  launch_probed(k_bicg_s<Op>, dim3(nb), s, ax.pslot, ax, op);
   hipLaunchKernelGGL(k_bicg_fin_s, dim3(1), dim3(BS), 0, s, a.ctl, pt, nb, hw);
   ax.pslot = probe_slot(KC_BICG_U);
-  if (ax.pslot >= 0) probe_begin(s);
-  hipLaunchKernelGGL(k_bicg_u, dim3(nb), dim3(BS), 0, s, ax);
-  if (ax.pslot >= 0) probe_end(s, ax.pslot);
+  launch_probed(k_bicg_u, dim3(nb), s, ax.pslot, ax);
   hipLaunchKernelGGL(k_bicg_fin_u, dim3(1), dim3(BS), 0, s, a.ctl, pt, nb, hw);
 }
 

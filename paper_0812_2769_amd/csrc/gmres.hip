@@ -290,25 +290,20 @@ static hipError_t launch_step(const KArgs& ka, const Op& op, int n, T* V, size_t
   const int jm = pick_jm(j + 1);
   dim3 block(BS);
   KArgs kx = ka;
-#define GSK_TIMED(CLS, LAUNCH)           \
-  kx.pslot = probe_slot(CLS);            \
-  if (kx.pslot >= 0) probe_begin(s);     \
-  LAUNCH;                                \
-  if (kx.pslot >= 0) probe_end(s, kx.pslot);
 #define GSK_STEP(JMV)                                                                          \
-  GSK_TIMED(KC_GMRES_A, hipLaunchKernelGGL((k_gmres_a<JMV, RA, R, Op, T>), dim3(ga), block, 0, \
-                                           s, kx, op, (const T*)V, ldv, w, j,                  \
-                                           merged ? j - 1 : j))                                \
+  kx.pslot = probe_slot(KC_GMRES_A);                                                           \
+  launch_probed(k_gmres_a<JMV, RA, R, Op, T>, dim3(ga), s, kx.pslot, kx, op, (const T*)V, ldv, \
+                w, j, merged ? j - 1 : j);                                                     \
   if (merged)                                                                                  \
     hipLaunchKernelGGL(k_gmres_fin_ca, dim3(j + 3), block, 0, s, ka.ctl,                       \
                        (const double*)ka.partials, ga, (const double*)ka.cpartials, gv, j);    \
   else                                                                                         \
     hipLaunchKernelGGL(k_gmres_fin_a, dim3(j + 2), block, 0, s, ka.ctl, ka.partials, ga, j);   \
-  GSK_TIMED(KC_GMRES_B, hipLaunchKernelGGL((k_gmres_b<JMV, RV, R, T>), dim3(gv), block, 0, s,  \
-                                           kx, (const T*)V, ldv, w, j))                        \
+  kx.pslot = probe_slot(KC_GMRES_B);                                                           \
+  launch_probed(k_gmres_b<JMV, RV, R, T>, dim3(gv), s, kx.pslot, kx, (const T*)V, ldv, w, j);  \
   hipLaunchKernelGGL(k_gmres_fin_b, dim3(j + 1), block, 0, s, ka.ctl, ka.partials, gv, j);     \
-  GSK_TIMED(KC_GMRES_C, hipLaunchKernelGGL((k_gmres_c<JMV, RV, R, T>), dim3(gv), block, 0, s,  \
-                                           kx, V, ldv, (const T*)w, j))
+  kx.pslot = probe_slot(KC_GMRES_C);                                                           \
+  launch_probed(k_gmres_c<JMV, RV, R, T>, dim3(gv), s, kx.pslot, kx, V, ldv, (const T*)w, j);
   switch (jm) {
     case 8: GSK_STEP(8) break;
     case 16: GSK_STEP(16) break;
@@ -316,7 +311,6 @@ static hipError_t launch_step(const KArgs& ka, const Op& op, int n, T* V, size_t
     default: GSK_STEP(64) break;
   }
 #undef GSK_STEP
-#undef GSK_TIMED
   return hipGetLastError();
 }
 
@@ -346,10 +340,7 @@ static void launch_residual(const KArgs& ka, const Op& op, int nb, const double*
                             hipStream_t s) {
   KArgs kx = ka;
   kx.pslot = probe_slot(KC_RESIDUAL);
-  if (kx.pslot >= 0) probe_begin(s);
-  hipLaunchKernelGGL((k_gmres_residual<Op, T>), dim3(nb), dim3(BS), 0, s, kx, op, b, x, W, u0,
-                     flags);
-  if (kx.pslot >= 0) probe_end(s, kx.pslot);
+  launch_probed(k_gmres_residual<Op, T>, dim3(nb), s, kx.pslot, kx, op, b, x, W, u0, flags);
   hipLaunchKernelGGL(k_gmres_fin_residual, dim3(1), dim3(BS), 0, s, ka.ctl,
                      (const double*)ka.partials, nb, W ? 1 : 0, mixed, flags);
 }
@@ -418,10 +409,8 @@ static SolveResult gmres_run(const Mat& A, const Op64& op, const OpT& opT, doubl
   auto tail = [&]() {
     KArgs kx = ka;
     kx.pslot = probe_slot(KC_GMRES_X);
-    if (kx.pslot >= 0) probe_begin(s);
-    hipLaunchKernelGGL((k_gmres_x<rpt_of<T>(), R, T>), dim3(grid_for(A.n, rpt_of<T>())), block,
-                       0, s, kx, (const T*)V, ldv, x);
-    if (kx.pslot >= 0) probe_end(s, kx.pslot);
+    launch_probed(k_gmres_x<rpt_of<T>(), R, T>, dim3(grid_for(A.n, rpt_of<T>())), s, kx.pslot,
+                  kx, (const T*)V, ldv, x);
     launch_residual(ka, op, g.nb, b, x, prm.weights, V, W.flags, mixed, s);
     return hipGetLastError() == hipSuccess;
   };

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -176,13 +177,23 @@ struct Pacer {
 };
 
 // Measurement hook (gsk_probe_begin / gsk_probe_end). While a kernel class is selected, every
-// sample_every-th launch of that class gets a slot number: the host brackets it with a pair
-// of HIP events and the kernel records its algorithmic bytes in the slot if it did work. At
-// the end of each solve the working launches' durations and bytes are added to the totals.
+// sample_every-th launch of that class gets a slot number and a pair of HIP events that the
+// launch itself carries (hipExtLaunchKernel: the events take the dispatch's own start and end
+// times, with no marker packets around it), and the kernel records its algorithmic bytes in
+// the slot if it did work. At the end of each solve the working launches' durations and bytes
+// are added to the totals.
 void probe_solve_begin();                  // a new solve starts: slots restart at 0
 int probe_slot(int kernel_class);          // -1 if this launch is not timed
-void probe_begin(hipStream_t s);
-void probe_end(hipStream_t s, int slot);
+bool probe_pair(int slot, hipEvent_t* start, hipEvent_t* stop);   // events for a timed launch
 void probe_collect(const ProbeSlots* device_slots, hipStream_t s);
+
+// Launches kernel(args...) on s with BS-wide workgroups; a launch with a probe slot carries
+// that slot's timing events.
+template <class F, class... Args>
+inline void launch_probed(F kernel, dim3 grid, hipStream_t s, int slot, Args... args) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (slot >= 0 && !probe_pair(slot, &e0, &e1)) e0 = e1 = nullptr;
+  hipExtLaunchKernelGGL(kernel, grid, dim3(BS), 0, s, e0, e1, 0, args...);
+}
 
 }  // namespace gsk
