@@ -122,10 +122,75 @@ __device__ inline int logical_block() {
   return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
+// Lane exchanges within one wave on the vector ALU (no LDS crossbar, unlike a shuffle through
+// ds_bpermute). Within 16-lane rows they are DPP moves: quad_perm [1,0,3,2] and [2,3,0,1]
+// give lane l ^ 1 and l ^ 2, row_ror:8 gives l ^ 8, and l ^ 4 takes row_ror:12 (lane l + 4)
+// in lanes with bit 2 clear and row_ror:4 (lane l - 4) in the others. Across rows gfx950 has
+// v_permlane16_swap / v_permlane32_swap: swap(a, b) exchanges the odd rows (upper half) of a
+// with the even rows (lower half) of b.
+template <int M>
+__device__ inline int dpp_xor(int x, int lane) {
+  static_assert(M == 1 || M == 2 || M == 4 || M == 8, "DPP exchange within a row");
+  if constexpr (M == 1) return __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);
+  if constexpr (M == 2) return __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);
+  if constexpr (M == 8) return __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false);
+  if constexpr (M == 4) {
+    const int up = __builtin_amdgcn_update_dpp(0, x, 0x12C, 0xF, 0xF, false);   // lane l + 4
+    const int dn = __builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false);   // lane l - 4
+    return (lane & 4) ? dn : up;
+  }
+  return x;
+}
+
+// (a', b') = swap(a, b) on both 32-bit halves of a double: a' keeps a in the lower half of
+// the lane group (row pair for M = 16, wave half for M = 32) and takes b's lower half in the
+// upper one; b' takes a's upper half in the lower one and keeps b in the upper one.
+template <int M>
+__device__ inline void lane_swap(double& a, double& b) {
+  static_assert(M == 16 || M == 32, "swap across rows");
+  const unsigned alo = __double2loint(a), ahi = __double2hiint(a);
+  const unsigned blo = __double2loint(b), bhi = __double2hiint(b);
+  if constexpr (M == 32) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+    a = __hiloint2double((int)hi[0], (int)lo[0]);
+    b = __hiloint2double((int)hi[1], (int)lo[1]);
+  } else {
+    const auto lo = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+    a = __hiloint2double((int)hi[0], (int)lo[0]);
+    b = __hiloint2double((int)hi[1], (int)lo[1]);
+  }
+}
+
+// The value of x in lane (lane ^ M), M a power of two below 64.
+template <int M>
+__device__ inline double xor_lanes(double x, int lane) {
+  if constexpr (M >= 16) {
+    double a = x, b = x;
+    lane_swap<M>(a, b);            // lower half: b = partner's x; upper half: a = partner's x
+    return (lane & M) ? a : b;
+  } else {
+    const int lo = dpp_xor<M>(__double2loint(x), lane);
+    const int hi = dpp_xor<M>(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
+  }
+}
+
+template <int M>
+struct WaveButterfly {
+  __device__ static inline double run(double v, int lane) {
+    v += xor_lanes<M>(v, lane);
+    return WaveButterfly<M / 2>::run(v, lane);
+  }
+};
+template <>
+struct WaveButterfly<0> {
+  __device__ static inline double run(double v, int) { return v; }
+};
+
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  return WaveButterfly<32>::run(v, threadIdx.x & 63);
 }
 
 // Reduce NC per-thread values over the workgroup and store them as this workgroup's partial
@@ -162,12 +227,23 @@ __device__ inline void block_partials(double (&acc)[NC], int nc, double* __restr
 template <int NV, int HALF, int BIT>
 struct Halving {
   __device__ static inline void run(double (&v)[NV], int lane) {
-    const bool hi = (lane & BIT) != 0;
+    if constexpr (BIT >= 16) {
+      // after the swap, a lane of the lower half holds its own v[k] and the partner's v[k],
+      // a lane of the upper half the partner's v[k + HALF] and its own: add the two
 #pragma unroll
-    for (int k = 0; k < HALF; ++k) {
-      const double send = hi ? v[k] : v[k + HALF];
-      const double keep = hi ? v[k + HALF] : v[k];
-      v[k] = keep + __shfl_xor(send, BIT, 64);
+      for (int k = 0; k < HALF; ++k) {
+        double a = v[k], b = v[k + HALF];
+        lane_swap<BIT>(a, b);
+        v[k] = a + b;
+      }
+    } else {
+      const bool hi = (lane & BIT) != 0;
+#pragma unroll
+      for (int k = 0; k < HALF; ++k) {
+        const double send = hi ? v[k] : v[k + HALF];
+        const double keep = hi ? v[k + HALF] : v[k];
+        v[k] = keep + xor_lanes<BIT>(send, lane);
+      }
     }
     Halving<NV, HALF / 2, BIT / 2>::run(v, lane);
   }
@@ -183,10 +259,7 @@ __device__ inline double wave_halving_sum(double (&v)[NV]) {
   static_assert(NV >= 1 && NV <= 64 && (NV & (NV - 1)) == 0, "NV must be a power of two");
   const int lane = threadIdx.x & 63;
   Halving<NV, NV / 2, 32>::run(v, lane);
-  double r = v[0];
-#pragma unroll
-  for (int bit = 32 / (NV > 1 ? NV : 1); bit >= 1; bit >>= 1) r += __shfl_xor(r, bit, 64);
-  return r;
+  return WaveButterfly<(NV > 1 ? 32 / NV : 32)>::run(v[0], lane);
 }
 
 template <int NV>
