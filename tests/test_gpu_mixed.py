@@ -80,7 +80,7 @@ def test_mixed_matches_oracle(G, case):
 def test_mixed_rounding_sensitive_case_matches_oracle_spread(G):
     """Restarted GMRES on the 2D jump problem is chaotic under rounding: perturbing A at
     float level (relative 2^-23) spreads the oracle's mixed-precision step count over
-    478-604 and the GPU's over 400-602, so single runs cannot be compared step for step.
+    478-604 and the GPU's over 401-637, so single runs cannot be compared step for step.
     Both sides solve the same 21 perturbed systems; all must converge and the medians agree
     within 10%. (FP64-ulp perturbations would not do: the FP32 copy of A erases most of them
     on the GPU while the oracle still sees them through its FP64 residual.)"""
