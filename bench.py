@@ -431,8 +431,8 @@ def bench_serve(args, gsk, problems, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is described in DESIGN.md but not implemented", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); sharding a solve "
+              "over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
