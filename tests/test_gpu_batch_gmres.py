@@ -158,6 +158,22 @@ def test_mixed_engine_matches_oracle(G):
     eng.close()
 
 
+@pytest.mark.parametrize("precision,rows", [("fp64", 13 << 20), ("mixed", 27 << 20)])
+def test_gmres_engine_basis_beyond_2gib(G, precision, rows):
+    """An engine whose basis (m+1 columns over its whole row space) exceeds 2^31 bytes reads it
+    with 64-bit addresses; a few small systems in it still return the single solves' bits."""
+    width = 8 if precision == "fp64" else 4
+    assert (M + 1) * width * rows >= 2 ** 31
+    syst = systems(G)[:4]
+    tol = 1e-10
+    ref = solo(G, syst, precision == "mixed", tol)
+    eng = G.Engine(rows, 4, graph=True, method="gmres", m=M, precision=precision)
+    xs, res, _ = run_engine(G, eng, syst, tol)
+    for k in range(len(syst)):
+        same((host(xs[k]), res[k]), ref[k], (precision, k))
+    eng.close()
+
+
 def test_gmres_engine_rejects_bad_systems(G):
     import torch
     P = problems.laplacian((8, 8))
