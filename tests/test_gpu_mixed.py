@@ -53,9 +53,9 @@ def gpu_scaled(G, P, p=2, stencil=True):
 
 
 CASES = {
-    "c2_16_gs2": (lambda: problems.slabs_3d(16), 2, 30, 1e-10),
-    "c2_16_gs1": (lambda: problems.slabs_3d(16), 1, 30, 1e-10),
-    "c3_32": (lambda: problems.checkerboard_3d(32, blocks_per_axis=4), 2, 30, 1e-8),
+    "slabs_3d_16_gs2": (lambda: problems.slabs_3d(16), 2, 30, 1e-10),
+    "slabs_3d_16_gs1": (lambda: problems.slabs_3d(16), 1, 30, 1e-10),
+    "checkerboard_3d_32": (lambda: problems.checkerboard_3d(32, blocks_per_axis=4), 2, 30, 1e-8),
     "lap_ragged": (lambda: problems.laplacian((13, 11, 7), conv=(40.0, -25.0, 10.0)), 2, 20,
                    1e-10),
 }
@@ -166,18 +166,18 @@ def test_mixed_repeatable(G):
 
 
 @pytest.fixture(scope="module")
-def c3():
+def checker160():
     return problems.checkerboard_3d()
 
 
-def test_c3_full_size_mixed_vs_fp64(G, c3):
+def test_checker160_full_size_mixed_vs_fp64(G, checker160):
     """160^3 checkerboard system (n = 4,096,000), GS(2) then GMRES(30), the configuration's
     own workload. Unpreconditioned restarted GMRES(30) needs far more than the paper's
     10,000-step cap to reach 1e-8 here (about 6e-5 after 3,000 steps), so the check runs 20
     cycles: the mixed solver must track FP64 GMRES(30) (true residuals within a factor 2 after
     the same 600 steps), and the residual it reports must equal the FP64 residual of the
     returned solution recomputed independently by the oracle."""
-    P = c3
+    P = checker160
     M, bs, _ = gpu_scaled(G, P)
     x64, i64 = G.gmres(M, bs, m=30, tol=1e-8, maxit=600)
     xm, im = G.gmres_mixed(M, bs, m=30, tol=1e-8, maxit=600)

@@ -182,8 +182,8 @@ def _check_solver(info, o_info, x, x_o, tol, sol_rtol):
 
 SOLVE_CASES = {
     # name: (problem maker, p, m, tol, bicgstab_sensitive)
-    "c2_16_gs2": (lambda: problems.slabs_3d(16), 2, 30, 1e-10, False),
-    "c2_16_gs1": (lambda: problems.slabs_3d(16, seed=5), 1, 30, 1e-10, False),
+    "slabs_3d_16_gs2": (lambda: problems.slabs_3d(16), 2, 30, 1e-10, False),
+    "slabs_3d_16_gs1": (lambda: problems.slabs_3d(16, seed=5), 1, 30, 1e-10, False),
     "c1_24_gs2": (lambda: problems.square_jump_2d(24), 2, 20, 1e-10, False),
     "p4_10": (lambda: problems.problem4(10, 1e4), 2, 10, 1e-4, True),
     "lap_conv_ragged": (lambda: problems.laplacian((37, 29), conv=(15.0, -7.0)), 2, 15, 1e-10,
@@ -383,11 +383,11 @@ def test_repeat_runs_are_bitwise_identical(G):
 # ------------------------------------------------------------------ full benchmark size
 
 @pytest.fixture(scope="module")
-def c2():
+def slabs80():
     return problems.slabs_3d()
 
 
-def _golden_c2():
+def _golden_slabs80():
     with open(os.path.join(HERE, "golden", "slabs80_oracle.json")) as f:
         return json.load(f)
 
@@ -402,9 +402,9 @@ def _sub_rows(P, rows):
                             P.b[rows].copy()), sel
 
 
-def test_c2_full_size_gs_and_spmv_sampled(G, c2):
+def test_slabs80_full_size_gs_and_spmv_sampled(G, slabs80):
     import torch
-    P = c2
+    P = slabs80
     A, b = up(G, P)
     rows = np.sort(np.random.default_rng(3).choice(P.n, size=4000, replace=False))
     rows = np.unique(np.concatenate([rows, [0, P.n - 1]]))
@@ -426,15 +426,15 @@ def test_c2_full_size_gs_and_spmv_sampled(G, c2):
 
 @pytest.mark.parametrize("operator", ["stencil", "csr"])
 @pytest.mark.parametrize("key", ["gs2_bicgstab", "gs2_gmres30", "gs1_bicgstab", "gs1_gmres30"])
-def test_c2_full_size_solves_match_oracle(G, c2, key, operator):
+def test_slabs80_full_size_solves_match_oracle(G, slabs80, key, operator):
     """The bench's four solves at full size, in the bench's launch configuration (GS(p) out of
     place, then, for the stencil operator, packing of the scaled matrix)."""
     import torch
-    gold = _golden_c2()
+    gold = _golden_slabs80()
     run = gold["runs"][key]
     idx = np.array(gold["sample_idx"])
     p = 2 if key.startswith("gs2") else 1
-    P = c2
+    P = slabs80
     A, b = up(G, P)
     As, bs, _, w = G.gs_scale(A, b, p, want_weights=True)
     if operator == "stencil":

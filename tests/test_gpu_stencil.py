@@ -45,7 +45,7 @@ def oracle_planes(P):
 
 
 CASES = {
-    "c2_3d_14": lambda: problems.slabs_3d(14),
+    "slabs_3d_14": lambda: problems.slabs_3d(14),
     "c1_2d_33": lambda: problems.square_jump_2d(33),
     "ragged_3d": lambda: problems.laplacian((13, 11, 7), conv=(40.0, -25.0, 10.0)),
     "ragged_2d": lambda: problems.laplacian((37, 29), conv=(30.0, 5.0)),
@@ -75,7 +75,7 @@ def _scaled_pair(G, P, p):
     return As, G.stencil_from_csr(As, nx, ny, nz), bs, w
 
 
-@pytest.mark.parametrize("case,p", [("c2_3d_14", 2), ("c2_3d_14", 1), ("ragged_3d", 2),
+@pytest.mark.parametrize("case,p", [("slabs_3d_14", 2), ("slabs_3d_14", 1), ("ragged_3d", 2),
                                     ("c1_2d_33", 2), ("ragged_2d", 1)])
 def test_solvers_identical_on_stencil(G, case, p):
     P = CASES[case]()
