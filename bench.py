@@ -570,6 +570,29 @@ def main():
             gsk.probe_begin(cls)
             step({k: [] for k in lat}, {})
             kernels[cls] = achieved(gsk.probe_end())
+        # the product alone (gsk_spmv) on the GS(2)-scaled matrix: CSR, and the stencil planes
+        # when they are the operator; algorithmic bytes = matrix + x once + y
+        gs(2)
+        products = [("spmv_csr", As, 12.0 * P.nnz + 4.0 * (n + 1) + 16.0 * n)]
+        if stencil:
+            pack()
+            products.append(("spmv_stencil", Ss, 56.0 * n + 16.0 * n))
+        xs, ys = b_s.clone(), torch.empty_like(b_s)
+        for name, Mx, nbytes in products:
+            for _ in range(3):
+                gsk.spmv(Mx, xs, out=ys)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(50):
+                gsk.spmv(Mx, xs, out=ys)
+            e1.record()
+            e1.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / 50
+            kernels[name] = {"achieved_GBs": round(nbytes / us / 1e3, 1),
+                             "avg_launch_us": round(us, 3), "bytes_per_launch": int(nbytes),
+                             "launches": 50, "note": "50 launches back to back, events around "
+                                                     "all of them"}
 
     for key, info in infos.items():
         if info.status != gsk.CONVERGED and not checker:
