@@ -71,3 +71,14 @@ def test_traffic_record_applies_only_to_its_workload():
     assert bench.traffic_for("gmres_b", rec["grid"], rec["operator"]) is None
     got = bench.traffic_for("gmres_a", rec["grid"], rec["operator"])
     assert got in (None, rec["bytes_per_launch"])   # None once the kernel sources change
+
+
+def test_tuner_rejects_bad_candidates():
+    """Candidate shapes are checked before anything runs on the device."""
+    from paper_0812_2769_amd import tune
+    with pytest.raises(ValueError):
+        tune.tune_engine([], shapes=(3,), chunks=(8,))
+    with pytest.raises(ValueError):
+        tune.tune_engine([], shapes=(1,), chunks=(5,))
+    with pytest.raises(ValueError):
+        tune.tune_engine([], shapes=(1,), chunks=(0,))
