@@ -99,15 +99,16 @@ class GmresEngineWorker(threading.Thread):
     each finished request. Results equal gsk_gmres (or gsk_gmres_mixed) on the same system."""
 
     def __init__(self, q: queue.Queue, device, t0: float, max_rows: int, max_systems: int,
-                 m: int, precision: str, graph: bool, on_done: Callable):
+                 m: int, precision: str, graph: bool, on_done: Callable,
+                 engine_factory: Callable = gsk.Engine):
         super().__init__(daemon=True)
         self.q = q
         self.error = None
         self.t0 = t0
         self.on_done = on_done
         self.m = m
-        self.engine = gsk.Engine(max_rows, max_systems, graph=graph, device=device,
-                                 method="gmres", m=m, precision=precision)
+        self.engine = engine_factory(max_rows, max_systems, graph=graph, device=device,
+                                     method="gmres", m=m, precision=precision)
 
     def run(self):
         waiting = collections.deque()
@@ -158,14 +159,17 @@ class Server:
                  graph: bool = True, gmres_rows: int = 0, m_max: int = 20, device="cuda",
                  gmres_lanes: int = 4, gmres_mode: str = "lanes",
                  gmres_precision: str = "fp64", gmres_engine_rows: int = 0,
-                 gmres_engine_systems: int = 64):
+                 gmres_engine_systems: int = 64, engine_factory: Callable = gsk.Engine):
         """gmres_mode "lanes": GMRES requests run one at a time on gmres_lanes host threads
         (workspaces for gmres_rows rows, any m <= m_max). "engine": they run in a GMRES(m_max)
         engine (gmres_precision "fp64" or "mixed") with room for gmres_engine_rows rows and
-        gmres_engine_systems systems."""
+        gmres_engine_systems systems. engine_factory(max_rows, max_systems, **options) builds
+        the engines (gsk.Engine; the scheduler's host-side tests pass a stand-in with the same
+        submit_gs / run / poll / close methods)."""
         self.device = torch.device(device)
-        self.engine = gsk.Engine(max_rows, max_systems, check_every=check_every, graph=graph,
-                                 device=self.device)
+        self.engine_factory = engine_factory
+        self.engine = engine_factory(max_rows, max_systems, check_every=check_every, graph=graph,
+                                     device=self.device)
         self.gmres_rows = gmres_rows
         self.m_max = m_max
         self.gmres_lanes = max(1, int(gmres_lanes))
@@ -194,7 +198,8 @@ class Server:
             if self.gmres_mode == "engine":
                 lanes = [GmresEngineWorker(gq, self.device, t0, self.gmres_engine_rows,
                                            self.gmres_engine_systems, self.m_max,
-                                           self.gmres_precision, self.graph, finished)]
+                                           self.gmres_precision, self.graph, finished,
+                                           self.engine_factory)]
             else:
                 lanes = [GmresLane(gq, self.device, t0, max(self.gmres_rows, 1), self.m_max,
                                    finished) for _ in range(self.gmres_lanes)]
