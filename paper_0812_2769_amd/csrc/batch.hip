@@ -130,11 +130,14 @@ __device__ inline void unit_rows2(const SysDesc& d, int unit, int& lt0, int (&ro
 }
 
 // The product over the two tiles of a unit. Stencil: both tiles' operands are loaded before
-// either sum (clamped addresses, so a tile past the end reads valid rows); CSR: one tile at a
-// time through LDS.
+// either sum (clamped addresses, so a tile past the end reads valid rows), and own[k] returns
+// the operands of the thread's own row in tile k, which the gather loaded already (own_ok);
+// CSR: one tile at a time through LDS, and the caller loads the row's operands itself.
 template <class G>
 __device__ inline void unit_product2(const SysDesc& d, const int (&row0)[2], const int (&nr)[2],
-                                     const G& g, TileLds& L, double (&y)[2]) {
+                                     const G& g, TileLds& L, double (&y)[2],
+                                     typename G::Raw (&own)[2], bool& own_ok) {
+  own_ok = false;
   if (d.kind == MAT_STENCIL) {
     const StencilOp op{d.coef, d.n, d.nx, d.ny, d.nz, (size_t)d.n};
     StencilOp::Pre<G> pre[2];
@@ -142,7 +145,11 @@ __device__ inline void unit_product2(const SysDesc& d, const int (&row0)[2], con
     for (int k = 0; k < 2; ++k) pre[k] = op.load(row0[k], nr[k], g);
     EmptyLds e;
 #pragma unroll
-    for (int k = 0; k < 2; ++k) y[k] = op.finish(pre[k], row0[k], nr[k], g, e);
+    for (int k = 0; k < 2; ++k) {
+      own[k] = pre[k].centre();   // the row's own operands, already gathered
+      y[k] = op.finish(pre[k], row0[k], nr[k], g, e);
+    }
+    own_ok = true;
   } else {
     const CsrOp op{d.rp, d.ci, d.val};
     for (int k = 0; k < 2; ++k) {
@@ -360,7 +367,9 @@ __global__ __launch_bounds__(BS) void k_batch_p(BArgsB a) {
       int lt0, row0[2], nr[2];
       unit_rows2(d, unit, lt0, row0, nr);
       double y[2];
-      unit_product2(d, row0, nr, G, L, y);
+      GatherPB::Raw own[2];
+      bool own_ok;
+      unit_product2(d, row0, nr, G, L, y, own, own_ok);
       const int t = threadIdx.x;
       for (int k = 0; k < 2; ++k) {
         if (nr[k] <= 0) break;
@@ -368,7 +377,7 @@ __global__ __launch_bounds__(BS) void k_batch_p(BArgsB a) {
         double acc[2] = {0.0, 0.0};
         if (t < nr[k]) {
           const int row = row0[k] + t;
-          a.p[q ^ 1][o + row] = G(row);
+          a.p[q ^ 1][o + row] = own_ok ? G.value(own[k]) : G(row);
           a.v[q ^ 1][o + row] = y[k];
           acc[0] = a.rh[o + row] * y[k];
           acc[1] = y[k] * y[k];
@@ -440,7 +449,9 @@ __global__ __launch_bounds__(BS) void k_batch_s(BArgsB a) {
       int lt0, row0[2], nr[2];
       unit_rows2(d, unit, lt0, row0, nr);
       double y[2];
-      unit_product2(d, row0, nr, G, L, y);
+      GatherSB::Raw own[2];
+      bool own_ok;
+      unit_product2(d, row0, nr, G, L, y, own, own_ok);
       const int t = threadIdx.x;
       for (int k = 0; k < 2; ++k) {
         if (nr[k] <= 0) break;
@@ -448,7 +459,7 @@ __global__ __launch_bounds__(BS) void k_batch_s(BArgsB a) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         if (t < nr[k]) {
           const int row = row0[k] + t;
-          const double sv = G(row);
+          const double sv = own_ok ? G.value(own[k]) : G(row);
           a.t[o + row] = y[k];
           acc[0] = y[k] * sv;
           acc[1] = y[k] * y[k];
