@@ -85,7 +85,8 @@ def parse():
     ap.add_argument("--gmres-precision", choices=["fp64", "mixed"], default="fp64",
                     help="serving with --gmres-mode engine: the GMRES engine's precision")
     ap.add_argument("--tile-units", type=int, default=0,
-                    help="batch512: tiles per workgroup (1 or 2) instead of measuring")
+                    help="batch512: tiles per workgroup (1 or 2) instead of measuring; serving: "
+                         "the Bi-CGSTAB engine's tiles per workgroup")
     ap.add_argument("--chunk", type=int, default=0,
                     help="batch512: iterations per chunk instead of measuring")
     ap.add_argument("--no-tune", action="store_true",
@@ -374,11 +375,12 @@ def bench_serve(args, gsk, problems, dev):
     nmax = max(s["n"] for s in pool)
     rng = np.random.default_rng(1006)
     # engine room for about 48 of the pool's systems at once
-    rows = int(sum((s["n"] + 255) // 256 * 256 for s in pool) * 0.75)
+    unit = 256 * max(1, args.tile_units)
+    rows = int(sum((s["n"] + unit - 1) // unit * unit for s in pool) * 0.75)
     srv = serve.Server(rows, 256, check_every=8, graph=True, gmres_rows=nmax, m_max=20,
                        device=dev, gmres_lanes=args.gmres_lanes, gmres_mode=args.gmres_mode,
                        gmres_precision=args.gmres_precision, gmres_engine_rows=rows,
-                       gmres_engine_systems=128)
+                       gmres_engine_systems=128, tile_units=args.tile_units)
     results = []
     for rate in rates:
         gaps = rng.exponential(1.0 / rate, size=args.serve_requests)

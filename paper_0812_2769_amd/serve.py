@@ -159,17 +159,21 @@ class Server:
                  graph: bool = True, gmres_rows: int = 0, m_max: int = 20, device="cuda",
                  gmres_lanes: int = 4, gmres_mode: str = "lanes",
                  gmres_precision: str = "fp64", gmres_engine_rows: int = 0,
-                 gmres_engine_systems: int = 64, engine_factory: Callable = gsk.Engine):
+                 gmres_engine_systems: int = 64, engine_factory: Callable = gsk.Engine,
+                 tile_units: int = 0):
         """gmres_mode "lanes": GMRES requests run one at a time on gmres_lanes host threads
         (workspaces for gmres_rows rows, any m <= m_max). "engine": they run in a GMRES(m_max)
         engine (gmres_precision "fp64" or "mixed") with room for gmres_engine_rows rows and
-        gmres_engine_systems systems. engine_factory(max_rows, max_systems, **options) builds
-        the engines (gsk.Engine; the scheduler's host-side tests pass a stand-in with the same
-        submit_gs / run / poll / close methods)."""
+        gmres_engine_systems systems. tile_units: the Bi-CGSTAB engine's tiles per workgroup
+        (0 or 1: one, 2: two; max_rows must then hold each system rounded up to 512 rows).
+        engine_factory(max_rows, max_systems, **options) builds the engines (gsk.Engine; the
+        scheduler's host-side tests pass a stand-in with the same submit_gs / run / poll /
+        close methods)."""
         self.device = torch.device(device)
         self.engine_factory = engine_factory
+        opts = {"tile_units": tile_units} if tile_units else {}
         self.engine = engine_factory(max_rows, max_systems, check_every=check_every, graph=graph,
-                                     device=self.device)
+                                     device=self.device, **opts)
         self.gmres_rows = gmres_rows
         self.m_max = m_max
         self.gmres_lanes = max(1, int(gmres_lanes))
