@@ -63,10 +63,14 @@ struct GatherSM {
 };
 
 // The FP32 product over the two tiles of a unit: y[k] for rows row0[k] .. row0[k] + nr[k].
-// Stencil: both tiles' operands are loaded before either sum; CSR: one tile at a time.
+// Stencil: both tiles' operands are loaded before either sum, and own[k] returns the operands
+// of the thread's own row in tile k, which the gather loaded already (own_ok); CSR: one tile
+// at a time, and the caller loads the row's operands itself.
 template <class G>
 __device__ inline void unit_product(const SysDesc& d, const int (&row0)[2], const int (&nr)[2],
-                                    const G& g, TileLds& L, double (&y)[2]) {
+                                    const G& g, TileLds& L, double (&y)[2],
+                                    typename G::Raw (&own)[2], bool& own_ok) {
+  own_ok = false;
   if (d.kind == MAT_STENCIL) {
     const StencilOpT<float> op{d.mat32, d.n, d.nx, d.ny, d.nz, d.ldp32};
     typename StencilOpT<float>::template Pre<G> pre[2];
@@ -74,7 +78,11 @@ __device__ inline void unit_product(const SysDesc& d, const int (&row0)[2], cons
     for (int k = 0; k < 2; ++k) pre[k] = op.load(row0[k], nr[k], g);
     EmptyLds e;
 #pragma unroll
-    for (int k = 0; k < 2; ++k) y[k] = op.finish(pre[k], row0[k], nr[k], g, e);
+    for (int k = 0; k < 2; ++k) {
+      own[k] = pre[k].centre();
+      y[k] = op.finish(pre[k], row0[k], nr[k], g, e);
+    }
+    own_ok = true;
   } else {
     const CsrOpT<float> op{d.rp, d.ci, d.mat32};
     for (int k = 0; k < 2; ++k) {
@@ -256,7 +264,9 @@ __global__ __launch_bounds__(BS) void k_bm_p(MArgs a) {
     int lt0, row0[2], nr[2];
     unit_rows(d, unit, lt0, row0, nr);
     double y[2];
-    unit_product(d, row0, nr, G, L, y);
+    typename GatherPM::Raw own[2];
+    bool own_ok;
+    unit_product(d, row0, nr, G, L, y, own, own_ok);
     const int t = threadIdx.x;
     for (int k = 0; k < 2; ++k) {
       if (nr[k] <= 0) break;
@@ -264,7 +274,7 @@ __global__ __launch_bounds__(BS) void k_bm_p(MArgs a) {
       double acc[2] = {0.0, 0.0};
       if (t < nr[k]) {
         const int row = row0[k] + t;
-        a.p[q ^ 1][o + row] = (float)G(row);
+        a.p[q ^ 1][o + row] = (float)(own_ok ? G.value(own[k]) : G(row));
         const float vs = (float)y[k];
         a.v[q ^ 1][o + row] = vs;
         acc[0] = (double)a.rh[o + row] * (double)vs;
@@ -308,7 +318,9 @@ __global__ __launch_bounds__(BS) void k_bm_s(MArgs a) {
     int lt0, row0[2], nr[2];
     unit_rows(d, unit, lt0, row0, nr);
     double y[2];
-    unit_product(d, row0, nr, G, L, y);
+    typename GatherSM::Raw own[2];
+    bool own_ok;
+    unit_product(d, row0, nr, G, L, y, own, own_ok);
     const int t = threadIdx.x;
     for (int k = 0; k < 2; ++k) {
       if (nr[k] <= 0) break;
@@ -316,7 +328,7 @@ __global__ __launch_bounds__(BS) void k_bm_s(MArgs a) {
       double acc[4] = {0.0, 0.0, 0.0, 0.0};
       if (t < nr[k]) {
         const int row = row0[k] + t;
-        const double sv = G(row);
+        const double sv = own_ok ? G.value(own[k]) : G(row);
         const float ts = (float)y[k];
         a.t[o + row] = ts;
         acc[0] = (double)ts * sv;
