@@ -82,8 +82,9 @@ def parse():
                     help="serving: host threads (each with its own stream) serving GMRES")
     ap.add_argument("--gmres-mode", choices=["lanes", "engine"], default="engine",
                     help="serving: GMRES requests on lanes or in a GMRES engine")
-    ap.add_argument("--gmres-precision", choices=["fp64", "mixed"], default="fp64",
-                    help="serving with --gmres-mode engine: the GMRES engine's precision")
+    ap.add_argument("--gmres-precision", choices=["fp64", "mixed"], default="mixed",
+                    help="serving with --gmres-mode engine: the GMRES engine's precision "
+                         "(mixed: FP32 Arnoldi cycles, FP64 restarts and stop test)")
     ap.add_argument("--tile-units", type=int, default=0,
                     help="batch512: tiles per workgroup (1 or 2) instead of measuring; serving: "
                          "the Bi-CGSTAB engine's tiles per workgroup")
@@ -415,7 +416,10 @@ def bench_serve(args, gsk, problems, dev):
         "metric": "completed solves/s under Poisson arrivals, p50/p99 latency",
         "value": best["completed_per_s"], "unit": "solves/s", "n_gpus": 1,
         "steps": len(rates), "warmup": 0, "ms_per_step": None, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": ("f64; GMRES f32 inner / f64 restarts"
+                  if args.gmres_mode == "engine" and args.gmres_precision == "mixed" else "f64"),
+        "data": "synthetic",
         "config": {"workload": f"serving: Poisson arrivals at {args.rates} req/s, "
                                f"{args.serve_requests} requests per rate from a pool of 64 "
                                f"batch-recipe systems, {args.gmres_share:.0%} GMRES(20), "
