@@ -632,8 +632,8 @@ done:
  *      ||W r~|| / ||W r0|| drops below max(tol, delta * rt): a reduction by delta of the
  *      residual it started from is as far as float storage is trusted to go. It also ends
  *      when the estimate ||W r~|| / ||W r0|| exceeds rt / delta or is not finite: the float
- *      recurrences have diverged, and the refinement step decides (reading of this build;
- *      float-storage Bi-CGSTAB can diverge to overflow on the jump problems).
+ *      recurrences have diverged, and the refinement step decides (a choice the paper leaves
+ *      open: float-storage Bi-CGSTAB can diverge to overflow on the jump problems).
  * Stagnation: a refinement step that does not halve rt counts as a failure; three failures
  * in a row end the solve as STAGNATED. Breakdown tests as in Bi-CGSTAB (R6), on the stored
  * vectors.
