@@ -4,7 +4,8 @@ Bars: against the oracle's mixed-precision GMRES on the same seeded systems, equ
 Arnoldi steps within one cycle (m) or 5%, and at tol 1e-10 a solution within 1e-8 of the
 oracle's; the FP64 refinement must reach residuals far below float precision; stencil and
 CSR operators agree to rounding. At the full 160^3 size the residual of the returned solution
-is recomputed independently by the oracle's FP64 product.
+is recomputed independently by the oracle's FP64 product, and GS(p) and the products of the
+scaled matrix are compared with the oracle bit for bit on sampled rows.
 """
 import numpy as np
 import pytest
@@ -188,3 +189,37 @@ def test_checker160_full_size_mixed_vs_fp64(G, checker160):
         r = S.b - oracle.spmv(S, host(x))
         rel = np.linalg.norm(r) / np.linalg.norm(S.b)   # x0 = 0
         assert rel == pytest.approx(info.relres_true, rel=1e-6)
+
+
+def test_checker160_full_size_gs_and_spmv_sampled(G, checker160):
+    """The 160^3 system at full size (n = 4,096,000): GS(1) and GS(2) outputs (scaled values,
+    right-hand side, row norms, stop weights) and the scaled matrix's product through the CSR
+    and the stencil operators, bit for bit equal to the oracle's on 4,000 sampled rows plus
+    the first and last. The oracle works on the sampled rows alone."""
+    P = checker160
+    A = G.CsrMatrix.from_problem(P)
+    b = dev(P.b)
+    rows = np.sort(np.random.default_rng(11).choice(P.n, size=4000, replace=False))
+    rows = np.unique(np.concatenate([rows, [0, P.n - 1]]))
+    starts, ends = P.row_ptr[rows], P.row_ptr[rows + 1]
+    sel = np.concatenate([np.arange(s, e) for s, e in zip(starts, ends)])
+    rp = np.zeros(len(rows) + 1, np.int32)
+    rp[1:] = np.cumsum(ends - starts)
+    sub = problems.Problem("sub", (len(rows),), rp, P.col_idx[sel].copy(), P.val[sel].copy(),
+                           P.b[rows].copy())
+    x = np.random.default_rng(12).standard_normal(P.n)
+    xd = dev(x)
+    for p in (1, 2):
+        S, bs, nrm, w = G.gs_scale(A, b, p, want_weights=True)
+        vo, bo, n_o, w_o = oracle.gs_scale(sub, sub.b, p)
+        np.testing.assert_array_equal(host(S.val)[sel], vo)
+        np.testing.assert_array_equal(host(bs)[rows], bo)
+        np.testing.assert_array_equal(host(nrm)[rows], n_o)
+        np.testing.assert_array_equal(host(w)[rows], w_o)
+        Ss = sub.copy()
+        Ss.val = vo
+        y_o = oracle.spmv(Ss, x)
+        np.testing.assert_array_equal(host(G.spmv(S, xd))[rows], y_o)
+        St = G.stencil_from_csr(S, *grid_of(P))
+        np.testing.assert_array_equal(host(G.spmv(St, xd))[rows], y_o)
+        del S, St
