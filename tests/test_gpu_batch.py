@@ -230,3 +230,46 @@ def test_engine_gs_stage_zero_row(G):
     done = dict(eng.poll())
     assert done[5].status == -2 and not x.any()
     eng.close()
+
+
+@pytest.mark.parametrize("tile_units", [1, 2])
+def test_batch512_real_sizes_equal_solo(G, tile_units):
+    """Systems of the 512-system batch workload at their own sizes: every 32nd of the seeded
+    list plus its largest 3D (96^3) and 2D systems, 1.78 M rows in all. They run as the
+    benchmark runs them: GS(2) inside the engine, chunks of 8 iterations replayed from a HIP
+    graph, tol 1e-8, one or two tiles per workgroup. Each result must equal bit for bit what
+    gsk_gs_scale, stencil packing and gsk_bicgstab give for that system alone."""
+    import torch
+    specs = problems.batch_specs(512)
+    sizes = [int(np.prod(s["dims"])) for s in specs]
+    largest = [max((i for i, s in enumerate(specs) if len(s["dims"]) == d),
+                   key=sizes.__getitem__) for d in (2, 3)]
+    pick = sorted(set(range(0, 512, 32)) | set(largest))
+    assert sizes[largest[1]] == 96 ** 3
+    unit = 256 * tile_units
+    built = []
+    for i in pick:
+        P = problems.batch_system(specs[i])
+        built.append((P, G.CsrMatrix.from_problem(P), dev(P.b)))
+    rows = sum(-(-P.n // unit) * unit for P, _, _ in built)
+    eng = G.Engine(max_rows=rows, max_systems=len(built), check_every=8, graph=True,
+                   tile_units=tile_units)
+    ref, xs = {}, {}
+    for k, (P, A, b) in enumerate(built):
+        As, bs, _, _ = G.gs_scale(A, b, 2)
+        x, info = G.bicgstab(G.stencil_from_csr(As, *grid_of(P)), bs, tol=1e-8)
+        ref[k] = (host(x), info)
+        xs[k] = torch.zeros_like(b)
+        assert eng.submit_gs(G.stencil_from_csr(A, *grid_of(P)), b, xs[k], p=2, tol=1e-8,
+                             tag=k)
+    done = {}
+    for _ in range(5000):
+        eng.run(1)
+        done.update(dict(eng.poll()))
+        if len(done) == len(built):
+            break
+    torch.cuda.synchronize()
+    assert len(done) == len(built)
+    for k in ref:
+        same((host(xs[k]), done[k]), ref[k])
+    eng.close()
