@@ -28,9 +28,9 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def pool(G, count=6):
+def pool(G, count=6, specs=None):
     out = []
-    for sp in problems.batch_specs(count, seed=21, n_min=8, n_max=28):
+    for sp in specs or problems.batch_specs(count, seed=21, n_min=8, n_max=28):
         P = problems.batch_system(sp)
         A = G.CsrMatrix.from_problem(P)
         d = list(P.dims) + [1] * (3 - len(P.dims))
@@ -47,15 +47,23 @@ def alone(G, s, method, mixed=False):
     return G.bicgstab(M, bs, tol=1e-8)
 
 
-@pytest.mark.parametrize("realtime,mode", [(False, "lanes"), (True, "lanes"),
-                                           (True, "engine"), (False, "engine-mixed")])
-def test_serving_results_equal_solo(G, realtime, mode):
+@pytest.mark.parametrize("realtime,mode,sizes", [(False, "lanes", "small"),
+                                                 (True, "lanes", "small"),
+                                                 (True, "engine", "small"),
+                                                 (False, "engine-mixed", "small"),
+                                                 (True, "engine-mixed", "workload")])
+def test_serving_results_equal_solo(G, realtime, mode, sizes):
+    """sizes "workload": six systems of the serving workload's own distribution (every 85th
+    of the 512-system list: 32^3 twice, 53^3, 54^3, 76^3 and 64^2), arriving at 2,000
+    requests/s, with GMRES in a mixed-precision engine, as the serving benchmark runs by
+    default."""
     import torch
     from paper_0812_2769_amd import serve
-    systems = pool(G)
+    systems = pool(G, specs=problems.batch_specs(512)[::85][:6] if sizes == "workload" else None)
     rng = np.random.default_rng(3)
     n_req = 24
-    arrivals = np.cumsum(rng.exponential(1 / 400.0, size=n_req))
+    rate = 2000.0 if sizes == "workload" else 400.0
+    arrivals = np.cumsum(rng.exponential(1 / rate, size=n_req))
     picks = rng.integers(0, len(systems), size=n_req)
     kinds = rng.random(n_req) < 0.25
     reqs = [serve.Request(tag=k, arrival=float(arrivals[k]), A=systems[picks[k]]["S"],
