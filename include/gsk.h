@@ -286,6 +286,13 @@ int gsk_bicgstab(const gsk_matrix* A, const double* b, double* x, double tol,
 #define GSK_KCLASS_BICG_U 6
 #define GSK_KCLASS_RESIDUAL 7
 #define GSK_KCLASS_GMRES_X 8
+/* Batch engine classes (FP64 Bi-CGSTAB engine): the engine samples whole chunks, every k-th
+ * chunk is enqueued without its captured graph and each launch of the class in it is timed.
+ * Bytes per launch are the BICG_P / BICG_S / BICG_U figures summed over the systems that the
+ * launch works on (systems whose solve is at that stage). */
+#define GSK_KCLASS_BATCH_P 9
+#define GSK_KCLASS_BATCH_S 10
+#define GSK_KCLASS_BATCH_U 11
 
 typedef struct gsk_probe_result {
     int64_t launches;       /* launches of the class that were timed                      */

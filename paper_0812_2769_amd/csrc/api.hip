@@ -197,6 +197,21 @@ int probe_slot(int kernel_class) {
   return p.next_slot++;
 }
 
+int probe_every(int kernel_class) {
+  Probe& p = probe_state();
+  if (p.cls.load(std::memory_order_relaxed) != kernel_class) return 0;
+  std::lock_guard<std::mutex> g(p.mu);
+  return p.every;
+}
+
+int probe_slot_all(int kernel_class) {
+  Probe& p = probe_state();
+  if (p.cls.load(std::memory_order_relaxed) != kernel_class) return -1;
+  std::lock_guard<std::mutex> g(p.mu);
+  if (p.next_slot >= PROBE_SLOTS) return -1;
+  return p.next_slot++;
+}
+
 bool probe_pair(int slot, hipEvent_t* start, hipEvent_t* stop) {
   Probe& p = probe_state();
   std::lock_guard<std::mutex> g(p.mu);
@@ -308,7 +323,7 @@ int gsk_version(void) { return GSK_VERSION; }
 
 int gsk_probe_begin(int32_t kernel_class, int32_t sample_every) {
   g_err.clear();
-  if (kernel_class < GSK_KCLASS_GMRES_A || kernel_class > GSK_KCLASS_GMRES_X)
+  if (kernel_class < GSK_KCLASS_GMRES_A || kernel_class > GSK_KCLASS_BATCH_U)
     return set_err(GSK_ERR_INVALID_ARG, "unknown kernel class %d", (int)kernel_class);
   if (sample_every < 1) return set_err(GSK_ERR_INVALID_ARG, "sample_every must be >= 1");
   Probe& p = probe_state();

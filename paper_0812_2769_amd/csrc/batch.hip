@@ -77,6 +77,8 @@ __device__ inline void for_active_units(const BArgsB& a, Body body) {
   if (k < *a.n_act) body(a.act[k], a.act[a.max_units + k]);
 }
 
+__device__ inline double2 ld2(const double* p) { return *reinterpret_cast<const double2*>(p); }
+
 struct GatherPB {
   const double* __restrict__ r;
   const double* __restrict__ p;
@@ -86,7 +88,14 @@ struct GatherPB {
   struct Raw {
     double r, p, v;
   };
+  struct Raw2 {   // the operands of rows col and col + 1 (16-byte loads; col even)
+    double2 r, p, v;
+  };
   __device__ Raw load(int col) const { return Raw{r[col], p[col], v[col]}; }
+  __device__ Raw2 load2(int col) const { return Raw2{ld2(r + col), ld2(p + col), ld2(v + col)}; }
+  __device__ static Raw half(const Raw2& a, int h) {
+    return h ? Raw{a.r.y, a.p.y, a.v.y} : Raw{a.r.x, a.p.x, a.v.x};
+  }
   __device__ double value(const Raw& a) const {
     return first ? a.r : fma(beta, fma(-omega, a.v, a.p), a.r);
   }
@@ -100,7 +109,14 @@ struct GatherSB {
   struct Raw {
     double r, v;
   };
+  struct Raw2 {
+    double2 r, v;
+  };
   __device__ Raw load(int col) const { return Raw{r[col], v[col]}; }
+  __device__ Raw2 load2(int col) const { return Raw2{ld2(r + col), ld2(v + col)}; }
+  __device__ static Raw half(const Raw2& a, int h) {
+    return h ? Raw{a.r.y, a.v.y} : Raw{a.r.x, a.v.x};
+  }
   __device__ double value(const Raw& a) const { return fma(-alpha, a.v, a.r); }
   __device__ double operator()(int col) const { return value(load(col)); }
 };
@@ -129,33 +145,193 @@ __device__ inline void unit_rows2(const SysDesc& d, int unit, int& lt0, int (&ro
   }
 }
 
-// The product over the two tiles of a unit. Stencil: both tiles' operands are loaded before
-// either sum (clamped addresses, so a tile past the end reads valid rows), and own[k] returns
-// the operands of the thread's own row in tile k, which the gather loaded already (own_ok);
-// CSR: one tile at a time through LDS, and the caller loads the row's operands itself.
+// ---------------------------------------------------------------------------------------
+// Stencil units of two tiles through an LDS window.
+//
+// The gathered value g of every row in [R0 - nx, R0 + 2 BS + nx) (the unit's rows and one
+// x-line on either side, clipped to the system) is formed once into LDS; a row then takes its
+// -y, -x, centre, +x and +y operands from the window and gathers only -z and +z from global
+// memory. Each row is summed in the stencil's position order with the same roundings as
+// StencilOp, so the product, the row's own value and every partial equal the global-gather
+// form bit for bit.
+//
+// Pair layout (16-byte loads): with n and nx even and the planes (and stop weights) 16-byte
+// aligned, thread t owns rows R0 + 2t and R0 + 2t + 1 and loads coefficients, window entries
+// and z-neighbours two rows at a time; the per-row dot-product terms then pass through LDS so
+// that each tile's partials are reduced in the single solver's order (row t of the tile in
+// thread t). Otherwise thread t owns rows R0 + t and R0 + BS + t (8-byte loads).
+// ---------------------------------------------------------------------------------------
+constexpr int WIN_NX = 256;                  // widest x-line the window serves
+constexpr int WIN_ROWS = 2 * BS + 2 * WIN_NX;
+
+union UnitLds {
+  TileLds csr;                               // CSR tiles (one at a time)
+  double g[WIN_ROWS];                        // the window of gathered values
+  double acc[4][2 * BS];                     // per-row dot-product terms (pair layout)
+};
+
+// Positions present in row i's stencil: bit q for -z, -y, -x, centre, +x, +y, +z (as in
+// StencilOp).
+__device__ inline unsigned stencil_present(const SysDesc& d, int i) {
+  const int ix = i % d.nx, rest = i / d.nx, iy = rest % d.ny, iz = rest / d.ny;
+  const bool three = d.nz > 1;
+  return (three && iz > 0 ? 1u : 0u) | (iy > 0 ? 2u : 0u) | (ix > 0 ? 4u : 0u) | 8u |
+         (ix < d.nx - 1 ? 16u : 0u) | (iy < d.ny - 1 ? 32u : 0u) |
+         (three && iz < d.nz - 1 ? 64u : 0u);
+}
+
+// Coefficient plane of position q (-1: none; the -z and +z positions of a 2D system).
+__device__ inline int plane_of(int q, bool three) {
+  return three ? q : (q == 0 || q == 6 ? -1 : q - 1);
+}
+
+__device__ inline bool unit_pairs(const SysDesc& d, const double* extra) {
+  return !(d.n & 1) && !(d.nx & 1) && !(reinterpret_cast<uintptr_t>(d.coef) & 15) &&
+         !(reinterpret_cast<uintptr_t>(extra) & 15);
+}
+
+// Sum of the row's stencil terms in position order (absent positions add +0.0).
+__device__ inline double stencil_sum(unsigned present, const double (&c)[7],
+                                     const double (&g)[7]) {
+#pragma clang fp contract(off)
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < 7; ++q) s += (present >> q) & 1u ? c[q] * g[q] : 0.0;
+  return s;
+}
+
+// y[h] = (A g)_row[h] and gv[h] = g(row[h]) for the thread's two row slots of the unit's rows
+// [R0, R0 + nr) of system d (stencil, nx <= WIN_NX); ok[h]: the slot is a row of the unit.
+// pair: slots are rows R0 + 2t and R0 + 2t + 1 (requires unit_pairs), else R0 + t and
+// R0 + BS + t. All threads of the workgroup call (one barrier); gw is the LDS window.
 template <class G>
-__device__ inline void unit_product2(const SysDesc& d, const int (&row0)[2], const int (&nr)[2],
-                                     const G& g, TileLds& L, double (&y)[2],
-                                     typename G::Raw (&own)[2], bool& own_ok) {
-  own_ok = false;
-  if (d.kind == MAT_STENCIL) {
-    const StencilOp op{d.coef, d.n, d.nx, d.ny, d.nz, (size_t)d.n};
-    StencilOp::Pre<G> pre[2];
+__device__ inline void unit_window(const SysDesc& d, int R0, int nr, bool pair, const G& g,
+                                   double* gw, int (&row)[2], bool (&ok)[2], double (&y)[2],
+                                   double (&gv)[2]) {
+  const int t = threadIdx.x;
+  const int n = d.n, nx = d.nx;
+  const int nxy = nx * d.ny;
+  const bool three = d.nz > 1;
+  const int W0 = max(0, R0 - nx);
+  const int W1 = min(n, R0 + 2 * BS + nx);
+  const int wn = W1 - W0;
+  double c[2][7];
+  if (pair) {
+    row[0] = R0 + min(2 * t, nr - 2);
+    row[1] = row[0] + 1;
+    ok[0] = ok[1] = 2 * t < nr;
+    const int wp = wn >> 1;
+    typename G::Raw2 f[WIN_ROWS / (2 * BS)];
 #pragma unroll
-    for (int k = 0; k < 2; ++k) pre[k] = op.load(row0[k], nr[k], g);
-    EmptyLds e;
+    for (int q = 0; q < WIN_ROWS / (2 * BS); ++q)
+      f[q] = g.load2(W0 + 2 * min(q * BS + t, wp - 1));
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      own[k] = pre[k].centre();   // the row's own operands, already gathered
-      y[k] = op.finish(pre[k], row0[k], nr[k], g, e);
+    for (int q = 0; q < 7; ++q) {
+      const int pl = plane_of(q, three);
+      const double2 cc = pl >= 0 ? ld2(d.coef + (size_t)pl * n + row[0]) : double2{0.0, 0.0};
+      c[0][q] = cc.x;
+      c[1][q] = cc.y;
     }
-    own_ok = true;
+    typename G::Raw2 z[2];
+    z[0] = g.load2(max(row[0] - nxy, 0));
+    z[1] = g.load2(min(row[0] + nxy, n - 2));
+#pragma unroll
+    for (int q = 0; q < WIN_ROWS / (2 * BS); ++q) {
+      const int kk = q * BS + t;
+      if (kk < wp) {
+        gw[2 * kk] = g.value(G::half(f[q], 0));
+        gw[2 * kk + 1] = g.value(G::half(f[q], 1));
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int li = row[h] - W0;
+      double gq[7];
+      gq[0] = three ? g.value(G::half(z[0], h)) : 0.0;
+      gq[1] = gw[max(li - nx, 0)];
+      gq[2] = gw[max(li - 1, 0)];
+      gq[3] = gw[li];
+      gq[4] = gw[min(li + 1, wn - 1)];
+      gq[5] = gw[min(li + nx, wn - 1)];
+      gq[6] = three ? g.value(G::half(z[1], h)) : 0.0;
+      y[h] = stencil_sum(stencil_present(d, row[h]), c[h], gq);
+      gv[h] = gq[3];
+    }
   } else {
-    const CsrOp op{d.rp, d.ci, d.val};
-    for (int k = 0; k < 2; ++k) {
-      if (k) __syncthreads();
-      y[k] = nr[k] > 0 ? op.tile(row0[k], nr[k], g, L) : 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      row[h] = R0 + min(h * BS + t, nr - 1);
+      ok[h] = h * BS + t < nr;
     }
+    typename G::Raw f[WIN_ROWS / BS];
+#pragma unroll
+    for (int q = 0; q < WIN_ROWS / BS; ++q)
+      if (q * BS < wn) f[q] = g.load(W0 + min(q * BS + t, wn - 1));
+    typename G::Raw z[2][2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int q = 0; q < 7; ++q) {
+        const int pl = plane_of(q, three);
+        c[h][q] = pl >= 0 ? d.coef[(size_t)pl * n + row[h]] : 0.0;
+      }
+      z[h][0] = g.load(max(row[h] - nxy, 0));
+      z[h][1] = g.load(min(row[h] + nxy, n - 1));
+    }
+#pragma unroll
+    for (int q = 0; q < WIN_ROWS / BS; ++q) {
+      const int kk = q * BS + t;
+      if (q * BS < wn && kk < wn) gw[kk] = g.value(f[q]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int li = row[h] - W0;
+      double gq[7];
+      gq[0] = three ? g.value(z[h][0]) : 0.0;
+      gq[1] = gw[max(li - nx, 0)];
+      gq[2] = gw[max(li - 1, 0)];
+      gq[3] = gw[li];
+      gq[4] = gw[min(li + 1, wn - 1)];
+      gq[5] = gw[min(li + nx, wn - 1)];
+      gq[6] = three ? g.value(z[h][1]) : 0.0;
+      y[h] = stencil_sum(stencil_present(d, row[h]), c[h], gq);
+      gv[h] = gq[3];
+    }
+  }
+}
+
+// Partials of NC per-row terms of the unit's two tiles (tile k holds unit rows
+// [k BS, (k+1) BS)), each tile reduced in the single solver's order: row t of the tile in
+// thread t. In the pair layout the terms pass through the LDS acc array (which may alias the
+// window: the caller has finished reading it). `tiles` = tiles of the unit inside the system.
+template <int NC>
+__device__ inline void unit_partials(bool pair, const double (&acc)[2][NC], double (*lds)[2 * BS],
+                                     int tiles, double* partials, int stride, int tile0,
+                                     double* red) {
+  const int t = threadIdx.x;
+  double v[2][NC];
+  if (pair) {
+    __syncthreads();   // the window is no longer read
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) lds[c][2 * t + h] = acc[h][c];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[k][c] = lds[c][k * BS + t];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[k][c] = acc[k][c];
+  }
+  for (int k = 0; k < tiles; ++k) {
+    if (k) __syncthreads();
+    block_partials<NC>(v[k], NC, partials, stride, tile0 + k, red);
   }
 }
 
@@ -330,7 +506,8 @@ __global__ __launch_bounds__(BS) void k_batch_fin_residual(BArgsB a) {
 // P: new p, v = A p; partials (r^, v), ||v||^2.
 template <int RV>
 __global__ __launch_bounds__(BS) void k_batch_p(BArgsB a) {
-  __shared__ TileLds L;
+  __shared__ UnitLds U;
+  TileLds& L = U.csr;
   __shared__ double red[NC_MAX * WAVES];
   if constexpr (RV == 1) {
     for_active_tiles(a, [&](int tile, int s) {
@@ -366,21 +543,58 @@ __global__ __launch_bounds__(BS) void k_batch_p(BArgsB a) {
       const GatherPB G{a.r + o, a.p[q] + o, a.v[q] + o, c->beta, c->omega, c->first};
       int lt0, row0[2], nr[2];
       unit_rows2(d, unit, lt0, row0, nr);
-      double y[2];
-      GatherPB::Raw own[2];
-      bool own_ok;
-      unit_product2(d, row0, nr, G, L, y, own, own_ok);
+      if (d.kind == MAT_STENCIL && d.nx <= WIN_NX) {
+        const bool pair = unit_pairs(d, nullptr);
+        const int R0 = row0[0], nu = nr[0] + nr[1];
+        int row[2];
+        bool ok[2];
+        double y[2], gv[2];
+        unit_window(d, R0, nu, pair, G, U.g, row, ok, y, gv);
+        double acc[2][2];
+        double rh[2];
+        if (pair) {
+          const double2 r2 = ld2(a.rh + o + row[0]);
+          rh[0] = r2.x;
+          rh[1] = r2.y;
+        } else {
+          rh[0] = a.rh[o + row[0]];
+          rh[1] = a.rh[o + row[1]];
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          acc[h][0] = ok[h] ? rh[h] * y[h] : 0.0;
+          acc[h][1] = ok[h] ? y[h] * y[h] : 0.0;
+        }
+        if (pair) {
+          if (ok[0]) {
+            *reinterpret_cast<double2*>(a.p[q ^ 1] + o + row[0]) = double2{gv[0], gv[1]};
+            *reinterpret_cast<double2*>(a.v[q ^ 1] + o + row[0]) = double2{y[0], y[1]};
+          }
+        } else {
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            if (ok[h]) {
+              a.p[q ^ 1][o + row[h]] = gv[h];
+              a.v[q ^ 1][o + row[h]] = y[h];
+            }
+        }
+        unit_partials<2>(pair, acc, U.acc, nr[1] > 0 ? 2 : 1, a.partials, a.max_tiles,
+                         d.tile_off + lt0, red);
+        return;
+      }
+      // CSR, or x-lines wider than the window: one tile at a time
       const int t = threadIdx.x;
       for (int k = 0; k < 2; ++k) {
         if (nr[k] <= 0) break;
         if (k) __syncthreads();
+        const double y = sys_tile(d, row0[k], nr[k], G, L);
         double acc[2] = {0.0, 0.0};
         if (t < nr[k]) {
           const int row = row0[k] + t;
-          a.p[q ^ 1][o + row] = own_ok ? G.value(own[k]) : G(row);
-          a.v[q ^ 1][o + row] = y[k];
-          acc[0] = a.rh[o + row] * y[k];
-          acc[1] = y[k] * y[k];
+          a.p[q ^ 1][o + row] = G(row);
+          a.v[q ^ 1][o + row] = y;
+          acc[0] = a.rh[o + row] * y;
+          acc[1] = y * y;
         }
         block_partials<2>(acc, 2, a.partials, a.max_tiles, d.tile_off + lt0 + k, red);
       }
@@ -411,7 +625,8 @@ __global__ __launch_bounds__(BS) void k_batch_fin_p(BArgsB a) {
 // S: t = A s with s = r - alpha v; partials (t,s), (t,t), ||s||^2, ||W s||^2.
 template <int RV>
 __global__ __launch_bounds__(BS) void k_batch_s(BArgsB a) {
-  __shared__ TileLds L;
+  __shared__ UnitLds U;
+  TileLds& L = U.csr;
   __shared__ double red[NC_MAX * WAVES];
   if constexpr (RV == 1) {
     for_active_tiles(a, [&](int tile, int s) {
@@ -448,21 +663,57 @@ __global__ __launch_bounds__(BS) void k_batch_s(BArgsB a) {
       const GatherSB G{a.r + o, a.v[a.par ^ 1] + o, c->alpha};
       int lt0, row0[2], nr[2];
       unit_rows2(d, unit, lt0, row0, nr);
-      double y[2];
-      GatherSB::Raw own[2];
-      bool own_ok;
-      unit_product2(d, row0, nr, G, L, y, own, own_ok);
+      if (d.kind == MAT_STENCIL && d.nx <= WIN_NX) {
+        const bool pair = unit_pairs(d, d.W);
+        const int R0 = row0[0], nu = nr[0] + nr[1];
+        int row[2];
+        bool ok[2];
+        double y[2], sv[2];
+        unit_window(d, R0, nu, pair, G, U.g, row, ok, y, sv);
+        double wv[2] = {0.0, 0.0};
+        if (d.W) {
+          if (pair) {
+            const double2 w2 = ld2(d.W + row[0]);
+            wv[0] = w2.x;
+            wv[1] = w2.y;
+          } else {
+            wv[0] = d.W[row[0]];
+            wv[1] = d.W[row[1]];
+          }
+        }
+        double acc[2][4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          acc[h][0] = ok[h] ? y[h] * sv[h] : 0.0;
+          acc[h][1] = ok[h] ? y[h] * y[h] : 0.0;
+          acc[h][2] = ok[h] ? sv[h] * sv[h] : 0.0;
+          const double ws = wv[h] * sv[h];
+          acc[h][3] = ok[h] && d.W ? ws * ws : 0.0;
+        }
+        if (pair) {
+          if (ok[0]) *reinterpret_cast<double2*>(a.t + o + row[0]) = double2{y[0], y[1]};
+        } else {
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            if (ok[h]) a.t[o + row[h]] = y[h];
+        }
+        unit_partials<4>(pair, acc, U.acc, nr[1] > 0 ? 2 : 1, a.partials, a.max_tiles,
+                         d.tile_off + lt0, red);
+        return;
+      }
+      // CSR, or x-lines wider than the window: one tile at a time
       const int t = threadIdx.x;
       for (int k = 0; k < 2; ++k) {
         if (nr[k] <= 0) break;
         if (k) __syncthreads();
+        const double y = sys_tile(d, row0[k], nr[k], G, L);
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         if (t < nr[k]) {
           const int row = row0[k] + t;
-          const double sv = own_ok ? G.value(own[k]) : G(row);
-          a.t[o + row] = y[k];
-          acc[0] = y[k] * sv;
-          acc[1] = y[k] * y[k];
+          const double sv = G(row);
+          a.t[o + row] = y;
+          acc[0] = y * sv;
+          acc[1] = y * y;
           acc[2] = sv * sv;
           if (d.W) {
             const double ws = d.W[row] * sv;
@@ -574,13 +825,41 @@ __global__ __launch_bounds__(BS) void k_batch_fin_u(BArgsB a) {
   c->first = 0;
 }
 
+// Measurement: the algorithmic bytes of the launch of class kc that ran just before (per
+// system at that stage, the figures of the kernel-class table in gsk.h), into ps->bytes[slot].
+// Runs between that launch and its finalize, so every system is in the state the launch saw.
+__global__ __launch_bounds__(BS) void k_batch_probe_bytes(BArgsB a, int max_sys, int kc,
+                                                          int slot, ProbeSlots* ps) {
+  __shared__ double red[NC_MAX * WAVES];
+  double acc[1] = {0.0};
+  for (int s = threadIdx.x; s < max_sys; s += BS) {
+    const SysDesc d = a.sys[s];
+    if (d.ntiles == 0) continue;
+    const BCtl* c = a.ctl + s;
+    const int st = c->sum.state;
+    const double n = (double)d.n;
+    if (kc == KC_BATCH_U) {
+      if (st == ST_RUNNING) acc[0] += (d.W ? 72.0 : 64.0) * n;
+      if (st == ST_HALF) acc[0] += 24.0 * n;
+      continue;
+    }
+    if (st != ST_RUNNING) continue;
+    // matrix term (a running system's CSR structure has been validated)
+    const double M = d.kind == MAT_STENCIL ? 8.0 * (d.nz > 1 ? 7 : 5) * n
+                                           : 12.0 * (double)d.rp[d.n] + 4.0 * (n + 1.0);
+    if (kc == KC_BATCH_P) acc[0] += M + (c->first ? 32.0 : 48.0) * n;
+    if (kc == KC_BATCH_S) acc[0] += M + (d.W ? 32.0 : 24.0) * n;
+  }
+  block_partials<1>(acc, 1, ps->bytes, 0, slot, red);
+}
+
 // ---------------------------------------------------------------------------------------
 // Host side: the engine.
 // ---------------------------------------------------------------------------------------
 constexpr int kBatchVectors = 7;
 
 struct EngineLayout {
-  size_t sys, tiles, ctl, sums, partials, vecs, total;
+  size_t sys, tiles, probe, ctl, sums, partials, vecs, total;
 };
 
 static int units_of(const EngineConfig& cfg) {
@@ -602,6 +881,8 @@ static EngineLayout engine_layout(const EngineConfig& cfg) {
   off += align256(sizeof(SysDesc) * ns);
   L.tiles = off;
   off += align256(sizeof(int) * (2 * (size_t)grid_tiles + 1));
+  L.probe = off;
+  off += align256(sizeof(ProbeSlots));
   L.ctl = off;
   if (cfg.method == 1) {
     off += align256(sizeof(Ctl) * ns);
@@ -647,6 +928,9 @@ struct Engine {
   MArgs margs{};
   SysDesc* d_sys = nullptr;        // device system table and unit list (any method)
   int* d_list = nullptr;
+  ProbeSlots* d_probe = nullptr;   // measurement slots (FP64 Bi-CGSTAB engine)
+  long long probe_chunks = 0;      // chunks run while a batch kernel class is probed
+  bool probe_pending = false;      // timed launches wait for their collection at the next poll
   // host state
   std::vector<SysDesc> h_sys;
   std::vector<int64_t> tags;
@@ -802,6 +1086,7 @@ int engine_create(void* ws, size_t ws_bytes, const EngineConfig& cfg, hipStream_
   }
   e->d_sys = reinterpret_cast<SysDesc*>(base + L.sys);
   e->d_list = reinterpret_cast<int*>(base + L.tiles);
+  e->d_probe = reinterpret_cast<ProbeSlots*>(base + L.probe);
   e->h_sys.assign(max_sys, SysDesc{});
   e->tags.assign(max_sys, 0);
   e->active.assign(max_sys, 0);
@@ -954,7 +1239,18 @@ static int upload(Engine& e) {
   return 0;
 }
 
-static void enqueue_chunk(Engine& e, int k, int64_t first_iter, int grid) {
+// Launch of a streaming kernel of class kc; in a sampled chunk (probed == kc) it carries a pair
+// of timing events and is followed by the launch that records its algorithmic bytes.
+template <class F>
+static void launch_stream(Engine& e, F kernel, int kc, int probed, dim3 grid, const BArgsB& a) {
+  const int slot = probed == kc ? probe_slot_all(kc) : -1;
+  launch_probed(kernel, grid, e.s, slot, a);
+  if (slot >= 0)
+    hipLaunchKernelGGL(k_batch_probe_bytes, dim3(1), dim3(BS), 0, e.s, a, e.max_sys, kc, slot,
+                       e.d_probe);
+}
+
+static void enqueue_chunk(Engine& e, int k, int64_t first_iter, int grid, int probed = 0) {
   if (e.method == 1) {
     (void)launch_gmres_chunk(e.gargs, e.m, grid, e.max_sys, e.column, e.s);
     return;
@@ -971,13 +1267,13 @@ static void enqueue_chunk(Engine& e, int k, int64_t first_iter, int grid) {
   hipLaunchKernelGGL(k_batch_fin_residual, gs, block, 0, e.s, a);
   for (int it = 0; it < k; ++it) {
     a.par = (int)((first_iter + it) & 1);
-    if (e.rv == 2) hipLaunchKernelGGL(k_batch_p<2>, gt, block, 0, e.s, a);
-    else hipLaunchKernelGGL(k_batch_p<1>, gt, block, 0, e.s, a);
+    if (e.rv == 2) launch_stream(e, k_batch_p<2>, KC_BATCH_P, probed, gt, a);
+    else launch_stream(e, k_batch_p<1>, KC_BATCH_P, probed, gt, a);
     hipLaunchKernelGGL(k_batch_fin_p, gs, block, 0, e.s, a);
-    if (e.rv == 2) hipLaunchKernelGGL(k_batch_s<2>, gt, block, 0, e.s, a);
-    else hipLaunchKernelGGL(k_batch_s<1>, gt, block, 0, e.s, a);
+    if (e.rv == 2) launch_stream(e, k_batch_s<2>, KC_BATCH_S, probed, gt, a);
+    else launch_stream(e, k_batch_s<1>, KC_BATCH_S, probed, gt, a);
     hipLaunchKernelGGL(k_batch_fin_s, gs, block, 0, e.s, a);
-    hipLaunchKernelGGL(k_batch_u, gt, block, 0, e.s, a);
+    launch_stream(e, k_batch_u, KC_BATCH_U, probed, gt, a);
     hipLaunchKernelGGL(k_batch_fin_u, gs, block, 0, e.s, a);
   }
 }
@@ -1005,8 +1301,23 @@ int engine_run(Engine* e, int chunks) {
       e->graphs[grid] = exec;
     }
   }
+  // measurement: while a batch kernel class is probed, every probe_every-th chunk is enqueued
+  // without its graph, with that class's launches timed
+  int probe_cls = 0, every = 0;
+  if (e->method == 0 && !e->mixed) {
+    for (int kc : {(int)KC_BATCH_P, (int)KC_BATCH_S, (int)KC_BATCH_U})
+      if ((every = probe_every(kc)) > 0) {
+        probe_cls = kc;
+        break;
+      }
+  }
   for (int c = 0; c < chunks; ++c) {
-    if (exec) {
+    const bool sampled = probe_cls && (e->probe_chunks++ % every) == 0;
+    if (sampled) {
+      if (!e->probe_pending) probe_solve_begin();
+      e->probe_pending = true;
+      enqueue_chunk(*e, k, e->launched, grid, probe_cls);
+    } else if (exec) {
       if (hipGraphLaunch(exec, e->s) != hipSuccess) return -5;
     } else {
       enqueue_chunk(*e, k, e->launched, grid);
@@ -1038,6 +1349,10 @@ int engine_poll(Engine* e, bool wait, EngineDone* out, int max_out, int* n_out) 
     return -5;
   }
   e->chunk_pending = false;
+  if (e->probe_pending) {   // the sampled chunk's timed launches and bytes are complete
+    probe_collect(e->d_probe, e->s);
+    e->probe_pending = false;
+  }
   int n = 0;
   for (int i = 0; i < e->max_sys && n < max_out; ++i) {
     if (!e->active[i] || status_of(*e, i).state != ST_DONE) continue;

@@ -47,7 +47,8 @@ enum : int { BRK_NONE = 0, BRK_SIGMA = 1, BRK_OMEGA = 2, BRK_RHO = 3, BRK_GIVENS
 // Kernel classes for the measurement hook (same numbering as GSK_KCLASS_* in gsk.h).
 enum : int {
   KC_NONE = 0, KC_GMRES_A = 1, KC_GMRES_B = 2, KC_GMRES_C = 3, KC_BICG_P = 4, KC_BICG_S = 5,
-  KC_BICG_U = 6, KC_RESIDUAL = 7, KC_GMRES_X = 8, KC_COUNT = 9
+  KC_BICG_U = 6, KC_RESIDUAL = 7, KC_GMRES_X = 8, KC_BATCH_P = 9, KC_BATCH_S = 10,
+  KC_BATCH_U = 11, KC_COUNT = 12
 };
 
 // Measurement slots: a launch that the host chose to time carries a slot number; if it does

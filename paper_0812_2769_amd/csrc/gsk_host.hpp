@@ -184,6 +184,11 @@ struct Pacer {
 // are added to the totals.
 void probe_solve_begin();                  // a new solve starts: slots restart at 0
 int probe_slot(int kernel_class);          // -1 if this launch is not timed
+// The batch engine samples whole chunks: probe_every(c) is the sampling period while class c
+// is selected (0 otherwise), and probe_slot_all(c) hands a slot to every launch of a sampled
+// chunk.
+int probe_every(int kernel_class);
+int probe_slot_all(int kernel_class);
 bool probe_pair(int slot, hipEvent_t* start, hipEvent_t* stop);   // events for a timed launch
 void probe_collect(const ProbeSlots* device_slots, hipStream_t s);
 

@@ -97,7 +97,10 @@ class EngineRequest(ctypes.Structure):
                 ("mat32", ctypes.c_void_p), ("mat32_ld", ctypes.c_int64)]
 
 KCLASS = {"gmres_a": 1, "gmres_b": 2, "gmres_c": 3, "bicg_p": 4, "bicg_s": 5, "bicg_u": 6,
-          "residual": 7, "gmres_x": 8}
+          "residual": 7, "gmres_x": 8, "batch_p": 9, "batch_s": 10, "batch_u": 11}
+SOLVER_KCLASSES = ("gmres_a", "gmres_b", "gmres_c", "bicg_p", "bicg_s", "bicg_u", "residual",
+                   "gmres_x")
+ENGINE_KCLASSES = ("batch_p", "batch_s", "batch_u")
 
 
 def _load() -> ctypes.CDLL:
@@ -326,6 +329,24 @@ def gs_scale(A: CsrMatrix, b: torch.Tensor, p: int = 2, *, inplace: bool = False
                             b_out.data_ptr(), _ptr(norms), _ptr(weights), ws.data_ptr(),
                             ws.numel(), _stream(A.device)))
     return A.with_values(val_out), b_out, norms, weights
+
+
+def gs_scale_into(A: CsrMatrix, b: torch.Tensor, p: int, val_out: torch.Tensor,
+                  b_out: torch.Tensor, weights: Optional[torch.Tensor] = None, *,
+                  norms: Optional[torch.Tensor] = None,
+                  ws: Optional[torch.Tensor] = None) -> None:
+    """GS(p) into caller-provided outputs (gsk_gs_scale): scaled values, b, and optionally
+    stop weights and row norms."""
+    _vec(b, A.n, "b")
+    _vec(b_out, A.n, "b_out")
+    if val_out.numel() != A.val.numel() or val_out.dtype != torch.float64:
+        raise GskError(ERR_INVALID_ARG, "val_out must hold nnz float64 values")
+    if ws is None:
+        ws = workspace(METHOD_GS, A.n, 0, A.device)
+    c = A.c_struct()
+    _check(lib.gsk_gs_scale(ctypes.byref(c), b.data_ptr(), int(p), val_out.data_ptr(),
+                            b_out.data_ptr(), _ptr(norms), _ptr(weights), ws.data_ptr(),
+                            ws.numel(), _stream(A.device)))
 
 
 def spmv(A, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:

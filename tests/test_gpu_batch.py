@@ -56,6 +56,10 @@ def systems(G):
         out.append(scaled(G, P, p=1 if i == 2 else 2, stencil=(i != 3)))
     out.append(scaled(G, problems.laplacian((13, 11, 7), conv=(40.0, -25.0, 10.0))))
     out.append(scaled(G, problems.laplacian((3, 2)), stencil=False))
+    # even row count and x-line (two rows per thread in two-tile units), and an x-line wider
+    # than the two-tile units' LDS window (global gathers)
+    out.append(scaled(G, problems.laplacian((12, 10, 6), conv=(5.0, 7.0, -3.0))))
+    out.append(scaled(G, problems.laplacian((300, 3), conv=(2.0, 1.0))))
     return out
 
 
@@ -85,14 +89,16 @@ def test_batch_equals_solo(G):
         same((host(xs[j]), infos[j]), ref[k])
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_engine_continuous_admission_equals_solo(G, graph):
+@pytest.mark.parametrize("graph,tile_units", [(False, 1), (True, 1), (False, 2), (True, 2)])
+def test_engine_continuous_admission_equals_solo(G, graph, tile_units):
     import torch
     syst = systems(G)
     ref = solo(G, syst)
     # room for only part of the set at a time: later systems wait for rows and slots
-    rows = sorted(((M.n + 255) // 256 * 256 for M, _, _ in syst), reverse=True)
-    eng = G.Engine(max_rows=rows[0] + rows[1], max_systems=3, check_every=8, graph=graph)
+    unit = 256 * tile_units
+    rows = sorted(((M.n + unit - 1) // unit * unit for M, _, _ in syst), reverse=True)
+    eng = G.Engine(max_rows=rows[0] + rows[1], max_systems=3, check_every=8, graph=graph,
+                   tile_units=tile_units)
     xs = [torch.zeros_like(b) for _, b, _ in syst]
     pending = list(range(len(syst)))
     results = {}
@@ -184,13 +190,13 @@ def test_engine_argument_errors(G):
         G.Engine(max_rows=1024, max_systems=4, check_every=7, graph=True)
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_engine_gs_stage_equals_solo(G, graph):
+@pytest.mark.parametrize("graph,tile_units", [(False, 1), (True, 1), (True, 2)])
+def test_engine_gs_stage_equals_solo(G, graph, tile_units):
     """GS(p) inside the engine (first chunk) + Bi-CGSTAB == gsk_gs_scale (+ stencil packing)
     + gsk_bicgstab, bit for bit, for stencil and CSR systems, p = 2 and p = 1."""
     import torch
     specs = problems.batch_specs(5, seed=9, n_min=8, n_max=24)
-    eng = G.Engine(max_rows=1 << 17, max_systems=8, graph=graph)
+    eng = G.Engine(max_rows=1 << 17, max_systems=8, graph=graph, tile_units=tile_units)
     ref, xs = {}, {}
     for i, sp in enumerate(specs):
         P = problems.batch_system(sp)
