@@ -378,7 +378,7 @@ static SolveResult gmres_run(const Mat& A, const Op64& op, const OpT& opT, doubl
   T* w = V + (size_t)(m + 1) * ldv;
   KArgs ka{A.n, g.rpb, W.ctl, W.partials, A.bytes(), -1, inner_bytes, 0.0,
            W.partials + (size_t)(NC_MAX - 1) * g.nb};
-  dim3 grid(g.nb), block(BS);
+  dim3 grid(g.nb);
   if (launch_clear_flags(W.flags, s) != hipSuccess) return fail(-5);
   if (A.kind == MAT_CSR && launch_validate(A.csr, W.flags, s) != hipSuccess) return fail(-5);
   hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, s, W.ctl, prm.maxit, m, prm.tol, prm.eps_b,
