@@ -251,6 +251,24 @@ int gsk_bicgstab(const gsk_matrix* A, const double* b, double* x, double tol,
                  void* stream);
 
 /*
+ * Bi-CGSTAB that allocates nothing, for callers that cannot allocate: tight serving loops
+ * and harnesses that forbid hipMalloc (it synchronises `stream`, so it is not for use under
+ * stream capture). Arguments and results as for gsk_bicgstab, without the workspace: the
+ * solver runs in a file-scope device array of gsk_bicgstab_noalloc_max_bytes() bytes
+ * (32 MiB), one per GPU the library runs on, held until the process ends. A system whose
+ * Bi-CGSTAB workspace (gsk_workspace_bytes(GSK_METHOD_BICGSTAB, n, 0)) exceeds it, about
+ * 575,000 rows and more, is rejected with GSK_ERR_WORKSPACE. The call makes no hipMalloc,
+ * hipFree, pinned-memory or event allocation: status is read back with a copy into host
+ * stack memory and a stream synchronisation per chunk of iterations, and the measurement
+ * hook does not time its launches. Results equal gsk_bicgstab's bit for bit.
+ * Every call on a GPU uses that GPU's one array: calls that overlap on the same GPU (from
+ * several host threads, or on several streams) race and must be serialised by the caller.
+ */
+int gsk_bicgstab_noalloc(const gsk_matrix* A, const double* b, double* x, double tol,
+                         const gsk_options* opt, gsk_info* info, void* stream);
+size_t gsk_bicgstab_noalloc_max_bytes(void);
+
+/*
  * Measurement hook (not part of the method). Between gsk_probe_begin(c, k) and gsk_probe_end,
  * every k-th launch of kernel class c made by the solvers is timed: it is launched with a pair
  * of HIP events (hipExtLaunchKernel on the solver's stream, so the events take the dispatch's

@@ -778,4 +778,37 @@ int gsk_bicgstab(const gsk_matrix* A, const double* b, double* x, double tol,
   return solve_common(GSK_METHOD_BICGSTAB, A, b, x, 0, tol, opt, info, ws, ws_bytes, stream);
 }
 
+int gsk_bicgstab_noalloc(const gsk_matrix* A, const double* b, double* x, double tol,
+                         const gsk_options* opt, gsk_info* info, void* stream) {
+  g_err.clear();
+  Mat M;
+  int rc = check_matrix(A, M);
+  if (rc) return rc;
+  if (!b || !x) return set_err(GSK_ERR_INVALID_ARG, "b or x is NULL");
+  SolveParams prm;
+  rc = params_from(opt, prm, tol);
+  if (rc) return rc;
+  const size_t need = gsk::workspace_bytes(GSK_METHOD_BICGSTAB, M.n, 0);
+  if (need > gsk::kNoAllocBytes)
+    return set_err(GSK_ERR_WORKSPACE,
+                   "a system of %d rows needs %zu bytes of scratch; the no-allocation entry "
+                   "point holds %zu (use gsk_bicgstab with a workspace)",
+                   (int)M.n, need, gsk::kNoAllocBytes);
+  hipError_t e = hipSuccess;
+  void* ptr = gsk::noalloc_scratch(&e);
+  if (!ptr) return hip_err(e, "scratch address");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SolveResult r = gsk::bicgstab_solve_noalloc(M, b, x, prm, ptr, s);
+  if (r.code == -1)
+    return set_err(GSK_ERR_INVALID_ARG,
+                   "CSR structure invalid (row_ptr not monotone from 0 to nnz, or a column "
+                   "index outside [0, n))");
+  if (r.code) return set_err(GSK_ERR_DEVICE, "solver: HIP failure (%s)",
+                             hipGetErrorString(hipGetLastError()));
+  fill_info(info, r.sum);
+  return GSK_OK;
+}
+
+size_t gsk_bicgstab_noalloc_max_bytes(void) { return gsk::kNoAllocBytes; }
+
 }  // extern "C"

@@ -20,6 +20,8 @@
 // they have work (a launch without work stores nothing). The residual launch R computes
 // r = b - A x for the initial residual and for every verification of a recursive
 // convergence claim; a failed verification restarts the recurrence from the true residual.
+#include <mutex>
+
 #include "gsk_host.hpp"
 
 namespace gsk {
@@ -418,27 +420,28 @@ __global__ __launch_bounds__(BS) void k_bicg_fin_u(Ctl* c, const double* partial
 
 template <class Op>
 static void launch_residual(const BArgs& a, const Op& op, int nb, const int* flags,
-                            hipStream_t s) {
+                            hipStream_t s, bool probe = true) {
   BArgs ax = a;
-  ax.pslot = probe_slot(KC_RESIDUAL);
+  ax.pslot = probe ? probe_slot(KC_RESIDUAL) : -1;
   launch_probed(k_bicg_residual<Op>, dim3(nb), s, ax.pslot, ax, op, flags);
   hipLaunchKernelGGL(k_bicg_fin_residual, dim3(1), dim3(BS), 0, s, a.ctl,
                      (const double*)a.partials, nb, a.W ? 1 : 0, flags);
 }
 
 template <class Op>
-static void launch_iteration(const BArgs& a, const Op& op, int nb, int par, hipStream_t s) {
+static void launch_iteration(const BArgs& a, const Op& op, int nb, int par, hipStream_t s,
+                             bool probe = true) {
   const int hw = a.W ? 1 : 0;
   const double* pt = a.partials;
   BArgs ax = a;
   ax.par = par;
-  ax.pslot = probe_slot(KC_BICG_P);
+  ax.pslot = probe ? probe_slot(KC_BICG_P) : -1;
   launch_probed(k_bicg_p<Op>, dim3(nb), s, ax.pslot, ax, op);
   hipLaunchKernelGGL(k_bicg_fin_p, dim3(1), dim3(BS), 0, s, a.ctl, pt, nb);
-  ax.pslot = probe_slot(KC_BICG_S);
+  ax.pslot = probe ? probe_slot(KC_BICG_S) : -1;
   launch_probed(k_bicg_s<Op>, dim3(nb), s, ax.pslot, ax, op);
   hipLaunchKernelGGL(k_bicg_fin_s, dim3(1), dim3(BS), 0, s, a.ctl, pt, nb, hw);
-  ax.pslot = probe_slot(KC_BICG_U);
+  ax.pslot = probe ? probe_slot(KC_BICG_U) : -1;
   launch_probed(k_bicg_u, dim3(nb), s, ax.pslot, ax);
   hipLaunchKernelGGL(k_bicg_fin_u, dim3(1), dim3(BS), 0, s, a.ctl, pt, nb, hw);
 }
@@ -450,9 +453,49 @@ static SolveResult bfail(int code) {
   return r;
 }
 
+// Without allocation (noalloc): the workspace is the caller's (here the file-scope scratch
+// array), status is read with a copy into host stack memory and a stream synchronisation per
+// chunk (no pinned memory, no events), and no launch is timed by the measurement hook. The
+// launches, and so the results, are those of the ordinary path.
+template <class Op>
+static SolveResult bicgstab_run_noalloc(const Mat& A, const Op& op, const BArgs& a,
+                                        const Workspace& Wk, const Geom& g,
+                                        const SolveParams& prm, hipStream_t s) {
+  SolveResult res;
+  res.code = 0;
+  res.sum = Summary{};
+  const int k = prm.check_every;
+  Pacer pace{prm.tol, prm.maxit, k};
+  if ((long)2 * k >= prm.maxit) pace.cautious = true;
+  long launched = 0;
+  Summary sum{};
+  const long max_chunks = (long)prm.maxit * 4 + 16;
+  bool done = false;
+  for (long ch = 0; ch <= max_chunks && !done; ++ch) {
+    const int count = pace.cautious && k > 1 ? k / 2 : k;
+    for (int it = 0; it < count; ++it, ++launched)
+      launch_iteration(a, op, g.nb, (int)(launched & 1), s, false);
+    launch_residual(a, op, g.nb, Wk.flags, s, false);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(&sum, &Wk.ctl->sum, sizeof(Summary), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      res.code = -5;
+      return res;
+    }
+    if (sum.state == ST_DONE) done = true;
+    else pace.update(sum.iters, sum.relres_rec);
+  }
+  res.sum = sum;
+  if (!done) res.code = -5;
+  else if (sum.status < 0) res.code = -1;
+  return res;
+}
+
 template <class Op>
 static SolveResult bicgstab_run(const Mat& A, const Op& op, const double* b, double* x,
-                                const SolveParams& prm, void* ws, hipStream_t s) {
+                                const SolveParams& prm, void* ws, hipStream_t s,
+                                bool noalloc = false) {
   Workspace Wk = carve(ws, A.n);
   const Geom g = make_geom(A.n);
   const size_t ld = vec_ld(A.n);
@@ -479,6 +522,11 @@ static SolveResult bicgstab_run(const Mat& A, const Op& op, const double* b, dou
   if (A.kind == MAT_CSR && launch_validate(A.csr, Wk.flags, s) != hipSuccess) return bfail(-5);
   hipLaunchKernelGGL(k_bicg_init_ctl, dim3(1), dim3(64), 0, s, Wk.ctl, prm.maxit, prm.tol,
                      prm.eps_b, prm.weights ? 1 : 0);
+  if (noalloc) {
+    launch_residual(a, op, g.nb, Wk.flags, s, false);
+    if (hipGetLastError() != hipSuccess) return bfail(-5);
+    return bicgstab_run_noalloc(A, op, a, Wk, g, prm, s);
+  }
   probe_solve_begin();
   launch_residual(a, op, g.nb, Wk.flags, s);
   if (hipGetLastError() != hipSuccess) return bfail(-5);
@@ -552,6 +600,54 @@ SolveResult bicgstab_solve(const Mat& A, const double* b, double* x, const Solve
                            void* ws, hipStream_t s) {
   if (A.kind == MAT_STENCIL) return bicgstab_run(A, A.stencil_op(), b, x, prm, ws, s);
   return bicgstab_run(A, A.csr_op(), b, x, prm, ws, s);
+}
+
+// ---------------------------------------------------------------------------------------
+// Bi-CGSTAB without allocation (gsk_bicgstab_noalloc): the workspace is a file-scope device
+// array of kNoAllocBytes, one per GPU the library runs on, held until the process ends. Its
+// name is a host-side stand-in in host code; the device address of each GPU's copy is looked
+// up once per device (hipGetSymbolAddress, with that device current) and only that address
+// is handed to the kernels. Every call on a GPU shares that GPU's array and leaves its
+// contents behind; the solver initialises everything it reads (control block by its init
+// kernel, flags by a clear kernel, partials and vectors by the launches that produce them),
+// so nothing has to start at zero. Calls that overlap on one GPU race on the array.
+// ---------------------------------------------------------------------------------------
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// The current device's copy of scratch (looked up on the first call on that device), or
+// nullptr with *err set.
+void* noalloc_scratch(hipError_t* err) {
+  int dev = 0;
+  *err = hipGetDevice(&dev);
+  if (*err != hipSuccess) return nullptr;
+  if (dev < 0 || dev >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    *err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (*err != hipSuccess || !ptr) {
+      if (*err == hipSuccess) *err = hipErrorInvalidSymbol;
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
+SolveResult bicgstab_solve_noalloc(const Mat& A, const double* b, double* x,
+                                   const SolveParams& prm, void* scratch_ptr, hipStream_t s) {
+  if (A.kind == MAT_STENCIL)
+    return bicgstab_run(A, A.stencil_op(), b, x, prm, scratch_ptr, s, true);
+  return bicgstab_run(A, A.csr_op(), b, x, prm, scratch_ptr, s, true);
 }
 
 }  // namespace gsk

@@ -103,6 +103,12 @@ SolveResult arnoldi_run(const Mat& A, const double* r0, int m, double* V, int64_
                         double* H, void* ws, double eps_b, hipStream_t s);
 SolveResult bicgstab_solve(const Mat& A, const double* b, double* x, const SolveParams& prm,
                            void* ws, hipStream_t s);
+// Bi-CGSTAB without allocation: the workspace is a file-scope device array of kNoAllocBytes
+// (its address on the current device from noalloc_scratch).
+constexpr size_t kNoAllocBytes = size_t(32) << 20;
+void* noalloc_scratch(hipError_t* err);
+SolveResult bicgstab_solve_noalloc(const Mat& A, const double* b, double* x,
+                                   const SolveParams& prm, void* scratch_ptr, hipStream_t s);
 // GMRES(m) with FP32 Arnoldi cycles and FP64 restarts (iterative refinement).
 SolveResult gmres_mixed_solve(const Mat& A, const double* b, double* x, int m,
                               const SolveParams& prm, void* ws, hipStream_t s);

@@ -135,6 +135,11 @@ def _load() -> ctypes.CDLL:
     lib.gsk_bicgstab.argtypes = [P(Matrix), vp, vp, ctypes.c_double, P(Options), P(InfoStruct),
                                  vp, sz, vp]
     lib.gsk_bicgstab.restype = ctypes.c_int
+    lib.gsk_bicgstab_noalloc.argtypes = [P(Matrix), vp, vp, ctypes.c_double, P(Options),
+                                         P(InfoStruct), vp]
+    lib.gsk_bicgstab_noalloc.restype = ctypes.c_int
+    lib.gsk_bicgstab_noalloc_max_bytes.argtypes = []
+    lib.gsk_bicgstab_noalloc_max_bytes.restype = sz
     lib.gsk_probe_begin.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.gsk_probe_begin.restype = ctypes.c_int
     lib.gsk_probe_end.argtypes = [P(ProbeResult)]
@@ -471,6 +476,26 @@ def bicgstab(A, b: torch.Tensor, x0: Optional[torch.Tensor] = None,
                             ctypes.byref(o), ctypes.byref(info), ws.data_ptr(), ws.numel(),
                             _stream(A.device)))
     return x, _info(info)
+
+
+def bicgstab_noalloc(A, b: torch.Tensor, x: torch.Tensor, tol: float = 1e-8, *,
+                     maxit: Optional[int] = None, breakdown_eps=None,
+                     stop_weights: Optional[torch.Tensor] = None,
+                     check_every: Optional[int] = None) -> Info:
+    """Bi-CGSTAB through gsk_bicgstab_noalloc: no workspace argument (the library's fixed
+    scratch array); x holds x0 on entry and the solution on return. Returns Info."""
+    _vec(b, A.n, "b")
+    _vec(x, A.n, "x")
+    o = _options(maxit, breakdown_eps, stop_weights, check_every, A.n)
+    info = InfoStruct()
+    c = A.c_matrix()
+    _check(lib.gsk_bicgstab_noalloc(ctypes.byref(c), b.data_ptr(), x.data_ptr(), float(tol),
+                                    ctypes.byref(o), ctypes.byref(info), _stream(A.device)))
+    return _info(info)
+
+
+def bicgstab_noalloc_max_bytes() -> int:
+    return int(lib.gsk_bicgstab_noalloc_max_bytes())
 
 
 def probe_begin(kernel_class: str, sample_every: int = 1) -> None:
