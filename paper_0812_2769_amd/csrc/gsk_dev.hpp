@@ -616,7 +616,7 @@ struct EmptyLds {
 // -z, -y, -x, centre, +x, +y, +z (-z and +z absent in 2D); neighbours outside the grid are
 // skipped. Each row is summed in that order with every product rounded before it is added,
 // so the result equals the CSR product of the same matrix bit for bit.
-template <class V>
+template <class V, bool NT = false>
 struct StencilOpT {
   const V* coef;
   int n, nx, ny, nz;
@@ -654,7 +654,8 @@ struct StencilOpT {
 #pragma unroll
     for (int q = 0; q < 7; ++q) {
       const int plane = three ? q : (q == 0 ? 0 : q == 6 ? 4 : q - 1);
-      p.c[q] = coef[(size_t)plane * ldp + i];
+      if constexpr (NT) p.c[q] = __builtin_nontemporal_load(coef + (size_t)plane * ldp + i);
+      else p.c[q] = coef[(size_t)plane * ldp + i];
       const long long k = (long long)i + off[q];
       p.x[q] = g.load((int)(k < 0 ? 0 : k >= n ? n - 1 : k));
       p.present |= in[q] ? 1u << q : 0u;
@@ -687,10 +688,14 @@ using StencilOp = StencilOpT<double>;
 // offset a single per-lane 32-bit value, so a thread reading 30 columns of its row holds no
 // per-column addresses. Requires the basis to span fewer than 2^31 bytes (checked on the
 // host). Values are returned as double.
-template <class T>
+// NT: the loads carry the non-temporal cache policy (a basis much larger than the caches is
+// streamed once per launch; keeping it out of the caches leaves room for the data that is
+// reused). The values are the same either way.
+template <class T, bool NT = false>
 struct ColumnReaderT {
   __amdgpu_buffer_rsrc_t rsrc;
   int ld_bytes;
+  static constexpr int kAux = NT ? 2 : 0;   // cache-policy operand: bit 1 = nt
   __device__ ColumnReaderT(const T* base, size_t ldv, int cols) {
     rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0,
                                              (int)(ldv * sizeof(T) * (size_t)cols), 0x00020000);
@@ -699,10 +704,11 @@ struct ColumnReaderT {
   __device__ T raw(int col, int row) const {
     if constexpr (sizeof(T) == 8) {
       typedef unsigned int u2 __attribute__((ext_vector_type(2)));
-      const u2 v = __builtin_amdgcn_raw_buffer_load_b64(rsrc, row * 8, col * ld_bytes, 0);
+      const u2 v = __builtin_amdgcn_raw_buffer_load_b64(rsrc, row * 8, col * ld_bytes, kAux);
       return __builtin_bit_cast(double, v);
     } else {
-      const unsigned int v = __builtin_amdgcn_raw_buffer_load_b32(rsrc, row * 4, col * ld_bytes, 0);
+      const unsigned int v =
+          __builtin_amdgcn_raw_buffer_load_b32(rsrc, row * 4, col * ld_bytes, kAux);
       return __builtin_bit_cast(float, v);
     }
   }
@@ -710,12 +716,15 @@ struct ColumnReaderT {
 };
 
 // Same interface with plain 64-bit addressing, for bases of 2^31 bytes or more.
-template <class T>
+template <class T, bool NT = false>
 struct PointerReaderT {
   const T* base;
   size_t ldv;
   __device__ PointerReaderT(const T* b, size_t l, int) : base(b), ldv(l) {}
-  __device__ T raw(int col, int row) const { return base[(size_t)col * ldv + row]; }
+  __device__ T raw(int col, int row) const {
+    if constexpr (NT) return __builtin_nontemporal_load(base + (size_t)col * ldv + row);
+    else return base[(size_t)col * ldv + row];
+  }
   __device__ double load(int col, int row) const { return (double)raw(col, row); }
 };
 
