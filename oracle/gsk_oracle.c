@@ -518,34 +518,49 @@ done:
  * x holds x0 on entry and the result on return. hist (nullable, capacity maxit) receives
  * ||W r||/ref (or ||W s||/ref at a half-step exit) after every iteration.
  * ------------------------------------------------------------------------------------- */
-int orc_bicgstab(int n, const int* rp, const int* ci, const double* val, const double* b,
-                 double* x, double tol, int maxit, double eps_b, const double* wts,
-                 const double* lu, double* hist, int* info_i, double* info_d) {
-    if (n <= 0 || maxit < 0 || !(tol > 0.0)) return ORC_ERR_ARG;
-    size_t nn = (size_t)n;
-    double* r = (double*)malloc(sizeof(double) * nn);
-    double* rh = (double*)malloc(sizeof(double) * nn);
-    double* p = (double*)malloc(sizeof(double) * nn);
-    double* v = (double*)malloc(sizeof(double) * nn);
-    double* s = (double*)malloc(sizeof(double) * nn);
-    double* t = (double*)malloc(sizeof(double) * nn);
-    double* ph = (double*)malloc(sizeof(double) * nn);
-    double* sh = (double*)malloc(sizeof(double) * nn);
-    if (!r || !rh || !p || !v || !s || !t || !ph || !sh) {
-        free(r); free(rh); free(p); free(v); free(s); free(t); free(ph); free(sh);
-        return ORC_ERR_ALLOC;
-    }
-    int iters = 0, restarts = 0, status = ORC_MAXIT, fails = 0, half = 0, brk = 0;
-    double est = 1.0, relres_true = 1.0;
+typedef struct {
+    int iters, restarts, status, fails, half, brk;
+    double est, relres_true;
+} bicg_state;
 
-    residual(n, rp, ci, val, b, x, r);
-    double ref = wnrm2(n, wts, r);
-    if (ref == 0.0) {
-        status = ORC_CONVERGED;
-        est = relres_true = 0.0;
-        goto done;
+typedef struct {
+    double *r, *rh, *p, *v, *s, *t, *ph, *sh;
+} bicg_work;
+
+static void bicg_work_free(bicg_work* w) {
+    free(w->r); free(w->rh); free(w->p); free(w->v); free(w->s); free(w->t); free(w->ph);
+    free(w->sh);
+}
+
+static int bicg_work_alloc(bicg_work* w, size_t nn) {
+    w->r = (double*)malloc(sizeof(double) * nn);
+    w->rh = (double*)malloc(sizeof(double) * nn);
+    w->p = (double*)malloc(sizeof(double) * nn);
+    w->v = (double*)malloc(sizeof(double) * nn);
+    w->s = (double*)malloc(sizeof(double) * nn);
+    w->t = (double*)malloc(sizeof(double) * nn);
+    w->ph = (double*)malloc(sizeof(double) * nn);
+    w->sh = (double*)malloc(sizeof(double) * nn);
+    if (!w->r || !w->rh || !w->p || !w->v || !w->s || !w->t || !w->ph || !w->sh) {
+        bicg_work_free(w);
+        return 0;
     }
-    if (maxit == 0) goto done;
+    return 1;
+}
+
+/* The FP64 iteration from the current x, with r = b - A x in w->r and the reference norm
+ * ref of the stop test: the recurrence (re)starts from r (r^ = r), stops on its estimate,
+ * is verified with the true residual (R4) and restarts from it after a failed check; three
+ * failed checks in a row end the solve as STAGNATED. The counters in *st continue from their
+ * values on entry (iters counts towards maxit); on return st->status is final and x, est and
+ * relres_true belong to it. */
+static void bicg64_run(int n, const int* rp, const int* ci, const double* val, const double* b,
+                       double* x, double tol, int maxit, double eps_b, const double* wts,
+                       const double* lu, double* hist, double ref, bicg_work* w,
+                       bicg_state* st) {
+    size_t nn = (size_t)n;
+    double *r = w->r, *rh = w->rh, *p = w->p, *v = w->v, *s = w->s, *t = w->t, *ph = w->ph,
+           *sh = w->sh;
     for (;;) {
         /* (re)start the recurrence from the current residual r */
         memcpy(rh, r, sizeof(double) * nn);
@@ -554,9 +569,9 @@ int orc_bicgstab(int n, const int* rp, const int* ci, const double* val, const d
         double rho_old = 1.0, alpha = 1.0, omega = 1.0;
         int first = 1;
         int verify = 0;
-        half = 0;
+        st->half = 0;
         while (!verify) {
-            if (fabs(rho) <= eps_b * rh_norm * nrm2(n, r)) { status = ORC_BREAKDOWN; brk = 3; goto final_check; }
+            if (fabs(rho) <= eps_b * rh_norm * nrm2(n, r)) { st->status = ORC_BREAKDOWN; st->brk = 3; goto final_check; }
             if (first) {
                 memcpy(p, r, sizeof(double) * nn);
             } else {
@@ -568,16 +583,16 @@ int orc_bicgstab(int n, const int* rp, const int* ci, const double* val, const d
             if (lu) { ilu0_apply(n, rp, ci, lu, p, ph); orc_spmv(n, rp, ci, val, ph, v); }
             else { memcpy(ph, p, sizeof(double) * nn); orc_spmv(n, rp, ci, val, p, v); }
             double sigma = dot(n, rh, v);
-            if (fabs(sigma) <= eps_b * rh_norm * nrm2(n, v)) { status = ORC_BREAKDOWN; brk = 1; goto final_check; }
+            if (fabs(sigma) <= eps_b * rh_norm * nrm2(n, v)) { st->status = ORC_BREAKDOWN; st->brk = 1; goto final_check; }
             alpha = rho / sigma;
             for (int i = 0; i < n; ++i) s[i] = r[i] - alpha * v[i];
-            ++iters;
-            est = wnrm2(n, wts, s) / ref;
-            if (est < tol) {
+            ++st->iters;
+            st->est = wnrm2(n, wts, s) / ref;
+            if (st->est < tol) {
                 /* half-step exit: x += alpha p^ */
                 for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * ph[i];
-                if (hist && iters <= maxit) hist[iters - 1] = est;
-                half = 1;
+                if (hist && st->iters <= maxit) hist[st->iters - 1] = st->est;
+                st->half = 1;
                 verify = 1;
                 break;
             }
@@ -586,35 +601,51 @@ int orc_bicgstab(int n, const int* rp, const int* ci, const double* val, const d
             else { memcpy(sh, s, sizeof(double) * nn); orc_spmv(n, rp, ci, val, s, t); }
             double ts = dot(n, t, s);
             double tt = dot(n, t, t);
-            if (fabs(ts) <= eps_b * sqrt(tt) * nrm2(n, s)) { status = ORC_BREAKDOWN; brk = 2; goto final_check; }
+            if (fabs(ts) <= eps_b * sqrt(tt) * nrm2(n, s)) { st->status = ORC_BREAKDOWN; st->brk = 2; goto final_check; }
             omega = ts / tt;
             for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * ph[i] + omega * sh[i];
             for (int i = 0; i < n; ++i) r[i] = s[i] - omega * t[i];
-            est = wnrm2(n, wts, r) / ref;
-            if (hist && iters <= maxit) hist[iters - 1] = est;
-            if (est < tol || iters >= maxit) { verify = 1; break; }
+            st->est = wnrm2(n, wts, r) / ref;
+            if (hist && st->iters <= maxit) hist[st->iters - 1] = st->est;
+            if (st->est < tol || st->iters >= maxit) { verify = 1; break; }
             rho_old = rho;
             rho = dot(n, rh, r);
         }
         /* verification with the true residual (R4) */
         residual(n, rp, ci, val, b, x, r);
-        relres_true = wnrm2(n, wts, r) / ref;
-        if (relres_true < tol) { status = ORC_CONVERGED; goto done; }
-        if (iters >= maxit) { status = ORC_MAXIT; goto done; }
-        ++fails;
-        if (fails >= 3) { status = ORC_STAGNATED; goto done; }
-        ++restarts;
+        st->relres_true = wnrm2(n, wts, r) / ref;
+        if (st->relres_true < tol) { st->status = ORC_CONVERGED; return; }
+        if (st->iters >= maxit) { st->status = ORC_MAXIT; return; }
+        ++st->fails;
+        if (st->fails >= 3) { st->status = ORC_STAGNATED; return; }
+        ++st->restarts;
     }
 final_check:
     residual(n, rp, ci, val, b, x, r);
-    relres_true = wnrm2(n, wts, r) / ref;
-done:
-    if (info_i) {
-        info_i[0] = iters; info_i[1] = restarts; info_i[2] = status; info_i[3] = half;
-        info_i[4] = fails; info_i[5] = brk;
+    st->relres_true = wnrm2(n, wts, r) / ref;
+}
+
+int orc_bicgstab(int n, const int* rp, const int* ci, const double* val, const double* b,
+                 double* x, double tol, int maxit, double eps_b, const double* wts,
+                 const double* lu, double* hist, int* info_i, double* info_d) {
+    if (n <= 0 || maxit < 0 || !(tol > 0.0)) return ORC_ERR_ARG;
+    bicg_work w;
+    if (!bicg_work_alloc(&w, (size_t)n)) return ORC_ERR_ALLOC;
+    bicg_state st = {0, 0, ORC_MAXIT, 0, 0, 0, 1.0, 1.0};
+    residual(n, rp, ci, val, b, x, w.r);
+    double ref = wnrm2(n, wts, w.r);
+    if (ref == 0.0) {
+        st.status = ORC_CONVERGED;
+        st.est = st.relres_true = 0.0;
+    } else if (maxit > 0) {
+        bicg64_run(n, rp, ci, val, b, x, tol, maxit, eps_b, wts, lu, hist, ref, &w, &st);
     }
-    if (info_d) { info_d[0] = est; info_d[1] = relres_true; }
-    free(r); free(rh); free(p); free(v); free(s); free(t); free(ph); free(sh);
+    if (info_i) {
+        info_i[0] = st.iters; info_i[1] = st.restarts; info_i[2] = st.status;
+        info_i[3] = st.half; info_i[4] = st.fails; info_i[5] = st.brk;
+    }
+    if (info_d) { info_d[0] = st.est; info_d[1] = st.relres_true; }
+    bicg_work_free(&w);
     return ORC_OK;
 }
 
@@ -635,12 +666,22 @@ done:
  *      recurrences have diverged, and the refinement step decides (a choice the paper leaves
  *      open: float-storage Bi-CGSTAB can diverge to overflow on the jump problems).
  * Stagnation: a refinement step that does not halve rt counts as a failure; three failures
- * in a row end the solve as STAGNATED. Breakdown tests as in Bi-CGSTAB (R6), on the stored
- * vectors.
+ * in a row end the refinement. Breakdown tests as in Bi-CGSTAB (R6), on the stored vectors.
+ * FP64 continuation (fallback != 0; a choice of this build, not in the paper): the solve is
+ * handed to FP64 Bi-CGSTAB (the algorithm of orc_bicgstab) when the refinement stops paying:
+ *   - a run leaves the true residual above the one it started from (float recurrences that
+ *     diverged move x away from the solution before the divergence test ends them): the run
+ *     is undone (x is restored to its value at the run's start), then handed over;
+ *   - three refinement steps in a row do not halve the true residual;
+ *   - a float-storage run breaks down (after the same undo test).
+ * The continuation starts from x with r = b - A x, keeps the reference norm and the
+ * iteration count towards maxit, counts as one more restart, and decides the status.
+ * info_i[6] = the iteration count at the hand-over (0 if it never happened). With
+ * fallback == 0 the refinement ends as STAGNATED or BREAKDOWN, without any undo.
  * ------------------------------------------------------------------------------------- */
 int orc_bicgstab_ir(int n, const int* rp, const int* ci, const double* val, const double* b,
                     double* x, double tol, int maxit, double eps_b, const double* wts,
-                    double delta, int* info_i, double* info_d) {
+                    double delta, int fallback, int* info_i, double* info_d) {
     if (n <= 0 || maxit < 0 || !(tol > 0.0) || !(delta > 0.0) || !(delta < 1.0))
         return ORC_ERR_ARG;
     size_t nn = (size_t)n;
@@ -653,12 +694,14 @@ int orc_bicgstab_ir(int n, const int* rp, const int* ci, const double* val, cons
     float* t = (float*)malloc(sizeof(float) * nn);
     double* r = (double*)malloc(sizeof(double) * nn);  /* true residual, double */
     double* s = (double*)malloc(sizeof(double) * nn);
-    if (!fval || !rs || !rh || !p || !v || !t || !r || !s) {
-        free(fval); free(rs); free(rh); free(p); free(v); free(t); free(r); free(s);
+    double* xs = (double*)malloc(sizeof(double) * nn); /* x at the start of the run */
+    if (!fval || !rs || !rh || !p || !v || !t || !r || !s || !xs) {
+        free(fval); free(rs); free(rh); free(p); free(v); free(t); free(r); free(s); free(xs);
         return ORC_ERR_ALLOC;
     }
     for (int k = 0; k < nnz; ++k) fval[k] = (float)val[k];
     int iters = 0, restarts = 0, status = ORC_MAXIT, fails = 0, half = 0, brk = 0;
+    int fp64_from = 0;
     double est = 1.0, relres_true = 1.0;
 
     residual(n, rp, ci, val, b, x, r);
@@ -673,6 +716,7 @@ int orc_bicgstab_ir(int n, const int* rp, const int* ci, const double* val, cons
     for (;;) {
         /* step 2: restart from the true residual */
         double target = delta * rt > tol ? delta * rt : tol;
+        memcpy(xs, x, sizeof(double) * nn);
         for (int i = 0; i < n; ++i) rs[i] = (float)r[i];
         memcpy(rh, rs, sizeof(float) * nn);
         double rh_norm = sqrt(fdot(n, rh, rh));
@@ -682,7 +726,7 @@ int orc_bicgstab_ir(int n, const int* rp, const int* ci, const double* val, cons
         half = 0;
         for (;;) {
             if (fabs(rho) <= eps_b * rh_norm * sqrt(fdot(n, rs, rs))) {
-                status = ORC_BREAKDOWN; brk = 3; goto final_check;
+                status = ORC_BREAKDOWN; brk = 3; goto float_breakdown;
             }
             if (first) {
                 memcpy(p, rs, sizeof(float) * nn);
@@ -700,7 +744,7 @@ int orc_bicgstab_ir(int n, const int* rp, const int* ci, const double* val, cons
             }
             double sigma = fdot(n, rh, v);
             if (fabs(sigma) <= eps_b * rh_norm * sqrt(fdot(n, v, v))) {
-                status = ORC_BREAKDOWN; brk = 1; goto final_check;
+                status = ORC_BREAKDOWN; brk = 1; goto float_breakdown;
             }
             alpha = rho / sigma;
             for (int i = 0; i < n; ++i) s[i] = (double)rs[i] - alpha * (double)v[i];
@@ -720,7 +764,7 @@ int orc_bicgstab_ir(int n, const int* rp, const int* ci, const double* val, cons
             for (int i = 0; i < n; ++i) ts += (double)t[i] * s[i];
             double tt = fdot(n, t, t);
             if (fabs(ts) <= eps_b * sqrt(tt) * nrm2(n, s)) {
-                status = ORC_BREAKDOWN; brk = 2; goto final_check;
+                status = ORC_BREAKDOWN; brk = 2; goto float_breakdown;
             }
             omega = ts / tt;
             for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * (double)p[i] + omega * s[i];
@@ -739,26 +783,56 @@ int orc_bicgstab_ir(int n, const int* rp, const int* ci, const double* val, cons
         residual(n, rp, ci, val, b, x, r);
         relres_true = wnrm2(n, wts, r) / ref;
         if (relres_true < tol) { status = ORC_CONVERGED; goto done; }
+        if (fallback && !(relres_true <= rt)) {   /* the run made x worse: undo, hand over */
+            memcpy(x, xs, sizeof(double) * nn);
+            goto fp64;
+        }
         if (iters >= maxit) { status = ORC_MAXIT; goto done; }
         if (!(relres_true < 0.5 * rt)) {
             ++fails;
-            if (fails >= 3) { status = ORC_STAGNATED; goto done; }
+            if (fails >= 3) {
+                if (fallback) goto fp64;
+                status = ORC_STAGNATED;
+                goto done;
+            }
         } else {
             fails = 0;
         }
         rt = relres_true;
         ++restarts;
     }
-final_check:
+float_breakdown:
     residual(n, rp, ci, val, b, x, r);
     relres_true = wnrm2(n, wts, r) / ref;
+    if (!fallback) goto done;
+    if (!(relres_true <= rt)) memcpy(x, xs, sizeof(double) * nn);   /* undo the run */
+fp64:
+    {
+        /* FP64 continuation from x: r = b - A x, then orc_bicgstab's iteration */
+        bicg_work w;
+        if (!bicg_work_alloc(&w, nn)) {
+            free(fval); free(rs); free(rh); free(p); free(v); free(t); free(r); free(s);
+            free(xs);
+            return ORC_ERR_ALLOC;
+        }
+        residual(n, rp, ci, val, b, x, w.r);
+        fp64_from = iters;
+        bicg_state st = {iters, restarts + 1, ORC_MAXIT, 0, 0, 0, est,
+                         wnrm2(n, wts, w.r) / ref};
+        if (st.relres_true < tol) st.status = ORC_CONVERGED;
+        else if (iters < maxit)
+            bicg64_run(n, rp, ci, val, b, x, tol, maxit, eps_b, wts, NULL, NULL, ref, &w, &st);
+        iters = st.iters; restarts = st.restarts; status = st.status; fails = st.fails;
+        half = st.half; brk = st.brk; est = st.est; relres_true = st.relres_true;
+        bicg_work_free(&w);
+    }
 done:
     if (info_i) {
         info_i[0] = iters; info_i[1] = restarts; info_i[2] = status; info_i[3] = half;
-        info_i[4] = fails; info_i[5] = brk;
+        info_i[4] = fails; info_i[5] = brk; info_i[6] = fp64_from;
     }
     if (info_d) { info_d[0] = est; info_d[1] = relres_true; }
-    free(fval); free(rs); free(rh); free(p); free(v); free(t); free(r); free(s);
+    free(fval); free(rs); free(rh); free(p); free(v); free(t); free(r); free(s); free(xs);
     return ORC_OK;
 }
 

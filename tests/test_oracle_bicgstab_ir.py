@@ -84,15 +84,55 @@ def test_float_storage_costs_iterations_on_jump_problems():
     assert itir > 1.2 * it64, (itir, it64)
 
 
-def test_divergence_ends_runs_and_stagnates():
+def test_divergence_ends_runs_and_stagnates_without_fallback():
     # Float-storage Bi-CGSTAB diverges to overflow on this GS(1)-scaled 2D jump system; the
-    # run ends once its estimate exceeds rt / delta, and three refinement steps without
-    # progress end the solve as stagnated with a finite residual (instead of 10,000 NaN
-    # iterations). FP64 Bi-CGSTAB converges on the same system.
+    # run ends once its estimate exceeds rt / delta, and (with the FP64 continuation switched
+    # off) three refinement steps without progress end the solve as stagnated with a finite
+    # residual (instead of 10,000 NaN iterations). FP64 Bi-CGSTAB converges on the system.
     P = problems.batch_system(problems.batch_specs(1, seed=47, n_min=12, n_max=20)[0])
     S, w = scaled(P, 1)
     _, i64 = oracle.bicgstab(S, S.b, tol=1e-10, weights=w)
     assert i64.status == oracle.CONVERGED
-    _, iir = oracle.bicgstab_ir(S, S.b, tol=1e-10, delta=1e-6, weights=w)
+    _, iir = oracle.bicgstab_ir(S, S.b, tol=1e-10, delta=1e-6, weights=w, fallback=False)
     assert iir.status == oracle.STAGNATED and iir.verify_failures == 3
-    assert np.isfinite(iir.relres_true) and iir.iters < 10000
+    assert np.isfinite(iir.relres_true) and iir.iters < 10000 and iir.fp64_from == 0
+
+
+@pytest.mark.parametrize("seed,p", [(47, 1), (95, 2), (13, 2)])
+def test_fp64_continuation_converges_where_refinement_stops(seed, p):
+    # Systems of the batch recipe on which float-storage refinement cannot reach the
+    # tolerance: without the continuation it stagnates (its runs diverge and the true residual
+    # is left far above the start, up to overflow); with it, the solve hands over to FP64
+    # Bi-CGSTAB and must end as an FP64 solve does: converged on the GS(2) metric, with the
+    # solution dense LU gives (to the condition-number bound) and the reported residual equal
+    # to one recomputed here.
+    n_min, n_max = (12, 20) if seed == 47 else (10, 22)
+    P = problems.batch_system(problems.batch_specs(1, seed=seed, n_min=n_min, n_max=n_max)[0])
+    S, w = scaled(P, p)
+    W = w if p == 1 else None
+    tol = 1e-10 if p == 1 else 1e-8
+    _, nofb = oracle.bicgstab_ir(S, S.b, tol=tol, delta=1e-6, weights=W, fallback=False)
+    assert nofb.status != oracle.CONVERGED
+    x, info = oracle.bicgstab_ir(S, S.b, tol=tol, delta=1e-6, weights=W)
+    assert info.status == oracle.CONVERGED and info.relres_true < tol
+    assert 0 < info.fp64_from < info.iters <= 10000
+    A = S.dense()
+    xs = np.linalg.solve(A, S.b)
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= 10 * np.linalg.cond(A) * tol
+    wt = np.ones(S.n) if W is None else W
+    r = wt * (S.b - A @ x)
+    assert np.linalg.norm(r) / np.linalg.norm(wt * S.b) == pytest.approx(info.relres_true,
+                                                                        rel=1e-6)
+
+
+def test_undo_restores_the_start_of_a_diverged_run():
+    # The continuation starts from the x the refinement last accepted: a run that diverged is
+    # undone. On this system the first float run diverges (its estimate rises far above the
+    # start before the divergence test ends it), so with maxit at the hand-over point the
+    # solve stops with x back at x0 = 0: relative residual exactly 1, not the run's.
+    P = problems.batch_system(problems.batch_specs(1, seed=13, n_min=10, n_max=22)[0])
+    S, _ = scaled(P)
+    _, full = oracle.bicgstab_ir(S, S.b, tol=1e-8, delta=1e-6)
+    x, cut = oracle.bicgstab_ir(S, S.b, tol=1e-8, delta=1e-6, maxit=full.fp64_from)
+    assert cut.status == oracle.MAXIT and cut.iters == full.fp64_from
+    assert cut.relres_true == 1.0 and not x.any()
