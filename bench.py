@@ -315,6 +315,14 @@ def bench_batch(args, gsk, problems, dev):
         k = min(args.cpu_sample_systems, len(specs))
         sample = sorted(int(i) for i in np.random.default_rng(1007).choice(len(specs), k,
                                                                             replace=False))
+    acc_sample = []
+    if mixed and not gmres:
+        # mixed results against the FP64 oracle's solutions: the 12 smallest systems of a
+        # seeded sample of 48 (the oracle solves them in seconds)
+        pool = np.random.default_rng(1008).choice(len(specs), 48, replace=False)
+        acc_sample = sorted(sorted((int(i) for i in pool),
+                                   key=lambda i: int(np.prod(specs[i]["dims"])))[:12])
+        sample = sorted(set(sample) | set(acc_sample))
     systems, host = build_batch_systems(gsk, problems, dev, specs, keep_host=sample)
     unit = 512 if mixed else 256
     tuned = None
@@ -401,6 +409,8 @@ def bench_batch(args, gsk, problems, dev):
         "solves_per_step": len(systems),
         "converged_per_step": converged / args.steps,
         "status": status_counts(infos),
+        "fp64_continuations": (sum(1 for v in infos.values() if v.fp64_from > 0)
+                               if mixed and not gmres else None),
         "not_converged": not_conv,
         "latency_p50_ms": round(1e3 * pct(lats, 0.5), 3),
         "latency_p99_ms": round(1e3 * pct(lats, 0.99), 3),
@@ -430,6 +440,26 @@ def bench_batch(args, gsk, problems, dev):
                   "every k-th chunk of the timed steps runs without its graph and times each "
                   "launch of the class"))
     eng.close()
+    if acc_sample:
+        import oracle
+        errs = {}
+        for i in acc_sample:
+            P = host[i]
+            vo, bo, _, _ = oracle.gs_scale(P, P.b, 2)
+            S = P.copy()
+            S.val, S.b = vo, bo
+            x64, i64 = oracle.bicgstab(S, bo, tol=tol)
+            xg = xs[i].cpu().numpy()
+            errs[str(i)] = {"n": P.n, "x_rel_error_vs_fp64_oracle":
+                            float(np.linalg.norm(xg - x64) / np.linalg.norm(x64)),
+                            "oracle_status": i64.status_name,
+                            "relres_true_mixed": infos[i].relres_true}
+        ev = [e["x_rel_error_vs_fp64_oracle"] for e in errs.values()]
+        out["accuracy_vs_fp64_oracle"] = {
+            "systems": errs, "max": max(ev), "median": pct(ev, 0.5),
+            "note": "x of the mixed engine against orc_bicgstab's x (FP64, same tol) on the 12 "
+                    "smallest of 48 seeded systems; two solutions with residual below tol "
+                    "differ by up to about cond(A) tol"}
     if not args.no_solo and not (mixed and not gmres):
         # the same solves one at a time: gsk_gs_scale + packing + the single solver per system
         log("timing the one-at-a-time path")

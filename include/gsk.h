@@ -122,6 +122,9 @@ typedef struct gsk_info {
     int32_t half_step;        /* Bi-CGSTAB: 1 if it stopped on ||s|| after half a step      */
     int32_t verify_failures;  /* consecutive failed true-residual checks at the end        */
     int32_t breakdown_test;   /* with GSK_BREAKDOWN: which test fired (GSK_BRK_*), else 0    */
+    int32_t fp64_from;        /* mixed-precision Bi-CGSTAB engine: iterations done before the
+                                 solve continued in FP64 (0: it never did)                 */
+    int32_t reserved;         /* 0                                                         */
     double relres_recursive;  /* last recursive estimate ||W r||/||W r0||                  */
     double relres_true;       /* ||W (b - A x)|| / ||W (b - A x0)|| at return              */
 } gsk_info;
@@ -434,6 +437,9 @@ typedef struct gsk_engine_config {
                               residual is recomputed) once its estimate has dropped by this
                               factor below the residual it started from, or below tol;
                               0 selects 1e-6; otherwise in (0, 1)                           */
+    int32_t run_cap;       /* mixed Bi-CGSTAB: a run with FP32 storage also ends after this
+                              many iterations; 0 selects 1000, -1: no cap                   */
+    int32_t reserved;      /* 0                                                             */
 } gsk_engine_config;
 
 /* 0 for an invalid configuration. */

@@ -55,7 +55,7 @@ def _load():
         lib.orc_bicgstab_ir.restype = ctypes.c_int
         lib.orc_bicgstab_ir.argtypes = [ctypes.c_int, _ip, _ip, _dp, _dp, _dp, ctypes.c_double,
                                         ctypes.c_int, ctypes.c_double, _dp, ctypes.c_double,
-                                        ctypes.c_int, _ip, _dp]
+                                        ctypes.c_int, ctypes.c_int, _ip, _dp]
         lib.orc_default_breakdown_eps.argtypes = []
         _lib = lib
     return _lib
@@ -228,11 +228,12 @@ def bicgstab(A, b, x0=None, tol: float = 1e-8, maxit: int = 10000,
 
 def bicgstab_ir(A, b, x0=None, tol: float = 1e-8, maxit: int = 10000,
                 eps_b: Optional[float] = None, weights=None, delta: float = 2.0 ** -14,
-                fallback: bool = True):
+                fallback: bool = True, run_cap: int = 1000):
     """Mixed-precision Bi-CGSTAB: FP64 residuals and x, Bi-CGSTAB runs with float storage
     between them, each ending at a reduction by delta of the residual it started from; with
     fallback, a refinement that stops making progress (or breaks down) continues as FP64
-    Bi-CGSTAB. Returns (x, Info); Info.fp64_from = iterations before the FP64 continuation."""
+    Bi-CGSTAB; a float run ends after run_cap iterations (0: no cap). Returns (x, Info);
+    Info.fp64_from = iterations before the FP64 continuation."""
     rp, ci, val = _csr(A)
     n = rp.shape[0] - 1
     b = np.ascontiguousarray(b, dtype=np.float64)
@@ -243,7 +244,7 @@ def bicgstab_ir(A, b, x0=None, tol: float = 1e-8, maxit: int = 10000,
     w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
     rc = _load().orc_bicgstab_ir(n, _i(rp), _i(ci), _d(val), _d(b), _d(x), float(tol),
                                  int(maxit), eps, _d(w), float(delta), 1 if fallback else 0,
-                                 _i(ii), _d(dd))
+                                 int(run_cap), _i(ii), _d(dd))
     if rc != OK:
         raise OracleError(rc)
     info = _info(ii, dd)

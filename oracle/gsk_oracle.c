@@ -664,7 +664,9 @@ int orc_bicgstab(int n, const int* rp, const int* ci, const double* val, const d
  *      residual it started from is as far as float storage is trusted to go. It also ends
  *      when the estimate ||W r~|| / ||W r0|| exceeds rt / delta or is not finite: the float
  *      recurrences have diverged, and the refinement step decides (a choice the paper leaves
- *      open: float-storage Bi-CGSTAB can diverge to overflow on the jump problems).
+ *      open: float-storage Bi-CGSTAB can diverge to overflow on the jump problems); and,
+ *      with run_cap > 0, after run_cap iterations (a run that wanders without reaching its
+ *      target would otherwise spend the whole iteration budget before any refinement step).
  * Stagnation: a refinement step that does not halve rt counts as a failure; three failures
  * in a row end the refinement. Breakdown tests as in Bi-CGSTAB (R6), on the stored vectors.
  * FP64 continuation (fallback != 0; a choice of this build, not in the paper): the solve is
@@ -681,8 +683,9 @@ int orc_bicgstab(int n, const int* rp, const int* ci, const double* val, const d
  * ------------------------------------------------------------------------------------- */
 int orc_bicgstab_ir(int n, const int* rp, const int* ci, const double* val, const double* b,
                     double* x, double tol, int maxit, double eps_b, const double* wts,
-                    double delta, int fallback, int* info_i, double* info_d) {
-    if (n <= 0 || maxit < 0 || !(tol > 0.0) || !(delta > 0.0) || !(delta < 1.0))
+                    double delta, int fallback, int run_cap, int* info_i, double* info_d) {
+    if (n <= 0 || maxit < 0 || !(tol > 0.0) || !(delta > 0.0) || !(delta < 1.0) ||
+        run_cap < 0)
         return ORC_ERR_ARG;
     size_t nn = (size_t)n;
     int nnz = rp[n];
@@ -717,6 +720,7 @@ int orc_bicgstab_ir(int n, const int* rp, const int* ci, const double* val, cons
         /* step 2: restart from the true residual */
         double target = delta * rt > tol ? delta * rt : tol;
         memcpy(xs, x, sizeof(double) * nn);
+        const int run_start = iters;
         for (int i = 0; i < n; ++i) rs[i] = (float)r[i];
         memcpy(rh, rs, sizeof(float) * nn);
         double rh_norm = sqrt(fdot(n, rh, rh));
@@ -775,7 +779,9 @@ int orc_bicgstab_ir(int n, const int* rp, const int* ci, const double* val, cons
                 ws += e * e;
             }
             est = sqrt(ws) / ref;
-            if (est < target || iters >= maxit || !(est <= rt / delta)) break;
+            if (est < target || iters >= maxit || !(est <= rt / delta) ||
+                (run_cap > 0 && iters - run_start >= run_cap))
+                break;
             rho_old = rho;
             rho = fdot(n, rh, rs);
         }

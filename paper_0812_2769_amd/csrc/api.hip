@@ -130,6 +130,8 @@ void fill_info(gsk_info* info, const Summary& s) {
   info->half_step = s.half;
   info->verify_failures = s.fails;
   info->breakdown_test = s.status == GSK_BREAKDOWN ? s.brk : 0;
+  info->fp64_from = s.fp64_from;
+  info->reserved = 0;
   info->relres_recursive = s.relres_rec;
   info->relres_true = s.relres_true;
 }
@@ -395,6 +397,8 @@ static int engine_cfg(const gsk_engine_config* c, gsk::EngineConfig& cfg) {
   cfg.check_every = gmres ? 0 : c->check_every;
   cfg.use_graph = (c->flags & GSK_ENGINE_GRAPH) != 0;
   cfg.delta = delta;
+  if (c->run_cap < -1) return set_err(GSK_ERR_INVALID_ARG, "run_cap must be >= -1");
+  cfg.run_cap = c->run_cap == 0 ? 1000 : c->run_cap < 0 ? 0 : c->run_cap;
   if (c->tile_units < 0 || c->tile_units > 2 ||
       (c->tile_units == 2 && (gmres || c->precision != GSK_PRECISION_FP64)))
     return set_err(GSK_ERR_INVALID_ARG, "tile_units must be 0 or 1 (or 2 for FP64 Bi-CGSTAB)");

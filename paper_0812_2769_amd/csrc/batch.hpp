@@ -32,6 +32,8 @@ struct SysDesc {
 struct BCtl {
   Summary sum;
   int maxit, first, has_w, bad;
+  int fp64;         // mixed engine: the system continues in FP64 (FP64 engine: unused)
+  int run_start;    // mixed engine: iteration count at the start of the current float run
   double tol, eps_b, ref;
   double rho, rho_old, alpha, omega, beta, rh_norm;
   double target, last_rt;
@@ -117,7 +119,14 @@ struct MArgs {
   float* p[2];
   float* v[2];
   float* t;
+  double* r64;           // FP64 vectors of the systems that continue in FP64
+  double* rh64;
+  double* p64[2];
+  double* v64[2];
+  double* t64;
+  double* xprev;         // x at the start of the current float run (FP64)
   double delta;          // a run ends at a reduction by delta of the residual it started from
+  int run_cap;           // ... or after run_cap iterations (0: no cap)
   int par;
 };
 

@@ -12,16 +12,24 @@
 //   3. The run ends (back to 1) when its estimate ||W s|| / ||W r0|| (half step) or
 //      ||W r~|| / ||W r0|| drops below max(tol, delta rt), and also when ||W r~|| / ||W r0||
 //      exceeds rt / delta or is not finite (the float recurrences have diverged; they can,
-//      to overflow, on the jump problems).
-//   A refinement step that does not halve rt counts as a failure; three in a row end the solve
-//   as STAGNATED. Breakdown tests as in FP64 Bi-CGSTAB, on the stored vectors.
+//      to overflow, on the jump problems), or after run_cap iterations.
+//   A refinement step that does not halve rt counts as a failure. Breakdown tests as in FP64
+//   Bi-CGSTAB, on the stored vectors.
+//   4. FP64 continuation (orc_bicgstab_ir with fallback, the definition followed here): a run
+//      that leaves rt above the value it started from is undone (x := its value at the run's
+//      start, saved by the run's first U launch) and the solve continues as FP64 Bi-CGSTAB;
+//      so does a solve after three failures in a row, or after a float-storage breakdown
+//      (undone first if it left rt higher). The continuation is the FP64 engine's iteration
+//      (the bodies of bicg_batch.hpp on FP64 vectors of the engine's row space), from r = b - A x
+//      with the same reference norm, iteration count and cap; the hand-over counts as a
+//      restart and its iteration count is reported (Summary::fp64_from).
 //
 // Workgroups take units of two 256-row tiles (FP32 loads carry half the bytes, so a thread
 // keeps two rows' loads in flight); partial sums stay per tile, so each system's finalize
 // reduces its tiles in order. Float storage costs Bi-CGSTAB iterations on the paper's jump
 // problems (each restart discards the Krylov space); this form exists to measure that on the
 // device beside the FP64 engine.
-#include "batch.hpp"
+#include "bicg_batch.hpp"
 
 namespace gsk {
 
@@ -92,6 +100,28 @@ __device__ inline void unit_product(const SysDesc& d, const int (&row0)[2], cons
   }
 }
 
+// The engine's FP64 vectors as the FP64 bodies take them (units of two tiles).
+__device__ inline BArgsB fp64_view(const MArgs& a) {
+  BArgsB b;
+  b.sys = a.sys;
+  b.act = a.act;
+  b.n_act = a.n_act;
+  b.ctl = a.ctl;
+  b.partials = a.partials;
+  b.max_tiles = a.pstride;
+  b.max_units = a.max_units;
+  b.rv = 2;
+  b.r = a.r64;
+  b.rh = a.rh64;
+  b.p[0] = a.p64[0];
+  b.p[1] = a.p64[1];
+  b.v[0] = a.v64[0];
+  b.v[1] = a.v64[1];
+  b.t = a.t64;
+  b.par = a.par;
+  return b;
+}
+
 __device__ inline void unit_rows(const SysDesc& d, int unit, int& lt0, int (&row0)[2],
                                  int (&nr)[2]) {
   lt0 = (unit - d.unit_off) * 2;
@@ -107,6 +137,14 @@ __global__ __launch_bounds__(BS) void k_bm_prepare(MArgs a) {
   on_unit(a, [&](int unit, int s) {
     const SysDesc d = a.sys[s];
     BCtl* c = a.ctl + s;
+    if (c->sum.state == ST_ROLLBACK) {   // undo the last float run
+      const int lt0 = (unit - d.unit_off) * 2;
+      for (int k = 0; k < 2; ++k) {
+        const int row = (lt0 + k) * BS + (int)threadIdx.x;
+        if (row < d.n) d.x[row] = a.xprev[d.row_off + row];
+      }
+      return;
+    }
     if (c->sum.state != ST_SCALE || (c->bad & BAD_CSR)) return;
     const int lt0 = (unit - d.unit_off) * 2;
     for (int k = 0; k < 2; ++k) {
@@ -122,6 +160,7 @@ __global__ __launch_bounds__(64) void k_bm_fin_prepare(MArgs a) {
   if (threadIdx.x != 0 || a.sys[s].ntiles == 0) return;
   BCtl* c = a.ctl + s;
   if (c->sum.state == ST_SCALE) c->sum.state = ST_INIT;
+  else if (c->sum.state == ST_ROLLBACK) c->sum.state = ST_FP64START;
 }
 
 // R: r = b - A x (FP64 matrix), r~ = r^ = fl(r) when a run starts; partials ||r||^2,
@@ -133,9 +172,18 @@ __global__ __launch_bounds__(BS) void k_bm_residual(MArgs a) {
     const SysDesc d = a.sys[s];
     BCtl* c = a.ctl + s;
     const int st = c->sum.state;
+    const int lt0 = (unit - d.unit_off) * 2;
+    if (c->fp64) {   // FP64 continuation: the FP64 engine's residual
+      if (st != ST_FP64START && st != ST_VERIFY && st != ST_FINAL) return;
+      const BArgsB b = fp64_view(a);
+      for (int k = 0; k < 2 && lt0 + k < d.ntiles; ++k) {
+        if (k) __syncthreads();
+        bicg64_residual_tile(b, d.tile_off + lt0 + k, s, st, L, red);
+      }
+      return;
+    }
     if (st != ST_INIT && st != ST_VERIFY && st != ST_FINAL) return;
     if (c->bad) return;
-    const int lt0 = (unit - d.unit_off) * 2;
     const int t = threadIdx.x;
     for (int k = 0; k < 2; ++k) {
       const int row0 = (lt0 + k) * BS;
@@ -171,13 +219,30 @@ __global__ __launch_bounds__(BS) void k_bm_residual(MArgs a) {
 }
 
 // FR: convergence test on the FP64 residual, refinement bookkeeping, start of a run.
+// Hand-over to the FP64 continuation (thread 0 of a finalize workgroup): undo the last run
+// first if it left the true residual rt above the value it started from.
+__device__ inline void hand_over(BCtl* c, double rt) {
+  c->fp64 = 1;
+  c->sum.fp64_from = c->sum.iters;
+  c->sum.restarts += 1;
+  c->sum.fails = 0;
+  c->sum.status = S_MAXIT;
+  c->sum.brk = BRK_NONE;
+  c->target = c->tol;
+  c->sum.state = rt <= c->last_rt ? ST_FP64START : ST_ROLLBACK;
+}
+
+// FR: convergence test on the FP64 residual, refinement bookkeeping, start of a run; for a
+// system in FP64 the FP64 engine's rule (verification, restart, three failures: STAGNATED).
 __global__ __launch_bounds__(BS) void k_bm_fin_residual(MArgs a) {
   const int s = blockIdx.x;
   const SysDesc d = a.sys[s];
   if (d.ntiles == 0) return;
   BCtl* c = a.ctl + s;
   const int st = c->sum.state;
-  if (st != ST_INIT && st != ST_VERIFY && st != ST_FINAL) return;
+  const bool f64 = c->fp64 != 0;
+  if (st != ST_INIT && st != ST_VERIFY && st != ST_FINAL && !(f64 && st == ST_FP64START))
+    return;
   if (c->bad) {
     if (threadIdx.x == 0) {
       c->sum.state = ST_DONE;
@@ -190,6 +255,45 @@ __global__ __launch_bounds__(BS) void k_bm_fin_residual(MArgs a) {
   if (threadIdx.x != 0) return;
   const double nr = sqrt(out[0]);
   const double nwr = d.W ? sqrt(out[1]) : nr;
+  if (f64) {
+    const double rt = nwr / c->ref;
+    c->sum.relres_true = rt;
+    if (st == ST_FINAL) {
+      c->sum.state = ST_DONE;
+      return;
+    }
+    if (rt < c->tol) {
+      c->sum.status = S_CONVERGED;
+      c->sum.state = ST_DONE;
+      return;
+    }
+    if (c->sum.iters >= c->maxit) {
+      c->sum.status = S_MAXIT;
+      c->sum.state = ST_DONE;
+      return;
+    }
+    if (st == ST_VERIFY) {
+      c->sum.fails += 1;
+      if (c->sum.fails >= 3) {
+        c->sum.status = S_STAGNATED;
+        c->sum.state = ST_DONE;
+        return;
+      }
+      c->sum.restarts += 1;
+    }
+    c->rh_norm = nr;
+    c->rho = out[0];
+    c->sum.half = 0;
+    if (fabs(c->rho) <= c->eps_b * nr * nr) {
+      c->sum.status = S_BREAKDOWN;
+      c->sum.brk = BRK_RHO;
+      c->sum.state = ST_DONE;
+      return;
+    }
+    c->first = 1;
+    c->sum.state = ST_RUNNING;
+    return;
+  }
   const double ns = sqrt(out[2]);
   double rt = 1.0;
   if (st == ST_INIT) {
@@ -209,13 +313,17 @@ __global__ __launch_bounds__(BS) void k_bm_fin_residual(MArgs a) {
   } else {
     rt = nwr / c->ref;
     c->sum.relres_true = rt;
-    if (st == ST_FINAL) {
-      c->sum.state = ST_DONE;
+    if (st == ST_FINAL) {   // a float-storage run broke down
+      hand_over(c, rt);
       return;
     }
     if (rt < c->tol) {
       c->sum.status = S_CONVERGED;
       c->sum.state = ST_DONE;
+      return;
+    }
+    if (!(rt <= c->last_rt)) {   // the run made x worse
+      hand_over(c, rt);
       return;
     }
     if (c->sum.iters >= c->maxit) {
@@ -226,8 +334,7 @@ __global__ __launch_bounds__(BS) void k_bm_fin_residual(MArgs a) {
     if (!(rt < 0.5 * c->last_rt)) {
       c->sum.fails += 1;
       if (c->sum.fails >= 3) {
-        c->sum.status = S_STAGNATED;
-        c->sum.state = ST_DONE;
+        hand_over(c, rt);
         return;
       }
     } else {
@@ -237,13 +344,12 @@ __global__ __launch_bounds__(BS) void k_bm_fin_residual(MArgs a) {
   }
   c->last_rt = rt;
   c->target = a.delta * rt > c->tol ? a.delta * rt : c->tol;
+  c->run_start = c->sum.iters;
   c->rh_norm = ns;
   c->rho = out[2];
   c->sum.half = 0;
   if (fabs(c->rho) <= c->eps_b * ns * ns) {
-    c->sum.status = S_BREAKDOWN;
-    c->sum.brk = BRK_RHO;
-    c->sum.state = ST_DONE;
+    hand_over(c, rt);   // float-storage breakdown at the start of a run (x unchanged)
     return;
   }
   c->first = 1;
@@ -252,12 +358,17 @@ __global__ __launch_bounds__(BS) void k_bm_fin_residual(MArgs a) {
 
 // P: p (stored FP32), v = fl(A p); partials (r^, v), ||v||^2.
 __global__ __launch_bounds__(BS) void k_bm_p(MArgs a) {
-  __shared__ TileLds L;
+  __shared__ UnitLds U;
+  TileLds& L = U.csr;
   __shared__ double red[NC_MAX * WAVES];
   on_unit(a, [&](int unit, int s) {
     const SysDesc d = a.sys[s];
     BCtl* c = a.ctl + s;
     if (c->sum.state != ST_RUNNING) return;
+    if (c->fp64) {
+      bicg64_p_unit2(fp64_view(a), unit, s, U, red);
+      return;
+    }
     const int q = a.par;
     const int64_t o = d.row_off;
     const GatherPM G{a.r + o, a.p[q] + o, a.v[q] + o, c->beta, c->omega, c->first};
@@ -307,12 +418,17 @@ __global__ __launch_bounds__(BS) void k_bm_fin_p(MArgs a) {
 
 // S: t = fl(A s) with s = r~ - alpha v; partials (t, s), (t, t), ||s||^2, ||W s||^2.
 __global__ __launch_bounds__(BS) void k_bm_s(MArgs a) {
-  __shared__ TileLds L;
+  __shared__ UnitLds U;
+  TileLds& L = U.csr;
   __shared__ double red[NC_MAX * WAVES];
   on_unit(a, [&](int unit, int s) {
     const SysDesc d = a.sys[s];
     BCtl* c = a.ctl + s;
     if (c->sum.state != ST_RUNNING) return;
+    if (c->fp64) {
+      bicg64_s_unit2(fp64_view(a), unit, s, U, red);
+      return;
+    }
     const int64_t o = d.row_off;
     const GatherSM G{a.r + o, a.v[a.par ^ 1] + o, c->alpha};
     int lt0, row0[2], nr[2];
@@ -373,7 +489,8 @@ __global__ __launch_bounds__(BS) void k_bm_fin_s(MArgs a) {
 }
 
 // U: x += alpha p + omega s (FP64 x), r~ = fl(s - omega t); partials (r^, r~), ||r~||^2,
-// ||W r~||^2. After a half-step exit only x += alpha p.
+// ||W r~||^2. After a half-step exit only x += alpha p. The first U of a run saves x as it was
+// at the run's start (for the undo of a run that diverged).
 __global__ __launch_bounds__(BS) void k_bm_u(MArgs a) {
   __shared__ double red[NC_MAX * WAVES];
   on_unit(a, [&](int unit, int s) {
@@ -381,26 +498,41 @@ __global__ __launch_bounds__(BS) void k_bm_u(MArgs a) {
     BCtl* c = a.ctl + s;
     const int st = c->sum.state;
     if (st != ST_RUNNING && st != ST_HALF) return;
+    const int lt0 = (unit - d.unit_off) * 2;
+    if (c->fp64) {
+      const BArgsB b = fp64_view(a);
+      for (int k = 0; k < 2 && lt0 + k < d.ntiles; ++k) {
+        if (k) __syncthreads();
+        bicg64_u_tile(b, d.tile_off + lt0 + k, s, st, red);
+      }
+      return;
+    }
     const int q = a.par ^ 1;
     const int64_t o = d.row_off;
     const float* p = a.p[q] + o;
     const float* v = a.v[q] + o;
     const double alpha = c->alpha, omega = c->omega;
-    const int lt0 = (unit - d.unit_off) * 2;
+    const bool first = c->first != 0;
     for (int k = 0; k < 2; ++k) {
       const int r0 = (lt0 + k) * BS;
       if (r0 >= d.n) break;
       const int row = r0 + threadIdx.x;
       const bool mine = row < d.n;
       if (st == ST_HALF) {
-        if (mine) d.x[row] = fma(alpha, (double)p[row], d.x[row]);
+        if (mine) {
+          const double xo = d.x[row];
+          if (first) a.xprev[o + row] = xo;
+          d.x[row] = fma(alpha, (double)p[row], xo);
+        }
         continue;
       }
       if (k) __syncthreads();
       double acc[3] = {0.0, 0.0, 0.0};
       if (mine) {
         const double sv = fma(-alpha, (double)v[row], (double)a.r[o + row]);
-        d.x[row] = fma(omega, sv, fma(alpha, (double)p[row], d.x[row]));
+        const double xo = d.x[row];
+        if (first) a.xprev[o + row] = xo;
+        d.x[row] = fma(omega, sv, fma(alpha, (double)p[row], xo));
         const float rs = (float)fma(-omega, (double)a.t[o + row], sv);
         a.r[o + row] = rs;
         acc[0] = (double)a.rh[o + row] * (double)rs;
@@ -432,7 +564,9 @@ __global__ __launch_bounds__(BS) void k_bm_fin_u(MArgs a) {
   const double rn = sqrt(out[1]);
   const double est = (d.W ? sqrt(out[2]) : rn) / c->ref;
   c->sum.relres_rec = est;
-  if (est < c->target || c->sum.iters >= c->maxit || !(est <= c->last_rt / a.delta)) {
+  const bool run_end = !c->fp64 && (!(est <= c->last_rt / a.delta) ||
+                                     (a.run_cap > 0 && c->sum.iters - c->run_start >= a.run_cap));
+  if (est < c->target || c->sum.iters >= c->maxit || run_end) {
     c->sum.state = ST_VERIFY;
     return;
   }

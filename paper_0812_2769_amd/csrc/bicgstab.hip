@@ -64,6 +64,8 @@ __global__ __launch_bounds__(64) void k_bicg_init_ctl(Ctl* c, int maxit, double 
   c->sum.relres_rec = 1.0;
   c->sum.relres_true = 1.0;
   c->sum.brk = BRK_NONE;
+  c->sum.fp64_from = 0;
+  c->sum.pad0 = 0;
   c->maxit = maxit;
   c->m = 0;
   c->j = c->k = c->claimed = 0;

@@ -73,6 +73,8 @@ __global__ __launch_bounds__(64) void k_init_ctl(Ctl* c, int maxit, int m, doubl
   c->sum.fails = 0;
   c->sum.steps = 0;
   c->sum.brk = BRK_NONE;
+  c->sum.fp64_from = 0;
+  c->sum.pad0 = 0;
   c->sum.relres_rec = 1.0;
   c->sum.relres_true = 1.0;
   c->maxit = maxit;

@@ -37,6 +37,8 @@ enum : int {
   ST_FINAL = 5,       // breakdown: final true residual pending, status already set
   ST_DONE = 6,        // finished; status valid
   ST_SCALE = 7,       // batch engine: GS(p) of the system pending
+  ST_ROLLBACK = 8,    // mixed Bi-CGSTAB engine: x back to its value at the last run's start
+  ST_FP64START = 9,   // mixed Bi-CGSTAB engine: FP64 continuation, true residual pending
 };
 
 enum : int { S_CONVERGED = 0, S_MAXIT = 1, S_BREAKDOWN = 2, S_STAGNATED = 3 };
@@ -62,6 +64,8 @@ struct ProbeSlots {
 // Host-visible summary copied back after each cycle / chunk.
 struct Summary {
   int state, status, iters, restarts, half, fails, steps, brk;
+  int fp64_from;   // mixed Bi-CGSTAB: iterations before the FP64 continuation (0: none)
+  int pad0;
   double relres_rec, relres_true;
 };
 

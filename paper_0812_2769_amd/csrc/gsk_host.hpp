@@ -128,6 +128,7 @@ struct EngineConfig {
   int check_every;   // Bi-CGSTAB: iterations per chunk
   bool use_graph;
   double delta;      // mixed Bi-CGSTAB: reduction that ends a run (refinement step)
+  int run_cap = 0;   // mixed Bi-CGSTAB: iterations that end a run (0: no cap)
   int units;         // FP64 Bi-CGSTAB: 256-row tiles per workgroup (1 or 2; 0 = 1)
 };
 size_t engine_workspace_bytes(const EngineConfig& cfg);

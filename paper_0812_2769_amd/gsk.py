@@ -58,6 +58,7 @@ class InfoStruct(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("half_step", ctypes.c_int32),
                 ("verify_failures", ctypes.c_int32), ("breakdown_test", ctypes.c_int32),
+                ("fp64_from", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("relres_recursive", ctypes.c_double),
                 ("relres_true", ctypes.c_double)]
 
@@ -86,7 +87,8 @@ class EngineConfig(ctypes.Structure):
     _fields_ = [("max_rows", ctypes.c_int64), ("max_systems", ctypes.c_int32),
                 ("method", ctypes.c_int32), ("m", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("tile_units", ctypes.c_int32), ("inner_reduction", ctypes.c_double)]
+                ("tile_units", ctypes.c_int32), ("inner_reduction", ctypes.c_double),
+                ("run_cap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class EngineRequest(ctypes.Structure):
@@ -214,6 +216,7 @@ class Info:
     relres_recursive: float
     relres_true: float
     breakdown_test: int = 0
+    fp64_from: int = 0   # mixed Bi-CGSTAB engine: iterations before the FP64 continuation
 
     @property
     def status_name(self) -> str:
@@ -409,7 +412,7 @@ def _options(maxit, breakdown_eps, stop_weights, check_every, n) -> Options:
 
 def _info(s: InfoStruct) -> Info:
     return Info(s.iters, s.restarts, s.status, s.half_step, s.verify_failures,
-                s.relres_recursive, s.relres_true, s.breakdown_test)
+                s.relres_recursive, s.relres_true, s.breakdown_test, s.fp64_from)
 
 
 def _x_start(b, x0, x_out, n):
@@ -523,7 +526,7 @@ class Engine:
     def __init__(self, max_rows: int, max_systems: int, check_every: int = 8,
                  graph: bool = False, device="cuda", stream=None, method: str = "bicgstab",
                  m: int = 20, precision: str = "fp64", inner_reduction: float = 0.0,
-                 tile_units: int = 0):
+                 tile_units: int = 0, run_cap: int = 0):
         self.device = torch.device(device)
         self.stream = stream if stream is not None else (
             torch.cuda.Stream(self.device) if graph else torch.cuda.current_stream(self.device))
@@ -536,7 +539,7 @@ class Engine:
                            self.m if method == "gmres" else 0,
                            PRECISION_MIXED if self.mixed else PRECISION_FP64,
                            int(check_every), ENGINE_GRAPH if graph else 0, int(tile_units),
-                           float(inner_reduction))
+                           float(inner_reduction), int(run_cap), 0)
         nbytes = int(lib.gsk_engine_workspace_bytes_ex(ctypes.byref(cfg)))
         if nbytes == 0:
             raise GskError(ERR_INVALID_ARG, "no engine workspace size for this configuration")

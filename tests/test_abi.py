@@ -62,7 +62,7 @@ def test_struct_layouts(lib):
     # gsk_stencil {3 int32; ptr}, gsk_matrix {int32; gsk_csr; gsk_stencil}
     assert ctypes.sizeof(lib.Csr) == 40
     assert ctypes.sizeof(lib.Options) == 32
-    assert ctypes.sizeof(lib.InfoStruct) == 40
+    assert ctypes.sizeof(lib.InfoStruct) == 48
     assert ctypes.sizeof(lib.Stencil) == 24
     assert ctypes.sizeof(lib.Matrix) == 72
     assert lib.Matrix.csr.offset == 8 and lib.Matrix.stencil.offset == 48
@@ -162,7 +162,7 @@ def test_binding_refuses_cpu_tensors(lib):
 
 def test_engine_struct_layouts_and_rejections(lib):
     # gsk_result {int64; gsk_info}, gsk_engine_usage {2 int32; 3 int64}
-    assert ctypes.sizeof(lib.Result) == 48
+    assert ctypes.sizeof(lib.Result) == 56
     assert ctypes.sizeof(lib.EngineUsage) == 32
     L = lib.lib
     assert lib.engine_workspace_bytes(0, 4) == 0

@@ -1,12 +1,14 @@
-"""Mixed-precision Bi-CGSTAB engines (FP32 storage, FP64 refinement) through the C ABI.
+"""Mixed-precision Bi-CGSTAB engines (FP32 storage, FP64 refinement, FP64 continuation)
+through the C ABI.
 
-Definition: the oracle's orc_bicgstab_ir. The device sums in a different order and uses fused
-multiply-adds, and float-storage Bi-CGSTAB amplifies such differences, so the bars are those
-of a rounding-sensitive solver: equal status, the FP64 true residual below tol, iteration
-counts within 30% of the oracle's, and x within the conditioning bound. The closed-form case
-(A = I: two half steps, one refinement) must match exactly. Within the engine, a system's
-result does not depend on what else is in the batch (bit for bit), and repeated runs agree
-bit for bit.
+Definition: the oracle's orc_bicgstab_ir with the FP64 continuation (a refinement that stops
+paying, or breaks down, continues as FP64 Bi-CGSTAB after undoing a run that made x worse).
+The device sums in a different order and uses fused multiply-adds, and float-storage
+Bi-CGSTAB amplifies such differences, so iteration counts are compared as the spread of the
+same perturbed systems on both sides; solutions are compared with the FP64 oracle's to the
+spec bar (x within 1e-8 at tol 1e-10). The closed-form case (A = I: two half steps, one
+refinement) must match exactly. Within the engine, a system's result does not depend on what
+else is in the batch (bit for bit), and repeated runs agree bit for bit.
 """
 import numpy as np
 import pytest
@@ -84,29 +86,112 @@ def test_identity_two_half_steps(G):
     assert (io.iters, io.restarts) == (i.iters, i.restarts)
 
 
-@pytest.mark.parametrize("seed,p,stencil", [(41, 2, True), (43, 2, False), (47, 1, True)])
+SYSTEMS = {41: (12, 20), 43: (12, 20), 95: (10, 22), 293: (10, 22)}
+
+
+def recipe_system(seed):
+    n_min, n_max = SYSTEMS[seed]
+    return problems.batch_system(problems.batch_specs(1, seed=seed, n_min=n_min,
+                                                      n_max=n_max)[0])
+
+
+@pytest.mark.parametrize("seed,p,stencil", [(41, 2, True), (43, 2, False), (95, 2, True),
+                                            (293, 1, True)])
 def test_mixed_bicgstab_matches_oracle(G, seed, p, stencil):
-    P = problems.batch_system(problems.batch_specs(1, seed=seed, n_min=12, n_max=20)[0])
+    # 95 and 293 (GS(1), stop weights): float refinement alone stagnates on these (its runs
+    # diverge); both sides must hand over to FP64 and converge
+    P = recipe_system(seed)
     S, w = oracle_scaled(P, p)
-    xo, io = oracle.bicgstab_ir(S, S.b, tol=1e-10, delta=DELTA, weights=None if p == 2 else w)
+    W = None if p == 2 else w
+    tol = 1e-10
+    xo, io = oracle.bicgstab_ir(S, S.b, tol=tol, delta=DELTA, weights=W)
+    x64, i64 = oracle.bicgstab(S, S.b, tol=tol, weights=W)
     A = G.CsrMatrix.from_problem(P)
     M = G.stencil_from_csr(A, *grid_of(P)) if stencil else A
-    xs, infos = solve(G, [(M, dev(P.b), p)], 1e-10)
+    xs, infos = solve(G, [(M, dev(P.b), p)], tol)
     ig = infos[0]
-    assert ig.status == io.status, (ig, io)
-    if io.status != G.CONVERGED:
-        # float storage diverges on this one (GS(1), 2D jump): both sides end the refinement
-        # as stagnated after three steps without progress
-        assert io.status == G.STAGNATED and ig.verify_failures == io.verify_failures == 3
-        return
-    assert ig.relres_true < 1e-10
-    assert abs(ig.iters - io.iters) <= 0.3 * io.iters + 5, (ig.iters, io.iters)
-    # the scaled system's solution, to the accuracy tol times its condition allows
+    assert io.status == i64.status == ig.status == G.CONVERGED, (ig, io)
+    assert ig.relres_true < tol
+    assert (ig.fp64_from > 0) == (io.fp64_from > 0), (ig.fp64_from, io.fp64_from)
+    # x: two solutions with residuals below tol differ by up to about cond(A) tol. Where that
+    # bound is small (cond(A) tol <= 1e-6), x must be within 1e-8 of the FP64 oracle's; on the
+    # ill-conditioned jump systems (cond up to 3e6: the two oracles' own solutions differ by
+    # 3.5e-7 on seed 41) it must be within the conditioning bound of the dense-LU solution.
     x = xs[0]
-    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-5
-    r = S.b - oracle.spmv(S, x)
-    rel = np.linalg.norm((w if p != 2 else 1.0) * r) / np.linalg.norm((w if p != 2 else 1.0) * S.b)
-    assert rel == pytest.approx(ig.relres_true, rel=1e-6)
+    Ad = S.dense()
+    xe = np.linalg.solve(Ad, S.b)
+    cond = np.linalg.cond(Ad)
+    err64 = np.linalg.norm(x - x64) / np.linalg.norm(x64)
+    if cond * tol <= 1e-6:
+        assert err64 <= 1e-8, (err64, cond)
+    assert np.linalg.norm(x - xe) / np.linalg.norm(xe) <= 10 * cond * tol, (err64, cond)
+    # the reported residual is the true one, recomputed by the oracle's product
+    wt = np.ones(S.n) if W is None else W
+    r = wt * (S.b - oracle.spmv(S, x))
+    assert np.linalg.norm(r) / np.linalg.norm(wt * S.b) == pytest.approx(ig.relres_true,
+                                                                        rel=1e-6)
+
+
+def _perturbed(S, k):
+    rng = np.random.default_rng(2000 + k)
+    T = S.copy()
+    T.val = S.val * (1 + 2.2e-16 * rng.choice([-1, 0, 1], size=S.nnz))
+    T.b = S.b * (1 + 2.2e-16 * rng.choice([-1, 0, 1], size=S.n))
+    return T
+
+
+@pytest.mark.parametrize("seed", [41, 43])
+def test_mixed_bicgstab_iteration_spread_matches_oracle(G, seed):
+    """Float-storage Bi-CGSTAB amplifies rounding, so one run's iteration count is not
+    reproducible even in the oracle: 1-ulp changes of A and b move it. Both sides solve the
+    same 21 perturbed (already GS(2)-scaled) systems; all must converge, and the medians of
+    the iteration counts must agree within 10% (the oracle's own spread is printed on
+    failure). These systems never hand over to FP64: where a float run diverges, the number
+    of iterations it takes to grow by 1/delta is set by amplified rounding and differs
+    between any two implementations (on seed 95, 1,183 against 817), so it is not compared;
+    the hand-over itself is checked below."""
+    P = recipe_system(seed)
+    S, _ = oracle_scaled(P)
+    tol = 1e-8
+    Ts = [_perturbed(S, k) for k in range(21)]
+    it_o = []
+    for T in Ts:
+        _, io = oracle.bicgstab_ir(T, T.b, tol=tol, delta=DELTA)
+        assert io.status == oracle.CONVERGED
+        it_o.append(io.iters)
+    items = [(G.CsrMatrix.from_problem(T), dev(T.b), 0) for T in Ts]
+    xs, infos = solve(G, items, tol)
+    assert all(i.status == G.CONVERGED and i.relres_true < tol for i in infos), infos
+    it_g = [i.iters for i in infos]
+    assert np.median(it_g) == pytest.approx(np.median(it_o), rel=0.10), (sorted(it_g),
+                                                                          sorted(it_o))
+
+
+def test_fp64_continuation_after_undo_equals_fp64_solve(G):
+    """On seed 95 the first float run diverges: it is undone (x back to x0 = 0) and the solve
+    continues in FP64 from x0 with the same reference norm. The continuation is the FP64
+    engine's iteration, which equals gsk_bicgstab's bit for bit, so the mixed engine's
+    result must equal the FP64 solve of the same scaled system exactly, after fp64_from more
+    iterations and one more restart (the oracle's bicgstab_ir does the same: its x equals
+    orc_bicgstab's)."""
+    import torch
+    P = recipe_system(95)
+    tol = 1e-10
+    S, _ = oracle_scaled(P)
+    xo, io = oracle.bicgstab_ir(S, S.b, tol=tol, delta=DELTA)
+    x64o, i64o = oracle.bicgstab(S, S.b, tol=tol)
+    assert np.array_equal(xo, x64o) and io.iters == io.fp64_from + i64o.iters
+    A = G.CsrMatrix.from_problem(P)
+    M = G.stencil_from_csr(A, *grid_of(P))
+    xs, infos = solve(G, [(M, dev(P.b), 2)], tol)
+    ig = infos[0]
+    As, bs, _, _ = G.gs_scale(A, dev(P.b), 2)
+    x64, i64 = G.bicgstab(G.stencil_from_csr(As, *grid_of(P)), bs, tol=tol)
+    torch.cuda.synchronize()
+    assert ig.status == i64.status == G.CONVERGED
+    assert ig.fp64_from > 0 and ig.iters == ig.fp64_from + i64.iters
+    assert ig.restarts == i64.restarts + 1
+    assert np.array_equal(xs[0], host(x64))
 
 
 def test_mixed_bicgstab_independent_of_batch_and_repeatable(G):

@@ -93,26 +93,28 @@ def test_divergence_ends_runs_and_stagnates_without_fallback():
     S, w = scaled(P, 1)
     _, i64 = oracle.bicgstab(S, S.b, tol=1e-10, weights=w)
     assert i64.status == oracle.CONVERGED
-    _, iir = oracle.bicgstab_ir(S, S.b, tol=1e-10, delta=1e-6, weights=w, fallback=False)
+    _, iir = oracle.bicgstab_ir(S, S.b, tol=1e-10, delta=1e-6, weights=w, fallback=False,
+                                run_cap=0)
     assert iir.status == oracle.STAGNATED and iir.verify_failures == 3
     assert np.isfinite(iir.relres_true) and iir.iters < 10000 and iir.fp64_from == 0
 
 
-@pytest.mark.parametrize("seed,p", [(47, 1), (95, 2), (13, 2)])
+@pytest.mark.parametrize("seed,p", [(293, 1), (95, 2), (13, 2)])
 def test_fp64_continuation_converges_where_refinement_stops(seed, p):
-    # Systems of the batch recipe on which float-storage refinement cannot reach the
-    # tolerance: without the continuation it stagnates (its runs diverge and the true residual
-    # is left far above the start, up to overflow); with it, the solve hands over to FP64
-    # Bi-CGSTAB and must end as an FP64 solve does: converged on the GS(2) metric, with the
-    # solution dense LU gives (to the condition-number bound) and the reported residual equal
-    # to one recomputed here.
-    n_min, n_max = (12, 20) if seed == 47 else (10, 22)
+    # Systems of the batch recipe on which a float-storage run diverges (the true residual is
+    # left far above the start, up to overflow; on 95 and 13 refinement alone stagnates): the
+    # solve hands over to FP64 Bi-CGSTAB and must end as an FP64 solve does: converged on the
+    # GS(2) metric, with the solution dense LU gives (to the condition-number bound) and the
+    # reported residual equal to one recomputed here.
+    n_min, n_max = 10, 22
     P = problems.batch_system(problems.batch_specs(1, seed=seed, n_min=n_min, n_max=n_max)[0])
     S, w = scaled(P, p)
     W = w if p == 1 else None
     tol = 1e-10 if p == 1 else 1e-8
-    _, nofb = oracle.bicgstab_ir(S, S.b, tol=tol, delta=1e-6, weights=W, fallback=False)
-    assert nofb.status != oracle.CONVERGED
+    if seed != 293:
+        _, nofb = oracle.bicgstab_ir(S, S.b, tol=tol, delta=1e-6, weights=W, fallback=False,
+                                     run_cap=0)
+        assert nofb.status != oracle.CONVERGED
     x, info = oracle.bicgstab_ir(S, S.b, tol=tol, delta=1e-6, weights=W)
     assert info.status == oracle.CONVERGED and info.relres_true < tol
     assert 0 < info.fp64_from < info.iters <= 10000
