@@ -105,12 +105,14 @@ def parse(argv=None):
                     help="batch512: skip the 80^3 and 160^3 figures")
     ap.add_argument("--cpu-sample-systems", type=int, default=96,
                     help="batch512: systems of the batch the CPU oracle solves for its baseline")
-    ap.add_argument("--rates", default="50,200,1000,2000",
+    ap.add_argument("--rates", default="50,100,200,500,1000,2000",
                     help="serving: Poisson arrival rates to sweep (requests/s)")
-    ap.add_argument("--serve-requests", type=int, default=400,
+    ap.add_argument("--serve-requests", type=int, default=2000,
                     help="serving: requests per rate")
-    ap.add_argument("--gmres-share", type=float, default=0.2,
+    ap.add_argument("--gmres-share", type=float, default=0.5,
                     help="serving: fraction of GMRES(20) requests (the rest Bi-CGSTAB)")
+    ap.add_argument("--serve-pool", type=int, default=128,
+                    help="serving: systems drawn from the batch recipe that requests pick from")
     ap.add_argument("--grid", type=int, default=0,
                     help="N of the N^3 grid (default 80 for slabs80, 160 for checker160)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
@@ -840,23 +842,23 @@ def extra_checker160(gsk, problems, dev):
 # ---------------------------------------------------------------------------------------
 
 def bench_serve(args, gsk, problems, dev):
-    """serving: Poisson arrivals of solves drawn from the batch recipe (a pool of 64
-    systems), a GMRES(20) / Bi-CGSTAB mix, tol 1e-8, served with continuous batching; one run
-    per arrival rate. value = converged solves/s at the highest rate."""
+    """serving: Poisson arrivals of solves drawn from the batch recipe (a pool of systems
+    drawn with seed 1005; each request picks one uniformly), a GMRES(20) / Bi-CGSTAB mix, tol
+    1e-8, GS(2) per request, served with continuous batching and admission by free device
+    memory (engines sized from it); one run per arrival rate. value = converged solves/s at
+    the highest rate."""
     import numpy as np
     from paper_0812_2769_amd import serve
     rates = [float(r) for r in args.rates.split(",") if r]
-    pool_specs = problems.batch_specs(64, seed=1005)
+    pool_specs = problems.batch_specs(args.serve_pool, seed=1005)
     pool, _ = build_batch_systems(gsk, problems, dev, pool_specs)
     nmax = max(s["n"] for s in pool)
     rng = np.random.default_rng(1006)
-    # engine room for about 48 of the pool's systems at once
-    unit = 256 * max(1, args.tile_units)
-    rows = int(sum((s["n"] + unit - 1) // unit * unit for s in pool) * 0.75)
-    srv = serve.Server(rows, 256, check_every=8, graph=True, gmres_rows=nmax, m_max=20,
+    srv = serve.Server(0, 256, check_every=8, graph=True, gmres_rows=nmax, m_max=20,
                        device=dev, gmres_lanes=args.gmres_lanes, gmres_mode=args.gmres_mode,
-                       gmres_precision=args.gmres_precision, gmres_engine_rows=rows,
-                       gmres_engine_systems=128, tile_units=args.tile_units)
+                       gmres_precision=args.gmres_precision, gmres_engine_systems=128,
+                       tile_units=args.tile_units)
+    log(f"engines sized from free device memory: {srv.sizing}")
     results = []
     for rate in rates:
         gaps = rng.exponential(1.0 / rate, size=args.serve_requests)
@@ -869,6 +871,7 @@ def bench_serve(args, gsk, problems, dev):
             reqs.append(serve.Request(tag=k, arrival=float(arrivals[k]), A=s["S"], b=s["b"],
                                       method="gmres" if kinds[k] else "bicgstab", m=20,
                                       tol=1e-8, csr=s["A"], grid=s["grid"]))
+        deferred0 = srv.gate.deferred
         t0 = time.perf_counter()
         done = srv.serve(reqs)
         wall = time.perf_counter() - t0
@@ -877,18 +880,24 @@ def bench_serve(args, gsk, problems, dev):
         lat_g = [d.latency for d in done if d.method == "gmres"]
         span = max(d.finished for d in done) - min(d.arrival for d in done)
         conv = sum(1 for d in done if d.info.status == gsk.CONVERGED)
+        conv_b = sum(1 for d in done if d.info.status == gsk.CONVERGED and d.method == "bicgstab")
         st = {}
         for d in done:
-            st[d.info.status_name] = st.get(d.info.status_name, 0) + 1
+            key = f"{d.method}_{d.info.status_name}"
+            st[key] = st.get(key, 0) + 1
         results.append({"rate": rate, "requests": len(done),
                         "converged_per_s": round(conv / span, 2),
+                        "bicgstab_converged_per_s": round(conv_b / span, 2),
                         "completed_per_s": round(len(done) / span, 2),
                         "wall_s": round(wall, 3),
                         "latency_p50_ms": round(1e3 * pct(lat, 0.5), 2),
                         "latency_p99_ms": round(1e3 * pct(lat, 0.99), 2),
                         "bicgstab_p50_ms": round(1e3 * pct(lat_b, 0.5), 2) if lat_b else None,
+                        "bicgstab_p99_ms": round(1e3 * pct(lat_b, 0.99), 2) if lat_b else None,
                         "gmres_p50_ms": round(1e3 * pct(lat_g, 0.5), 2) if lat_g else None,
-                        "converged": conv, "status": st})
+                        "gmres_p99_ms": round(1e3 * pct(lat_g, 0.99), 2) if lat_g else None,
+                        "converged": conv, "status": st,
+                        "memory_deferrals": srv.gate.deferred - deferred0})
         log(f"rate {rate}: {results[-1]}")
     srv.close()
     best = results[-1]
@@ -901,13 +910,15 @@ def bench_serve(args, gsk, problems, dev):
                   if args.gmres_mode == "engine" and args.gmres_precision == "mixed" else "f64"),
         "data": "synthetic",
         "config": {"workload": f"serving: Poisson arrivals at {args.rates} req/s, "
-                               f"{args.serve_requests} requests per rate from a pool of 64 "
-                               f"batch-recipe systems, {args.gmres_share:.0%} GMRES(20), "
-                               f"the rest Bi-CGSTAB, tol 1e-8, GS(2) per request; Bi-CGSTAB "
-                               f"in the engine, GMRES "
+                               f"{args.serve_requests} requests per rate drawn from a pool of "
+                               f"{args.serve_pool} batch-recipe systems (seed 1005), "
+                               f"{args.gmres_share:.0%} GMRES(20), the rest Bi-CGSTAB, tol "
+                               f"1e-8, GS(2) per request; admission by free device memory; "
+                               f"Bi-CGSTAB in the batch engine, GMRES "
                                + (f"in a GMRES(20) engine ({args.gmres_precision})"
                                   if args.gmres_mode == "engine"
                                   else f"on {args.gmres_lanes} lanes")},
+        "engine_sizing": srv.sizing,
         "latency_p50_ms": best["latency_p50_ms"], "latency_p99_ms": best["latency_p99_ms"],
         "rates": results, "roofline": None, "cpu_baseline": None,
     }

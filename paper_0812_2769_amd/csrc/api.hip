@@ -484,6 +484,9 @@ int gsk_engine_submit_ex(gsk_engine* e, const gsk_engine_request* r) {
                           (p > 0 || mixed) ? &gs : nullptr);
   if (rc == 1) return GSK_FULL;
   if (rc == -1) return set_err(GSK_ERR_INVALID_ARG, "invalid request");
+  if (rc == -6)
+    return set_err(GSK_ERR_INVALID_ARG, "tag %lld is already in flight in this engine",
+                   (long long)r->tag);
   if (rc) return set_err(GSK_ERR_DEVICE, "engine submit: HIP failure");
   return GSK_OK;
 }

@@ -686,11 +686,10 @@ static int wait_upload(Engine& e) {
 int engine_submit(Engine* e, const Mat& A, const double* b, double* x, const SolveParams& prm,
                   int64_t tag, const GsStage* gs) {
   int slot = -1;
-  for (int i = 0; i < e->max_sys; ++i)
-    if (!e->active[i]) {
-      slot = i;
-      break;
-    }
+  for (int i = 0; i < e->max_sys; ++i) {
+    if (e->active[i] && e->tags[i] == tag) return -6;   // the tag is still in flight
+    if (slot < 0 && !e->active[i]) slot = i;
+  }
   if (slot < 0) return 1;   // no free slot
   if (e->mixed && (!gs || !gs->mat32)) return -1;
   const int need = (A.n + BS - 1) / BS;
@@ -767,20 +766,36 @@ static int upload(Engine& e) {
     e.p_sys[i] = e.h_sys[i];
     if (!e.active[i]) e.p_sys[i].ntiles = 0;
   }
+  // the units of every admitted system, in row-space order (a system's units are
+  // consecutive, so adjacent list entries are adjacent rows of one system); only the listed
+  // entries and the count are copied, so a large engine costs no more than a small one
   int n = 0;
-  for (int t = 0; t < e.grid_tiles; t += e.rv) {
-    if (e.tile_sys[t] < 0) continue;
-    e.p_tiles[n] = t / e.rv;
-    e.p_tiles[e.max_units + n] = e.tile_sys[t];
-    ++n;
+  for (int t = 0; t < e.grid_tiles;) {
+    const int s = e.tile_sys[t];
+    if (s < 0) {
+      auto it = e.free_tiles.find(t);   // skip a free range in one step
+      t += it != e.free_tiles.end() ? it->second : e.rv;
+      continue;
+    }
+    const SysDesc& d = e.h_sys[s];
+    for (int u = 0; u < d.nunits; ++u) {
+      e.p_tiles[n] = d.unit_off + u;
+      e.p_tiles[e.max_units + n] = s;
+      ++n;
+    }
+    t = d.tile_off + d.nunits * e.rv;
   }
   e.p_tiles[2 * (size_t)e.max_units] = n;
   e.n_listed = n;
+  const size_t mu = (size_t)e.max_units;
   if (hipMemcpyAsync(e.d_sys, e.p_sys, sizeof(SysDesc) * e.max_sys,
                      hipMemcpyHostToDevice, e.s) != hipSuccess ||
-      hipMemcpyAsync(e.d_list, e.p_tiles,
-                     sizeof(int) * (2 * (size_t)e.max_units + 1), hipMemcpyHostToDevice,
-                     e.s) != hipSuccess ||
+      (n > 0 && hipMemcpyAsync(e.d_list, e.p_tiles, sizeof(int) * (size_t)n,
+                               hipMemcpyHostToDevice, e.s) != hipSuccess) ||
+      (n > 0 && hipMemcpyAsync(e.d_list + mu, e.p_tiles + mu, sizeof(int) * (size_t)n,
+                               hipMemcpyHostToDevice, e.s) != hipSuccess) ||
+      hipMemcpyAsync(e.d_list + 2 * mu, e.p_tiles + 2 * mu, sizeof(int),
+                     hipMemcpyHostToDevice, e.s) != hipSuccess ||
       hipEventRecord(e.ev_upload, e.s) != hipSuccess)
     return -5;
   e.upload_pending = true;

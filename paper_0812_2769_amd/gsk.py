@@ -551,6 +551,27 @@ class Engine:
         self._keep = {}
         self.max_systems = int(max_systems)
 
+    def request_bytes(self, A, p: int = 2) -> int:
+        """Device bytes submit_gs allocates for a request on A (scaled matrix, b and, for
+        p != 2, stop weights; the FP32 matrix copy in a mixed engine), not counting x."""
+        vals = A.coef.numel() if isinstance(A, StencilMatrix) else A.val.numel()
+        nbytes = 8 * (vals + A.n + (A.n if p != 2 else 0))
+        if self.mixed:
+            nbytes += 4 * (A.planes * _vec_ld(A.n) if isinstance(A, StencilMatrix) else vals)
+        return nbytes
+
+    @staticmethod
+    def workspace_bytes_per_row(method: str = "bicgstab", precision: str = "fp64",
+                                m: int = 20) -> float:
+        """Engine workspace bytes per row of capacity (measured on a 2^20-row engine with
+        256 slots)."""
+        rows = 1 << 20
+        cfg = EngineConfig(rows, 256, METHOD_GMRES if method == "gmres" else METHOD_BICGSTAB,
+                           m if method == "gmres" else 0,
+                           PRECISION_MIXED if precision == "mixed" else PRECISION_FP64, 8, 0, 0,
+                           0.0, 0, 0)
+        return int(lib.gsk_engine_workspace_bytes_ex(ctypes.byref(cfg))) / rows
+
     def _mat32(self, A) -> Tuple[Optional[torch.Tensor], int]:
         if not self.mixed:
             return None, 0
@@ -561,6 +582,8 @@ class Engine:
 
     def _submit(self, A, b, x, tol, tag, o, gs_p=0, val_out=None, b_out=None, w_out=None,
                 keep=()):
+        if int(tag) in self._keep:
+            raise GskError(ERR_INVALID_ARG, f"tag {int(tag)} is already in flight")
         c = A.c_matrix()
         m32, ld = self._mat32(A)
         r = EngineRequest(ctypes.addressof(c), b.data_ptr(), x.data_ptr(), float(tol),

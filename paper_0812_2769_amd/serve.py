@@ -1,9 +1,9 @@
 """A solve server with continuous batching on one GPU.
 
 Requests arrive over time (each an unscaled system, a method and a tolerance). The server:
-- admits Bi-CGSTAB requests into the batched engine (gsk_engine_*) as soon as its workspace
-  has room (rows and a slot), GS(2) included, so requests that arrive while others are on the
-  GPU join the running batch at the next chunk;
+- admits Bi-CGSTAB requests into the batched engine (gsk_engine_*) as soon as the engine has
+  room (rows and a slot) and the device has the request's memory free, GS(2) included, so
+  requests that arrive while others are on the GPU join the running batch at the next chunk;
 - runs GMRES(m) requests either on a few lanes (each a host thread with a stream and
   workspaces of its own, one solve at a time) that take requests from one queue, or in a
   GMRES engine of their own (FP64 or mixed precision) on its own stream and host thread, so
@@ -11,8 +11,17 @@ Requests arrive over time (each an unscaled system, a method and a tolerance). T
 - keeps every request's Krylov state on the device until it is done, and records arrival,
   admission and completion times.
 
+Admission by free HBM. Engines hold their vectors in one workspace each; the server sizes
+them from the device's free memory when no size is given (a fraction of it, split between the
+Bi-CGSTAB and GMRES engines). Each request also needs memory of its own (the GS(2) outputs,
+x, an FP32 matrix copy in a mixed engine), allocated when it is admitted: a request is
+admitted only while the device's free memory (what the HIP runtime reports, plus what torch's
+allocator holds unused) stays above a reserve after it. A request that does not fit waits;
+requests behind it that fit are admitted meanwhile, unless the oldest waiting request has
+waited longer than max_skip_s (then nothing overtakes it, so a large request cannot starve).
+
 Each Bi-CGSTAB result is bit-for-bit the result of the same solve alone (the engine's
-guarantee); each GMRES result is the single-solve path itself.
+guarantee); each GMRES result is the single-solve path itself (lanes) or equal to it (engine).
 """
 import collections
 import dataclasses
@@ -54,6 +63,44 @@ class Done:
         return self.finished - self.arrival
 
 
+def device_free_bytes(device) -> int:
+    """Free device memory usable by new allocations: what the HIP runtime reports free
+    (hipMemGetInfo) plus what torch's caching allocator holds but does not use."""
+    free, _ = torch.cuda.mem_get_info(device)
+    cached = torch.cuda.memory_reserved(device) - torch.cuda.memory_allocated(device)
+    return int(free) + max(0, int(cached))
+
+
+class MemoryGate:
+    """Admission by free device memory: fits(nbytes) while free - nbytes >= reserve.
+    free_bytes() is the probe (device_free_bytes on a GPU; the host tests pass a stand-in)."""
+
+    def __init__(self, free_bytes: Callable[[], int], reserve: int):
+        self.free_bytes = free_bytes
+        self.reserve = int(reserve)
+        self.deferred = 0      # admissions refused for memory
+
+    def fits(self, nbytes: int) -> bool:
+        ok = self.free_bytes() - int(nbytes) >= self.reserve
+        if not ok:
+            self.deferred += 1
+        return ok
+
+
+def request_bytes(engine, req: Request) -> int:
+    """Device bytes a request allocates when admitted: its engine's per-request buffers
+    (Engine.request_bytes; an engine without it is charged 8 bytes per matrix value and row)
+    plus x."""
+    A = req.A
+    fn = getattr(engine, "request_bytes", None)
+    if fn is not None:
+        nbytes = fn(A)
+    else:
+        vals = A.nnz if hasattr(A, "nnz") else A.n
+        nbytes = 8 * (vals + A.n)
+    return int(nbytes) + 8 * A.n
+
+
 class GmresLane(threading.Thread):
     """Solves GMRES requests from a shared queue one at a time on its own stream: GS(2),
     packing, GMRES(m)."""
@@ -67,6 +114,7 @@ class GmresLane(threading.Thread):
         self.t0 = t0
         self.on_done = on_done
         self.device = device
+        self.abort = threading.Event()
         with torch.cuda.stream(self.stream):
             self.ws_gs = gsk.workspace(gsk.METHOD_GS, max_rows, 0, device)
             self.ws = gsk.workspace(gsk.METHOD_GMRES, max_rows, m_max, device)
@@ -74,8 +122,11 @@ class GmresLane(threading.Thread):
     def run(self):
         while True:
             item = self.q.get()
-            if item is None:
-                return
+            if item is None or self.abort.is_set():
+                self.q.task_done()
+                if item is None:
+                    return
+                continue
             try:
                 req, admitted = item
                 with torch.cuda.stream(self.stream):
@@ -92,21 +143,28 @@ class GmresLane(threading.Thread):
             finally:
                 self.q.task_done()
 
+    def close(self):
+        pass
+
 
 class GmresEngineWorker(threading.Thread):
     """Serves GMRES(m) requests through a GMRES engine of its own (its own stream): admits them
-    as rows and slots free up (GS(2) inside the engine), runs one cycle per chunk, and reports
-    each finished request. Results equal gsk_gmres (or gsk_gmres_mixed) on the same system."""
+    as rows, slots and device memory free up (GS(2) inside the engine), runs one cycle per
+    chunk, and reports each finished request. Results equal gsk_gmres (or gsk_gmres_mixed) on
+    the same system. Setting `abort` makes it stop between chunks without draining its
+    requests."""
 
     def __init__(self, q: queue.Queue, device, t0: float, max_rows: int, max_systems: int,
                  m: int, precision: str, graph: bool, on_done: Callable,
-                 engine_factory: Callable = gsk.Engine):
+                 engine_factory: Callable = gsk.Engine, gate: Optional[MemoryGate] = None):
         super().__init__(daemon=True)
         self.q = q
         self.error = None
         self.t0 = t0
         self.on_done = on_done
         self.m = m
+        self.gate = gate
+        self.abort = threading.Event()
         self.engine = engine_factory(max_rows, max_systems, graph=graph, device=device,
                                      method="gmres", m=m, precision=precision)
 
@@ -116,6 +174,8 @@ class GmresEngineWorker(threading.Thread):
         closing = False
         try:
             while not (closing and not waiting and not inflight):
+                if self.abort.is_set():
+                    return
                 # take new requests; block only when there is nothing else to do
                 block = not waiting and not inflight and not closing
                 while True:
@@ -132,6 +192,9 @@ class GmresEngineWorker(threading.Thread):
                     req, admitted = waiting[0]
                     if req.m != self.m:
                         raise ValueError(f"request m={req.m} on a GMRES({self.m}) engine")
+                    if self.gate is not None and inflight and \
+                            not self.gate.fits(request_bytes(self.engine, req)):
+                        break
                     x = torch.zeros_like(req.b)
                     if not self.engine.submit_gs(req.A, req.b, x, p=2, tol=req.tol,
                                                  tag=req.tag):
@@ -155,41 +218,73 @@ class GmresEngineWorker(threading.Thread):
 
 
 class Server:
-    def __init__(self, max_rows: int, max_systems: int, check_every: int = 8,
+    def __init__(self, max_rows: int = 0, max_systems: int = 256, check_every: int = 8,
                  graph: bool = True, gmres_rows: int = 0, m_max: int = 20, device="cuda",
                  gmres_lanes: int = 4, gmres_mode: str = "lanes",
                  gmres_precision: str = "fp64", gmres_engine_rows: int = 0,
                  gmres_engine_systems: int = 64, engine_factory: Callable = gsk.Engine,
-                 tile_units: int = 0):
-        """gmres_mode "lanes": GMRES requests run one at a time on gmres_lanes host threads
-        (workspaces for gmres_rows rows, any m <= m_max). "engine": they run in a GMRES(m_max)
-        engine (gmres_precision "fp64" or "mixed") with room for gmres_engine_rows rows and
-        gmres_engine_systems systems. tile_units: the Bi-CGSTAB engine's tiles per workgroup
-        (0 or 1: one, 2: two; max_rows must then hold each system rounded up to 512 rows).
-        engine_factory(max_rows, max_systems, **options) builds the engines (gsk.Engine; the
-        scheduler's host-side tests pass a stand-in with the same submit_gs / run / poll /
-        close methods)."""
+                 tile_units: int = 0, free_bytes: Optional[Callable[[], int]] = None,
+                 hbm_fraction: float = 0.25, reserve_bytes: int = 2 << 30,
+                 max_rows_cap: int = 1 << 28, max_skip_s: float = 1.0):
+        """max_rows / gmres_engine_rows: the engines' row capacity; 0 sizes them from free
+        device memory (hbm_fraction of it, half to each engine when GMRES runs in an engine,
+        at most max_rows_cap rows each). gmres_mode "lanes": GMRES requests run one at a time
+        on gmres_lanes host threads (workspaces for gmres_rows rows, any m <= m_max).
+        "engine": they run in a GMRES(m_max) engine (gmres_precision "fp64" or "mixed").
+        tile_units: the Bi-CGSTAB engine's tiles per workgroup. free_bytes(): the free-memory
+        probe (device_free_bytes by default); requests are admitted while free memory after
+        them stays above reserve_bytes. A request that does not fit is overtaken by later
+        ones that fit until it has waited max_skip_s. engine_factory(max_rows, max_systems,
+        **options) builds the engines (gsk.Engine; the scheduler's host-side tests pass a
+        stand-in with the same submit_gs / run / poll / close methods)."""
         self.device = torch.device(device)
         self.engine_factory = engine_factory
+        if free_bytes is not None:
+            probe = free_bytes
+        elif self.device.type == "cuda":
+            probe = lambda: device_free_bytes(self.device)   # noqa: E731
+        else:
+            probe = lambda: 1 << 62   # noqa: E731  (host stand-in engines: memory is no limit)
+        self.gate = MemoryGate(probe, reserve_bytes)
+        if gmres_mode not in ("lanes", "engine"):
+            raise ValueError("gmres_mode must be 'lanes' or 'engine'")
+        self.sizing = None
+        if not max_rows or (gmres_mode == "engine" and not gmres_engine_rows):
+            budget = max(0, probe() - reserve_bytes) * hbm_fraction
+            parts = 2 if gmres_mode == "engine" else 1
+            bpr_b = self._bytes_per_row("bicgstab", "fp64", 0)
+            bpr_g = self._bytes_per_row("gmres", gmres_precision, m_max)
+            if not max_rows:
+                max_rows = max(256, min(max_rows_cap, int(budget / parts / bpr_b)))
+            if gmres_mode == "engine" and not gmres_engine_rows:
+                gmres_engine_rows = max(256, min(max_rows_cap, int(budget / parts / bpr_g)))
+            self.sizing = {"free_bytes": probe(), "budget_bytes": int(budget),
+                           "bicgstab_rows": int(max_rows),
+                           "gmres_rows": int(gmres_engine_rows) if gmres_mode == "engine"
+                           else None}
         opts = {"tile_units": tile_units} if tile_units else {}
         self.engine = engine_factory(max_rows, max_systems, check_every=check_every, graph=graph,
                                      device=self.device, **opts)
+        self.max_rows = max_rows
         self.gmres_rows = gmres_rows
         self.m_max = m_max
         self.gmres_lanes = max(1, int(gmres_lanes))
-        if gmres_mode not in ("lanes", "engine"):
-            raise ValueError("gmres_mode must be 'lanes' or 'engine'")
         self.gmres_mode = gmres_mode
         self.gmres_precision = gmres_precision
         self.gmres_engine_rows = gmres_engine_rows or max(gmres_rows, 1)
         self.gmres_engine_systems = gmres_engine_systems
         self.graph = graph
+        self.max_skip_s = max_skip_s
+
+    def _bytes_per_row(self, method, precision, m):
+        fn = getattr(self.engine_factory, "workspace_bytes_per_row", None)
+        return fn(method, precision, m) if fn is not None else 64.0
 
     def serve(self, requests: List[Request], realtime: bool = True) -> List[Done]:
         """Serve the requests (sorted by arrival). With realtime, a request is visible only
         once the wall clock has passed its arrival time."""
         reqs = collections.deque(sorted(requests, key=lambda r: r.arrival))
-        waiting = collections.deque()
+        waiting: List[Request] = []
         done: List[Done] = []
         lock = threading.Lock()
         t0 = time.perf_counter()
@@ -203,7 +298,7 @@ class Server:
                 lanes = [GmresEngineWorker(gq, self.device, t0, self.gmres_engine_rows,
                                            self.gmres_engine_systems, self.m_max,
                                            self.gmres_precision, self.graph, finished,
-                                           self.engine_factory)]
+                                           self.engine_factory, self.gate)]
             else:
                 lanes = [GmresLane(gq, self.device, t0, max(self.gmres_rows, 1), self.m_max,
                                    finished) for _ in range(self.gmres_lanes)]
@@ -211,26 +306,17 @@ class Server:
                 lane.start()
         inflight = {}     # engine tag -> (request, admitted time, x)
         n_total = len(reqs)
+        failed = False
         try:
             while True:
                 now = time.perf_counter() - t0
                 while reqs and (not realtime or reqs[0].arrival <= now):
-                    waiting.append(reqs.popleft())
-                # admit in arrival order; a request that does not fit waits for retirements
-                while waiting:
-                    r = waiting[0]
+                    r = reqs.popleft()
                     if r.method == "gmres":
                         gq.put((r, now))
-                        waiting.popleft()
-                        continue
-                    x = torch.zeros_like(r.b)
-                    if not self.engine.submit_gs(r.A, r.b, x, p=2, tol=r.tol, tag=r.tag):
-                        if not inflight:   # an empty engine that cannot take it never will
-                            raise ValueError(f"request {r.tag} ({r.A.n} rows) does not fit "
-                                             "the engine")
-                        break
-                    inflight[r.tag] = (r, now, x)
-                    waiting.popleft()
+                    else:
+                        waiting.append(r)
+                self._admit(waiting, inflight, now)
                 if inflight:
                     self.engine.run(1)
                     for tag, info in self.engine.poll(wait=True):
@@ -252,14 +338,44 @@ class Server:
                 with lock:
                     if len(done) >= n_total:
                         break
+        except BaseException:
+            failed = True
+            raise
         finally:
-            for _ in lanes:
+            for lane in lanes:
+                if failed:
+                    lane.abort.set()
                 gq.put(None)
             for lane in lanes:
                 lane.join(timeout=60)
-                if isinstance(lane, GmresEngineWorker):
-                    lane.close()
+                if lane.is_alive():
+                    # still inside a device call: leave its engine alone (closing it under
+                    # a running worker would free memory the worker still uses)
+                    continue
+                lane.close()
         return done
+
+    def _admit(self, waiting: List[Request], inflight: dict, now: float) -> None:
+        """Admit waiting Bi-CGSTAB requests that fit the engine and the free memory, in
+        arrival order; a request that does not fit is overtaken by later ones until it has
+        waited max_skip_s."""
+        k = 0
+        while k < len(waiting):
+            r = waiting[k]
+            fits = not inflight or self.gate.fits(request_bytes(self.engine, r))
+            x = None
+            if fits:
+                x = torch.zeros_like(r.b)
+                fits = self.engine.submit_gs(r.A, r.b, x, p=2, tol=r.tol, tag=r.tag)
+                if not fits and not inflight:   # an empty engine that cannot take it never will
+                    raise ValueError(f"request {r.tag} ({r.A.n} rows) does not fit the engine")
+            if fits:
+                inflight[r.tag] = (r, now, x)
+                waiting.pop(k)
+                continue
+            if k == 0 and now - r.arrival > self.max_skip_s:
+                return      # the oldest request has waited long enough: nothing overtakes it
+            k += 1
 
     def close(self):
         self.engine.close()

@@ -105,3 +105,50 @@ def test_request_larger_than_engine_is_an_error(G):
     with pytest.raises(ValueError):
         srv.serve(reqs, realtime=False)
     srv.close()
+
+
+def test_served_results_match_the_oracle(G):
+    """Served results checked against the oracle itself (GS(2), then Bi-CGSTAB or
+    GMRES(20), tol 1e-8): equal status, the true residual below tol, iteration counts within
+    max(2, 10%) (rounding moves them), and x within the conditioning bound of the oracle's
+    x. The engines are sized from the device's free memory (no row counts given). GMRES(20)
+    requests use the systems on which the oracle needs at most 10 cycles: over tens of
+    restarts (27 on system 0) the step count of restarted GMRES moves by more than 10% with
+    rounding alone, which the GMRES parity tests cover with their own bars."""
+    import torch
+    import oracle
+    from paper_0812_2769_amd import serve
+    specs = problems.batch_specs(8, seed=31, n_min=8, n_max=16)
+    systems = pool(G, specs=specs)
+    hosts = [problems.batch_system(sp) for sp in specs]
+    n_req = 16
+    few_cycles = [2, 4, 7]       # the oracle's GMRES(20) converges in <= 10 cycles on these
+    pick = list(range(8)) + [few_cycles[k % 3] for k in range(8)]
+    reqs = [serve.Request(tag=k, arrival=0.001 * k, A=systems[pick[k]]["S"],
+                          b=systems[pick[k]]["b"], method="gmres" if k >= 8 else "bicgstab",
+                          m=20, tol=1e-8, csr=systems[pick[k]]["A"], grid=systems[pick[k]]["grid"])
+            for k in range(n_req)]
+    srv = serve.Server(0, 8, graph=True, m_max=20, gmres_mode="engine",
+                       gmres_precision="fp64", gmres_engine_systems=8)
+    assert srv.sizing["bicgstab_rows"] >= 256 and srv.sizing["gmres_rows"] >= 256
+    done = srv.serve(reqs, realtime=True)
+    srv.close()
+    torch.cuda.synchronize()
+    assert sorted(d.tag for d in done) == list(range(n_req))
+    for d in done:
+        P = hosts[pick[d.tag]]
+        vo, bo, _, _ = oracle.gs_scale(P, P.b, 2)
+        S = P.copy()
+        S.val, S.b = vo, bo
+        if d.method == "gmres":
+            xo, io = oracle.gmres(S, bo, m=20, tol=1e-8)
+        else:
+            xo, io = oracle.bicgstab(S, bo, tol=1e-8)
+        assert d.info.status == io.status, (d.tag, d.info, io)
+        assert abs(d.info.iters - io.iters) <= max(2, 0.1 * io.iters), (d.tag, d.info, io)
+        if io.status == oracle.CONVERGED:
+            assert d.info.relres_true < 1e-8
+            A = S.dense()
+            x = d.x.cpu().numpy()
+            bound = 10 * np.linalg.cond(A) * 1e-8
+            assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= bound, (d.tag, bound)
