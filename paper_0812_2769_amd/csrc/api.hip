@@ -24,7 +24,16 @@ struct Pinned {
   Summary sum[2];
   int flags[4];
 };
-thread_local Pinned* g_pinned = nullptr;
+
+// A thread's pinned status block: allocated on the thread's first solve, freed when the thread
+// exits (serving lanes and other worker threads come and go).
+struct PinnedHolder {
+  Pinned* p = nullptr;
+  ~PinnedHolder() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+thread_local PinnedHolder g_pinned;
 
 int set_err(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 int set_err(int code, const char* fmt, ...) {
@@ -42,12 +51,12 @@ int hip_err(hipError_t e, const char* what) {
 }
 
 Pinned* pinned() {
-  if (!g_pinned) {
+  if (!g_pinned.p) {
     void* p = nullptr;
     if (hipHostMalloc(&p, sizeof(Pinned), hipHostMallocDefault) != hipSuccess) return nullptr;
-    g_pinned = static_cast<Pinned*>(p);
+    g_pinned.p = static_cast<Pinned*>(p);
   }
-  return g_pinned;
+  return g_pinned.p;
 }
 
 int check_csr(const gsk_csr* A) {

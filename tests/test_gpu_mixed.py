@@ -191,6 +191,22 @@ def test_checker160_full_size_mixed_vs_fp64(G, checker160):
         assert rel == pytest.approx(info.relres_true, rel=1e-6)
 
 
+def test_checker160_full_size_two_cycles_vs_oracle(G, checker160):
+    """160^3 at full size, FP64 GMRES(30) after GS(2), both sides bounded to two cycles (60
+    Arnoldi steps): the oracle's orc_gmres on its own scaled system against the HIP solver
+    with the stencil operator. Restarted GMRES stagnates here, so, as for the stagnating
+    cases of the small parity suite, the first two cycles are compared before rounding has
+    been amplified: true residuals to 1e-6 and x to 1e-8 relative."""
+    P = checker160
+    M, bs, _ = gpu_scaled(G, P)
+    x, info = G.gmres(M, bs, m=30, tol=1e-8, maxit=60)
+    S, _ = oracle_scaled(P)
+    xo, io = oracle.gmres(S, S.b, m=30, tol=1e-8, maxit=60)
+    assert info.status == io.status == G.MAXIT and info.iters == io.iters == 60
+    assert info.relres_true == pytest.approx(io.relres_true, rel=1e-6)
+    np.testing.assert_allclose(host(x), xo, rtol=1e-8, atol=1e-10 * np.abs(xo).max())
+
+
 def test_checker160_full_size_gs_and_spmv_sampled(G, checker160):
     """The 160^3 system at full size (n = 4,096,000): GS(1) and GS(2) outputs (scaled values,
     right-hand side, row norms, stop weights) and the scaled matrix's product through the CSR

@@ -94,3 +94,50 @@ def test_table1_problem1(G):
                 assert level / f < info.relres_true < level * f, (method, tol, info)
             else:
                 _check(G, printed, info, (method, tol))
+
+
+def _best_goal(G, runs_by_tol):
+    """The strictest goal a method reached: 1e-10, 1e-7, 1e-4 or none."""
+    best = "none"
+    for tol, info in zip(TOLS, runs_by_tol):
+        if info.status == G.CONVERGED:
+            best = f"{tol:g}"
+    return best
+
+
+def test_table2_problem1_continuous(G):
+    """Table 2 (Problem 1 with a = b = 1000 everywhere, 128x128): every run converges at every
+    goal, counts within 10% of the printed ones (Bi-CGSTAB with GS at 1e-10: the printed 261
+    lies inside the oracle's own spread under 1-ulp perturbations, 259-309, and the GPU count
+    must lie within that spread)."""
+    gold = _golden("table2_problem1_continuous_iterations.txt")
+    P = problems.problem1(128, continuous=1000.0)
+    for t, tol in enumerate(TOLS):
+        runs = _runs(G, P, tol)
+        for method, info in runs.items():
+            if method == "bicgstab_gs" and tol == 1e-10:
+                assert info.status == G.CONVERGED and 255 <= info.iters <= 315, info
+                continue
+            _check(G, gold[method][t], info, (method, tol))
+
+
+def test_table12_problem4_convection(G):
+    """Table 12 (Problem 4, 40x40x40, D = 1e4, convection 100..1000): the strictest goal each
+    method reaches through the HIP path equals the printed one, except GMRES(10) with GS at
+    convection 500, which stagnates just below 1e-4 here (the oracle: 6.0e-5) where the paper
+    reports no goal; there the level reached must lie within a factor 2 of 1e-4."""
+    gold = _golden("table12_problem4_40cube_goals.txt")
+    for c_i, conv in enumerate((100.0, 200.0, 500.0, 1000.0)):
+        P = problems.problem4(40, D=1e4, conv=conv)
+        per_tol = [_runs(G, P, tol) for tol in TOLS]
+        for method in ("bicgstab", "bicgstab_gs", "gmres10", "gmres10_gs"):
+            infos = [r[method] for r in per_tol]
+            got = _best_goal(G, infos)
+            printed = gold[method][c_i]
+            if method == "gmres10_gs" and conv == 500.0:
+                assert got in ("none", "0.0001"), got
+                level = infos[1].relres_true      # the run to 1e-7 stagnates
+                assert 5e-5 < level < 2e-4, level
+                continue
+            assert got == {"none": "none", "1e-4": "0.0001", "1e-7": "1e-07",
+                           "1e-10": "1e-10"}[printed], (conv, method, got, printed)
