@@ -328,23 +328,54 @@ def bench_batch(args, gsk, problems, dev):
     systems, host = build_batch_systems(gsk, problems, dev, specs, keep_host=sample)
     unit = 512 if mixed else 256
     tuned = None
-    check_every, tile_units = 8, 0
+    check_every, tile_units, class_shapes = 8, 0, None
     if args.tile_units or args.chunk:
         tile_units, check_every = args.tile_units or 1, args.chunk or 8
-    elif not gmres and not mixed and not args.no_tune:
-        # launch shape and chunk length measured on the batch, before (and outside) the timing
+    elif not gmres and not args.no_tune:
+        # launch shapes and chunk length measured on the batch, before (and outside) the timing
         from paper_0812_2769_amd import tune
-        tuned = tune.tune_engine(systems, device=dev, maxit=48)
-        tile_units, check_every = tuned["best"]
-        log(f"engine tuned on {tuned['sample']} systems x {tuned['maxit']} iterations: "
-            f"{ {f'{u}x{k}': round(v, 4) for (u, k), v in tuned['seconds'].items()} } -> "
-            f"{tile_units} tile(s) per workgroup, chunks of {check_every}")
+        t0 = time.perf_counter()
+        if mixed:
+            t = tune.tune_mixed_chunk(systems, device=dev, maxit=48)
+            check_every = t["chunk"]
+            tuned = {"engine": "mixed Bi-CGSTAB: two tiles per workgroup (FP32 data), chunk "
+                               "length measured",
+                     "chunk": check_every, "iterations_each": t["maxit"],
+                     "chunk_seconds": {str(k): round(v, 4)
+                                       for k, v in t["chunk_seconds"].items()}}
+        else:
+            t = tune.tune_classes(systems, device=dev, maxit=48)
+            class_shapes, check_every = t["class_shapes"], t["chunk"]
+            one = {name: min(tune.time_batch(systems, check_every, device=dev, tile_units=u,
+                                             maxit=48) for _ in range(2))
+                   for name, u in (("tile", 1), ("pair", 2))}
+            tuned = {"engine": "FP64 Bi-CGSTAB: a launch shape per size class, each class "
+                               "timed alone with every shape; then the chunk length",
+                     "class_shapes": class_shapes, "chunk": check_every,
+                     "iterations_each": t["maxit"],
+                     "class_systems": t["class_systems"], "class_rows": t["class_rows"],
+                     "class_seconds": {c: {k: round(v, 4) for k, v in d.items()}
+                                       for c, d in t["class_seconds"].items()},
+                     "chunk_seconds": {str(k): round(v, 4)
+                                       for k, v in t["chunk_seconds"].items()},
+                     "whole_batch_seconds": {
+                         "per_class": round(t["chunk_seconds"][check_every], 4),
+                         "one_shape_tile": round(one["tile"], 4),
+                         "one_shape_pair": round(one["pair"], 4)}}
+        tuned["tuning_s"] = round(time.perf_counter() - t0, 1)
+        log(f"engine tuned: {tuned}")
+    elif gmres:
+        tuned = {"engine": f"GMRES(20) {'mixed' if mixed else 'FP64'}: shape fixed by the "
+                           "single solver's partial sums (one tile per workgroup for FP64, "
+                           "two for FP32 data); a chunk is one restart cycle"}
     if tile_units:
         unit = 256 * tile_units
+    if class_shapes:
+        unit = 512
     rows = sum((s["n"] + unit - 1) // unit * unit for s in systems)
     eng = gsk.Engine(rows, len(systems), check_every=check_every, graph=True, device=dev,
                      method=args.batch_method, m=20, precision="mixed" if mixed else "fp64",
-                     tile_units=tile_units)
+                     tile_units=tile_units, class_shapes=class_shapes)
     solver = (f"GMRES(20) {'mixed precision' if mixed else 'FP64'}" if gmres
               else f"Bi-CGSTAB {'mixed precision' if mixed else 'FP64'}")
     xbuf = torch.zeros(sum(s["n"] for s in systems), dtype=torch.float64, device=dev)
@@ -427,10 +458,7 @@ def bench_batch(args, gsk, problems, dev):
             "note": "algorithmic bytes of every Krylov iteration (Arnoldi step) of a step / "
                     "whole step time (GS, residual and finalize launches, host polls "
                     "included)"},
-        "engine_tuning": None if tuned is None else {
-            "tiles_per_workgroup": tuned["best"][0], "chunk": tuned["best"][1],
-            "sample_systems": tuned["sample"], "iterations_each": tuned["maxit"],
-            "seconds": {f"{u}x{k}": round(v, 4) for (u, k), v in tuned["seconds"].items()}},
+        "engine_tuning": tuned,
         "roofline": None, "cpu_baseline": None,
     }
     a = achieved(pr)

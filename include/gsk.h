@@ -439,7 +439,16 @@ typedef struct gsk_engine_config {
                               0 selects 1e-6; otherwise in (0, 1)                           */
     int32_t run_cap;       /* mixed Bi-CGSTAB: a run with FP32 storage also ends after this
                               many iterations; 0 selects 1000, -1: no cap                   */
-    int32_t reserved;      /* 0                                                             */
+    int32_t class_shapes;  /* FP64 Bi-CGSTAB: launch shape per size class, 0 for one shape
+                              (tile_units) for every system. Classes: 0 = 2D stencils and
+                              CSR matrices, 1 = 3D stencils of fewer than 2^18 rows, 2 = 3D
+                              stencils of 2^18 rows or more; bits 4c..4c+3 hold class c's
+                              code: 1 = P and S one tile per workgroup, U one tile; 2 = P and
+                              S two tiles per workgroup, U one tile; 3 = P and S two tiles,
+                              U a unit's two tiles in turn; 0 = the code tile_units selects
+                              (2 -> 3, otherwise 1). Each class then has its own launches and
+                              rows are handed out in pairs of tiles. A shape choice only:
+                              every system returns the same bits under any code.          */
 } gsk_engine_config;
 
 /* 0 for an invalid configuration. */

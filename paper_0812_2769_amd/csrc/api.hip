@@ -412,6 +412,17 @@ static int engine_cfg(const gsk_engine_config* c, gsk::EngineConfig& cfg) {
       (c->tile_units == 2 && (gmres || c->precision != GSK_PRECISION_FP64)))
     return set_err(GSK_ERR_INVALID_ARG, "tile_units must be 0 or 1 (or 2 for FP64 Bi-CGSTAB)");
   cfg.units = c->tile_units;
+  if (c->class_shapes != 0) {
+    if (gmres || c->precision != GSK_PRECISION_FP64)
+      return set_err(GSK_ERR_INVALID_ARG, "class_shapes applies to FP64 Bi-CGSTAB engines only");
+    if ((uint32_t)c->class_shapes >> 12)
+      return set_err(GSK_ERR_INVALID_ARG, "class_shapes has bits beyond its three classes");
+    for (int k = 0; k < 3; ++k) {
+      const int code = (c->class_shapes >> (4 * k)) & 15;
+      if (code > 3) return set_err(GSK_ERR_INVALID_ARG, "class_shapes: shape codes are 0..3");
+      cfg.class_shape[k] = code;
+    }
+  }
   return GSK_OK;
 }
 

@@ -359,12 +359,12 @@ __global__ __launch_bounds__(BS) void k_batch_fin_u(BArgsB a) {
 // system at that stage, the figures of the kernel-class table in gsk.h), into ps->bytes[slot].
 // Runs between that launch and its finalize, so every system is in the state the launch saw.
 __global__ __launch_bounds__(BS) void k_batch_probe_bytes(BArgsB a, int max_sys, int kc,
-                                                          int slot, ProbeSlots* ps) {
+                                                          int cls, int slot, ProbeSlots* ps) {
   __shared__ double red[NC_MAX * WAVES];
   double acc[1] = {0.0};
   for (int s = threadIdx.x; s < max_sys; s += BS) {
     const SysDesc d = a.sys[s];
-    if (d.ntiles == 0) continue;
+    if (d.ntiles == 0 || d.cls != cls) continue;
     const BCtl* c = a.ctl + s;
     const int st = c->sum.state;
     const double n = (double)d.n;
@@ -392,13 +392,26 @@ struct EngineLayout {
   size_t sys, tiles, probe, ctl, sums, partials, vecs, total;
 };
 
+static bool per_class(const EngineConfig& cfg) {
+  return cfg.method == 0 && !cfg.mixed &&
+         (cfg.class_shape[0] | cfg.class_shape[1] | cfg.class_shape[2]) != 0;
+}
+
+static int classes_of(const EngineConfig& cfg) { return per_class(cfg) ? kClassCount : 1; }
+
 static int units_of(const EngineConfig& cfg) {
-  if (cfg.mixed) return 2;
+  if (cfg.mixed || per_class(cfg)) return 2;
   return cfg.method == 0 && cfg.units == 2 ? 2 : 1;   // FP64 Bi-CGSTAB may take two
 }
 
-// Workspace carve-up. Bi-CGSTAB: system table, unit list, control blocks, partials (4 per
-// tile), the 7 vectors. GMRES: system table, unit list, control blocks, status copies,
+// Size class of a system in an engine with per-class shapes.
+static int class_of(const Mat& A) {
+  if (A.kind != MAT_STENCIL || A.nz <= 1) return kClass2D;
+  return A.n < kClassLargeRows ? kClass3DSmall : kClass3DLarge;
+}
+
+// Workspace carve-up. Bi-CGSTAB: system table, unit lists (per size class: units, slots;
+// then the classes' counts), control blocks, partials (4 per tile), the 7 vectors. GMRES: system table, unit list, control blocks, status copies,
 // partials (max(m+1, 3) columns per tile and one more for C), basis (m+1 columns) and w, in
 // FP64 or FP32.
 static EngineLayout engine_layout(const EngineConfig& cfg) {
@@ -410,7 +423,7 @@ static EngineLayout engine_layout(const EngineConfig& cfg) {
   L.sys = off;
   off += align256(sizeof(SysDesc) * ns);
   L.tiles = off;
-  off += align256(sizeof(int) * (2 * (size_t)grid_tiles + 1));
+  off += align256(sizeof(int) * (size_t)classes_of(cfg) * (2 * (size_t)grid_tiles + 1));
   L.probe = off;
   off += align256(sizeof(ProbeSlots));
   L.ctl = off;
@@ -457,6 +470,8 @@ struct Engine {
   bool mixed = false;
   int rv = 1;                      // tiles per unit
   int max_units = 0;
+  int nclass = 1;                  // size classes, each with its own unit list and launches
+  int shape[kClassCount] = {kShapeTile, kShapeTile, kShapeTile};
   bool column = true;              // GMRES basis fits one buffer descriptor
   BArgsB args{};
   GArgs gargs{};
@@ -481,8 +496,8 @@ struct Engine {
   Summary* p_sums = nullptr;
   hipEvent_t ev_upload = nullptr, ev_chunk = nullptr;
   bool upload_pending = false, chunk_pending = false;
-  int n_listed = 0;                          // entries of the device tile list
-  std::map<int, hipGraphExec_t> graphs;      // captured chunk per streaming grid size
+  int n_listed[kClassCount] = {0, 0, 0};     // entries of each class's device unit list
+  std::map<std::vector<int>, hipGraphExec_t> graphs;   // captured chunk per grid sizes
 };
 
 static const Summary& status_of(const Engine& e, int slot) {
@@ -553,6 +568,14 @@ int engine_create(void* ws, size_t ws_bytes, const EngineConfig& cfg, hipStream_
   e->mixed = cfg.mixed;
   e->rv = units_of(cfg);
   e->max_units = e->grid_tiles / e->rv;
+  e->nclass = classes_of(cfg);
+  if (per_class(cfg)) {
+    const int dflt = cfg.units == 2 ? kShapePair : kShapeTile;
+    for (int c = 0; c < kClassCount; ++c)
+      e->shape[c] = cfg.class_shape[c] ? cfg.class_shape[c] : dflt;
+  } else {
+    e->shape[0] = e->rv == 2 ? kShapePair : kShapeTile;
+  }
   const int max_sys = cfg.max_sys;
   char* base = static_cast<char*>(ws);
   if (e->method == 1) {
@@ -619,6 +642,7 @@ int engine_create(void* ws, size_t ws_bytes, const EngineConfig& cfg, hipStream_
     a.max_tiles = e->grid_tiles;
     a.max_units = e->max_units;
     a.rv = e->rv;
+    a.split = 0;
     a.n_act = a.act + 2 * (size_t)e->max_units;
     const size_t vb = align256(sizeof(double) * (size_t)e->grid_tiles * BS);
     double* v[kBatchVectors];
@@ -643,7 +667,8 @@ int engine_create(void* ws, size_t ws_bytes, const EngineConfig& cfg, hipStream_
   e->free_tiles[0] = e->max_tiles;
   bool ok = hipHostMalloc((void**)&e->p_sys, sizeof(SysDesc) * max_sys, hipHostMallocDefault) ==
                 hipSuccess &&
-            hipHostMalloc((void**)&e->p_tiles, sizeof(int) * (2 * (size_t)e->grid_tiles + 1),
+            hipHostMalloc((void**)&e->p_tiles,
+                          sizeof(int) * (size_t)e->nclass * (2 * (size_t)e->max_units + 1),
                           hipHostMallocDefault) == hipSuccess &&
             hipEventCreateWithFlags(&e->ev_upload, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&e->ev_chunk, hipEventDisableTiming) == hipSuccess;
@@ -706,6 +731,7 @@ int engine_submit(Engine* e, const Mat& A, const double* b, double* x, const Sol
   d.ntiles = need;
   d.unit_off = start / e->rv;
   d.nunits = held / e->rv;
+  d.cls = e->nclass > 1 ? class_of(A) : 0;
   d.row_off = (int64_t)start * BS;
   d.rp = A.csr.rp;
   d.ci = A.csr.ci;
@@ -767,9 +793,11 @@ static int upload(Engine& e) {
     if (!e.active[i]) e.p_sys[i].ntiles = 0;
   }
   // the units of every admitted system, in row-space order (a system's units are
-  // consecutive, so adjacent list entries are adjacent rows of one system); only the listed
-  // entries and the count are copied, so a large engine costs no more than a small one
-  int n = 0;
+  // consecutive, so adjacent list entries are adjacent rows of one system), each in its size
+  // class's list; only the listed entries and the counts are copied, so a large engine costs
+  // no more than a small one
+  const size_t mu = (size_t)e.max_units;
+  int n[kClassCount] = {0, 0, 0};
   for (int t = 0; t < e.grid_tiles;) {
     const int s = e.tile_sys[t];
     if (s < 0) {
@@ -778,79 +806,144 @@ static int upload(Engine& e) {
       continue;
     }
     const SysDesc& d = e.h_sys[s];
+    int* list = e.p_tiles + (size_t)d.cls * 2 * mu;
     for (int u = 0; u < d.nunits; ++u) {
-      e.p_tiles[n] = d.unit_off + u;
-      e.p_tiles[e.max_units + n] = s;
-      ++n;
+      list[n[d.cls]] = d.unit_off + u;
+      list[mu + n[d.cls]] = s;
+      ++n[d.cls];
     }
     t = d.tile_off + d.nunits * e.rv;
   }
-  e.p_tiles[2 * (size_t)e.max_units] = n;
-  e.n_listed = n;
-  const size_t mu = (size_t)e.max_units;
-  if (hipMemcpyAsync(e.d_sys, e.p_sys, sizeof(SysDesc) * e.max_sys,
-                     hipMemcpyHostToDevice, e.s) != hipSuccess ||
-      (n > 0 && hipMemcpyAsync(e.d_list, e.p_tiles, sizeof(int) * (size_t)n,
-                               hipMemcpyHostToDevice, e.s) != hipSuccess) ||
-      (n > 0 && hipMemcpyAsync(e.d_list + mu, e.p_tiles + mu, sizeof(int) * (size_t)n,
-                               hipMemcpyHostToDevice, e.s) != hipSuccess) ||
-      hipMemcpyAsync(e.d_list + 2 * mu, e.p_tiles + 2 * mu, sizeof(int),
-                     hipMemcpyHostToDevice, e.s) != hipSuccess ||
-      hipEventRecord(e.ev_upload, e.s) != hipSuccess)
-    return -5;
+  int* counts = e.p_tiles + (size_t)e.nclass * 2 * mu;
+  bool ok = hipMemcpyAsync(e.d_sys, e.p_sys, sizeof(SysDesc) * e.max_sys,
+                           hipMemcpyHostToDevice, e.s) == hipSuccess;
+  for (int c = 0; c < e.nclass; ++c) {
+    counts[c] = n[c];
+    e.n_listed[c] = n[c];
+    const size_t base = (size_t)c * 2 * mu;
+    if (n[c] > 0)
+      ok = ok &&
+           hipMemcpyAsync(e.d_list + base, e.p_tiles + base, sizeof(int) * (size_t)n[c],
+                          hipMemcpyHostToDevice, e.s) == hipSuccess &&
+           hipMemcpyAsync(e.d_list + base + mu, e.p_tiles + base + mu,
+                          sizeof(int) * (size_t)n[c], hipMemcpyHostToDevice, e.s) == hipSuccess;
+  }
+  ok = ok &&
+       hipMemcpyAsync(e.d_list + (size_t)e.nclass * 2 * mu, counts, sizeof(int) * e.nclass,
+                      hipMemcpyHostToDevice, e.s) == hipSuccess &&
+       hipEventRecord(e.ev_upload, e.s) == hipSuccess;
+  if (!ok) return -5;
   e.upload_pending = true;
   e.dirty = false;
   return 0;
 }
 
-// Launch of a streaming kernel of class kc; in a sampled chunk (probed == kc) it carries a pair
-// of timing events and is followed by the launch that records its algorithmic bytes.
+// Launch of a streaming kernel of class kc over the systems of size class cls; in a sampled
+// chunk (probed == kc) it carries a pair of timing events and is followed by the launch that
+// records its algorithmic bytes.
 template <class F>
-static void launch_stream(Engine& e, F kernel, int kc, int probed, dim3 grid, const BArgsB& a) {
+static void launch_stream(Engine& e, F kernel, int kc, int probed, dim3 grid, const BArgsB& a,
+                          int cls) {
   const int slot = probed == kc ? probe_slot_all(kc) : -1;
   launch_probed(kernel, grid, e.s, slot, a);
   if (slot >= 0)
-    hipLaunchKernelGGL(k_batch_probe_bytes, dim3(1), dim3(BS), 0, e.s, a, e.max_sys, kc, slot,
-                       e.d_probe);
+    hipLaunchKernelGGL(k_batch_probe_bytes, dim3(1), dim3(BS), 0, e.s, a, e.max_sys, kc, cls,
+                       slot, e.d_probe);
 }
 
-static void enqueue_chunk(Engine& e, int k, int64_t first_iter, int grid, int probed = 0) {
+// Streaming grid of each size class's unit list (0: the class has no systems).
+static std::vector<int> class_grids(const Engine& e) {
+  std::vector<int> g(e.nclass, 0);
+  for (int c = 0; c < e.nclass; ++c)
+    g[c] = e.n_listed[c] > 0 || e.nclass == 1 ? stream_grid(e.n_listed[c]) : 0;
+  return g;
+}
+
+static void enqueue_chunk(Engine& e, int k, int64_t first_iter, const std::vector<int>& grids,
+                          int probed = 0) {
   if (e.method == 1) {
-    (void)launch_gmres_chunk(e.gargs, e.m, grid, e.max_sys, e.column, e.s);
+    (void)launch_gmres_chunk(e.gargs, e.m, grids[0], e.max_sys, e.column, e.s);
     return;
   }
   if (e.mixed) {
-    (void)launch_bicg_mixed_chunk(e.margs, k, first_iter, grid, e.max_sys, e.s);
+    (void)launch_bicg_mixed_chunk(e.margs, k, first_iter, grids[0], e.max_sys, e.s);
     return;
   }
-  const dim3 gt(grid), gs(e.max_sys), block(BS);
-  BArgsB a = e.args;
-  hipLaunchKernelGGL(k_batch_gs, gt, block, 0, e.s, a);
-  hipLaunchKernelGGL(k_batch_fin_gs, gs, dim3(64), 0, e.s, a);
-  hipLaunchKernelGGL(k_batch_residual, gt, block, 0, e.s, a);
-  hipLaunchKernelGGL(k_batch_fin_residual, gs, block, 0, e.s, a);
+  // each class's launches read its own unit list; with units of two tiles, per-tile launches
+  // (split) take a unit with two workgroups
+  const size_t mu = (size_t)e.max_units;
+  const dim3 gs(e.max_sys), block(BS);
+  BArgsB ac[kClassCount];
+  dim3 gu[kClassCount], gt[kClassCount];
+  for (int c = 0; c < e.nclass; ++c) {
+    ac[c] = e.args;
+    ac[c].act = e.d_list + (size_t)c * 2 * mu;
+    ac[c].n_act = e.d_list + (size_t)e.nclass * 2 * mu + c;
+    gu[c] = dim3(grids[c]);
+    gt[c] = dim3(grids[c] * (e.nclass > 1 ? e.rv : 1));
+  }
+  auto each = [&](auto body) {
+    for (int c = 0; c < e.nclass; ++c)
+      if (grids[c] > 0) body(c);
+  };
+  // per-tile launches: split in an engine with size classes (units of two tiles), otherwise
+  // one workgroup per unit as before
+  auto tiled = [&](int c) {
+    BArgsB a = ac[c];
+    a.split = e.nclass > 1 ? 1 : 0;
+    return a;
+  };
+  each([&](int c) { hipLaunchKernelGGL(k_batch_gs, gt[c], block, 0, e.s, tiled(c)); });
+  hipLaunchKernelGGL(k_batch_fin_gs, gs, dim3(64), 0, e.s, e.args);
+  each([&](int c) { hipLaunchKernelGGL(k_batch_residual, gt[c], block, 0, e.s, tiled(c)); });
+  hipLaunchKernelGGL(k_batch_fin_residual, gs, block, 0, e.s, e.args);
   for (int it = 0; it < k; ++it) {
-    a.par = (int)((first_iter + it) & 1);
-    if (e.rv == 2) launch_stream(e, k_batch_p<2>, KC_BATCH_P, probed, gt, a);
-    else launch_stream(e, k_batch_p<1>, KC_BATCH_P, probed, gt, a);
-    hipLaunchKernelGGL(k_batch_fin_p, gs, block, 0, e.s, a);
-    if (e.rv == 2) launch_stream(e, k_batch_s<2>, KC_BATCH_S, probed, gt, a);
-    else launch_stream(e, k_batch_s<1>, KC_BATCH_S, probed, gt, a);
-    hipLaunchKernelGGL(k_batch_fin_s, gs, block, 0, e.s, a);
-    launch_stream(e, k_batch_u, KC_BATCH_U, probed, gt, a);
-    hipLaunchKernelGGL(k_batch_fin_u, gs, block, 0, e.s, a);
+    const int par = (int)((first_iter + it) & 1);
+    for (int c = 0; c < e.nclass; ++c) ac[c].par = par;
+    BArgsB fa = e.args;
+    fa.par = par;
+    each([&](int c) {
+      if (e.shape[c] == kShapeTile) {
+        BArgsB a = tiled(c);
+        a.par = par;
+        launch_stream(e, k_batch_p<1>, KC_BATCH_P, probed, gt[c], a, c);
+      } else {
+        launch_stream(e, k_batch_p<2>, KC_BATCH_P, probed, gu[c], ac[c], c);
+      }
+    });
+    hipLaunchKernelGGL(k_batch_fin_p, gs, block, 0, e.s, fa);
+    each([&](int c) {
+      if (e.shape[c] == kShapeTile) {
+        BArgsB a = tiled(c);
+        a.par = par;
+        launch_stream(e, k_batch_s<1>, KC_BATCH_S, probed, gt[c], a, c);
+      } else {
+        launch_stream(e, k_batch_s<2>, KC_BATCH_S, probed, gu[c], ac[c], c);
+      }
+    });
+    hipLaunchKernelGGL(k_batch_fin_s, gs, block, 0, e.s, fa);
+    each([&](int c) {
+      if (e.shape[c] == kShapePair) {
+        launch_stream(e, k_batch_u, KC_BATCH_U, probed, gu[c], ac[c], c);
+      } else {
+        BArgsB a = tiled(c);
+        a.par = par;
+        launch_stream(e, k_batch_u, KC_BATCH_U, probed, gt[c], a, c);
+      }
+    });
+    hipLaunchKernelGGL(k_batch_fin_u, gs, block, 0, e.s, fa);
   }
 }
 
 int engine_run(Engine* e, int chunks) {
   if (upload(*e)) return -5;
   const int k = e->check_every;
-  const int grid = stream_grid(e->n_listed);
+  const std::vector<int> grid = class_grids(*e);
   hipGraphExec_t exec = nullptr;
   if (e->use_graph) {
     // Every Bi-CGSTAB chunk starts at an even iteration (k is even) and every GMRES chunk at
-    // the start of a cycle, so one captured chunk per grid size serves all; the chunk reads
-    // the unit list and control blocks from device memory.
+    // the start of a cycle, so one captured chunk per set of grid sizes serves all; the chunk
+    // reads the unit lists and control blocks from device memory.
     auto it = e->graphs.find(grid);
     if (it != e->graphs.end()) {
       exec = it->second;

@@ -9,9 +9,10 @@ namespace gsk {
 // One admitted system. Its rows occupy tiles [tile_off, tile_off + ntiles) of the engine's
 // row space (row_off = tile_off * BS); a workgroup of a streaming launch takes one unit of
 // `units` consecutive tiles (1, or 2 for FP32 data), units [unit_off, unit_off + nunits).
+// cls: the size class whose launches take the system (0 when the engine has one class).
 struct SysDesc {
   int n, kind, nx, ny, nz, tile_off, ntiles, gs_p;
-  int unit_off, nunits;
+  int unit_off, nunits, cls;
   int64_t row_off;
   const int* rp;
   const int* ci;

@@ -111,6 +111,7 @@ __device__ inline BArgsB fp64_view(const MArgs& a) {
   b.max_tiles = a.pstride;
   b.max_units = a.max_units;
   b.rv = 2;
+  b.split = 0;
   b.r = a.r64;
   b.rh = a.rh64;
   b.p[0] = a.p64[0];

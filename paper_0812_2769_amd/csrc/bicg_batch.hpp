@@ -10,13 +10,14 @@ namespace gsk {
 
 struct BArgsB {
   const SysDesc* sys;
-  const int* act;        // [2][max_units]: units of the admitted systems, then their slots
+  const int* act;        // [2][max_units]: units of one class's systems, then their slots
   const int* n_act;      // number of entries in act
   BCtl* ctl;             // [max_systems]
   double* partials;      // [4][max_tiles]
   int max_tiles;
   int max_units;         // list capacity (its second half starts there)
   int rv;                // tiles per list unit (1 or 2)
+  int split;             // per-tile launches: rv workgroups per unit, one tile each
   double* r;
   double* rh;
   double* p[2];
@@ -25,19 +26,28 @@ struct BArgsB {
   int par;               // buffer parity of this iteration
 };
 
-// Calls body(tile, slot) for the list entry of this workgroup (logical block k takes entry k;
-// consecutive entries, adjacent rows of one system, go to one XCD). Workgroups past the end of
-// the list (the launch grid is the list length rounded up) return at once.
+// Calls body(tile, slot) for the tile of this workgroup. Logical block k takes list entry k,
+// or with `split` tile k % rv of entry k / rv; consecutive entries, adjacent rows of one
+// system, go to one XCD. Without split a unit of two tiles is taken by one workgroup, its
+// tiles in turn (the workgroup's LDS is reused between them). Workgroups past the end of the
+// list (the launch grid is the list length rounded up) return at once.
 template <class Body>
 __device__ inline void for_active_tiles(const BArgsB& a, Body body) {
   const int k = logical_block();
+  if (a.split) {
+    const int e = k / a.rv, q = k - e * a.rv;
+    if (e >= *a.n_act) return;
+    const int unit = a.act[e], s = a.act[a.max_units + e];
+    const int lt = (unit - a.sys[s].unit_off) * a.rv + q;
+    if (lt < a.sys[s].ntiles) body(a.sys[s].tile_off + lt, s);
+    return;
+  }
   if (k >= *a.n_act) return;
   const int unit = a.act[k], s = a.act[a.max_units + k];
   if (a.rv == 1) {
     body(unit, s);
     return;
   }
-  // the unit's tiles in turn (the workgroup's LDS is reused between them)
   const int t0 = a.sys[s].tile_off + (unit - a.sys[s].unit_off) * a.rv;
   const int t1 = a.sys[s].tile_off + a.sys[s].ntiles;
   for (int q = 0; q < a.rv && t0 + q < t1; ++q) {

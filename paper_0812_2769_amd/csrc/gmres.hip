@@ -509,7 +509,6 @@ static SolveResult arnoldi_impl(const Mat& A, const Op& op, const double* r0, in
 // planes are loaded non-temporally, which keeps the caches for the gathered column's
 // neighbours and the partials. Below that size the data stays cache-resident between launches
 // and ordinary loads are faster. Results are the same bits either way.
-constexpr double kStreamBytes = 256.0 * (1 << 20);
 
 static bool streams(const Mat& A, int m, size_t value_bytes, double inner_bytes) {
   return (double)(m + 2) * (double)vec_ld(A.n) * (double)value_bytes + inner_bytes >

@@ -119,6 +119,11 @@ struct EngineDone {
   int64_t tag;
   Summary sum;
 };
+// Last-level cache of the device (256 MB of Infinity Cache on MI355X): working sets above it
+// are streamed from HBM once per launch, and loads or stores that are not reused within the
+// launch then take the non-temporal policy.
+constexpr double kStreamBytes = 256.0 * (1 << 20);
+
 struct EngineConfig {
   int64_t max_rows;
   int max_sys;
@@ -130,7 +135,18 @@ struct EngineConfig {
   double delta;      // mixed Bi-CGSTAB: reduction that ends a run (refinement step)
   int run_cap = 0;   // mixed Bi-CGSTAB: iterations that end a run (0: no cap)
   int units;         // FP64 Bi-CGSTAB: 256-row tiles per workgroup (1 or 2; 0 = 1)
+  // FP64 Bi-CGSTAB: launch shape per size class (kClass2D, kClass3DSmall, kClass3DLarge), each
+  // one of the kShape* codes; all 0: one class, shaped by `units`
+  int class_shape[3] = {0, 0, 0};
 };
+// Size classes of an FP64 Bi-CGSTAB engine with per-class launch shapes: 2D stencils and CSR
+// matrices; 3D stencils of fewer than kClassLargeRows rows; larger 3D stencils.
+enum : int { kClass2D = 0, kClass3DSmall = 1, kClass3DLarge = 2, kClassCount = 3 };
+constexpr int kClassLargeRows = 1 << 18;
+// Launch shapes of a class (rows are handed out in pairs of tiles): P and S one tile per
+// workgroup, U one tile; P and S two tiles per workgroup (both tiles' loads in flight), U one
+// tile; P and S two tiles, U a unit's two tiles in turn.
+enum : int { kShapeTile = 1, kShapePairTileU = 2, kShapePair = 3 };
 size_t engine_workspace_bytes(const EngineConfig& cfg);
 // 0 ok, -4 workspace too small, -1 invalid arguments, -5 HIP failure.
 int engine_create(void* ws, size_t ws_bytes, const EngineConfig& cfg, hipStream_t s,

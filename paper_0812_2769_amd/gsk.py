@@ -88,7 +88,31 @@ class EngineConfig(ctypes.Structure):
                 ("method", ctypes.c_int32), ("m", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("tile_units", ctypes.c_int32), ("inner_reduction", ctypes.c_double),
-                ("run_cap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("run_cap", ctypes.c_int32), ("class_shapes", ctypes.c_int32)]
+
+
+# Size classes of an FP64 Bi-CGSTAB engine with per-class launch shapes (gsk_engine_config):
+# 2D stencils and CSR, 3D stencils under 2^18 rows, larger 3D stencils; and the shape codes.
+SIZE_CLASSES = ("2d", "3d_small", "3d_large")
+CLASS_LARGE_ROWS = 1 << 18
+SHAPE_TILE, SHAPE_PAIR_TILE_U, SHAPE_PAIR = 1, 2, 3
+SHAPES = {"tile": SHAPE_TILE, "pair_tile_u": SHAPE_PAIR_TILE_U, "pair": SHAPE_PAIR}
+
+
+def size_class(A) -> str:
+    """The size class of a matrix in an engine with per-class shapes."""
+    if isinstance(A, StencilMatrix) and A.nz > 1:
+        return "3d_large" if A.n >= CLASS_LARGE_ROWS else "3d_small"
+    return "2d"
+
+
+def encode_class_shapes(shapes) -> int:
+    """{class name: shape name or code} -> gsk_engine_config.class_shapes."""
+    code = 0
+    for c, v in (shapes or {}).items():
+        k = SIZE_CLASSES.index(c)
+        code |= (SHAPES[v] if isinstance(v, str) else int(v)) << (4 * k)
+    return code
 
 
 class EngineRequest(ctypes.Structure):
@@ -526,7 +550,7 @@ class Engine:
     def __init__(self, max_rows: int, max_systems: int, check_every: int = 8,
                  graph: bool = False, device="cuda", stream=None, method: str = "bicgstab",
                  m: int = 20, precision: str = "fp64", inner_reduction: float = 0.0,
-                 tile_units: int = 0, run_cap: int = 0):
+                 tile_units: int = 0, run_cap: int = 0, class_shapes=None):
         self.device = torch.device(device)
         self.stream = stream if stream is not None else (
             torch.cuda.Stream(self.device) if graph else torch.cuda.current_stream(self.device))
@@ -539,7 +563,8 @@ class Engine:
                            self.m if method == "gmres" else 0,
                            PRECISION_MIXED if self.mixed else PRECISION_FP64,
                            int(check_every), ENGINE_GRAPH if graph else 0, int(tile_units),
-                           float(inner_reduction), int(run_cap), 0)
+                           float(inner_reduction), int(run_cap),
+                           encode_class_shapes(class_shapes))
         nbytes = int(lib.gsk_engine_workspace_bytes_ex(ctypes.byref(cfg)))
         if nbytes == 0:
             raise GskError(ERR_INVALID_ARG, "no engine workspace size for this configuration")

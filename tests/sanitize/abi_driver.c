@@ -76,6 +76,15 @@ int main(void) {
     CHECK(gsk_engine_workspace_bytes_ex(&c) == 0);
     c.tile_units = 0;
     CHECK(gsk_engine_workspace_bytes_ex(&c) > 0);
+    c.class_shapes = 0x321;   /* per-class shapes: FP64 Bi-CGSTAB only */
+    CHECK(gsk_engine_workspace_bytes_ex(&c) == 0);
+    c.method = GSK_METHOD_BICGSTAB;
+    c.precision = GSK_PRECISION_FP64;
+    CHECK(gsk_engine_workspace_bytes_ex(&c) > 0);
+    c.class_shapes = 0x5;
+    CHECK(gsk_engine_workspace_bytes_ex(&c) == 0);
+    c.class_shapes = 0;
+    c.method = GSK_METHOD_GMRES;
     gsk_engine* e = NULL;
     CHECK(gsk_engine_create_ex(NULL, dummy, 8, NULL, &e) == GSK_ERR_INVALID_ARG && e == NULL);
     CHECK(gsk_engine_create_ex(&c, dummy, 8, NULL, &e) == GSK_ERR_WORKSPACE && e == NULL);

@@ -199,7 +199,8 @@ def test_struct_layouts_match_the_header(lib, tmp_path):
                                                "free_rows", "largest_free_rows"]),
         "gsk_engine_config": (lib.EngineConfig, ["max_rows", "max_systems", "method", "m",
                                                  "precision", "check_every", "flags",
-                                                 "tile_units", "inner_reduction"]),
+                                                 "tile_units", "inner_reduction", "run_cap",
+                                                 "class_shapes"]),
         "gsk_engine_request": (lib.EngineRequest, ["A", "b", "x", "tol", "opt", "tag", "gs_p",
                                                    "val_out", "b_out", "stop_weight_out",
                                                    "mat32", "mat32_ld"]),
@@ -238,6 +239,11 @@ def test_engine_config_rejections(lib):
         lib.EngineConfig(4096, 4, lib.METHOD_BICGSTAB, 0, 1, 8, 0, 2, 0.0),   # 2 tiles, mixed
         lib.EngineConfig(0, 4, lib.METHOD_BICGSTAB, 0, 0, 8, 0, 0, 0.0),      # no rows
         lib.EngineConfig(4096, 4, lib.METHOD_BICGSTAB, 0, 7, 8, 0, 0, 0.0),   # precision
+        # per-class shapes: FP64 Bi-CGSTAB only, codes 0..3, three classes
+        lib.EngineConfig(4096, 4, lib.METHOD_GMRES, 20, 0, 8, 0, 0, 0.0, 0, 0x3),
+        lib.EngineConfig(4096, 4, lib.METHOD_BICGSTAB, 0, 1, 8, 0, 0, 0.0, 0, 0x3),
+        lib.EngineConfig(4096, 4, lib.METHOD_BICGSTAB, 0, 0, 8, 0, 0, 0.0, 0, 0x4),
+        lib.EngineConfig(4096, 4, lib.METHOD_BICGSTAB, 0, 0, 8, 0, 0, 0.0, 0, 0x1000),
     ]
     h = ctypes.c_void_p()
     for cfg in bad:
@@ -246,6 +252,11 @@ def test_engine_config_rejections(lib):
                                       ctypes.byref(h)) == lib.ERR_INVALID_ARG
     assert L.gsk_engine_create_ex(None, 0x100000, 1 << 30, None, ctypes.byref(h)) == \
         lib.ERR_INVALID_ARG
+    # per-class shapes hand out rows in pairs of tiles and keep one unit list per class
+    one = lib.EngineConfig(4096, 4, lib.METHOD_BICGSTAB, 0, 0, 8, 0, 0, 0.0, 0, 0)
+    three = lib.EngineConfig(4096, 4, lib.METHOD_BICGSTAB, 0, 0, 8, 0, 0, 0.0, 0, 0x321)
+    assert L.gsk_engine_workspace_bytes_ex(ctypes.byref(three)) >= \
+        L.gsk_engine_workspace_bytes_ex(ctypes.byref(one)) > 0
     # a valid configuration with too small a workspace fails before any device work
     assert L.gsk_engine_create_ex(ctypes.byref(good), 0x100000, 256, None,
                                   ctypes.byref(h)) == lib.ERR_WORKSPACE

@@ -279,3 +279,43 @@ def test_batch512_real_sizes_equal_solo(G, tile_units):
     for k in ref:
         same((host(xs[k]), done[k]), ref[k])
     eng.close()
+
+
+def test_engine_beyond_the_cache_equals_solo(G):
+    """The 14 largest 3D systems of the 512-system workload (about 11 M rows, over 600 MB of
+    engine vectors: far beyond the 256 MB last-level cache) in one engine with per-class
+    launch shapes, as the benchmark runs them. Each result must equal bit for bit what the
+    single solver gives for that system alone."""
+    import torch
+    specs = problems.batch_specs(512)
+    sizes = [int(np.prod(s["dims"])) for s in specs]
+    pick = sorted((i for i, s in enumerate(specs) if len(s["dims"]) == 3),
+                  key=sizes.__getitem__)[-14:]
+    rows = sum(-(-sizes[i] // 512) * 512 for i in pick)
+    assert 7 * 8 * rows > 2 * 256 * 2 ** 20
+    eng = G.Engine(max_rows=rows, max_systems=len(pick), check_every=16, graph=True,
+                   class_shapes={"2d": "pair", "3d_small": "pair_tile_u",
+                                 "3d_large": "pair_tile_u"})
+    ref, xs, keep = {}, {}, []
+    for k, i in enumerate(pick):
+        P = problems.batch_system(specs[i])
+        A, b = G.CsrMatrix.from_problem(P), dev(P.b)
+        As, bs, _, _ = G.gs_scale(A, b, 2)
+        x, info = G.bicgstab(G.stencil_from_csr(As, *grid_of(P)), bs, tol=1e-8)
+        ref[k] = (host(x), info)
+        del As, bs, x
+        xs[k] = torch.zeros_like(b)
+        S = G.stencil_from_csr(A, *grid_of(P))
+        keep.append((S, b))
+        assert eng.submit_gs(S, b, xs[k], p=2, tol=1e-8, tag=k)
+    done = {}
+    for _ in range(5000):
+        eng.run(1)
+        done.update(dict(eng.poll()))
+        if len(done) == len(pick):
+            break
+    torch.cuda.synchronize()
+    assert len(done) == len(pick)
+    for k in ref:
+        same((host(xs[k]), done[k]), ref[k])
+    eng.close()

@@ -30,10 +30,11 @@ def batch(G, count=6):
     return out
 
 
-def solve(G, systems, k, units=0):
+def solve(G, systems, k, units=0, class_shapes=None):
     import torch
     rows = sum((s["n"] + 511) // 512 * 512 for s in systems)
-    eng = G.Engine(rows, len(systems), check_every=k, graph=True, tile_units=units)
+    eng = G.Engine(rows, len(systems), check_every=k, graph=True, tile_units=units,
+                   class_shapes=class_shapes)
     xs = [torch.zeros_like(s["b"]) for s in systems]
     for i, s in enumerate(systems):
         assert eng.submit_gs(s["S"], s["b"], xs[i], p=2, tol=1e-10, tag=i)
@@ -86,3 +87,38 @@ def test_engine_tuner_covers_shapes(G):
     assert t["best"] in ((1, 8), (2, 8)) and set(t["seconds"]) == {(1, 8), (2, 8)}
     with pytest.raises(G.GskError):
         G.Engine(1024, 2, method="gmres", tile_units=2)
+
+
+def test_class_shapes_do_not_change_results(G):
+    """Per-size-class launch shapes (each class its own launches, rows in pairs of tiles) give
+    the bits of the one-shape engine, for every shape in every class: small 2D and 3D
+    stencils, a CSR matrix, a 3D stencil above the large-class bound, ragged sizes."""
+    import torch
+    systems = batch(G, 8)
+    P = problems.laplacian((30, 27), conv=(20.0, 5.0))
+    systems.append({"S": G.CsrMatrix.from_problem(P), "b": torch.from_numpy(P.b).cuda(),
+                    "n": P.n})
+    P = problems.laplacian((66, 64, 63), conv=(10.0, -5.0, 3.0))
+    assert P.n >= G.CLASS_LARGE_ROWS
+    A = G.CsrMatrix.from_problem(P)
+    systems.append({"S": G.stencil_from_csr(A, 66, 64, 63), "b": torch.from_numpy(P.b).cuda(),
+                    "n": P.n})
+    classes = {G.size_class(s["S"]) for s in systems}
+    assert classes == set(G.SIZE_CLASSES)
+    x0, r0 = solve(G, systems, 8, units=1)
+    for shapes in ({"2d": "tile", "3d_small": "pair_tile_u", "3d_large": "pair"},
+                   {"2d": "pair", "3d_small": "tile", "3d_large": "pair_tile_u"},
+                   {"3d_large": "tile"}):
+        x, r = solve(G, systems, 8, class_shapes=shapes)
+        assert r == r0, shapes
+        for a, b in zip(x0, x):
+            assert np.array_equal(a, b), shapes
+
+
+def test_class_shapes_argument_checks(G):
+    with pytest.raises(G.GskError):
+        G.Engine(1024, 2, method="gmres", class_shapes={"2d": "pair"})
+    with pytest.raises(G.GskError):
+        G.Engine(1024, 2, precision="mixed", class_shapes={"2d": "pair"})
+    with pytest.raises(G.GskError):
+        G.Engine(1024, 2, class_shapes={"2d": 4})
