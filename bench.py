@@ -56,22 +56,41 @@ KERNEL_NAMES = {"gmres_a": "k_gmres_a (matrix product + CGS2 pass-1 dots)",
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; FETCH_SIZE scaled by 2.000 and WRITE_SIZE by
 # 1.000 from a plain 512 MiB copy), recorded with the hash of the kernel sources they were
 # measured on. A source change makes the figure stale and it is reported as null.
-TRAFFIC = {"gmres_a": {"bytes_per_launch": 96161325, "grid": 80, "operator": "stencil",
-                       "sources_sha256_16": "ba7a51460425de28"}}
-TRAFFIC_SOURCES = ["paper_0812_2769_amd/csrc/gmres.hip", "paper_0812_2769_amd/csrc/gmres_body.hpp",
-                   "paper_0812_2769_amd/csrc/gsk_dev.hpp"]
+TRAFFIC = {
+    # FETCH_SIZE (x 2.000, calibrated on a copy) + WRITE_SIZE per working launch, 80^3 slabs
+    "gmres_a": {"bytes_per_launch": 96161325, "grid": 80, "operator": "stencil",
+                "sources": ["paper_0812_2769_amd/csrc/gmres.hip",
+                            "paper_0812_2769_amd/csrc/gmres_body.hpp",
+                            "paper_0812_2769_amd/csrc/gsk_dev.hpp"],
+                "sources_sha256_16": "ba7a51460425de28"},
+    # the batch engine's P launches of the 512-system batch: measured over the full-batch
+    # launches of the first chunk (profiles/k_batch_p_batch_512systems_hbm_counters.md) as a
+    # ratio to their algorithmic bytes
+    "batch_p": {"ratio": 8.536 / 8.491, "grid": None, "operator": "stencil",
+                "sources": ["paper_0812_2769_amd/csrc/batch.hip",
+                            "paper_0812_2769_amd/csrc/bicg_batch.hpp",
+                            "paper_0812_2769_amd/csrc/batch.hpp",
+                            "paper_0812_2769_amd/csrc/gsk_dev.hpp"],
+                "sources_sha256_16": "e84ba41c6bc4dc52"},
+}
 
 
-def traffic_for(probe, grid, operator):
+def traffic_for(probe, grid, operator, bytes_per_launch=None):
+    """Counter-measured HBM bytes per launch of the probed class, or None when no record
+    matches the workload or the kernel sources have changed since the counters were taken."""
     import hashlib
     rec = TRAFFIC.get(probe)
     if rec is None or rec["grid"] != grid or rec.get("operator", "csr") != operator:
         return None
     h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
+    for f in rec["sources"]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    return rec["bytes_per_launch"] if h.hexdigest()[:16] == rec["sources_sha256_16"] else None
+    if h.hexdigest()[:16] != rec["sources_sha256_16"]:
+        return None
+    if "ratio" in rec:
+        return None if bytes_per_launch is None else int(rec["ratio"] * bytes_per_launch)
+    return rec["bytes_per_launch"]
 
 
 def parse(argv=None):
@@ -95,6 +114,10 @@ def parse(argv=None):
                     help="batch512: iterations per chunk instead of measuring")
     ap.add_argument("--no-tune", action="store_true",
                     help="batch512: one tile per workgroup and chunks of 8 instead of measuring")
+    ap.add_argument("--class-shapes", default="",
+                    help="batch512 (FP64 Bi-CGSTAB): launch shape per size class instead of "
+                         "measuring, e.g. 2d=pair,3d_small=pair_tile_u,3d_large=pair_tile_u "
+                         "(chunks of --chunk, default 16)")
     ap.add_argument("--batch-method", choices=["bicgstab", "gmres"], default="bicgstab",
                     help="batch512: the engine's solver (GMRES(20) with --precision)")
     ap.add_argument("--batch-count", type=int, default=512,
@@ -329,7 +352,12 @@ def bench_batch(args, gsk, problems, dev):
     unit = 512 if mixed else 256
     tuned = None
     check_every, tile_units, class_shapes = 8, 0, None
-    if args.tile_units or args.chunk:
+    if args.class_shapes and not gmres and not mixed:
+        class_shapes = dict(kv.split("=") for kv in args.class_shapes.split(","))
+        check_every = args.chunk or 16
+        tuned = {"engine": "FP64 Bi-CGSTAB: launch shapes per size class given on the command "
+                           "line", "class_shapes": class_shapes, "chunk": check_every}
+    elif args.tile_units or args.chunk:
         tile_units, check_every = args.tile_units or 1, args.chunk or 8
     elif not gmres and not args.no_tune:
         # launch shapes and chunk length measured on the batch, before (and outside) the timing
@@ -463,12 +491,16 @@ def bench_batch(args, gsk, problems, dev):
     }
     a = achieved(pr)
     if a is not None:
+        traffic = (traffic_for(probe, None, "stencil", a["bytes_per_launch"])
+                   if not gmres and not mixed else None)
         out["roofline"] = roofline_of(
-            a, probe, args.probe_every,
+            a, probe, args.probe_every, traffic=traffic,
             note=("achieved = algorithmic bytes of the timed launches (per running system at "
                   "that stage, the kernel-class table in gsk.h) / their HIP-event durations; "
                   "every k-th chunk of the timed steps runs without its graph and times each "
-                  "launch of the class"))
+                  "launch of the class; traffic = the counter-measured ratio of HBM bytes to "
+                  "algorithmic bytes of this class (FETCH_SIZE x 2.000 + WRITE_SIZE, full-batch "
+                  "launches) times bytes_per_launch, null once the kernel sources change"))
     eng.close()
     if acc_sample:
         import oracle
