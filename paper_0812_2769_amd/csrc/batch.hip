@@ -851,18 +851,29 @@ static void launch_stream(Engine& e, F kernel, int kc, int probed, dim3 grid, co
                        slot, e.d_probe);
 }
 
-// Streaming grid of each size class's unit list (0: the class has no systems).
+// Non-temporal policy of a GMRES chunk: the admitted systems' cycle working set (m + 2
+// vectors of their rows, FP64 or FP32) exceeds the 256 MB last-level cache, so it streams from
+// HBM once per launch whatever the policy.
+static int gmres_streams(const Engine& e) {
+  if (e.method != 1) return 0;
+  const double rows = (double)e.n_listed[0] * e.rv * BS;
+  return (double)(e.m + 2) * rows * (e.mixed ? 4.0 : 8.0) > kStreamBytes ? 1 : 0;
+}
+
+// Streaming grid of each size class's unit list (0: the class has no systems), then the GMRES
+// load policy: what a captured chunk depends on.
 static std::vector<int> class_grids(const Engine& e) {
-  std::vector<int> g(e.nclass, 0);
+  std::vector<int> g(e.nclass + 1, 0);
   for (int c = 0; c < e.nclass; ++c)
     g[c] = e.n_listed[c] > 0 || e.nclass == 1 ? stream_grid(e.n_listed[c]) : 0;
+  g[e.nclass] = gmres_streams(e);
   return g;
 }
 
 static void enqueue_chunk(Engine& e, int k, int64_t first_iter, const std::vector<int>& grids,
                           int probed = 0) {
   if (e.method == 1) {
-    (void)launch_gmres_chunk(e.gargs, e.m, grids[0], e.max_sys, e.column, e.s);
+    (void)launch_gmres_chunk(e.gargs, e.m, grids[0], e.max_sys, e.column, grids[1] != 0, e.s);
     return;
   }
   if (e.mixed) {

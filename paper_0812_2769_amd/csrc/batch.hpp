@@ -137,9 +137,11 @@ hipError_t launch_bicg_mixed_chunk(MArgs a, int k, int64_t first_iter, int grid,
 
 // Enqueues one GMRES chunk (one cycle of m steps for every running system, with the
 // preparation, start, x update and restart launches around it) with streaming grid `grid`.
-// column: the basis fits one buffer descriptor (under 2^31 bytes).
+// column: the basis fits one buffer descriptor (under 2^31 bytes). nt: the admitted systems'
+// cycle working set exceeds the last-level cache (non-temporal basis and plane loads, and the
+// LDS-window product for FP64 stencils; the same bits).
 hipError_t launch_gmres_chunk(const GArgs& a, int m, int grid, int max_sys, bool column,
-                              hipStream_t s);
+                              bool nt, hipStream_t s);
 
 // Initial control block of an admitted GMRES system.
 hipError_t launch_gmres_init(Ctl* c, int maxit, int m, double tol, double eps_b, int has_w,

@@ -151,10 +151,18 @@ __device__ inline size_t inner_ldp(const SysDesc& d) {
 // A_j. A stencil product takes the unit's RV tiles at once (partials per unit); a CSR product
 // stages one tile at a time through LDS (partials per tile), as in the single solver. jexp:
 // the step counter of a running step (j, or j-1 when FC_{j-1} runs after A_j).
-template <int JM, class R, class T>
+// NT: the engine's admitted working set streams from HBM (see launch_gmres_chunk); the basis
+// and the coefficient planes are then loaded non-temporally, and FP64 stencil products gather
+// through the LDS window of StencilWinOpT. The bits are the same either way.
+template <int JM, class R, class T, bool NT>
 __global__ __launch_bounds__(BS) void k_bg_a(GArgs a, int j, int jexp) {
   constexpr int RV = rpt_of<T>();
-  __shared__ TileLds L;
+  constexpr bool kWindow = NT && RV == 1;
+  union Lds {
+    TileLds csr;
+    typename StencilWinOpT<double, NT>::Lds win;
+  };
+  __shared__ Lds L;
   __shared__ double red[NC_MAX * WAVES];
   __shared__ double red1[WAVES];
   on_unit(a, [&](int unit, int s) {
@@ -165,11 +173,21 @@ __global__ __launch_bounds__(BS) void k_bg_a(GArgs a, int j, int jexp) {
     const T zero = (T)a.zero;
     const int u = unit - d.unit_off;
     if (d.kind == MAT_STENCIL) {
+      if constexpr (kWindow) {
+        if (d.nx <= kWinNx) {
+          const StencilWinOpT<double, NT> op{inner_coef<T>(d), d.n, d.nx, d.ny, d.nz,
+                                             inner_ldp<T>(d)};
+          gmres_a_tile<JM, RV, R, StencilWinOpT<double, NT>, T>(
+              c, op, d.n, V, a.ldv, w, j, jexp, u, a.partials + d.unit_off, a.pstride, zero,
+              -1, 0.0, L.win, red, red1);
+          return;
+        }
+      }
       EmptyLds e;
-      const StencilOpT<T> op{inner_coef<T>(d), d.n, d.nx, d.ny, d.nz, inner_ldp<T>(d)};
-      gmres_a_tile<JM, RV, R, StencilOpT<T>, T>(c, op, d.n, V, a.ldv, w, j, jexp, u,
-                                                a.partials + d.unit_off, a.pstride, zero, -1,
-                                                0.0, e, red, red1);
+      const StencilOpT<T, NT> op{inner_coef<T>(d), d.n, d.nx, d.ny, d.nz, inner_ldp<T>(d)};
+      gmres_a_tile<JM, RV, R, StencilOpT<T, NT>, T>(c, op, d.n, V, a.ldv, w, j, jexp, u,
+                                                    a.partials + d.unit_off, a.pstride, zero,
+                                                    -1, 0.0, e, red, red1);
     } else {
       const CsrOpT<T> op{d.rp, d.ci, inner_val<T>(d)};
 #pragma unroll
@@ -179,7 +197,7 @@ __global__ __launch_bounds__(BS) void k_bg_a(GArgs a, int j, int jexp) {
         if (q) __syncthreads();
         gmres_a_tile<JM, 1, R, CsrOpT<T>, T>(c, op, d.n, V, a.ldv, w, j, jexp, lt,
                                              a.partials + d.tile_off, a.pstride, zero, -1, 0.0,
-                                             L, red, red1);
+                                             L.csr, red, red1);
       }
     }
   });
@@ -284,7 +302,7 @@ __global__ __launch_bounds__(64) void k_bg_sums(GArgs a) {
 
 static int pick_jm(int cols) { return cols <= 8 ? 8 : cols <= 16 ? 16 : cols <= 32 ? 32 : 64; }
 
-template <class R, class T>
+template <class R, class T, bool NT>
 static hipError_t gmres_chunk(const GArgs& a, int m, int grid, int max_sys, hipStream_t s) {
   const dim3 gt(grid), gs(max_sys), block(BS);
   hipLaunchKernelGGL(k_bg_prepare<T>, gt, block, 0, s, a);
@@ -293,7 +311,7 @@ static hipError_t gmres_chunk(const GArgs& a, int m, int grid, int max_sys, hipS
   hipLaunchKernelGGL(k_bg_fin_residual, gs, block, 0, s, a);
   for (int j = 0; j < m; ++j) {
 #define GSK_BG_STEP(JMV)                                                                     \
-  hipLaunchKernelGGL((k_bg_a<JMV, R, T>), gt, block, 0, s, a, j, j > 0 ? j - 1 : 0);         \
+  hipLaunchKernelGGL((k_bg_a<JMV, R, T, NT>), gt, block, 0, s, a, j, j > 0 ? j - 1 : 0);     \
   if (j > 0)                                                                                 \
     hipLaunchKernelGGL(k_bg_fin_ca<T>, dim3(max_sys, j + 3), block, 0, s, a, j);             \
   else                                                                                       \
@@ -317,14 +335,22 @@ static hipError_t gmres_chunk(const GArgs& a, int m, int grid, int max_sys, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_gmres_chunk(const GArgs& a, int m, int grid, int max_sys, bool column,
-                              hipStream_t s) {
+template <bool NT>
+static hipError_t gmres_chunk_nt(const GArgs& a, int m, int grid, int max_sys, bool column,
+                                 hipStream_t s) {
   if (a.mixed) {
-    if (column) return gmres_chunk<ColumnReaderT<float>, float>(a, m, grid, max_sys, s);
-    return gmres_chunk<PointerReaderT<float>, float>(a, m, grid, max_sys, s);
+    if (column)
+      return gmres_chunk<ColumnReaderT<float, NT>, float, NT>(a, m, grid, max_sys, s);
+    return gmres_chunk<PointerReaderT<float, NT>, float, NT>(a, m, grid, max_sys, s);
   }
-  if (column) return gmres_chunk<ColumnReader, double>(a, m, grid, max_sys, s);
-  return gmres_chunk<PointerReader, double>(a, m, grid, max_sys, s);
+  if (column) return gmres_chunk<ColumnReaderT<double, NT>, double, NT>(a, m, grid, max_sys, s);
+  return gmres_chunk<PointerReaderT<double, NT>, double, NT>(a, m, grid, max_sys, s);
+}
+
+hipError_t launch_gmres_chunk(const GArgs& a, int m, int grid, int max_sys, bool column,
+                              bool nt, hipStream_t s) {
+  return nt ? gmres_chunk_nt<true>(a, m, grid, max_sys, column, s)
+            : gmres_chunk_nt<false>(a, m, grid, max_sys, column, s);
 }
 
 hipError_t launch_gmres_init(Ctl* c, int maxit, int m, double tol, double eps_b, int has_w,

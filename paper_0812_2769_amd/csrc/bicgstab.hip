@@ -21,7 +21,9 @@
 // r = b - A x for the initial residual and for every verification of a recursive
 // convergence claim; a failed verification restarts the recurrence from the true residual.
 #include <mutex>
+#include <type_traits>
 
+#include "bicg_batch.hpp"   // the LDS-window workgroup bodies shared with the batch engine
 #include "gsk_host.hpp"
 
 namespace gsk {
@@ -257,6 +259,146 @@ __global__ __launch_bounds__(BS) void k_bicg_p(BArgs a, Op op) {
   block_partials<2>(acc, 2, a.partials, nb, lb, red);
 }
 
+// ---------------------------------------------------------------------------------------
+// P and S for a stencil matrix through the LDS window of the batch engine's bodies: one
+// workgroup per two tiles; the gathered values of the tiles' rows and one x-line on either
+// side are formed once into LDS, rows read in 16-byte pairs where n and nx are even. Every
+// tile's partials are reduced in the order of the one-tile kernels above, so the results are
+// the same bits. The control words are read first and tested after the window is formed (its
+// loads are clamped, valid addresses in any state). Partial slots of tiles past the matrix
+// (the partial stride nb is the tile grid) are written as zeros, as the one-tile kernels do.
+// ---------------------------------------------------------------------------------------
+constexpr int kWindowRows = 1 << 20;   // systems from this size on take the window kernels
+
+__device__ inline SysDesc window_sys(const StencilOp& op, const double* W) {
+  SysDesc d{};
+  d.n = op.n;
+  d.kind = MAT_STENCIL;
+  d.nx = op.nx;
+  d.ny = op.ny;
+  d.nz = op.nz;
+  d.coef = op.coef;
+  d.W = W;
+  return d;
+}
+
+template <int NC>
+__device__ inline void zero_tail_partials(double* partials, int nb, int tiles, int lt0) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int tile = lt0 + k;
+    if (tile >= tiles && tile < nb && threadIdx.x < NC)
+      partials[(size_t)threadIdx.x * nb + tile] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(BS) void k_bicg_p_win(BArgs a, StencilOp op, int nb) {
+  __shared__ UnitLds U;
+  __shared__ double red[NC_MAX * WAVES];
+  Ctl* c = a.ctl;
+  const int state = c->sum.state, first = c->first;
+  const double beta = c->beta, omega = c->omega;
+  const int q = a.par;
+  const GatherPB G{a.r, a.p[q], a.v[q], beta, omega, first};
+  const SysDesc d = window_sys(op, nullptr);
+  const int tiles = (a.n + BS - 1) / BS;
+  const int lt0 = 2 * logical_block();
+  if (lt0 >= tiles) {
+    if (state == ST_RUNNING) zero_tail_partials<2>(a.partials, nb, tiles, lt0);
+    return;
+  }
+  const int R0 = lt0 * BS, nu = min(2 * BS, a.n - R0);
+  const bool pair = unit_pairs(d, nullptr);
+  int row[2];
+  bool ok[2];
+  double y[2], gv[2];
+  unit_window(d, R0, nu, pair, G, U.g, row, ok, y, gv);
+  double rh[2];
+  if (pair) {
+    const double2 r2 = ld2(a.rh + row[0]);
+    rh[0] = r2.x;
+    rh[1] = r2.y;
+  } else {
+    rh[0] = a.rh[row[0]];
+    rh[1] = a.rh[row[1]];
+  }
+  if (state != ST_RUNNING) return;
+  mark_work(c, a.pslot, a.mat_bytes + 8.0 * a.n * (first ? 4 : 6));
+  double acc[2][2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    acc[h][0] = ok[h] ? rh[h] * y[h] : 0.0;
+    acc[h][1] = ok[h] ? y[h] * y[h] : 0.0;
+  }
+  if (pair) {
+    if (ok[0]) {
+      *reinterpret_cast<double2*>(a.p[q ^ 1] + row[0]) = double2{gv[0], gv[1]};
+      *reinterpret_cast<double2*>(a.v[q ^ 1] + row[0]) = double2{y[0], y[1]};
+    }
+  } else {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      if (ok[h]) {
+        a.p[q ^ 1][row[h]] = gv[h];
+        a.v[q ^ 1][row[h]] = y[h];
+      }
+  }
+  unit_partials<2>(pair, acc, U.acc, min(2, tiles - lt0), a.partials, nb, lt0, red);
+  zero_tail_partials<2>(a.partials, nb, tiles, lt0);
+}
+
+__global__ __launch_bounds__(BS) void k_bicg_s_win(BArgs a, StencilOp op, int nb) {
+  __shared__ UnitLds U;
+  __shared__ double red[NC_MAX * WAVES];
+  Ctl* c = a.ctl;
+  const int state = c->sum.state;
+  const GatherSB G{a.r, a.v[a.par ^ 1], c->alpha};   // the v written by P in this iteration
+  const SysDesc d = window_sys(op, a.W);
+  const int tiles = (a.n + BS - 1) / BS;
+  const int lt0 = 2 * logical_block();
+  if (lt0 >= tiles) {
+    if (state == ST_RUNNING) zero_tail_partials<4>(a.partials, nb, tiles, lt0);
+    return;
+  }
+  const int R0 = lt0 * BS, nu = min(2 * BS, a.n - R0);
+  const bool pair = unit_pairs(d, a.W);
+  int row[2];
+  bool ok[2];
+  double y[2], sv[2];
+  unit_window(d, R0, nu, pair, G, U.g, row, ok, y, sv);
+  double wv[2] = {0.0, 0.0};
+  if (a.W) {
+    if (pair) {
+      const double2 w2 = ld2(a.W + row[0]);
+      wv[0] = w2.x;
+      wv[1] = w2.y;
+    } else {
+      wv[0] = a.W[row[0]];
+      wv[1] = a.W[row[1]];
+    }
+  }
+  if (state != ST_RUNNING) return;
+  mark_work(c, a.pslot, a.mat_bytes + 8.0 * a.n * (a.W ? 4 : 3));
+  double acc[2][4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    acc[h][0] = ok[h] ? y[h] * sv[h] : 0.0;
+    acc[h][1] = ok[h] ? y[h] * y[h] : 0.0;
+    acc[h][2] = ok[h] ? sv[h] * sv[h] : 0.0;
+    const double ws = wv[h] * sv[h];
+    acc[h][3] = ok[h] && a.W ? ws * ws : 0.0;
+  }
+  if (pair) {
+    if (ok[0]) *reinterpret_cast<double2*>(a.t + row[0]) = double2{y[0], y[1]};
+  } else {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      if (ok[h]) a.t[row[h]] = y[h];
+  }
+  unit_partials<4>(pair, acc, U.acc, min(2, tiles - lt0), a.partials, nb, lt0, red);
+  zero_tail_partials<4>(a.partials, nb, tiles, lt0);
+}
+
 // FP: alpha = rho / (r^, v), or breakdown. (The finalize launches read their control words
 // together with the partials, one memory round trip, and only the stores depend on them.)
 __global__ __launch_bounds__(BS) void k_bicg_fin_p(Ctl* c, const double* partials, int nb) {
@@ -437,11 +579,27 @@ static void launch_iteration(const BArgs& a, const Op& op, int nb, int par, hipS
   const double* pt = a.partials;
   BArgs ax = a;
   ax.par = par;
+  // the window kernels for large systems; small ones are bound by launch latency, where the
+  // one-tile kernels' speculative loads are faster (the bits are the same either way)
+  bool window = false;
+  if constexpr (std::is_same_v<Op, StencilOp>)
+    window = op.ldp == (size_t)op.n && op.nx <= WIN_NX && op.n >= kWindowRows;
+  const dim3 gw(grid_for(a.n, 2));
   ax.pslot = probe ? probe_slot(KC_BICG_P) : -1;
-  launch_probed(k_bicg_p<Op>, dim3(nb), s, ax.pslot, ax, op);
+  if constexpr (std::is_same_v<Op, StencilOp>) {
+    if (window) launch_probed(k_bicg_p_win, gw, s, ax.pslot, ax, op, nb);
+    else launch_probed(k_bicg_p<Op>, dim3(nb), s, ax.pslot, ax, op);
+  } else {
+    launch_probed(k_bicg_p<Op>, dim3(nb), s, ax.pslot, ax, op);
+  }
   hipLaunchKernelGGL(k_bicg_fin_p, dim3(1), dim3(BS), 0, s, a.ctl, pt, nb);
   ax.pslot = probe ? probe_slot(KC_BICG_S) : -1;
-  launch_probed(k_bicg_s<Op>, dim3(nb), s, ax.pslot, ax, op);
+  if constexpr (std::is_same_v<Op, StencilOp>) {
+    if (window) launch_probed(k_bicg_s_win, gw, s, ax.pslot, ax, op, nb);
+    else launch_probed(k_bicg_s<Op>, dim3(nb), s, ax.pslot, ax, op);
+  } else {
+    launch_probed(k_bicg_s<Op>, dim3(nb), s, ax.pslot, ax, op);
+  }
   hipLaunchKernelGGL(k_bicg_fin_s, dim3(1), dim3(BS), 0, s, a.ctl, pt, nb, hw);
   ax.pslot = probe ? probe_slot(KC_BICG_U) : -1;
   launch_probed(k_bicg_u, dim3(nb), s, ax.pslot, ax);

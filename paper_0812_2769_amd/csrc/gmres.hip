@@ -533,6 +533,12 @@ SolveResult gmres_solve(const Mat& A, const double* b, double* x, int m, const S
   if (A.kind == MAT_STENCIL) {
     const StencilOp op = A.stencil_op();
     if (nt) {
+      // a streamed working set: the Arnoldi product gathers through the LDS window (the same
+      // bits as the plain stencil product)
+      if (A.nx <= kWinNx) {
+        const StencilWinOpT<double, true> opw{A.coef, A.n, A.nx, A.ny, A.nz, (size_t)A.n};
+        return gmres_dispatch_nt<true>(A, op, opw, b, x, m, prm, ws, s);
+      }
       const StencilOpT<double, true> opn{A.coef, A.n, A.nx, A.ny, A.nz, (size_t)A.n};
       return gmres_dispatch_nt<true>(A, op, opn, b, x, m, prm, ws, s);
     }

@@ -687,6 +687,90 @@ struct StencilOpT {
 
 using StencilOp = StencilOpT<double>;
 
+// The same product with the gathered vector's x and y neighbours read from an LDS window: the
+// tile's rows and one x-line on either side (clipped to the matrix) are loaded once and
+// formed into LDS; a row takes -y, -x, centre, +x and +y from there and gathers only -z and +z
+// from global memory. One tile per workgroup (one row per thread), x-lines of at most kWinNx
+// points; finish() holds a workgroup barrier, so every thread of the workgroup calls it. Each
+// row is summed in position order with the roundings of StencilOpT: the same bits.
+constexpr int kWinNx = 256;
+
+template <class V, bool NT = false>
+struct StencilWinOpT {
+  const V* coef;
+  int n, nx, ny, nz;
+  size_t ldp;
+  struct Lds {
+    double g[BS + 2 * kWinNx];
+  };
+  static constexpr bool kRowwise = true;
+  static constexpr int kWin = (BS + 2 * kWinNx) / BS;   // window loads per thread
+  template <class G>
+  struct Pre {
+    V c[7];
+    typename G::Raw z[2];
+    typename G::Raw w[kWin];
+    unsigned present;
+    int i, w0, wn;
+  };
+  template <class G>
+  __device__ Pre<G> load(int row0, int nrows, const G& g) const {
+    Pre<G> p;
+    const int t = threadIdx.x;
+    const int i = min(row0 + max(0, min(t, nrows - 1)), n - 1);
+    const int ix = i % nx;
+    const int rest = i / nx;
+    const int iy = rest % ny;
+    const int iz = rest / ny;
+    const int nxy = nx * ny;
+    const bool three = nz > 1;
+    const bool in[7] = {three && iz > 0, iy > 0,      ix > 0, true,
+                        ix < nx - 1,     iy < ny - 1, three && iz < nz - 1};
+    p.present = 0;
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+      const int plane = three ? q : (q == 0 ? 0 : q == 6 ? 4 : q - 1);
+      if constexpr (NT) p.c[q] = __builtin_nontemporal_load(coef + (size_t)plane * ldp + i);
+      else p.c[q] = coef[(size_t)plane * ldp + i];
+      p.present |= in[q] ? 1u << q : 0u;
+    }
+    p.z[0] = g.load(max(i - nxy, 0));
+    p.z[1] = g.load(min(i + nxy, n - 1));
+    const int r0 = min(row0, n - 1);
+    p.w0 = max(0, r0 - nx);
+    p.wn = min(n, r0 + BS + nx) - p.w0;
+#pragma unroll
+    for (int k = 0; k < kWin; ++k) p.w[k] = g.load(p.w0 + min(k * BS + t, p.wn - 1));
+    p.i = i;
+    return p;
+  }
+  template <class G>
+  __device__ double finish(const Pre<G>& p, int, int nrows, const G& g, Lds& L) const {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kWin; ++k)
+      if (k * BS + t < p.wn) L.g[k * BS + t] = g.value(p.w[k]);
+    __syncthreads();
+    if (t >= nrows) return 0.0;
+    const int li = p.i - p.w0;
+    double x[7];
+    x[0] = g.value(p.z[0]);
+    x[1] = L.g[max(li - nx, 0)];
+    x[2] = L.g[max(li - 1, 0)];
+    x[3] = L.g[li];
+    x[4] = L.g[min(li + 1, p.wn - 1)];
+    x[5] = L.g[min(li + nx, p.wn - 1)];
+    x[6] = g.value(p.z[1]);
+    double s = 0.0;
+    {
+#pragma clang fp contract(off)
+#pragma unroll
+      for (int q = 0; q < 7; ++q) s += (p.present >> q) & 1u ? (double)p.c[q] * x[q] : 0.0;
+    }
+    return s;
+  }
+};
+
 // Reads columns of a column-major n x k basis stored as T (double or float) through one buffer
 // descriptor: the column offset is a uniform scalar (i * ldv * sizeof(T) bytes) and the row
 // offset a single per-lane 32-bit value, so a thread reading 30 columns of its row holds no

@@ -453,3 +453,47 @@ def test_slabs80_full_size_solves_match_oracle(G, slabs80, key, operator):
     assert np.linalg.norm(xs - xo) / np.linalg.norm(xo) <= 1e-8
     err = np.linalg.norm(host(x) - P.u_star) / np.linalg.norm(P.u_star)
     assert err == pytest.approx(run["err_vs_u_star"], rel=0.5, abs=1e-9)
+
+
+@pytest.mark.parametrize("dims,conv,p", [((104, 104, 100), (30.0, -10.0, 5.0), 2),
+                                         ((103, 101, 101), (30.0, -10.0, 5.0), 2),
+                                         ((104, 104, 100), (10.0, 20.0, -5.0), 1),
+                                         ((256, 4100), (25.0, 5.0), 2),
+                                         ((300, 3500), (5.0, 1.0), 2),
+                                         ((24, 20, 12), (30.0, -10.0, 5.0), 2)])
+def test_bicgstab_stencil_equals_csr_bitwise(G, dims, conv, p):
+    """Bi-CGSTAB on the packed stencil matrix returns the bits of the same solve on the CSR
+    matrix (one tile per workgroup): x, counts, status, both residuals. From 2^20 rows the
+    stencil solve's P and S run through the LDS window, two tiles per workgroup: rows in
+    16-byte pairs where n and nx are even (the first, third and fourth cases), single rows
+    otherwise (the second); x-lines wider than the window (the fifth) and small systems (the
+    last) take the one-tile kernels. GS(1) runs with stop weights."""
+    import torch
+    P = problems.laplacian(dims, conv=conv)
+    A, b = up(G, P)
+    As, bs, _, w = G.gs_scale(A, b, p, want_weights=True)
+    weights = None if p == 2 else w
+    St = G.stencil_from_csr(As, *(list(P.dims) + [1] * (3 - len(P.dims))))
+    xs, i_s = G.bicgstab(St, bs, tol=1e-10, stop_weights=weights)
+    xc, i_c = G.bicgstab(As, bs, tol=1e-10, stop_weights=weights)
+    torch.cuda.synchronize()
+    assert i_s == i_c
+    assert np.array_equal(host(xs), host(xc))
+
+
+@pytest.mark.parametrize("dims", [(104, 104, 100), (103, 101, 101), (256, 4100)])
+def test_gmres_large_stencil_equals_csr_bitwise(G, dims):
+    """FP64 GMRES(30) on systems whose cycle working set exceeds the 256 MB last-level cache
+    (over 10^6 rows): the stencil solve's Arnoldi product gathers through the LDS window
+    (non-temporal basis and plane loads), the CSR solve through the LDS-staged CSR tiles. Two
+    cycles (60 steps) return the same bits: x, counts, status, both residuals."""
+    import torch
+    P = problems.laplacian(dims, conv=(30.0, -10.0, 5.0)[:len(dims)])
+    A, b = up(G, P)
+    As, bs, _, _ = G.gs_scale(A, b, 2, want_weights=True)
+    St = G.stencil_from_csr(As, *(list(P.dims) + [1] * (3 - len(P.dims))))
+    xs, i_s = G.gmres(St, bs, m=30, tol=1e-12, maxit=60)
+    xc, i_c = G.gmres(As, bs, m=30, tol=1e-12, maxit=60)
+    torch.cuda.synchronize()
+    assert i_s == i_c and i_s.iters == 60
+    assert np.array_equal(host(xs), host(xc))
