@@ -56,41 +56,44 @@ KERNEL_NAMES = {"gmres_a": "k_gmres_a (matrix product + CGS2 pass-1 dots)",
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; FETCH_SIZE scaled by 2.000 and WRITE_SIZE by
 # 1.000 from a plain 512 MiB copy), recorded with the hash of the kernel sources they were
 # measured on. A source change makes the figure stale and it is reported as null.
-TRAFFIC = {
-    # FETCH_SIZE (x 2.000, calibrated on a copy) + WRITE_SIZE per working launch, 80^3 slabs
-    "gmres_a": {"bytes_per_launch": 96161325, "grid": 80, "operator": "stencil",
-                "sources": ["paper_0812_2769_amd/csrc/gmres.hip",
-                            "paper_0812_2769_amd/csrc/gmres_body.hpp",
-                            "paper_0812_2769_amd/csrc/gsk_dev.hpp"],
-                "sources_sha256_16": "ba7a51460425de28"},
-    # the batch engine's P launches of the 512-system batch: measured over the full-batch
-    # launches of the first chunk (profiles/k_batch_p_batch_512systems_hbm_counters.md) as a
-    # ratio to their algorithmic bytes
-    "batch_p": {"ratio": 8.536 / 8.491, "grid": None, "operator": "stencil",
-                "sources": ["paper_0812_2769_amd/csrc/batch.hip",
-                            "paper_0812_2769_amd/csrc/bicg_batch.hpp",
-                            "paper_0812_2769_amd/csrc/batch.hpp",
-                            "paper_0812_2769_amd/csrc/gsk_dev.hpp"],
-                "sources_sha256_16": "e84ba41c6bc4dc52"},
-}
+# Counter-measured HBM traffic (FETCH_SIZE x 2.000 + WRITE_SIZE, calibrated on a copy) of the
+# dominant kernel per workload, as a ratio to the algorithmic bytes of the same launches
+# (profiles/*_hbm_counters.md). A record applies while the kernel sources hash to the ones
+# the counters were taken with.
+GMRES_SOURCES = ["paper_0812_2769_amd/csrc/gmres.hip", "paper_0812_2769_amd/csrc/gmres_body.hpp",
+                 "paper_0812_2769_amd/csrc/gsk_dev.hpp"]
+BATCH_SOURCES = ["paper_0812_2769_amd/csrc/batch.hip", "paper_0812_2769_amd/csrc/bicg_batch.hpp",
+                 "paper_0812_2769_amd/csrc/batch.hpp", "paper_0812_2769_amd/csrc/gsk_dev.hpp"]
+TRAFFIC = [
+    # the 512-system batch: P launches of full-batch iterations
+    {"probe": "batch_p", "grid": None, "ratio": 8.536 / 8.491, "sources": BATCH_SOURCES,
+     "sources_sha256_16": "8ed2ff4616106afc"},
+    # FP64 GMRES(30) on the 160^3 checkerboard: the A launches of two cycles
+    {"probe": "gmres_a", "grid": 160, "ratio": 775.12 / 770.05, "sources": GMRES_SOURCES,
+     "sources_sha256_16": "eec4e4962cd957ab"},
+    # the 80^3 slabs (cache-resident): the A launches of the two GMRES(30) solves
+    {"probe": "gmres_a", "grid": 80, "ratio": 96.14 / 96.03, "sources": GMRES_SOURCES,
+     "sources_sha256_16": "eec4e4962cd957ab"},
+]
 
 
-def traffic_for(probe, grid, operator, bytes_per_launch=None):
-    """Counter-measured HBM bytes per launch of the probed class, or None when no record
-    matches the workload or the kernel sources have changed since the counters were taken."""
+def traffic_for(probe, grid, operator, bytes_per_launch):
+    """Counter-measured HBM bytes per launch of the probed class (the record's ratio times the
+    algorithmic bytes per launch), or None when no record matches the workload or the kernel
+    sources have changed since the counters were taken."""
     import hashlib
-    rec = TRAFFIC.get(probe)
-    if rec is None or rec["grid"] != grid or rec.get("operator", "csr") != operator:
+    if operator != "stencil" or bytes_per_launch is None:
         return None
-    h = hashlib.sha256()
-    for f in rec["sources"]:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    if h.hexdigest()[:16] != rec["sources_sha256_16"]:
-        return None
-    if "ratio" in rec:
-        return None if bytes_per_launch is None else int(rec["ratio"] * bytes_per_launch)
-    return rec["bytes_per_launch"]
+    for rec in TRAFFIC:
+        if rec["probe"] != probe or rec["grid"] != grid or rec["ratio"] is None:
+            continue
+        h = hashlib.sha256()
+        for f in rec["sources"]:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest()[:16] == rec["sources_sha256_16"]:
+            return int(rec["ratio"] * bytes_per_launch)
+    return None
 
 
 def parse(argv=None):
@@ -787,7 +790,8 @@ def bench_slabs80(args, gsk, problems, dev):
     a = achieved(pr)
     if a is not None:
         out["roofline"] = roofline_of(a, probe, args.probe_every,
-                                      traffic_for(probe, grid, args.operator) if not mixed
+                                      traffic_for(probe, grid, args.operator,
+                                                  a["bytes_per_launch"]) if not mixed
                                       else None)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
@@ -889,8 +893,11 @@ def extra_checker160(gsk, problems, dev):
     return {"workload": "160^3 7-point, 16^3-block checkerboard a in {1, 1e4} (seed 1003), "
                         "stencil operator",
             "k_gmres_a_fp64": None if a is None else roofline_of(
-                a, "gmres_a", 1, note="two GMRES(30) cycles (60 Arnoldi steps), every launch "
-                                      "timed; HBM-resident working set (1.2 GB)"),
+                a, "gmres_a", 1, traffic=traffic_for("gmres_a", 160, "stencil",
+                                                     a["bytes_per_launch"]),
+                note="two GMRES(30) cycles (60 Arnoldi steps), every launch timed; HBM-resident "
+                     "working set (1.2 GB); traffic = the counter-measured ratio of HBM to "
+                     "algorithmic bytes of these launches times bytes_per_launch"),
             "bicgstab_to_1e-8": {"solves_per_s": round((info.status == gsk.CONVERGED) / el, 4),
                                  "seconds": round(el, 3), "iters": info.iters,
                                  "status": info.status_name,

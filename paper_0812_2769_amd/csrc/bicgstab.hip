@@ -401,11 +401,12 @@ __global__ __launch_bounds__(BS) void k_bicg_s_win(BArgs a, StencilOp op, int nb
 
 // FP: alpha = rho / (r^, v), or breakdown. (The finalize launches read their control words
 // together with the partials, one memory round trip, and only the stores depend on them.)
+template <bool BIG>
 __global__ __launch_bounds__(BS) void k_bicg_fin_p(Ctl* c, const double* partials, int nb) {
   const int state = c->sum.state;
   const double eps_b = c->eps_b, rh_norm = c->rh_norm, rho = c->rho;
   __shared__ double out[8];
-  small_sums<2>(partials, nb, out);
+  small_sums<2, BIG ? sum_batch<2>() : SUM_BATCH>(partials, nb, out);
   if (state != ST_RUNNING || threadIdx.x != 0) return;
   const double sigma = out[0];
   const double vn = sqrt(out[1]);
@@ -463,12 +464,13 @@ __global__ __launch_bounds__(BS) void k_bicg_s(BArgs a, Op op) {
 }
 
 // FS: iteration count, half-step test on ||W s||, omega = (t,s)/(t,t), or breakdown.
+template <bool BIG>
 __global__ __launch_bounds__(BS) void k_bicg_fin_s(Ctl* c, const double* partials, int nb,
                                                    int has_w) {
   const int state = c->sum.state, iters = c->sum.iters;
   const double ref = c->ref, tol = c->tol, eps_b = c->eps_b;
   __shared__ double out[8];
-  small_sums<4>(partials, nb, out);
+  small_sums<4, BIG ? sum_batch<4>() : SUM_BATCH>(partials, nb, out);
   if (state != ST_RUNNING || threadIdx.x != 0) return;
   c->sum.iters = iters + 1;
   const double sn = sqrt(out[2]);
@@ -529,13 +531,14 @@ __global__ __launch_bounds__(BS) void k_bicg_u(BArgs a) {
 }
 
 // FU: stop test on ||W r|| (or the iteration cap), then rho, beta, or breakdown.
+template <bool BIG>
 __global__ __launch_bounds__(BS) void k_bicg_fin_u(Ctl* c, const double* partials, int nb,
                                                    int has_w) {
   const int st = c->sum.state, iters = c->sum.iters, maxit = c->maxit;
   const double ref = c->ref, tol = c->tol, eps_b = c->eps_b, rh_norm = c->rh_norm;
   const double rho = c->rho, alpha = c->alpha, omega = c->omega;
   __shared__ double out[8];
-  small_sums<3>(partials, nb, out);
+  small_sums<3, BIG ? sum_batch<3>() : SUM_BATCH>(partials, nb, out);
   if (threadIdx.x != 0) return;
   if (st == ST_HALF) {
     c->sum.state = ST_VERIFY;
@@ -592,7 +595,10 @@ static void launch_iteration(const BArgs& a, const Op& op, int nb, int par, hipS
   } else {
     launch_probed(k_bicg_p<Op>, dim3(nb), s, ax.pslot, ax, op);
   }
-  hipLaunchKernelGGL(k_bicg_fin_p, dim3(1), dim3(BS), 0, s, a.ctl, pt, nb);
+  // finalize launches with larger batches of partials for systems of many tiles
+  const bool big = nb > SUM_BATCH * BS;
+  hipLaunchKernelGGL(big ? k_bicg_fin_p<true> : k_bicg_fin_p<false>, dim3(1), dim3(BS), 0, s,
+                     a.ctl, pt, nb);
   ax.pslot = probe ? probe_slot(KC_BICG_S) : -1;
   if constexpr (std::is_same_v<Op, StencilOp>) {
     if (window) launch_probed(k_bicg_s_win, gw, s, ax.pslot, ax, op, nb);
@@ -600,10 +606,12 @@ static void launch_iteration(const BArgs& a, const Op& op, int nb, int par, hipS
   } else {
     launch_probed(k_bicg_s<Op>, dim3(nb), s, ax.pslot, ax, op);
   }
-  hipLaunchKernelGGL(k_bicg_fin_s, dim3(1), dim3(BS), 0, s, a.ctl, pt, nb, hw);
+  hipLaunchKernelGGL(big ? k_bicg_fin_s<true> : k_bicg_fin_s<false>, dim3(1), dim3(BS), 0, s,
+                     a.ctl, pt, nb, hw);
   ax.pslot = probe ? probe_slot(KC_BICG_U) : -1;
   launch_probed(k_bicg_u, dim3(nb), s, ax.pslot, ax);
-  hipLaunchKernelGGL(k_bicg_fin_u, dim3(1), dim3(BS), 0, s, a.ctl, pt, nb, hw);
+  hipLaunchKernelGGL(big ? k_bicg_fin_u<true> : k_bicg_fin_u<false>, dim3(1), dim3(BS), 0, s,
+                     a.ctl, pt, nb, hw);
 }
 
 static SolveResult bfail(int code) {

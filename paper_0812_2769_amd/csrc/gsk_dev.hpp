@@ -25,7 +25,37 @@ constexpr int WAVES = BS / 64;
 constexpr int TILE_NNZ = BS * 8;    // LDS product slots per tile (8 per row on average)
 constexpr int MMAX = 64;            // largest GMRES restart length
 constexpr int NC_MAX = MMAX + 2;    // most values reduced in one launch
-constexpr int SUM_BATCH = 8;        // partials one thread of a finalize launch loads at once
+// Partials one thread of a finalize launch loads at once per column: SUM_BATCH, or in the single
+// solver's Bi-CGSTAB finalize launches for sums of more than SUM_BATCH * BS partials (a large
+// system has tens of thousands of tiles) sum_batch<NC>() for NC columns (at most 64 values in
+// flight per thread; those launches are instantiated for both, so that a small sum keeps the
+// short kernel). A thread adds its partials t, t + BS, t + 2 BS, ... in that order whatever
+// the batch, so the batch changes the number of memory round trips of a sum, not its value.
+constexpr int SUM_BATCH = 8;
+template <int NC>
+constexpr int sum_batch() {
+  return NC <= 2 ? 32 : 16;
+}
+
+// acc[c] += partials[c * stride + l] for l = t, t + BS, ... < count, in that order, loading SB
+// values per column before adding them.
+template <int NC, int SB>
+__device__ inline void sweep_partials(const double* __restrict__ partials, int count, int stride,
+                                      double (&acc)[NC]) {
+  for (int base = 0; base < count; base += SB * BS) {
+    double v[NC][SB];
+#pragma unroll
+    for (int q = 0; q < SB; ++q) {
+      const int l = base + q * BS + (int)threadIdx.x;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[c][q] = l < count ? partials[(size_t)c * stride + l] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int q = 0; q < SB; ++q) acc[c] += v[c][q];
+  }
+}
 
 // Solver state machine (Ctl::state)
 enum : int {
@@ -295,20 +325,11 @@ __device__ inline void block_halving_partials(double (&v)[NV], int nc,
 // Sum of partials[0..nb) in a fixed order (thread t adds t, t+BS, ... in turn; then the wave
 // and workgroup trees). Every thread of the workgroup must call; all threads get the result.
 __device__ inline double column_sum(const double* __restrict__ partials, int nb, double* lds) {
-  // Each thread requests SUM_BATCH partials before it adds any of them, so a column of up to
-  // SUM_BATCH * BS partials costs one memory round trip.
-  double acc = 0.0;
-  for (int base = 0; base < nb; base += SUM_BATCH * BS) {
-    double v[SUM_BATCH];
-#pragma unroll
-    for (int q = 0; q < SUM_BATCH; ++q) {
-      const int l = base + q * BS + (int)threadIdx.x;
-      v[q] = l < nb ? partials[l] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < SUM_BATCH; ++q) acc += v[q];
-  }
-  const double v = wave_sum(acc);
+  // Each thread requests a batch of partials before it adds any of them, so a column of up to
+  // a batch of BS-strided partials costs one memory round trip.
+  double acc[1] = {0.0};
+  sweep_partials<1, SUM_BATCH>(partials, nb, nb, acc);
+  const double v = wave_sum(acc[0]);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
   __syncthreads();
@@ -321,29 +342,17 @@ __device__ inline double column_sum(const double* __restrict__ partials, int nb,
 // In a single-workgroup finalize launch: out[c] = sum of partial column c (c < NC <= 8), all
 // BS threads sweeping every column with independent loads; then the workgroup tree.
 // out[c] = sum of the `count` partials of column c (column c starts at partials + c * stride),
-// for c < NC <= 8, by one workgroup: every thread requests SUM_BATCH values per column before
+// for c < NC <= 8, by one workgroup: every thread requests sum_batch values per column before
 // it adds any, then the wave and workgroup trees. The result depends only on the column
 // values and count, so a system's sums are the same wherever its partials sit.
-template <int NC>
+template <int NC, int SB = SUM_BATCH>
 __device__ inline void small_sums_strided(const double* __restrict__ partials, int count,
                                           int stride, double* out) {
   __shared__ double lds[8 * WAVES];
   double acc[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-  for (int base = 0; base < count; base += SUM_BATCH * BS) {
-    double v[NC][SUM_BATCH];
-#pragma unroll
-    for (int q = 0; q < SUM_BATCH; ++q) {
-      const int l = base + q * BS + (int)threadIdx.x;
-#pragma unroll
-      for (int c = 0; c < NC; ++c) v[c][q] = l < count ? partials[(size_t)c * stride + l] : 0.0;
-    }
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-      for (int q = 0; q < SUM_BATCH; ++q) acc[c] += v[c][q];
-  }
+  sweep_partials<NC, SB>(partials, count, stride, acc);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
 #pragma unroll
@@ -361,9 +370,9 @@ __device__ inline void small_sums_strided(const double* __restrict__ partials, i
   __syncthreads();
 }
 
-template <int NC>
+template <int NC, int SB = SUM_BATCH>
 __device__ inline void small_sums(const double* __restrict__ partials, int nb, double* out) {
-  small_sums_strided<NC>(partials, nb, nb, out);
+  small_sums_strided<NC, SB>(partials, nb, nb, out);
 }
 
 // ---------------------------------------------------------------------------------------

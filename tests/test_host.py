@@ -63,14 +63,20 @@ def test_bench_runs_on_one_gpu_only():
 
 
 def test_traffic_record_applies_only_to_its_workload():
+    """A counter record applies to its own kernel class, grid and operator only, and only while
+    the kernel sources hash to the measured ones (then it scales the algorithmic bytes)."""
     sys.path.insert(0, ROOT)
     import bench
-    rec = bench.TRAFFIC["gmres_a"]
-    assert bench.traffic_for("gmres_a", rec["grid"] + 1, rec["operator"]) is None
-    assert bench.traffic_for("gmres_a", rec["grid"], "csr") is None
-    assert bench.traffic_for("gmres_b", rec["grid"], rec["operator"]) is None
-    got = bench.traffic_for("gmres_a", rec["grid"], rec["operator"])
-    assert got in (None, rec["bytes_per_launch"])   # None once the kernel sources change
+    for rec in bench.TRAFFIC:
+        p, g = rec["probe"], rec["grid"]
+        bad_grid = 7 if g is None else g + 1
+        assert bench.traffic_for(p, bad_grid, "stencil", 1000) is None
+        assert bench.traffic_for(p, g, "csr", 1000) is None
+        assert bench.traffic_for("gmres_b", g, "stencil", 1000) is None
+        assert bench.traffic_for(p, g, "stencil", None) is None
+        got = bench.traffic_for(p, g, "stencil", 10 ** 9)
+        assert got is None or got == int(rec["ratio"] * 10 ** 9)   # None once sources change
+        assert rec["ratio"] is None or 0.9 < rec["ratio"] < 1.2
 
 
 def test_tuner_rejects_bad_candidates():
