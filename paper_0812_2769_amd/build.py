@@ -27,6 +27,9 @@ HIPCC_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INCLUDE,
     "-I", CSRC,
+    # roctx ranges for rocprofv3's marker trace
+    "-L", os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib"),
+    "-lrocprofiler-sdk-roctx",
 ]
 
 

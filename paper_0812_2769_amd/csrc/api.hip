@@ -12,6 +12,8 @@
 #include <utility>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "gsk.h"
 #include "gsk_host.hpp"
 
@@ -19,6 +21,16 @@ namespace gsk {
 
 namespace {
 thread_local std::string g_err;
+
+// A named range on the calling thread for rocprofv3's marker trace (--marker-trace): one per
+// solve, GS(p) call and engine chunk run or poll. Without a profiler attached the calls cost a
+// function call each.
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 struct Pinned {
   Summary sum[2];
@@ -530,6 +542,7 @@ int gsk_engine_submit_gs(gsk_engine* e, const gsk_matrix* A, const double* b, in
 }
 
 int gsk_engine_run(gsk_engine* e, int32_t chunks) {
+  const Range range("gsk_engine_run");
   g_err.clear();
   if (!e) return set_err(GSK_ERR_INVALID_ARG, "engine is NULL");
   if (chunks < 0) return set_err(GSK_ERR_INVALID_ARG, "chunks must be >= 0");
@@ -542,6 +555,7 @@ int gsk_engine_run(gsk_engine* e, int32_t chunks) {
 
 int gsk_engine_poll(gsk_engine* e, int32_t wait, gsk_result* out, int32_t max_out,
                     int32_t* n_out) {
+  const Range range("gsk_engine_poll");
   g_err.clear();
   if (!e || !n_out || (max_out > 0 && !out) || max_out < 0)
     return set_err(GSK_ERR_INVALID_ARG, "engine, out or n_out invalid");
@@ -658,6 +672,7 @@ int gsk_bicgstab_batch(int32_t count, const gsk_matrix* A, const double* const* 
 int gsk_gs_scale(const gsk_csr* A, const double* b, int32_t p, double* val_out, double* b_out,
                  double* row_norm, double* stop_weight, void* ws, size_t ws_bytes,
                  void* stream) {
+  const Range range("gsk_gs_scale");
   g_err.clear();
   int rc = check_csr(A);
   if (rc) return rc;
@@ -790,18 +805,21 @@ static int solve_common(int method, const gsk_matrix* A, const double* b, double
 
 int gsk_gmres(const gsk_matrix* A, const double* b, double* x, int32_t m, double tol,
               const gsk_options* opt, gsk_info* info, void* ws, size_t ws_bytes, void* stream) {
+  const Range range("gsk_gmres");
   return solve_common(GSK_METHOD_GMRES, A, b, x, m, tol, opt, info, ws, ws_bytes, stream);
 }
 
 int gsk_gmres_mixed(const gsk_matrix* A, const double* b, double* x, int32_t m, double tol,
                     const gsk_options* opt, gsk_info* info, void* ws, size_t ws_bytes,
                     void* stream) {
+  const Range range("gsk_gmres_mixed");
   return solve_common(GSK_METHOD_GMRES_MIXED, A, b, x, m, tol, opt, info, ws, ws_bytes, stream);
 }
 
 int gsk_bicgstab(const gsk_matrix* A, const double* b, double* x, double tol,
                  const gsk_options* opt, gsk_info* info, void* ws, size_t ws_bytes,
                  void* stream) {
+  const Range range("gsk_bicgstab");
   return solve_common(GSK_METHOD_BICGSTAB, A, b, x, 0, tol, opt, info, ws, ws_bytes, stream);
 }
 
