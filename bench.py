@@ -328,6 +328,30 @@ def status_counts(infos):
     return c
 
 
+def measured_copy_peak(dev, mib=1024, reps=10):
+    """Achievable HBM bandwidth on this device, measured beside the roofline's published peak:
+    a device-to-device copy of `mib` MiB (torch's copy kernel), best of `reps`, counting the
+    bytes read and written."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    gbs = 2 * n * 8 / (best * 1e-3) / 1e9
+    return {"GBs": round(gbs, 1), "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4),
+            "kernel": f"device-to-device copy of {mib} MiB (read + written bytes), best of {reps}"}
+
+
 def bench_batch(args, gsk, problems, dev):
     """batch512: a batch of independent GS(2) + Bi-CGSTAB (or GMRES(20)) solves, tol 1e-8, run
     by the engine with every chunk replayed from a HIP graph."""
@@ -490,6 +514,7 @@ def bench_batch(args, gsk, problems, dev):
                     "whole step time (GS, residual and finalize launches, host polls "
                     "included)"},
         "engine_tuning": tuned,
+        "measured_copy_peak": measured_copy_peak(dev),
         "roofline": None, "cpu_baseline": None,
     }
     a = achieved(pr)
