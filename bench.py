@@ -530,6 +530,15 @@ def bench_batch(args, gsk, problems, dev):
                   "algorithmic bytes of this class (FETCH_SIZE x 2.000 + WRITE_SIZE, full-batch "
                   "launches) times bytes_per_launch, null once the kernel sources change"))
     eng.close()
+    if out["roofline"] is not None and probe == "batch_p":
+        # the same 13-stream mix (7 planes, r, p, v, r^ read; p, v written) without gathers,
+        # engine lookups or tails: what a kernel with P's mix can reach on this device
+        c = gsk.stream_mix(11, 2, 40_000_000, reps=10, device=dev)
+        out["stream_ceiling"] = {
+            "mix": "P's arrays: 11 read, 2 written, one row per thread, 8-byte loads, tile "
+                   "reductions, no gathers (gsk_stream_mix_ms, 40 M rows, best of 10)",
+            "GBs": round(c["GBs"], 1), "frac_of_8TBs": round(c["GBs"] / HBM_PEAK_GBS, 4),
+            "kernel_frac_of_ceiling": round(out["roofline"]["achieved"] / c["GBs"], 4)}
     if acc_sample:
         import oracle
         errs = {}

@@ -12,7 +12,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libgsk.so")
-SOURCES = ["api.hip", "gs_spmv.hip", "gmres.hip", "bicgstab.hip", "batch.hip", "batch_gmres.hip", "batch_mixed.hip"]
+SOURCES = ["api.hip", "gs_spmv.hip", "gmres.hip", "bicgstab.hip", "batch.hip", "batch_gmres.hip",
+           "batch_mixed.hip", "measure.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -363,6 +363,32 @@ int gsk_probe_begin(int32_t kernel_class, int32_t sample_every) {
   return GSK_OK;
 }
 
+static bool stream_mix_supported(int32_t reads, int32_t writes) {
+  return (reads == 1 && (writes == 0 || writes == 1)) || (reads == 6 && writes == 2) ||
+         (reads == 9 && writes == 1) || (reads == 11 && writes == 2);
+}
+
+size_t gsk_stream_mix_bytes(int32_t reads, int32_t writes, int64_t n) {
+  if (!stream_mix_supported(reads, writes) || n < 1 || n > ((int64_t)1 << 34)) return 0;
+  const int64_t tiles = (n + gsk::BS - 1) / gsk::BS;
+  return sizeof(double) * ((size_t)(reads + writes) * (size_t)n + (size_t)((tiles + 7) / 8 * 8));
+}
+
+int gsk_stream_mix_ms(int32_t reads, int32_t writes, int64_t n, void* buf, size_t buf_bytes,
+                      int32_t reps, float* best_ms, void* stream) {
+  g_err.clear();
+  const size_t need = gsk_stream_mix_bytes(reads, writes, n);
+  if (need == 0) return set_err(GSK_ERR_INVALID_ARG, "unsupported mix or n");
+  if (!buf || !best_ms || reps < 1) return set_err(GSK_ERR_INVALID_ARG, "buf, best_ms or reps");
+  if (buf_bytes < need) return set_err(GSK_ERR_WORKSPACE, "buf needs %zu bytes", need);
+  if ((int64_t)((n + gsk::BS - 1) / gsk::BS) > (int64_t)INT32_MAX / 2)
+    return set_err(GSK_ERR_INVALID_ARG, "n too large");
+  const int rc = gsk::stream_mix_ms(reads, writes, n, static_cast<double*>(buf), reps, best_ms,
+                                    static_cast<hipStream_t>(stream));
+  if (rc) return set_err(GSK_ERR_DEVICE, "stream mix: HIP failure");
+  return GSK_OK;
+}
+
 int gsk_probe_end(gsk_probe_result* out) {
   g_err.clear();
   Probe& p = probe_state();

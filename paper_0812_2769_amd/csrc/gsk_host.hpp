@@ -124,6 +124,10 @@ struct EngineDone {
 // launch then take the non-temporal policy.
 constexpr double kStreamBytes = 256.0 * (1 << 20);
 
+// measure.hip: the measurement hook's stream-mix kernel (0, -1 unsupported mix, -5 HIP failure)
+int stream_mix_ms(int reads, int writes, int64_t n, double* buf, int reps, float* best_ms,
+                  hipStream_t s);
+
 struct EngineConfig {
   int64_t max_rows;
   int max_sys;

@@ -169,6 +169,11 @@ def _load() -> ctypes.CDLL:
     lib.gsk_probe_begin.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.gsk_probe_begin.restype = ctypes.c_int
     lib.gsk_probe_end.argtypes = [P(ProbeResult)]
+    lib.gsk_stream_mix_bytes.restype = sz
+    lib.gsk_stream_mix_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64]
+    lib.gsk_stream_mix_ms.restype = ctypes.c_int
+    lib.gsk_stream_mix_ms.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, vp, sz,
+                                      ctypes.c_int32, P(ctypes.c_float), vp]
     lib.gsk_probe_end.restype = ctypes.c_int
     lib.gsk_last_error.argtypes = []
     lib.gsk_last_error.restype = ctypes.c_char_p
@@ -535,6 +540,23 @@ def probe_end() -> dict:
     _check(lib.gsk_probe_end(ctypes.byref(r)))
     return {"launches": r.launches, "busy_launches": r.busy_launches, "total_ms": r.total_ms,
             "bytes": r.bytes}
+
+
+def stream_mix(reads: int, writes: int, n: int, reps: int = 10, device="cuda") -> dict:
+    """The memory ceiling of a streaming mix (gsk_stream_mix_ms): `reads` arrays read and
+    `writes` written, n doubles each, best of `reps` launches. Returns the time, the bytes per
+    launch and the rate."""
+    nbytes = int(lib.gsk_stream_mix_bytes(int(reads), int(writes), int(n)))
+    if nbytes == 0:
+        raise GskError(ERR_INVALID_ARG, f"unsupported stream mix ({reads}, {writes}) or n")
+    dev = torch.device(device)
+    buf = torch.zeros(nbytes // 8, dtype=torch.float64, device=dev)
+    ms = ctypes.c_float(0.0)
+    _check(lib.gsk_stream_mix_ms(int(reads), int(writes), int(n), buf.data_ptr(), nbytes,
+                                 int(reps), ctypes.byref(ms), _stream(dev)))
+    moved = 8 * (reads + writes) * n
+    return {"reads": reads, "writes": writes, "n": n, "best_ms": ms.value,
+            "bytes": moved, "GBs": moved / (ms.value * 1e-3) / 1e9}
 
 
 def _vec_ld(n: int) -> int:

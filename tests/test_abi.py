@@ -260,3 +260,21 @@ def test_engine_config_rejections(lib):
     # a valid configuration with too small a workspace fails before any device work
     assert L.gsk_engine_create_ex(ctypes.byref(good), 0x100000, 256, None,
                                   ctypes.byref(h)) == lib.ERR_WORKSPACE
+
+
+def test_stream_mix_sizes_and_rejections(lib):
+    """The measurement hook sizes its buffer and rejects bad arguments before any device work."""
+    L = lib.lib
+    n = 1000
+    tiles = (n + 255) // 256
+    assert L.gsk_stream_mix_bytes(11, 2, n) == 8 * (13 * n + (tiles + 7) // 8 * 8)
+    assert L.gsk_stream_mix_bytes(1, 0, n) == 8 * (n + 8)
+    assert L.gsk_stream_mix_bytes(2, 2, n) == 0
+    assert L.gsk_stream_mix_bytes(11, 2, 0) == 0
+    ms = ctypes.c_float(0.0)
+    assert L.gsk_stream_mix_ms(2, 2, n, 0x100000, 1 << 20, 1, ctypes.byref(ms), None) == \
+        lib.ERR_INVALID_ARG
+    assert L.gsk_stream_mix_ms(11, 2, n, 0x100000, 64, 1, ctypes.byref(ms), None) == \
+        lib.ERR_WORKSPACE
+    assert L.gsk_stream_mix_ms(11, 2, n, 0x100000, 1 << 20, 0, ctypes.byref(ms), None) == \
+        lib.ERR_INVALID_ARG
