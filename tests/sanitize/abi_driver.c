@@ -88,6 +88,11 @@ int main(void) {
     gsk_engine* e = NULL;
     CHECK(gsk_engine_create_ex(NULL, dummy, 8, NULL, &e) == GSK_ERR_INVALID_ARG && e == NULL);
     CHECK(gsk_engine_create_ex(&c, dummy, 8, NULL, &e) == GSK_ERR_WORKSPACE && e == NULL);
+    CHECK(gsk_stream_mix_bytes(11, 2, 1000) > 13 * 8 * 1000);
+    CHECK(gsk_stream_mix_bytes(2, 2, 1000) == 0);
+    float ms = 0.0f;
+    CHECK(gsk_stream_mix_ms(2, 2, 1000, dummy, 8, 1, &ms, NULL) == GSK_ERR_INVALID_ARG);
+    CHECK(gsk_stream_mix_ms(11, 2, 1000, dummy, 8, 1, &ms, NULL) == GSK_ERR_WORKSPACE);
     CHECK(gsk_probe_begin(99, 1) == GSK_ERR_INVALID_ARG);
     CHECK(gsk_probe_begin(GSK_KCLASS_BATCH_P, 0) == GSK_ERR_INVALID_ARG);
     printf("abi driver: ok\n");
