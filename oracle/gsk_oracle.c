@@ -669,7 +669,7 @@ int orc_bicgstab(int n, const int* rp, const int* ci, const double* val, const d
  *      target would otherwise spend the whole iteration budget before any refinement step).
  * Stagnation: a refinement step that does not halve rt counts as a failure; three failures
  * in a row end the refinement. Breakdown tests as in Bi-CGSTAB (R6), on the stored vectors.
- * FP64 continuation (fallback != 0; a choice of this build, not in the paper): the solve is
+ * FP64 continuation (fallback != 0; a design choice, not in the paper): the solve is
  * handed to FP64 Bi-CGSTAB (the algorithm of orc_bicgstab) when the refinement stops paying:
  *   - a run leaves the true residual above the one it started from (float recurrences that
  *     diverged move x away from the solution before the divergence test ends them): the run
