@@ -89,16 +89,22 @@ def test_batch_equals_solo(G):
         same((host(xs[j]), infos[j]), ref[k])
 
 
-@pytest.mark.parametrize("graph,tile_units", [(False, 1), (True, 1), (False, 2), (True, 2)])
-def test_engine_continuous_admission_equals_solo(G, graph, tile_units):
+@pytest.mark.parametrize("graph,tile_units,shapes", [
+    (False, 1, None), (True, 1, None), (False, 2, None), (True, 2, None),
+    (True, 0, {"2d": "tile", "3d_small": "pair", "3d_large": "pair_tile_u"}),
+    (False, 0, {"2d": "pair_tile_u", "3d_small": "tile"})])
+def test_engine_continuous_admission_equals_solo(G, graph, tile_units, shapes):
+    """Systems admitted while others run (room for part of the set), with one shape or per-class
+    shapes (per-class unit lists rebuilt at every admission and retirement), eager or replayed
+    from graphs: every result equals the single solve bit for bit."""
     import torch
     syst = systems(G)
     ref = solo(G, syst)
     # room for only part of the set at a time: later systems wait for rows and slots
-    unit = 256 * tile_units
+    unit = 512 if shapes else 256 * tile_units
     rows = sorted(((M.n + unit - 1) // unit * unit for M, _, _ in syst), reverse=True)
     eng = G.Engine(max_rows=rows[0] + rows[1], max_systems=3, check_every=8, graph=graph,
-                   tile_units=tile_units)
+                   tile_units=tile_units, class_shapes=shapes)
     xs = [torch.zeros_like(b) for _, b, _ in syst]
     pending = list(range(len(syst)))
     results = {}
