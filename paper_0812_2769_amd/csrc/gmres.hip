@@ -137,24 +137,30 @@ __global__ __launch_bounds__(BS) void k_gmres_a(KArgs a, Op op, const T* __restr
 }
 
 // FA (j+2 workgroups): workgroup i <= j -> c1_i = sigma_i (u_i . w); workgroup j+1 -> ||w||.
+// BIG: partial sums of more than SUM_BATCH * BS tiles, with larger batches of loads (the same
+// order of additions).
+template <bool BIG>
 __global__ __launch_bounds__(BS) void k_gmres_fin_a(Ctl* c, const double* partials, int nb,
                                                     int j) {
   __shared__ double lds[WAVES];
   const int col = blockIdx.x;
-  gmres_fin_a_body(c, partials + (size_t)col * nb, nb, j, col, lds);
+  gmres_fin_a_body<false, BIG ? sum_batch<1>() : SUM_BATCH>(c, partials + (size_t)col * nb,
+                                                            nb, j, col, lds);
 }
 
 // FC of step j-1 and FA of step j (j >= 1) in one launch of j+3 workgroups: workgroup 0 runs
 // FC on C's nbc partials, workgroup 1+i the FA column i on A's nba partials.
+template <bool BIG>
 __global__ __launch_bounds__(BS) void k_gmres_fin_ca(Ctl* c, const double* pa, int nba,
                                                      const double* pc, int nbc, int j) {
+  constexpr int SB = BIG ? sum_batch<1>() : SUM_BATCH;
   if (blockIdx.x == 0) {
-    gmres_fin_c_body(c, pc, nbc, j - 1);
+    gmres_fin_c_body<SB>(c, pc, nbc, j - 1);
     return;
   }
   __shared__ double lds[WAVES];
   const int col = blockIdx.x - 1;
-  gmres_fin_a_body<true>(c, pa + (size_t)col * nba, nba, j, col, lds, pc, nbc);
+  gmres_fin_a_body<true, SB>(c, pa + (size_t)col * nba, nba, j, col, lds, pc, nbc);
 }
 
 // B: w -= sum_i c1_i v_i, then partials of u_i . w, sharing one read of the basis.
@@ -167,11 +173,13 @@ __global__ __launch_bounds__(BS) void k_gmres_b(KArgs a, const T* __restrict__ V
 }
 
 // FB (j+1 workgroups): c2_i = sigma_i (u_i . w).
+template <bool BIG>
 __global__ __launch_bounds__(BS) void k_gmres_fin_b(Ctl* c, const double* partials, int nb,
                                                     int j) {
   __shared__ double lds[WAVES];
   const int col = blockIdx.x;
-  gmres_fin_b_body(c, partials + (size_t)col * nb, nb, j, col, lds);
+  gmres_fin_b_body<BIG ? sum_batch<1>() : SUM_BATCH>(c, partials + (size_t)col * nb, nb, j,
+                                                     col, lds);
 }
 
 // C: u_{j+1} = sigma_j (w - sum_i c2_i v_i), partial ||u_{j+1}||^2 (into cpartials).
@@ -185,9 +193,10 @@ __global__ __launch_bounds__(BS) void k_gmres_c(KArgs a, T* __restrict__ V, size
 
 // FC (1 workgroup): Hessenberg column, Givens rotations, residual estimate; at the end of a
 // cycle the triangular solve for y.
+template <bool BIG>
 __global__ __launch_bounds__(BS) void k_gmres_fin_c(Ctl* c, const double* partials, int nb,
                                                     int j) {
-  gmres_fin_c_body(c, partials, nb, j);
+  gmres_fin_c_body<BIG ? sum_batch<1>() : SUM_BATCH>(c, partials, nb, j);
 }
 
 // X: x += sum_{l<k} y_l v_l (y already carries sigma).
@@ -290,6 +299,7 @@ static hipError_t launch_step(const KArgs& ka, const Op& op, int n, T* V, size_t
   constexpr int RA = Op::kRowwise ? RV : 1;        // A
   const int ga = grid_for(n, RA), gv = grid_for(n, RV);
   const int jm = pick_jm(j + 1);
+  const bool big = (ga > gv ? ga : gv) > SUM_BATCH * BS;   // finalize with larger batches
   dim3 block(BS);
   KArgs kx = ka;
 #define GSK_STEP(JMV)                                                                          \
@@ -297,13 +307,16 @@ static hipError_t launch_step(const KArgs& ka, const Op& op, int n, T* V, size_t
   launch_probed(k_gmres_a<JMV, RA, R, Op, T>, dim3(ga), s, kx.pslot, kx, op, (const T*)V, ldv, \
                 w, j, merged ? j - 1 : j);                                                     \
   if (merged)                                                                                  \
-    hipLaunchKernelGGL(k_gmres_fin_ca, dim3(j + 3), block, 0, s, ka.ctl,                       \
-                       (const double*)ka.partials, ga, (const double*)ka.cpartials, gv, j);    \
+    hipLaunchKernelGGL(big ? k_gmres_fin_ca<true> : k_gmres_fin_ca<false>, dim3(j + 3), block, \
+                       0, s, ka.ctl, (const double*)ka.partials, ga,                           \
+                       (const double*)ka.cpartials, gv, j);                                    \
   else                                                                                         \
-    hipLaunchKernelGGL(k_gmres_fin_a, dim3(j + 2), block, 0, s, ka.ctl, ka.partials, ga, j);   \
+    hipLaunchKernelGGL(big ? k_gmres_fin_a<true> : k_gmres_fin_a<false>, dim3(j + 2), block,   \
+                       0, s, ka.ctl, ka.partials, ga, j);                                      \
   kx.pslot = probe_slot(KC_GMRES_B);                                                           \
   launch_probed(k_gmres_b<JMV, RV, R, T>, dim3(gv), s, kx.pslot, kx, (const T*)V, ldv, w, j);  \
-  hipLaunchKernelGGL(k_gmres_fin_b, dim3(j + 1), block, 0, s, ka.ctl, ka.partials, gv, j);     \
+  hipLaunchKernelGGL(big ? k_gmres_fin_b<true> : k_gmres_fin_b<false>, dim3(j + 1), block, 0, \
+                     s, ka.ctl, ka.partials, gv, j);                                           \
   kx.pslot = probe_slot(KC_GMRES_C);                                                           \
   launch_probed(k_gmres_c<JMV, RV, R, T>, dim3(gv), s, kx.pslot, kx, V, ldv, (const T*)w, j);
   switch (jm) {
@@ -319,8 +332,9 @@ static hipError_t launch_step(const KArgs& ka, const Op& op, int n, T* V, size_t
 // The plain FC of step j (after the last step of an enqueued run of steps).
 template <class T>
 static hipError_t launch_fin_c(const KArgs& ka, int n, int j, hipStream_t s) {
-  hipLaunchKernelGGL(k_gmres_fin_c, dim3(1), dim3(BS), 0, s, ka.ctl,
-                     (const double*)ka.cpartials, grid_for(n, rpt_of<T>()), j);
+  const int gv = grid_for(n, rpt_of<T>());
+  hipLaunchKernelGGL(gv > SUM_BATCH * BS ? k_gmres_fin_c<true> : k_gmres_fin_c<false>, dim3(1),
+                     dim3(BS), 0, s, ka.ctl, (const double*)ka.cpartials, gv, j);
   return hipGetLastError();
 }
 

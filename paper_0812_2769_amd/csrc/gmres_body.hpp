@@ -234,7 +234,7 @@ __device__ inline void gmres_a_tile(Ctl* c, const Op& op, int n, const T* __rest
 // reads none of them: column j computes sigma_j itself from C's `ccount` partials `cpart`,
 // with FC's arithmetic, and the stores are unconditional (if step j-1 ends the cycle, nothing
 // reads them before the next cycle rewrites them).
-template <bool kMerged = false>
+template <bool kMerged = false, int SB = SUM_BATCH>
 __device__ inline void gmres_fin_a_body(Ctl* c, const double* col_partials, int count, int j,
                                         int col, double* lds, const double* cpart = nullptr,
                                         int ccount = 0) {
@@ -245,8 +245,8 @@ __device__ inline void gmres_fin_a_body(Ctl* c, const double* col_partials, int 
   }
   const bool own = kMerged && col == j;
   const double sg0 = (col <= j && !own) ? c->sigma[col] : 0.0;
-  const double s = column_sum(col_partials, count, lds);
-  const double sg = own ? 1.0 / sqrt(column_sum(cpart, ccount, lds)) : sg0;
+  const double s = column_sum<SB>(col_partials, count, lds);
+  const double sg = own ? 1.0 / sqrt(column_sum<SB>(cpart, ccount, lds)) : sg0;
   if (state != ST_RUNNING || cj != j || threadIdx.x != 0) return;
   const int par = j & 1;
   if (col == j + 1) {
@@ -311,11 +311,12 @@ __device__ inline void gmres_b_tile(Ctl* c, int n, const T* __restrict__ V, size
 }
 
 // FB (one workgroup per column col <= j): c2_col = sigma_col (u_col . w).
+template <int SB = SUM_BATCH>
 __device__ inline void gmres_fin_b_body(Ctl* c, const double* col_partials, int count, int j,
                                         int col, double* lds) {
   const int state = c->sum.state, cj = c->j;
   const double sg = c->sigma[col];
-  const double s = column_sum(col_partials, count, lds);
+  const double s = column_sum<SB>(col_partials, count, lds);
   if (state != ST_RUNNING || cj != j || threadIdx.x != 0) return;
   const double c2 = sg * s;
   c->c2[col] = c2;
@@ -374,6 +375,7 @@ __device__ inline void gmres_c_tile(Ctl* c, int n, T* __restrict__ V, size_t ldv
 // Givens rotations, residual estimate; at the end of a cycle the k x k triangular solve
 // H y = g (y stored pre-multiplied by sigma). `partials` are the `count` partials of C. Every control word the body needs is requested before the first
 // wait; the old rotations are applied in registers by one thread.
+template <int SB = SUM_BATCH>
 __device__ inline void gmres_fin_c_body(Ctl* c, const double* partials, int count, int j) {
   __shared__ double lds[WAVES];
   __shared__ double s_h[MMAX + 2];
@@ -392,7 +394,7 @@ __device__ inline void gmres_fin_c_body(Ctl* c, const double* partials, int coun
     s_cs[t] = c->cs[t];
     s_sn[t] = c->sn[t];
   }
-  const double nrm2 = column_sum(partials, count, lds);   // also orders the LDS writes above
+  const double nrm2 = column_sum<SB>(partials, count, lds);   // also orders the LDS writes above
   if (state != ST_RUNNING || cj != j) return;
   const double hn = sqrt(nrm2);
   if (t <= j) c->Hraw[(size_t)j * LDH + t] = s_h[t];

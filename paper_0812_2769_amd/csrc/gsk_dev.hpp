@@ -26,10 +26,10 @@ constexpr int TILE_NNZ = BS * 8;    // LDS product slots per tile (8 per row on 
 constexpr int MMAX = 64;            // largest GMRES restart length
 constexpr int NC_MAX = MMAX + 2;    // most values reduced in one launch
 // Partials one thread of a finalize launch loads at once per column: SUM_BATCH, or in the single
-// solver's Bi-CGSTAB finalize launches for sums of more than SUM_BATCH * BS partials (a large
-// system has tens of thousands of tiles) sum_batch<NC>() for NC columns (at most 64 values in
-// flight per thread; those launches are instantiated for both, so that a small sum keeps the
-// short kernel). A thread adds its partials t, t + BS, t + 2 BS, ... in that order whatever
+// solvers' finalize launches for sums of more than SUM_BATCH * BS partials (a large system has
+// tens of thousands of tiles) sum_batch<NC>() for NC columns (at most 64 values in flight per
+// thread; those launches are instantiated for both, so that a small sum keeps the short
+// kernel). A thread adds its partials t, t + BS, t + 2 BS, ... in that order whatever
 // the batch, so the batch changes the number of memory round trips of a sum, not its value.
 constexpr int SUM_BATCH = 8;
 template <int NC>
@@ -324,11 +324,12 @@ __device__ inline void block_halving_partials(double (&v)[NV], int nc,
 
 // Sum of partials[0..nb) in a fixed order (thread t adds t, t+BS, ... in turn; then the wave
 // and workgroup trees). Every thread of the workgroup must call; all threads get the result.
+template <int SB = SUM_BATCH>
 __device__ inline double column_sum(const double* __restrict__ partials, int nb, double* lds) {
   // Each thread requests a batch of partials before it adds any of them, so a column of up to
   // a batch of BS-strided partials costs one memory round trip.
   double acc[1] = {0.0};
-  sweep_partials<1, SUM_BATCH>(partials, nb, nb, acc);
+  sweep_partials<1, SB>(partials, nb, nb, acc);
   const double v = wave_sum(acc[0]);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
