@@ -327,10 +327,10 @@ int gsk_probe_end(gsk_probe_result* out);
 
 /*
  * Measurement hook (not part of the method): the memory ceiling of a streaming kernel's mix of
- * arrays on this device. Times `reps` launches (after one warm-up launch) of a kernel that
- * reads `reads` arrays and writes `writes` arrays of n doubles, one row per thread in 256-row
- * tiles in the solvers' workgroup order, with one tile reduction into a partial and no
- * gathers; *best_ms receives the shortest launch (HIP events). The mixes of the batch engine's
+ * arrays on this device. Times `reps` (1..1000) launches (after one warm-up launch) of a
+ * kernel that reads `reads` arrays and writes `writes` arrays of n doubles, one row per thread
+ * in 256-row tiles in the solvers' workgroup order, with one tile reduction into a partial and
+ * no gathers; *best_ms receives the shortest launch (HIP events). The mixes of the batch engine's
  * passes are supported: (11, 2) P with 7-point planes, (9, 1) S, (6, 2) U, and (1, 0) a plain
  * read, (1, 1) a copy; any other gives GSK_ERR_INVALID_ARG. buf: device memory of at least
  * gsk_stream_mix_bytes(reads, writes, n) bytes (the arrays back to back, then the partials),

@@ -379,7 +379,8 @@ int gsk_stream_mix_ms(int32_t reads, int32_t writes, int64_t n, void* buf, size_
   g_err.clear();
   const size_t need = gsk_stream_mix_bytes(reads, writes, n);
   if (need == 0) return set_err(GSK_ERR_INVALID_ARG, "unsupported mix or n");
-  if (!buf || !best_ms || reps < 1) return set_err(GSK_ERR_INVALID_ARG, "buf, best_ms or reps");
+  if (!buf || !best_ms || reps < 1 || reps > 1000)
+    return set_err(GSK_ERR_INVALID_ARG, "buf, best_ms or reps (1..1000)");
   if (buf_bytes < need) return set_err(GSK_ERR_WORKSPACE, "buf needs %zu bytes", need);
   if ((int64_t)((n + gsk::BS - 1) / gsk::BS) > (int64_t)INT32_MAX / 2)
     return set_err(GSK_ERR_INVALID_ARG, "n too large");

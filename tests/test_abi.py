@@ -278,3 +278,5 @@ def test_stream_mix_sizes_and_rejections(lib):
         lib.ERR_WORKSPACE
     assert L.gsk_stream_mix_ms(11, 2, n, 0x100000, 1 << 20, 0, ctypes.byref(ms), None) == \
         lib.ERR_INVALID_ARG
+    assert L.gsk_stream_mix_ms(11, 2, n, 0x100000, 1 << 20, 1001, ctypes.byref(ms), None) == \
+        lib.ERR_INVALID_ARG
