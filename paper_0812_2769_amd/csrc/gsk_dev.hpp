@@ -27,14 +27,14 @@ constexpr int MMAX = 64;            // largest GMRES restart length
 constexpr int NC_MAX = MMAX + 2;    // most values reduced in one launch
 // Partials one thread of a finalize launch loads at once per column: SUM_BATCH, or in the single
 // solvers' finalize launches for sums of more than SUM_BATCH * BS partials (a large system has
-// tens of thousands of tiles) sum_batch<NC>() for NC columns (at most 64 values in flight per
+// tens of thousands of tiles) sum_batch<NC>() for NC columns (at most 128 values in flight per
 // thread; those launches are instantiated for both, so that a small sum keeps the short
 // kernel). A thread adds its partials t, t + BS, t + 2 BS, ... in that order whatever
 // the batch, so the batch changes the number of memory round trips of a sum, not its value.
 constexpr int SUM_BATCH = 8;
 template <int NC>
 constexpr int sum_batch() {
-  return NC <= 2 ? 32 : 16;
+  return NC <= 4 ? 32 : 16;
 }
 
 // acc[c] += partials[c * stride + l] for l = t, t + BS, ... < count, in that order, loading SB
