@@ -79,6 +79,7 @@ __global__ __launch_bounds__(64) void k_bicg_init_ctl(Ctl* c, int maxit, double 
   c->ref = 0.0;
   c->ratio = 1.0;
   c->rho = c->rho_old = c->alpha = c->omega = c->beta = c->rh_norm = 0.0;
+  c->fin_count = 0;
 }
 
 // R: r = b - A x, r^ = r (initial residual, verification, or final residual after a
@@ -406,7 +407,11 @@ __global__ __launch_bounds__(BS) void k_bicg_fin_p(Ctl* c, const double* partial
   const int state = c->sum.state;
   const double eps_b = c->eps_b, rh_norm = c->rh_norm, rho = c->rho;
   __shared__ double out[8];
-  small_sums<2, BIG ? sum_batch<2>() : SUM_BATCH>(partials, nb, out);
+  if constexpr (BIG) {
+    if (!split_sums<2, sum_batch<2>()>(c, partials, nb, out)) return;
+  } else {
+    small_sums<2, SUM_BATCH>(partials, nb, out);
+  }
   if (state != ST_RUNNING || threadIdx.x != 0) return;
   const double sigma = out[0];
   const double vn = sqrt(out[1]);
@@ -470,7 +475,11 @@ __global__ __launch_bounds__(BS) void k_bicg_fin_s(Ctl* c, const double* partial
   const int state = c->sum.state, iters = c->sum.iters;
   const double ref = c->ref, tol = c->tol, eps_b = c->eps_b;
   __shared__ double out[8];
-  small_sums<4, BIG ? sum_batch<4>() : SUM_BATCH>(partials, nb, out);
+  if constexpr (BIG) {
+    if (!split_sums<4, sum_batch<4>()>(c, partials, nb, out)) return;
+  } else {
+    small_sums<4, SUM_BATCH>(partials, nb, out);
+  }
   if (state != ST_RUNNING || threadIdx.x != 0) return;
   c->sum.iters = iters + 1;
   const double sn = sqrt(out[2]);
@@ -538,7 +547,11 @@ __global__ __launch_bounds__(BS) void k_bicg_fin_u(Ctl* c, const double* partial
   const double ref = c->ref, tol = c->tol, eps_b = c->eps_b, rh_norm = c->rh_norm;
   const double rho = c->rho, alpha = c->alpha, omega = c->omega;
   __shared__ double out[8];
-  small_sums<3, BIG ? sum_batch<3>() : SUM_BATCH>(partials, nb, out);
+  if constexpr (BIG) {
+    if (!split_sums<3, sum_batch<3>()>(c, partials, nb, out)) return;
+  } else {
+    small_sums<3, SUM_BATCH>(partials, nb, out);
+  }
   if (threadIdx.x != 0) return;
   if (st == ST_HALF) {
     c->sum.state = ST_VERIFY;
@@ -595,10 +608,12 @@ static void launch_iteration(const BArgs& a, const Op& op, int nb, int par, hipS
   } else {
     launch_probed(k_bicg_p<Op>, dim3(nb), s, ax.pslot, ax, op);
   }
-  // finalize launches with larger batches of partials for systems of many tiles
+  // systems of many tiles: finalize launches split over WAVES workgroups, with larger
+  // batches of partials (the same sums)
   const bool big = nb > SUM_BATCH * BS;
-  hipLaunchKernelGGL(big ? k_bicg_fin_p<true> : k_bicg_fin_p<false>, dim3(1), dim3(BS), 0, s,
-                     a.ctl, pt, nb);
+  const dim3 fg(big ? WAVES : 1), fb(big ? 64 : BS);
+  hipLaunchKernelGGL(big ? k_bicg_fin_p<true> : k_bicg_fin_p<false>, fg, fb, 0, s, a.ctl, pt,
+                     nb);
   ax.pslot = probe ? probe_slot(KC_BICG_S) : -1;
   if constexpr (std::is_same_v<Op, StencilOp>) {
     if (window) launch_probed(k_bicg_s_win, gw, s, ax.pslot, ax, op, nb);
@@ -606,12 +621,12 @@ static void launch_iteration(const BArgs& a, const Op& op, int nb, int par, hipS
   } else {
     launch_probed(k_bicg_s<Op>, dim3(nb), s, ax.pslot, ax, op);
   }
-  hipLaunchKernelGGL(big ? k_bicg_fin_s<true> : k_bicg_fin_s<false>, dim3(1), dim3(BS), 0, s,
-                     a.ctl, pt, nb, hw);
+  hipLaunchKernelGGL(big ? k_bicg_fin_s<true> : k_bicg_fin_s<false>, fg, fb, 0, s, a.ctl, pt,
+                     nb, hw);
   ax.pslot = probe ? probe_slot(KC_BICG_U) : -1;
   launch_probed(k_bicg_u, dim3(nb), s, ax.pslot, ax);
-  hipLaunchKernelGGL(big ? k_bicg_fin_u<true> : k_bicg_fin_u<false>, dim3(1), dim3(BS), 0, s,
-                     a.ctl, pt, nb, hw);
+  hipLaunchKernelGGL(big ? k_bicg_fin_u<true> : k_bicg_fin_u<false>, fg, fb, 0, s, a.ctl, pt,
+                     nb, hw);
 }
 
 static SolveResult bfail(int code) {

@@ -39,14 +39,16 @@ constexpr int sum_batch() {
 
 // acc[c] += partials[c * stride + l] for l = t, t + BS, ... < count, in that order, loading SB
 // values per column before adding them.
+// The thread's index t in [0, BS) is an argument, so that the split finalize (split_sums) can
+// run the thread of index t of the one-workgroup sum in another workgroup.
 template <int NC, int SB>
-__device__ inline void sweep_partials(const double* __restrict__ partials, int count, int stride,
-                                      double (&acc)[NC]) {
+__device__ inline void sweep_partials_of(const double* __restrict__ partials, int count,
+                                         int stride, int t, double (&acc)[NC]) {
   for (int base = 0; base < count; base += SB * BS) {
     double v[NC][SB];
 #pragma unroll
     for (int q = 0; q < SB; ++q) {
-      const int l = base + q * BS + (int)threadIdx.x;
+      const int l = base + q * BS + t;
 #pragma unroll
       for (int c = 0; c < NC; ++c) v[c][q] = l < count ? partials[(size_t)c * stride + l] : 0.0;
     }
@@ -55,6 +57,12 @@ __device__ inline void sweep_partials(const double* __restrict__ partials, int c
 #pragma unroll
       for (int q = 0; q < SB; ++q) acc[c] += v[c][q];
   }
+}
+
+template <int NC, int SB>
+__device__ inline void sweep_partials(const double* __restrict__ partials, int count, int stride,
+                                      double (&acc)[NC]) {
+  sweep_partials_of<NC, SB>(partials, count, stride, (int)threadIdx.x, acc);
 }
 
 // Solver state machine (Ctl::state)
@@ -112,6 +120,11 @@ struct Ctl {
   double last_rt;            // GMRES: relative true residual at the start of the cycle
   // Bi-CGSTAB scalars
   double rho, rho_old, alpha, omega, beta, rh_norm;
+  // Split finalize of a large single-solver Bi-CGSTAB sum (split_sums): the wave sums of the
+  // workgroups, column-major by wave, and the count of workgroups that have stored theirs.
+  double wsum[4 * WAVES];
+  int fin_count;
+  int pad2;
   // GMRES: lazy column scales, orthogonalisation coefficients, Hessenberg + Givens. The
   // pass-1 values of step j sit in slot j % 2: the single solver finalises step j-1 in the
   // launch that reduces the pass-1 sums of step j.
@@ -374,6 +387,52 @@ __device__ inline void small_sums_strided(const double* __restrict__ partials, i
 template <int NC, int SB = SUM_BATCH>
 __device__ inline void small_sums(const double* __restrict__ partials, int nb, double* out) {
   small_sums_strided<NC, SB>(partials, nb, nb, out);
+}
+
+// small_sums over WAVES workgroups of one wave, so that WAVES compute units read the partials:
+// workgroup w runs the threads 64 w .. 64 w + 63 of the one-workgroup sum (the same additions
+// in the same order, and the same wave tree) and stores its NC wave sums into c->wsum; the
+// workgroup that stores last then adds the WAVES wave sums of each column in wave order, as
+// the one-workgroup tree does. The result is small_sums' bit for bit. Returns true in that
+// last workgroup, whose out[0..NC) then hold the sums (all its threads); false elsewhere.
+// Launch with dim3(WAVES) x dim3(64); c->fin_count must be 0 at the launch (the last
+// workgroup leaves it 0). No workgroup waits for another.
+template <int NC, int SB>
+__device__ inline bool split_sums(Ctl* c, const double* __restrict__ partials, int nb,
+                                  double* out) {
+  static_assert(NC <= 4, "c->wsum holds four columns");
+  const int lane = threadIdx.x;
+  const int w = blockIdx.x;
+  double acc[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) acc[k] = 0.0;
+  sweep_partials_of<NC, SB>(partials, nb, nb, w * 64 + lane, acc);
+  double v[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) v[k] = wave_sum(acc[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+      __hip_atomic_store(&c->wsum[k * WAVES + w], v[k], __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __threadfence();   // release: the wave sums reach device scope before the count
+  int arrived = 0;
+  if (lane == 0) arrived = atomicAdd(&c->fin_count, 1);
+  arrived = __builtin_amdgcn_readfirstlane(arrived);
+  if (arrived != WAVES - 1) return false;
+  __threadfence();   // acquire: the other workgroups' wave sums
+  if (lane < NC) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < WAVES; ++q)
+      t += __hip_atomic_load(&c->wsum[lane * WAVES + q], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    out[lane] = t;
+  }
+  if (lane == 0) c->fin_count = 0;   // the next launch runs after this one has ended
+  __syncthreads();
+  return true;
 }
 
 // ---------------------------------------------------------------------------------------
