@@ -235,6 +235,18 @@ def _vec(t: torch.Tensor, n: int, name: str) -> torch.Tensor:
     return t
 
 
+def _opt_vec(t: Optional[torch.Tensor], n: int, name: str) -> Optional[int]:
+    """Device pointer of an optional float64 vector of n elements (None stays None)."""
+    return None if t is None else _vec(t, n, name).data_ptr()
+
+
+def _ws(ws: torch.Tensor):
+    """(pointer, bytes) of a workspace tensor: contiguous device memory of any element type."""
+    if not ws.is_cuda or not ws.is_contiguous():
+        raise ValueError("ws must be a contiguous CUDA tensor")
+    return ws.data_ptr(), ws.numel() * ws.element_size()
+
+
 @dataclasses.dataclass
 class Info:
     iters: int
@@ -363,8 +375,8 @@ def gs_scale(A: CsrMatrix, b: torch.Tensor, p: int = 2, *, inplace: bool = False
         ws = workspace(METHOD_GS, A.n, 0, A.device)
     c = A.c_struct()
     _check(lib.gsk_gs_scale(ctypes.byref(c), b.data_ptr(), int(p), val_out.data_ptr(),
-                            b_out.data_ptr(), _ptr(norms), _ptr(weights), ws.data_ptr(),
-                            ws.numel(), _stream(A.device)))
+                            b_out.data_ptr(), _ptr(norms), _ptr(weights), *_ws(ws),
+                            _stream(A.device)))
     return A.with_values(val_out), b_out, norms, weights
 
 
@@ -376,14 +388,17 @@ def gs_scale_into(A: CsrMatrix, b: torch.Tensor, p: int, val_out: torch.Tensor,
     stop weights and row norms."""
     _vec(b, A.n, "b")
     _vec(b_out, A.n, "b_out")
-    if val_out.numel() != A.val.numel() or val_out.dtype != torch.float64:
-        raise GskError(ERR_INVALID_ARG, "val_out must hold nnz float64 values")
+    if (val_out.numel() != A.val.numel() or val_out.dtype != torch.float64
+            or not val_out.is_cuda or not val_out.is_contiguous()):
+        raise GskError(ERR_INVALID_ARG, "val_out must be a contiguous CUDA tensor of nnz "
+                                        "float64 values")
     if ws is None:
         ws = workspace(METHOD_GS, A.n, 0, A.device)
     c = A.c_struct()
     _check(lib.gsk_gs_scale(ctypes.byref(c), b.data_ptr(), int(p), val_out.data_ptr(),
-                            b_out.data_ptr(), _ptr(norms), _ptr(weights), ws.data_ptr(),
-                            ws.numel(), _stream(A.device)))
+                            b_out.data_ptr(), _opt_vec(norms, A.n, "norms"),
+                            _opt_vec(weights, A.n, "weights"), *_ws(ws),
+                            _stream(A.device)))
 
 
 def spmv(A, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
@@ -401,12 +416,12 @@ def stencil_from_csr(A: CsrMatrix, nx: int, ny: int, nz: int = 1,
     """Pack a CSR matrix with a 5/7-point pattern into a StencilMatrix."""
     planes = 7 if nz > 1 else 5
     coef = (torch.empty(planes * A.n, dtype=torch.float64, device=A.device) if out is None
-            else out)
+            else _vec(out, planes * A.n, "out"))
     if ws is None:
         ws = workspace(METHOD_GS, A.n, 0, A.device)
     c = A.c_struct()
     _check(lib.gsk_stencil_from_csr(ctypes.byref(c), int(nx), int(ny), int(nz), coef.data_ptr(),
-                                    ws.data_ptr(), ws.numel(), _stream(A.device)))
+                                    *_ws(ws), _stream(A.device)))
     return StencilMatrix(nx, ny, nz, coef)
 
 
@@ -421,7 +436,7 @@ def arnoldi(A, r0: torch.Tensor, m: int, ws: Optional[torch.Tensor] = None):
         ws = workspace(METHOD_ARNOLDI, A.n, m, A.device)
     c = A.c_matrix()
     _check(lib.gsk_arnoldi(ctypes.byref(c), r0.data_ptr(), int(m), Vs.data_ptr(), A.n,
-                           Hs.data_ptr(), ctypes.byref(steps), ws.data_ptr(), ws.numel(),
+                           Hs.data_ptr(), ctypes.byref(steps), *_ws(ws),
                            _stream(A.device)))
     return Vs.t(), Hs.t(), int(steps.value)
 
@@ -468,7 +483,7 @@ def gmres(A, b: torch.Tensor, x0: Optional[torch.Tensor] = None, m: int = 30,
     info = InfoStruct()
     c = A.c_matrix()
     _check(lib.gsk_gmres(ctypes.byref(c), b.data_ptr(), x.data_ptr(), int(m), float(tol),
-                         ctypes.byref(o), ctypes.byref(info), ws.data_ptr(), ws.numel(),
+                         ctypes.byref(o), ctypes.byref(info), *_ws(ws),
                          _stream(A.device)))
     return x, _info(info)
 
@@ -487,7 +502,7 @@ def gmres_mixed(A, b: torch.Tensor, x0: Optional[torch.Tensor] = None, m: int = 
     info = InfoStruct()
     c = A.c_matrix()
     _check(lib.gsk_gmres_mixed(ctypes.byref(c), b.data_ptr(), x.data_ptr(), int(m), float(tol),
-                               ctypes.byref(o), ctypes.byref(info), ws.data_ptr(), ws.numel(),
+                               ctypes.byref(o), ctypes.byref(info), *_ws(ws),
                                _stream(A.device)))
     return x, _info(info)
 
@@ -505,7 +520,7 @@ def bicgstab(A, b: torch.Tensor, x0: Optional[torch.Tensor] = None,
     info = InfoStruct()
     c = A.c_matrix()
     _check(lib.gsk_bicgstab(ctypes.byref(c), b.data_ptr(), x.data_ptr(), float(tol),
-                            ctypes.byref(o), ctypes.byref(info), ws.data_ptr(), ws.numel(),
+                            ctypes.byref(o), ctypes.byref(info), *_ws(ws),
                             _stream(A.device)))
     return x, _info(info)
 
@@ -733,5 +748,5 @@ def bicgstab_batch(As, bs, tol: float = 1e-8, *, xs=None, maxit: Optional[int] =
     o = _options(maxit, breakdown_eps, None, check_every, As[0].n)
     infos = (InfoStruct * count)()
     _check(lib.gsk_bicgstab_batch(count, mats, bp, xp, float(tol), ctypes.byref(o), infos,
-                                  ws.data_ptr(), ws.numel(), _stream(As[0].device)))
+                                  *_ws(ws), _stream(As[0].device)))
     return xs, [_info(i) for i in infos]

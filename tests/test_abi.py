@@ -158,6 +158,13 @@ def test_binding_refuses_cpu_tensors(lib):
     with pytest.raises(ValueError):
         lib.CsrMatrix(torch.zeros(3, dtype=torch.int32), torch.zeros(2, dtype=torch.int32),
                       torch.zeros(2, dtype=torch.float64))
+    # workspaces and optional outputs must be device memory too (a host pointer handed to a
+    # kernel would fault the GPU)
+    with pytest.raises(ValueError):
+        lib._ws(torch.zeros(1024, dtype=torch.uint8))
+    with pytest.raises(ValueError):
+        lib._opt_vec(torch.zeros(3, dtype=torch.float64), 3, "weights")
+    assert lib._opt_vec(None, 3, "weights") is None
 
 
 def test_engine_struct_layouts_and_rejections(lib):
