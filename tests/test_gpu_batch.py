@@ -325,3 +325,44 @@ def test_engine_beyond_the_cache_equals_solo(G):
     for k in ref:
         same((host(xs[k]), done[k]), ref[k])
     eng.close()
+
+
+def test_large_single_solves_equal_engine_on_every_exit(G):
+    """A single solve of a system of over 2,048 tiles splits its finalize sums over four
+    workgroups; the engine sums each system's partials in one. The results must still be equal
+    bit for bit, whatever ends the solve: the iteration cap, loose tolerances (half- or
+    full-step exits), a converged solve, GS(1) with stop weights, the stencil product (LDS
+    window) and the CSR product."""
+    import torch
+    P = problems.laplacian((84, 84, 84), conv=(30.0, -20.0, 10.0))
+    assert P.n > 2048 * 256
+    cases = []
+    for stencil in (True, False):
+        M, b, _ = scaled(G, P, 2, stencil)
+        for tol, maxit in ((1e-8, 3), (0.9, None), (0.3, None), (1e-6, None)):
+            cases.append((M, b, None, tol, maxit))
+    M, b, w = scaled(G, P, 1, True)
+    cases.append((M, b, w, 1e-6, None))
+    ref = []
+    for M, b, w, tol, maxit in cases:
+        x, info = G.bicgstab(M, b, tol=tol, maxit=maxit, stop_weights=w)
+        ref.append((host(x), info))
+    assert any(i.status == G.MAXIT for _, i in ref)
+    assert any(i.status == G.CONVERGED and i.iters > 10 for _, i in ref)
+    unit = 256
+    rows = sum((M.n + unit - 1) // unit * unit for M, _, _, _, _ in cases)
+    eng = G.Engine(max_rows=rows, max_systems=len(cases), check_every=8, graph=True)
+    xs = [torch.zeros_like(b) for _, b, _, _, _ in cases]
+    for k, (M, b, w, tol, maxit) in enumerate(cases):
+        assert eng.submit(M, b, xs[k], tol=tol, tag=k, maxit=maxit, stop_weights=w)
+    done = {}
+    for _ in range(5000):
+        eng.run(1)
+        done.update(dict(eng.poll()))
+        if len(done) == len(cases):
+            break
+    torch.cuda.synchronize()
+    assert len(done) == len(cases)
+    for k in range(len(cases)):
+        same((host(xs[k]), done[k]), ref[k])
+    eng.close()
