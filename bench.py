@@ -352,6 +352,18 @@ def measured_copy_peak(dev, mib=1024, reps=10):
             "kernel": f"device-to-device copy of {mib} MiB (read + written bytes), best of {reps}"}
 
 
+def device_info(dev):
+    """What the runtime reports for the device the line was measured on (compute units, wave
+    size, memory, L2), beside the published figures the roofline uses."""
+    import torch
+    pr = torch.cuda.get_device_properties(dev)
+    return {"name": pr.name, "arch": getattr(pr, "gcnArchName", ""),
+            "compute_units": pr.multi_processor_count, "wave_size": pr.warp_size,
+            "hbm_GiB": round(pr.total_memory / 2 ** 30, 1),
+            "l2_cache_bytes": getattr(pr, "L2_cache_size", None),
+            "lds_bytes_per_workgroup": getattr(pr, "shared_memory_per_block", None)}
+
+
 def bench_batch(args, gsk, problems, dev):
     """batch512: a batch of independent GS(2) + Bi-CGSTAB (or GMRES(20)) solves, tol 1e-8, run
     by the engine with every chunk replayed from a HIP graph."""
@@ -515,6 +527,7 @@ def bench_batch(args, gsk, problems, dev):
                     "included)"},
         "engine_tuning": tuned,
         "measured_copy_peak": measured_copy_peak(dev),
+        "device": device_info(dev),
         "roofline": None, "cpu_baseline": None,
     }
     a = achieved(pr)
