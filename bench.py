@@ -184,14 +184,24 @@ def log(msg):
 def host_cpu():
     """The host's processor model and the cores this process may use."""
     model = None
+    ids = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
+                key, _, val = line.partition(":")
+                key = key.strip()
+                if key == "model name" and model is None:
+                    model = val.strip()
+                elif key in ("cpu family", "model") and key not in ids:
+                    ids[key] = val.strip()
+                elif not line.strip() and model is not None:
+                    break   # first processor's block read
     except OSError:
         pass
+    if model is not None and ids:
+        # the model name can be generic under virtualisation; family and model numbers
+        # identify the core generation
+        model = f"{model} (family {ids.get('cpu family', '?')}, model {ids.get('model', '?')})"
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
