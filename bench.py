@@ -619,6 +619,8 @@ def bench_batch(args, gsk, problems, dev):
         torch.cuda.empty_cache()
         log("extras: 80^3 slabs")
         ex = {"slabs80": extra_slabs80(gsk, problems, dev)}
+        log("extras: 64^2 square jump")
+        ex["square64"] = extra_square64(gsk, problems, dev)
         torch.cuda.empty_cache()
         log("extras: 160^3 checkerboard")
         ex["checker160"] = extra_checker160(gsk, problems, dev)
@@ -935,6 +937,71 @@ def extra_slabs80(gsk, problems, dev):
             "k_gmres_a_avg_launch_us": a["avg_launch_us"] if a else None,
             "note": "working set fits in the 256 MB Infinity Cache: fabric bandwidth, not an "
                     "HBM figure"}
+
+
+def extra_square64(gsk, problems, dev, solves=30, gmres_solves=5):
+    """The 64^2 square-jump system (4,096 unknowns) from the unscaled CSR matrix in HBM, scaled
+    by GS(2) and packed into 5-point planes for each solve, one solve at a time, tol 1e-8:
+    GMRES(20), which stagnates near 4.5e-4 on this system and runs to the 10,000-step cap
+    (reported with the residual it reached), and Bi-CGSTAB, which converges. At this size a
+    solve is bound by launch and reduction latency, not bandwidth: the figures are latency,
+    steps/s and solves/s, beside the oracle's time for the same solves on one host thread."""
+    import torch
+    import oracle
+    P = problems.square_jump_2d(64)
+    N = P.dims[0]
+    A = gsk.CsrMatrix.from_problem(P, dev)
+    b = torch.from_numpy(P.b).to(dev)
+    val_s, b_s = torch.empty_like(A.val), torch.empty_like(b)
+    x = torch.empty_like(b)
+    coef = torch.empty(5 * P.n, dtype=torch.float64, device=dev)
+    As = A.with_values(val_s)
+    S = gsk.StencilMatrix(N, N, 1, coef)
+    ws_gs = gsk.workspace(gsk.METHOD_GS, P.n, 0, dev)
+    ws_gm = gsk.workspace(gsk.METHOD_GMRES, P.n, 20, dev)
+    ws_bi = gsk.workspace(gsk.METHOD_BICGSTAB, P.n, 0, dev)
+
+    def solve(method):
+        gsk.gs_scale_into(A, b, 2, val_s, b_s, ws=ws_gs)
+        gsk.stencil_from_csr(As, N, N, 1, out=coef, ws=ws_gs)
+        if method == "gmres20":
+            return gsk.gmres(S, b_s, m=20, tol=1e-8, ws=ws_gm, x_out=x)[1]
+        return gsk.bicgstab(S, b_s, tol=1e-8, ws=ws_bi, x_out=x)[1]
+
+    vo, bo, _, _ = oracle.gs_scale(P, P.b, 2)
+    Po = P.copy()
+    Po.val, Po.b = vo, bo
+    out = {"workload": "64^2 5-point, a = 1e3 on the centred square, convection (10, 10); "
+                       "GS(2) + GMRES(20) or Bi-CGSTAB, FP64, tol 1e-8, stencil operator",
+           "note": "latency-bound: 4,096 rows are 16 tiles; oracle = the same solve by the "
+                   "sequential C oracle on one host thread"}
+    for method, count in (("gmres20", gmres_solves), ("bicgstab", solves)):
+        for _ in range(2):
+            solve(method)
+        torch.cuda.synchronize()
+        lat = []
+        t0 = time.perf_counter()
+        for _ in range(count):
+            t = time.perf_counter()
+            info = solve(method)
+            lat.append(time.perf_counter() - t)
+        elapsed = time.perf_counter() - t0
+        t = time.perf_counter()
+        if method == "gmres20":
+            _, oinfo = oracle.gmres(Po, bo, m=20, tol=1e-8)
+        else:
+            _, oinfo = oracle.bicgstab(Po, bo, tol=1e-8)
+        t_oracle = time.perf_counter() - t
+        out[method] = {"solves": count, "iters": info.iters, "status": info.status_name,
+                       "relres_true": info.relres_true,
+                       "converged_per_s": round(count * (info.status == gsk.CONVERGED)
+                                                / elapsed, 2),
+                       "iters_per_s": round(count * info.iters / elapsed, 1),
+                       "p50_ms": round(1e3 * pct(lat, 0.5), 3),
+                       "p99_ms": round(1e3 * pct(lat, 0.99), 3),
+                       "oracle_s": round(t_oracle, 3), "oracle_iters": oinfo.iters,
+                       "oracle_status": oinfo.status_name}
+    return out
 
 
 def extra_checker160(gsk, problems, dev):
