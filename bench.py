@@ -275,14 +275,15 @@ def batch_cpu_baseline(host, tol, threads):
         vo, bo, _, _ = oracle.gs_scale(P, P.b, 2)
         S = P.copy()
         S.val, S.b = vo, bo
-        _, info = oracle.bicgstab(S, bo, tol=tol)
-        return info
+        return oracle.bicgstab(S, bo, tol=tol)
 
     items = sorted(host.items())
     t0 = time.perf_counter()
     with ThreadPoolExecutor(max_workers=threads) as ex:
-        infos = list(ex.map(lambda kv: one(kv[1]), items))
+        results = list(ex.map(lambda kv: one(kv[1]), items))
     wall = time.perf_counter() - t0
+    infos = [info for _, info in results]
+    per_system = {i: r for (i, _), r in zip(items, results)}
     conv = sum(1 for i in infos if i.status == oracle.CONVERGED)
     cpu = host_cpu()
     return {"value": round(conv / wall, 4), "unit": "solves/s", "cores": threads,
@@ -294,7 +295,29 @@ def batch_cpu_baseline(host, tol, threads):
             "converged": conv, "wall_s": round(wall, 2),
             "iterations": int(sum(i.iters for i in infos)),
             "host_cpu": cpu["model"], "host_nproc": cpu["nproc"],
-            "host_cores_available": cpu["cores_available"]}
+            "host_cores_available": cpu["cores_available"]}, per_system
+
+
+def batch_oracle_parity(per_system, infos, xs):
+    """The engine's results on the oracle's sampled systems (full batch, the timed launch
+    configuration) against the oracle's: equal statuses, iteration counts (relative
+    difference), and solutions (largest difference over the largest entry of the oracle's x;
+    two solutions to a relative residual of 1e-8 may differ by up to cond(A) x 1e-8)."""
+    import numpy as np
+    st_eq, rel_it, rel_x = 0, [], []
+    for i, (xo, io) in per_system.items():
+        ig = infos[i]
+        st_eq += int(ig.status == io.status)
+        rel_it.append(abs(ig.iters - io.iters) / max(io.iters, 1))
+        xg = xs[i].cpu().numpy()
+        rel_x.append(float(np.max(np.abs(xg - xo)) / max(float(np.max(np.abs(xo))), 1e-300)))
+    rel_it, rel_x = np.array(rel_it), np.array(rel_x)
+    return {"systems": len(per_system), "status_equal": st_eq,
+            "iters_within_5pct": int(np.sum(rel_it <= 0.05)),
+            "iters_rel_diff": {"median": round(float(np.median(rel_it)), 4),
+                               "max": round(float(np.max(rel_it)), 4)},
+            "x_rel_diff": {"median": float(f"{np.median(rel_x):.3g}"),
+                           "max": float(f"{np.max(rel_x):.3g}")}}
 
 
 def batch_iter_bytes(systems, infos, gmres, mixed):
@@ -613,7 +636,8 @@ def bench_batch(args, gsk, problems, dev):
     if want_cpu:
         threads = cpu_threads()
         log(f"timing the CPU oracle on {len(host)} sampled systems, {threads} threads")
-        out["cpu_baseline"] = batch_cpu_baseline(host, tol, threads)
+        out["cpu_baseline"], per_system = batch_cpu_baseline(host, tol, threads)
+        out["oracle_parity"] = batch_oracle_parity(per_system, infos, xs)
     if not args.no_extras and not gmres and not mixed:
         del systems, xs, xbuf
         torch.cuda.empty_cache()
