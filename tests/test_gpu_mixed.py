@@ -207,6 +207,27 @@ def test_checker160_full_size_two_cycles_vs_oracle(G, checker160):
     np.testing.assert_allclose(host(x), xo, rtol=1e-8, atol=1e-10 * np.abs(xo).max())
 
 
+def test_checker160_full_size_mixed_two_cycles_vs_oracle(G, checker160):
+    """The configuration's own solver at full size: GMRES(30) with FP32 Arnoldi cycles and
+    FP64 restarts on the 160^3 system after GS(2), bounded to two cycles (60 Arnoldi steps),
+    against the oracle's orc_gmres_ir on its own scaled system. Both store the matrix, the
+    basis and w in FP32 and compute in FP64, but the device's sums run in another order, so a
+    stored FP32 value can round the other way. Over two cycles that stays near FP32 rounding
+    (6e-8; measured 1e-8 on the residual, 7e-8 on x): the bar is 1e-6 relative for both."""
+    P = checker160
+    M, bs, _ = gpu_scaled(G, P)
+    x, info = G.gmres_mixed(M, bs, m=30, tol=1e-8, maxit=60)
+    S, _ = oracle_scaled(P)
+    xo, io = oracle.gmres_ir(S, S.b, m=30, tol=1e-8, maxit=60)
+    rel_res = abs(info.relres_true - io.relres_true) / io.relres_true
+    rel_x = np.linalg.norm(host(x) - xo) / np.linalg.norm(xo)
+    print(f"mixed 160^3 two cycles: relres {info.relres_true:.6e} vs {io.relres_true:.6e} "
+          f"(rel {rel_res:.2e}), x rel {rel_x:.2e}")
+    assert info.status == io.status == G.MAXIT and info.iters == io.iters == 60
+    assert rel_res < 1e-6
+    assert rel_x < 1e-6
+
+
 def test_checker160_full_size_gs_and_spmv_sampled(G, checker160):
     """The 160^3 system at full size (n = 4,096,000): GS(1) and GS(2) outputs (scaled values,
     right-hand side, row norms, stop weights) and the scaled matrix's product through the CSR
