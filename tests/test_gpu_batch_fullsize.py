@@ -108,3 +108,51 @@ def test_full_batch_against_the_oracle(G):
             assert 0.95 * lo <= res["g_iters"] <= 1.05 * hi, res
     print(f"sampled {len(results)} systems; {moved} counts beyond 5% of the oracle's, each "
           f"within its perturbed spread")
+
+
+def test_full_mixed_batch_reaches_the_tolerance(G):
+    """The same 512 systems in the mixed-precision engine (FP32 storage, FP64 refinement, FP64
+    continuation where refinement stops paying), as the benchmark's mixed form runs them: every
+    system converges, and on 24 seeded samples at full size the oracle's true relative residual
+    of the returned x (FP64, on the oracle's own GS(2)-scaled system) is below the tolerance."""
+    import torch
+    specs = problems.batch_specs(512)
+    pick = set(int(i) for i in np.random.default_rng(1010).choice(512, 24, replace=False))
+    keep, host = [], {}
+    for i, sp in enumerate(specs):
+        P = problems.batch_system(sp)
+        d = list(P.dims) + [1] * (3 - len(P.dims))
+        A = G.CsrMatrix.from_problem(P)
+        keep.append((G.stencil_from_csr(A, *d), torch.from_numpy(P.b).cuda(), P.n))
+        del A
+        if i in pick:
+            host[i] = P
+    rows = sum((n + 511) // 512 * 512 for _, _, n in keep)
+    eng = G.Engine(rows, len(keep), check_every=16, graph=True, precision="mixed")
+    xs = [torch.zeros_like(b) for _, b, _ in keep]
+    for i, (S, b, _) in enumerate(keep):
+        assert eng.submit_gs(S, b, xs[i], p=2, tol=TOL, tag=i)
+    done = {}
+    for _ in range(20000):
+        eng.run(1)
+        done.update(dict(eng.poll()))
+        if len(done) == len(keep):
+            break
+    torch.cuda.synchronize()
+    eng.close()
+    assert len(done) == len(keep)
+    assert all(info.status == G.CONVERGED for info in done.values())
+    switched = sum(1 for info in done.values() if info.fp64_from > 0)
+
+    def residual(i):
+        S = _oracle_scaled(host[i])
+        r = S.b - oracle.spmv(S, xs[i].cpu().numpy())
+        return i, float(np.linalg.norm(r) / np.linalg.norm(S.b))
+
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        res = list(ex.map(residual, sorted(host)))
+    for i, rel in res:
+        assert rel < 1.01 * TOL, (i, rel, done[i])
+    print(f"mixed batch: 512 converged, {switched} after changing over to FP64; sampled "
+          f"residuals up to {max(r for _, r in res):.2e}")
