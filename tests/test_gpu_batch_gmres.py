@@ -212,3 +212,39 @@ def test_gmres_engine_arguments(G):
                  else 65)
     with pytest.raises(G.GskError):
         G.Engine(1024, 4, method="bicgstab", precision="mixed", inner_reduction=1.5)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_gmres_engine_streaming_largest_systems_equal_solo(G, precision):
+    """The 14 largest 3D systems of the 512-system workload (about 11 M rows: the engine's
+    admitted cycle working set is far beyond the 256 MB last-level cache, so its chunks take
+    the non-temporal load policy and, in FP64, the LDS-window product), each bounded to five
+    GMRES(20) cycles. Alone, each system's cycle fits in the cache and the single solver takes
+    ordinary loads and the plain product. The results must still be equal bit for bit."""
+    import torch
+    specs = problems.batch_specs(512)
+    sizes = [int(np.prod(s["dims"])) for s in specs]
+    pick = sorted((i for i, s in enumerate(specs) if len(s["dims"]) == 3),
+                  key=sizes.__getitem__)[-14:]
+    width = 4 if precision == "mixed" else 8
+    assert (M + 2) * width * sum(sizes[i] for i in pick) > 2 * 256 * 2 ** 20
+    syst = [scaled(G, problems.batch_system(specs[i])) for i in pick]
+    f = G.gmres_mixed if precision == "mixed" else G.gmres
+    ref = [(host(x), info) for x, info in
+           (f(A, b, m=M, tol=1e-8, maxit=5 * M) for A, b, _ in syst)]
+    rows = sum((A.n + 511) // 512 * 512 for A, _, _ in syst)
+    eng = G.Engine(rows, len(syst), graph=True, method="gmres", m=M, precision=precision)
+    xs = [torch.zeros_like(b) for _, b, _ in syst]
+    for k, (A, b, _) in enumerate(syst):
+        assert eng.submit(A, b, xs[k], tol=1e-8, tag=k, maxit=5 * M)
+    res = {}
+    for _ in range(100):
+        eng.run(1)
+        res.update(dict(eng.poll(wait=True)))
+        if len(res) == len(syst):
+            break
+    torch.cuda.synchronize()
+    eng.close()
+    assert len(res) == len(syst)
+    for k in range(len(syst)):
+        same((host(xs[k]), res[k]), ref[k], (precision, pick[k]))
