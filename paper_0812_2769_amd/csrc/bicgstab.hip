@@ -1,7 +1,8 @@
 // Bi-CGSTAB (van der Vorst; section 2 of the paper) on the device, shadow residual r^ = r0.
 //
-// One iteration is three streaming launches, each followed by a one-workgroup finalize launch
-// that sums the per-workgroup partials in a fixed order; every scalar stays on the device:
+// One iteration is three streaming launches, each followed by a finalize launch that sums the
+// per-tile partials in a fixed order (one workgroup; for systems of many tiles four one-wave
+// workgroups with the same additions, see split_sums); every scalar stays on the device:
 //
 //   P  p = r + beta (p - omega v)       (p = r on the first iteration after a (re)start)
 //      v = A p, with the p entries of neighbouring rows recomputed inside the gather, so p
