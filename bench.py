@@ -67,13 +67,13 @@ BATCH_SOURCES = ["paper_0812_2769_amd/csrc/batch.hip", "paper_0812_2769_amd/csrc
 TRAFFIC = [
     # the 512-system batch: P launches of full-batch iterations
     {"probe": "batch_p", "grid": None, "ratio": 8.536 / 8.491, "sources": BATCH_SOURCES,
-     "sources_sha256_16": "a020ce730aa49140"},
+     "sources_sha256_16": "31777f05ccd859a5"},
     # FP64 GMRES(30) on the 160^3 checkerboard: the A launches of two cycles
     {"probe": "gmres_a", "grid": 160, "ratio": 775.12 / 770.05, "sources": GMRES_SOURCES,
-     "sources_sha256_16": "2223e096b7c11b46"},
+     "sources_sha256_16": "32fbb655b87db429"},
     # the 80^3 slabs (cache-resident): the A launches of the two GMRES(30) solves
     {"probe": "gmres_a", "grid": 80, "ratio": 96.14 / 96.03, "sources": GMRES_SOURCES,
-     "sources_sha256_16": "2223e096b7c11b46"},
+     "sources_sha256_16": "32fbb655b87db429"},
 ]
 
 

@@ -121,7 +121,8 @@ struct Ctl {
   // Bi-CGSTAB scalars
   double rho, rho_old, alpha, omega, beta, rh_norm;
   // Split finalize of a large single-solver Bi-CGSTAB sum (split_sums): the wave sums of the
-  // workgroups, column-major by wave, and the count of workgroups that have stored theirs.
+  // WAVES one-wave workgroups, WAVES consecutive entries per column, and the count of
+  // workgroups that have stored theirs.
   double wsum[4 * WAVES];
   int fin_count;
   int pad2;
